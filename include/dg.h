@@ -1,0 +1,201 @@
+/*
+ * dg.h -- C ABI of the MI355X dynamic-graph library.
+ *
+ * The operations follow the problem statement of Kumar et al., "Generating
+ * Dynamic Graph Algorithms for Multiple Backends for a Graph DSL" (arXiv
+ * 2507.11094): given a graph G and a batch of edge insertions and deletions
+ * (Delta G), update G and recompute only what the batch disturbs.  The three
+ * maintained properties are those of the paper's Appendix A programs:
+ * single-source shortest paths (DynSSSP), PageRank (DynPR) and triangle count
+ * (DynTC).  The graph store is the diff-CSR of Section 3.5: a sorted CSR whose
+ * deleted entries carry a tombstone, one sorted diff level for insertions, and a
+ * merge back into plain CSR once the diff and tombstones pass a threshold.
+ *
+ * Conventions for every call:
+ *   - Return value: DG_OK (0) or a negative DG_E* code.  dg_last_error() gives a
+ *     message for the calling thread's last failure.
+ *   - Vertex ids are int32 in [0, n) with n <= 2^30; edge weights are int32 in
+ *     [1, 2^30) (positive, so a shortest-path parent is always strictly closer to
+ *     the source).  Graphs are simple: no self-loops, no parallel edges.
+ *   - Pointer arguments are host memory unless DG_DEVICE_PTRS is passed in the
+ *     call's flags, in which case they are device memory of the current HIP
+ *     device.  The library copies what it needs and never keeps a caller pointer.
+ *   - All device memory behind a handle is owned by the library and released by
+ *     the matching destroy/detach call.
+ *   - Work is issued on the graph's stream (dg_graph_set_stream; default: the
+ *     null stream).  Calls return after their results are complete, except where
+ *     a call says otherwise.  One host thread at a time may use a given graph;
+ *     different graphs are independent.
+ */
+#ifndef DG_H
+#define DG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------------ */
+#define DG_OK 0
+#define DG_EINVAL (-1)   /* bad argument or invalid batch; nothing was changed     */
+#define DG_ENOMEM (-2)   /* device allocation failed; nothing was changed           */
+#define DG_EDEVICE (-3)  /* a HIP runtime call failed                               */
+#define DG_ESTATE (-4)   /* handle unusable (earlier device error) or wrong kind    */
+#define DG_EBUSY (-5)    /* server queue full                                       */
+#define DG_EBUDGET (-6)  /* request exceeds the server's memory budget              */
+#define DG_ENOTFOUND (-7)/* no such request / result not ready                      */
+
+/* Distance of a vertex the source cannot reach: INT_MAX / 2, the paper's INF
+ * (Appendix A, Dynamic SSSP listing). */
+#define DG_INF 1073741823
+
+/* ---- flags --------------------------------------------------------------------- */
+#define DG_DIRECTED 0u
+#define DG_UNDIRECTED 1u     /* graph_create: each edge given once, stored both ways */
+#define DG_DEVICE_PTRS 2u    /* pointer arguments of this call are device memory     */
+
+typedef struct dg_graph dg_graph;
+typedef struct dg_query dg_query;
+typedef struct dg_snapshot dg_snapshot;
+
+/* Tunables.  Zero-initialise and set what you need; zero fields take defaults. */
+typedef struct dg_config {
+    /* Merge the diff level and tombstones back into plain CSR when
+     * (diff entries + tombstones) > merge_threshold * (live edges)
+     * (Section 3.5: the chain of diffs is merged after a configurable number of
+     * batches).  Default 0.05.  A negative value merges after every batch. */
+    double merge_threshold;
+    /* PageRank stops when the L1 step is <= tol * pr_tol_scale.  Default 1. */
+    double pr_tol_scale;
+    /* Vertices with more edges than this are split into chunks across waves.
+     * Default 0 = autotuned table / built-in value. */
+    int32_t heavy_degree;
+    /* Workgroups of the persistent SSSP kernel; 0 = autotuned / built-in. */
+    int32_t persistent_groups;
+    /* 1 = run SSSP fixed points with the persistent single-launch kernel,
+     * 0 = one launch per frontier step; default (-1 or 0 field) = automatic. */
+    int32_t sssp_persistent;
+    int32_t reserved[7];
+} dg_config;
+
+/* Per-batch statistics and phase timings (HIP events on the graph's stream). */
+typedef struct dg_batch_stats {
+    int64_t updates;            /* updates in the call                                  */
+    int64_t deleted;            /* edges removed (undirected: counted once per edge)    */
+    int64_t inserted;           /* edges added, including re-inserts of deleted edges   */
+    int64_t ignored_del;        /* deletions of absent edges                            */
+    int64_t ignored_ins;        /* insertions of present edges                          */
+    int64_t diff_entries;       /* diff-level entries after the call                    */
+    int64_t tombstones;         /* tombstoned entries after the call                    */
+    int32_t merged;             /* merges performed                                     */
+    int32_t chunks;             /* batch_size chunks processed                          */
+    int64_t sssp_invalidated;   /* vertices whose tree path was cut                     */
+    int64_t sssp_relaxed;       /* vertices processed by push relaxation                */
+    int32_t sssp_steps;         /* frontier steps                                       */
+    int32_t pr_iterations;      /* Jacobi iterations                                    */
+    int64_t pr_affected;        /* vertices in the affected set                         */
+    int64_t edges_traversed;    /* adjacency entries examined by all maintained queries */
+    int64_t tc_removed;         /* triangles removed by the deletions                   */
+    int64_t tc_added;           /* triangles added by the insertions                    */
+    float t_validate_ms, t_update_ms, t_merge_ms, t_sssp_ms, t_pr_ms, t_tc_ms, t_total_ms;
+    float reserved_f;
+} dg_batch_stats;
+
+const char *dg_last_error(void);
+
+/* Device allocator hook for all library allocations (default hipMalloc/hipFree).
+ * Must be set before any graph exists; alloc returns NULL on failure. */
+int dg_set_allocator(void *(*alloc)(size_t bytes, void *ctx), void (*free_fn)(void *p, void *ctx),
+                     void *ctx);
+
+/* ---- graph ----------------------------------------------------------------------- */
+
+/* Build a device-resident graph from an edge list (CSR and reverse CSR, Section
+ * 3.5 "diff-CSR" with an empty diff level).  src/dst/w hold m entries; w may be
+ * NULL (all weights 1).  Directed: m arcs src->dst.  DG_UNDIRECTED: m unordered
+ * pairs, each stored in both directions.  Duplicate edges or self-loops, ids
+ * outside [0, n), or weights outside [1, 2^30) give DG_EINVAL.  flags may add
+ * DG_DEVICE_PTRS.  cfg may be NULL. */
+int dg_graph_create(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                    const int32_t *w, uint32_t flags, const dg_config *cfg, dg_graph **out);
+int dg_graph_destroy(dg_graph *g);
+
+/* Issue the graph's work on this hipStream_t (NULL = null stream). */
+int dg_graph_set_stream(dg_graph *g, void *hip_stream);
+
+/* n, live edge count (undirected: edges, not arcs), diff-level entries and
+ * tombstones of the forward direction.  Any output pointer may be NULL. */
+int dg_graph_info(dg_graph *g, int32_t *n, int64_t *m_live, int64_t *diff_entries,
+                  int64_t *tombstones);
+
+/* Copy the live edge set to host arrays, sorted by (src, dst); undirected graphs
+ * give each edge once with src < dst.  Call with src == NULL to get *m only;
+ * otherwise *m must hold the capacity on entry and receives the count. */
+int dg_graph_export(dg_graph *g, int64_t *m, int32_t *src, int32_t *dst, int32_t *w);
+
+/* Merge diff level and tombstones into plain CSR now (Section 3.5). */
+int dg_graph_merge(dg_graph *g);
+
+/* Apply k updates (updateCSRDel then updateCSRAdd, Section 3.2 and the
+ * Appendix A drivers), in chunks of batch_size (<= 0: one chunk), as the Batch
+ * construct of Section 3.3.1 does, and update every attached query after each
+ * chunk.  op[i] = 0 deletes src[i]->dst[i] (w[i] ignored), op[i] = 1 inserts
+ * it with weight w[i] (w may be NULL: weight 1).  Semantics per chunk:
+ * G' = (E \ D) U A; deleting an absent edge or inserting a present one changes
+ * nothing; repeated inserts of one edge keep the smallest weight; an edge both
+ * deleted and inserted ends present with the inserted weight.  Undirected graphs
+ * take unordered pairs.  A self-loop, an id outside [0, n), an op other than 0/1
+ * or a weight outside [1, 2^30) anywhere in a chunk rejects that chunk with
+ * DG_EINVAL before any change (earlier chunks stay applied).  flags may hold
+ * DG_DEVICE_PTRS.  stats may be NULL. */
+int dg_apply_batch(dg_graph *g, int64_t k, const int32_t *src, const int32_t *dst,
+                   const int32_t *w, const uint8_t *op, int64_t batch_size, uint32_t flags,
+                   dg_batch_stats *stats);
+
+/* Device-side copy of the graph and all attached query state, and its restore
+ * (for repeated timing of the same batch on the same graph). */
+int dg_snapshot_save(dg_graph *g, dg_snapshot **out);
+int dg_snapshot_restore(dg_graph *g, const dg_snapshot *s);
+int dg_snapshot_free(dg_snapshot *s);
+
+/* ---- maintained queries -------------------------------------------------------- */
+
+/* Attach a shortest-path query from `source`: computes the static solution
+ * (staticSSSP of Appendix A) and keeps it exact across dg_apply_batch calls
+ * (OnDelete / Decremental / OnAdd / Incremental of the Dynamic SSSP listing). */
+int dg_sssp_attach(dg_graph *g, int32_t source, dg_query **q);
+
+/* Attach PageRank with damping in (0, 1), L1 tolerance tol > 0 and an iteration
+ * cap (staticPR of Appendix A, with delta = damping and beta = tol); kept current
+ * across batches by the Incremental/Decremental PR steps on the affected set. */
+int dg_pr_attach(dg_graph *g, double damping, double tol, int32_t max_iter, dg_query **q);
+
+/* Attach a triangle count (staticTC, then the Decremental/Incremental TC steps
+ * of Appendix A).  Undirected graphs only (DG_EINVAL otherwise). */
+int dg_tc_attach(dg_graph *g, dg_query **q);
+
+int dg_query_detach(dg_query *q);
+
+/* Distances (DG_INF when unreachable) and one shortest-path tree (parent -1 for
+ * the source and unreachable vertices); n entries each.  parent may be NULL. */
+int dg_sssp_read(dg_query *q, int32_t *dist, int32_t *parent, uint32_t flags);
+
+/* PageRank normalised to sum 1 (n entries); iters (nullable) receives the
+ * iterations of the last solve, converged (nullable) 1 if it met the tolerance. */
+int dg_pr_read(dg_query *q, double *rank, int32_t *iters, int32_t *converged, uint32_t flags);
+
+int dg_tc_read(dg_query *q, uint64_t *count);
+
+/* ---- static recompute on the current graph (comparators) -------------------------- */
+
+int dg_sssp_static(dg_graph *g, int32_t source, int32_t *dist, int32_t *parent, uint32_t flags);
+int dg_pr_static(dg_graph *g, double damping, double tol, int32_t max_iter, double *rank,
+                 int32_t *iters, uint32_t flags);
+int dg_tc_static(dg_graph *g, uint64_t *count);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DG_H */

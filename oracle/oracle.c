@@ -27,7 +27,7 @@
 #include <string.h>
 
 #define ORC_INF 1073741823 /* INT_MAX / 2: the paper's INF for unreachable vertices */
-#define ORC_WMAX (1 << 30) /* weights must lie in [0, 2^30) */
+#define ORC_WMAX (1 << 30) /* weights must lie in [1, 2^30) */
 
 typedef struct {
     int64_t key; /* (u << 32) | v */
@@ -82,7 +82,7 @@ static int64_t find_kw(const orc_kw *a, int64_t n, int64_t key) {
  *   B5  an edge deleted and inserted in one batch ends present with the new weight.
  *   B6  a self-loop or a vertex id outside [0, n) anywhere in the batch rejects the
  *       whole batch (return -1, nothing written); so does an op other than 0/1 or an
- *       insert weight outside [0, 2^30).
+ *       insert weight outside [1, 2^30) (weights are positive).
  *   B7  undirected graphs: every edge and every update is an unordered pair.
  *   B8  the weight field of a deletion is ignored.
  * Output: G' sorted by (u, v) (u < v for undirected).  stats[0..3] = deletions
@@ -98,7 +98,7 @@ int64_t orc_apply(int32_t n, int32_t undirected, int64_t m, const int32_t *src,
         if (bsrc[i] < 0 || bsrc[i] >= n || bdst[i] < 0 || bdst[i] >= n) return -1;
         if (bsrc[i] == bdst[i]) return -1;
         if (bop[i] > 1) return -1;
-        if (bop[i] == 1 && (bw[i] < 0 || bw[i] >= ORC_WMAX)) return -1;
+        if (bop[i] == 1 && (bw[i] < 1 || bw[i] >= ORC_WMAX)) return -1;
     }
     orc_kw *E = (orc_kw *)malloc(sizeof(orc_kw) * (m > 0 ? m : 1));
     for (int64_t i = 0; i < m; ++i) {

@@ -1,0 +1,118 @@
+// Device-side helpers shared by the kernels (64-wide CDNA wavefronts).
+#pragma once
+
+#include "dg_internal.h"
+
+namespace dg {
+
+constexpr int WAVE = 64;
+
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+__device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << lane_id()) - 1ull; }
+__device__ __forceinline__ uint64_t ballot(bool p) { return (uint64_t)__ballot(p); }
+
+// Position of neighbour v in the sorted base row, or -1.  Tombstoned entries
+// keep their place in the order, so they are found too (caller checks flags).
+__device__ __forceinline__ int64_t find_sorted(const int32_t *__restrict__ col, int64_t lo,
+                                               int64_t hi, uint32_t v) {
+    int64_t end = hi;
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        uint32_t c = (uint32_t)col[mid] & ID_MASK;
+        if (c < v) lo = mid + 1;
+        else hi = mid;
+    }
+    if (lo < end && ((uint32_t)col[lo] & ID_MASK) == v) return lo;
+    return -1;
+}
+
+// First position in [lo, hi) whose neighbour id is >= v.
+__device__ __forceinline__ int64_t lower_sorted(const int32_t *__restrict__ col, int64_t lo,
+                                                int64_t hi, uint32_t v) {
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if (((uint32_t)col[mid] & ID_MASK) < v) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ int64_t lower_key(const uint64_t *__restrict__ k, int64_t lo, int64_t hi,
+                                             uint64_t v) {
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if (k[mid] < v) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Largest r in [lo, hi] with off[r] <= i: the row holding entry i.
+__device__ __forceinline__ int32_t row_of(const int64_t *__restrict__ off, int32_t lo, int32_t hi,
+                                          int64_t i) {
+    while (lo < hi) {
+        int32_t mid = lo + ((hi - lo + 1) >> 1);
+        if (off[mid] <= i) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Wave-wide inclusive scan (Hillis-Steele over 64 lanes).
+template <class T>
+__device__ __forceinline__ T wave_incl_scan(T x) {
+    int l = lane_id();
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        T y = __shfl_up(x, d, WAVE);
+        if (l >= d) x += y;
+    }
+    return x;
+}
+
+template <class T>
+__device__ __forceinline__ T wave_sum(T x) {
+#pragma unroll
+    for (int d = WAVE / 2; d > 0; d >>= 1) x += __shfl_xor(x, d, WAVE);
+    return x;
+}
+
+template <class T>
+__device__ __forceinline__ T wave_min(T x) {
+#pragma unroll
+    for (int d = WAVE / 2; d > 0; d >>= 1) {
+        T y = __shfl_xor(x, d, WAVE);
+        x = y < x ? y : x;
+    }
+    return x;
+}
+
+// One atomic per wave for a counter bump of `pred` lanes; returns the slot of
+// this lane (valid where pred is true).
+__device__ __forceinline__ int64_t wave_append(int64_t *counter, bool pred) {
+    uint64_t b = ballot(pred);
+    if (b == 0) return -1;
+    int leader = __ffsll((long long)b) - 1;
+    int64_t base = 0;
+    if (lane_id() == leader) base = atomicAdd((unsigned long long *)counter, (unsigned long long)__popcll(b));
+    base = __shfl(base, leader, WAVE);
+    return base + __popcll(b & lanemask_lt());
+}
+
+__device__ __forceinline__ void wave_count(int64_t *counter, bool pred) {
+    uint64_t b = ballot(pred);
+    if (b && lane_id() == __ffsll((long long)b) - 1)
+        atomicAdd((unsigned long long *)counter, (unsigned long long)__popcll(b));
+}
+
+__device__ __forceinline__ uint64_t sssp_pack(int32_t dist, int32_t parent) {
+    return ((uint64_t)(uint32_t)dist << 32) | (uint64_t)(uint32_t)parent;
+}
+__device__ __forceinline__ int32_t sssp_dist(uint64_t k) { return (int32_t)(k >> 32); }
+__device__ __forceinline__ int32_t sssp_parent(uint64_t k) { return (int32_t)(uint32_t)(k & 0xffffffffu); }
+
+// Grid-stride helpers
+__device__ __forceinline__ int64_t gtid() { return (int64_t)blockIdx.x * blockDim.x + threadIdx.x; }
+__device__ __forceinline__ int64_t gstride() { return (int64_t)gridDim.x * blockDim.x; }
+
+}  // namespace dg

@@ -1,0 +1,216 @@
+// Internal declarations of the MI355X dynamic-graph library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/dg.h"
+
+struct dg_query;
+
+namespace dg {
+
+// ---- entry encoding --------------------------------------------------------------
+// A neighbour entry (base CSR `col`, diff `dcol`) holds the neighbour id in bits
+// 0..29 and two flags:
+//   DEAD (bit 31): tombstone of a deleted edge (the sentinel of Section 3.5);
+//   MARK (bit 30): the entry is touched by the batch in flight -- set on edges the
+//         batch deletes until the deletion is committed (pre-hooks read the old
+//         graph with it), and on edges the batch inserts until the post-hooks are
+//         done.  It plays the role of the edge flags of the Dynamic TC listing.
+constexpr uint32_t ID_MASK = 0x3FFFFFFFu;
+constexpr uint32_t MARK = 0x40000000u;
+constexpr uint32_t DEAD = 0x80000000u;
+constexpr int32_t INF = DG_INF;
+constexpr int TILE = 2048;  // base entries per merge tile (tombstone counters per tile)
+
+// ---- errors ------------------------------------------------------------------------
+int set_error(int code, const char *fmt, ...);
+#define DG_HIP(expr)                                                                    \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return ::dg::set_error(DG_EDEVICE, "%s failed: %s (%s:%d)", #expr,         \
+                                   hipGetErrorString(e_), __FILE__, __LINE__);          \
+    } while (0)
+#define DG_TRY(expr)                      \
+    do {                                  \
+        int r_ = (expr);                  \
+        if (r_ != DG_OK) return r_;       \
+    } while (0)
+
+// ---- device memory -------------------------------------------------------------------
+void *dmalloc(size_t bytes);
+void dfree(void *p);
+
+// Growable device buffer.  ensure() keeps contents only when asked.
+template <class T>
+struct DBuf {
+    T *p = nullptr;
+    size_t cap = 0;
+    int ensure(size_t n, bool keep = false, hipStream_t s = nullptr) {
+        if (n <= cap && p) return DG_OK;
+        size_t nc = n < 64 ? 64 : n + n / 8;
+        T *q = static_cast<T *>(dmalloc(nc * sizeof(T)));
+        if (!q) return set_error(DG_ENOMEM, "device allocation of %zu bytes failed", nc * sizeof(T));
+        if (keep && p && cap) {
+            hipError_t e = hipMemcpyAsync(q, p, cap * sizeof(T), hipMemcpyDeviceToDevice, s);
+            if (e != hipSuccess) { dfree(q); return set_error(DG_EDEVICE, "copy failed"); }
+            (void)hipStreamSynchronize(s);
+        }
+        release();
+        p = q;
+        cap = nc;
+        return DG_OK;
+    }
+    void release() {
+        if (p) dfree(p);
+        p = nullptr;
+        cap = 0;
+    }
+    void swap(DBuf &o) {
+        std::swap(p, o.p);
+        std::swap(cap, o.cap);
+    }
+};
+
+// One direction of the graph store: rows are sources (forward) or destinations
+// (reverse).  Base CSR with tombstones plus one sorted diff level (Section 3.5).
+struct Dir {
+    int32_t n = 0;
+    int keybits = 1;          // diff key = (row << keybits) | col
+    DBuf<int64_t> off;        // [n+1] base row offsets
+    DBuf<int32_t> col, w;     // base entries (DEAD / MARK flags in col)
+    int64_t m = 0;            // base entries, tombstones included
+    DBuf<int64_t> doff;       // [n+1] diff row offsets
+    DBuf<uint64_t> dkey;      // [dm] sorted diff keys
+    DBuf<int32_t> dcol, dw;   // [dm] diff entries (flags in dcol)
+    int64_t dm = 0;           // diff entries, tombstones included
+    DBuf<int32_t> deg;        // [n] live degree
+    DBuf<int32_t> ntomb;      // [n] base tombstones per row
+    DBuf<int32_t> ttomb;      // [ceil(m/TILE)] base tombstones per merge tile
+    int64_t tomb_base = 0;    // host mirrors
+    int64_t tomb_diff = 0;
+    // spares used by merges and diff rebuilds
+    DBuf<int64_t> off2;
+    DBuf<int32_t> col2, w2;
+    DBuf<uint64_t> dkey2;
+    DBuf<int32_t> dcol2, dw2;
+};
+
+// Workspace: scratch grown on demand, reused across batches.
+struct Work {
+    DBuf<int32_t> bsrc, bdst, bw;
+    DBuf<uint8_t> bop;
+    DBuf<uint64_t> ikey, ikey_s, rkey, rkey_s;
+    DBuf<int32_t> iw, iw_s, rw, rw_s;
+    DBuf<int32_t> ddu, ddv;               // deletion arcs to look up
+    DBuf<int32_t> adu, adv;               // applied deletion arcs (forward)
+    DBuf<int64_t> adpos;                  // position: >= 0 base, < 0 diff (-1 - p)
+    DBuf<int32_t> aiu, aiv, aiw;          // applied insertion arcs (forward)
+    DBuf<int64_t> aipos;                  // revive position or NEW
+    DBuf<uint64_t> nkey;                  // NEW forward keys (sorted)
+    DBuf<int32_t> nw;
+    DBuf<int32_t> tcu, tcv;               // undirected edges for TC (deleted / inserted)
+    DBuf<uint8_t> tmp;                    // hipcub temp storage
+    DBuf<int64_t> scan64;                 // merge scans
+    DBuf<int64_t> tscan;
+    // frontier machinery shared by the traversals
+    DBuf<int32_t> f0, f1, heavy;          // frontiers and heavy-chunk queue
+    DBuf<int32_t> stamp;                  // per-vertex dedup stamps
+    int32_t stamp_ctr = 0;
+    DBuf<double> part;                    // partial sums of split rows
+    // counters: device block + pinned host mirror
+    int64_t *dcnt = nullptr;
+    int64_t *hcnt = nullptr;
+    hipEvent_t ev[16] = {};
+};
+
+enum Counter {
+    C_ERR = 0, C_NDEL, C_NINS, C_ADEL, C_IGNDEL, C_DISTINCT, C_AINS, C_IGNINS, C_NEW,
+    C_TCDEL, C_TCINS, C_F0, C_F1, C_HEAVY, C_AUX0, C_AUX1, C_AUX2, C_AUX3,
+    C_TC0, C_TC1, C_RED0 = 24, C_COUNT = 40
+};
+
+}  // namespace dg
+
+// ---- handles -------------------------------------------------------------------------
+struct dg_graph {
+    int32_t n = 0;
+    bool undirected = false;
+    bool broken = false;
+    dg::Dir fwd, rev_own;
+    dg::Dir *rev = nullptr;  // == &fwd for undirected graphs
+    int64_t m_live = 0;      // live arcs in fwd
+    hipStream_t stream = nullptr;
+    dg_config cfg{};
+    dg::Work ws;
+    std::vector<dg_query *> queries;
+};
+
+enum QueryKind { Q_SSSP = 1, Q_PR = 2, Q_TC = 3 };
+
+struct dg_query {
+    dg_graph *g = nullptr;
+    QueryKind kind = Q_SSSP;
+    // SSSP: packed (dist << 32 | parent) keys, parent stored as uint32 (-1 = none)
+    int32_t source = 0;
+    dg::DBuf<uint64_t> key;
+    dg::DBuf<int32_t> inval;  // cut vertices (seeds first)
+    int64_t nseeds = 0;
+    // PageRank: unnormalised x of the dangling-dropped system, x/outdeg cache
+    double damping = 0.85, tol = 1e-9;
+    int32_t max_iter = 1000;
+    dg::DBuf<double> x, xn, contrib;
+    int32_t last_iters = 0;
+    int32_t converged = 0;
+    // triangle count
+    uint64_t tc = 0;
+};
+
+struct dg_snapshot {
+    dg_graph *g = nullptr;
+    std::vector<std::pair<void *, size_t>> bufs;  // device copies in a fixed order
+    std::vector<int64_t> scalars;
+    std::vector<dg_query *> queries;
+};
+
+namespace dg {
+// graph store (graph.hip)
+int graph_build(dg_graph *g, int64_t m, const int32_t *src, const int32_t *dst, const int32_t *w);
+int graph_export(dg_graph *g, int64_t *m, int32_t *src, int32_t *dst, int32_t *w);
+int graph_merge(dg_graph *g);
+int apply_chunk(dg_graph *g, int64_t k, const int32_t *src, const int32_t *dst, const int32_t *w,
+                const uint8_t *op, bool dev, dg_batch_stats *st);
+int counters_read(dg_graph *g);
+int counters_clear(dg_graph *g);
+int ws_init(dg_graph *g);
+void ws_free(dg_graph *g);
+void dir_free(Dir &d);
+int next_stamp(dg_graph *g, int32_t *stamp);
+int fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
+
+// SSSP (sssp.hip)
+int sssp_init(dg_query *q);
+int sssp_static_solve(dg_graph *g, uint64_t *key, int32_t source, dg_batch_stats *st);
+int sssp_pre_delete(dg_query *q, int64_t n_applied_del);
+int sssp_post_update(dg_query *q, int64_t n_applied_del, int64_t n_applied_ins, dg_batch_stats *st);
+int sssp_read(dg_query *q, int32_t *dist, int32_t *parent, bool dev);
+int sssp_unpack(dg_graph *g, const uint64_t *key, int32_t *dist, int32_t *parent, hipStream_t s);
+
+// PageRank (pagerank.hip)
+int pr_init(dg_query *q);
+int pr_static_solve(dg_graph *g, double damping, double tol, int32_t max_iter, double *x,
+                    double *contrib, double *xn, int32_t *iters, int32_t *conv);
+int pr_post_update(dg_query *q, int64_t n_applied_del, int64_t n_applied_ins, dg_batch_stats *st);
+int pr_read(dg_query *q, double *rank, bool dev);
+int pr_normalize(dg_graph *g, const double *x, double *rank, bool dev);
+
+// triangle counting (tc.hip)
+int tc_count_static(dg_graph *g, uint64_t *count);
+int tc_delta(dg_graph *g, const int32_t *eu, const int32_t *ev, int64_t ne, uint64_t *sum6);
+}  // namespace dg

@@ -1,0 +1,1041 @@
+// Graph store: build, batch application (updateCSRDel / updateCSRAdd) and merge.
+//
+// The store is the diff-CSR of Section 3.5 re-laid for MI355X: per direction a
+// sorted base CSR whose deleted entries keep their slot with a tombstone bit (the
+// paper's sentinel), plus ONE sorted diff level that collects insertions.  Each
+// batch merges its insertions into the diff (instead of chaining a new diff per
+// batch); when diff entries plus tombstones pass a threshold the diff and the
+// tombstones are merged into a fresh base CSR by a coalesced tile-parallel stream
+// (Section 3.5: the chain is merged after a configurable number of batches).
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+#include <cstring>
+
+#include "dg_device.h"
+
+namespace dg {
+
+static int keybits_for(int32_t n) {
+    int b = 1;
+    while ((1ll << b) < (int64_t)n) ++b;
+    return b;
+}
+
+static inline int grid_for(int64_t n, int block = 256, int cap = 8192) {
+    int64_t g = (n + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+// ---------------------------------------------------------------- small kernels
+
+__global__ void k_fill_i32(int32_t *p, int32_t v, int64_t n) {
+    for (int64_t i = gtid(); i < n; i += gstride()) p[i] = v;
+}
+__global__ void k_fill_i64(int64_t *p, int64_t v, int64_t n) {
+    for (int64_t i = gtid(); i < n; i += gstride()) p[i] = v;
+}
+
+int fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s) {
+    if (n <= 0) return DG_OK;
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n)), dim3(256), 0, s, p, v, n);
+    DG_HIP(hipGetLastError());
+    return DG_OK;
+}
+static int fill_i64(int64_t *p, int64_t v, int64_t n, hipStream_t s) {
+    if (n <= 0) return DG_OK;
+    hipLaunchKernelGGL(k_fill_i64, dim3(grid_for(n)), dim3(256), 0, s, p, v, n);
+    DG_HIP(hipGetLastError());
+    return DG_OK;
+}
+
+// ---------------------------------------------------------------- library primitives
+
+static int sort_pairs(dg_graph *g, const uint64_t *kin, uint64_t *kout, const int32_t *vin,
+                      int32_t *vout, int64_t n, int bits) {
+    if (n <= 0) return DG_OK;
+    if (n > INT32_MAX) return set_error(DG_EINVAL, "sort of more than 2^31 keys");
+    size_t bytes = 0;
+    DG_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, kin, kout, vin, vout, (int)n, 0, bits,
+                                              g->stream));
+    DG_TRY(g->ws.tmp.ensure(bytes));
+    DG_HIP(hipcub::DeviceRadixSort::SortPairs(g->ws.tmp.p, bytes, kin, kout, vin, vout, (int)n, 0,
+                                              bits, g->stream));
+    return DG_OK;
+}
+
+static int scan_excl(dg_graph *g, const int64_t *in, int64_t *out, int64_t n) {
+    if (n <= 0) return DG_OK;
+    size_t bytes = 0;
+    DG_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, bytes, in, out, (int)n, g->stream));
+    DG_TRY(g->ws.tmp.ensure(bytes));
+    DG_HIP(hipcub::DeviceScan::ExclusiveSum(g->ws.tmp.p, bytes, in, out, (int)n, g->stream));
+    return DG_OK;
+}
+
+// ---------------------------------------------------------------- counters
+
+int counters_clear(dg_graph *g) { return fill_i64(g->ws.dcnt, 0, C_COUNT, g->stream); }
+
+int counters_read(dg_graph *g) {
+    DG_HIP(hipMemcpyAsync(g->ws.hcnt, g->ws.dcnt, sizeof(int64_t) * C_COUNT, hipMemcpyDeviceToHost,
+                          g->stream));
+    DG_HIP(hipStreamSynchronize(g->stream));
+    return DG_OK;
+}
+
+int ws_init(dg_graph *g) {
+    g->ws.dcnt = static_cast<int64_t *>(dmalloc(sizeof(int64_t) * C_COUNT));
+    if (!g->ws.dcnt) return set_error(DG_ENOMEM, "counter allocation failed");
+    DG_HIP(hipHostMalloc((void **)&g->ws.hcnt, sizeof(int64_t) * C_COUNT, hipHostMallocDefault));
+    for (auto &e : g->ws.ev) DG_HIP(hipEventCreate(&e));
+    return counters_clear(g);
+}
+
+void dir_free(Dir &d) {
+    d.off.release(); d.col.release(); d.w.release(); d.doff.release(); d.dkey.release();
+    d.dcol.release(); d.dw.release(); d.deg.release(); d.ntomb.release(); d.ttomb.release();
+    d.off2.release(); d.col2.release(); d.w2.release(); d.dkey2.release(); d.dcol2.release();
+    d.dw2.release();
+}
+
+void ws_free(dg_graph *g) {
+    Work &w = g->ws;
+    w.bsrc.release(); w.bdst.release(); w.bw.release(); w.bop.release();
+    w.ikey.release(); w.ikey_s.release(); w.rkey.release(); w.rkey_s.release();
+    w.iw.release(); w.iw_s.release(); w.rw.release(); w.rw_s.release();
+    w.ddu.release(); w.ddv.release(); w.adu.release(); w.adv.release(); w.adpos.release();
+    w.aiu.release(); w.aiv.release(); w.aiw.release(); w.aipos.release();
+    w.nkey.release(); w.nw.release(); w.tcu.release(); w.tcv.release(); w.tmp.release();
+    w.scan64.release(); w.tscan.release(); w.f0.release(); w.f1.release(); w.heavy.release();
+    w.stamp.release(); w.part.release();
+    if (w.dcnt) dfree(w.dcnt);
+    if (w.hcnt) (void)hipHostFree(w.hcnt);
+    for (auto &e : w.ev)
+        if (e) (void)hipEventDestroy(e);
+    w.dcnt = nullptr;
+    w.hcnt = nullptr;
+}
+
+// Fresh per-vertex stamp value (stamps dedup frontier pushes without clearing).
+int next_stamp(dg_graph *g, int32_t *stamp) {
+    Work &w = g->ws;
+    if (!w.stamp.p || w.stamp_ctr >= INT32_MAX - 4) {
+        DG_TRY(w.stamp.ensure((size_t)g->n + 1));
+        DG_TRY(fill_i32(w.stamp.p, 0, g->n + 1, g->stream));
+        w.stamp_ctr = 0;
+    }
+    *stamp = ++w.stamp_ctr;
+    return DG_OK;
+}
+
+// ---------------------------------------------------------------- build
+
+__global__ void k_validate_edges(int64_t m, const int32_t *s, const int32_t *d, const int32_t *w,
+                                 int32_t n, int64_t *cnt) {
+    for (int64_t i = gtid(); i < m; i += gstride()) {
+        int32_t u = s[i], v = d[i];
+        bool bad = u < 0 || u >= n || v < 0 || v >= n || u == v;
+        if (w) bad |= (w[i] < 1 || w[i] >= (1 << 30));
+        if (bad) atomicOr((unsigned long long *)&cnt[C_ERR], 1ull);
+    }
+}
+
+__global__ void k_make_keys(int64_t m, const int32_t *s, const int32_t *d, const int32_t *w, int B,
+                            int reverse, int both, uint64_t *keys, int32_t *vals) {
+    for (int64_t i = gtid(); i < m; i += gstride()) {
+        uint32_t u = (uint32_t)s[i], v = (uint32_t)d[i];
+        if (reverse) { uint32_t t = u; u = v; v = t; }
+        int32_t wt = w ? w[i] : 1;
+        keys[i] = ((uint64_t)u << B) | v;
+        vals[i] = wt;
+        if (both) {
+            keys[m + i] = ((uint64_t)v << B) | u;
+            vals[m + i] = wt;
+        }
+    }
+}
+
+__global__ void k_check_dup(int64_t m, const uint64_t *k, int64_t *cnt) {
+    for (int64_t i = gtid() + 1; i < m; i += gstride())
+        if (k[i] == k[i - 1]) atomicOr((unsigned long long *)&cnt[C_ERR], 2ull);
+}
+
+__global__ void k_split_keys(int64_t m, const uint64_t *k, const int32_t *vals, int B, int32_t *col,
+                             int32_t *w) {
+    const uint64_t mask = (1ull << B) - 1;
+    for (int64_t i = gtid(); i < m; i += gstride()) {
+        col[i] = (int32_t)(k[i] & mask);
+        w[i] = vals[i];
+    }
+}
+
+// off[r] = first position whose row is >= r, for r in [0, n]
+__global__ void k_row_offsets(int32_t n, const uint64_t *k, int64_t m, int B, int64_t *off) {
+    for (int64_t r = gtid(); r <= n; r += gstride()) off[r] = lower_key(k, 0, m, (uint64_t)r << B);
+}
+
+__global__ void k_degrees(int32_t n, const int64_t *off, int32_t *deg) {
+    for (int64_t r = gtid(); r < n; r += gstride()) deg[r] = (int32_t)(off[r + 1] - off[r]);
+}
+
+static int64_t ntiles_for(int64_t m) { return (m + TILE - 1) / TILE; }
+
+static int dir_from_sorted(dg_graph *g, Dir &d, const uint64_t *keys, const int32_t *vals, int64_t m,
+                           int B) {
+    hipStream_t s = g->stream;
+    d.n = g->n;
+    d.keybits = B;
+    d.m = m;
+    d.dm = 0;
+    d.tomb_base = 0;
+    d.tomb_diff = 0;
+    DG_TRY(d.off.ensure(g->n + 1));
+    DG_TRY(d.col.ensure(m + 1));
+    DG_TRY(d.w.ensure(m + 1));
+    DG_TRY(d.deg.ensure(g->n + 1));
+    DG_TRY(d.ntomb.ensure(g->n + 1));
+    DG_TRY(d.ttomb.ensure(ntiles_for(m) + 2));
+    DG_TRY(d.doff.ensure(g->n + 1));
+    if (m > 0)
+        hipLaunchKernelGGL(k_split_keys, dim3(grid_for(m)), dim3(256), 0, s, m, keys, vals, B,
+                           d.col.p, d.w.p);
+    hipLaunchKernelGGL(k_row_offsets, dim3(grid_for(g->n + 1)), dim3(256), 0, s, g->n, keys, m, B,
+                       d.off.p);
+    hipLaunchKernelGGL(k_degrees, dim3(grid_for(g->n)), dim3(256), 0, s, g->n, d.off.p, d.deg.p);
+    DG_HIP(hipGetLastError());
+    DG_TRY(fill_i32(d.ntomb.p, 0, g->n + 1, s));
+    DG_TRY(fill_i32(d.ttomb.p, 0, ntiles_for(m) + 2, s));
+    DG_TRY(fill_i64(d.doff.p, 0, g->n + 1, s));
+    return DG_OK;
+}
+
+int graph_build(dg_graph *g, int64_t m, const int32_t *src, const int32_t *dst, const int32_t *w) {
+    hipStream_t s = g->stream;
+    Work &ws = g->ws;
+    const int B = keybits_for(g->n);
+    DG_TRY(counters_clear(g));
+    if (m > 0)
+        hipLaunchKernelGGL(k_validate_edges, dim3(grid_for(m)), dim3(256), 0, s, m, src, dst, w, g->n,
+                           ws.dcnt);
+    DG_HIP(hipGetLastError());
+    DG_TRY(counters_read(g));
+    if (ws.hcnt[C_ERR]) return set_error(DG_EINVAL, "edge list holds a self-loop, an id outside [0,n) or a weight outside [1,2^30)");
+    const int64_t arcs = g->undirected ? 2 * m : m;
+    if (arcs > INT32_MAX) return set_error(DG_EINVAL, "more than 2^31 arcs");
+    DG_TRY(ws.ikey.ensure(arcs + 1));
+    DG_TRY(ws.ikey_s.ensure(arcs + 1));
+    DG_TRY(ws.iw.ensure(arcs + 1));
+    DG_TRY(ws.iw_s.ensure(arcs + 1));
+    for (int dir = 0; dir < (g->undirected ? 1 : 2); ++dir) {
+        if (m > 0)
+            hipLaunchKernelGGL(k_make_keys, dim3(grid_for(m)), dim3(256), 0, s, m, src, dst, w, B, dir,
+                               (int)g->undirected, ws.ikey.p, ws.iw.p);
+        DG_HIP(hipGetLastError());
+        DG_TRY(sort_pairs(g, ws.ikey.p, ws.ikey_s.p, ws.iw.p, ws.iw_s.p, arcs, 2 * B));
+        if (dir == 0) {
+            if (arcs > 1)
+                hipLaunchKernelGGL(k_check_dup, dim3(grid_for(arcs)), dim3(256), 0, s, arcs, ws.ikey_s.p,
+                                   ws.dcnt);
+            DG_TRY(counters_read(g));
+            if (ws.hcnt[C_ERR]) return set_error(DG_EINVAL, "edge list holds a repeated edge");
+        }
+        Dir &d = dir == 0 ? g->fwd : g->rev_own;
+        DG_TRY(dir_from_sorted(g, d, ws.ikey_s.p, ws.iw_s.p, arcs, B));
+    }
+    g->rev = g->undirected ? &g->fwd : &g->rev_own;
+    g->m_live = arcs;
+    // the build-sized scratch is not needed again
+    ws.ikey.release(); ws.ikey_s.release(); ws.iw.release(); ws.iw_s.release(); ws.tmp.release();
+    DG_HIP(hipStreamSynchronize(s));
+    return DG_OK;
+}
+
+// ---------------------------------------------------------------- merge (Section 3.5)
+
+__global__ void k_deg_to_i64(int32_t n, const int32_t *deg, int64_t *out) {
+    for (int64_t i = gtid(); i <= n; i += gstride()) out[i] = i < n ? deg[i] : 0;
+}
+
+// Tile-parallel merge of one direction: every workgroup streams TILE consecutive
+// base entries (4 waves x 8 x 64, coalesced), drops tombstones and interleaves
+// the diff entries of the rows it touches.  Output positions come from
+//   off2[r] + (live base entries of row r before i) + (diff entries of r below col)
+// where the live count uses tombstone prefix counts that the delete step keeps per
+// row (RB = scan of ntomb) and per tile (TS = scan of ttomb), so no extra pass over
+// the base arrays is needed.
+__global__ __launch_bounds__(256) void k_merge_base(
+    int32_t n, int64_t m, const int64_t *__restrict__ off, const int32_t *__restrict__ col,
+    const int32_t *__restrict__ w, const int64_t *__restrict__ doff, const int32_t *__restrict__ dcol,
+    const int32_t *__restrict__ dw, const int64_t *__restrict__ off2, const int64_t *__restrict__ RB,
+    const int64_t *__restrict__ TS, int32_t *__restrict__ col2, int32_t *__restrict__ w2, int64_t cap,
+    int64_t *cnt) {
+    constexpr int PER_WAVE = TILE / 4;
+    constexpr int IT = PER_WAVE / WAVE;
+    __shared__ int64_t wdead[4];
+    const int t = blockIdx.x;
+    const int wv = threadIdx.x / WAVE;
+    const int l = lane_id();
+    const int64_t e0 = (int64_t)t * TILE;
+    const int64_t wbase = e0 + (int64_t)wv * PER_WAVE;
+    int32_t c[IT];
+    uint64_t deadm[IT];
+    int ndead = 0;
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        int64_t i = wbase + it * WAVE + l;
+        bool valid = i < m;
+        c[it] = valid ? col[i] : 0;
+        deadm[it] = ballot(valid && ((uint32_t)c[it] & DEAD));
+        ndead += __popcll(deadm[it]);
+    }
+    if (l == 0) wdead[wv] = ndead;
+    __syncthreads();
+    if (wbase >= m) return;
+    int64_t tb = TS[t];
+    for (int j = 0; j < wv; ++j) tb += wdead[j];
+    const int64_t wlast = min(wbase + PER_WAVE - 1, m - 1);
+    const int32_t r_lo = row_of(off, 0, n - 1, wbase);
+    const int32_t r_hi = row_of(off, r_lo, n - 1, wlast);
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int64_t i = wbase + it * WAVE + l;
+        const int64_t tb_i = tb + __popcll(deadm[it] & lanemask_lt());
+        if (i < m) {
+            const int32_t r = row_of(off, r_lo, r_hi, i);
+            const int64_t ro = off[r], re = off[r + 1];
+            const int64_t rank = (i - ro) - (tb_i - RB[r]);
+            const uint32_t cu = (uint32_t)c[it];
+            const uint32_t cur = cu & ID_MASK;
+            const bool dead = cu & DEAD;
+            const int64_t dlo = doff[r], dhi = doff[r + 1];
+            const int64_t ob = off2[r];
+            if (!dead) {
+                int64_t ndl = dlo < dhi ? lower_sorted(dcol, dlo, dhi, cur) - dlo : 0;
+                int64_t o = ob + rank + ndl;
+                if (o >= 0 && o < cap) {
+                    col2[o] = (int32_t)cu;
+                    w2[o] = w[i];
+                } else {
+                    atomicOr((unsigned long long *)&cnt[C_ERR], 4ull);
+                }
+            }
+            if (dlo < dhi) {
+                // diff entries whose insertion point is entry i ...
+                int64_t a = dlo;
+                if (i > ro) a = lower_sorted(dcol, dlo, dhi, ((uint32_t)col[i - 1] & ID_MASK) + 1);
+                int64_t b = lower_sorted(dcol, dlo, dhi, cur);
+                for (int64_t j = a; j < b; ++j) {
+                    int64_t o = ob + rank + (j - dlo);
+                    if (o < 0 || o >= cap) { atomicOr((unsigned long long *)&cnt[C_ERR], 4ull); break; }
+                    col2[o] = dcol[j];
+                    w2[o] = dw[j];
+                }
+                // ... and, after the row's last base entry, the diff tail
+                if (i == re - 1) {
+                    int64_t a2 = lower_sorted(dcol, dlo, dhi, cur + 1);
+                    int64_t after = rank + (dead ? 0 : 1);
+                    for (int64_t j = a2; j < dhi; ++j) {
+                        int64_t o = ob + after + (j - dlo);
+                        if (o < 0 || o >= cap) { atomicOr((unsigned long long *)&cnt[C_ERR], 4ull); break; }
+                        col2[o] = dcol[j];
+                        w2[o] = dw[j];
+                    }
+                }
+            }
+        }
+        tb += __popcll(deadm[it]);
+    }
+}
+
+// Diff entries of rows whose base part is empty.
+__global__ void k_merge_diff_empty(int64_t dm, const uint64_t *dkey, int B, const int64_t *off,
+                                   const int64_t *doff, const int32_t *dcol, const int32_t *dw,
+                                   const int64_t *off2, int32_t *col2, int32_t *w2, int64_t cap,
+                                   int64_t *cnt) {
+    for (int64_t j = gtid(); j < dm; j += gstride()) {
+        int32_t r = (int32_t)(dkey[j] >> B);
+        if (off[r] != off[r + 1]) continue;
+        int64_t o = off2[r] + (j - doff[r]);
+        if (o < 0 || o >= cap) { atomicOr((unsigned long long *)&cnt[C_ERR], 4ull); continue; }
+        col2[o] = dcol[j];
+        w2[o] = dw[j];
+    }
+}
+
+// Merge direction d into (off2, col2, w2); returns the new entry count.
+static int merge_into(dg_graph *g, Dir &d, int64_t *off2, int32_t *col2, int32_t *w2, int64_t m2) {
+    hipStream_t s = g->stream;
+    Work &ws = g->ws;
+    const int32_t n = g->n;
+    const int64_t ntiles = ntiles_for(d.m);
+    DG_TRY(ws.scan64.ensure(2 * ((size_t)n + 1) + 2 * (ntiles + 1)));
+    int64_t *tmpa = ws.scan64.p;
+    int64_t *RB = tmpa + (n + 1);
+    int64_t *tsin = RB + (n + 1);
+    int64_t *TS = tsin + (ntiles + 1);
+    // off2 = exclusive scan of live degrees
+    hipLaunchKernelGGL(k_deg_to_i64, dim3(grid_for(n + 1)), dim3(256), 0, s, n, d.deg.p, tmpa);
+    DG_TRY(scan_excl(g, tmpa, off2, n + 1));
+    // RB = tombstones before each row, TS = tombstones before each tile
+    hipLaunchKernelGGL(k_deg_to_i64, dim3(grid_for(n + 1)), dim3(256), 0, s, n, d.ntomb.p, tmpa);
+    DG_TRY(scan_excl(g, tmpa, RB, n + 1));
+    hipLaunchKernelGGL(k_deg_to_i64, dim3(grid_for(ntiles + 1)), dim3(256), 0, s, (int32_t)ntiles,
+                       d.ttomb.p, tsin);
+    DG_TRY(scan_excl(g, tsin, TS, ntiles + 1));
+    DG_HIP(hipGetLastError());
+    DG_TRY(counters_clear(g));
+    if (d.m > 0)
+        hipLaunchKernelGGL(k_merge_base, dim3((unsigned)ntiles), dim3(256), 0, s, n, d.m, d.off.p,
+                           d.col.p, d.w.p, d.doff.p, d.dcol.p, d.dw.p, off2, RB, TS, col2, w2, m2,
+                           ws.dcnt);
+    if (d.dm > 0)
+        hipLaunchKernelGGL(k_merge_diff_empty, dim3(grid_for(d.dm)), dim3(256), 0, s, d.dm, d.dkey.p,
+                           d.keybits, d.off.p, d.doff.p, d.dcol.p, d.dw.p, off2, col2, w2, m2, ws.dcnt);
+    DG_HIP(hipGetLastError());
+    DG_TRY(counters_read(g));
+    if (ws.hcnt[C_ERR]) return set_error(DG_EDEVICE, "merge: inconsistent degree counts (internal error)");
+    return DG_OK;
+}
+
+static int merge_dir(dg_graph *g, Dir &d, int64_t live) {
+    hipStream_t s = g->stream;
+    if (d.dm == 0 && d.tomb_base == 0) return DG_OK;
+    DG_TRY(d.off2.ensure(g->n + 1));
+    DG_TRY(d.col2.ensure(live + 1));
+    DG_TRY(d.w2.ensure(live + 1));
+    DG_TRY(merge_into(g, d, d.off2.p, d.col2.p, d.w2.p, live));
+    d.off.swap(d.off2);
+    d.col.swap(d.col2);
+    d.w.swap(d.w2);
+    d.m = live;
+    d.dm = 0;
+    d.tomb_base = 0;
+    d.tomb_diff = 0;
+    DG_TRY(fill_i64(d.doff.p, 0, g->n + 1, s));
+    DG_TRY(fill_i32(d.ntomb.p, 0, g->n + 1, s));
+    DG_TRY(d.ttomb.ensure(ntiles_for(live) + 2));
+    DG_TRY(fill_i32(d.ttomb.p, 0, ntiles_for(live) + 2, s));
+    return DG_OK;
+}
+
+int graph_merge(dg_graph *g) {
+    DG_TRY(merge_dir(g, g->fwd, g->m_live));
+    if (!g->undirected) DG_TRY(merge_dir(g, g->rev_own, g->m_live));
+    DG_HIP(hipStreamSynchronize(g->stream));
+    return DG_OK;
+}
+
+// ---------------------------------------------------------------- export
+
+__global__ void k_rows_of_entries(int32_t n, int64_t m, const int64_t *off, int32_t *row) {
+    for (int64_t i = gtid(); i < m; i += gstride()) row[i] = row_of(off, 0, n - 1, i);
+}
+
+int graph_export(dg_graph *g, int64_t *m, int32_t *src, int32_t *dst, int32_t *w) {
+    const int64_t arcs = g->m_live;
+    const int64_t count = g->undirected ? arcs / 2 : arcs;
+    if (!src) {
+        *m = count;
+        return DG_OK;
+    }
+    if (*m < count) return set_error(DG_EINVAL, "export capacity %lld < %lld", (long long)*m, (long long)count);
+    hipStream_t s = g->stream;
+    Dir &d = g->fwd;
+    DBuf<int64_t> off2;
+    DBuf<int32_t> col2, w2, row;
+    DG_TRY(off2.ensure(g->n + 1));
+    DG_TRY(col2.ensure(arcs + 1));
+    DG_TRY(w2.ensure(arcs + 1));
+    DG_TRY(row.ensure(arcs + 1));
+    int rc = merge_into(g, d, off2.p, col2.p, w2.p, arcs);
+    if (rc == DG_OK && arcs > 0)
+        hipLaunchKernelGGL(k_rows_of_entries, dim3(grid_for(arcs)), dim3(256), 0, s, g->n, arcs, off2.p,
+                           row.p);
+    std::vector<int32_t> hr(arcs), hc(arcs), hw(arcs);
+    if (rc == DG_OK && arcs > 0) {
+        (void)hipMemcpyAsync(hr.data(), row.p, arcs * 4, hipMemcpyDeviceToHost, s);
+        (void)hipMemcpyAsync(hc.data(), col2.p, arcs * 4, hipMemcpyDeviceToHost, s);
+        (void)hipMemcpyAsync(hw.data(), w2.p, arcs * 4, hipMemcpyDeviceToHost, s);
+    }
+    hipError_t e = hipStreamSynchronize(s);
+    off2.release(); col2.release(); w2.release(); row.release();
+    if (rc != DG_OK) return rc;
+    if (e != hipSuccess) return set_error(DG_EDEVICE, "export copy failed: %s", hipGetErrorString(e));
+    int64_t o = 0;
+    for (int64_t i = 0; i < arcs; ++i) {
+        int32_t u = hr[i], v = (int32_t)((uint32_t)hc[i] & ID_MASK);
+        if (g->undirected && u > v) continue;
+        src[o] = u;
+        dst[o] = v;
+        if (w) w[o] = hw[i];
+        ++o;
+    }
+    *m = o;
+    return DG_OK;
+}
+
+// ---------------------------------------------------------------- batch application
+
+// Validation of a whole chunk before any change (rejects self-loops, ids outside
+// [0, n), ops other than 0/1 and insert weights outside [1, 2^30)).
+__global__ void k_validate_batch(int64_t k, const int32_t *s, const int32_t *d, const int32_t *w,
+                                 const uint8_t *op, int32_t n, int64_t *cnt) {
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < k; base += gstride()) {
+        int64_t i = base + threadIdx.x;
+        bool valid = i < k;
+        bool bad = false, del = false, ins = false;
+        if (valid) {
+            int32_t u = s[i], v = d[i];
+            uint8_t o = op[i];
+            bad = u < 0 || u >= n || v < 0 || v >= n || u == v || o > 1;
+            if (o == 1 && w) bad |= (w[i] < 1 || w[i] >= (1 << 30));
+            del = !bad && o == 0;
+            ins = !bad && o == 1;
+        }
+        if (bad) atomicOr((unsigned long long *)&cnt[C_ERR], 1ull);
+        wave_count(&cnt[C_NDEL], del);
+        wave_count(&cnt[C_NINS], ins);
+    }
+}
+
+// Split the chunk into deletion arcs and insertion keys (undirected updates give
+// both arcs).
+__global__ void k_expand_batch(int64_t k, const int32_t *s, const int32_t *d, const int32_t *w,
+                               const uint8_t *op, int B, int undirected, int32_t *ddu, int32_t *ddv,
+                               uint64_t *ikey, int32_t *iw, int64_t *cnt) {
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < k; base += gstride()) {
+        int64_t i = base + threadIdx.x;
+        bool valid = i < k;
+        bool del = valid && op[i] == 0;
+        bool ins = valid && op[i] == 1;
+        uint32_t u0 = valid ? (uint32_t)s[i] : 0, v0 = valid ? (uint32_t)d[i] : 0;
+        int32_t wt = (valid && w) ? w[i] : 1;
+        for (int r = 0; r < (undirected ? 2 : 1); ++r) {
+            uint32_t u = r ? v0 : u0, v = r ? u0 : v0;
+            int64_t pd = wave_append(&cnt[C_AUX0], del);
+            if (del) { ddu[pd] = (int32_t)u; ddv[pd] = (int32_t)v; }
+            int64_t pi = wave_append(&cnt[C_AUX1], ins);
+            if (ins) { ikey[pi] = ((uint64_t)u << B) | v; iw[pi] = wt; }
+        }
+    }
+}
+
+// updateCSRDel, first half: find each deletion arc and MARK it (the old graph is
+// still intact for the pre-hooks).  The atomic MARK also dedups repeated
+// deletions of one arc.  Applied arcs are listed with their slot
+// (>= 0: base position, <= -2: diff position -2-p).
+__global__ void k_mark_deletes(int64_t na, const int32_t *ddu, const int32_t *ddv,
+                               const int64_t *__restrict__ off, int32_t *col,
+                               const int64_t *__restrict__ doff, int32_t *dcol, int undirected,
+                               int32_t *adu, int32_t *adv, int64_t *adpos, int32_t *tcu, int32_t *tcv,
+                               int64_t *cnt) {
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < na; base += gstride()) {
+        int64_t i = base + threadIdx.x;
+        bool applied = false;
+        int64_t pos = 0;
+        int32_t u = 0, v = 0;
+        if (i < na) {
+            u = ddu[i];
+            v = ddv[i];
+            int64_t p = find_sorted(col, off[u], off[u + 1], (uint32_t)v);
+            if (p >= 0) {
+                if (!((uint32_t)col[p] & DEAD)) {
+                    uint32_t old = atomicOr((unsigned int *)&col[p], MARK);
+                    if (!(old & MARK)) { applied = true; pos = p; }
+                }
+            } else {
+                int64_t q = find_sorted(dcol, doff[u], doff[u + 1], (uint32_t)v);
+                if (q >= 0 && !((uint32_t)dcol[q] & DEAD)) {
+                    uint32_t old = atomicOr((unsigned int *)&dcol[q], MARK);
+                    if (!(old & MARK)) { applied = true; pos = -2 - q; }
+                }
+            }
+        }
+        int64_t slot = wave_append(&cnt[C_ADEL], applied);
+        if (applied) { adu[slot] = u; adv[slot] = v; adpos[slot] = pos; }
+        bool tc = applied && undirected && u < v;
+        int64_t ts = wave_append(&cnt[C_TCDEL], tc);
+        if (tc) { tcu[ts] = u; tcv[ts] = v; }
+    }
+}
+
+// Classify the sorted insertion keys: the first key of each run takes the
+// smallest weight of the run; it is IGNORED if the edge is live and not being
+// deleted, REVIVED in place if its slot is a tombstone or is being deleted in this
+// chunk (delete + insert ends present with the new weight), otherwise NEW.
+__global__ void k_classify_inserts(int64_t ni, const uint64_t *key, int32_t *iw, int B,
+                                   const int64_t *__restrict__ off, const int32_t *__restrict__ col,
+                                   const int64_t *__restrict__ doff, const int32_t *__restrict__ dcol,
+                                   int undirected, int64_t *isnew, int32_t *aiu, int32_t *aiv,
+                                   int32_t *aiw, int64_t *aipos, int64_t *cnt) {
+    const uint64_t mask = (1ull << B) - 1;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < ni; base += gstride()) {
+        int64_t i = base + threadIdx.x;
+        bool valid = i < ni;
+        bool head = valid && (i == 0 || key[i] != key[i - 1]);
+        int act = 0;  // 0 none, 1 new, 2 revive, 3 ignore
+        int64_t pos = -1;
+        int32_t u = 0, v = 0, wt = 0;
+        if (head) {
+            uint64_t kk = key[i];
+            wt = iw[i];
+            for (int64_t j = i + 1; j < ni && key[j] == kk; ++j) wt = min(wt, iw[j]);
+            iw[i] = wt;
+            u = (int32_t)(kk >> B);
+            v = (int32_t)(kk & mask);
+            int64_t p = find_sorted(col, off[u], off[u + 1], (uint32_t)v);
+            if (p >= 0) {
+                if ((uint32_t)col[p] & (DEAD | MARK)) { act = 2; pos = p; }
+                else act = 3;
+            } else {
+                int64_t q = find_sorted(dcol, doff[u], doff[u + 1], (uint32_t)v);
+                if (q >= 0) {
+                    if ((uint32_t)dcol[q] & (DEAD | MARK)) { act = 2; pos = -2 - q; }
+                    else act = 3;
+                } else {
+                    act = 1;
+                }
+            }
+        }
+        if (valid) isnew[i] = act == 1;
+        bool applied = act == 1 || act == 2;
+        int64_t slot = wave_append(&cnt[C_AINS], applied);
+        if (applied) { aiu[slot] = u; aiv[slot] = v; aiw[slot] = wt; aipos[slot] = pos; }
+        wave_count(&cnt[C_NEW], act == 1);
+        wave_count(&cnt[C_IGNINS], valid && act != 1 && act != 2);
+        wave_count(&cnt[C_DISTINCT], head);
+    }
+    (void)undirected;
+}
+
+__global__ void k_compact_new(int64_t ni, const uint64_t *key, const int32_t *iw, const int64_t *isnew,
+                              const int64_t *pos, uint64_t *nkey, int32_t *nw) {
+    for (int64_t i = gtid(); i < ni; i += gstride())
+        if (isnew[i]) { nkey[pos[i]] = key[i]; nw[pos[i]] = iw[i]; }
+}
+
+// TC needs the inserted undirected edges once each.
+__global__ void k_list_tc_inserts(int64_t na, const int32_t *aiu, const int32_t *aiv, int32_t *tcu,
+                                  int32_t *tcv, int64_t *cnt) {
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < na; base += gstride()) {
+        int64_t i = base + threadIdx.x;
+        bool p = i < na && aiu[i] < aiv[i];
+        int64_t s = wave_append(&cnt[C_TCINS], p);
+        if (p) { tcu[s] = aiu[i]; tcv[s] = aiv[i]; }
+    }
+}
+
+// updateCSRDel, second half: turn the MARKs of applied deletions into tombstones.
+__global__ void k_commit_deletes(int64_t na, const int32_t *adu, const int64_t *adpos, int32_t *col,
+                                 int32_t *dcol, int32_t *deg, int32_t *ntomb, int32_t *ttomb,
+                                 int64_t *cnt) {
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < na; base += gstride()) {
+        int64_t i = base + threadIdx.x;
+        bool inbase = false, indiff = false;
+        if (i < na) {
+            int32_t u = adu[i];
+            int64_t p = adpos[i];
+            if (p >= 0) {
+                col[p] = (int32_t)(((uint32_t)col[p] & ~MARK) | DEAD);
+                atomicAdd(&ntomb[u], 1);
+                atomicAdd(&ttomb[p / TILE], 1);
+                inbase = true;
+            } else {
+                int64_t q = -2 - p;
+                dcol[q] = (int32_t)(((uint32_t)dcol[q] & ~MARK) | DEAD);
+                indiff = true;
+            }
+            atomicSub(&deg[u], 1);
+        }
+        wave_count(&cnt[C_AUX2], inbase);
+        wave_count(&cnt[C_AUX3], indiff);
+    }
+}
+
+// Reverse direction of a directed graph: find (v, u) in row v and tombstone it.
+__global__ void k_commit_deletes_rev(int64_t na, const int32_t *adu, const int32_t *adv,
+                                     const int64_t *__restrict__ off, int32_t *col,
+                                     const int64_t *__restrict__ doff, int32_t *dcol, int32_t *deg,
+                                     int32_t *ntomb, int32_t *ttomb, int64_t *cnt) {
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < na; base += gstride()) {
+        int64_t i = base + threadIdx.x;
+        bool inbase = false, indiff = false;
+        if (i < na) {
+            int32_t u = adu[i], v = adv[i];
+            int64_t p = find_sorted(col, off[v], off[v + 1], (uint32_t)u);
+            if (p >= 0) {
+                col[p] = (int32_t)(((uint32_t)col[p] & ~MARK) | DEAD);
+                atomicAdd(&ntomb[v], 1);
+                atomicAdd(&ttomb[p / TILE], 1);
+                inbase = true;
+            } else {
+                int64_t q = find_sorted(dcol, doff[v], doff[v + 1], (uint32_t)u);
+                if (q >= 0) {
+                    dcol[q] = (int32_t)(((uint32_t)dcol[q] & ~MARK) | DEAD);
+                    indiff = true;
+                }
+            }
+            if (inbase || indiff) atomicSub(&deg[v], 1);
+        }
+        wave_count(&cnt[C_AUX2], inbase);
+        wave_count(&cnt[C_AUX3], indiff);
+    }
+}
+
+// updateCSRAdd for slots that already exist: revive a tombstone in place
+// (sorted hole reuse) with the new weight; NEW arcs only bump the degree here.
+// Inserted entries carry MARK until the post-hooks have run.
+__global__ void k_revive(int64_t na, const int32_t *aiu, const int32_t *aiv, const int32_t *aiw,
+                         const int64_t *aipos, int reverse, const int64_t *__restrict__ off, int32_t *col,
+                         int32_t *w, const int64_t *__restrict__ doff, int32_t *dcol, int32_t *dw,
+                         int32_t *deg, int32_t *ntomb, int32_t *ttomb, int B, uint64_t *rkey,
+                         int32_t *rw, int64_t *cnt) {
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < na; base += gstride()) {
+        int64_t i = base + threadIdx.x;
+        bool revived_base = false, is_new = false;
+        int32_t r = 0, c = 0, wt = 0;
+        if (i < na) {
+            int32_t u = aiu[i], v = aiv[i];
+            wt = aiw[i];
+            r = reverse ? v : u;
+            c = reverse ? u : v;
+            int64_t p = aipos[i];
+            if (p == -1) {
+                is_new = true;
+            } else {
+                if (reverse) {  // locate the slot in the reverse store
+                    p = find_sorted(col, off[r], off[r + 1], (uint32_t)c);
+                    if (p < 0) {
+                        int64_t q = find_sorted(dcol, doff[r], doff[r + 1], (uint32_t)c);
+                        p = q >= 0 ? -2 - q : -1;
+                    }
+                }
+                if (p == -1) {
+                    // not present in the reverse store: cannot happen for a consistent graph
+                } else if (p >= 0) {
+                    col[p] = (int32_t)((uint32_t)c | MARK);
+                    w[p] = wt;
+                    atomicSub(&ntomb[r], 1);
+                    atomicSub(&ttomb[p / TILE], 1);
+                    revived_base = true;
+                } else {
+                    int64_t q = -2 - p;
+                    dcol[q] = (int32_t)((uint32_t)c | MARK);
+                    dw[q] = wt;
+                }
+            }
+            atomicAdd(&deg[r], 1);
+        }
+        wave_count(&cnt[C_AUX2], revived_base);
+        if (rkey) {
+            int64_t s = wave_append(&cnt[C_AUX1], is_new);
+            if (is_new) { rkey[s] = ((uint64_t)(uint32_t)r << B) | (uint32_t)c; rw[s] = wt; }
+        }
+    }
+}
+
+// Drop MARK from the entries this chunk inserted.
+__global__ void k_clear_marks(int64_t na, const int32_t *aiu, const int32_t *aiv, int reverse,
+                              const int64_t *__restrict__ off, int32_t *col,
+                              const int64_t *__restrict__ doff, int32_t *dcol) {
+    for (int64_t i = gtid(); i < na; i += gstride()) {
+        int32_t r = reverse ? aiv[i] : aiu[i];
+        int32_t c = reverse ? aiu[i] : aiv[i];
+        int64_t p = find_sorted(col, off[r], off[r + 1], (uint32_t)c);
+        if (p >= 0) {
+            col[p] = (int32_t)((uint32_t)col[p] & ~MARK);
+        } else {
+            int64_t q = find_sorted(dcol, doff[r], doff[r + 1], (uint32_t)c);
+            if (q >= 0) dcol[q] = (int32_t)((uint32_t)dcol[q] & ~MARK);
+        }
+    }
+}
+
+// Diff rebuild: merge the live old diff entries with the sorted NEW keys (keys
+// are distinct, so each side's output slot is its rank plus the count of smaller
+// keys on the other side) and drop the tombstoned diff entries.
+__global__ void k_live_flags(int64_t dm, const int32_t *dcol, int64_t *flags) {
+    for (int64_t i = gtid(); i <= dm; i += gstride())
+        flags[i] = i < dm ? !((uint32_t)dcol[i] & DEAD) : 0;
+}
+
+__global__ void k_diff_old(int64_t dm, const uint64_t *dkey, const int32_t *dcol, const int32_t *dw,
+                           const int64_t *rank, const uint64_t *nkey, int64_t nk, uint64_t *dkey2,
+                           int32_t *dcol2, int32_t *dw2, int64_t cap) {
+    for (int64_t i = gtid(); i < dm; i += gstride()) {
+        if ((uint32_t)dcol[i] & DEAD) continue;
+        int64_t p = rank[i] + lower_key(nkey, 0, nk, dkey[i]);
+        if (p >= cap) continue;
+        dkey2[p] = dkey[i];
+        dcol2[p] = dcol[i];
+        dw2[p] = dw[i];
+    }
+}
+
+__global__ void k_diff_new(int64_t nk, const uint64_t *nkey, const int32_t *nw, const uint64_t *dkey,
+                           int64_t dm, const int64_t *rank, int B, uint64_t *dkey2, int32_t *dcol2,
+                           int32_t *dw2, int64_t cap) {
+    const uint64_t mask = (1ull << B) - 1;
+    for (int64_t j = gtid(); j < nk; j += gstride()) {
+        int64_t p = j + rank[lower_key(dkey, 0, dm, nkey[j])];
+        if (p >= cap) continue;
+        dkey2[p] = nkey[j];
+        dcol2[p] = (int32_t)((uint32_t)(nkey[j] & mask) | MARK);
+        dw2[p] = nw[j];
+    }
+}
+
+static int diff_rebuild(dg_graph *g, Dir &d, const uint64_t *nkey, const int32_t *nw, int64_t nk,
+                        int64_t killed) {
+    if (nk == 0 && killed == 0) return DG_OK;
+    hipStream_t s = g->stream;
+    Work &ws = g->ws;
+    const int64_t dm = d.dm;
+    DG_TRY(ws.scan64.ensure(2 * ((size_t)dm + 1)));
+    int64_t *flags = ws.scan64.p;
+    int64_t *rank = flags + (dm + 1);
+    hipLaunchKernelGGL(k_live_flags, dim3(grid_for(dm + 1)), dim3(256), 0, s, dm, d.dcol.p, flags);
+    DG_TRY(scan_excl(g, flags, rank, dm + 1));
+    const int64_t live = dm - killed;
+    const int64_t dm2 = live + nk;
+    DG_TRY(d.dkey2.ensure(dm2 + 1));
+    DG_TRY(d.dcol2.ensure(dm2 + 1));
+    DG_TRY(d.dw2.ensure(dm2 + 1));
+    if (dm > 0)
+        hipLaunchKernelGGL(k_diff_old, dim3(grid_for(dm)), dim3(256), 0, s, dm, d.dkey.p, d.dcol.p,
+                           d.dw.p, rank, nkey, nk, d.dkey2.p, d.dcol2.p, d.dw2.p, dm2);
+    if (nk > 0)
+        hipLaunchKernelGGL(k_diff_new, dim3(grid_for(nk)), dim3(256), 0, s, nk, nkey, nw, d.dkey.p, dm,
+                           rank, d.keybits, d.dkey2.p, d.dcol2.p, d.dw2.p, dm2);
+    hipLaunchKernelGGL(k_row_offsets, dim3(grid_for(g->n + 1)), dim3(256), 0, s, g->n, d.dkey2.p, dm2,
+                       d.keybits, d.doff.p);
+    DG_HIP(hipGetLastError());
+    d.dkey.swap(d.dkey2);
+    d.dcol.swap(d.dcol2);
+    d.dw.swap(d.dw2);
+    d.dm = dm2;
+    d.tomb_diff = 0;
+    return DG_OK;
+}
+
+// Wrappers that time a phase with HIP events on the graph's stream.
+struct PhaseTimer {
+    dg_graph *g;
+    int a, b;
+    float *acc;
+    PhaseTimer(dg_graph *g_, int slot, float *acc_) : g(g_), a(2 * slot), b(2 * slot + 1), acc(acc_) {
+        (void)hipEventRecord(g->ws.ev[a], g->stream);
+    }
+    void stop() {
+        (void)hipEventRecord(g->ws.ev[b], g->stream);
+        (void)hipEventSynchronize(g->ws.ev[b]);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, g->ws.ev[a], g->ws.ev[b]);
+        if (acc) *acc += ms;
+    }
+};
+
+int apply_chunk(dg_graph *g, int64_t k, const int32_t *src, const int32_t *dst, const int32_t *w,
+                const uint8_t *op, bool dev, dg_batch_stats *st) {
+    hipStream_t s = g->stream;
+    Work &ws = g->ws;
+    Dir &F = g->fwd;
+    Dir &R = *g->rev;
+    const bool und = g->undirected;
+    const int B = F.keybits;
+    dg_batch_stats dummy{};
+    if (!st) st = &dummy;
+    PhaseTimer t_all(g, 7, &st->t_total_ms);
+    PhaseTimer t_val(g, 0, &st->t_validate_ms);
+
+    // ---- stage the chunk on the device
+    const int32_t *ds = src, *dd = dst, *dw = w;
+    const uint8_t *dop = op;
+    if (!dev) {
+        DG_TRY(ws.bsrc.ensure(k + 1));
+        DG_TRY(ws.bdst.ensure(k + 1));
+        DG_TRY(ws.bop.ensure(k + 1));
+        DG_HIP(hipMemcpyAsync(ws.bsrc.p, src, k * 4, hipMemcpyHostToDevice, s));
+        DG_HIP(hipMemcpyAsync(ws.bdst.p, dst, k * 4, hipMemcpyHostToDevice, s));
+        DG_HIP(hipMemcpyAsync(ws.bop.p, op, k, hipMemcpyHostToDevice, s));
+        ds = ws.bsrc.p;
+        dd = ws.bdst.p;
+        dop = ws.bop.p;
+        if (w) {
+            DG_TRY(ws.bw.ensure(k + 1));
+            DG_HIP(hipMemcpyAsync(ws.bw.p, w, k * 4, hipMemcpyHostToDevice, s));
+            dw = ws.bw.p;
+        }
+    }
+    // ---- validate and count (no change to the graph before this passes)
+    DG_TRY(counters_clear(g));
+    hipLaunchKernelGGL(k_validate_batch, dim3(grid_for(k)), dim3(256), 0, s, k, ds, dd, dw, dop, g->n,
+                       ws.dcnt);
+    DG_HIP(hipGetLastError());
+    DG_TRY(counters_read(g));
+    if (ws.hcnt[C_ERR]) {
+        t_val.stop();
+        t_all.stop();
+        return set_error(DG_EINVAL, "batch holds a self-loop, an id outside [0,n), an op other than 0/1 or a weight outside [1,2^30)");
+    }
+    const int rep = und ? 2 : 1;
+    const int64_t nda = ws.hcnt[C_NDEL] * rep, nia = ws.hcnt[C_NINS] * rep;
+    DG_TRY(ws.ddu.ensure(nda + 1)); DG_TRY(ws.ddv.ensure(nda + 1));
+    DG_TRY(ws.adu.ensure(nda + 1)); DG_TRY(ws.adv.ensure(nda + 1)); DG_TRY(ws.adpos.ensure(nda + 1));
+    DG_TRY(ws.ikey.ensure(nia + 1)); DG_TRY(ws.ikey_s.ensure(nia + 1));
+    DG_TRY(ws.iw.ensure(nia + 1)); DG_TRY(ws.iw_s.ensure(nia + 1));
+    DG_TRY(ws.aiu.ensure(nia + 1)); DG_TRY(ws.aiv.ensure(nia + 1)); DG_TRY(ws.aiw.ensure(nia + 1));
+    DG_TRY(ws.aipos.ensure(nia + 1));
+    DG_TRY(ws.nkey.ensure(nia + 1)); DG_TRY(ws.nw.ensure(nia + 1));
+    DG_TRY(ws.rkey.ensure(nia + 1)); DG_TRY(ws.rkey_s.ensure(nia + 1));
+    DG_TRY(ws.rw.ensure(nia + 1)); DG_TRY(ws.rw_s.ensure(nia + 1));
+    DG_TRY(ws.tcu.ensure(nda + nia + 1)); DG_TRY(ws.tcv.ensure(nda + nia + 1));
+    DG_TRY(ws.scan64.ensure(2 * ((size_t)nia + 1)));
+    hipLaunchKernelGGL(k_expand_batch, dim3(grid_for(k)), dim3(256), 0, s, k, ds, dd, dw, dop, B,
+                       (int)und, ws.ddu.p, ws.ddv.p, ws.ikey.p, ws.iw.p, ws.dcnt);
+    DG_HIP(hipGetLastError());
+    DG_TRY(sort_pairs(g, ws.ikey.p, ws.ikey_s.p, ws.iw.p, ws.iw_s.p, nia, 2 * B));
+    // ---- updateCSRDel (mark) and insert classification against the old graph
+    if (nda > 0)
+        hipLaunchKernelGGL(k_mark_deletes, dim3(grid_for(nda)), dim3(256), 0, s, nda, ws.ddu.p, ws.ddv.p,
+                           F.off.p, F.col.p, F.doff.p, F.dcol.p, (int)und, ws.adu.p, ws.adv.p, ws.adpos.p,
+                           ws.tcu.p, ws.tcv.p, ws.dcnt);
+    int64_t *isnew = ws.scan64.p, *newpos = ws.scan64.p + (nia + 1);
+    if (nia > 0)
+        hipLaunchKernelGGL(k_classify_inserts, dim3(grid_for(nia)), dim3(256), 0, s, nia, ws.ikey_s.p,
+                           ws.iw_s.p, B, F.off.p, F.col.p, F.doff.p, F.dcol.p, (int)und, isnew, ws.aiu.p,
+                           ws.aiv.p, ws.aiw.p, ws.aipos.p, ws.dcnt);
+    DG_HIP(hipGetLastError());
+    if (nia > 0) {
+        DG_TRY(scan_excl(g, isnew, newpos, nia));
+        hipLaunchKernelGGL(k_compact_new, dim3(grid_for(nia)), dim3(256), 0, s, nia, ws.ikey_s.p,
+                           ws.iw_s.p, isnew, newpos, ws.nkey.p, ws.nw.p);
+        DG_HIP(hipGetLastError());
+    }
+    DG_TRY(counters_read(g));
+    const int64_t adel = ws.hcnt[C_ADEL], ains = ws.hcnt[C_AINS], nnew = ws.hcnt[C_NEW];
+    const int64_t tcdel = ws.hcnt[C_TCDEL];
+    t_val.stop();
+
+    // ---- pre-hooks on the old graph (deleted arcs still present, MARKed)
+    for (dg_query *q : g->queries) {
+        if (q->kind == Q_SSSP) {
+            PhaseTimer t(g, 2, &st->t_sssp_ms);
+            DG_TRY(sssp_pre_delete(q, adel));
+            t.stop();
+        } else if (q->kind == Q_TC && tcdel > 0) {
+            PhaseTimer t(g, 4, &st->t_tc_ms);
+            uint64_t sum6 = 0;
+            DG_TRY(tc_delta(g, ws.tcu.p, ws.tcv.p, tcdel, &sum6));
+            q->tc -= sum6 / 6;
+            st->tc_removed += (int64_t)(sum6 / 6);
+            t.stop();
+        }
+    }
+
+    // ---- commit deletions, revive slots, rebuild the diff (both directions)
+    PhaseTimer t_upd(g, 1, &st->t_update_ms);
+    DG_TRY(counters_clear(g));
+    if (adel > 0) {
+        hipLaunchKernelGGL(k_commit_deletes, dim3(grid_for(adel)), dim3(256), 0, s, adel, ws.adu.p,
+                           ws.adpos.p, F.col.p, F.dcol.p, F.deg.p, F.ntomb.p, F.ttomb.p, ws.dcnt);
+        if (!und)
+            hipLaunchKernelGGL(k_commit_deletes_rev, dim3(grid_for(adel)), dim3(256), 0, s, adel, ws.adu.p,
+                               ws.adv.p, R.off.p, R.col.p, R.doff.p, R.dcol.p, R.deg.p, R.ntomb.p,
+                               R.ttomb.p, ws.dcnt + 8);
+    }
+    DG_HIP(hipGetLastError());
+    DG_TRY(counters_read(g));
+    const int64_t killed_base_f = ws.hcnt[C_AUX2], killed_diff_f = ws.hcnt[C_AUX3];
+    const int64_t killed_base_r = und ? 0 : ws.hcnt[C_AUX2 + 8], killed_diff_r = und ? 0 : ws.hcnt[C_AUX3 + 8];
+    DG_TRY(counters_clear(g));
+    if (ains > 0) {
+        hipLaunchKernelGGL(k_revive, dim3(grid_for(ains)), dim3(256), 0, s, ains, ws.aiu.p, ws.aiv.p,
+                           ws.aiw.p, ws.aipos.p, 0, F.off.p, F.col.p, F.w.p, F.doff.p, F.dcol.p, F.dw.p,
+                           F.deg.p, F.ntomb.p, F.ttomb.p, B, (uint64_t *)nullptr, (int32_t *)nullptr,
+                           ws.dcnt);
+        if (!und)
+            hipLaunchKernelGGL(k_revive, dim3(grid_for(ains)), dim3(256), 0, s, ains, ws.aiu.p, ws.aiv.p,
+                               ws.aiw.p, ws.aipos.p, 1, R.off.p, R.col.p, R.w.p, R.doff.p, R.dcol.p,
+                               R.dw.p, R.deg.p, R.ntomb.p, R.ttomb.p, B, ws.rkey.p, ws.rw.p,
+                               ws.dcnt + 8);
+        if (und)
+            hipLaunchKernelGGL(k_list_tc_inserts, dim3(grid_for(ains)), dim3(256), 0, s, ains, ws.aiu.p,
+                               ws.aiv.p, ws.tcu.p + tcdel, ws.tcv.p + tcdel, ws.dcnt);
+    }
+    DG_HIP(hipGetLastError());
+    DG_TRY(counters_read(g));
+    const int64_t revived_base_f = ws.hcnt[C_AUX2];
+    const int64_t revived_base_r = und ? 0 : ws.hcnt[C_AUX2 + 8];
+    const int64_t tcins = ws.hcnt[C_TCINS];
+    F.tomb_base += killed_base_f - revived_base_f;
+    DG_TRY(diff_rebuild(g, F, ws.nkey.p, ws.nw.p, nnew, killed_diff_f));
+    if (!und) {
+        R.tomb_base += killed_base_r - revived_base_r;
+        DG_TRY(sort_pairs(g, ws.rkey.p, ws.rkey_s.p, ws.rw.p, ws.rw_s.p, nnew, 2 * B));
+        DG_TRY(diff_rebuild(g, R, ws.rkey_s.p, ws.rw_s.p, nnew, killed_diff_r));
+    }
+    g->m_live += ains - adel;
+    t_upd.stop();
+
+    // ---- merge policy (Section 3.5)
+    {
+        double thr = g->cfg.merge_threshold;
+        double live = (double)(g->m_live > 0 ? g->m_live : 1);
+        bool need = thr < 0 ? (F.dm + F.tomb_base > 0)
+                            : ((double)(F.dm + F.tomb_base) > thr * live ||
+                               (!und && (double)(R.dm + R.tomb_base) > thr * live));
+        if (need) {
+            PhaseTimer t(g, 3, &st->t_merge_ms);
+            DG_TRY(merge_dir(g, F, g->m_live));
+            if (!und) DG_TRY(merge_dir(g, g->rev_own, g->m_live));
+            st->merged += 1;
+            t.stop();
+        }
+    }
+
+    // ---- post-hooks on the new graph
+    for (dg_query *q : g->queries) {
+        if (q->kind == Q_SSSP) {
+            PhaseTimer t(g, 2, &st->t_sssp_ms);
+            DG_TRY(sssp_post_update(q, adel, ains, st));
+            t.stop();
+        } else if (q->kind == Q_PR) {
+            PhaseTimer t(g, 5, &st->t_pr_ms);
+            DG_TRY(pr_post_update(q, adel, ains, st));
+            t.stop();
+        } else if (q->kind == Q_TC && tcins > 0) {
+            PhaseTimer t(g, 4, &st->t_tc_ms);
+            uint64_t sum6 = 0;
+            DG_TRY(tc_delta(g, ws.tcu.p + tcdel, ws.tcv.p + tcdel, tcins, &sum6));
+            q->tc += sum6 / 6;
+            st->tc_added += (int64_t)(sum6 / 6);
+            t.stop();
+        }
+    }
+    // ---- drop the MARKs of inserted entries
+    if (ains > 0) {
+        hipLaunchKernelGGL(k_clear_marks, dim3(grid_for(ains)), dim3(256), 0, s, ains, ws.aiu.p, ws.aiv.p,
+                           0, F.off.p, F.col.p, F.doff.p, F.dcol.p);
+        if (!und)
+            hipLaunchKernelGGL(k_clear_marks, dim3(grid_for(ains)), dim3(256), 0, s, ains, ws.aiu.p,
+                               ws.aiv.p, 1, R.off.p, R.col.p, R.doff.p, R.dcol.p);
+        DG_HIP(hipGetLastError());
+    }
+    t_all.stop();
+    const int64_t div = und ? 2 : 1;
+    st->updates += k;
+    st->deleted += adel / div;
+    st->inserted += ains / div;
+    st->ignored_del += (nda - adel) / div;
+    st->ignored_ins += (nia - ains) / div;
+    st->diff_entries = F.dm;
+    st->tombstones = F.tomb_base;
+    st->chunks += 1;
+    return DG_OK;
+}
+
+}  // namespace dg

@@ -1,0 +1,450 @@
+// PageRank: static Jacobi solve and the delta update on the affected set.
+//
+// The iteration is the one of the Appendix A PR listings (staticPR and the
+// Incremental/Decremental steps): double-buffered Jacobi,
+//     x'[v] = (1 - d)/n + d * sum_{u -> v} x[u] / outdeg(u),
+// repeated while the L1 step exceeds the tolerance and the iteration cap is not
+// reached, in FP64.  Like the listing, vertices without out-edges pass nothing
+// on; the ranks the library returns are x / sum(x), which equals the usual
+// PageRank with dangling mass spread uniformly (the fixed point of the
+// dangling-dropped system, normalised, satisfies the dangling-uniform equation
+// because the dangling redistribution vector equals the teleport vector).  Keeping
+// the dangling-dropped system is what makes the update local.
+//
+// Delta update for one batch (DynPR: OnDelete/OnAdd flag the heads of changed
+// arcs, propagateNodeFlags spreads the flags, Decremental/Incremental iterate on
+// the flagged vertices):
+//   seeds  = heads of every deleted or inserted arc, plus all current
+//            out-neighbours of every tail (their share x[u]/outdeg(u) changed);
+//   A      = everything reachable from the seeds along out-edges of the new graph
+//            (the complement of A has no in-edge from A and no changed in-edge, so
+//            its old values still satisfy the fixed-point equations);
+//   Jacobi on A only, warm-started from the previous x, until the L1 step <= tol.
+#include <algorithm>
+#include <cstring>
+
+#include "traverse.h"
+
+namespace dg {
+
+static inline int grid_for(int64_t n) {
+    int64_t g = (n + 255) / 256;
+    return (int)(g < 1 ? 1 : (g > 8192 ? 8192 : g));
+}
+
+constexpr int APPLY_GROUPS = 1024;
+
+__global__ void k_pr_init(int32_t n, double *x, double *contrib, const int32_t *deg) {
+    const double x0 = 1.0 / (double)n;
+    for (int64_t v = gtid(); v < n; v += gstride()) {
+        x[v] = x0;
+        contrib[v] = deg[v] > 0 ? x0 / (double)deg[v] : 0.0;
+    }
+}
+
+// Pull for the vertices of A (A == nullptr: all vertices): xn[v] = base + d * sum
+// of contrib over live in-edges.  Light vertices: a wave walks the edges of 64
+// vertices 64 slots at a time and reduces each vertex's slots with a segmented
+// scan in a fixed lane order; heavy vertices are cut into chunks (partial sums in
+// `part`, combined in chunk order by k_pr_finish).  Deterministic throughout.
+__global__ __launch_bounds__(256) void k_pr_pull(const int32_t *A, int64_t na, DirView g,
+                                                 const double *__restrict__ contrib, double base,
+                                                 double damp, double *xn, int64_t *hq, int64_t *hcount,
+                                                 int64_t *hv, int64_t *hvcount, int heavy_deg, int chunk) {
+    __shared__ double sacc[4][WAVE];
+    const int wslot = threadIdx.x / WAVE;
+    const int64_t wave_global = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / WAVE;
+    const int l = lane_id();
+    for (int64_t wb = wave_global * WAVE; wb < na; wb += nwaves * WAVE) {
+        const int64_t fi = wb + l;
+        int32_t v = -1;
+        int64_t ob = 0, od = 0;
+        int32_t db = 0, tot = 0;
+        if (fi < na) {
+            v = A ? A[fi] : (int32_t)fi;
+            ob = g.off[v];
+            db = (int32_t)(g.off[v + 1] - ob);
+            od = g.doff[v];
+            tot = db + (int32_t)(g.doff[v + 1] - od);
+        }
+        const bool heavy = tot > heavy_deg;
+        int32_t nch = heavy ? (tot + chunk - 1) / chunk : 0;
+        int64_t incl_ch = wave_incl_scan((int64_t)nch);
+        int64_t tot_ch = __shfl(incl_ch, WAVE - 1, WAVE);
+        int64_t base_ch = 0;
+        if (l == 0 && tot_ch > 0) base_ch = atomicAdd((unsigned long long *)hcount, (unsigned long long)tot_ch);
+        base_ch = __shfl(base_ch, 0, WAVE);
+        const int64_t slot0 = base_ch + incl_ch - nch;
+        for (int32_t c = 0; c < nch; ++c) hq[slot0 + c] = ((int64_t)v << 32) | (uint32_t)c;
+        int64_t hs = wave_append(hvcount, heavy);
+        if (heavy) {
+            hv[2 * hs] = ((int64_t)v << 32) | (uint32_t)nch;
+            hv[2 * hs + 1] = slot0;
+            tot = 0;
+        }
+        sacc[wslot][l] = 0.0;
+        __builtin_amdgcn_wave_barrier();
+        const int64_t incl = wave_incl_scan((int64_t)tot);
+        const int64_t excl = incl - tot;
+        const int64_t T = __shfl(incl, WAVE - 1, WAVE);
+        for (int64_t eb = 0; eb < T; eb += WAVE) {
+            const int64_t e = eb + l;
+            int o = 0;
+#pragma unroll
+            for (int step = 32; step > 0; step >>= 1) {
+                int cand = o + step;
+                int64_t x = __shfl(excl, cand, WAVE);
+                if (x <= e) o = cand;
+            }
+            const int64_t obo = __shfl(ob, o, WAVE);
+            const int64_t odo = __shfl(od, o, WAVE);
+            const int32_t dbo = __shfl(db, o, WAVE);
+            const int64_t exo = __shfl(excl, o, WAVE);
+            double val = 0.0;
+            if (e < T) {
+                int64_t j = e - exo;
+                uint32_t c = j < dbo ? (uint32_t)g.col[obo + j] : (uint32_t)g.dcol[odo + (j - dbo)];
+                if (!(c & DEAD)) val = contrib[c & ID_MASK];
+            }
+#pragma unroll
+            for (int d = 1; d < WAVE; d <<= 1) {
+                double y = __shfl_up(val, d, WAVE);
+                int oo = __shfl_up(o, d, WAVE);
+                if (l >= d && oo == o) val += y;
+            }
+            int on = __shfl_down(o, 1, WAVE);
+            if (l == WAVE - 1 || on != o) sacc[wslot][o] += val;
+            __builtin_amdgcn_wave_barrier();
+        }
+        if (v >= 0 && !heavy) xn[v] = base + damp * sacc[wslot][l];
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+__global__ __launch_bounds__(256) void k_pr_heavy(DirView g, const double *__restrict__ contrib,
+                                                  const int64_t *hq, const int64_t *hcount, int chunk,
+                                                  double *part) {
+    const int64_t wave_global = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / WAVE;
+    const int l = lane_id();
+    const int64_t nq = *hcount;
+    for (int64_t qi = wave_global; qi < nq; qi += nwaves) {
+        const int64_t ent = hq[qi];
+        const int32_t v = (int32_t)(ent >> 32);
+        const int32_t c = (int32_t)(ent & 0xffffffff);
+        const int64_t ob = g.off[v];
+        const int32_t db = (int32_t)(g.off[v + 1] - ob);
+        const int64_t od = g.doff[v];
+        const int32_t tot = db + (int32_t)(g.doff[v + 1] - od);
+        const int64_t s = (int64_t)c * chunk;
+        const int64_t e = min((int64_t)tot, s + chunk);
+        double acc = 0.0;
+        for (int64_t j = s + l; j < e; j += WAVE) {
+            uint32_t cc = j < db ? (uint32_t)g.col[ob + j] : (uint32_t)g.dcol[od + (j - db)];
+            if (!(cc & DEAD)) acc += contrib[cc & ID_MASK];
+        }
+        acc = wave_sum(acc);
+        if (l == 0) part[qi] = acc;
+    }
+}
+
+__global__ void k_pr_finish(const int64_t *hv, const int64_t *hvcount, const double *part, double base,
+                            double damp, double *xn) {
+    const int64_t nh = *hvcount;
+    for (int64_t i = gtid(); i < nh; i += gstride()) {
+        const int32_t v = (int32_t)(hv[2 * i] >> 32);
+        const int32_t nch = (int32_t)(hv[2 * i] & 0xffffffff);
+        const int64_t s0 = hv[2 * i + 1];
+        double sum = 0.0;
+        for (int32_t c = 0; c < nch; ++c) sum += part[s0 + c];
+        xn[v] = base + damp * sum;
+    }
+}
+
+// x := xn, contrib := x / outdeg on A, and the L1 step as fixed-order partials.
+__global__ __launch_bounds__(256) void k_pr_apply(const int32_t *A, int64_t na, const double *xn, double *x,
+                                                  double *contrib, const int32_t *deg, double *partials) {
+    __shared__ double red[256];
+    double acc = 0.0;
+    for (int64_t i = gtid(); i < na; i += gstride()) {
+        int32_t v = A ? A[i] : (int32_t)i;
+        double nv = xn[v];
+        acc += fabs(nv - x[v]);
+        x[v] = nv;
+        int32_t dg = deg[v];
+        contrib[v] = dg > 0 ? nv / (double)dg : 0.0;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
+}
+
+__global__ void k_sum_partials(const double *partials, int np, double *out) {
+    __shared__ double red[256];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < np; i += blockDim.x) acc += partials[i];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0];
+}
+
+__global__ __launch_bounds__(256) void k_sum_vec(const double *x, int64_t n, double *partials) {
+    __shared__ double red[256];
+    double acc = 0.0;
+    for (int64_t i = gtid(); i < n; i += gstride()) acc += x[i];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
+}
+
+__global__ void k_scale(const double *x, int64_t n, const double *sum, double *out) {
+    const double s = *sum;
+    for (int64_t i = gtid(); i < n; i += gstride()) out[i] = x[i] / s;
+}
+
+// Reach closure and seeds.
+struct ReachOp {
+    int32_t *stamp;
+    int32_t st;
+    int32_t *next;
+    int64_t *ncount;
+    __device__ bool vtx(int32_t, int32_t &pay) const { pay = 0; return true; }
+    __device__ void edge(bool valid, int32_t, int32_t, int32_t x, int32_t) const {
+        bool p = valid && atomicExch(&stamp[x], st) != st;
+        int64_t slot = wave_append(ncount, p);
+        if (p) next[slot] = x;
+    }
+};
+
+// Mark a list of vertices with stamp st; append the first-time ones to out.
+__global__ void k_mark_list(int64_t n, const int32_t *a, int32_t *stamp, int32_t st, int32_t *out,
+                            int64_t *count) {
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += gstride()) {
+        int64_t i = base + threadIdx.x;
+        bool p = false;
+        int32_t v = 0;
+        if (i < n) {
+            v = a[i];
+            p = atomicExch(&stamp[v], st) != st;
+        }
+        int64_t slot = wave_append(count, p);
+        if (p) out[slot] = v;
+    }
+}
+
+__global__ void k_refresh_contrib(int64_t n, const int32_t *u, const double *x, const int32_t *deg,
+                                  double *contrib) {
+    for (int64_t i = gtid(); i < n; i += gstride()) {
+        int32_t v = u[i];
+        int32_t dg = deg[v];
+        contrib[v] = dg > 0 ? x[v] / (double)dg : 0.0;
+    }
+}
+
+// ---- host side ---------------------------------------------------------------------------
+
+static int heavy_deg(dg_graph *g) { return g->cfg.heavy_degree > 0 ? g->cfg.heavy_degree : 512; }
+
+static int ensure_pr_ws(dg_graph *g) {
+    Work &ws = g->ws;
+    DG_TRY(ws.f0.ensure((size_t)g->n + 1));
+    DG_TRY(ws.f1.ensure((size_t)g->n + 1));
+    int64_t edges = std::max(g->fwd.m + g->fwd.dm, g->rev->m + g->rev->dm);
+    const int64_t qcap = 2 * (edges / heavy_deg(g) + 2) + g->n / 8 + 64;
+    DG_TRY(ws.heavy.ensure((size_t)qcap * 2 + 2 * (size_t)qcap * 2));
+    DG_TRY(ws.part.ensure((size_t)qcap + APPLY_GROUPS + 8));
+    return DG_OK;
+}
+
+// Jacobi on A (nullptr = all n vertices) until the L1 step <= tol or max_iter.
+static int pr_iterate(dg_graph *g, const int32_t *A, int64_t na, double damping, double tol,
+                      int32_t max_iter, double *x, double *xn, double *contrib, int32_t *iters,
+                      int32_t *conv) {
+    hipStream_t s = g->stream;
+    Work &ws = g->ws;
+    const int64_t qcap = 2 * (std::max(g->fwd.m + g->fwd.dm, g->rev->m + g->rev->dm) / heavy_deg(g) + 2) +
+                         g->n / 8 + 64;
+    int64_t *hq = reinterpret_cast<int64_t *>(ws.heavy.p);
+    int64_t *hv = hq + qcap;
+    double *partials = ws.part.p + qcap;
+    const double base = (1.0 - damping) / (double)g->n;
+    DirView rv = view(*g->rev);
+    int32_t it = 0;
+    *conv = 0;
+    double *dsum = reinterpret_cast<double *>(ws.dcnt + C_RED0);
+    while (it < max_iter && na > 0) {
+        DG_TRY(counters_clear(g));
+        int64_t blocks = std::min<int64_t>((na + 255) / 256, 65535);
+        hipLaunchKernelGGL(k_pr_pull, dim3((unsigned)blocks), dim3(256), 0, s, A, na, rv, contrib, base,
+                           damping, xn, hq, ws.dcnt + C_HEAVY, hv, ws.dcnt + C_AUX3, heavy_deg(g),
+                           heavy_deg(g));
+        hipLaunchKernelGGL(k_pr_heavy, dim3(1024), dim3(256), 0, s, rv, contrib, hq, ws.dcnt + C_HEAVY,
+                           heavy_deg(g), ws.part.p);
+        hipLaunchKernelGGL(k_pr_finish, dim3(64), dim3(256), 0, s, hv, ws.dcnt + C_AUX3, ws.part.p, base,
+                           damping, xn);
+        hipLaunchKernelGGL(k_pr_apply, dim3(APPLY_GROUPS), dim3(256), 0, s, A, na, xn, x, contrib,
+                           g->fwd.deg.p, partials);
+        hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, partials, APPLY_GROUPS, dsum);
+        DG_HIP(hipGetLastError());
+        DG_TRY(counters_read(g));
+        ++it;
+        double diff;
+        std::memcpy(&diff, &ws.hcnt[C_RED0], sizeof(double));
+        if (diff <= tol) {
+            *conv = 1;
+            break;
+        }
+    }
+    if (na == 0) *conv = 1;
+    *iters = it;
+    return DG_OK;
+}
+
+int pr_static_solve(dg_graph *g, double damping, double tol, int32_t max_iter, double *x,
+                    double *contrib, double *xn, int32_t *iters, int32_t *conv) {
+    DG_TRY(ensure_pr_ws(g));
+    hipLaunchKernelGGL(k_pr_init, dim3(grid_for(g->n)), dim3(256), 0, g->stream, g->n, x, contrib,
+                       g->fwd.deg.p);
+    DG_HIP(hipGetLastError());
+    return pr_iterate(g, nullptr, g->n, damping, tol, max_iter, x, xn, contrib, iters, conv);
+}
+
+static double tol_of(dg_query *q) {
+    double sc = q->g->cfg.pr_tol_scale > 0 ? q->g->cfg.pr_tol_scale : 1.0;
+    return q->tol * sc;
+}
+
+int pr_init(dg_query *q) {
+    dg_graph *g = q->g;
+    DG_TRY(q->x.ensure((size_t)g->n + 1));
+    DG_TRY(q->xn.ensure((size_t)g->n + 1));
+    DG_TRY(q->contrib.ensure((size_t)g->n + 1));
+    return pr_static_solve(g, q->damping, tol_of(q), q->max_iter, q->x.p, q->contrib.p, q->xn.p,
+                           &q->last_iters, &q->converged);
+}
+
+int pr_post_update(dg_query *q, int64_t adel, int64_t ains, dg_batch_stats *st) {
+    dg_graph *g = q->g;
+    hipStream_t s = g->stream;
+    Work &ws = g->ws;
+    if (adel + ains == 0) {
+        q->last_iters = 0;
+        return DG_OK;
+    }
+    DG_TRY(ensure_pr_ws(g));
+    const int64_t qcap = 2 * (std::max(g->fwd.m + g->fwd.dm, g->rev->m + g->rev->dm) / heavy_deg(g) + 2) +
+                         g->n / 8 + 64;
+    int64_t *hq = reinterpret_cast<int64_t *>(ws.heavy.p);
+    int32_t *Alist = ws.f0.p;
+    int32_t *S = ws.f1.p;
+    // tails of changed arcs (distinct)
+    int32_t st_s, st_a;
+    DG_TRY(next_stamp(g, &st_s));
+    DG_TRY(counters_clear(g));
+    if (adel > 0)
+        hipLaunchKernelGGL(k_mark_list, dim3(grid_for(adel)), dim3(256), 0, s, adel, ws.adu.p,
+                           ws.stamp.p, st_s, S, ws.dcnt + C_AUX0);
+    if (ains > 0)
+        hipLaunchKernelGGL(k_mark_list, dim3(grid_for(ains)), dim3(256), 0, s, ains, ws.aiu.p,
+                           ws.stamp.p, st_s, S, ws.dcnt + C_AUX0);
+    DG_HIP(hipGetLastError());
+    DG_TRY(counters_read(g));
+    const int64_t ns = ws.hcnt[C_AUX0];
+    // seeds: heads of changed arcs, then all out-neighbours of the tails
+    DG_TRY(next_stamp(g, &st_a));
+    DG_TRY(counters_clear(g));
+    if (adel > 0)
+        hipLaunchKernelGGL(k_mark_list, dim3(grid_for(adel)), dim3(256), 0, s, adel, ws.adv.p,
+                           ws.stamp.p, st_a, Alist, ws.dcnt + C_F0);
+    if (ains > 0)
+        hipLaunchKernelGGL(k_mark_list, dim3(grid_for(ains)), dim3(256), 0, s, ains, ws.aiv.p,
+                           ws.stamp.p, st_a, Alist, ws.dcnt + C_F0);
+    hipLaunchKernelGGL(k_refresh_contrib, dim3(grid_for(ns)), dim3(256), 0, s, ns, S, q->x.p, g->fwd.deg.p,
+                       q->contrib.p);
+    DG_HIP(hipGetLastError());
+    DG_TRY(counters_read(g));
+    int64_t na = ws.hcnt[C_F0];
+    ExpandArgs a;
+    a.g = view(g->fwd);
+    a.hq = hq;
+    a.hcount = ws.dcnt + C_HEAVY;
+    a.heavy_deg = heavy_deg(g);
+    a.chunk = heavy_deg(g);
+    (void)qcap;
+    {
+        DG_TRY(counters_clear(g));
+        a.F = S;
+        a.nf = ns;
+        ReachOp op{ws.stamp.p, st_a, Alist + na, ws.dcnt + C_F1};
+        DG_TRY(launch_expand(s, a, op, 1024));
+        DG_TRY(counters_read(g));
+        na += ws.hcnt[C_F1];
+    }
+    // forward closure (propagateNodeFlags): levels appended to Alist
+    int64_t lo = 0, hi = na;
+    while (hi > lo) {
+        DG_TRY(counters_clear(g));
+        a.F = Alist + lo;
+        a.nf = hi - lo;
+        ReachOp op{ws.stamp.p, st_a, Alist + hi, ws.dcnt + C_F1};
+        DG_TRY(launch_expand(s, a, op, 1024));
+        DG_TRY(counters_read(g));
+        lo = hi;
+        hi += ws.hcnt[C_F1];
+    }
+    na = hi;
+    int32_t iters = 0, conv = 0;
+    DG_TRY(pr_iterate(g, Alist, na, q->damping, tol_of(q), q->max_iter, q->x.p, q->xn.p, q->contrib.p,
+                      &iters, &conv));
+    q->last_iters = iters;
+    q->converged = conv;
+    if (st) {
+        st->pr_iterations += iters;
+        st->pr_affected += na;
+    }
+    return DG_OK;
+}
+
+// rank = x / sum(x), written to device memory (dev) or copied to the host.
+int pr_normalize(dg_graph *g, const double *x, double *rank, bool dev) {
+    hipStream_t s = g->stream;
+    DG_TRY(ensure_pr_ws(g));
+    double *partials = g->ws.part.p;
+    double *dsum = reinterpret_cast<double *>(g->ws.dcnt + C_RED0);
+    hipLaunchKernelGGL(k_sum_vec, dim3(APPLY_GROUPS), dim3(256), 0, s, x, (int64_t)g->n, partials);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, partials, APPLY_GROUPS, dsum);
+    DG_HIP(hipGetLastError());
+    if (dev) {
+        hipLaunchKernelGGL(k_scale, dim3(grid_for(g->n)), dim3(256), 0, s, x, (int64_t)g->n, dsum, rank);
+        DG_HIP(hipGetLastError());
+        DG_HIP(hipStreamSynchronize(s));
+        return DG_OK;
+    }
+    DBuf<double> tmp;
+    DG_TRY(tmp.ensure((size_t)g->n + 1));
+    hipLaunchKernelGGL(k_scale, dim3(grid_for(g->n)), dim3(256), 0, s, x, (int64_t)g->n, dsum, tmp.p);
+    hipError_t e1 = hipGetLastError();
+    hipError_t e2 = hipMemcpyAsync(rank, tmp.p, (size_t)g->n * sizeof(double), hipMemcpyDeviceToHost, s);
+    hipError_t e3 = hipStreamSynchronize(s);
+    tmp.release();
+    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess)
+        return set_error(DG_EDEVICE, "pagerank read failed");
+    return DG_OK;
+}
+
+int pr_read(dg_query *q, double *rank, bool dev) { return pr_normalize(q->g, q->x.p, rank, dev); }
+
+}  // namespace dg

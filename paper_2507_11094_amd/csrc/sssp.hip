@@ -1,0 +1,323 @@
+// Single-source shortest paths: static solve and the dynamic update.
+//
+// State per query: key[v] = (dist << 32) | parent as one 64-bit word, so the
+// paper's Min construct -- "<dist, modified_nxt, parent> = <Min(dist, d+w), True,
+// v>" in the Dynamic SSSP listing of Appendix A -- is a single atomicMin; ties in
+// distance resolve to the smaller parent id, and any tie is a valid tree.
+//
+// Dynamic update for one batch (Appendix A, DynSSSP: OnDelete, updateCSRDel,
+// Decremental, OnAdd, updateCSRAdd, Incremental), scheduled for a GPU:
+//   pre-hook  (old graph)  OnDelete: a deleted arc (u, v) with parent[v] == u cuts
+//                          v from the tree: v := (INF, -1).
+//   post-hook (new graph)  1. Decremental, phase 1: every vertex whose parent was
+//                             cut is cut too -- a frontier walk down the tree edges
+//                             instead of the listing's repeated full sweeps.
+//                          2. Decremental, phase 2: each cut vertex pulls
+//                             min(dist[u] + w) over its live in-edges once.
+//                          3. OnAdd: each inserted arc (u, v, w) relaxes v.
+//                          4. Incremental: push relaxation to a fixed point from
+//                             every vertex whose distance dropped in 2-3.
+// Why this reaches the static result: after step 1 every value is the length of a
+// path that still exists (uncut vertices keep their old tree path, and deletions
+// only lengthen paths), so all values are upper bounds; steps 2-4 then run
+// Bellman-Ford from every vertex that could violate d[v] <= d[u] + w, and the fixed
+// point of a Bellman-Ford started from achievable upper bounds and all possibly
+// violated edges is the exact distance (Section 3.1: only the affected part moves).
+#include "traverse.h"
+
+namespace dg {
+
+// ---- ops for the expansion kernel ---------------------------------------------
+
+// Push relaxation: payload = dist of the frontier vertex.
+struct RelaxOp {
+    uint64_t *key;
+    int32_t *stamp;
+    int32_t st;
+    int32_t *next;
+    int64_t *ncount;
+    __device__ bool vtx(int32_t v, int32_t &pay) const {
+        int32_t d = sssp_dist(__atomic_load_n(&key[v], __ATOMIC_RELAXED));
+        pay = d;
+        return d < INF;
+    }
+    __device__ void edge(bool valid, int32_t v, int32_t d, int32_t x, int32_t w) const {
+        bool push = false;
+        if (valid) {
+            uint64_t cand = sssp_pack(d + w, v);
+            uint64_t old = atomicMin((unsigned long long *)&key[x], (unsigned long long)cand);
+            if (cand < old && sssp_dist(cand) < sssp_dist(old))
+                push = atomicExch(&stamp[x], st) != st;
+        }
+        int64_t slot = wave_append(ncount, push);
+        if (push) next[slot] = x;
+    }
+};
+
+// Decremental phase 1: cut children whose tree parent is the frontier vertex.
+struct CutOp {
+    uint64_t *key;
+    int32_t *next;
+    int64_t *ncount;
+    __device__ bool vtx(int32_t, int32_t &pay) const { pay = 0; return true; }
+    __device__ void edge(bool valid, int32_t v, int32_t, int32_t x, int32_t) const {
+        bool cut = false;
+        if (valid) {
+            uint64_t k = key[x];
+            if (sssp_parent(k) == v) {
+                key[x] = sssp_pack(INF, -1);
+                cut = true;
+            }
+        }
+        int64_t slot = wave_append(ncount, cut);
+        if (cut) next[slot] = x;
+    }
+};
+
+// Decremental phase 2: pull over in-edges (reverse store); the frontier holds the
+// cut vertices, an edge (v <- x) offers dist[x] + w to v.
+struct PullOp {
+    uint64_t *key;
+    __device__ bool vtx(int32_t, int32_t &pay) const { pay = 0; return true; }
+    __device__ void edge(bool valid, int32_t v, int32_t, int32_t x, int32_t w) const {
+        if (!valid) return;
+        int32_t dx = sssp_dist(__atomic_load_n(&key[x], __ATOMIC_RELAXED));
+        if (dx >= INF) return;
+        atomicMin((unsigned long long *)&key[v], (unsigned long long)sssp_pack(dx + w, x));
+    }
+};
+
+// ---- plain kernels ---------------------------------------------------------------
+
+__global__ void k_sssp_init(int32_t n, uint64_t *key, int32_t source) {
+    for (int64_t v = gtid(); v < n; v += gstride()) key[v] = sssp_pack(v == source ? 0 : INF, -1);
+}
+
+// OnDelete: (u, v) deleted and parent[v] == u  ->  v := (INF, -1), v is a seed.
+__global__ void k_sssp_on_delete(int64_t na, const int32_t *adu, const int32_t *adv, uint64_t *key,
+                                 int32_t *seeds, int64_t *count) {
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < na; base += gstride()) {
+        int64_t i = base + threadIdx.x;
+        bool cut = false;
+        int32_t v = 0;
+        if (i < na) {
+            v = adv[i];
+            if (sssp_parent(key[v]) == adu[i]) {
+                key[v] = sssp_pack(INF, -1);
+                cut = true;
+            }
+        }
+        int64_t slot = wave_append(count, cut);
+        if (cut) seeds[slot] = v;
+    }
+}
+
+// After the pull: cut vertices that now have a finite distance start the push.
+__global__ void k_sssp_pulled(int64_t nc, const int32_t *cut, const uint64_t *key, int32_t *stamp,
+                              int32_t st, int32_t *front, int64_t *count) {
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < nc; base += gstride()) {
+        int64_t i = base + threadIdx.x;
+        bool p = false;
+        int32_t v = 0;
+        if (i < nc) {
+            v = cut[i];
+            p = sssp_dist(key[v]) < INF && atomicExch(&stamp[v], st) != st;
+        }
+        int64_t slot = wave_append(count, p);
+        if (p) front[slot] = v;
+    }
+}
+
+// OnAdd: each inserted arc relaxes its head once; improved heads join the push.
+__global__ void k_sssp_on_add(int64_t na, const int32_t *aiu, const int32_t *aiv, const int32_t *aiw,
+                              uint64_t *key, int32_t *stamp, int32_t st, int32_t *front,
+                              int64_t *count) {
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < na; base += gstride()) {
+        int64_t i = base + threadIdx.x;
+        bool p = false;
+        int32_t v = 0;
+        if (i < na) {
+            int32_t u = aiu[i];
+            v = aiv[i];
+            int32_t du = sssp_dist(key[u]);
+            if (du < INF) {
+                uint64_t cand = sssp_pack(du + aiw[i], u);
+                uint64_t old = atomicMin((unsigned long long *)&key[v], (unsigned long long)cand);
+                if (cand < old && sssp_dist(cand) < sssp_dist(old)) p = atomicExch(&stamp[v], st) != st;
+            }
+        }
+        int64_t slot = wave_append(count, p);
+        if (p) front[slot] = v;
+    }
+}
+
+__global__ void k_sssp_unpack(int32_t n, const uint64_t *key, int32_t *dist, int32_t *parent) {
+    for (int64_t v = gtid(); v < n; v += gstride()) {
+        uint64_t k = key[v];
+        int32_t d = sssp_dist(k);
+        if (dist) dist[v] = d >= INF ? INF : d;
+        if (parent) parent[v] = d >= INF ? -1 : sssp_parent(k);
+    }
+}
+
+// ---- host drivers -------------------------------------------------------------------
+
+static inline int grid_for(int64_t n) {
+    int64_t g = (n + 255) / 256;
+    return (int)(g < 1 ? 1 : (g > 8192 ? 8192 : g));
+}
+
+static int heavy_deg(dg_graph *g) { return g->cfg.heavy_degree > 0 ? g->cfg.heavy_degree : 512; }
+
+// Frontier buffers sized for the graph (n vertices; heavy queue for m / chunk).
+static int ensure_frontiers(dg_graph *g) {
+    Work &ws = g->ws;
+    DG_TRY(ws.f0.ensure((size_t)g->n + 1));
+    DG_TRY(ws.f1.ensure((size_t)g->n + 1));
+    int64_t edges = g->fwd.m + g->fwd.dm;
+    if (g->rev != &g->fwd) edges = std::max(edges, g->rev->m + g->rev->dm);
+    DG_TRY(ws.heavy.ensure((size_t)(2 * (edges / heavy_deg(g) + 2) + g->n / 8 + 64) * 2));
+    return DG_OK;
+}
+
+static ExpandArgs make_args(dg_graph *g, const Dir &d, const int32_t *F, int64_t nf) {
+    ExpandArgs a;
+    a.F = F;
+    a.nf = nf;
+    a.g = view(d);
+    a.hq = reinterpret_cast<int64_t *>(g->ws.heavy.p);
+    a.hcount = g->ws.dcnt + C_HEAVY;
+    a.heavy_deg = heavy_deg(g);
+    a.chunk = a.heavy_deg;
+    return a;
+}
+
+// Push relaxation from frontier f0 (nf vertices) until no distance drops.
+static int sssp_push(dg_graph *g, uint64_t *key, int64_t nf, dg_batch_stats *st) {
+    hipStream_t s = g->stream;
+    Work &ws = g->ws;
+    int32_t *F = ws.f0.p, *N = ws.f1.p;
+    int steps = 0;
+    int64_t relaxed = 0;
+    while (nf > 0) {
+        int32_t stv;
+        DG_TRY(next_stamp(g, &stv));
+        DG_TRY(counters_clear(g));
+        RelaxOp op{key, ws.stamp.p, stv, N, ws.dcnt + C_F1};
+        DG_TRY(launch_expand(s, make_args(g, g->fwd, F, nf), op, 1024));
+        DG_TRY(counters_read(g));
+        relaxed += nf;
+        nf = ws.hcnt[C_F1];
+        std::swap(F, N);
+        ++steps;
+    }
+    if (st) {
+        st->sssp_steps += steps;
+        st->sssp_relaxed += relaxed;
+    }
+    return DG_OK;
+}
+
+int sssp_static_solve(dg_graph *g, uint64_t *key, int32_t source, dg_batch_stats *st) {
+    hipStream_t s = g->stream;
+    DG_TRY(ensure_frontiers(g));
+    hipLaunchKernelGGL(k_sssp_init, dim3(grid_for(g->n)), dim3(256), 0, s, g->n, key, source);
+    DG_HIP(hipGetLastError());
+    int32_t src = source;
+    DG_HIP(hipMemcpyAsync(g->ws.f0.p, &src, 4, hipMemcpyHostToDevice, s));
+    DG_TRY(sssp_push(g, key, 1, st));
+    return DG_OK;
+}
+
+int sssp_init(dg_query *q) {
+    dg_graph *g = q->g;
+    DG_TRY(q->key.ensure((size_t)g->n + 1));
+    DG_TRY(q->inval.ensure((size_t)g->n + 1));
+    q->nseeds = 0;
+    return sssp_static_solve(g, q->key.p, q->source, nullptr);
+}
+
+int sssp_pre_delete(dg_query *q, int64_t adel) {
+    dg_graph *g = q->g;
+    q->nseeds = 0;
+    if (adel <= 0) return DG_OK;
+    DG_TRY(counters_clear(g));
+    hipLaunchKernelGGL(k_sssp_on_delete, dim3(grid_for(adel)), dim3(256), 0, g->stream, adel,
+                       g->ws.adu.p, g->ws.adv.p, q->key.p, q->inval.p, g->ws.dcnt + C_AUX0);
+    DG_HIP(hipGetLastError());
+    DG_TRY(counters_read(g));
+    q->nseeds = g->ws.hcnt[C_AUX0];
+    return DG_OK;
+}
+
+int sssp_post_update(dg_query *q, int64_t adel, int64_t ains, dg_batch_stats *st) {
+    (void)adel;
+    dg_graph *g = q->g;
+    hipStream_t s = g->stream;
+    Work &ws = g->ws;
+    DG_TRY(ensure_frontiers(g));
+    // 1. cut the subtrees below the seeds; q->inval collects every cut vertex
+    int64_t ncut = q->nseeds;
+    int64_t lo = 0, hi = ncut;
+    while (hi > lo) {
+        DG_TRY(counters_clear(g));
+        CutOp op{q->key.p, q->inval.p + hi, ws.dcnt + C_F1};
+        DG_TRY(launch_expand(s, make_args(g, g->fwd, q->inval.p + lo, hi - lo), op, 1024));
+        DG_TRY(counters_read(g));
+        lo = hi;
+        hi += ws.hcnt[C_F1];
+    }
+    ncut = hi;
+    if (st) st->sssp_invalidated += ncut;
+    // 2. one pull per cut vertex over its live in-edges
+    if (ncut > 0) {
+        DG_TRY(counters_clear(g));
+        PullOp op{q->key.p};
+        DG_TRY(launch_expand(s, make_args(g, *g->rev, q->inval.p, ncut), op, 1024));
+    }
+    // 3. inserted arcs relax their heads; 2+3 seed the push frontier
+    int32_t stv;
+    DG_TRY(next_stamp(g, &stv));
+    DG_TRY(counters_clear(g));
+    if (ncut > 0)
+        hipLaunchKernelGGL(k_sssp_pulled, dim3(grid_for(ncut)), dim3(256), 0, s, ncut, q->inval.p,
+                           q->key.p, ws.stamp.p, stv, ws.f0.p, ws.dcnt + C_F0);
+    if (ains > 0)
+        hipLaunchKernelGGL(k_sssp_on_add, dim3(grid_for(ains)), dim3(256), 0, s, ains, ws.aiu.p,
+                           ws.aiv.p, ws.aiw.p, q->key.p, ws.stamp.p, stv, ws.f0.p, ws.dcnt + C_F0);
+    DG_HIP(hipGetLastError());
+    DG_TRY(counters_read(g));
+    // 4. push to the fixed point
+    return sssp_push(g, q->key.p, ws.hcnt[C_F0], st);
+}
+
+int sssp_unpack(dg_graph *g, const uint64_t *key, int32_t *dist, int32_t *parent, hipStream_t s) {
+    hipLaunchKernelGGL(k_sssp_unpack, dim3(grid_for(g->n)), dim3(256), 0, s, g->n, key, dist, parent);
+    DG_HIP(hipGetLastError());
+    return DG_OK;
+}
+
+int sssp_read(dg_query *q, int32_t *dist, int32_t *parent, bool dev) {
+    dg_graph *g = q->g;
+    hipStream_t s = g->stream;
+    if (dev) {
+        DG_TRY(sssp_unpack(g, q->key.p, dist, parent, s));
+    } else {
+        DBuf<int32_t> tmp;
+        DG_TRY(tmp.ensure(2 * (size_t)g->n + 2));
+        DG_TRY(sssp_unpack(g, q->key.p, tmp.p, tmp.p + g->n, s));
+        hipError_t e1 = hipMemcpyAsync(dist, tmp.p, (size_t)g->n * 4, hipMemcpyDeviceToHost, s);
+        hipError_t e2 = parent ? hipMemcpyAsync(parent, tmp.p + g->n, (size_t)g->n * 4,
+                                                hipMemcpyDeviceToHost, s)
+                               : hipSuccess;
+        hipError_t e3 = hipStreamSynchronize(s);
+        tmp.release();
+        if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess)
+            return set_error(DG_EDEVICE, "sssp read copy failed");
+        return DG_OK;
+    }
+    DG_HIP(hipStreamSynchronize(s));
+    return DG_OK;
+}
+
+}  // namespace dg

@@ -1,0 +1,161 @@
+// Triangle counting: static count and the delta for a batch (undirected graphs).
+//
+// Delta (Appendix A, DynTC: Decremental runs on the old graph, Incremental on the
+// new one).  For a changed edge {a, b} every common neighbour c closes a
+// triangle {a, b, c}; if k of that triangle's three edges are in the batch, the
+// triangle is met once from each of them, so each meeting adds 6 / k and the sum
+// over all changed edges is 6x the number of changed triangles -- the listing's
+// count1/2 + count2/4 + count3/6 with every edge taken once instead of twice.
+// An edge is "in the batch" when its entry carries MARK: deletions carry it
+// between marking and commit (so the old graph still holds them), insertions
+// from insertion until the post-hooks are done -- the edge flags modified_del /
+// modified_add of the listing.
+//
+// Static (comparator; Appendix A staticTC counts every triangle once by vertex
+// order): here vertices are ordered by (degree, id) so every triangle is counted
+// once from its lowest-ranked edge, and each intersection walks the row of the
+// lower-ranked endpoint -- the standard degree ordering that bounds work on
+// skewed graphs.
+#include <algorithm>
+
+#include "dg_device.h"
+
+namespace dg {
+
+static inline int grid_for(int64_t n) {
+    int64_t g = (n + 255) / 256;
+    return (int)(g < 1 ? 1 : (g > 8192 ? 8192 : g));
+}
+
+struct RowRef {
+    int64_t ob, db, od, dd;  // base start/len, diff start/len
+};
+
+__device__ __forceinline__ RowRef row_ref(const int64_t *off, const int64_t *doff, int32_t v) {
+    RowRef r;
+    r.ob = off[v];
+    r.db = off[v + 1] - r.ob;
+    r.od = doff[v];
+    r.dd = doff[v + 1] - r.od;
+    return r;
+}
+
+// Live entry for neighbour x in row r: returns the raw entry (flags) or 0 with
+// found = false.
+__device__ __forceinline__ bool row_find(const int32_t *col, const int32_t *dcol, const RowRef &r,
+                                         uint32_t x, uint32_t &ent) {
+    int64_t p = find_sorted(col, r.ob, r.ob + r.db, x);
+    if (p >= 0) {
+        ent = (uint32_t)col[p];
+        return !(ent & DEAD);
+    }
+    if (r.dd > 0) {
+        int64_t q = find_sorted(dcol, r.od, r.od + r.dd, x);
+        if (q >= 0) {
+            ent = (uint32_t)dcol[q];
+            return !(ent & DEAD);
+        }
+    }
+    return false;
+}
+
+// One wave per changed edge; lanes walk the smaller row, probe the larger one.
+__global__ __launch_bounds__(256) void k_tc_delta(int64_t ne, const int32_t *eu, const int32_t *ev,
+                                                  const int64_t *__restrict__ off,
+                                                  const int32_t *__restrict__ col,
+                                                  const int64_t *__restrict__ doff,
+                                                  const int32_t *__restrict__ dcol,
+                                                  unsigned long long *sum6) {
+    const int64_t wave_global = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / WAVE;
+    const int l = lane_id();
+    uint64_t acc = 0;
+    for (int64_t i = wave_global; i < ne; i += nwaves) {
+        int32_t a = eu[i], b = ev[i];
+        RowRef ra = row_ref(off, doff, a), rb = row_ref(off, doff, b);
+        if (ra.db + ra.dd > rb.db + rb.dd) {
+            RowRef t = ra; ra = rb; rb = t;
+        }
+        const int64_t tot = ra.db + ra.dd;
+        for (int64_t j = l; j < tot; j += WAVE) {
+            uint32_t e = j < ra.db ? (uint32_t)col[ra.ob + j] : (uint32_t)dcol[ra.od + (j - ra.db)];
+            if (e & DEAD) continue;
+            uint32_t c = e & ID_MASK;
+            uint32_t e2;
+            if (!row_find(col, dcol, rb, c, e2)) continue;
+            int k = 1 + ((e & MARK) ? 1 : 0) + ((e2 & MARK) ? 1 : 0);
+            acc += (uint64_t)(6 / k);
+        }
+    }
+    acc = wave_sum(acc);
+    if (l == 0 && acc) atomicAdd(sum6, (unsigned long long)acc);
+}
+
+int tc_delta(dg_graph *g, const int32_t *eu, const int32_t *ev, int64_t ne, uint64_t *sum6) {
+    *sum6 = 0;
+    if (ne <= 0) return DG_OK;
+    hipStream_t s = g->stream;
+    Dir &F = g->fwd;
+    DG_TRY(counters_clear(g));
+    unsigned long long *acc = reinterpret_cast<unsigned long long *>(g->ws.dcnt + C_TC0);
+    int64_t blocks = std::min<int64_t>((ne + 3) / 4, 16384);
+    hipLaunchKernelGGL(k_tc_delta, dim3((unsigned)blocks), dim3(256), 0, s, ne, eu, ev, F.off.p, F.col.p,
+                       F.doff.p, F.dcol.p, acc);
+    DG_HIP(hipGetLastError());
+    DG_TRY(counters_read(g));
+    *sum6 = (uint64_t)g->ws.hcnt[C_TC0];
+    return DG_OK;
+}
+
+// ---- static count on a merged (plain CSR) graph -------------------------------------
+
+__device__ __forceinline__ bool rank_lt(int32_t du, int32_t u, int32_t dv, int32_t v) {
+    return du < dv || (du == dv && u < v);
+}
+
+// For every arc (x, y) with rank(x) < rank(y): common neighbours c of x and y with
+// rank(c) > rank(y).  One wave per row x; lanes walk N(x) for each oriented arc.
+__global__ __launch_bounds__(256) void k_tc_static(int32_t n, const int64_t *__restrict__ off,
+                                                   const int32_t *__restrict__ col,
+                                                   const int32_t *__restrict__ deg,
+                                                   unsigned long long *total) {
+    const int64_t wave_global = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / WAVE;
+    const int l = lane_id();
+    uint64_t acc = 0;
+    for (int64_t x = wave_global; x < n; x += nwaves) {
+        const int64_t xs = off[x], xe = off[x + 1];
+        const int32_t dx = deg[x];
+        for (int64_t p = xs; p < xe; ++p) {
+            const int32_t y = col[p] & (int32_t)ID_MASK;
+            const int32_t dy = deg[y];
+            if (!rank_lt(dx, (int32_t)x, dy, y)) continue;
+            const int64_t ys = off[y], ye = off[y + 1];
+            for (int64_t j = xs + l; j < xe; j += WAVE) {
+                const int32_t c = col[j] & (int32_t)ID_MASK;
+                const int32_t dc = deg[c];
+                if (!rank_lt(dy, y, dc, c)) continue;
+                if (find_sorted(col, ys, ye, (uint32_t)c) >= 0) ++acc;
+            }
+        }
+    }
+    acc = wave_sum(acc);
+    if (l == 0 && acc) atomicAdd(total, (unsigned long long)acc);
+}
+
+int tc_count_static(dg_graph *g, uint64_t *count) {
+    DG_TRY(graph_merge(g));
+    hipStream_t s = g->stream;
+    Dir &F = g->fwd;
+    DG_TRY(counters_clear(g));
+    unsigned long long *acc = reinterpret_cast<unsigned long long *>(g->ws.dcnt + C_TC1);
+    int64_t blocks = std::min<int64_t>(((int64_t)g->n + 3) / 4, 32768);
+    hipLaunchKernelGGL(k_tc_static, dim3((unsigned)blocks), dim3(256), 0, s, g->n, F.off.p, F.col.p,
+                       F.deg.p, acc);
+    DG_HIP(hipGetLastError());
+    DG_TRY(counters_read(g));
+    *count = (uint64_t)g->ws.hcnt[C_TC1];
+    return DG_OK;
+}
+
+}  // namespace dg

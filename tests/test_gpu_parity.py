@@ -1,0 +1,398 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Shortest-path distances, exported edge sets and triangle counts must be
+bit-exact; PageRank must be within max-abs 1e-10 of the oracle run at the same
+L1 tolerance (1e-9).  Parent arrays are checked for validity (several shortest
+path trees are correct).  Every case prints its name and seed first so that a
+failing run names it.
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+import paper_2507_11094_amd as dg
+
+pytestmark = pytest.mark.gpu
+
+INF = dg.DG_INF
+PR_TOL = 1e-9
+PR_MAXABS = 1e-10
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def cfg(merge=0.0, heavy=0, tol_scale=0.0):
+    c = dg.Config()
+    c.merge_threshold = merge
+    c.heavy_degree = heavy
+    c.pr_tol_scale = tol_scale
+    return c
+
+
+def assert_edges(G, s, d, w, undirected=False):
+    gs, gd, gw = G.export()
+    assert gs.size == s.size
+    assert np.array_equal(gs, s) and np.array_equal(gd, d)
+    if not undirected:
+        assert np.array_equal(gw, w)
+
+
+def assert_tree(n, s, d, w, source, dist, parent):
+    """parent[] is a shortest-path tree of the distances dist[]."""
+    emap = {}
+    for a, b, c in zip(s.tolist(), d.tolist(), w.tolist()):
+        emap[(a, b)] = c
+    assert parent[source] == -1
+    for v in range(n):
+        if v == source:
+            continue
+        if dist[v] >= INF:
+            assert parent[v] == -1
+            continue
+        p = int(parent[v])
+        assert (p, v) in emap, (p, v)
+        assert int(dist[p]) + emap[(p, v)] == int(dist[v])
+
+
+def rmat_small(scale=12, deg=16, seed=7):
+    return graphgen.rmat_directed(scale, deg << scale, seed)
+
+
+# ------------------------------------------------------------------ graph store
+
+def test_build_and_export_c1():
+    n, s, d, w, _ = graphgen.c1_workload()
+    say("build/export C1")
+    G = dg.Graph(n, s, d, w)
+    os_, od, ow, _ = oracle.apply(n, s, d, w, [], [], [], [])
+    assert_edges(G, os_, od, ow)
+    assert G.info()["m"] == s.size
+
+
+def test_diffcsr_figure_example():
+    """Section 3.5 diff-CSR example (figure reconstructed from the printed array
+    entries): deleting B->D leaves a tombstone, inserting E->C goes to the diff."""
+    say("diff-CSR figure example")
+    A, B, C, D, E, F = range(6)
+    s = np.array([A, B, B, C, D, E, F]); d = np.array([B, C, D, A, E, F, D])
+    G = dg.Graph(6, s, d, None, config=cfg(merge=1e9))
+    G.apply([B, E], [D, C], [0, 1], [0, 1])
+    info = G.info()
+    assert info["tombstones"] == 1 and info["diff_entries"] == 1 and info["m"] == 7
+    es, ed, _ = G.export()
+    assert list(zip(es.tolist(), ed.tolist())) == sorted([(A, B), (B, C), (C, A), (D, E), (E, C), (E, F), (F, D)])
+
+
+@pytest.mark.parametrize("merge", [0.0, -1.0, 1e9])
+def test_batch_sequence_matches_oracle(merge):
+    n, s, d, w = rmat_small(11, 16, 21)
+    say("batch sequence merge", merge)
+    G = dg.Graph(n, s, d, w, config=cfg(merge=merge))
+    cs, cd, cw = s, d, w
+    sizes = [1, 7, 100, 2000, 33, 640, 5000, 1, 0, 300, 1200, 9000]
+    for i, k in enumerate(sizes):
+        bs, bd, bw, bo = graphgen.update_batch(n, cs, cd, k, 1000 + i)
+        if i % 3 == 1 and k > 4:  # noise: repeats, absent deletes, present inserts
+            bs = np.concatenate([bs, bs[:4], cd[:3], [cs[5]]]).astype(np.int32)
+            bd = np.concatenate([bd, bd[:4], cs[:3], [cd[5]]]).astype(np.int32)
+            bw = np.concatenate([bw, bw[:4] + 3, [7, 7, 7], [2]]).astype(np.int32)
+            bo = np.concatenate([bo, bo[:4], [0, 0, 0], [1]]).astype(np.uint8)
+        st = G.apply(bs, bd, bw, bo)
+        cs, cd, cw, ost = oracle.apply(n, cs, cd, cw, bs, bd, bw, bo)
+        assert (st.deleted, st.inserted) == (ost[0], ost[1]), (i, st.as_dict(), ost)
+        assert_edges(G, cs, cd, cw)
+
+
+def test_delete_then_reinsert_and_revive():
+    n, s, d, w = rmat_small(9, 8, 5)
+    say("delete + reinsert")
+    G = dg.Graph(n, s, d, w, config=cfg(merge=1e9))
+    # batch 1: delete 50 edges; batch 2: re-insert 25 of them with new weights and
+    # delete+insert 10 others in the same batch
+    k = 50
+    G.apply(s[:k], d[:k], w[:k], np.zeros(k, np.uint8))
+    cs, cd, cw, _ = oracle.apply(n, s, d, w, s[:k], d[:k], w[:k], np.zeros(k, np.uint8))
+    bs = np.concatenate([s[:25], s[100:110], s[100:110]])
+    bd = np.concatenate([d[:25], d[100:110], d[100:110]])
+    bw = np.concatenate([np.full(25, 77), np.zeros(10), np.full(10, 55)]).astype(np.int32)
+    bo = np.concatenate([np.ones(25), np.zeros(10), np.ones(10)]).astype(np.uint8)
+    st = G.apply(bs, bd, bw, bo)
+    cs, cd, cw, ost = oracle.apply(n, cs, cd, cw, bs, bd, bw, bo)
+    assert (st.deleted, st.inserted) == (ost[0], ost[1])
+    assert_edges(G, cs, cd, cw)
+    assert G.info()["tombstones"] == 25
+
+
+def test_invalid_batch_changes_nothing():
+    n, s, d, w = rmat_small(9, 8, 6)
+    say("invalid batch")
+    G = dg.Graph(n, s, d, w)
+    q = G.sssp_attach(0)
+    before = G.export()
+    dist0, _ = q.read()
+    for bad in ([(1, 1, 1, 1)], [(0, n, 1, 1)], [(2, 3, 1, 9)], [(2, 3, -5, 1)]):
+        b = np.array(bad + [(s[0], d[0], 0, 0)], dtype=np.int64)
+        with pytest.raises(dg.DGError) as e:
+            G.apply(b[:, 0], b[:, 1], b[:, 2], b[:, 3])
+        assert e.value.code == dg.DG_EINVAL
+    after = G.export()
+    for x, y in zip(before, after):
+        assert np.array_equal(x, y)
+    assert np.array_equal(q.read()[0], dist0)
+
+
+def test_build_rejects_bad_edge_lists():
+    say("bad edge lists")
+    for s, d in (([0, 1], [1, 1]), ([0, 0], [1, 1]), ([0, 5], [1, 2])):
+        with pytest.raises(dg.DGError):
+            dg.Graph(4, s, d)
+
+
+# ------------------------------------------------------------------ SSSP
+
+@pytest.mark.parametrize("heavy", [0, 8, 1 << 20])
+def test_sssp_c1_dynamic(heavy):
+    n, s, d, w, (bs, bd, bw, bo) = graphgen.c1_workload()
+    say("sssp C1 heavy", heavy)
+    G = dg.Graph(n, s, d, w, config=cfg(heavy=heavy))
+    q = G.sssp_attach(0)
+    dist, par = q.read()
+    assert np.array_equal(dist, oracle.sssp(n, s, d, w, 0))
+    G.apply(bs, bd, bw, bo)
+    cs, cd, cw, _ = oracle.apply(n, s, d, w, bs, bd, bw, bo)
+    want = oracle.sssp(n, cs, cd, cw, 0)
+    dist, par = q.read()
+    assert np.array_equal(dist, want)
+    assert_tree(n, cs, cd, cw, 0, dist, par)
+    sd, sp = G.sssp_static(0)
+    assert np.array_equal(sd, want)
+    assert_tree(n, cs, cd, cw, 0, sd, sp)
+
+
+def test_sssp_many_batches_with_merges():
+    n, s, d, w = rmat_small(12, 8, 33)
+    say("sssp sequence")
+    G = dg.Graph(n, s, d, w, config=cfg(merge=0.02))
+    qs = [G.sssp_attach(0), G.sssp_attach(17)]
+    cs, cd, cw = s, d, w
+    merges = 0
+    for i in range(22):
+        k = [50, 400, 3, 1500][i % 4]
+        bs, bd, bw, bo = graphgen.update_batch(n, cs, cd, k, 3000 + i)
+        if i % 5 == 0:  # delete tree edges near the source on purpose
+            dist, par = qs[0].read()
+            kids = np.nonzero(par == 0)[0][:20]
+            bs = np.concatenate([bs, np.zeros(kids.size, np.int32)]).astype(np.int32)
+            bd = np.concatenate([bd, kids]).astype(np.int32)
+            bw = np.concatenate([bw, np.zeros(kids.size, np.int32)]).astype(np.int32)
+            bo = np.concatenate([bo, np.zeros(kids.size, np.uint8)]).astype(np.uint8)
+        st = G.apply(bs, bd, bw, bo)
+        merges += st.merged
+        cs, cd, cw, _ = oracle.apply(n, cs, cd, cw, bs, bd, bw, bo)
+        for q, src in zip(qs, (0, 17)):
+            dist, par = q.read()
+            assert np.array_equal(dist, oracle.sssp(n, cs, cd, cw, src)), (i, src)
+            if i % 7 == 0:
+                assert_tree(n, cs, cd, cw, src, dist, par)
+    assert merges >= 2
+
+
+def test_sssp_grid_and_hub():
+    """High-diameter grid (many frontier steps) plus a hub above the heavy limit."""
+    n, s, d, w = graphgen.grid4(40, 40, 9, 1000)
+    hub = 5
+    extra = np.setdiff1d(np.arange(0, n, 2), np.concatenate([[hub], d[s == hub]]))
+    s = np.concatenate([s, np.full(extra.size, hub)]).astype(np.int32)
+    d = np.concatenate([d, extra]).astype(np.int32)
+    w = np.concatenate([w, np.full(extra.size, 5000)]).astype(np.int32)
+    say("sssp grid+hub")
+    G = dg.Graph(n, s, d, w, config=cfg(heavy=64))
+    q = G.sssp_attach(0)
+    cs, cd, cw = s, d, w
+    for i in range(6):
+        bs, bd, bw, bo = graphgen.update_batch(n, cs, cd, 60, 4000 + i, wmax=1000)
+        G.apply(bs, bd, bw, bo)
+        cs, cd, cw, _ = oracle.apply(n, cs, cd, cw, bs, bd, bw, bo)
+        dist, par = q.read()
+        assert np.array_equal(dist, oracle.sssp(n, cs, cd, cw, 0))
+        assert_tree(n, cs, cd, cw, 0, dist, par)
+
+
+def test_sssp_fig_dynsssp_reconstructed():
+    g = json.load(open(os.path.join(GOLDEN, "fig_dynsssp.json")))
+    say("fig dynsssp")
+    e = np.array(g["edges"]); b = np.array(g["batch"]); V = g["vertices"]
+    G = dg.Graph(g["n"], e[:, 0], e[:, 1], e[:, 2])
+    q = G.sssp_attach(g["source"])
+    dist, _ = q.read()
+    for name, val in g["printed_before"].items():
+        assert dist[V[name]] == val
+    G.apply(b[:, 0], b[:, 1], b[:, 2], b[:, 3])
+    dist, _ = q.read()
+    for name, val in g["printed_after"].items():
+        assert dist[V[name]] == val
+
+
+def test_sssp_unreachable_and_disconnect():
+    say("sssp disconnect")
+    # chain 0->1->2->3, 4 isolated; delete 1->2 cuts 2 and 3
+    G = dg.Graph(5, [0, 1, 2], [1, 2, 3], [1, 1, 1])
+    q = G.sssp_attach(0)
+    G.apply([1], [2], [0], [0])
+    dist, par = q.read()
+    assert list(dist) == [0, 1, INF, INF, INF] and list(par) == [-1, 0, -1, -1, -1]
+    G.apply([0], [3], [9], [1])
+    dist, par = q.read()
+    assert list(dist) == [0, 1, INF, 9, INF] and par[3] == 0
+
+
+# ------------------------------------------------------------------ PageRank
+
+def pr_check(got, n, s, d):
+    want, _, conv = oracle.pagerank(n, s, d, 0.85, PR_TOL, 1000)
+    tight, _, _ = oracle.pagerank(n, s, d, 0.85, 1e-14, 5000)
+    err = float(np.max(np.abs(got - want)))
+    err_t = float(np.max(np.abs(got - tight)))
+    print(f"    pr max-abs vs oracle@1e-9 {err:.3e}, vs oracle@1e-14 {err_t:.3e}", flush=True)
+    assert conv
+    assert abs(got.sum() - 1.0) < 1e-12
+    assert err <= PR_MAXABS
+
+
+@pytest.mark.parametrize("heavy", [0, 8])
+def test_pagerank_c1_dynamic(heavy):
+    n, s, d, w, (bs, bd, bw, bo) = graphgen.c1_workload()
+    say("pagerank C1 heavy", heavy)
+    G = dg.Graph(n, s, d, w, config=cfg(heavy=heavy))
+    q = G.pr_attach(0.85, PR_TOL, 1000)
+    r, it, conv = q.read()
+    pr_check(r, n, s, d)
+    cs, cd, cw = s, d, w
+    for i in range(4):
+        if i:
+            bs, bd, bw, bo = graphgen.update_batch(n, cs, cd, [300, 5000, 20][i - 1], 5000 + i)
+        st = G.apply(bs, bd, bw, bo)
+        cs, cd, cw, _ = oracle.apply(n, cs, cd, cw, bs, bd, bw, bo)
+        r, it, conv = q.read()
+        assert conv and st.pr_affected > 0
+        pr_check(r, n, cs, cd)
+    rs, _ = G.pr_static(0.85, PR_TOL, 1000)
+    pr_check(rs, n, cs, cd)
+
+
+def test_pagerank_dangling_and_isolated():
+    say("pagerank dangling")
+    # 0->1, 1 dangling, 2 isolated, 3->0, 3->1
+    G = dg.Graph(4, [0, 3, 3], [1, 0, 1])
+    q = G.pr_attach(0.85, 1e-12, 1000)
+    r, _, _ = q.read()
+    want, _, _ = oracle.pagerank(4, [0, 3, 3], [1, 0, 1], 0.85, 1e-14, 5000)
+    assert np.max(np.abs(r - want)) < 1e-11
+    G.apply([1, 3], [2, 0], [1, 0], [1, 0])  # 1->2 added, 3->0 deleted
+    r, _, _ = q.read()
+    want, _, _ = oracle.pagerank(4, [0, 3, 1], [1, 1, 2], 0.85, 1e-14, 5000)
+    assert np.max(np.abs(r - want)) < 1e-11
+
+
+# ------------------------------------------------------------------ triangles
+
+@pytest.mark.parametrize("heavy", [0, 16])
+def test_tc_dynamic(heavy):
+    n, u, v = graphgen.rmat_undirected(11, 16 << 11, 77)
+    say("tc dynamic heavy", heavy)
+    G = dg.Graph(n, u, v, None, undirected=True, config=cfg(heavy=heavy))
+    q = G.tc_attach()
+    assert q.read() == oracle.triangles(n, u, v)
+    cu, cv = u, v
+    for i, k in enumerate([10, 327, 3000, 1, 900]):
+        bs, bd, bw, bo = graphgen.update_batch(n, cu, cv, k, 6000 + i, undirected=True)
+        if i == 2:  # delete and re-insert some edges in the same batch
+            bs = np.concatenate([bs, cu[:5], cv[:5]]).astype(np.int32)
+            bd = np.concatenate([bd, cv[:5], cu[:5]]).astype(np.int32)
+            bw = np.concatenate([bw, np.ones(10, np.int32)]).astype(np.int32)
+            bo = np.concatenate([bo, np.zeros(5, np.uint8), np.ones(5, np.uint8)]).astype(np.uint8)
+        G.apply(bs, bd, bw, bo)
+        cu, cv, _, _ = oracle.apply(n, cu, cv, None, bs, bd, bw, bo, undirected=True)
+        want = oracle.triangles(n, cu, cv)
+        assert q.read() == want, i
+        es, ed, _ = G.export()
+        assert np.array_equal(es, cu) and np.array_equal(ed, cv)
+    assert G.tc_static() == oracle.triangles(n, cu, cv)
+
+
+def test_tc_small_closed_forms():
+    say("tc closed forms")
+    k = 9
+    pairs = np.array([(a, b) for a in range(k) for b in range(a + 1, k)])
+    G = dg.Graph(k, pairs[:, 0], pairs[:, 1], None, undirected=True)
+    q = G.tc_attach()
+    assert q.read() == 84
+    # delete every edge of vertex 0: removes C(8,2) = 28 triangles
+    G.apply(np.zeros(8, np.int32), np.arange(1, 9), None, np.zeros(8, np.uint8))
+    assert q.read() == 84 - 28
+    # insert them back: all triangles return
+    G.apply(np.arange(1, 9), np.zeros(8, np.int32), None, np.ones(8, np.uint8))
+    assert q.read() == 84
+
+
+# ------------------------------------------------------------------ snapshots, batches, device memory
+
+def test_snapshot_restore_repeats_a_batch():
+    n, s, d, w, (bs, bd, bw, bo) = graphgen.c1_workload()
+    say("snapshot")
+    G = dg.Graph(n, s, d, w)
+    qs, qp = G.sssp_attach(0), G.pr_attach()
+    G.snapshot()
+    G.apply(bs, bd, bw, bo)
+    d1, r1 = qs.read()[0], qp.read()[0]
+    e1 = G.export()
+    G.restore()
+    assert np.array_equal(G.export()[0], s[np.lexsort((d, s))])
+    G.apply(bs, bd, bw, bo)
+    assert np.array_equal(qs.read()[0], d1)
+    assert np.array_equal(qp.read()[0], r1)  # deterministic reductions
+    for x, y in zip(G.export(), e1):
+        assert np.array_equal(x, y)
+
+
+def test_batch_size_chunks_match_one_shot():
+    n, s, d, w, (bs, bd, bw, bo) = graphgen.c1_workload()
+    say("batch_size chunks")
+    G1 = dg.Graph(n, s, d, w)
+    G2 = dg.Graph(n, s, d, w)
+    q1, q2 = G1.sssp_attach(0), G2.sssp_attach(0)
+    G1.apply(bs, bd, bw, bo)
+    st = G2.apply(bs, bd, bw, bo, batch_size=500)
+    assert st.chunks == (bs.size + 499) // 500
+    # chunked application is sequential application of the chunks
+    cs, cd, cw = s, d, w
+    for o in range(0, bs.size, 500):
+        cs, cd, cw, _ = oracle.apply(n, cs, cd, cw, bs[o:o + 500], bd[o:o + 500], bw[o:o + 500], bo[o:o + 500])
+    assert_edges(G2, cs, cd, cw)
+    assert np.array_equal(q2.read()[0], oracle.sssp(n, cs, cd, cw, 0))
+
+
+def test_device_pointer_batch():
+    import torch
+    n, s, d, w, (bs, bd, bw, bo) = graphgen.c1_workload()
+    say("device pointers")
+    dev = torch.device("cuda:0")
+    G = dg.Graph(n, torch.from_numpy(s).to(dev), torch.from_numpy(d).to(dev), torch.from_numpy(w).to(dev))
+    q = G.sssp_attach(0)
+    G.set_stream(torch.cuda.current_stream().cuda_stream)
+    G.apply(torch.from_numpy(bs).to(dev), torch.from_numpy(bd).to(dev), torch.from_numpy(bw).to(dev),
+            torch.from_numpy(bo).to(dev))
+    out = torch.empty(n, dtype=torch.int32, device=dev)
+    q.read(out)
+    torch.cuda.synchronize()
+    cs, cd, cw, _ = oracle.apply(n, s, d, w, bs, bd, bw, bo)
+    assert np.array_equal(out.cpu().numpy(), oracle.sssp(n, cs, cd, cw, 0))

@@ -353,7 +353,7 @@ def test_apply_roundtrip_and_rejects():
     ref = oracle.apply(n, s, d, w, [], [], [], [])
     for x, y in zip(back[:3], ref[:3]):
         assert np.array_equal(x, y)
-    for bad in ([(3, 3, 1, 1)], [(0, n, 1, 1)], [(-1, 2, 1, 0)], [(1, 2, 1, 2)], [(1, 2, -4, 1)]):
+    for bad in ([(3, 3, 1, 1)], [(0, n, 1, 1)], [(-1, 2, 1, 0)], [(1, 2, 1, 2)], [(1, 2, -4, 1)], [(1, 2, 0, 1)]):
         b = np.array(bad)
         with pytest.raises(oracle.InvalidBatch):
             oracle.apply(n, s, d, w, b[:, 0], b[:, 1], b[:, 2], b[:, 3])
