@@ -294,8 +294,17 @@ def _new_pairs(seed: int, n: int, want: int, existing_sorted: np.ndarray, undire
     return got_u, got_v
 
 
+def edge_keys(src: np.ndarray, dst: np.ndarray, undirected: bool = False) -> np.ndarray:
+    """Sorted int64 keys (u << 32 | v) of an edge list (u < v when undirected);
+    pass to update_batch to avoid re-sorting a large graph for every batch."""
+    if undirected:
+        return _sorted_keys(np.minimum(src, dst).astype(np.int64), np.maximum(src, dst).astype(np.int64))
+    return _sorted_keys(src, dst)
+
+
 def update_batch(n: int, src: np.ndarray, dst: np.ndarray, k: int, seed: int,
-                 wmax: int = 100, undirected: bool = False, shuffle: bool = True):
+                 wmax: int = 100, undirected: bool = False, shuffle: bool = True,
+                 existing: np.ndarray | None = None):
     """A batch of ``k`` updates: ``k // 2`` deletions of uniformly chosen existing
     edges and ``k - k // 2`` insertions of uniform new edges (weights uniform in
     [1, wmax]).  For an undirected graph, ``src``/``dst`` list each edge once and
@@ -309,12 +318,8 @@ def update_batch(n: int, src: np.ndarray, dst: np.ndarray, k: int, seed: int,
     di = _distinct_indices(stream_seed(seed, "del"), m, n_del)
     ds = src[di].astype(np.int64)
     dd = dst[di].astype(np.int64)
-    if undirected:
-        ex_u = np.minimum(src, dst).astype(np.int64)
-        ex_v = np.maximum(src, dst).astype(np.int64)
-        existing = _sorted_keys(ex_u, ex_v)
-    else:
-        existing = _sorted_keys(src, dst)
+    if existing is None:
+        existing = edge_keys(src, dst, undirected)
     iu, iv = _new_pairs(seed, n, n_ins, existing, undirected)
     iw = uniform_int(stream_seed(seed, "ins_w"), 0, n_ins, 1, wmax)
     bsrc = np.concatenate([ds, iu])

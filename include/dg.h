@@ -188,6 +188,28 @@ int dg_pr_read(dg_query *q, double *rank, int32_t *iters, int32_t *converged, ui
 
 int dg_tc_read(dg_query *q, uint64_t *count);
 
+/* ---- kernel timing ---------------------------------------------------------------- */
+
+/* Per-kernel totals collected while profiling is on: launches, summed duration
+ * (HIP events recorded on the stream each launch runs on) and summed algorithmic
+ * bytes -- the bytes the method must move per launch, as documented per kernel
+ * (not hardware counters). */
+typedef struct dg_kernel_prof {
+    char name[32];
+    int64_t launches;
+    double ms;
+    double bytes;
+} dg_kernel_prof;
+
+/* Turn launch timing on (1) or off (0) for every graph of the process.  Timing
+ * adds two event records per profiled launch and no synchronisation. */
+int dg_profile_enable(int32_t on);
+/* Drop all collected totals. */
+int dg_profile_reset(void);
+/* Wait for profiled work to finish and copy up to cap entries; *count gets the
+ * number of kernels with totals. */
+int dg_profile_read(dg_kernel_prof *out, int32_t cap, int32_t *count);
+
 /* ---- static recompute on the current graph (comparators) -------------------------- */
 
 int dg_sssp_static(dg_graph *g, int32_t source, int32_t *dist, int32_t *parent, uint32_t flags);

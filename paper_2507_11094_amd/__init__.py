@@ -38,6 +38,7 @@ EXPORTS = (
     "dg_apply_batch", "dg_snapshot_save", "dg_snapshot_restore", "dg_snapshot_free",
     "dg_sssp_attach", "dg_pr_attach", "dg_tc_attach", "dg_query_detach", "dg_sssp_read",
     "dg_pr_read", "dg_tc_read", "dg_sssp_static", "dg_pr_static", "dg_tc_static",
+    "dg_profile_enable", "dg_profile_reset", "dg_profile_read",
 )
 
 
@@ -51,6 +52,11 @@ class Config(ctypes.Structure):
     _fields_ = [("merge_threshold", ctypes.c_double), ("pr_tol_scale", ctypes.c_double),
                 ("heavy_degree", ctypes.c_int32), ("persistent_groups", ctypes.c_int32),
                 ("sssp_persistent", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+
+
+class KernelProf(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64), ("ms", ctypes.c_double),
+                ("bytes", ctypes.c_double)]
 
 
 class BatchStats(ctypes.Structure):
@@ -82,6 +88,13 @@ def load_library() -> ctypes.CDLL:
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it first (python paper_2507_11094_amd/build.py)")
+    # One HIP runtime per process: load PyTorch's first so libdg.so binds to the
+    # libamdhip64.so.7 it already mapped (same SONAME) and device pointers, streams
+    # and the device context are shared with torch.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     P = ctypes.c_void_p
     I32, I64, U32, D = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_double
@@ -108,6 +121,9 @@ def load_library() -> ctypes.CDLL:
         "dg_sssp_static": ([P, I32, P, P, U32], ctypes.c_int),
         "dg_pr_static": ([P, D, D, I32, P, P, U32], ctypes.c_int),
         "dg_tc_static": ([P, P], ctypes.c_int),
+        "dg_profile_enable": ([I32], ctypes.c_int),
+        "dg_profile_reset": ([], ctypes.c_int),
+        "dg_profile_read": ([P, I32, P], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -166,6 +182,24 @@ def dg_apply_batch(g, src, dst, w, op, batch_size=0):
     _check(lib.dg_apply_batch(g, k, ps, pd, pw, po, int(batch_size),
                               DG_DEVICE_PTRS if dev else 0, ctypes.byref(st)))
     return st
+
+
+def dg_profile_enable(on: bool = True):
+    _check(load_library().dg_profile_enable(1 if on else 0))
+
+
+def dg_profile_reset():
+    _check(load_library().dg_profile_reset())
+
+
+def dg_profile_read() -> dict:
+    """{kernel: {"launches", "ms", "bytes"}} of the launches timed so far."""
+    lib = load_library()
+    buf = (KernelProf * 64)()
+    cnt = ctypes.c_int32()
+    _check(lib.dg_profile_read(buf, 64, ctypes.byref(cnt)))
+    return {buf[i].name.decode(): {"launches": buf[i].launches, "ms": buf[i].ms, "bytes": buf[i].bytes}
+            for i in range(min(cnt.value, 64))}
 
 
 # ---------------------------------------------------------------------------- classes

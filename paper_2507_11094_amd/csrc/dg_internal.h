@@ -193,6 +193,7 @@ void ws_free(dg_graph *g);
 void dir_free(Dir &d);
 int next_stamp(dg_graph *g, int32_t *stamp);
 int fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
+int scan_excl(dg_graph *g, const int64_t *in, int64_t *out, int64_t n);  // exclusive prefix sum
 
 // SSSP (sssp.hip)
 int sssp_init(dg_query *q);
@@ -209,6 +210,11 @@ int pr_static_solve(dg_graph *g, double damping, double tol, int32_t max_iter, d
 int pr_post_update(dg_query *q, int64_t n_applied_del, int64_t n_applied_ins, dg_batch_stats *st);
 int pr_read(dg_query *q, double *rank, bool dev);
 int pr_normalize(dg_graph *g, const double *x, double *rank, bool dev);
+
+// launch timing (prof.hip)
+bool prof_on();
+int prof_begin(const char *name, hipStream_t s);
+void prof_end(int slot, hipStream_t s, double bytes);
 
 // triangle counting (tc.hip)
 int tc_count_static(dg_graph *g, uint64_t *count);

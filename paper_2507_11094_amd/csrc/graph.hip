@@ -66,7 +66,7 @@ static int sort_pairs(dg_graph *g, const uint64_t *kin, uint64_t *kout, const in
     return DG_OK;
 }
 
-static int scan_excl(dg_graph *g, const int64_t *in, int64_t *out, int64_t n) {
+int scan_excl(dg_graph *g, const int64_t *in, int64_t *out, int64_t n) {
     if (n <= 0) return DG_OK;
     size_t bytes = 0;
     DG_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, bytes, in, out, (int)n, g->stream));
@@ -387,10 +387,14 @@ static int merge_into(dg_graph *g, Dir &d, int64_t *off2, int32_t *col2, int32_t
     DG_TRY(scan_excl(g, tsin, TS, ntiles + 1));
     DG_HIP(hipGetLastError());
     DG_TRY(counters_clear(g));
+    // merge_base bytes: col+w read 8 per old entry, write 8 per new entry, and per
+    // row off, doff, off2 and the tombstone prefix (8 each)
+    int pm = prof_begin("merge_base", s);
     if (d.m > 0)
         hipLaunchKernelGGL(k_merge_base, dim3((unsigned)ntiles), dim3(256), 0, s, n, d.m, d.off.p,
                            d.col.p, d.w.p, d.doff.p, d.dcol.p, d.dw.p, off2, RB, TS, col2, w2, m2,
                            ws.dcnt);
+    prof_end(pm, s, 8.0 * (double)d.m + 8.0 * (double)m2 + 32.0 * (double)n + 8.0 * (double)d.dm);
     if (d.dm > 0)
         hipLaunchKernelGGL(k_merge_diff_empty, dim3(grid_for(d.dm)), dim3(256), 0, s, d.dm, d.dkey.p,
                            d.keybits, d.off.p, d.doff.p, d.dcol.p, d.dw.p, off2, col2, w2, m2, ws.dcnt);

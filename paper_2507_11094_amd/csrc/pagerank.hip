@@ -245,6 +245,15 @@ __global__ void k_mark_list(int64_t n, const int32_t *a, int32_t *stamp, int32_t
     }
 }
 
+// Affected set in vertex order (deterministic sums and near-contiguous row reads).
+__global__ void k_stamp_flags(int32_t n, const int32_t *stamp, int32_t st, int64_t *flags) {
+    for (int64_t v = gtid(); v <= n; v += gstride()) flags[v] = v < n && stamp[v] == st;
+}
+__global__ void k_compact_flags(int32_t n, const int64_t *flags, const int64_t *pos, int32_t *out) {
+    for (int64_t v = gtid(); v < n; v += gstride())
+        if (flags[v]) out[pos[v]] = (int32_t)v;
+}
+
 __global__ void k_refresh_contrib(int64_t n, const int32_t *u, const double *x, const int32_t *deg,
                                   double *contrib) {
     for (int64_t i = gtid(); i < n; i += gstride()) {
@@ -269,10 +278,25 @@ static int ensure_pr_ws(dg_graph *g) {
     return DG_OK;
 }
 
+// Total entries (base + diff, tombstones included) of the rows of A.
+__global__ void k_sum_degrees(const int32_t *A, int64_t na, const int64_t *off, const int64_t *doff,
+                              int64_t *out) {
+    int64_t acc = 0;
+    for (int64_t i = gtid(); i < na; i += gstride()) {
+        int32_t v = A[i];
+        acc += (off[v + 1] - off[v]) + (doff[v + 1] - doff[v]);
+    }
+    acc = wave_sum(acc);
+    if (lane_id() == 0 && acc) atomicAdd((unsigned long long *)out, (unsigned long long)acc);
+}
+
 // Jacobi on A (nullptr = all n vertices) until the L1 step <= tol or max_iter.
-static int pr_iterate(dg_graph *g, const int32_t *A, int64_t na, double damping, double tol,
-                      int32_t max_iter, double *x, double *xn, double *contrib, int32_t *iters,
-                      int32_t *conv) {
+// `edges` = entries scanned per pull (for the algorithmic byte count):
+//   pull:  A[i] 4 + off 8 + doff 8 + xn write 8 per vertex, col 4 + contrib 8 per entry
+//   apply: A[i] 4 + xn 8 + x read 8 + x write 8 + contrib write 8 + outdeg 4 per vertex
+static int pr_iterate(dg_graph *g, const int32_t *A, int64_t na, int64_t edges, double damping,
+                      double tol, int32_t max_iter, double *x, double *xn, double *contrib,
+                      int32_t *iters, int32_t *conv) {
     hipStream_t s = g->stream;
     Work &ws = g->ws;
     const int64_t qcap = 2 * (std::max(g->fwd.m + g->fwd.dm, g->rev->m + g->rev->dm) / heavy_deg(g) + 2) +
@@ -288,15 +312,19 @@ static int pr_iterate(dg_graph *g, const int32_t *A, int64_t na, double damping,
     while (it < max_iter && na > 0) {
         DG_TRY(counters_clear(g));
         int64_t blocks = std::min<int64_t>((na + 255) / 256, 65535);
+        int ps = prof_begin("pr_pull", s);
         hipLaunchKernelGGL(k_pr_pull, dim3((unsigned)blocks), dim3(256), 0, s, A, na, rv, contrib, base,
                            damping, xn, hq, ws.dcnt + C_HEAVY, hv, ws.dcnt + C_AUX3, heavy_deg(g),
                            heavy_deg(g));
+        prof_end(ps, s, 28.0 * (double)na + 12.0 * (double)edges);
         hipLaunchKernelGGL(k_pr_heavy, dim3(1024), dim3(256), 0, s, rv, contrib, hq, ws.dcnt + C_HEAVY,
                            heavy_deg(g), ws.part.p);
         hipLaunchKernelGGL(k_pr_finish, dim3(64), dim3(256), 0, s, hv, ws.dcnt + C_AUX3, ws.part.p, base,
                            damping, xn);
+        int pa = prof_begin("pr_apply", s);
         hipLaunchKernelGGL(k_pr_apply, dim3(APPLY_GROUPS), dim3(256), 0, s, A, na, xn, x, contrib,
                            g->fwd.deg.p, partials);
+        prof_end(pa, s, 40.0 * (double)na);
         hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, partials, APPLY_GROUPS, dsum);
         DG_HIP(hipGetLastError());
         DG_TRY(counters_read(g));
@@ -319,7 +347,8 @@ int pr_static_solve(dg_graph *g, double damping, double tol, int32_t max_iter, d
     hipLaunchKernelGGL(k_pr_init, dim3(grid_for(g->n)), dim3(256), 0, g->stream, g->n, x, contrib,
                        g->fwd.deg.p);
     DG_HIP(hipGetLastError());
-    return pr_iterate(g, nullptr, g->n, damping, tol, max_iter, x, xn, contrib, iters, conv);
+    return pr_iterate(g, nullptr, g->n, g->rev->m + g->rev->dm, damping, tol, max_iter, x, xn, contrib,
+                      iters, conv);
 }
 
 static double tol_of(dg_query *q) {
@@ -406,14 +435,31 @@ int pr_post_update(dg_query *q, int64_t adel, int64_t ains, dg_batch_stats *st) 
         hi += ws.hcnt[C_F1];
     }
     na = hi;
+    if (na > 0) {
+        DG_TRY(ws.scan64.ensure(2 * ((size_t)g->n + 1)));
+        int64_t *flags = ws.scan64.p, *pos = ws.scan64.p + (g->n + 1);
+        hipLaunchKernelGGL(k_stamp_flags, dim3(grid_for(g->n + 1)), dim3(256), 0, s, g->n, ws.stamp.p, st_a,
+                           flags);
+        DG_TRY(scan_excl(g, flags, pos, g->n + 1));
+        hipLaunchKernelGGL(k_compact_flags, dim3(grid_for(g->n)), dim3(256), 0, s, g->n, flags, pos, Alist);
+        DG_HIP(hipGetLastError());
+    }
+    DG_TRY(counters_clear(g));
+    if (na > 0)
+        hipLaunchKernelGGL(k_sum_degrees, dim3(grid_for(na)), dim3(256), 0, s, Alist, na, g->rev->off.p,
+                           g->rev->doff.p, ws.dcnt + C_AUX0);
+    DG_HIP(hipGetLastError());
+    DG_TRY(counters_read(g));
+    const int64_t edges = ws.hcnt[C_AUX0];
     int32_t iters = 0, conv = 0;
-    DG_TRY(pr_iterate(g, Alist, na, q->damping, tol_of(q), q->max_iter, q->x.p, q->xn.p, q->contrib.p,
-                      &iters, &conv));
+    DG_TRY(pr_iterate(g, Alist, na, edges, q->damping, tol_of(q), q->max_iter, q->x.p, q->xn.p,
+                      q->contrib.p, &iters, &conv));
     q->last_iters = iters;
     q->converged = conv;
     if (st) {
         st->pr_iterations += iters;
         st->pr_affected += na;
+        st->edges_traversed += edges * iters;
     }
     return DG_OK;
 }

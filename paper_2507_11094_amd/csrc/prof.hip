@@ -1,0 +1,127 @@
+// Launch timing for the roofline figures: HIP event pairs around selected kernel
+// launches, resolved lazily, plus the algorithmic bytes each launch reports.
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "dg_internal.h"
+
+namespace dg {
+
+namespace {
+struct Pending {
+    std::string name;
+    hipEvent_t a, b;
+    double bytes;
+};
+struct Total {
+    int64_t launches = 0;
+    double ms = 0.0;
+    double bytes = 0.0;
+};
+std::mutex g_mu;
+bool g_on = false;
+std::vector<Pending> g_pending;
+std::vector<hipEvent_t> g_pool;
+std::vector<std::string> g_order;
+std::unordered_map<std::string, Total> g_tot;
+
+hipEvent_t take_event() {
+    if (!g_pool.empty()) {
+        hipEvent_t e = g_pool.back();
+        g_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+void resolve_locked() {
+    for (auto &p : g_pending) {
+        float ms = 0.f;
+        if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+            auto it = g_tot.find(p.name);
+            if (it == g_tot.end()) {
+                g_order.push_back(p.name);
+                it = g_tot.emplace(p.name, Total{}).first;
+            }
+            it->second.launches += 1;
+            it->second.ms += ms;
+            it->second.bytes += p.bytes;
+        }
+        g_pool.push_back(p.a);
+        g_pool.push_back(p.b);
+    }
+    g_pending.clear();
+}
+}  // namespace
+
+bool prof_on() { return g_on; }
+
+int prof_begin(const char *name, hipStream_t s) {
+    if (!g_on) return -1;
+    std::lock_guard<std::mutex> lk(g_mu);
+    Pending p{name, take_event(), take_event(), 0.0};
+    if (!p.a || !p.b) return -1;
+    (void)hipEventRecord(p.a, s);
+    g_pending.push_back(p);
+    if (g_pending.size() > 20000) {
+        // keep the pending list bounded: resolve everything but the new entry
+        Pending last = g_pending.back();
+        g_pending.pop_back();
+        resolve_locked();
+        g_pending.push_back(last);
+    }
+    return (int)g_pending.size() - 1;
+}
+
+void prof_end(int slot, hipStream_t s, double bytes) {
+    if (slot < 0) return;
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (slot >= (int)g_pending.size()) return;
+    (void)hipEventRecord(g_pending[slot].b, s);
+    g_pending[slot].bytes += bytes;
+}
+
+}  // namespace dg
+
+extern "C" {
+
+int dg_profile_enable(int32_t on) {
+    std::lock_guard<std::mutex> lk(dg::g_mu);
+    dg::g_on = on != 0;
+    return DG_OK;
+}
+
+int dg_profile_reset(void) {
+    std::lock_guard<std::mutex> lk(dg::g_mu);
+    dg::resolve_locked();
+    dg::g_tot.clear();
+    dg::g_order.clear();
+    return DG_OK;
+}
+
+int dg_profile_read(dg_kernel_prof *out, int32_t cap, int32_t *count) {
+    if (!count || (cap > 0 && !out)) return dg::set_error(DG_EINVAL, "bad profile arguments");
+    std::lock_guard<std::mutex> lk(dg::g_mu);
+    dg::resolve_locked();
+    int32_t c = 0;
+    for (const auto &name : dg::g_order) {
+        if (c < cap) {
+            const auto &t = dg::g_tot[name];
+            std::memset(&out[c], 0, sizeof(out[c]));
+            std::strncpy(out[c].name, name.c_str(), sizeof(out[c].name) - 1);
+            out[c].launches = t.launches;
+            out[c].ms = t.ms;
+            out[c].bytes = t.bytes;
+        }
+        ++c;
+    }
+    *count = c;
+    return DG_OK;
+}
+
+}  // extern "C"
