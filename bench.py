@@ -47,7 +47,23 @@ def main() -> int:
     ap.add_argument("--batch", type=int, default=100_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-static", action="store_true")
+    ap.add_argument("--heavy-degree", type=int, default=0, help="rows longer than this are split (0: library default)")
+    ap.add_argument("--sssp-persistent", type=int, default=0, help="1: SSSP on the single-launch work queue")
+    ap.add_argument("--pr-mode", type=int, default=0, help="PageRank form after a batch: 0 auto, 1 local, 2 global")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run five plain 256 MiB device-to-device copies (reference for the "
+                         "FETCH_SIZE / WRITE_SIZE counter scale) and exit")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+
+        a = torch.ones(256 << 20, dtype=torch.uint8, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": int(a.numel()), "copies": 5}), flush=True)
+        return 0
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures the dynamic-graph hot path on one GPU; this build runs on a single "
@@ -74,7 +90,11 @@ def main() -> int:
     torch.cuda.synchronize()
 
     t = time.perf_counter()
-    G = dg.Graph(n, s, d, w)
+    cfg = dg.Config()
+    cfg.heavy_degree = args.heavy_degree
+    cfg.sssp_persistent = args.sssp_persistent
+    cfg.pr_mode = args.pr_mode
+    G = dg.Graph(n, s, d, w, config=cfg)
     log(f"graph built on device in {time.perf_counter() - t:.2f}s")
     t = time.perf_counter()
     qs = G.sssp_attach(0)
@@ -176,7 +196,8 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": f"rmat{args.scale}-dynamic-sssp+pagerank", "vertices": n, "arcs": int(s.size),
                    "batch": k, "insert_fraction": 0.5, "queries": ["sssp(0)", "pagerank(0.85, l1 1e-9)"],
-                   "parallelism": "1 gpu"},
+                   "parallelism": "1 gpu", "heavy_degree": args.heavy_degree or 512,
+                   "sssp_persistent": args.sssp_persistent, "pr_mode": args.pr_mode},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "static_recompute": static,

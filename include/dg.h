@@ -77,7 +77,11 @@ typedef struct dg_config {
     /* 1 = run SSSP fixed points with the persistent single-launch kernel,
      * 0 = one launch per frontier step; default (-1 or 0 field) = automatic. */
     int32_t sssp_persistent;
-    int32_t reserved[7];
+    /* PageRank iteration after a batch: 0 = automatic (global dangling-uniform
+     * form when the affected set holds >= 20% of the edges, else the local
+     * restricted form), 1 = always local, 2 = always global. */
+    int32_t pr_mode;
+    int32_t reserved[6];
 } dg_config;
 
 /* Per-batch statistics and phase timings (HIP events on the graph's stream). */
@@ -187,6 +191,118 @@ int dg_sssp_read(dg_query *q, int32_t *dist, int32_t *parent, uint32_t flags);
 int dg_pr_read(dg_query *q, double *rank, int32_t *iters, int32_t *converged, uint32_t flags);
 
 int dg_tc_read(dg_query *q, uint64_t *count);
+
+/* ---- batched sets of independent graphs ------------------------------------------------ */
+
+/* Many independent directed graphs kept as one device-resident store and updated
+ * together (the paper's Batch construct, Section 3.3.1, applied across graphs).
+ * Member i has n[i] vertices and m[i] arcs; the arcs of all members are
+ * concatenated in src/dst/w (w may be NULL: weight 1) with member-local vertex
+ * ids.  flags may hold DG_DEVICE_PTRS for src/dst/w (n and m are host arrays).
+ * Shortest paths run on the persistent work queue (cfg->sssp_persistent is forced
+ * to 1) and each batch's update is replayed from a captured hipGraph. */
+typedef struct dg_set dg_set;
+int dg_set_create(int32_t count, const int32_t *n, const int64_t *m, const int32_t *src,
+                  const int32_t *dst, const int32_t *w, uint32_t flags, const dg_config *cfg,
+                  dg_set **out);
+int dg_set_destroy(dg_set *s);
+/* Members, total vertices and total live arcs. */
+int dg_set_info(dg_set *s, int32_t *count, int64_t *vertices, int64_t *arcs);
+/* Attach shortest paths from member-local vertex sources[i] of every member
+ * (static solve of every member; staticSSSP of Appendix A). */
+int dg_set_sssp_attach(dg_set *s, const int32_t *sources);
+/* Apply one update batch per member and bring every member's distances up to
+ * date (DynSSSP of Appendix A).  k[i] updates for member i (host array),
+ * concatenated in src/dst/w/op with member-local ids, semantics as
+ * dg_apply_batch.  An id outside [0, n[i]) for its member, or any other invalid
+ * update, rejects the whole call with DG_EINVAL before any change. */
+int dg_set_apply_sssp(dg_set *s, const int64_t *k, const int32_t *src, const int32_t *dst,
+                      const int32_t *w, const uint8_t *op, uint32_t flags, dg_batch_stats *stats);
+/* Distances / parents of member i (member-local ids; n[i] entries each, parent
+ * may be NULL).  Host pointers unless DG_DEVICE_PTRS. */
+int dg_set_sssp_read(dg_set *s, int32_t member, int32_t *dist, int32_t *parent, uint32_t flags);
+/* hipGraph replays and captures so far (a capture happens on the first batch and
+ * whenever a buffer of the store is reallocated). */
+int dg_set_graph_stats(dg_set *s, int64_t *launches, int64_t *captures);
+
+/* ---- serving ------------------------------------------------------------------------- */
+
+/* A request loop over resident graphs.  This is not in the paper; the Batch
+ * construct of Section 3.3.1 is applied per request.  Every resident directed
+ * graph keeps a PageRank (damping 0.85, L1 tolerance 1e-9) and a symmetrised
+ * undirected copy with a triangle count: {u,v} is an edge of the copy while
+ * (u,v) or (v,u) is an arc.
+ *
+ * A request is one update batch for one graph plus one query:
+ *   - kind 0: distances from `source`, written to out (int32[n]);
+ *   - kind 1: PageRank, written to out (double[n]);
+ *   - kind 2: triangle count of the copy, also written to out (uint64, nullable).
+ *
+ * Scheduling.  `workers` threads each own a HIP stream.  A free worker takes the
+ * oldest waiting request of a graph no other worker holds, once the request's
+ * device-memory estimate fits under budget_bytes together with the running
+ * requests.  So work for different graphs overlaps, and requests of one graph run
+ * in arrival order, with results equal to running that sequence alone.
+ *
+ * Submission.  Submit copies the batch and returns at once:
+ *   - DG_EBUSY when max_waiting requests already wait;
+ *   - DG_EBUDGET when one request alone exceeds the budget.
+ * The caller's out buffer must stay valid until the request is waited for.
+ *
+ * Clock.  Times are seconds since dg_server_start. */
+typedef struct dg_server dg_server;
+typedef struct dg_server_config {
+    int32_t workers;       /* worker threads / streams; 0 = 4 */
+    int32_t reserved0;
+    int64_t budget_bytes;  /* device bytes for running requests; 0 = 8 GiB */
+    int64_t max_waiting;   /* 0 = 2^20 */
+} dg_server_config;
+typedef struct dg_request {
+    int32_t graph;
+    int32_t kind;          /* 0 SSSP, 1 PageRank, 2 triangles */
+    int32_t source;
+    int32_t reserved0;
+    int64_t k;             /* updates in the batch (may be 0) */
+    const int32_t *src, *dst, *w; /* host arrays; w nullable (weight 1) */
+    const uint8_t *op;     /* 0 delete, 1 insert */
+    void *out;             /* host result buffer (see above) */
+} dg_request;
+typedef struct dg_result {
+    int32_t status;        /* DG_OK or the error of the request */
+    int32_t pr_iters;
+    double t_submit, t_start, t_end;
+    int64_t applied;       /* edges deleted + inserted in the directed graph */
+    uint64_t tc;
+} dg_result;
+int dg_server_create(const dg_server_config *cfg, dg_server **out);
+/* Add a directed graph (host arrays; see dg_graph_create) before start. */
+int dg_server_add_graph(dg_server *s, int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                        const int32_t *w, const dg_config *cfg, int32_t *graph_id);
+int dg_server_start(dg_server *s);
+int dg_server_submit(dg_server *s, const dg_request *req, int64_t *ticket);
+/* Block until the request ends (timeout < 0: no limit) and release its ticket;
+ * DG_ENOTFOUND on timeout (the ticket stays valid) or for an unknown ticket. */
+int dg_server_wait(dg_server *s, int64_t ticket, double timeout_s, dg_result *res);
+/* Non-blocking form of dg_server_wait. */
+int dg_server_poll(dg_server *s, int64_t ticket, dg_result *res);
+/* Requests waiting for a worker, device bytes of the running ones. */
+int dg_server_stats(dg_server *s, int64_t *waiting, int64_t *inflight_bytes);
+/* Stop the workers after the running requests and free everything. */
+int dg_server_destroy(dg_server *s);
+
+/* ---- tuning ------------------------------------------------------------------------ */
+
+/* Time candidate tile shapes (rows split above heavy_degree in {32..512},
+ * persistent workgroups in {256..2048} where relevant) on one batch of updates
+ * (same arguments as dg_apply_batch, applied to a device snapshot and rolled back
+ * after every trial, so the graph is unchanged), keep the fastest in the graph's
+ * configuration and report it in *best (nullable) with its time in *best_ms. */
+int dg_autotune(dg_graph *g, int64_t k, const int32_t *src, const int32_t *dst, const int32_t *w,
+                const uint8_t *op, uint32_t flags, dg_config *best, double *best_ms);
+/* The same for a set, with one batch per member (arguments of dg_set_apply_sssp). */
+int dg_set_autotune(dg_set *s, const int64_t *k, const int32_t *src, const int32_t *dst,
+                    const int32_t *w, const uint8_t *op, uint32_t flags, dg_config *best,
+                    double *best_ms);
 
 /* ---- kernel timing ---------------------------------------------------------------- */
 

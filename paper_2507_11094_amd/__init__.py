@@ -39,6 +39,10 @@ EXPORTS = (
     "dg_sssp_attach", "dg_pr_attach", "dg_tc_attach", "dg_query_detach", "dg_sssp_read",
     "dg_pr_read", "dg_tc_read", "dg_sssp_static", "dg_pr_static", "dg_tc_static",
     "dg_profile_enable", "dg_profile_reset", "dg_profile_read",
+    "dg_set_create", "dg_set_destroy", "dg_set_info", "dg_set_sssp_attach", "dg_set_apply_sssp",
+    "dg_set_sssp_read", "dg_set_graph_stats", "dg_autotune", "dg_set_autotune",
+    "dg_server_create", "dg_server_add_graph", "dg_server_start", "dg_server_submit", "dg_server_wait",
+    "dg_server_poll", "dg_server_stats", "dg_server_destroy",
 )
 
 
@@ -51,7 +55,8 @@ class DGError(RuntimeError):
 class Config(ctypes.Structure):
     _fields_ = [("merge_threshold", ctypes.c_double), ("pr_tol_scale", ctypes.c_double),
                 ("heavy_degree", ctypes.c_int32), ("persistent_groups", ctypes.c_int32),
-                ("sssp_persistent", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+                ("sssp_persistent", ctypes.c_int32), ("pr_mode", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 6)]
 
 
 class KernelProf(ctypes.Structure):
@@ -124,6 +129,15 @@ def load_library() -> ctypes.CDLL:
         "dg_profile_enable": ([I32], ctypes.c_int),
         "dg_profile_reset": ([], ctypes.c_int),
         "dg_profile_read": ([P, I32, P], ctypes.c_int),
+        "dg_set_create": ([I32, P, P, P, P, P, U32, P, ctypes.POINTER(P)], ctypes.c_int),
+        "dg_set_destroy": ([P], ctypes.c_int),
+        "dg_set_info": ([P, P, P, P], ctypes.c_int),
+        "dg_set_sssp_attach": ([P, P], ctypes.c_int),
+        "dg_set_apply_sssp": ([P, P, P, P, P, P, U32, P], ctypes.c_int),
+        "dg_set_sssp_read": ([P, I32, P, P, U32], ctypes.c_int),
+        "dg_set_graph_stats": ([P, P, P], ctypes.c_int),
+        "dg_autotune": ([P, I64, P, P, P, P, U32, P, P], ctypes.c_int),
+        "dg_set_autotune": ([P, P, P, P, P, P, U32, P, P], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -341,3 +355,208 @@ class Graph:
         c = ctypes.c_uint64()
         _check(load_library().dg_tc_static(self.handle, ctypes.byref(c)))
         return int(c.value)
+
+
+class GraphSet:
+    """Many independent directed graphs updated together (dg_set_*).
+
+    Members are given as lists of (n_i, src_i, dst_i, w_i) with member-local ids."""
+
+    def __init__(self, members, config: Config | None = None):
+        lib = load_library()
+        self.count = len(members)
+        self.n = np.array([m[0] for m in members], np.int32)
+        self.m = np.array([len(m[1]) for m in members], np.int64)
+        src = np.ascontiguousarray(np.concatenate([np.asarray(m[1], np.int32) for m in members]))
+        dst = np.ascontiguousarray(np.concatenate([np.asarray(m[2], np.int32) for m in members]))
+        w = np.ascontiguousarray(np.concatenate([np.asarray(m[3], np.int32) for m in members]))
+        h = ctypes.c_void_p()
+        _check(lib.dg_set_create(self.count, self.n.ctypes.data, self.m.ctypes.data, src.ctypes.data,
+                                 dst.ctypes.data, w.ctypes.data, 0,
+                                 ctypes.byref(config) if config is not None else None, ctypes.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _check(load_library().dg_set_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self):
+        c = ctypes.c_int32()
+        v = ctypes.c_int64()
+        a = ctypes.c_int64()
+        _check(load_library().dg_set_info(self.handle, ctypes.byref(c), ctypes.byref(v), ctypes.byref(a)))
+        return {"count": c.value, "vertices": v.value, "arcs": a.value}
+
+    def sssp_attach(self, sources):
+        s = np.ascontiguousarray(np.asarray(sources, np.int32))
+        _check(load_library().dg_set_sssp_attach(self.handle, s.ctypes.data))
+
+    @staticmethod
+    def _batches(batches):
+        k = np.array([len(b[0]) for b in batches], np.int64)
+        cat = [np.ascontiguousarray(np.concatenate([np.asarray(b[i], dt) for b in batches]))
+               for i, dt in ((0, np.int32), (1, np.int32), (2, np.int32), (3, np.uint8))]
+        return k, cat
+
+    def apply(self, batches) -> BatchStats:
+        """batches: per member (src, dst, w, op) with member-local ids."""
+        k, (s, d, w, o) = self._batches(batches)
+        st = BatchStats()
+        _check(load_library().dg_set_apply_sssp(self.handle, k.ctypes.data, s.ctypes.data, d.ctypes.data,
+                                                w.ctypes.data, o.ctypes.data, 0, ctypes.byref(st)))
+        return st
+
+    def apply_device(self, k, s, d, w, o) -> BatchStats:
+        """Pre-concatenated batch already in device memory (torch tensors); k host int64."""
+        kk = np.ascontiguousarray(np.asarray(k, np.int64))
+        st = BatchStats()
+        _check(load_library().dg_set_apply_sssp(self.handle, kk.ctypes.data, ctypes.c_void_p(s.data_ptr()),
+                                                ctypes.c_void_p(d.data_ptr()), ctypes.c_void_p(w.data_ptr()),
+                                                ctypes.c_void_p(o.data_ptr()), DG_DEVICE_PTRS,
+                                                ctypes.byref(st)))
+        return st
+
+    def autotune(self, batches):
+        k, (s, d, w, o) = self._batches(batches)
+        best = Config()
+        ms = ctypes.c_double()
+        _check(load_library().dg_set_autotune(self.handle, k.ctypes.data, s.ctypes.data, d.ctypes.data,
+                                              w.ctypes.data, o.ctypes.data, 0, ctypes.byref(best),
+                                              ctypes.byref(ms)))
+        return best, ms.value
+
+    def read(self, member):
+        n = int(self.n[member])
+        dist = np.empty(n, np.int32)
+        par = np.empty(n, np.int32)
+        _check(load_library().dg_set_sssp_read(self.handle, int(member), dist.ctypes.data, par.ctypes.data, 0))
+        return dist, par
+
+    def graph_stats(self):
+        a = ctypes.c_int64()
+        b = ctypes.c_int64()
+        _check(load_library().dg_set_graph_stats(self.handle, ctypes.byref(a), ctypes.byref(b)))
+        return {"launches": a.value, "captures": b.value}
+
+
+def autotune(graph: "Graph", src, dst, w, op):
+    """dg_autotune on one batch (host arrays); returns (best Config, ms)."""
+    ps, ks, _ = _arr(src, np.int32)
+    pd, kd, _ = _arr(dst, np.int32)
+    pw, kw, _ = _arr(w, np.int32)
+    po, ko, _ = _arr(op, np.uint8)
+    best = Config()
+    ms = ctypes.c_double()
+    _check(load_library().dg_autotune(graph.handle, int(ks.size), ps, pd, pw, po, 0, ctypes.byref(best),
+                                      ctypes.byref(ms)))
+    return best, ms.value
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("workers", ctypes.c_int32), ("reserved0", ctypes.c_int32), ("budget_bytes", ctypes.c_int64),
+                ("max_waiting", ctypes.c_int64)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("graph", ctypes.c_int32), ("kind", ctypes.c_int32), ("source", ctypes.c_int32),
+                ("reserved0", ctypes.c_int32), ("k", ctypes.c_int64), ("src", ctypes.c_void_p),
+                ("dst", ctypes.c_void_p), ("w", ctypes.c_void_p), ("op", ctypes.c_void_p),
+                ("out", ctypes.c_void_p)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("pr_iters", ctypes.c_int32), ("t_submit", ctypes.c_double),
+                ("t_start", ctypes.c_double), ("t_end", ctypes.c_double), ("applied", ctypes.c_int64),
+                ("tc", ctypes.c_uint64)]
+
+
+SSSP, PAGERANK, TRIANGLES = 0, 1, 2
+
+
+def _server_lib():
+    lib = load_library()
+    if not getattr(lib, "_server_sigs", False):
+        P = ctypes.c_void_p
+        for name, args in (("dg_server_create", [P, ctypes.POINTER(P)]),
+                           ("dg_server_add_graph", [P, ctypes.c_int32, ctypes.c_int64, P, P, P, P, P]),
+                           ("dg_server_start", [P]), ("dg_server_submit", [P, P, P]),
+                           ("dg_server_wait", [P, ctypes.c_int64, ctypes.c_double, P]),
+                           ("dg_server_poll", [P, ctypes.c_int64, P]), ("dg_server_stats", [P, P, P]),
+                           ("dg_server_destroy", [P])):
+            f = getattr(lib, name)
+            f.argtypes = args
+            f.restype = ctypes.c_int
+        lib._server_sigs = True
+    return lib
+
+
+class Server:
+    """dg_server_*: resident graphs, continuous batching across graphs, admission by
+    a device-memory budget."""
+
+    def __init__(self, workers=4, budget_bytes=8 << 30, max_waiting=1 << 20):
+        lib = _server_lib()
+        c = ServerConfig(workers, 0, budget_bytes, max_waiting)
+        h = ctypes.c_void_p()
+        _check(lib.dg_server_create(ctypes.byref(c), ctypes.byref(h)))
+        self.handle = h
+        self.n = []
+        self._pending = {}
+
+    def add_graph(self, n, src, dst, w=None, config: Config | None = None) -> int:
+        s = np.ascontiguousarray(np.asarray(src, np.int32))
+        d = np.ascontiguousarray(np.asarray(dst, np.int32))
+        ww = None if w is None else np.ascontiguousarray(np.asarray(w, np.int32))
+        gid = ctypes.c_int32()
+        _check(_server_lib().dg_server_add_graph(self.handle, int(n), s.size, s.ctypes.data, d.ctypes.data,
+                                                 None if ww is None else ww.ctypes.data,
+                                                 ctypes.byref(config) if config is not None else None,
+                                                 ctypes.byref(gid)))
+        self.n.append(int(n))
+        return gid.value
+
+    def start(self):
+        _check(_server_lib().dg_server_start(self.handle))
+
+    def submit(self, graph, kind, src, dst, w, op, source=0) -> int:
+        n = self.n[graph]
+        out = (np.empty(n, np.int32) if kind == SSSP else np.empty(n, np.float64) if kind == PAGERANK
+               else np.zeros(1, np.uint64))
+        arrs = [np.ascontiguousarray(np.asarray(a, dt)) for a, dt in
+                ((src, np.int32), (dst, np.int32), (w, np.int32), (op, np.uint8))]
+        r = Request(int(graph), int(kind), int(source), 0, arrs[0].size, arrs[0].ctypes.data, arrs[1].ctypes.data,
+                    arrs[2].ctypes.data, arrs[3].ctypes.data, out.ctypes.data)
+        t = ctypes.c_int64()
+        _check(_server_lib().dg_server_submit(self.handle, ctypes.byref(r), ctypes.byref(t)))
+        self._pending[t.value] = out  # keep the result buffer alive
+        return t.value
+
+    def wait(self, ticket, timeout=-1.0):
+        res = Result()
+        _check(_server_lib().dg_server_wait(self.handle, int(ticket), float(timeout), ctypes.byref(res)))
+        out = self._pending.pop(ticket)
+        return res, out
+
+    def stats(self):
+        a = ctypes.c_int64()
+        b = ctypes.c_int64()
+        _check(_server_lib().dg_server_stats(self.handle, ctypes.byref(a), ctypes.byref(b)))
+        return {"waiting": a.value, "inflight_bytes": b.value}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _check(_server_lib().dg_server_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

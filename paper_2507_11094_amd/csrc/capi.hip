@@ -192,6 +192,8 @@ int dg_graph_destroy(dg_graph *g) {
     if (!g) return set_error(DG_EINVAL, "null graph");
     for (dg_query *q : g->queries) {
         q->key.release(); q->inval.release(); q->x.release(); q->xn.release(); q->contrib.release();
+        q->qcnt.release(); q->srcs.release();
+        if (q->hpin) (void)hipHostFree(q->hpin);
         delete q;
     }
     g->queries.clear();
@@ -312,6 +314,8 @@ static int attach(dg_graph *g, dg_query *q, dg_query **out) {
     int rc = q->kind == Q_SSSP ? sssp_init(q) : (q->kind == Q_PR ? pr_init(q) : tc_count_static(g, &q->tc));
     if (rc != DG_OK) {
         q->key.release(); q->inval.release(); q->x.release(); q->xn.release(); q->contrib.release();
+        q->qcnt.release(); q->srcs.release();
+        if (q->hpin) (void)hipHostFree(q->hpin);
         delete q;
         return mark_device_error(g, rc);
     }
@@ -361,6 +365,8 @@ int dg_query_detach(dg_query *q) {
     g->queries.erase(it);
     (void)hipStreamSynchronize(g->stream);
     q->key.release(); q->inval.release(); q->x.release(); q->xn.release(); q->contrib.release();
+        q->qcnt.release(); q->srcs.release();
+        if (q->hpin) (void)hipHostFree(q->hpin);
     delete q;
     return DG_OK;
 }
@@ -433,3 +439,33 @@ int dg_tc_static(dg_graph *g, uint64_t *count) {
 }
 
 }  // extern "C"
+
+namespace dg {
+
+// Build a directed graph from device edge arrays on a given stream (batched sets).
+int graph_create_dev(int32_t n, int64_t m, const int32_t *ds, const int32_t *dd, const int32_t *dw,
+                     const dg_config *cfg, hipStream_t stream, dg_graph **out) {
+    *out = nullptr;
+    if (n <= 0 || n > (1 << 30)) return set_error(DG_EINVAL, "n must be in [1, 2^30]");
+    dg_graph *g = new dg_graph();
+    g->n = n;
+    g->cfg = defaults(cfg);
+    g->rev = &g->rev_own;
+    g->stream = stream;
+    int rc = ws_init(g);
+    if (rc == DG_OK) rc = graph_build(g, m, ds, dd, dw);
+    if (rc != DG_OK) {
+        dir_free(g->fwd);
+        dir_free(g->rev_own);
+        ws_free(g);
+        delete g;
+        return rc;
+    }
+    ++g_live_graphs;
+    *out = g;
+    return DG_OK;
+}
+
+int query_attach(dg_graph *g, dg_query *q, dg_query **out) { return attach(g, q, out); }
+
+}  // namespace dg

@@ -87,6 +87,15 @@ __device__ __forceinline__ T wave_min(T x) {
     return x;
 }
 
+__device__ __forceinline__ int32_t wave_max_i32(int32_t x) {
+#pragma unroll
+    for (int d = WAVE / 2; d > 0; d >>= 1) {
+        int32_t y = __shfl_xor(x, d, WAVE);
+        x = y > x ? y : x;
+    }
+    return x;
+}
+
 // One atomic per wave for a counter bump of `pred` lanes; returns the slot of
 // this lane (valid where pred is true).
 __device__ __forceinline__ int64_t wave_append(int64_t *counter, bool pred) {

@@ -124,10 +124,25 @@ struct Work {
     DBuf<int32_t> stamp;                  // per-vertex dedup stamps
     int32_t stamp_ctr = 0;
     DBuf<double> part;                    // partial sums of split rows
+    DBuf<double> prs;                     // PageRank scalars: step, dangling mass, constant term
+    // device work queue of the persistent traversals (worklist.hip)
+    DBuf<int64_t> wq;
+    DBuf<uint64_t> wseq, wctr;
+    DBuf<int32_t> inq;                    // per-vertex in-queue flags (all zero between runs)
     // counters: device block + pinned host mirror
     int64_t *dcnt = nullptr;
     int64_t *hcnt = nullptr;
     hipEvent_t ev[16] = {};
+};
+
+// Captured hipGraphs of a launch sequence, keyed by the pointers they bake in.
+struct GraphCacheEntry {
+    std::vector<const void *> sig;
+    hipGraphExec_t exec;
+};
+struct GraphCache {
+    std::vector<GraphCacheEntry> entries;
+    int64_t captures = 0, launches = 0;
 };
 
 enum Counter {
@@ -162,6 +177,11 @@ struct dg_query {
     dg::DBuf<uint64_t> key;
     dg::DBuf<int32_t> inval;  // cut vertices (seeds first)
     int64_t nseeds = 0;
+    dg::DBuf<int64_t> qcnt;   // device copies of nseeds and the applied-insert count
+    int64_t *hpin = nullptr;  // pinned staging for qcnt
+    dg::DBuf<int32_t> srcs;   // device list of sources (multi-source: one per member graph)
+    int64_t nsrc = 0;         // 0: single source `source`
+    dg::GraphCache *gcache = nullptr;  // set: replay the update from captured hipGraphs
     // PageRank: unnormalised x of the dangling-dropped system, x/outdeg cache
     double damping = 0.85, tol = 1e-9;
     int32_t max_iter = 1000;
@@ -202,6 +222,22 @@ int sssp_pre_delete(dg_query *q, int64_t n_applied_del);
 int sssp_post_update(dg_query *q, int64_t n_applied_del, int64_t n_applied_ins, dg_batch_stats *st);
 int sssp_read(dg_query *q, int32_t *dist, int32_t *parent, bool dev);
 int sssp_unpack(dg_graph *g, const uint64_t *key, int32_t *dist, int32_t *parent, hipStream_t s);
+
+// handles (capi.hip)
+int graph_create_dev(int32_t n, int64_t m, const int32_t *ds, const int32_t *dd, const int32_t *dw,
+                     const dg_config *cfg, hipStream_t stream, dg_graph **out);
+int query_attach(dg_graph *g, dg_query *q, dg_query **out);
+
+// persistent worklist traversals (worklist.hip)
+int sssp_static_persistent(dg_graph *g, uint64_t *key, const int32_t *sources, int64_t ns);
+int sssp_post_persistent(dg_graph *g, uint64_t *key, const int32_t *seeds, const int64_t *nseeds_dev,
+                         int32_t *cut, const int64_t *ains_dev, int64_t *ncut_out);
+int sssp_post_graph(dg_graph *g, GraphCache *cache, uint64_t *key, const int32_t *seeds,
+                    const int64_t *nseeds_dev, int32_t *cut, const int64_t *ains_dev, int64_t *ncut_out);
+void graph_cache_clear(GraphCache *cache);
+int wl_prepare(dg_graph *g);
+int wl_groups(dg_graph *g);
+int sssp_static_multi(dg_graph *g, uint64_t *key, const int32_t *srcs, int64_t ns, dg_batch_stats *st);
 
 // PageRank (pagerank.hip)
 int pr_init(dg_query *q);

@@ -110,7 +110,8 @@ void ws_free(dg_graph *g) {
     w.aiu.release(); w.aiv.release(); w.aiw.release(); w.aipos.release();
     w.nkey.release(); w.nw.release(); w.tcu.release(); w.tcv.release(); w.tmp.release();
     w.scan64.release(); w.tscan.release(); w.f0.release(); w.f1.release(); w.heavy.release();
-    w.stamp.release(); w.part.release();
+    w.stamp.release(); w.part.release(); w.prs.release();
+    w.wq.release(); w.wseq.release(); w.wctr.release(); w.inq.release();
     if (w.dcnt) dfree(w.dcnt);
     if (w.hcnt) (void)hipHostFree(w.hcnt);
     for (auto &e : w.ev)

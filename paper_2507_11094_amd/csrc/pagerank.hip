@@ -20,6 +20,20 @@
 //            (the complement of A has no in-edge from A and no changed in-edge, so
 //            its old values still satisfy the fixed-point equations);
 //   Jacobi on A only, warm-started from the previous x, until the L1 step <= tol.
+//
+// Two iteration forms share the kernels (only the constant term differs):
+//   local  (the listing's): x' = d P^T x + (1-d)/n, on A only.  Its error decays
+//          like (d * rho)^k, rho the spectral radius of P^T on the recirculating
+//          core (measured ~0.80 per step on R-MAT), hence many iterations.
+//   global (dangling mass spread uniformly): y' = d P^T y + ((1-d) S + d D(y))/n
+//          with S = sum(y) (conserved) and D(y) the mass on dangling vertices.  Its
+//          fixed point is S * PageRank and it contracts at the second eigenvalue
+//          of the Google matrix (~0.46 per step measured on R-MAT), but every
+//          vertex moves each step.  Used for the static solve and for batches whose
+//          affected set already covers most edges (auto: >= 20% of them), where
+//          locality buys nothing; the result is rescaled to the local form's
+//          fixed point, x = (1-d) / ((1-d) S + d D(y)) * y, so the next small batch
+//          can continue locally.
 #include <algorithm>
 #include <cstring>
 
@@ -48,10 +62,11 @@ __global__ void k_pr_init(int32_t n, double *x, double *contrib, const int32_t *
 // scan in a fixed lane order; heavy vertices are cut into chunks (partial sums in
 // `part`, combined in chunk order by k_pr_finish).  Deterministic throughout.
 __global__ __launch_bounds__(256) void k_pr_pull(const int32_t *A, int64_t na, DirView g,
-                                                 const double *__restrict__ contrib, double base,
+                                                 const double *__restrict__ contrib, const double *cterm,
                                                  double damp, double *xn, int64_t *hq, int64_t *hcount,
                                                  int64_t *hv, int64_t *hvcount, int heavy_deg, int chunk) {
     __shared__ double sacc[4][WAVE];
+    const double base = *cterm;
     const int wslot = threadIdx.x / WAVE;
     const int64_t wave_global = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / WAVE;
@@ -149,9 +164,10 @@ __global__ __launch_bounds__(256) void k_pr_heavy(DirView g, const double *__res
     }
 }
 
-__global__ void k_pr_finish(const int64_t *hv, const int64_t *hvcount, const double *part, double base,
-                            double damp, double *xn) {
+__global__ void k_pr_finish(const int64_t *hv, const int64_t *hvcount, const double *part,
+                            const double *cterm, double damp, double *xn) {
     const int64_t nh = *hvcount;
+    const double base = *cterm;
     for (int64_t i = gtid(); i < nh; i += gstride()) {
         const int32_t v = (int32_t)(hv[2 * i] >> 32);
         const int32_t nch = (int32_t)(hv[2 * i] & 0xffffffff);
@@ -162,11 +178,30 @@ __global__ void k_pr_finish(const int64_t *hv, const int64_t *hvcount, const dou
     }
 }
 
-// x := xn, contrib := x / outdeg on A, and the L1 step as fixed-order partials.
+// Fixed-order block reduction of two values.
+__device__ __forceinline__ void block_sum2(double a, double b, double *out_a, double *out_b) {
+    __shared__ double ra[256], rb[256];
+    ra[threadIdx.x] = a;
+    rb[threadIdx.x] = b;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            ra[threadIdx.x] += ra[threadIdx.x + s];
+            rb[threadIdx.x] += rb[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        *out_a = ra[0];
+        *out_b = rb[0];
+    }
+}
+
+// x := xn, contrib := x / outdeg on A; fixed-order partials of the L1 step and of
+// the new mass on dangling vertices.
 __global__ __launch_bounds__(256) void k_pr_apply(const int32_t *A, int64_t na, const double *xn, double *x,
                                                   double *contrib, const int32_t *deg, double *partials) {
-    __shared__ double red[256];
-    double acc = 0.0;
+    double acc = 0.0, dang = 0.0;
     for (int64_t i = gtid(); i < na; i += gstride()) {
         int32_t v = A ? A[i] : (int32_t)i;
         double nv = xn[v];
@@ -174,14 +209,50 @@ __global__ __launch_bounds__(256) void k_pr_apply(const int32_t *A, int64_t na, 
         x[v] = nv;
         int32_t dg = deg[v];
         contrib[v] = dg > 0 ? nv / (double)dg : 0.0;
+        if (dg == 0) dang += nv;
     }
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-        __syncthreads();
+    block_sum2(acc, dang, &partials[2 * blockIdx.x], &partials[2 * blockIdx.x + 1]);
+}
+
+// prs[0] = L1 step, prs[1] = dangling mass, prs[2] = constant term of the next
+// step (global form: ((1-d) S + d D) / n; local form: (1-d) / n).  The step is
+// also copied to *step_out for the host.
+__global__ void k_pr_reduce(const double *partials, int np, int global, double S, double damp,
+                            double ninv, double *prs, double *step_out) {
+    double a = 0.0, b = 0.0;
+    for (int i = threadIdx.x; i < np; i += blockDim.x) {
+        a += partials[2 * i];
+        b += partials[2 * i + 1];
     }
-    if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
+    block_sum2(a, b, &prs[0], &prs[1]);
+    if (threadIdx.x == 0) {
+        prs[2] = global ? ((1.0 - damp) * S + damp * prs[1]) * ninv : (1.0 - damp) * ninv;
+        *step_out = prs[0];
+    }
+}
+
+// Sum and dangling mass of a whole vector: partials for k_pr_reduce.
+__global__ __launch_bounds__(256) void k_sum_vec2(const double *x, const int32_t *deg, int64_t n,
+                                                  double *partials) {
+    double a = 0.0, b = 0.0;
+    for (int64_t i = gtid(); i < n; i += gstride()) {
+        a += x[i];
+        if (deg[i] == 0) b += x[i];
+    }
+    block_sum2(a, b, &partials[2 * blockIdx.x], &partials[2 * blockIdx.x + 1]);
+}
+
+// Scale a global-form solution y to the local form's fixed point:
+// x = (1-d) / ((1-d) S + d D(y)) * y, contrib = x / outdeg.
+__global__ void k_pr_rescale(int32_t n, double *x, double *contrib, const int32_t *deg, const double *prs,
+                             double S, double damp) {
+    const double alpha = (1.0 - damp) / ((1.0 - damp) * S + damp * prs[1]);
+    for (int64_t v = gtid(); v < n; v += gstride()) {
+        double nv = x[v] * alpha;
+        x[v] = nv;
+        int32_t dg = deg[v];
+        contrib[v] = dg > 0 ? nv / (double)dg : 0.0;
+    }
 }
 
 __global__ void k_sum_partials(const double *partials, int np, double *out) {
@@ -223,7 +294,8 @@ struct ReachOp {
     int64_t *ncount;
     __device__ bool vtx(int32_t, int32_t &pay) const { pay = 0; return true; }
     __device__ void edge(bool valid, int32_t, int32_t, int32_t x, int32_t) const {
-        bool p = valid && atomicExch(&stamp[x], st) != st;
+        // plain load first: most edges reach vertices that are already marked
+        bool p = valid && stamp[x] != st && atomicExch(&stamp[x], st) != st;
         int64_t slot = wave_append(ncount, p);
         if (p) next[slot] = x;
     }
@@ -274,7 +346,8 @@ static int ensure_pr_ws(dg_graph *g) {
     int64_t edges = std::max(g->fwd.m + g->fwd.dm, g->rev->m + g->rev->dm);
     const int64_t qcap = 2 * (edges / heavy_deg(g) + 2) + g->n / 8 + 64;
     DG_TRY(ws.heavy.ensure((size_t)qcap * 2 + 2 * (size_t)qcap * 2));
-    DG_TRY(ws.part.ensure((size_t)qcap + APPLY_GROUPS + 8));
+    DG_TRY(ws.part.ensure((size_t)qcap + 2 * APPLY_GROUPS + 8));
+    DG_TRY(ws.prs.ensure(8));
     return DG_OK;
 }
 
@@ -291,12 +364,14 @@ __global__ void k_sum_degrees(const int32_t *A, int64_t na, const int64_t *off, 
 }
 
 // Jacobi on A (nullptr = all n vertices) until the L1 step <= tol or max_iter.
-// `edges` = entries scanned per pull (for the algorithmic byte count):
+// global: the dangling-uniform form with conserved mass S (see the file header);
+// otherwise the local form.  `edges` = entries scanned per pull (for the
+// algorithmic byte count):
 //   pull:  A[i] 4 + off 8 + doff 8 + xn write 8 per vertex, col 4 + contrib 8 per entry
 //   apply: A[i] 4 + xn 8 + x read 8 + x write 8 + contrib write 8 + outdeg 4 per vertex
 static int pr_iterate(dg_graph *g, const int32_t *A, int64_t na, int64_t edges, double damping,
-                      double tol, int32_t max_iter, double *x, double *xn, double *contrib,
-                      int32_t *iters, int32_t *conv) {
+                      double tol, int32_t max_iter, bool global, double S, double *x, double *xn,
+                      double *contrib, int32_t *iters, int32_t *conv) {
     hipStream_t s = g->stream;
     Work &ws = g->ws;
     const int64_t qcap = 2 * (std::max(g->fwd.m + g->fwd.dm, g->rev->m + g->rev->dm) / heavy_deg(g) + 2) +
@@ -304,28 +379,39 @@ static int pr_iterate(dg_graph *g, const int32_t *A, int64_t na, int64_t edges, 
     int64_t *hq = reinterpret_cast<int64_t *>(ws.heavy.p);
     int64_t *hv = hq + qcap;
     double *partials = ws.part.p + qcap;
-    const double base = (1.0 - damping) / (double)g->n;
+    const double ninv = 1.0 / (double)g->n;
     DirView rv = view(*g->rev);
+    double *prs = ws.prs.p;
+    double *step_out = reinterpret_cast<double *>(ws.dcnt + C_RED0);
+    // constant term of the first step
+    if (global)
+        hipLaunchKernelGGL(k_sum_vec2, dim3(APPLY_GROUPS), dim3(256), 0, s, x, g->fwd.deg.p, (int64_t)g->n,
+                           partials);
+    else
+        hipLaunchKernelGGL(k_sum_vec2, dim3(1), dim3(256), 0, s, x, g->fwd.deg.p, (int64_t)0, partials);
+    hipLaunchKernelGGL(k_pr_reduce, dim3(1), dim3(256), 0, s, partials, global ? APPLY_GROUPS : 1,
+                       (int)global, S, damping, ninv, prs, step_out);
+    DG_HIP(hipGetLastError());
     int32_t it = 0;
     *conv = 0;
-    double *dsum = reinterpret_cast<double *>(ws.dcnt + C_RED0);
     while (it < max_iter && na > 0) {
         DG_TRY(counters_clear(g));
         int64_t blocks = std::min<int64_t>((na + 255) / 256, 65535);
         int ps = prof_begin("pr_pull", s);
-        hipLaunchKernelGGL(k_pr_pull, dim3((unsigned)blocks), dim3(256), 0, s, A, na, rv, contrib, base,
+        hipLaunchKernelGGL(k_pr_pull, dim3((unsigned)blocks), dim3(256), 0, s, A, na, rv, contrib, prs + 2,
                            damping, xn, hq, ws.dcnt + C_HEAVY, hv, ws.dcnt + C_AUX3, heavy_deg(g),
                            heavy_deg(g));
         prof_end(ps, s, 28.0 * (double)na + 12.0 * (double)edges);
-        hipLaunchKernelGGL(k_pr_heavy, dim3(1024), dim3(256), 0, s, rv, contrib, hq, ws.dcnt + C_HEAVY,
+        hipLaunchKernelGGL(k_pr_heavy, dim3(8192), dim3(256), 0, s, rv, contrib, hq, ws.dcnt + C_HEAVY,
                            heavy_deg(g), ws.part.p);
-        hipLaunchKernelGGL(k_pr_finish, dim3(64), dim3(256), 0, s, hv, ws.dcnt + C_AUX3, ws.part.p, base,
+        hipLaunchKernelGGL(k_pr_finish, dim3(64), dim3(256), 0, s, hv, ws.dcnt + C_AUX3, ws.part.p, prs + 2,
                            damping, xn);
         int pa = prof_begin("pr_apply", s);
         hipLaunchKernelGGL(k_pr_apply, dim3(APPLY_GROUPS), dim3(256), 0, s, A, na, xn, x, contrib,
                            g->fwd.deg.p, partials);
         prof_end(pa, s, 40.0 * (double)na);
-        hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, partials, APPLY_GROUPS, dsum);
+        hipLaunchKernelGGL(k_pr_reduce, dim3(1), dim3(256), 0, s, partials, APPLY_GROUPS, (int)global, S,
+                           damping, ninv, prs, step_out);
         DG_HIP(hipGetLastError());
         DG_TRY(counters_read(g));
         ++it;
@@ -338,17 +424,23 @@ static int pr_iterate(dg_graph *g, const int32_t *A, int64_t na, int64_t edges, 
     }
     if (na == 0) *conv = 1;
     *iters = it;
+    if (global && na > 0) {
+        hipLaunchKernelGGL(k_pr_rescale, dim3(grid_for(g->n)), dim3(256), 0, s, g->n, x, contrib, g->fwd.deg.p,
+                           prs, S, damping);
+        DG_HIP(hipGetLastError());
+    }
     return DG_OK;
 }
 
+// Static solve: global form from the uniform vector (S = 1).
 int pr_static_solve(dg_graph *g, double damping, double tol, int32_t max_iter, double *x,
                     double *contrib, double *xn, int32_t *iters, int32_t *conv) {
     DG_TRY(ensure_pr_ws(g));
     hipLaunchKernelGGL(k_pr_init, dim3(grid_for(g->n)), dim3(256), 0, g->stream, g->n, x, contrib,
                        g->fwd.deg.p);
     DG_HIP(hipGetLastError());
-    return pr_iterate(g, nullptr, g->n, g->rev->m + g->rev->dm, damping, tol, max_iter, x, xn, contrib,
-                      iters, conv);
+    return pr_iterate(g, nullptr, g->n, g->rev->m + g->rev->dm, damping, tol, max_iter, true, 1.0, x, xn,
+                      contrib, iters, conv);
 }
 
 static double tol_of(dg_query *q) {
@@ -392,20 +484,26 @@ int pr_post_update(dg_query *q, int64_t adel, int64_t ains, dg_batch_stats *st) 
     DG_HIP(hipGetLastError());
     DG_TRY(counters_read(g));
     const int64_t ns = ws.hcnt[C_AUX0];
-    // seeds: heads of changed arcs, then all out-neighbours of the tails
-    DG_TRY(next_stamp(g, &st_a));
-    DG_TRY(counters_clear(g));
-    if (adel > 0)
-        hipLaunchKernelGGL(k_mark_list, dim3(grid_for(adel)), dim3(256), 0, s, adel, ws.adv.p,
-                           ws.stamp.p, st_a, Alist, ws.dcnt + C_F0);
-    if (ains > 0)
-        hipLaunchKernelGGL(k_mark_list, dim3(grid_for(ains)), dim3(256), 0, s, ains, ws.aiv.p,
-                           ws.stamp.p, st_a, Alist, ws.dcnt + C_F0);
+    // the tails' share x / outdeg changed: refresh it before any Jacobi step
     hipLaunchKernelGGL(k_refresh_contrib, dim3(grid_for(ns)), dim3(256), 0, s, ns, S, q->x.p, g->fwd.deg.p,
                        q->contrib.p);
     DG_HIP(hipGetLastError());
-    DG_TRY(counters_read(g));
-    int64_t na = ws.hcnt[C_F0];
+    const int mode = g->cfg.pr_mode;  // 0 auto, 1 local, 2 global
+    const int64_t vlimit = (int64_t)(0.2 * (double)g->n);
+    bool global = mode == 2;
+    if (mode == 0) {
+        // the seeds are the heads plus the tails' out-neighbours; when their count
+        // with repeats already passes 20% of the vertices, take the global form
+        // without expanding (both forms reach the same ranks; this only picks the
+        // cheaper one)
+        DG_TRY(counters_clear(g));
+        hipLaunchKernelGGL(k_sum_degrees, dim3(grid_for(ns)), dim3(256), 0, s, S, ns, g->fwd.off.p,
+                           g->fwd.doff.p, ws.dcnt + C_AUX1);
+        DG_HIP(hipGetLastError());
+        DG_TRY(counters_read(g));
+        if (adel + ains + ws.hcnt[C_AUX1] >= vlimit) global = true;
+    }
+    int64_t na = 0;
     ExpandArgs a;
     a.g = view(g->fwd);
     a.hq = hq;
@@ -413,47 +511,82 @@ int pr_post_update(dg_query *q, int64_t adel, int64_t ains, dg_batch_stats *st) 
     a.heavy_deg = heavy_deg(g);
     a.chunk = heavy_deg(g);
     (void)qcap;
-    {
+    if (!global) {
+        // seeds: heads of changed arcs, then all out-neighbours of the tails
+        DG_TRY(next_stamp(g, &st_a));
+        DG_TRY(counters_clear(g));
+        if (adel > 0)
+            hipLaunchKernelGGL(k_mark_list, dim3(grid_for(adel)), dim3(256), 0, s, adel, ws.adv.p,
+                               ws.stamp.p, st_a, Alist, ws.dcnt + C_F0);
+        if (ains > 0)
+            hipLaunchKernelGGL(k_mark_list, dim3(grid_for(ains)), dim3(256), 0, s, ains, ws.aiv.p,
+                               ws.stamp.p, st_a, Alist, ws.dcnt + C_F0);
+        DG_HIP(hipGetLastError());
+        DG_TRY(counters_read(g));
+        na = ws.hcnt[C_F0];
         DG_TRY(counters_clear(g));
         a.F = S;
         a.nf = ns;
         ReachOp op{ws.stamp.p, st_a, Alist + na, ws.dcnt + C_F1};
-        DG_TRY(launch_expand(s, a, op, 1024));
+        DG_TRY(launch_expand(s, a, op, 8192));
         DG_TRY(counters_read(g));
         na += ws.hcnt[C_F1];
+        if (mode == 0 && na >= vlimit) global = true;
     }
-    // forward closure (propagateNodeFlags): levels appended to Alist
+    // forward closure (propagateNodeFlags): levels appended to Alist.  In the
+    // automatic mode it stops once the set passes 20% of the vertices, since the
+    // global form then runs over every vertex anyway.
     int64_t lo = 0, hi = na;
-    while (hi > lo) {
+    while (!global && hi > lo) {
         DG_TRY(counters_clear(g));
         a.F = Alist + lo;
         a.nf = hi - lo;
         ReachOp op{ws.stamp.p, st_a, Alist + hi, ws.dcnt + C_F1};
-        DG_TRY(launch_expand(s, a, op, 1024));
+        DG_TRY(launch_expand(s, a, op, 8192));
         DG_TRY(counters_read(g));
         lo = hi;
         hi += ws.hcnt[C_F1];
+        if (mode == 0 && hi >= vlimit) global = true;
     }
     na = hi;
-    if (na > 0) {
+    int64_t edges = 0;
+    const int64_t all_edges = g->rev->m + g->rev->dm;
+    if (!global && na > 0) {
         DG_TRY(ws.scan64.ensure(2 * ((size_t)g->n + 1)));
         int64_t *flags = ws.scan64.p, *pos = ws.scan64.p + (g->n + 1);
         hipLaunchKernelGGL(k_stamp_flags, dim3(grid_for(g->n + 1)), dim3(256), 0, s, g->n, ws.stamp.p, st_a,
                            flags);
         DG_TRY(scan_excl(g, flags, pos, g->n + 1));
         hipLaunchKernelGGL(k_compact_flags, dim3(grid_for(g->n)), dim3(256), 0, s, g->n, flags, pos, Alist);
-        DG_HIP(hipGetLastError());
-    }
-    DG_TRY(counters_clear(g));
-    if (na > 0)
+        DG_TRY(counters_clear(g));
         hipLaunchKernelGGL(k_sum_degrees, dim3(grid_for(na)), dim3(256), 0, s, Alist, na, g->rev->off.p,
                            g->rev->doff.p, ws.dcnt + C_AUX0);
-    DG_HIP(hipGetLastError());
-    DG_TRY(counters_read(g));
-    const int64_t edges = ws.hcnt[C_AUX0];
+        DG_HIP(hipGetLastError());
+        DG_TRY(counters_read(g));
+        edges = ws.hcnt[C_AUX0];
+        if (mode == 0 && (double)edges >= 0.2 * (double)all_edges) global = true;
+    }
     int32_t iters = 0, conv = 0;
-    DG_TRY(pr_iterate(g, Alist, na, edges, q->damping, tol_of(q), q->max_iter, q->x.p, q->xn.p,
-                      q->contrib.p, &iters, &conv));
+    if (global) {
+        // warm start from the current x; S = sum(x) is conserved by the global form
+        double *partials = ws.part.p + qcap;
+        hipLaunchKernelGGL(k_sum_vec2, dim3(APPLY_GROUPS), dim3(256), 0, s, q->x.p, g->fwd.deg.p,
+                           (int64_t)g->n, partials);
+        hipLaunchKernelGGL(k_pr_reduce, dim3(1), dim3(256), 0, s, partials, APPLY_GROUPS, 0, 0.0, q->damping,
+                           1.0, ws.prs.p, reinterpret_cast<double *>(ws.dcnt + C_RED0));
+        DG_HIP(hipGetLastError());
+        double Ssum;
+        DG_HIP(hipMemcpyAsync(&Ssum, ws.prs.p, sizeof(double), hipMemcpyDeviceToHost, s));
+        DG_HIP(hipStreamSynchronize(s));
+        // prs[0] here holds the plain sum (first partial of each pair)
+        na = g->n;
+        edges = all_edges;
+        DG_TRY(pr_iterate(g, nullptr, na, edges, q->damping, tol_of(q) * Ssum, q->max_iter, true, Ssum,
+                          q->x.p, q->xn.p, q->contrib.p, &iters, &conv));
+    } else {
+        DG_TRY(pr_iterate(g, Alist, na, edges, q->damping, tol_of(q), q->max_iter, false, 0.0, q->x.p,
+                          q->xn.p, q->contrib.p, &iters, &conv));
+    }
     q->last_iters = iters;
     q->converged = conv;
     if (st) {

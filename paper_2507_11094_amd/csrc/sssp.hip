@@ -45,9 +45,13 @@ struct RelaxOp {
         bool push = false;
         if (valid) {
             uint64_t cand = sssp_pack(d + w, v);
-            uint64_t old = atomicMin((unsigned long long *)&key[x], (unsigned long long)cand);
-            if (cand < old && sssp_dist(cand) < sssp_dist(old))
-                push = atomicExch(&stamp[x], st) != st;
+            // keys only decrease, so a stale plain load can only make us skip a
+            // candidate that would not have won the atomicMin either
+            if (cand < __atomic_load_n(&key[x], __ATOMIC_RELAXED)) {
+                uint64_t old = atomicMin((unsigned long long *)&key[x], (unsigned long long)cand);
+                if (cand < old && sssp_dist(cand) < sssp_dist(old))
+                    push = atomicExch(&stamp[x], st) != st;
+            }
         }
         int64_t slot = wave_append(ncount, push);
         if (push) next[slot] = x;
@@ -204,7 +208,7 @@ static int sssp_push(dg_graph *g, uint64_t *key, int64_t nf, dg_batch_stats *st)
         DG_TRY(next_stamp(g, &stv));
         DG_TRY(counters_clear(g));
         RelaxOp op{key, ws.stamp.p, stv, N, ws.dcnt + C_F1};
-        DG_TRY(launch_expand(s, make_args(g, g->fwd, F, nf), op, 1024));
+        DG_TRY(launch_expand(s, make_args(g, g->fwd, F, nf), op, 8192));
         DG_TRY(counters_read(g));
         relaxed += nf;
         nf = ws.hcnt[C_F1];
@@ -218,15 +222,35 @@ static int sssp_push(dg_graph *g, uint64_t *key, int64_t nf, dg_batch_stats *st)
     return DG_OK;
 }
 
-int sssp_static_solve(dg_graph *g, uint64_t *key, int32_t source, dg_batch_stats *st) {
+__global__ void k_sssp_set_sources(const int32_t *src, int64_t ns, uint64_t *key) {
+    for (int64_t i = gtid(); i < ns; i += gstride()) key[src[i]] = sssp_pack(0, -1);
+}
+
+// Static solve from ns distinct sources (device array) -- one per member graph
+// of a batched set, or a single source.
+int sssp_static_multi(dg_graph *g, uint64_t *key, const int32_t *srcs, int64_t ns, dg_batch_stats *st) {
     hipStream_t s = g->stream;
     DG_TRY(ensure_frontiers(g));
-    hipLaunchKernelGGL(k_sssp_init, dim3(grid_for(g->n)), dim3(256), 0, s, g->n, key, source);
+    hipLaunchKernelGGL(k_sssp_init, dim3(grid_for(g->n)), dim3(256), 0, s, g->n, key, -1);
+    hipLaunchKernelGGL(k_sssp_set_sources, dim3(grid_for(ns)), dim3(256), 0, s, srcs, ns, key);
     DG_HIP(hipGetLastError());
-    int32_t src = source;
-    DG_HIP(hipMemcpyAsync(g->ws.f0.p, &src, 4, hipMemcpyHostToDevice, s));
-    DG_TRY(sssp_push(g, key, 1, st));
+    if (g->cfg.sssp_persistent == 1) {
+        DG_TRY(sssp_static_persistent(g, key, srcs, ns));
+        DG_HIP(hipStreamSynchronize(s));
+        return DG_OK;
+    }
+    if (srcs != g->ws.f0.p)
+        DG_HIP(hipMemcpyAsync(g->ws.f0.p, srcs, (size_t)ns * 4, hipMemcpyDeviceToDevice, s));
+    DG_TRY(sssp_push(g, key, ns, st));
     return DG_OK;
+}
+
+int sssp_static_solve(dg_graph *g, uint64_t *key, int32_t source, dg_batch_stats *st) {
+    DG_TRY(ensure_frontiers(g));
+    int32_t src = source;
+    DG_HIP(hipMemcpyAsync(g->ws.f0.p, &src, 4, hipMemcpyHostToDevice, g->stream));
+    DG_HIP(hipStreamSynchronize(g->stream));
+    return sssp_static_multi(g, key, g->ws.f0.p, 1, st);
 }
 
 int sssp_init(dg_query *q) {
@@ -234,6 +258,7 @@ int sssp_init(dg_query *q) {
     DG_TRY(q->key.ensure((size_t)g->n + 1));
     DG_TRY(q->inval.ensure((size_t)g->n + 1));
     q->nseeds = 0;
+    if (q->nsrc > 0) return sssp_static_multi(g, q->key.p, q->srcs.p, q->nsrc, nullptr);
     return sssp_static_solve(g, q->key.p, q->source, nullptr);
 }
 
@@ -256,13 +281,31 @@ int sssp_post_update(dg_query *q, int64_t adel, int64_t ains, dg_batch_stats *st
     hipStream_t s = g->stream;
     Work &ws = g->ws;
     DG_TRY(ensure_frontiers(g));
+    if (g->cfg.sssp_persistent == 1) {
+        // the same four steps on device work queues, without host round trips
+        DG_TRY(q->qcnt.ensure(4));
+        if (!q->hpin) DG_HIP(hipHostMalloc((void **)&q->hpin, 4 * sizeof(int64_t), hipHostMallocDefault));
+        q->hpin[0] = q->nseeds;
+        q->hpin[1] = ains;
+        DG_HIP(hipMemcpyAsync(q->qcnt.p, q->hpin, 2 * sizeof(int64_t), hipMemcpyHostToDevice, s));
+        int64_t ncut = 0;
+        if (q->gcache)
+            DG_TRY(sssp_post_graph(g, q->gcache, q->key.p, q->inval.p, q->qcnt.p, ws.f1.p, q->qcnt.p + 1, &ncut));
+        else
+            DG_TRY(sssp_post_persistent(g, q->key.p, q->inval.p, q->qcnt.p, ws.f1.p, q->qcnt.p + 1, &ncut));
+        if (st) {
+            st->sssp_invalidated += ncut;
+            st->sssp_steps += 1;
+        }
+        return DG_OK;
+    }
     // 1. cut the subtrees below the seeds; q->inval collects every cut vertex
     int64_t ncut = q->nseeds;
     int64_t lo = 0, hi = ncut;
     while (hi > lo) {
         DG_TRY(counters_clear(g));
         CutOp op{q->key.p, q->inval.p + hi, ws.dcnt + C_F1};
-        DG_TRY(launch_expand(s, make_args(g, g->fwd, q->inval.p + lo, hi - lo), op, 1024));
+        DG_TRY(launch_expand(s, make_args(g, g->fwd, q->inval.p + lo, hi - lo), op, 8192));
         DG_TRY(counters_read(g));
         lo = hi;
         hi += ws.hcnt[C_F1];
@@ -273,7 +316,7 @@ int sssp_post_update(dg_query *q, int64_t adel, int64_t ains, dg_batch_stats *st
     if (ncut > 0) {
         DG_TRY(counters_clear(g));
         PullOp op{q->key.p};
-        DG_TRY(launch_expand(s, make_args(g, *g->rev, q->inval.p, ncut), op, 1024));
+        DG_TRY(launch_expand(s, make_args(g, *g->rev, q->inval.p, ncut), op, 8192));
     }
     // 3. inserted arcs relax their heads; 2+3 seed the push frontier
     int32_t stv;

@@ -27,6 +27,7 @@ inline DirView view(const Dir &d) { return DirView{d.off.p, d.col.p, d.w.p, d.do
 struct ExpandArgs {
     const int32_t *F;   // frontier
     int64_t nf;
+    const int64_t *nfp = nullptr;  // when set, the frontier length is read from device memory
     DirView g;
     int64_t *hq;        // heavy chunk queue: (v << 32) | chunk
     int64_t *hcount;    // its length
@@ -44,12 +45,13 @@ __global__ __launch_bounds__(256) void k_expand(ExpandArgs a, Op op) {
     const int64_t wave_global = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / WAVE;
     const int l = lane_id();
-    for (int64_t wb = wave_global * WAVE; wb < a.nf; wb += nwaves * WAVE) {
+    const int64_t nf = a.nfp ? *a.nfp : a.nf;
+    for (int64_t wb = wave_global * WAVE; wb < nf; wb += nwaves * WAVE) {
         const int64_t fi = wb + l;
         int32_t v = -1, pay = 0;
         int64_t ob = 0, od = 0;
         int32_t db = 0, tot = 0;
-        if (fi < a.nf) {
+        if (fi < nf) {
             v = a.F[fi];
             if (op.vtx(v, pay)) {
                 ob = a.g.off[v];
@@ -142,8 +144,8 @@ __global__ __launch_bounds__(256) void k_expand_heavy(ExpandArgs a, Op op) {
 // hcount must point at a zeroed device counter.
 template <class Op>
 inline int launch_expand(hipStream_t s, const ExpandArgs &a, const Op &op, int heavy_groups) {
-    if (a.nf <= 0) return DG_OK;
-    int64_t blocks = (a.nf + 255) / 256;
+    if (!a.nfp && a.nf <= 0) return DG_OK;
+    int64_t blocks = a.nfp ? 4096 : (a.nf + 255) / 256;  // device-side count: fixed grid-stride grid
     if (blocks > 65535) blocks = 65535;
     hipLaunchKernelGGL(k_expand<Op>, dim3((unsigned)blocks), dim3(256), 0, s, a, op);
     hipLaunchKernelGGL(k_expand_heavy<Op>, dim3(heavy_groups), dim3(256), 0, s, a, op);

@@ -51,7 +51,8 @@ def test_bad_arguments_are_rejected_on_the_host():
 
 def test_struct_layouts_match_header(tmp_path):
     """The ctypes mirrors have the sizes and field offsets the C compiler gives."""
-    fields = {"dg_config": dg.Config, "dg_batch_stats": dg.BatchStats}
+    fields = {"dg_config": dg.Config, "dg_batch_stats": dg.BatchStats, "dg_kernel_prof": dg.KernelProf,
+              "dg_server_config": dg.ServerConfig, "dg_request": dg.Request, "dg_result": dg.Result}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "dg.h"', "int main(void) {"]
     for cname, cls in fields.items():
         lines.append(f'printf("%zu\\n", sizeof({cname}));')

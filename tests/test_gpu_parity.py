@@ -30,11 +30,12 @@ def say(*a):
     sys.stdout.flush()
 
 
-def cfg(merge=0.0, heavy=0, tol_scale=0.0):
+def cfg(merge=0.0, heavy=0, tol_scale=0.0, persistent=0):
     c = dg.Config()
     c.merge_threshold = merge
     c.heavy_degree = heavy
     c.pr_tol_scale = tol_scale
+    c.sssp_persistent = persistent
     return c
 
 
@@ -159,11 +160,11 @@ def test_build_rejects_bad_edge_lists():
 
 # ------------------------------------------------------------------ SSSP
 
-@pytest.mark.parametrize("heavy", [0, 8, 1 << 20])
-def test_sssp_c1_dynamic(heavy):
+@pytest.mark.parametrize("heavy,persistent", [(0, 0), (8, 0), (1 << 20, 0), (0, 1), (8, 1)])
+def test_sssp_c1_dynamic(heavy, persistent):
     n, s, d, w, (bs, bd, bw, bo) = graphgen.c1_workload()
-    say("sssp C1 heavy", heavy)
-    G = dg.Graph(n, s, d, w, config=cfg(heavy=heavy))
+    say("sssp C1 heavy", heavy, "persistent", persistent)
+    G = dg.Graph(n, s, d, w, config=cfg(heavy=heavy, persistent=persistent))
     q = G.sssp_attach(0)
     dist, par = q.read()
     assert np.array_equal(dist, oracle.sssp(n, s, d, w, 0))
@@ -178,10 +179,11 @@ def test_sssp_c1_dynamic(heavy):
     assert_tree(n, cs, cd, cw, 0, sd, sp)
 
 
-def test_sssp_many_batches_with_merges():
+@pytest.mark.parametrize("persistent", [0, 1])
+def test_sssp_many_batches_with_merges(persistent):
     n, s, d, w = rmat_small(12, 8, 33)
-    say("sssp sequence")
-    G = dg.Graph(n, s, d, w, config=cfg(merge=0.02))
+    say("sssp sequence persistent", persistent)
+    G = dg.Graph(n, s, d, w, config=cfg(merge=0.02, persistent=persistent))
     qs = [G.sssp_attach(0), G.sssp_attach(17)]
     cs, cd, cw = s, d, w
     merges = 0
@@ -206,7 +208,8 @@ def test_sssp_many_batches_with_merges():
     assert merges >= 2
 
 
-def test_sssp_grid_and_hub():
+@pytest.mark.parametrize("persistent", [0, 1])
+def test_sssp_grid_and_hub(persistent):
     """High-diameter grid (many frontier steps) plus a hub above the heavy limit."""
     n, s, d, w = graphgen.grid4(40, 40, 9, 1000)
     hub = 5
@@ -214,8 +217,8 @@ def test_sssp_grid_and_hub():
     s = np.concatenate([s, np.full(extra.size, hub)]).astype(np.int32)
     d = np.concatenate([d, extra]).astype(np.int32)
     w = np.concatenate([w, np.full(extra.size, 5000)]).astype(np.int32)
-    say("sssp grid+hub")
-    G = dg.Graph(n, s, d, w, config=cfg(heavy=64))
+    say("sssp grid+hub persistent", persistent)
+    G = dg.Graph(n, s, d, w, config=cfg(heavy=64, persistent=persistent))
     q = G.sssp_attach(0)
     cs, cd, cw = s, d, w
     for i in range(6):
@@ -268,11 +271,13 @@ def pr_check(got, n, s, d):
     assert err <= PR_MAXABS
 
 
-@pytest.mark.parametrize("heavy", [0, 8])
-def test_pagerank_c1_dynamic(heavy):
+@pytest.mark.parametrize("heavy,mode", [(0, 0), (8, 0), (0, 1), (0, 2), (8, 1)])
+def test_pagerank_c1_dynamic(heavy, mode):
     n, s, d, w, (bs, bd, bw, bo) = graphgen.c1_workload()
-    say("pagerank C1 heavy", heavy)
-    G = dg.Graph(n, s, d, w, config=cfg(heavy=heavy))
+    say("pagerank C1 heavy", heavy, "mode", mode)
+    c = cfg(heavy=heavy)
+    c.pr_mode = mode
+    G = dg.Graph(n, s, d, w, config=c)
     q = G.pr_attach(0.85, PR_TOL, 1000)
     r, it, conv = q.read()
     pr_check(r, n, s, d)
