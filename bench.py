@@ -1,27 +1,40 @@
 #!/usr/bin/env python3
 """Dynamic-graph update throughput on one MI355X.
 
-Workload (one step): a batch of updates (default 100,000: half deletions of
-existing arcs, half insertions of new uniform arcs, weights U[1,100]) applied to
-a directed R-MAT scale-22 graph (4,194,304 vertices, 67,108,864 arcs, a=0.57
-b=0.19 c=0.19, weights U[1,100]) that keeps a shortest-path query from vertex 0
-and a PageRank query (damping 0.85, L1 tolerance 1e-9, FP64) current.  Every
-step gets its own batch (all drawn against the initial graph); the batches are
-resident in HBM before the timed region.  value = updates applied per second of
-wall time over the timed steps.
+Default workload (one step): a batch of updates (default 100,000: half
+deletions of existing arcs, half insertions of new uniform arcs, weights
+U[1,100]) applied to a directed R-MAT scale-22 graph (4,194,304 vertices,
+67,108,864 arcs, a=0.57 b=0.19 c=0.19, weights U[1,100]) that keeps a
+shortest-path query from vertex 0 and a PageRank query (damping 0.85, L1
+tolerance 1e-9, FP64) current.  Every step gets its own batch (all drawn against
+the initial graph); the batches are resident in HBM before the timed region.
+value = updates applied per second of wall time over the timed steps.
 
 Also reported: the static-recompute GPU path on the same graph (batch apply
-plus SSSP and PageRank from scratch), the roofline of the dominant kernel (the
-PageRank pull) from HIP-event launch timing inside this run, and the CPU oracle
-(edge-list apply + Dijkstra + FP64 power iteration) timed on the host for one
-batch.  One GPU only.
+plus SSSP and PageRank from scratch), the roofline of the dominant kernel from
+HIP-event launch timing inside this run, and the CPU oracle (edge-list apply +
+Dijkstra + FP64 power iteration) timed on the host for one batch.
+
+Other workloads (--workload), each printing one line of the same form:
+  grid     4096 x 4096 4-neighbour grid (weights U[1,1000]) with SSSP + PageRank;
+  tc       undirected R-MAT scale 20 (16,777,216 edges) with an exact triangle
+           count, batches of --pct of |E|;
+  batched  4,096 directed R-MAT graphs (scale U{10..14}, 16 arcs per vertex),
+           each with its own batch of U[1%,10%] of its arcs, dynamic SSSP from 0
+           of every member in one set update (autotuned);
+  serve    64 resident R-MAT graphs (scale U{12..20}), open-loop Poisson request
+           arrivals; each request is a batch of log-uniform[100, 1e5] updates
+           plus one query (SSSP 40 %, PageRank 40 %, triangles 20 %).
+One GPU only.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
+import threading
 import time
 
 import numpy as np
@@ -32,10 +45,590 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "dyn SSSP/PR/TC updates/sec + HBM GB/s vs static recompute; serve p50/p99"
+CSRC = os.path.join(ROOT, "paper_2507_11094_amd", "csrc")
+
+# HBM bytes per launch read from rocprofv3 FETCH_SIZE / WRITE_SIZE (KiB per
+# dispatch) for the named kernel and workload, divided by what the same counters
+# read per byte of a plain device copy (FETCH 2.0, WRITE 1.0).  Each entry holds
+# the SHA-1 of the kernel's source file at the time the counters were taken; a
+# changed source makes the figure stale and it is reported as null.
+MEASURED_TRAFFIC: dict = {}
+
+# Serving objective stated up front: 99th percentile latency (submit -> result
+# on the host) at the default arrival rate.
+SERVE_SLO_P99_MS = 250.0
 
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def source_sha1(fname: str) -> str:
+    with open(os.path.join(CSRC, fname), "rb") as f:
+        return hashlib.sha1(f.read()).hexdigest()
+
+
+def traffic_for(kernel: str, workload: str):
+    e = MEASURED_TRAFFIC.get((kernel, workload))
+    if not e or source_sha1(e["source"]) != e["sha1"]:
+        return None
+    return round(e["fetch_kib"] * 1024 / e["fetch_factor"] + e["write_kib"] * 1024 / e["write_factor"])
+
+
+KERNEL_SOURCE = {"pr_pull": ("k_pr_pull", "pagerank.hip"), "pr_apply": ("k_pr_apply", "pagerank.hip"),
+                 "merge_base": ("k_merge_base", "graph.hip"),
+                 "sssp_worklist": ("k_wl_cut + pull + k_wl_push", "worklist.hip"),
+                 "tc_delta": ("k_tc_delta", "tc.hip")}
+
+
+def roofline_of(prof: dict, workload: str, prefer: str | None = None) -> dict | None:
+    """Roofline of the dominant profiled kernel (largest total time), or `prefer`."""
+    if not prof:
+        return None
+    name = prefer if prefer in prof else max(prof, key=lambda x: prof[x]["ms"])
+    p = prof[name]
+    launches = max(p["launches"], 1)
+    achieved = p["bytes"] / (p["ms"] * 1e-3) / 1e9 if p["ms"] > 0 else 0.0
+    kname = KERNEL_SOURCE.get(name, (name, None))[0]
+    return {
+        "kernel": kname,
+        "bound": "hbm",
+        "achieved": round(achieved, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": traffic_for(kname, workload),
+        "launches": p["launches"],
+        "avg_launch_us": round(1e3 * p["ms"] / launches, 2),
+        "alg_bytes_per_launch": round(p["bytes"] / launches),
+    }
+
+
+def kernel_table(prof: dict) -> dict:
+    return {name: {"launches": v["launches"], "avg_us": round(1e3 * v["ms"] / max(v["launches"], 1), 2),
+                   "total_ms": round(v["ms"], 3),
+                   "GB/s": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1) if v["ms"] > 0 and v["bytes"] > 0 else None}
+            for name, v in prof.items()}
+
+
+def line(args, value, unit, ms_per_step, dtype, config, roofline, cpu, higher=True, **extra) -> dict:
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": unit,
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": higher,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype,
+        "data": "synthetic",
+        "config": config,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    out.update(extra)
+    return out
+
+
+class EdgeIndex:
+    """Sorted (u << 32 | v) keys of a directed edge list with the position of each
+    key's edge, to look up the weights of arcs a batch deletes."""
+
+    def __init__(self, src, dst, w):
+        k = (src.astype(np.int64) << 32) | dst.astype(np.int64)
+        self.order = np.argsort(k, kind="stable")
+        self.keys = k[self.order]
+        self.w = w
+
+    def weights(self, a, b):
+        q = (a.astype(np.int64) << 32) | b.astype(np.int64)
+        pos = np.searchsorted(self.keys, q)
+        assert np.all(self.keys[np.minimum(pos, self.keys.size - 1)] == q), "arc not in the graph"
+        return self.w[self.order[pos]]
+
+
+def inverse(batch, index: EdgeIndex):
+    """The batch that undoes `batch` on the directed graph it was drawn against:
+    its deleted arcs re-inserted with their weights, its inserted arcs deleted."""
+    bs, bd, bw, bo = batch
+    dels = bo == 0
+    w = np.zeros(bs.size, np.int32)
+    w[dels] = index.weights(bs[dels], bd[dels])
+    return bs.copy(), bd.copy(), w, dels.astype(np.uint8)
+
+
+# ----------------------------------------------------------------------------- one graph
+
+def run_single(args, kind: str) -> int:
+    import torch
+
+    import graphgen
+    import paper_2507_11094_amd as dg
+
+    dev = torch.device("cuda:0")
+    K, W = args.steps, args.warmup
+    t = time.perf_counter()
+    undirected = kind == "tc"
+    if kind == "rmat":
+        n, s, d, w = graphgen.c2r_graph(args.scale)
+        k, wmax = args.batch, 100
+        wl = f"rmat{args.scale}-dynamic-sssp+pagerank"
+    elif kind == "grid":
+        n, s, d, w = graphgen.c2g_graph(args.side)
+        k, wmax = args.batch, 1000
+        wl = f"grid{args.side}x{args.side}-dynamic-sssp+pagerank"
+    else:
+        n, s, d = graphgen.c3_graph(args.tc_scale)
+        w = None
+        k, wmax = int(args.pct * s.size), 100
+        wl = f"rmat{args.tc_scale}-undirected-dynamic-tc"
+    log(f"{wl}: n={n} m={s.size} generated in {time.perf_counter() - t:.1f}s")
+    keys = graphgen.edge_keys(s, d, undirected)
+    t = time.perf_counter()
+    batches = [graphgen.update_batch(n, s, d, k, graphgen.config_seed(1 if kind != "tc" else 2, 100 + i),
+                                     wmax=wmax, undirected=undirected, existing=keys) for i in range(W + K)]
+    log(f"{W + K} batches of {k} drawn in {time.perf_counter() - t:.1f}s")
+    dbatches = [tuple(torch.from_numpy(np.ascontiguousarray(x)).to(dev) for x in b) for b in batches]
+    torch.cuda.synchronize()
+
+    persistent = args.sssp_persistent if args.sssp_persistent >= 0 else (1 if kind == "grid" else 0)
+    cfg = dg.Config()
+    cfg.heavy_degree = args.heavy_degree
+    cfg.sssp_persistent = persistent
+    cfg.pr_mode = args.pr_mode
+    t = time.perf_counter()
+    G = dg.Graph(n, s, d, w, undirected=undirected, config=cfg)
+    log(f"graph built on device in {time.perf_counter() - t:.2f}s")
+    t = time.perf_counter()
+    if kind == "tc":
+        qt = G.tc_attach()
+        tc0 = qt.read()
+    else:
+        G.sssp_attach(0)
+        G.pr_attach(0.85, 1e-9, 1000)
+    log(f"queries attached (static solves) in {time.perf_counter() - t:.2f}s")
+
+    for i in range(W):
+        G.apply(*dbatches[i])
+        log(f"warmup {i + 1}/{W}")
+    dg.dg_profile_enable(True)
+    dg.dg_profile_reset()
+    stats = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(K):
+        st = G.apply(*dbatches[W + i])
+        stats.append(st.as_dict())
+        log(f"step {i + 1}/{K}: {st.t_total_ms:.2f} ms (sssp {st.t_sssp_ms:.2f}, pr {st.t_pr_ms:.2f}, "
+            f"tc {st.t_tc_ms:.2f}, update {st.t_update_ms + st.t_validate_ms:.2f}, merge {st.t_merge_ms:.2f}, "
+            f"pr_iters {st.pr_iterations}, |A| {st.pr_affected})")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = dg.dg_profile_read()
+    dg.dg_profile_enable(False)
+    value = K * k / elapsed
+
+    def avg(key):
+        return float(np.mean([x[key] for x in stats]))
+
+    static = None
+    if not args.no_static:
+        t_apply = 1e-3 * (avg("t_validate_ms") + avg("t_update_ms") + avg("t_merge_ms"))
+        torch.cuda.synchronize()
+        if kind == "tc":
+            t = time.perf_counter()
+            G.tc_static()
+            t_s = time.perf_counter() - t
+            static = {"tc_ms": round(1e3 * t_s, 3), "apply_ms": round(1e3 * t_apply, 3)}
+        else:
+            t = time.perf_counter()
+            G.sssp_static(0)
+            t_ss = time.perf_counter() - t
+            t = time.perf_counter()
+            _, it_pr = G.pr_static(0.85, 1e-9, 1000)
+            t_ps = time.perf_counter() - t
+            t_s = t_ss + t_ps
+            static = {"sssp_ms": round(1e3 * t_ss, 3), "pr_ms": round(1e3 * t_ps, 3), "pr_iterations": it_pr,
+                      "apply_ms": round(1e3 * t_apply, 3)}
+        static["updates_per_s"] = round(k / (t_apply + t_s), 1)
+        static["dynamic_speedup"] = round((t_apply + t_s) / (elapsed / K), 3)
+        log(f"static recompute: {static}")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_single(args, kind, n, s, d, w, batches[W], k)
+
+    config = {"workload": wl, "vertices": n, "arcs": int(s.size) * (2 if undirected else 1),
+              "batch": k, "insert_fraction": 0.5, "parallelism": "1 gpu",
+              "heavy_degree": args.heavy_degree or 512, "sssp_persistent": persistent, "pr_mode": args.pr_mode}
+    if kind == "tc":
+        config.update({"undirected_edges": int(s.size), "batch_fraction": args.pct, "queries": ["triangles"]})
+    else:
+        config["queries"] = ["sssp(0)", "pagerank(0.85, l1 1e-9)"]
+    extra = {
+        "static_recompute": static,
+        "phases_ms": {key: round(avg(key), 3) for key in
+                      ("t_validate_ms", "t_update_ms", "t_merge_ms", "t_sssp_ms", "t_pr_ms", "t_tc_ms",
+                       "t_total_ms")},
+        "per_batch": {"pr_iterations": avg("pr_iterations"), "pr_affected": avg("pr_affected"),
+                      "sssp_invalidated": avg("sssp_invalidated"), "sssp_steps": avg("sssp_steps"),
+                      "deleted": avg("deleted"), "inserted": avg("inserted"),
+                      "tc_removed": avg("tc_removed"), "tc_added": avg("tc_added"),
+                      "merged": sum(x["merged"] for x in stats)},
+        "gteps": round(sum(x["edges_traversed"] for x in stats) / elapsed / 1e9, 3),
+        "kernels": kernel_table(prof),
+    }
+    if kind == "tc":
+        extra["triangles"] = {"initial": int(tc0), "final": int(qt.read())}
+    out = line(args, value, "updates/s", 1e3 * elapsed / K, "u64" if kind == "tc" else "i32+f64", config,
+               roofline_of(prof, wl, "pr_pull" if kind != "tc" else None), cpu, **extra)
+    print(json.dumps(out), flush=True)
+    G.close()
+    return 0
+
+
+def cpu_single(args, kind, n, s, d, w, batch, k):
+    import oracle
+
+    if kind == "tc":
+        # a full recount at scale 20 takes minutes on one core (about 2.6x per
+        # scale step), so the sample is the same recipe at scale <= 17
+        import graphgen
+
+        sc = min(args.tc_scale, 17)
+        if sc != args.tc_scale:
+            n, s, d = graphgen.c3_graph(sc)
+            k = int(args.pct * s.size)
+            batch = graphgen.update_batch(n, s, d, k, graphgen.config_seed(2, 100), undirected=True)
+        t = time.perf_counter()
+        s2, d2, _, _ = oracle.apply(n, s, d, None, *batch, undirected=True)
+        oracle.triangles(n, s2, d2)
+        t_cpu = time.perf_counter() - t
+        sample = (f"one {k}-update batch ({args.pct:g} of |E|) on the undirected R-MAT recipe at scale {sc}: "
+                  f"edge-list apply and a full triangle recount (single thread)")
+    else:
+        t = time.perf_counter()
+        s2, d2, w2, _ = oracle.apply(n, s, d, w, *batch)
+        oracle.sssp(n, s2, d2, w2, 0)
+        oracle.pagerank(n, s2, d2, 0.85, 1e-9, 1000)
+        t_cpu = time.perf_counter() - t
+        sample = (f"one {k}-update batch on the full graph: edge-list apply, Dijkstra from 0, FP64 power "
+                  f"iteration to L1 1e-9 (single thread)")
+    log(f"cpu oracle: {t_cpu:.1f}s")
+    return {"value": round(k / t_cpu, 1), "unit": "updates/s", "cores": 1, "kind": "oracle",
+            "seconds": round(t_cpu, 2), "sample": sample}
+
+
+# ----------------------------------------------------------------------------- batched set
+
+def set_members(count: int, seed: int):
+    """Member graphs of the batched workload: scale U{10..14}, 16 arcs per vertex,
+    batch sizes U[1 %, 10 %] of each member's arcs."""
+    import graphgen
+
+    scales = graphgen.uniform_int(graphgen.stream_seed(seed, "scale"), 0, count, 10, 14)
+    frac = 0.01 + 0.09 * graphgen.uniform01(graphgen.stream_seed(seed, "frac"), 0, count)
+    members, ks = [], []
+    for i in range(count):
+        sc = int(scales[i])
+        members.append(graphgen.rmat_directed(sc, 16 << sc, graphgen.config_seed(3, i)))
+        ks.append(int(frac[i] * (16 << sc)))
+    return members, ks
+
+
+def run_batched(args) -> int:
+    import torch
+
+    import graphgen
+    import paper_2507_11094_amd as dg
+
+    dev = torch.device("cuda:0")
+    K, W = args.steps, args.warmup
+    count = args.graphs or 4096
+    t = time.perf_counter()
+    members, ks = set_members(count, graphgen.config_seed(3, 0))
+    log(f"{count} members generated in {time.perf_counter() - t:.1f}s")
+    t = time.perf_counter()
+    fwd, bwd = [], []
+    for i, ((n, s, d, w), k) in enumerate(zip(members, ks)):
+        idx = EdgeIndex(s, d, w)
+        fwd.append(graphgen.update_batch(n, s, d, k, graphgen.config_seed(3, 100000 + i), existing=idx.keys))
+        bwd.append(inverse(fwd[-1], idx))
+    log(f"batches drawn in {time.perf_counter() - t:.1f}s (forward + inverse)")
+    total_k = int(sum(ks))
+
+    def concat(bs):
+        kk = np.array([b[0].size for b in bs], np.int64)
+        cols = [torch.from_numpy(np.ascontiguousarray(np.concatenate([b[j] for b in bs]))).to(dev)
+                for j in range(4)]
+        return kk, cols
+
+    dfwd, dbwd = concat(fwd), concat(bwd)
+    torch.cuda.synchronize()
+    cfg = dg.Config()
+    cfg.heavy_degree = args.heavy_degree
+    t = time.perf_counter()
+    S = dg.GraphSet(members, config=cfg)
+    info = S.info()
+    log(f"set built: {info} in {time.perf_counter() - t:.1f}s")
+    t = time.perf_counter()
+    S.sssp_attach(np.zeros(count, np.int32))
+    log(f"sssp attached (static multi-source solve) in {time.perf_counter() - t:.2f}s")
+    tune = None
+    if not args.no_autotune:
+        t = time.perf_counter()
+        best, best_ms = S.autotune(fwd)
+        tune = {"heavy_degree": best.heavy_degree, "persistent_groups": best.persistent_groups,
+                "best_ms": round(best_ms, 3), "seconds": round(time.perf_counter() - t, 1)}
+        log(f"autotune: {tune}")
+    # steps alternate the forward batches and their inverses: every step is a
+    # genuine 50/50 batch against the graph it meets
+    for i in range(W):
+        kk, cols = dfwd if i % 2 == 0 else dbwd
+        S.apply_device(kk, *cols)
+    dg.dg_profile_enable(True)
+    dg.dg_profile_reset()
+    stats = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(K):
+        kk, cols = dfwd if (W + i) % 2 == 0 else dbwd
+        st = S.apply_device(kk, *cols)
+        stats.append(st.as_dict())
+        log(f"step {i + 1}/{K}: {st.t_total_ms:.2f} ms (sssp {st.t_sssp_ms:.2f}, update "
+            f"{st.t_update_ms + st.t_validate_ms:.2f}, merge {st.t_merge_ms:.2f}, cut {st.sssp_invalidated})")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = dg.dg_profile_read()
+    dg.dg_profile_enable(False)
+    gstats = S.graph_stats()
+
+    static = None
+    if not args.no_static:
+        # static comparator: the same batch applied, then every member's SSSP from scratch
+        kk, cols = dfwd if (W + K) % 2 == 0 else dbwd
+        cfg2 = dg.Config()
+        S2 = dg.GraphSet(members, config=cfg2)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        st = S2.apply_device(kk, *cols)
+        S2.sssp_attach(np.zeros(count, np.int32))
+        torch.cuda.synchronize()
+        t_s = time.perf_counter() - t
+        static = {"ms": round(1e3 * t_s, 3), "updates_per_s": round(total_k / t_s, 1),
+                  "dynamic_speedup": round(t_s / (elapsed / K), 3)}
+        S2.close()
+        log(f"static recompute: {static}")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+
+        sample = min(count, 256)
+        t = time.perf_counter()
+        upd = 0
+        for i in range(sample):
+            n, s, d, w = members[i]
+            s2, d2, w2, _ = oracle.apply(n, s, d, w, *fwd[i])
+            oracle.sssp(n, s2, d2, w2, 0)
+            upd += ks[i]
+        t_cpu = time.perf_counter() - t
+        cpu = {"value": round(upd / t_cpu, 1), "unit": "updates/s", "cores": 1, "kind": "oracle",
+               "seconds": round(t_cpu, 2),
+               "sample": f"the first {sample} members of the set: edge-list apply of each member's batch and "
+                         f"Dijkstra from 0 (single thread)"}
+        log(f"cpu oracle: {cpu}")
+
+    def avg(key):
+        return float(np.mean([x[key] for x in stats]))
+
+    config = {"workload": f"batched{count}-rmat10to14-dynamic-sssp", "graphs": count,
+              "vertices": info["vertices"], "arcs": info["arcs"], "updates_per_step": total_k,
+              "batch_fraction": "U[0.01,0.10] per member", "insert_fraction": 0.5, "queries": ["sssp(0) per member"],
+              "parallelism": "1 gpu", "autotune": tune}
+    out = line(args, K * total_k / elapsed, "updates/s", 1e3 * elapsed / K, "i32", config,
+               roofline_of(prof, config["workload"], "sssp_worklist"), cpu,
+               static_recompute=static,
+               phases_ms={key: round(avg(key), 3) for key in
+                          ("t_validate_ms", "t_update_ms", "t_merge_ms", "t_sssp_ms", "t_total_ms")},
+               per_step={"sssp_invalidated": avg("sssp_invalidated"), "deleted": avg("deleted"),
+                         "inserted": avg("inserted"), "merged": sum(x["merged"] for x in stats)},
+               gteps=round(sum(x["edges_traversed"] for x in stats) / elapsed / 1e9, 3),
+               graph_launches=gstats, kernels=kernel_table(prof))
+    print(json.dumps(out), flush=True)
+    S.close()
+    return 0
+
+
+# ----------------------------------------------------------------------------- serving
+
+def serve_graphs(count: int, seed: int):
+    import graphgen
+
+    scales = graphgen.uniform_int(graphgen.stream_seed(seed, "scale"), 0, count, 12, 20)
+    return [graphgen.rmat_directed(int(sc), 16 << int(sc), graphgen.config_seed(4, i))
+            for i, sc in enumerate(scales)]
+
+
+def serve_requests(graphs, seed: int, rate: float, duration: float):
+    """Open-loop request stream: Poisson arrivals, graph uniform, batch size
+    log-uniform in [100, 1e5], query kinds 40/40/20, source uniform.  For each
+    graph its requests alternate a fresh batch and that batch's inverse, so every
+    batch is drawn against the graph it will meet."""
+    import graphgen
+
+    count = int(rate * duration * 1.5) + 16
+    gaps = -np.log(1.0 - graphgen.uniform01(graphgen.stream_seed(seed, "gap"), 0, count)) / rate
+    at = np.cumsum(gaps)
+    count = int(np.searchsorted(at, duration))
+    gi = graphgen.uniform_int(graphgen.stream_seed(seed, "graph"), 0, count, 0, len(graphs) - 1)
+    ku = graphgen.uniform01(graphgen.stream_seed(seed, "k"), 0, count)
+    qu = graphgen.uniform01(graphgen.stream_seed(seed, "kind"), 0, count)
+    su = graphgen.uniform01(graphgen.stream_seed(seed, "source"), 0, count)
+    index = {}
+    pending_inverse = {}
+    reqs = []
+    for i in range(count):
+        g = int(gi[i])
+        n, s, d, w = graphs[g]
+        if g in pending_inverse:
+            b = pending_inverse.pop(g)
+        else:
+            k = int(round(np.exp(np.log(100) + ku[i] * (np.log(1e5) - np.log(100)))))
+            k = min(k, s.size)  # never more deletions than half the graph's arcs
+            if g not in index:
+                index[g] = EdgeIndex(s, d, w)
+            b = graphgen.update_batch(n, s, d, k, graphgen.config_seed(4, 10000 + i), existing=index[g].keys)
+            pending_inverse[g] = inverse(b, index[g])
+        kind = 0 if qu[i] < 0.4 else (1 if qu[i] < 0.8 else 2)
+        reqs.append((float(at[i]), g, kind, int(su[i] * n), b))
+    return reqs
+
+
+def run_serve(args) -> int:
+    import torch
+
+    import graphgen
+    import paper_2507_11094_amd as dg
+
+    count = args.graphs or 64
+    seed = graphgen.config_seed(4, 0)
+    t = time.perf_counter()
+    graphs = serve_graphs(count, seed)
+    log(f"{count} graphs generated in {time.perf_counter() - t:.1f}s "
+        f"({sum(g[0] for g in graphs)} vertices, {sum(g[1].size for g in graphs)} arcs)")
+    t = time.perf_counter()
+    reqs = serve_requests(graphs, seed, args.rate, args.duration)
+    log(f"{len(reqs)} requests drawn in {time.perf_counter() - t:.1f}s")
+    S = dg.Server(workers=args.workers, budget_bytes=args.budget_gib << 30)
+    t = time.perf_counter()
+    for n, s, d, w in graphs:
+        S.add_graph(n, s, d, w)
+    torch.cuda.synchronize()
+    log(f"graphs resident in {time.perf_counter() - t:.1f}s")
+    S.start()
+    # warmup: one request per kind on graph 0 (and its inverse), untimed
+    n0, s0, d0, w0 = graphs[0]
+    idx0 = EdgeIndex(s0, d0, w0)
+    wb = graphgen.update_batch(n0, s0, d0, 1000, graphgen.config_seed(4, 999), existing=idx0.keys)
+    wi = inverse(wb, idx0)
+    for kind, b in ((0, wb), (1, wi), (2, wb), (1, wi)):
+        S.wait(S.submit(0, kind, *b, source=0))
+
+    tickets = []
+    lock = threading.Lock()
+    results = []
+    done = threading.Event()
+
+    def collector():
+        i = 0
+        while True:
+            with lock:
+                if i >= len(tickets):
+                    if done.is_set():
+                        return
+                    tk = None
+                else:
+                    tk = tickets[i]
+            if tk is None:
+                time.sleep(0.0005)
+                continue
+            res, _ = S.wait(tk[0])
+            results.append((tk[1], res.status, res.t_submit, res.t_start, res.t_end, tk[2]))
+            i += 1
+
+    th = threading.Thread(target=collector)
+    th.start()
+    t0 = time.perf_counter()
+    for at, g, kind, source, b in reqs:
+        now = time.perf_counter() - t0
+        if at > now:
+            time.sleep(at - now)
+        tk = S.submit(g, kind, *b, source=source)
+        with lock:
+            tickets.append((tk, kind, b[0].size))
+    done.set()
+    th.join()
+    elapsed = time.perf_counter() - t0
+    S.close()
+    bad = [r for r in results if r[1] != 0]
+    lat = np.array([1e3 * (r[4] - r[2]) for r in results])
+    qwait = np.array([1e3 * (r[3] - r[2]) for r in results])
+    upd = int(sum(r[5] for r in results))
+    by_kind = {}
+    for kname, kv in (("sssp", 0), ("pagerank", 1), ("triangles", 2)):
+        l = np.array([1e3 * (r[4] - r[2]) for r in results if r[0] == kv])
+        if l.size:
+            by_kind[kname] = {"count": int(l.size), "p50_ms": round(float(np.percentile(l, 50)), 3),
+                              "p99_ms": round(float(np.percentile(l, 99)), 3)}
+    p50, p99 = float(np.percentile(lat, 50)), float(np.percentile(lat, 99))
+    log(f"served {len(results)} requests in {elapsed:.1f}s: p50 {p50:.1f} ms p99 {p99:.1f} ms, errors {len(bad)}")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+
+        t = time.perf_counter()
+        upd_c, done_c = 0, 0
+        for at, g, kind, source, b in reqs:
+            n, s, d, w = graphs[g]
+            s2, d2, w2, _ = oracle.apply(n, s, d, w, *b)
+            if kind == 0:
+                oracle.sssp(n, s2, d2, w2, source)
+            elif kind == 1:
+                oracle.pagerank(n, s2, d2, 0.85, 1e-9, 1000)
+            else:
+                u, v = oracle.symmetrise(s2, d2)
+                oracle.triangles(n, u, v)
+            upd_c += b[0].size
+            done_c += 1
+            if time.perf_counter() - t > 20.0:
+                break
+        t_cpu = time.perf_counter() - t
+        cpu = {"value": round(upd_c / t_cpu, 1), "unit": "updates/s", "cores": 1, "kind": "oracle",
+               "seconds": round(t_cpu, 2),
+               "sample": f"the first {done_c} requests of the stream, each: edge-list apply against the "
+                         f"graph's initial state and a full recompute of its query (single thread)"}
+        log(f"cpu oracle: {cpu}")
+
+    config = {"workload": f"serve{count}-rmat12to20-poisson", "graphs": count,
+              "vertices": int(sum(g[0] for g in graphs)), "arcs": int(sum(g[1].size for g in graphs)),
+              "rate_per_s": args.rate, "duration_s": args.duration, "requests": len(results),
+              "batch": "log-uniform[100, 1e5]", "insert_fraction": 0.5,
+              "query_mix": {"sssp": 0.4, "pagerank": 0.4, "triangles": 0.2}, "workers": args.workers,
+              "budget_gib": args.budget_gib, "parallelism": "1 gpu"}
+    out = line(args, upd / elapsed, "updates/s", 1e3 * elapsed / max(len(results), 1), "i32+f64+u64", config,
+               None, cpu, serve={"p50_ms": round(p50, 3), "p99_ms": round(p99, 3),
+                                 "p99_queue_ms": round(float(np.percentile(qwait, 99)), 3),
+                                 "slo_p99_ms": SERVE_SLO_P99_MS, "slo_met": bool(p99 <= SERVE_SLO_P99_MS),
+                                 "errors": len(bad), "by_kind": by_kind})
+    out["steps"] = len(results)
+    out["warmup"] = 4
+    print(json.dumps(out), flush=True)
+    return 0
 
 
 def main() -> int:
@@ -43,12 +636,23 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=8)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--scale", type=int, default=22)
-    ap.add_argument("--batch", type=int, default=100_000)
+    ap.add_argument("--workload", default="rmat", choices=["rmat", "grid", "tc", "batched", "serve"])
+    ap.add_argument("--scale", type=int, default=22, help="rmat: R-MAT scale")
+    ap.add_argument("--side", type=int, default=4096, help="grid: side length")
+    ap.add_argument("--tc-scale", type=int, default=20, help="tc: R-MAT scale")
+    ap.add_argument("--batch", type=int, default=100_000, help="rmat/grid: updates per batch")
+    ap.add_argument("--pct", type=float, default=0.01, help="tc: batch size as a fraction of |E|")
+    ap.add_argument("--graphs", type=int, default=0, help="batched/serve: member graphs (0: 4096 / 64)")
+    ap.add_argument("--rate", type=float, default=20.0, help="serve: Poisson arrival rate (requests/s)")
+    ap.add_argument("--duration", type=float, default=15.0, help="serve: seconds of arrivals")
+    ap.add_argument("--workers", type=int, default=4, help="serve: worker streams")
+    ap.add_argument("--budget-gib", type=int, default=64, help="serve: device-memory admission budget")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-static", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--heavy-degree", type=int, default=0, help="rows longer than this are split (0: library default)")
-    ap.add_argument("--sssp-persistent", type=int, default=0, help="1: SSSP on the single-launch work queue")
+    ap.add_argument("--sssp-persistent", type=int, default=-1,
+                    help="1: SSSP on the single-launch work queue, 0: frontier steps (-1: grid 1, else 0)")
     ap.add_argument("--pr-mode", type=int, default=0, help="PageRank form after a batch: 0 auto, 1 local, 2 global")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run five plain 256 MiB device-to-device copies (reference for the "
@@ -70,148 +674,11 @@ def main() -> int:
               "MI355X, so --gpus must be 1 (multi-GPU sharding is a design note, not a measured path).",
               file=sys.stderr)
         return 2
-
-    import torch
-
-    import graphgen
-    import paper_2507_11094_amd as dg
-
-    dev = torch.device("cuda:0")
-    K, W, k = args.steps, args.warmup, args.batch
-    t = time.perf_counter()
-    n, s, d, w = graphgen.rmat_directed(args.scale, 16 << args.scale, graphgen.config_seed(1, 0))
-    log(f"graph n={n} m={s.size} generated in {time.perf_counter() - t:.1f}s")
-    keys = graphgen.edge_keys(s, d)
-    batches = []
-    for i in range(W + K):
-        batches.append(graphgen.update_batch(n, s, d, k, graphgen.config_seed(1, 100 + i), existing=keys))
-    log(f"{W + K} batches of {k} drawn")
-    dbatches = [tuple(torch.from_numpy(np.ascontiguousarray(x)).to(dev) for x in b) for b in batches]
-    torch.cuda.synchronize()
-
-    t = time.perf_counter()
-    cfg = dg.Config()
-    cfg.heavy_degree = args.heavy_degree
-    cfg.sssp_persistent = args.sssp_persistent
-    cfg.pr_mode = args.pr_mode
-    G = dg.Graph(n, s, d, w, config=cfg)
-    log(f"graph built on device in {time.perf_counter() - t:.2f}s")
-    t = time.perf_counter()
-    qs = G.sssp_attach(0)
-    qp = G.pr_attach(0.85, 1e-9, 1000)
-    log(f"queries attached (static solves) in {time.perf_counter() - t:.2f}s")
-
-    for i in range(W):
-        G.apply(*dbatches[i])
-        log(f"warmup {i + 1}/{W}")
-    dg.dg_profile_enable(True)
-    dg.dg_profile_reset()
-    stats = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(K):
-        st = G.apply(*dbatches[W + i])
-        stats.append(st.as_dict())
-        log(f"step {i + 1}/{K}: {st.t_total_ms:.2f} ms (sssp {st.t_sssp_ms:.2f}, pr {st.t_pr_ms:.2f}, "
-            f"update {st.t_update_ms + st.t_validate_ms:.2f}, merge {st.t_merge_ms:.2f}, "
-            f"pr_iters {st.pr_iterations}, |A| {st.pr_affected})")
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    prof = dg.dg_profile_read()
-    dg.dg_profile_enable(False)
-    elapsed = t1 - t0
-    value = K * k / elapsed
-    ms_per_step = 1e3 * elapsed / K
-
-    def avg(key):
-        return float(np.mean([x[key] for x in stats]))
-
-    pull = prof.get("pr_pull", {"launches": 0, "ms": 0.0, "bytes": 0.0})
-    achieved = pull["bytes"] / (pull["ms"] * 1e-3) / 1e9 if pull["ms"] > 0 else 0.0
-    roofline = {
-        "kernel": "k_pr_pull",
-        "bound": "hbm",
-        "achieved": round(achieved, 1),
-        "peak": HBM_PEAK_GBS,
-        "unit": "GB/s",
-        "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "traffic": None,
-        "launches": pull["launches"],
-        "avg_launch_us": round(1e3 * pull["ms"] / max(pull["launches"], 1), 2),
-        "alg_bytes_per_launch": round(pull["bytes"] / max(pull["launches"], 1)),
-    }
-    kernels = {name: {"launches": v["launches"], "avg_us": round(1e3 * v["ms"] / max(v["launches"], 1), 2),
-                      "GB/s": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1) if v["ms"] > 0 else None}
-               for name, v in prof.items()}
-
-    static = None
-    if not args.no_static:
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        G.sssp_static(0)
-        t_ss = time.perf_counter() - t
-        t = time.perf_counter()
-        _, it_pr = G.pr_static(0.85, 1e-9, 1000)
-        t_ps = time.perf_counter() - t
-        t_apply = 1e-3 * (avg("t_validate_ms") + avg("t_update_ms") + avg("t_merge_ms"))
-        static = {
-            "sssp_ms": round(1e3 * t_ss, 3),
-            "pr_ms": round(1e3 * t_ps, 3),
-            "pr_iterations": it_pr,
-            "apply_ms": round(1e3 * t_apply, 3),
-            "updates_per_s": round(k / (t_apply + t_ss + t_ps), 1),
-            "dynamic_speedup": round((t_apply + t_ss + t_ps) / (elapsed / K), 3),
-        }
-        log(f"static recompute: sssp {1e3 * t_ss:.1f} ms, pr {1e3 * t_ps:.1f} ms ({it_pr} iters)")
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        import oracle
-
-        log("cpu oracle on one batch (apply + Dijkstra + power iteration) ...")
-        b = batches[W]
-        t = time.perf_counter()
-        s2, d2, w2, _ = oracle.apply(n, s, d, w, *b)
-        oracle.sssp(n, s2, d2, w2, 0)
-        oracle.pagerank(n, s2, d2, 0.85, 1e-9, 1000)
-        t_cpu = time.perf_counter() - t
-        cpu = {"value": round(k / t_cpu, 1), "unit": "updates/s", "cores": 1, "kind": "oracle",
-               "seconds": round(t_cpu, 2),
-               "sample": f"one {k}-update batch on the full R-MAT scale-{args.scale} graph: edge-list "
-                         f"apply, Dijkstra from 0, FP64 power iteration to L1 1e-9 (single thread)"}
-        log(f"cpu oracle: {t_cpu:.1f}s")
-
-    out = {
-        "metric": METRIC,
-        "value": round(value, 1),
-        "unit": "updates/s",
-        "n_gpus": 1,
-        "steps": K,
-        "warmup": W,
-        "ms_per_step": round(ms_per_step, 3),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "i32+f64",
-        "data": "synthetic",
-        "config": {"workload": f"rmat{args.scale}-dynamic-sssp+pagerank", "vertices": n, "arcs": int(s.size),
-                   "batch": k, "insert_fraction": 0.5, "queries": ["sssp(0)", "pagerank(0.85, l1 1e-9)"],
-                   "parallelism": "1 gpu", "heavy_degree": args.heavy_degree or 512,
-                   "sssp_persistent": args.sssp_persistent, "pr_mode": args.pr_mode},
-        "roofline": roofline,
-        "cpu_baseline": cpu,
-        "static_recompute": static,
-        "phases_ms": {key: round(avg(key), 3) for key in
-                      ("t_validate_ms", "t_update_ms", "t_merge_ms", "t_sssp_ms", "t_pr_ms", "t_total_ms")},
-        "per_batch": {"pr_iterations": avg("pr_iterations"), "pr_affected": avg("pr_affected"),
-                      "sssp_invalidated": avg("sssp_invalidated"), "sssp_steps": avg("sssp_steps"),
-                      "deleted": avg("deleted"), "inserted": avg("inserted"), "merged": sum(x["merged"] for x in stats)},
-        "gteps": round(sum(x["edges_traversed"] for x in stats) / elapsed / 1e9, 3),
-        "kernels": kernels,
-    }
-    print(json.dumps(out), flush=True)
-    G.close()
-    return 0
+    if args.workload in ("rmat", "grid", "tc"):
+        return run_single(args, args.workload)
+    if args.workload == "batched":
+        return run_batched(args)
+    return run_serve(args)
 
 
 if __name__ == "__main__":

@@ -31,6 +31,10 @@ _MASK64 = (1 << 64) - 1
 _TAG = {
     "rmat": 0x52, "w": 0x57, "del": 0x44, "ins_u": 0x49, "ins_v": 0x4A,
     "ins_w": 0x4B, "perm": 0x50, "orient": 0x4F, "misc": 0x4D,
+    # workload-level draws: member scales and batch fractions of a graph set,
+    # request arrival gaps, target graph, batch size, query kind and source
+    "scale": 0x53, "frac": 0x46, "gap": 0x47, "graph": 0x67, "k": 0x6B, "kind": 0x71,
+    "source": 0x73,
 }
 
 BASE_SEED = 0xD15C0

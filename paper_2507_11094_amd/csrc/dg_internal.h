@@ -230,10 +230,12 @@ int query_attach(dg_graph *g, dg_query *q, dg_query **out);
 
 // persistent worklist traversals (worklist.hip)
 int sssp_static_persistent(dg_graph *g, uint64_t *key, const int32_t *sources, int64_t ns);
+// ncut_out: vertices cut; edges_out: arcs examined by the cut and push kernels.
 int sssp_post_persistent(dg_graph *g, uint64_t *key, const int32_t *seeds, const int64_t *nseeds_dev,
-                         int32_t *cut, const int64_t *ains_dev, int64_t *ncut_out);
+                         int32_t *cut, const int64_t *ains_dev, int64_t *ncut_out, int64_t *edges_out);
 int sssp_post_graph(dg_graph *g, GraphCache *cache, uint64_t *key, const int32_t *seeds,
-                    const int64_t *nseeds_dev, int32_t *cut, const int64_t *ains_dev, int64_t *ncut_out);
+                    const int64_t *nseeds_dev, int32_t *cut, const int64_t *ains_dev, int64_t *ncut_out,
+                    int64_t *edges_out);
 void graph_cache_clear(GraphCache *cache);
 int wl_prepare(dg_graph *g);
 int wl_groups(dg_graph *g);
@@ -251,6 +253,8 @@ int pr_normalize(dg_graph *g, const double *x, double *rank, bool dev);
 bool prof_on();
 int prof_begin(const char *name, hipStream_t s);
 void prof_end(int slot, hipStream_t s, double bytes);
+// Add bytes to a recorded launch once they are known (after the launch finished).
+void prof_add(int slot, double bytes);
 
 // triangle counting (tc.hip)
 int tc_count_static(dg_graph *g, uint64_t *count);

@@ -15,6 +15,7 @@ struct Pending {
     std::string name;
     hipEvent_t a, b;
     double bytes;
+    int id;
 };
 struct Total {
     int64_t launches = 0;
@@ -24,6 +25,7 @@ struct Total {
 std::mutex g_mu;
 bool g_on = false;
 std::vector<Pending> g_pending;
+int g_next_id = 0;  // launch ids stay valid across resolves (a resolved id is simply not found)
 std::vector<hipEvent_t> g_pool;
 std::vector<std::string> g_order;
 std::unordered_map<std::string, Total> g_tot;
@@ -64,8 +66,9 @@ bool prof_on() { return g_on; }
 int prof_begin(const char *name, hipStream_t s) {
     if (!g_on) return -1;
     std::lock_guard<std::mutex> lk(g_mu);
-    Pending p{name, take_event(), take_event(), 0.0};
+    Pending p{name, take_event(), take_event(), 0.0, g_next_id};
     if (!p.a || !p.b) return -1;
+    g_next_id = (g_next_id + 1) & 0x3fffffff;
     (void)hipEventRecord(p.a, s);
     g_pending.push_back(p);
     if (g_pending.size() > 20000) {
@@ -75,15 +78,29 @@ int prof_begin(const char *name, hipStream_t s) {
         resolve_locked();
         g_pending.push_back(last);
     }
-    return (int)g_pending.size() - 1;
+    return p.id;
+}
+
+static Pending *find_pending(int id) {
+    for (size_t i = g_pending.size(); i-- > 0;)
+        if (g_pending[i].id == id) return &g_pending[i];
+    return nullptr;
 }
 
 void prof_end(int slot, hipStream_t s, double bytes) {
     if (slot < 0) return;
     std::lock_guard<std::mutex> lk(g_mu);
-    if (slot >= (int)g_pending.size()) return;
-    (void)hipEventRecord(g_pending[slot].b, s);
-    g_pending[slot].bytes += bytes;
+    Pending *p = find_pending(slot);
+    if (!p) return;
+    (void)hipEventRecord(p->b, s);
+    p->bytes += bytes;
+}
+
+void prof_add(int slot, double bytes) {
+    if (slot < 0) return;
+    std::lock_guard<std::mutex> lk(g_mu);
+    Pending *p = find_pending(slot);
+    if (p) p->bytes += bytes;
 }
 
 }  // namespace dg

@@ -288,14 +288,17 @@ int sssp_post_update(dg_query *q, int64_t adel, int64_t ains, dg_batch_stats *st
         q->hpin[0] = q->nseeds;
         q->hpin[1] = ains;
         DG_HIP(hipMemcpyAsync(q->qcnt.p, q->hpin, 2 * sizeof(int64_t), hipMemcpyHostToDevice, s));
-        int64_t ncut = 0;
+        int64_t ncut = 0, edges = 0;
         if (q->gcache)
-            DG_TRY(sssp_post_graph(g, q->gcache, q->key.p, q->inval.p, q->qcnt.p, ws.f1.p, q->qcnt.p + 1, &ncut));
+            DG_TRY(sssp_post_graph(g, q->gcache, q->key.p, q->inval.p, q->qcnt.p, ws.f1.p, q->qcnt.p + 1, &ncut,
+                                   &edges));
         else
-            DG_TRY(sssp_post_persistent(g, q->key.p, q->inval.p, q->qcnt.p, ws.f1.p, q->qcnt.p + 1, &ncut));
+            DG_TRY(sssp_post_persistent(g, q->key.p, q->inval.p, q->qcnt.p, ws.f1.p, q->qcnt.p + 1, &ncut,
+                                        &edges));
         if (st) {
             st->sssp_invalidated += ncut;
             st->sssp_steps += 1;
+            st->edges_traversed += edges;
         }
         return DG_OK;
     }

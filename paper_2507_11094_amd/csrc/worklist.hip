@@ -28,6 +28,10 @@
 namespace dg {
 
 enum { WQ_HEAD = 0, WQ_TAIL = 1, WQ_DONE = 2, WQ_ERR = 3, WQ_LIST = 4, WQ_NCTR = 8 };
+// Second block of counters (not cleared between the phases of one update):
+// the cut-list length carried into the push phase, then the tallies of arcs
+// examined and items processed by the cut and push kernels.
+enum { WT_LIST = WQ_NCTR, WT_EDGES = WQ_NCTR + 1, WT_ITEMS = WQ_NCTR + 2, WT_N = 3 };
 constexpr uint32_t WHOLE = 0xFFFFFFFFu;
 constexpr int64_t SPIN_LIMIT = 1ll << 24;  // ~ seconds of s_sleep(1) polling
 
@@ -214,11 +218,23 @@ __device__ __forceinline__ bool wq_items(const WorkQ &wq, const DirView &g, unsi
 
 // ---- SSSP push (Incremental) ------------------------------------------------------
 
+// Per-wave tallies, added to the counters once when the wave leaves.
+__device__ __forceinline__ void wq_tally(const WorkQ &wq, int64_t edges, int64_t items) {
+    edges = wave_sum(edges);
+    items = wave_sum(items);
+    if (lane_id() == 0) {
+        atomicAdd(&wq.ctr[WT_EDGES], (unsigned long long)edges);
+        atomicAdd(&wq.ctr[WT_ITEMS], (unsigned long long)items);
+    }
+}
+
 __global__ __launch_bounds__(256) void k_wl_push(WorkQ wq, DirView g, uint64_t *key, int32_t *inq, int heavy_deg,
                                                  int chunk) {
     unsigned long long h;
     int cnt;
+    int64_t ne = 0, ni = 0;
     while (wq_claim(wq, h, cnt)) {
+        if (lane_id() == 0) ni += cnt;
         int32_t v, d;
         Row r;
         int32_t s, len;
@@ -234,6 +250,7 @@ __global__ __launch_bounds__(256) void k_wl_push(WorkQ wq, DirView g, uint64_t *
         if (ok) {
             wave_walk(g, v, d, r, s, len, [&](bool valid, int32_t vo, int32_t dov, int32_t x, int32_t w) {
                 bool push = false;
+                ne += valid;
                 if (valid) {
                     uint64_t cand = sssp_pack(dov + w, vo);
                     if (cand < __atomic_load_n(&key[x], __ATOMIC_RELAXED)) {
@@ -246,6 +263,7 @@ __global__ __launch_bounds__(256) void k_wl_push(WorkQ wq, DirView g, uint64_t *
         }
         wq_finish(wq, cnt);
     }
+    wq_tally(wq, ne, ni);
 }
 
 // ---- SSSP subtree cut (Decremental, phase 1) ----------------------------------------
@@ -255,7 +273,9 @@ __global__ __launch_bounds__(256) void k_wl_cut(WorkQ wq, DirView g, uint64_t *k
                                                 int heavy_deg, int chunk) {
     unsigned long long h;
     int cnt;
+    int64_t ne = 0, ni = 0;
     while (wq_claim(wq, h, cnt)) {
+        if (lane_id() == 0) ni += cnt;
         int32_t v, p0;
         Row r;
         int32_t s, len;
@@ -268,6 +288,7 @@ __global__ __launch_bounds__(256) void k_wl_cut(WorkQ wq, DirView g, uint64_t *k
         if (ok) {
             wave_walk(g, v, p0, r, s, len, [&](bool valid, int32_t vo, int32_t, int32_t x, int32_t) {
                 bool cut = false;
+                ne += valid;
                 if (valid && sssp_parent(key[x]) == vo) {
                     key[x] = sssp_pack(INF, -1);
                     cut = true;
@@ -279,6 +300,7 @@ __global__ __launch_bounds__(256) void k_wl_cut(WorkQ wq, DirView g, uint64_t *k
         }
         wq_finish(wq, cnt);
     }
+    wq_tally(wq, ne, ni);
 }
 
 // ---- seeding kernels ---------------------------------------------------------------------
@@ -405,6 +427,27 @@ static int wl_reset(dg_graph *g, const WorkQ &wq) {
     return DG_OK;
 }
 
+static int wl_reset_tally(dg_graph *g, const WorkQ &wq) {
+    hipLaunchKernelGGL(k_wq_reset, dim3(1), dim3(64), 0, g->stream, wq.ctr + WT_EDGES, 2);
+    DG_HIP(hipGetLastError());
+    return DG_OK;
+}
+
+// t[0] cut-list length, t[1] arcs examined, t[2] items processed (synchronous).
+static int wl_tally(dg_graph *g, const WorkQ &wq, int64_t *t) {
+    unsigned long long h[WT_N];
+    DG_HIP(hipMemcpyAsync(h, wq.ctr + WT_LIST, sizeof(h), hipMemcpyDeviceToHost, g->stream));
+    DG_HIP(hipStreamSynchronize(g->stream));
+    for (int i = 0; i < WT_N; ++i) t[i] = (int64_t)h[i];
+    return DG_OK;
+}
+
+// Algorithmic bytes of the cut and push kernels: per item its queue slot and tag
+// (16 B read, 16 B written when it was pushed), the base and diff offset pairs
+// (32 B), its key (8 B) and in-queue flag (4 B); per arc the column and weight
+// (8 B) and the head's key (8 B).
+static double wl_bytes(int64_t edges, int64_t items) { return 16.0 * (double)edges + 76.0 * (double)items; }
+
 static int wl_check(dg_graph *g, const WorkQ &wq, int64_t *list_count) {
     unsigned long long h[WQ_NCTR];
     DG_HIP(hipMemcpyAsync(h, wq.ctr, sizeof(h), hipMemcpyDeviceToHost, g->stream));
@@ -428,6 +471,7 @@ int sssp_static_persistent(dg_graph *g, uint64_t *key, const int32_t *sources, i
     DG_TRY(wl_ensure(g, &wq));
     hipStream_t s = g->stream;
     DG_TRY(wl_reset(g, wq));
+    DG_TRY(wl_reset_tally(g, wq));
     DG_TRY(wl_clear_tags(g, wq));
     hipLaunchKernelGGL(k_wl_seed_sources, dim3(gridc(ns)), dim3(256), 0, s, wq, sources, ns, g->ws.inq.p);
     int ps = prof_begin("sssp_worklist", s);
@@ -435,7 +479,11 @@ int sssp_static_persistent(dg_graph *g, uint64_t *key, const int32_t *sources, i
                        heavy_of(g), heavy_of(g));
     prof_end(ps, s, 0.0);
     DG_HIP(hipGetLastError());
-    return wl_check(g, wq, nullptr);
+    DG_TRY(wl_check(g, wq, nullptr));
+    int64_t t[WT_N];
+    DG_TRY(wl_tally(g, wq, t));
+    prof_add(ps, wl_bytes(t[1], t[2]));
+    return DG_OK;
 }
 
 // Dynamic SSSP post-hook on the worklists: enqueue only, no host round trip and
@@ -458,6 +506,7 @@ static int sssp_post_enqueue(dg_graph *g, uint64_t *key, const int32_t *seeds, c
     const int H = heavy_of(g);
     // 1. cut the subtrees below the seeds
     DG_TRY(wl_reset(g, wq));
+    DG_TRY(wl_reset_tally(g, wq));
     DG_TRY(wl_clear_tags(g, wq));
     hipLaunchKernelGGL(k_wl_seed_list, dim3(64), dim3(256), 0, s, wq, seeds, nseeds_dev, cut);
     hipLaunchKernelGGL(k_wl_cut, dim3(wl_groups(g)), dim3(256), 0, s, wq, view(g->fwd), key, cut, H, H);
@@ -478,7 +527,7 @@ static int sssp_post_enqueue(dg_graph *g, uint64_t *key, const int32_t *seeds, c
         DG_TRY(launch_expand(s, a, op, 4096));
     }
     // 3. push from the pulled cut vertices and the improved heads of inserted arcs
-    unsigned long long *listc = wq.ctr + WQ_NCTR;  // keep the cut count across the reset
+    unsigned long long *listc = wq.ctr + WT_LIST;  // keep the cut count across the reset
     hipLaunchKernelGGL(k_wq_copy_ctr, dim3(1), dim3(64), 0, s, listc, &wq.ctr[WQ_LIST]);
     DG_TRY(wl_reset(g, wq));
     DG_TRY(wl_clear_tags(g, wq));
@@ -490,31 +539,32 @@ static int sssp_post_enqueue(dg_graph *g, uint64_t *key, const int32_t *seeds, c
     return DG_OK;
 }
 
-static int sssp_post_finish(dg_graph *g, int64_t *ncut_out) {
+static int sssp_post_finish(dg_graph *g, int ps, int64_t *ncut_out, int64_t *edges_out) {
     WorkQ wq;
     DG_TRY(wl_ensure(g, &wq));
     DG_TRY(wl_check(g, wq, nullptr));
-    if (ncut_out) {
-        unsigned long long c = 0;
-        DG_HIP(hipMemcpy(&c, wq.ctr + WQ_NCTR, sizeof(c), hipMemcpyDeviceToHost));
-        *ncut_out = (int64_t)c;
-    }
+    int64_t t[WT_N];
+    DG_TRY(wl_tally(g, wq, t));
+    if (ncut_out) *ncut_out = t[0];
+    if (edges_out) *edges_out = t[1];
+    prof_add(ps, wl_bytes(t[1], t[2]));
     return DG_OK;
 }
 
 int sssp_post_persistent(dg_graph *g, uint64_t *key, const int32_t *seeds, const int64_t *nseeds_dev,
-                         int32_t *cut, const int64_t *ains_dev, int64_t *ncut_out) {
+                         int32_t *cut, const int64_t *ains_dev, int64_t *ncut_out, int64_t *edges_out) {
     int ps = prof_begin("sssp_worklist", g->stream);
     DG_TRY(sssp_post_enqueue(g, key, seeds, nseeds_dev, cut, ains_dev));
     prof_end(ps, g->stream, 0.0);
-    return sssp_post_finish(g, ncut_out);
+    return sssp_post_finish(g, ps, ncut_out, edges_out);
 }
 
 // Same work replayed from a captured hipGraph.  The graph bakes pointers in, so it
 // is cached under the set of pointers it uses (the diff level alternates between
 // two buffers, so two graphs cover steady state); a new layout captures again.
 int sssp_post_graph(dg_graph *g, GraphCache *cache, uint64_t *key, const int32_t *seeds,
-                    const int64_t *nseeds_dev, int32_t *cut, const int64_t *ains_dev, int64_t *ncut_out) {
+                    const int64_t *nseeds_dev, int32_t *cut, const int64_t *ains_dev, int64_t *ncut_out,
+                    int64_t *edges_out) {
     DG_TRY(wl_prepare(g));
     if (!g->stream) return set_error(DG_ESTATE, "graph capture needs a non-null stream");
     std::vector<const void *> sig = {key, seeds, nseeds_dev, cut, ains_dev, g->fwd.off.p, g->fwd.col.p,
@@ -548,7 +598,7 @@ int sssp_post_graph(dg_graph *g, GraphCache *cache, uint64_t *key, const int32_t
     DG_HIP(hipGraphLaunch(exec, g->stream));
     prof_end(ps, g->stream, 0.0);
     cache->launches += 1;
-    return sssp_post_finish(g, ncut_out);
+    return sssp_post_finish(g, ps, ncut_out, edges_out);
 }
 
 void graph_cache_clear(GraphCache *cache) {
