@@ -75,7 +75,8 @@ def traffic_for(kernel: str, workload: str):
     return round(e["fetch_kib"] * 1024 / e["fetch_factor"] + e["write_kib"] * 1024 / e["write_factor"])
 
 
-KERNEL_SOURCE = {"pr_pull": ("k_pr_pull", "pagerank.hip"), "pr_apply": ("k_pr_apply", "pagerank.hip"),
+KERNEL_SOURCE = {"pr_pull": ("k_pr_pull", "pagerank.hip"), "pr_tiles": ("k_pr_tiles", "pagerank.hip"),
+                 "pr_apply": ("k_pr_apply", "pagerank.hip"),
                  "merge_base": ("k_merge_base", "graph.hip"),
                  "sssp_worklist": ("k_wl_cut + pull + k_wl_push", "worklist.hip"),
                  "tc_delta": ("k_tc_delta", "tc.hip")}
@@ -199,6 +200,7 @@ def run_single(args, kind: str) -> int:
     cfg.heavy_degree = args.heavy_degree
     cfg.sssp_persistent = persistent
     cfg.pr_mode = args.pr_mode
+    cfg.pr_pull = args.pr_pull
     t = time.perf_counter()
     G = dg.Graph(n, s, d, w, undirected=undirected, config=cfg)
     log(f"graph built on device in {time.perf_counter() - t:.2f}s")
@@ -263,7 +265,8 @@ def run_single(args, kind: str) -> int:
 
     config = {"workload": wl, "vertices": n, "arcs": int(s.size) * (2 if undirected else 1),
               "batch": k, "insert_fraction": 0.5, "parallelism": "1 gpu",
-              "heavy_degree": args.heavy_degree or 512, "sssp_persistent": persistent, "pr_mode": args.pr_mode}
+              "heavy_degree": args.heavy_degree or 512, "sssp_persistent": persistent, "pr_mode": args.pr_mode,
+              "pr_pull": ["merge-path tiles", "vertex waves"][args.pr_pull]}
     if kind == "tc":
         config.update({"undirected_edges": int(s.size), "batch_fraction": args.pct, "queries": ["triangles"]})
     else:
@@ -284,7 +287,7 @@ def run_single(args, kind: str) -> int:
     if kind == "tc":
         extra["triangles"] = {"initial": int(tc0), "final": int(qt.read())}
     out = line(args, value, "updates/s", 1e3 * elapsed / K, "u64" if kind == "tc" else "i32+f64", config,
-               roofline_of(prof, wl, "pr_pull" if kind != "tc" else None), cpu, **extra)
+               roofline_of(prof, wl), cpu, **extra)
     print(json.dumps(out), flush=True)
     G.close()
     return 0
@@ -654,6 +657,8 @@ def main() -> int:
     ap.add_argument("--sssp-persistent", type=int, default=-1,
                     help="1: SSSP on the single-launch work queue, 0: frontier steps (-1: grid 1, else 0)")
     ap.add_argument("--pr-mode", type=int, default=0, help="PageRank form after a batch: 0 auto, 1 local, 2 global")
+    ap.add_argument("--pr-pull", type=int, default=0,
+                    help="whole-graph PageRank pull: 0 merge-path tiles, 1 per-vertex waves")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run five plain 256 MiB device-to-device copies (reference for the "
                          "FETCH_SIZE / WRITE_SIZE counter scale) and exit")

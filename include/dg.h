@@ -81,7 +81,11 @@ typedef struct dg_config {
      * form when the affected set holds >= 20% of the edges, else the local
      * restricted form), 1 = always local, 2 = always global. */
     int32_t pr_mode;
-    int32_t reserved[6];
+    /* Whole-graph PageRank pull (static solve and the global form): 0 = merge-path
+     * tiles (equal rows + entries per workgroup, default), 1 = the per-vertex wave
+     * kernel that the affected-set iteration uses.  Same results up to rounding. */
+    int32_t pr_pull;
+    int32_t reserved[5];
 } dg_config;
 
 /* Per-batch statistics and phase timings (HIP events on the graph's stream). */

@@ -339,6 +339,154 @@ __global__ void k_refresh_contrib(int64_t n, const int32_t *u, const double *x, 
 
 static int heavy_deg(dg_graph *g) { return g->cfg.heavy_degree > 0 ? g->cfg.heavy_degree : 512; }
 
+// ---- whole-graph pull: merge-path tiles ---------------------------------------------
+// When every vertex is pulled (static solve, global form) the pull is a sparse
+// matrix-vector product over the reverse CSR.  The row ends and the base entries
+// form one merged sequence of n + m items; tile b takes the items
+// [b * MP_ITEMS, (b + 1) * MP_ITEMS) of it (the merge-path decomposition of
+// Merrill and Garland, PPoPP 2016), so every workgroup streams the same amount of
+// work whatever the degree skew: no per-vertex wave, no heavy-row queue.
+//   k_mp_partition  tile start coordinates (row, entry), once per iteration call;
+//   k_pr_tiles      entries staged through LDS (column reads coalesced, one
+//                   contribution gather per entry), then each row that ends in
+//                   the tile is summed in entry order: short pieces by one lane,
+//                   long pieces by a wave; rows that began in an earlier tile
+//                   leave their piece in pf[b], the row still open at the tile's
+//                   end leaves its piece in pl[b];
+//   k_pr_fixup      rows split across tiles: pieces added in tile order;
+//   k_pr_diff_add   diff-level entries added per row in key order.
+// Every sum has a fixed order, so results are bit-reproducible.
+constexpr int MP_THREADS = 256;
+constexpr int MP_ITEMS = 2048;
+constexpr int MP_IPT = MP_ITEMS / MP_THREADS;
+constexpr int MP_LONG = 64;  // row pieces longer than this are summed by a whole wave
+
+__global__ void k_mp_partition(const int64_t *__restrict__ off, int32_t n, int64_t m, int64_t nb,
+                               int32_t *mp_row, int64_t *mp_edge) {
+    for (int64_t b = gtid(); b <= nb; b += gstride()) {
+        const int64_t diag = min(b * (int64_t)MP_ITEMS, (int64_t)n + m);
+        // rows consumed at this diagonal: the largest r with off[r] <= diag - r
+        // (a row's end is taken before the entry that starts the next row)
+        int64_t lo = max(diag - m, (int64_t)0), hi = min(diag, (int64_t)n);
+        while (lo < hi) {
+            const int64_t p = (lo + hi) >> 1;
+            if (off[p + 1] <= diag - p - 1) lo = p + 1;
+            else hi = p;
+        }
+        mp_row[b] = (int32_t)lo;
+        mp_edge[b] = diag - lo;
+    }
+}
+
+__global__ __launch_bounds__(MP_THREADS) void k_pr_tiles(const int32_t *__restrict__ mp_row,
+                                                         const int64_t *__restrict__ mp_edge,
+                                                         const int64_t *__restrict__ off,
+                                                         const int32_t *__restrict__ col,
+                                                         const double *__restrict__ contrib, const double *cterm,
+                                                         double damp, double *xn, double *pf, double *pl) {
+    __shared__ double s_val[MP_ITEMS];
+    __shared__ int32_t s_off[MP_ITEMS + 1];
+    __shared__ int32_t s_long[MP_ITEMS / MP_LONG + 2];
+    __shared__ int32_t s_nlong;
+    const int64_t b = blockIdx.x;
+    const int32_t r0 = mp_row[b], r1 = mp_row[b + 1];
+    const int64_t e0 = mp_edge[b];
+    const int32_t ne = (int32_t)(mp_edge[b + 1] - e0);
+    const int32_t nr = r1 - r0;
+    const int t = threadIdx.x;
+    if (t == 0) s_nlong = 0;
+    // stage the entries: all column loads first, then all gathers (MP_IPT in flight)
+    uint32_t c[MP_IPT];
+#pragma unroll
+    for (int u = 0; u < MP_IPT; ++u) {
+        const int j = t + u * MP_THREADS;
+        c[u] = j < ne ? (uint32_t)col[e0 + j] : DEAD;
+    }
+    double v[MP_IPT];
+#pragma unroll
+    for (int u = 0; u < MP_IPT; ++u) v[u] = (c[u] & DEAD) ? 0.0 : contrib[c[u] & ID_MASK];
+#pragma unroll
+    for (int u = 0; u < MP_IPT; ++u) {
+        const int j = t + u * MP_THREADS;
+        if (j < ne) s_val[j] = v[u];
+    }
+    // row starts relative to the tile (-1: the row began in an earlier tile)
+    for (int i = t; i <= nr; i += MP_THREADS) {
+        const int64_t o = off[r0 + i] - e0;
+        s_off[i] = (int32_t)(o < 0 ? -1 : o);
+    }
+    __syncthreads();
+    const double base = *cterm;
+    // rows that end in this tile: short pieces one lane each
+    for (int i = t; i < nr; i += MP_THREADS) {
+        const int32_t lo = max(s_off[i], 0), hi = s_off[i + 1];
+        if (hi - lo > MP_LONG) {
+            s_long[atomicAdd(&s_nlong, 1)] = i;
+            continue;
+        }
+        double acc = 0.0;
+        for (int32_t j = lo; j < hi; ++j) acc += s_val[j];
+        if (s_off[i] < 0) pf[b] = acc;
+        else xn[r0 + i] = base + damp * acc;
+    }
+    __syncthreads();
+    // long pieces, then the piece of the row left open at the tile's end, one wave each
+    const int wv = t / WAVE, l = lane_id();
+    const int nlong = s_nlong;
+    for (int k = wv; k <= nlong; k += MP_THREADS / WAVE) {
+        int32_t lo, hi;
+        if (k < nlong) {
+            lo = max(s_off[s_long[k]], 0);
+            hi = s_off[s_long[k] + 1];
+        } else {
+            lo = max(s_off[nr], 0);
+            hi = ne;
+        }
+        double acc = 0.0;
+        for (int32_t j = lo + l; j < hi; j += WAVE) acc += s_val[j];
+        acc = wave_sum(acc);
+        if (l == 0) {
+            if (k == nlong) pl[b] = acc;
+            else if (s_off[s_long[k]] < 0) pf[b] = acc;
+            else xn[r0 + s_long[k]] = base + damp * acc;
+        }
+    }
+}
+
+// Rows that began in an earlier tile and end in tile b: the open pieces of the
+// tiles before (pl, in tile order) plus the closing piece (pf[b]).
+__global__ void k_pr_fixup(int64_t nb, const int32_t *__restrict__ mp_row, const int64_t *__restrict__ mp_edge,
+                           const int64_t *__restrict__ off, const double *pf, const double *pl,
+                           const double *cterm, double damp, double *xn) {
+    const double base = *cterm;
+    for (int64_t b = gtid(); b < nb; b += gstride()) {
+        const int32_t R = mp_row[b];
+        if (R >= mp_row[b + 1] || off[R] >= mp_edge[b]) continue;
+        int64_t first = b - 1;  // tile b-1 ends inside row R
+        while (first > 0 && mp_row[first] == R) --first;
+        double acc = 0.0;
+        for (int64_t j = first; j < b; ++j) acc += pl[j];
+        acc += pf[b];
+        xn[R] = base + damp * acc;
+    }
+}
+
+// Diff-level entries: the first entry of each row's run adds the run's live
+// contributions, in key order.
+__global__ void k_pr_diff_add(int64_t dm, const uint64_t *__restrict__ dkey, const int32_t *__restrict__ dcol,
+                              int keybits, const double *__restrict__ contrib, double damp, double *xn) {
+    for (int64_t j = gtid(); j < dm; j += gstride()) {
+        const int32_t r = (int32_t)(dkey[j] >> keybits);
+        if (j > 0 && (int32_t)(dkey[j - 1] >> keybits) == r) continue;
+        double acc = 0.0;
+        for (int64_t q = j; q < dm && (int32_t)(dkey[q] >> keybits) == r; ++q) {
+            const uint32_t cc = (uint32_t)dcol[q];
+            if (!(cc & DEAD)) acc += contrib[cc & ID_MASK];
+        }
+        if (acc != 0.0) xn[r] += damp * acc;
+    }
+}
+
 static int ensure_pr_ws(dg_graph *g) {
     Work &ws = g->ws;
     DG_TRY(ws.f0.ensure((size_t)g->n + 1));
@@ -392,20 +540,47 @@ static int pr_iterate(dg_graph *g, const int32_t *A, int64_t na, int64_t edges, 
     hipLaunchKernelGGL(k_pr_reduce, dim3(1), dim3(256), 0, s, partials, global ? APPLY_GROUPS : 1,
                        (int)global, S, damping, ninv, prs, step_out);
     DG_HIP(hipGetLastError());
+    // every vertex pulled: merge-path tiles over the base level, then the diff level
+    const Dir &R = *g->rev;
+    const bool tiles = A == nullptr && g->cfg.pr_pull == 0;
+    int64_t nb = 0;
+    if (tiles) {
+        nb = ((int64_t)g->n + R.m + MP_ITEMS - 1) / MP_ITEMS;
+        DG_TRY(ws.mp_row.ensure((size_t)nb + 1));
+        DG_TRY(ws.mp_edge.ensure((size_t)nb + 1));
+        DG_TRY(ws.mp_part.ensure(2 * (size_t)nb + 2));
+        hipLaunchKernelGGL(k_mp_partition, dim3(grid_for(nb + 1)), dim3(256), 0, s, R.off.p, g->n, R.m, nb,
+                           ws.mp_row.p, ws.mp_edge.p);
+        DG_HIP(hipGetLastError());
+    }
+    double *pf = ws.mp_part.p, *pl = ws.mp_part.p + nb + 1;
     int32_t it = 0;
     *conv = 0;
     while (it < max_iter && na > 0) {
         DG_TRY(counters_clear(g));
-        int64_t blocks = std::min<int64_t>((na + 255) / 256, 65535);
-        int ps = prof_begin("pr_pull", s);
-        hipLaunchKernelGGL(k_pr_pull, dim3((unsigned)blocks), dim3(256), 0, s, A, na, rv, contrib, prs + 2,
-                           damping, xn, hq, ws.dcnt + C_HEAVY, hv, ws.dcnt + C_AUX3, heavy_deg(g),
-                           heavy_deg(g));
-        prof_end(ps, s, 28.0 * (double)na + 12.0 * (double)edges);
-        hipLaunchKernelGGL(k_pr_heavy, dim3(8192), dim3(256), 0, s, rv, contrib, hq, ws.dcnt + C_HEAVY,
-                           heavy_deg(g), ws.part.p);
-        hipLaunchKernelGGL(k_pr_finish, dim3(64), dim3(256), 0, s, hv, ws.dcnt + C_AUX3, ws.part.p, prs + 2,
-                           damping, xn);
+        if (tiles) {
+            // tiles: off 8 + xn 8 per row, col 4 + contrib 8 per base entry
+            int ps = prof_begin("pr_tiles", s);
+            hipLaunchKernelGGL(k_pr_tiles, dim3((unsigned)nb), dim3(MP_THREADS), 0, s, ws.mp_row.p, ws.mp_edge.p,
+                               R.off.p, R.col.p, contrib, prs + 2, damping, xn, pf, pl);
+            prof_end(ps, s, 16.0 * (double)g->n + 12.0 * (double)R.m);
+            hipLaunchKernelGGL(k_pr_fixup, dim3(grid_for(nb)), dim3(256), 0, s, nb, ws.mp_row.p, ws.mp_edge.p,
+                               R.off.p, pf, pl, prs + 2, damping, xn);
+            if (R.dm > 0)
+                hipLaunchKernelGGL(k_pr_diff_add, dim3(grid_for(R.dm)), dim3(256), 0, s, R.dm, R.dkey.p, R.dcol.p,
+                                   R.keybits, contrib, damping, xn);
+        } else {
+            int64_t blocks = std::min<int64_t>((na + 255) / 256, 65535);
+            int ps = prof_begin("pr_pull", s);
+            hipLaunchKernelGGL(k_pr_pull, dim3((unsigned)blocks), dim3(256), 0, s, A, na, rv, contrib, prs + 2,
+                               damping, xn, hq, ws.dcnt + C_HEAVY, hv, ws.dcnt + C_AUX3, heavy_deg(g),
+                               heavy_deg(g));
+            prof_end(ps, s, 28.0 * (double)na + 12.0 * (double)edges);
+            hipLaunchKernelGGL(k_pr_heavy, dim3(8192), dim3(256), 0, s, rv, contrib, hq, ws.dcnt + C_HEAVY,
+                               heavy_deg(g), ws.part.p);
+            hipLaunchKernelGGL(k_pr_finish, dim3(64), dim3(256), 0, s, hv, ws.dcnt + C_AUX3, ws.part.p, prs + 2,
+                               damping, xn);
+        }
         int pa = prof_begin("pr_apply", s);
         hipLaunchKernelGGL(k_pr_apply, dim3(APPLY_GROUPS), dim3(256), 0, s, A, na, xn, x, contrib,
                            g->fwd.deg.p, partials);

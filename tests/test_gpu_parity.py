@@ -294,6 +294,54 @@ def test_pagerank_c1_dynamic(heavy, mode):
     pr_check(rs, n, cs, cd)
 
 
+def hub_graph(n=1 << 14, hub_in=12000, seed=11):
+    """Uniform arcs among the lower half of the vertices (the upper half is
+    isolated) plus one hub with `hub_in` in-arcs, so that whole-graph pulls see
+    rows far longer than a tile, runs of empty rows and tiny rows."""
+    rng_s = graphgen.uniform_int(seed, 0, 80000, 0, n // 2 - 1)
+    rng_d = graphgen.uniform_int(seed + 1, 0, 80000, 0, n // 2 - 1)
+    hs = np.arange(1, hub_in + 1)
+    src = np.concatenate([rng_s, hs])
+    dst = np.concatenate([rng_d, np.full(hub_in, 0)])
+    keep = src != dst
+    key = np.unique((src[keep].astype(np.int64) << 32) | dst[keep].astype(np.int64))
+    s = (key >> 32).astype(np.int32)
+    d = (key & 0xFFFFFFFF).astype(np.int32)
+    w = graphgen.uniform_int(seed + 2, 0, s.size, 1, 100).astype(np.int32)
+    return n, s, d, w
+
+
+@pytest.mark.parametrize("pull", [0, 1])
+def test_pagerank_whole_graph_pull(pull):
+    """Static solve and global-form updates, merge-path tiles (0) or per-vertex
+    waves (1), with a live diff level (no merges), against the oracle."""
+    n, s, d, w = hub_graph()
+    say("pagerank whole-graph pull", pull, "arcs", s.size)
+    c = cfg(merge=1e9)
+    c.pr_mode = 2
+    c.pr_pull = pull
+    G = dg.Graph(n, s, d, w, config=c)
+    q = G.pr_attach(0.85, PR_TOL, 1000)
+    r, it, conv = q.read()
+    pr_check(r, n, s, d)
+    cs, cd, cw = s, d, w
+    for i, k in enumerate([2000, 9000, 400]):
+        bs, bd, bw, bo = graphgen.update_batch(n, cs, cd, k, 7100 + i)
+        # extra arcs into the hub so the diff level holds a long row too
+        lo = 13000 + 600 * i
+        extra_s = np.arange(lo, lo + 500, dtype=np.int32)
+        bs = np.concatenate([bs, extra_s]); bd = np.concatenate([bd, np.zeros(500, np.int32)])
+        bw = np.concatenate([bw, np.full(500, 3, np.int32)]); bo = np.concatenate([bo, np.ones(500, np.uint8)])
+        G.apply(bs, bd, bw, bo)
+        cs, cd, cw, _ = oracle.apply(n, cs, cd, cw, bs, bd, bw, bo)
+        r, it, conv = q.read()
+        assert conv
+        pr_check(r, n, cs, cd)
+    assert G.info()["diff_entries"] > 0
+    rs, _ = G.pr_static(0.85, PR_TOL, 1000)
+    pr_check(rs, n, cs, cd)
+
+
 def test_pagerank_dangling_and_isolated():
     say("pagerank dangling")
     # 0->1, 1 dangling, 2 isolated, 3->0, 3->1

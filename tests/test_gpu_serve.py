@@ -91,7 +91,10 @@ def test_serve_admission_errors():
     for n, s, d, w in graphs:
         S.add_graph(n, s, d, w)
     n, s, d, w = graphs[0]
-    big = graphgen.update_batch(n, s, d, 20000, 9)
+    # 20,000 insertions (duplicates allowed: the request is refused before it runs)
+    big = (graphgen.uniform_int(9, 0, 20000, 0, n - 1).astype(np.int32),
+           graphgen.uniform_int(10, 0, 20000, 0, n - 1).astype(np.int32),
+           np.ones(20000, np.int32), np.ones(20000, np.uint8))
     with pytest.raises(dg.DGError) as e:
         S.submit(0, dg.TRIANGLES, *big)
     assert e.value.code == dg.DG_EBUDGET
