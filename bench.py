@@ -195,10 +195,12 @@ def run_single(args, kind: str) -> int:
     dbatches = [tuple(torch.from_numpy(np.ascontiguousarray(x)).to(dev) for x in b) for b in batches]
     torch.cuda.synchronize()
 
-    persistent = args.sssp_persistent if args.sssp_persistent >= 0 else (1 if kind == "grid" else 0)
+    persistent = max(args.sssp_persistent, 0)
+    delta = args.sssp_delta if args.sssp_delta >= 0 else (8000 if kind == "grid" else 0)
     cfg = dg.Config()
     cfg.heavy_degree = args.heavy_degree
     cfg.sssp_persistent = persistent
+    cfg.sssp_delta = delta
     cfg.pr_mode = args.pr_mode
     cfg.pr_pull = args.pr_pull
     t = time.perf_counter()
@@ -265,7 +267,8 @@ def run_single(args, kind: str) -> int:
 
     config = {"workload": wl, "vertices": n, "arcs": int(s.size) * (2 if undirected else 1),
               "batch": k, "insert_fraction": 0.5, "parallelism": "1 gpu",
-              "heavy_degree": args.heavy_degree or 512, "sssp_persistent": persistent, "pr_mode": args.pr_mode,
+              "heavy_degree": args.heavy_degree or 512, "sssp_persistent": persistent, "sssp_delta": delta,
+              "pr_mode": args.pr_mode,
               "pr_pull": ["merge-path tiles", "vertex waves"][args.pr_pull]}
     if kind == "tc":
         config.update({"undirected_edges": int(s.size), "batch_fraction": args.pct, "queries": ["triangles"]})
@@ -654,8 +657,10 @@ def main() -> int:
     ap.add_argument("--no-static", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--heavy-degree", type=int, default=0, help="rows longer than this are split (0: library default)")
-    ap.add_argument("--sssp-persistent", type=int, default=-1,
-                    help="1: SSSP on the single-launch work queue, 0: frontier steps (-1: grid 1, else 0)")
+    ap.add_argument("--sssp-persistent", type=int, default=0,
+                    help="1: SSSP on the single-launch work queue, 0: frontier steps")
+    ap.add_argument("--sssp-delta", type=int, default=-1,
+                    help="near-far bucket width of the frontier SSSP (0: plain rounds; -1: grid 8000, else 0)")
     ap.add_argument("--pr-mode", type=int, default=0, help="PageRank form after a batch: 0 auto, 1 local, 2 global")
     ap.add_argument("--pr-pull", type=int, default=0,
                     help="whole-graph PageRank pull: 0 merge-path tiles, 1 per-vertex waves")

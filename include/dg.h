@@ -85,7 +85,12 @@ typedef struct dg_config {
      * tiles (equal rows + entries per workgroup, default), 1 = the per-vertex wave
      * kernel that the affected-set iteration uses.  Same results up to rounding. */
     int32_t pr_pull;
-    int32_t reserved[5];
+    /* Frontier-step SSSP schedule: 0 = plain Bellman-Ford rounds (default);
+     * > 0 = near-far buckets of this width (vertices at distance >= the current
+     * threshold wait in a far pile until the nearer ones settle), which cuts the
+     * re-relaxations of high-diameter graphs such as road networks.  Same result. */
+    int32_t sssp_delta;
+    int32_t reserved[4];
 } dg_config;
 
 /* Per-batch statistics and phase timings (HIP events on the graph's stream). */

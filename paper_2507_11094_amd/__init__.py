@@ -56,7 +56,7 @@ class Config(ctypes.Structure):
     _fields_ = [("merge_threshold", ctypes.c_double), ("pr_tol_scale", ctypes.c_double),
                 ("heavy_degree", ctypes.c_int32), ("persistent_groups", ctypes.c_int32),
                 ("sssp_persistent", ctypes.c_int32), ("pr_mode", ctypes.c_int32),
-                ("pr_pull", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+                ("pr_pull", ctypes.c_int32), ("sssp_delta", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
 
 
 class KernelProf(ctypes.Structure):

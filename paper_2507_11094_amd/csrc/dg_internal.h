@@ -122,6 +122,8 @@ struct Work {
     // frontier machinery shared by the traversals
     DBuf<int32_t> f0, f1, heavy;          // frontiers and heavy-chunk queue
     DBuf<int32_t> stamp;                  // per-vertex dedup stamps
+    DBuf<int32_t> farflag, far0, far1;    // near-far SSSP: far-pile membership stamps and piles
+    int32_t far_ctr = 0;
     int32_t stamp_ctr = 0;
     DBuf<double> part;                    // partial sums of split rows
     DBuf<double> prs;                     // PageRank scalars: step, dangling mass, constant term
@@ -258,6 +260,8 @@ int prof_begin(const char *name, hipStream_t s);
 void prof_end(int slot, hipStream_t s, double bytes);
 // Add bytes to a recorded launch once they are known (after the launch finished).
 void prof_add(int slot, double bytes);
+// Forget a recorded launch (it did no work).
+void prof_drop(int slot);
 
 // triangle counting (tc.hip)
 int tc_count_static(dg_graph *g, uint64_t *count);

@@ -112,6 +112,7 @@ void ws_free(dg_graph *g) {
     w.scan64.release(); w.tscan.release(); w.f0.release(); w.f1.release(); w.heavy.release();
     w.stamp.release(); w.part.release(); w.prs.release();
     w.mp_row.release(); w.mp_edge.release(); w.mp_part.release();
+    w.farflag.release(); w.far0.release(); w.far1.release();
     w.wq.release(); w.wseq.release(); w.wctr.release(); w.inq.release();
     if (w.dcnt) dfree(w.dcnt);
     if (w.hcnt) (void)hipHostFree(w.hcnt);

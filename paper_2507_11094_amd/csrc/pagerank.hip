@@ -36,6 +36,7 @@
 //          can continue locally.
 #include <algorithm>
 #include <cstring>
+#include <vector>
 
 #include "traverse.h"
 
@@ -64,7 +65,9 @@ __global__ void k_pr_init(int32_t n, double *x, double *contrib, const int32_t *
 __global__ __launch_bounds__(256) void k_pr_pull(const int32_t *A, int64_t na, DirView g,
                                                  const double *__restrict__ contrib, const double *cterm,
                                                  double damp, double *xn, int64_t *hq, int64_t *hcount,
-                                                 int64_t *hv, int64_t *hvcount, int heavy_deg, int chunk) {
+                                                 int64_t *hv, int64_t *hvcount, int heavy_deg, int chunk,
+                                                 const double *done) {
+    if (*done != 0.0) return;
     __shared__ double sacc[4][WAVE];
     const double base = *cterm;
     const int wslot = threadIdx.x / WAVE;
@@ -200,7 +203,9 @@ __device__ __forceinline__ void block_sum2(double a, double b, double *out_a, do
 // x := xn, contrib := x / outdeg on A; fixed-order partials of the L1 step and of
 // the new mass on dangling vertices.
 __global__ __launch_bounds__(256) void k_pr_apply(const int32_t *A, int64_t na, const double *xn, double *x,
-                                                  double *contrib, const int32_t *deg, double *partials) {
+                                                  double *contrib, const int32_t *deg, double *partials,
+                                                  const double *done) {
+    if (*done != 0.0) return;
     double acc = 0.0, dang = 0.0;
     for (int64_t i = gtid(); i < na; i += gstride()) {
         int32_t v = A ? A[i] : (int32_t)i;
@@ -215,10 +220,13 @@ __global__ __launch_bounds__(256) void k_pr_apply(const int32_t *A, int64_t na, 
 }
 
 // prs[0] = L1 step, prs[1] = dangling mass, prs[2] = constant term of the next
-// step (global form: ((1-d) S + d D) / n; local form: (1-d) / n).  The step is
-// also copied to *step_out for the host.
+// step (global form: ((1-d) S + d D) / n; local form: (1-d) / n), prs[3] = 1 once
+// the step is <= tol (every later kernel of the iteration then returns at once),
+// prs[4] = steps taken.  first = 1: the set-up call before the first step (resets
+// prs[3], prs[4]).  The step is also copied to *step_out.
 __global__ void k_pr_reduce(const double *partials, int np, int global, double S, double damp,
-                            double ninv, double *prs, double *step_out) {
+                            double ninv, double tol, int first, double *prs, double *step_out) {
+    if (!first && prs[3] != 0.0) return;
     double a = 0.0, b = 0.0;
     for (int i = threadIdx.x; i < np; i += blockDim.x) {
         a += partials[2 * i];
@@ -228,6 +236,13 @@ __global__ void k_pr_reduce(const double *partials, int np, int global, double S
     if (threadIdx.x == 0) {
         prs[2] = global ? ((1.0 - damp) * S + damp * prs[1]) * ninv : (1.0 - damp) * ninv;
         *step_out = prs[0];
+        if (first) {
+            prs[3] = 0.0;
+            prs[4] = 0.0;
+        } else {
+            prs[4] += 1.0;
+            if (prs[0] <= tol) prs[3] = 1.0;
+        }
     }
 }
 
@@ -383,7 +398,9 @@ __global__ __launch_bounds__(MP_THREADS) void k_pr_tiles(const int32_t *__restri
                                                          const int64_t *__restrict__ off,
                                                          const int32_t *__restrict__ col,
                                                          const double *__restrict__ contrib, const double *cterm,
-                                                         double damp, double *xn, double *pf, double *pl) {
+                                                         double damp, double *xn, double *pf, double *pl,
+                                                         const double *done) {
+    if (*done != 0.0) return;
     __shared__ double s_val[MP_ITEMS];
     __shared__ int32_t s_off[MP_ITEMS + 1];
     __shared__ int32_t s_long[MP_ITEMS / MP_LONG + 2];
@@ -457,7 +474,8 @@ __global__ __launch_bounds__(MP_THREADS) void k_pr_tiles(const int32_t *__restri
 // tiles before (pl, in tile order) plus the closing piece (pf[b]).
 __global__ void k_pr_fixup(int64_t nb, const int32_t *__restrict__ mp_row, const int64_t *__restrict__ mp_edge,
                            const int64_t *__restrict__ off, const double *pf, const double *pl,
-                           const double *cterm, double damp, double *xn) {
+                           const double *cterm, double damp, double *xn, const double *done) {
+    if (*done != 0.0) return;
     const double base = *cterm;
     for (int64_t b = gtid(); b < nb; b += gstride()) {
         const int32_t R = mp_row[b];
@@ -474,7 +492,9 @@ __global__ void k_pr_fixup(int64_t nb, const int32_t *__restrict__ mp_row, const
 // Diff-level entries: the first entry of each row's run adds the run's live
 // contributions, in key order.
 __global__ void k_pr_diff_add(int64_t dm, const uint64_t *__restrict__ dkey, const int32_t *__restrict__ dcol,
-                              int keybits, const double *__restrict__ contrib, double damp, double *xn) {
+                              int keybits, const double *__restrict__ contrib, double damp, double *xn,
+                              const double *done) {
+    if (*done != 0.0) return;
     for (int64_t j = gtid(); j < dm; j += gstride()) {
         const int32_t r = (int32_t)(dkey[j] >> keybits);
         if (j > 0 && (int32_t)(dkey[j - 1] >> keybits) == r) continue;
@@ -538,7 +558,7 @@ static int pr_iterate(dg_graph *g, const int32_t *A, int64_t na, int64_t edges, 
     else
         hipLaunchKernelGGL(k_sum_vec2, dim3(1), dim3(256), 0, s, x, g->fwd.deg.p, (int64_t)0, partials);
     hipLaunchKernelGGL(k_pr_reduce, dim3(1), dim3(256), 0, s, partials, global ? APPLY_GROUPS : 1,
-                       (int)global, S, damping, ninv, prs, step_out);
+                       (int)global, S, damping, ninv, tol, 1, prs, step_out);
     DG_HIP(hipGetLastError());
     // every vertex pulled: merge-path tiles over the base level, then the diff level
     const Dir &R = *g->rev;
@@ -554,45 +574,65 @@ static int pr_iterate(dg_graph *g, const int32_t *A, int64_t na, int64_t edges, 
         DG_HIP(hipGetLastError());
     }
     double *pf = ws.mp_part.p, *pl = ws.mp_part.p + nb + 1;
-    int32_t it = 0;
+    const double *done = prs + 3;
+    // Steps are launched in groups without a host round trip; the convergence
+    // test runs on the device (k_pr_reduce), and once it passes the remaining
+    // launches of the group return at once.  The host reads the flag per group.
+    constexpr int GROUP = 4;
+    int32_t it = 0, launched = 0;
     *conv = 0;
-    while (it < max_iter && na > 0) {
-        DG_TRY(counters_clear(g));
-        if (tiles) {
-            // tiles: off 8 + xn 8 per row, col 4 + contrib 8 per base entry
-            int ps = prof_begin("pr_tiles", s);
-            hipLaunchKernelGGL(k_pr_tiles, dim3((unsigned)nb), dim3(MP_THREADS), 0, s, ws.mp_row.p, ws.mp_edge.p,
-                               R.off.p, R.col.p, contrib, prs + 2, damping, xn, pf, pl);
-            prof_end(ps, s, 16.0 * (double)g->n + 12.0 * (double)R.m);
-            hipLaunchKernelGGL(k_pr_fixup, dim3(grid_for(nb)), dim3(256), 0, s, nb, ws.mp_row.p, ws.mp_edge.p,
-                               R.off.p, pf, pl, prs + 2, damping, xn);
-            if (R.dm > 0)
-                hipLaunchKernelGGL(k_pr_diff_add, dim3(grid_for(R.dm)), dim3(256), 0, s, R.dm, R.dkey.p, R.dcol.p,
-                                   R.keybits, contrib, damping, xn);
-        } else {
-            int64_t blocks = std::min<int64_t>((na + 255) / 256, 65535);
-            int ps = prof_begin("pr_pull", s);
-            hipLaunchKernelGGL(k_pr_pull, dim3((unsigned)blocks), dim3(256), 0, s, A, na, rv, contrib, prs + 2,
-                               damping, xn, hq, ws.dcnt + C_HEAVY, hv, ws.dcnt + C_AUX3, heavy_deg(g),
-                               heavy_deg(g));
-            prof_end(ps, s, 28.0 * (double)na + 12.0 * (double)edges);
-            hipLaunchKernelGGL(k_pr_heavy, dim3(8192), dim3(256), 0, s, rv, contrib, hq, ws.dcnt + C_HEAVY,
-                               heavy_deg(g), ws.part.p);
-            hipLaunchKernelGGL(k_pr_finish, dim3(64), dim3(256), 0, s, hv, ws.dcnt + C_AUX3, ws.part.p, prs + 2,
-                               damping, xn);
+    std::vector<std::pair<int, int>> slots;  // profiled launches of the group (pull, apply)
+    while (launched < max_iter && na > 0) {
+        const int grp = std::min(GROUP, max_iter - launched);
+        slots.clear();
+        for (int j = 0; j < grp; ++j) {
+            DG_TRY(counters_clear(g));
+            int ps;
+            if (tiles) {
+                // tiles: off 8 + xn 8 per row, col 4 + contrib 8 per base entry
+                ps = prof_begin("pr_tiles", s);
+                hipLaunchKernelGGL(k_pr_tiles, dim3((unsigned)nb), dim3(MP_THREADS), 0, s, ws.mp_row.p,
+                                   ws.mp_edge.p, R.off.p, R.col.p, contrib, prs + 2, damping, xn, pf, pl, done);
+                prof_end(ps, s, 16.0 * (double)g->n + 12.0 * (double)R.m);
+                hipLaunchKernelGGL(k_pr_fixup, dim3(grid_for(nb)), dim3(256), 0, s, nb, ws.mp_row.p,
+                                   ws.mp_edge.p, R.off.p, pf, pl, prs + 2, damping, xn, done);
+                if (R.dm > 0)
+                    hipLaunchKernelGGL(k_pr_diff_add, dim3(grid_for(R.dm)), dim3(256), 0, s, R.dm, R.dkey.p,
+                                       R.dcol.p, R.keybits, contrib, damping, xn, done);
+            } else {
+                int64_t blocks = std::min<int64_t>((na + 255) / 256, 65535);
+                ps = prof_begin("pr_pull", s);
+                hipLaunchKernelGGL(k_pr_pull, dim3((unsigned)blocks), dim3(256), 0, s, A, na, rv, contrib,
+                                   prs + 2, damping, xn, hq, ws.dcnt + C_HEAVY, hv, ws.dcnt + C_AUX3,
+                                   heavy_deg(g), heavy_deg(g), done);
+                prof_end(ps, s, 28.0 * (double)na + 12.0 * (double)edges);
+                hipLaunchKernelGGL(k_pr_heavy, dim3(8192), dim3(256), 0, s, rv, contrib, hq, ws.dcnt + C_HEAVY,
+                                   heavy_deg(g), ws.part.p);
+                hipLaunchKernelGGL(k_pr_finish, dim3(64), dim3(256), 0, s, hv, ws.dcnt + C_AUX3, ws.part.p,
+                                   prs + 2, damping, xn);
+            }
+            int pa = prof_begin("pr_apply", s);
+            hipLaunchKernelGGL(k_pr_apply, dim3(APPLY_GROUPS), dim3(256), 0, s, A, na, xn, x, contrib,
+                               g->fwd.deg.p, partials, done);
+            prof_end(pa, s, 40.0 * (double)na);
+            hipLaunchKernelGGL(k_pr_reduce, dim3(1), dim3(256), 0, s, partials, APPLY_GROUPS, (int)global, S,
+                               damping, ninv, tol, 0, prs, step_out);
+            DG_HIP(hipGetLastError());
+            slots.emplace_back(ps, pa);
         }
-        int pa = prof_begin("pr_apply", s);
-        hipLaunchKernelGGL(k_pr_apply, dim3(APPLY_GROUPS), dim3(256), 0, s, A, na, xn, x, contrib,
-                           g->fwd.deg.p, partials);
-        prof_end(pa, s, 40.0 * (double)na);
-        hipLaunchKernelGGL(k_pr_reduce, dim3(1), dim3(256), 0, s, partials, APPLY_GROUPS, (int)global, S,
-                           damping, ninv, prs, step_out);
-        DG_HIP(hipGetLastError());
-        DG_TRY(counters_read(g));
-        ++it;
-        double diff;
-        std::memcpy(&diff, &ws.hcnt[C_RED0], sizeof(double));
-        if (diff <= tol) {
+        launched += grp;
+        double hp[5];
+        DG_HIP(hipMemcpyAsync(ws.hcnt + 32, prs, sizeof(hp), hipMemcpyDeviceToHost, s));
+        DG_HIP(hipStreamSynchronize(s));
+        std::memcpy(hp, ws.hcnt + 32, sizeof(hp));
+        const int32_t total = (int32_t)hp[4];
+        // launches after convergence did no work: keep them out of the timings
+        for (int j = total - it; j < (int)slots.size(); ++j) {
+            prof_drop(slots[j].first);
+            prof_drop(slots[j].second);
+        }
+        it = total;
+        if (hp[3] != 0.0) {
             *conv = 1;
             break;
         }
@@ -748,7 +788,7 @@ int pr_post_update(dg_query *q, int64_t adel, int64_t ains, dg_batch_stats *st) 
         hipLaunchKernelGGL(k_sum_vec2, dim3(APPLY_GROUPS), dim3(256), 0, s, q->x.p, g->fwd.deg.p,
                            (int64_t)g->n, partials);
         hipLaunchKernelGGL(k_pr_reduce, dim3(1), dim3(256), 0, s, partials, APPLY_GROUPS, 0, 0.0, q->damping,
-                           1.0, ws.prs.p, reinterpret_cast<double *>(ws.dcnt + C_RED0));
+                           1.0, 0.0, 1, ws.prs.p, reinterpret_cast<double *>(ws.dcnt + C_RED0));
         DG_HIP(hipGetLastError());
         double Ssum;
         DG_HIP(hipMemcpyAsync(&Ssum, ws.prs.p, sizeof(double), hipMemcpyDeviceToHost, s));

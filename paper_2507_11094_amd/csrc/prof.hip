@@ -96,6 +96,20 @@ void prof_end(int slot, hipStream_t s, double bytes) {
     p->bytes += bytes;
 }
 
+void prof_drop(int slot) {
+    if (slot < 0) return;
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (size_t i = g_pending.size(); i-- > 0;) {
+        if (g_pending[i].id != slot) continue;
+        // the events may still be pending on the stream: wait before reuse
+        (void)hipEventSynchronize(g_pending[i].b);
+        g_pool.push_back(g_pending[i].a);
+        g_pool.push_back(g_pending[i].b);
+        g_pending.erase(g_pending.begin() + (std::ptrdiff_t)i);
+        return;
+    }
+}
+
 void prof_add(int slot, double bytes) {
     if (slot < 0) return;
     std::lock_guard<std::mutex> lk(g_mu);

@@ -23,6 +23,8 @@
 // Bellman-Ford from every vertex that could violate d[v] <= d[u] + w, and the fixed
 // point of a Bellman-Ford started from achievable upper bounds and all possibly
 // violated edges is the exact distance (Section 3.1: only the affected part moves).
+#include <algorithm>
+
 #include "traverse.h"
 
 namespace dg {
@@ -196,8 +198,147 @@ static ExpandArgs make_args(dg_graph *g, const Dir &d, const int32_t *F, int64_t
     return a;
 }
 
+// ---- near-far schedule --------------------------------------------------------------
+// The push relaxes in Bellman-Ford rounds; on high-diameter graphs with spread
+// weights (road networks) a vertex is improved many times before its distance
+// settles.  The near-far schedule (Davidson, Baxter, Garland and Owens, IPDPS
+// 2014; a two-bucket form of Meyer and Sanders' delta-stepping) relaxes only the
+// improved vertices below a threshold T; the others wait in a far pile (each
+// vertex at most once, marked by a per-call stamp).  When the near side is empty,
+// T moves to (smallest live far distance) + delta and the far pile is split again.
+// Far entries below the previous T were relaxed when they dropped below it, so
+// they are stale and leave the pile.  Only the order of relaxations changes; the
+// fixed point is the same.
+
+// Improved vertices (count on the device) -> near (dist < T) or the far pile.
+__global__ void k_nf_split(const int64_t *nn_p, const int32_t *N, const uint64_t *key, int32_t T, int32_t *near,
+                           int64_t *nnear, int32_t *far, int64_t *nfar, int32_t *farflag, int32_t fst) {
+    const int64_t nn = *nn_p;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < nn; base += gstride()) {
+        const int64_t i = base + threadIdx.x;
+        bool pn = false, pf = false;
+        int32_t v = 0;
+        if (i < nn) {
+            v = N[i];
+            pn = sssp_dist(key[v]) < T;
+            pf = !pn && atomicExch(&farflag[v], fst) != fst;
+        }
+        const int64_t sn = wave_append(nnear, pn);
+        if (pn) near[sn] = v;
+        const int64_t sf = wave_append(nfar, pf);
+        if (pf) far[sf] = v;
+    }
+}
+
+// Smallest distance >= T in the far pile, as INF - d through a max (0: none).
+__global__ void k_nf_min(int64_t nf, const int32_t *far, const uint64_t *key, int32_t T, int64_t *out) {
+    int64_t best = 0;
+    for (int64_t i = gtid(); i < nf; i += gstride()) {
+        const int32_t d = sssp_dist(key[far[i]]);
+        if (d >= T && d < INF) best = max(best, (int64_t)(INF - d));
+    }
+    best = wave_max_i32((int32_t)best);
+    if (lane_id() == 0 && best > 0) atomicMax((unsigned long long *)out, (unsigned long long)best);
+}
+
+// Next bucket: entries in [T0, T1) go near, entries >= T1 stay, the rest are stale.
+__global__ void k_nf_refill(int64_t nf, const int32_t *far, const uint64_t *key, int32_t T0, int32_t T1,
+                            int32_t *near, int64_t *nnear, int32_t *far2, int64_t *nfar2, int32_t *farflag) {
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < nf; base += gstride()) {
+        const int64_t i = base + threadIdx.x;
+        bool pn = false, pk = false;
+        int32_t v = 0;
+        if (i < nf) {
+            v = far[i];
+            const int32_t d = sssp_dist(key[v]);
+            pk = d >= T1;
+            pn = !pk && d >= T0;
+            if (!pk) farflag[v] = 0;
+        }
+        const int64_t sn = wave_append(nnear, pn);
+        if (pn) near[sn] = v;
+        const int64_t sk = wave_append(nfar2, pk);
+        if (pk) far2[sk] = v;
+    }
+}
+
+__global__ void k_nf_seed_min(int64_t nf, const int32_t *F, const uint64_t *key, int64_t *out) {
+    int64_t best = 0;
+    for (int64_t i = gtid(); i < nf; i += gstride()) {
+        const int32_t d = sssp_dist(key[F[i]]);
+        if (d < INF) best = max(best, (int64_t)(INF - d));
+    }
+    best = wave_max_i32((int32_t)best);
+    if (lane_id() == 0 && best > 0) atomicMax((unsigned long long *)out, (unsigned long long)best);
+}
+
+static int sssp_push_nearfar(dg_graph *g, uint64_t *key, int64_t nf, int32_t delta, dg_batch_stats *st) {
+    hipStream_t s = g->stream;
+    Work &ws = g->ws;
+    const size_t cap = (size_t)g->n + 1;
+    if (!ws.farflag.p || ws.farflag.cap < cap || ws.far_ctr >= INT32_MAX - 4) {
+        DG_TRY(ws.farflag.ensure(cap));
+        DG_TRY(fill_i32(ws.farflag.p, 0, (int64_t)cap, s));
+        ws.far_ctr = 0;
+    }
+    DG_TRY(ws.far0.ensure(cap));
+    DG_TRY(ws.far1.ensure(cap));
+    const int32_t fst = ++ws.far_ctr;
+    int32_t *A = ws.f0.p, *B = ws.f1.p, *far = ws.far0.p, *far2 = ws.far1.p;
+    // first threshold: nearest seed + delta (every seed is relaxed in the first round)
+    DG_TRY(counters_clear(g));
+    hipLaunchKernelGGL(k_nf_seed_min, dim3(grid_for(nf)), dim3(256), 0, s, nf, A, key, ws.dcnt + C_AUX2);
+    DG_HIP(hipGetLastError());
+    DG_TRY(counters_read(g));
+    if (ws.hcnt[C_AUX2] == 0) return DG_OK;
+    int32_t T = (int32_t)std::min<int64_t>((int64_t)(INF - ws.hcnt[C_AUX2]) + delta, INF);
+    int64_t nnear = nf, nfar = 0;
+    int steps = 0;
+    int64_t relaxed = 0;
+    for (;;) {
+        while (nnear > 0) {
+            int32_t stv;
+            DG_TRY(next_stamp(g, &stv));
+            DG_TRY(counters_clear(g));
+            RelaxOp op{key, ws.stamp.p, stv, B, ws.dcnt + C_F1};
+            DG_TRY(launch_expand(s, make_args(g, g->fwd, A, nnear), op, 8192));
+            hipLaunchKernelGGL(k_nf_split, dim3(4096), dim3(256), 0, s, ws.dcnt + C_F1, B, key, T, A,
+                               ws.dcnt + C_F0, far + nfar, ws.dcnt + C_AUX1, ws.farflag.p, fst);
+            DG_HIP(hipGetLastError());
+            DG_TRY(counters_read(g));
+            relaxed += nnear;
+            nnear = ws.hcnt[C_F0];
+            nfar += ws.hcnt[C_AUX1];
+            ++steps;
+        }
+        if (nfar == 0) break;
+        DG_TRY(counters_clear(g));
+        hipLaunchKernelGGL(k_nf_min, dim3(grid_for(nfar)), dim3(256), 0, s, nfar, far, key, T, ws.dcnt + C_AUX2);
+        DG_HIP(hipGetLastError());
+        DG_TRY(counters_read(g));
+        const int64_t best = ws.hcnt[C_AUX2];
+        const int32_t T1 = best == 0 ? INF : (int32_t)std::min<int64_t>((int64_t)(INF - best) + delta, INF);
+        DG_TRY(counters_clear(g));
+        hipLaunchKernelGGL(k_nf_refill, dim3(grid_for(nfar)), dim3(256), 0, s, nfar, far, key, T, T1, A,
+                           ws.dcnt + C_F0, far2, ws.dcnt + C_AUX1, ws.farflag.p);
+        DG_HIP(hipGetLastError());
+        DG_TRY(counters_read(g));
+        nnear = ws.hcnt[C_F0];
+        nfar = ws.hcnt[C_AUX1];
+        std::swap(far, far2);
+        T = T1;
+        if (best == 0) break;  // the pile held only stale entries (now cleared)
+    }
+    if (st) {
+        st->sssp_steps += steps;
+        st->sssp_relaxed += relaxed;
+    }
+    return DG_OK;
+}
+
 // Push relaxation from frontier f0 (nf vertices) until no distance drops.
 static int sssp_push(dg_graph *g, uint64_t *key, int64_t nf, dg_batch_stats *st) {
+    if (g->cfg.sssp_delta > 0 && nf > 0) return sssp_push_nearfar(g, key, nf, g->cfg.sssp_delta, st);
     hipStream_t s = g->stream;
     Work &ws = g->ws;
     int32_t *F = ws.f0.p, *N = ws.f1.p;

@@ -33,7 +33,7 @@ enum { WQ_HEAD = 0, WQ_TAIL = 1, WQ_DONE = 2, WQ_ERR = 3, WQ_LIST = 4, WQ_NCTR =
 // examined and items processed by the cut and push kernels.
 enum { WT_LIST = WQ_NCTR, WT_EDGES = WQ_NCTR + 1, WT_ITEMS = WQ_NCTR + 2, WT_N = 3 };
 constexpr uint32_t WHOLE = 0xFFFFFFFFu;
-constexpr int64_t SPIN_LIMIT = 1ll << 24;  // ~ seconds of s_sleep(1) polling
+constexpr int64_t SPIN_LIMIT = 1ll << 22;  // a few seconds of polling (a legitimate wait is microseconds)
 
 struct WorkQ {
     int64_t *q;
@@ -41,6 +41,7 @@ struct WorkQ {
     int64_t cap;
     int64_t margin;           // claimed-but-unread items at most (64 per wave of the grid)
     unsigned long long *ctr;  // WQ_* counters
+    unsigned long long budget;  // items one run may claim in total (bounds pathological schedules)
 };
 
 __device__ __forceinline__ unsigned long long ld_acq(unsigned long long *p) {
@@ -79,6 +80,7 @@ __device__ __forceinline__ bool wq_claim(const WorkQ &wq, unsigned long long &h,
             if (ld_acq(&wq.ctr[WQ_ERR])) { ex = 1; break; }
             unsigned long long a = ld_acq(&wq.ctr[WQ_HEAD]);
             unsigned long long t = ld_acq(&wq.ctr[WQ_TAIL]);
+            if (a >= wq.budget) { atomicOr(&wq.ctr[WQ_ERR], 8ull); ex = 1; break; }
             if (a < t) {
                 unsigned long long take = t - a < 64 ? t - a : 64;
                 if (atomicCAS(&wq.ctr[WQ_HEAD], a, a + take) == a) {
@@ -417,6 +419,9 @@ static int wl_ensure(dg_graph *g, WorkQ *wq) {
     wq->cap = (int64_t)std::min(ws.wq.cap, ws.wseq.cap);
     wq->margin = 64ll * 4 * wl_groups(g) + 1024;
     wq->ctr = reinterpret_cast<unsigned long long *>(ws.wctr.p);
+    // FIFO relaxation on high-diameter graphs can re-relax each vertex ~sqrt(n)
+    // times; past 16 items per vertex and arc the run stops with an error instead
+    wq->budget = 16ull * (unsigned long long)(g->n + edges) + (1ull << 20);
     return DG_OK;
 }
 
@@ -452,6 +457,9 @@ static int wl_check(dg_graph *g, const WorkQ &wq, int64_t *list_count) {
     unsigned long long h[WQ_NCTR];
     DG_HIP(hipMemcpyAsync(h, wq.ctr, sizeof(h), hipMemcpyDeviceToHost, g->stream));
     DG_HIP(hipStreamSynchronize(g->stream));
+    if (h[WQ_ERR] & 8)
+        return set_error(DG_EDEVICE, "work queue passed its work bound (high-diameter graph: use the frontier "
+                                     "schedule with near-far buckets, sssp_persistent = 0, sssp_delta > 0)");
     if (h[WQ_ERR]) return set_error(DG_EDEVICE, "work queue error %llu (capacity or wait limit)", h[WQ_ERR]);
     if (list_count) *list_count = (int64_t)h[WQ_LIST];
     return DG_OK;

@@ -30,12 +30,13 @@ def say(*a):
     sys.stdout.flush()
 
 
-def cfg(merge=0.0, heavy=0, tol_scale=0.0, persistent=0):
+def cfg(merge=0.0, heavy=0, tol_scale=0.0, persistent=0, delta=0):
     c = dg.Config()
     c.merge_threshold = merge
     c.heavy_degree = heavy
     c.pr_tol_scale = tol_scale
     c.sssp_persistent = persistent
+    c.sssp_delta = delta
     return c
 
 
@@ -179,11 +180,11 @@ def test_sssp_c1_dynamic(heavy, persistent):
     assert_tree(n, cs, cd, cw, 0, sd, sp)
 
 
-@pytest.mark.parametrize("persistent", [0, 1])
-def test_sssp_many_batches_with_merges(persistent):
+@pytest.mark.parametrize("persistent,delta", [(0, 0), (1, 0), (0, 15)])
+def test_sssp_many_batches_with_merges(persistent, delta):
     n, s, d, w = rmat_small(12, 8, 33)
-    say("sssp sequence persistent", persistent)
-    G = dg.Graph(n, s, d, w, config=cfg(merge=0.02, persistent=persistent))
+    say("sssp sequence persistent", persistent, "delta", delta)
+    G = dg.Graph(n, s, d, w, config=cfg(merge=0.02, persistent=persistent, delta=delta))
     qs = [G.sssp_attach(0), G.sssp_attach(17)]
     cs, cd, cw = s, d, w
     merges = 0
@@ -208,8 +209,8 @@ def test_sssp_many_batches_with_merges(persistent):
     assert merges >= 2
 
 
-@pytest.mark.parametrize("persistent", [0, 1])
-def test_sssp_grid_and_hub(persistent):
+@pytest.mark.parametrize("persistent,delta", [(0, 0), (1, 0), (0, 1), (0, 700), (0, 6000)])
+def test_sssp_grid_and_hub(persistent, delta):
     """High-diameter grid (many frontier steps) plus a hub above the heavy limit."""
     n, s, d, w = graphgen.grid4(40, 40, 9, 1000)
     hub = 5
@@ -217,9 +218,11 @@ def test_sssp_grid_and_hub(persistent):
     s = np.concatenate([s, np.full(extra.size, hub)]).astype(np.int32)
     d = np.concatenate([d, extra]).astype(np.int32)
     w = np.concatenate([w, np.full(extra.size, 5000)]).astype(np.int32)
-    say("sssp grid+hub persistent", persistent)
-    G = dg.Graph(n, s, d, w, config=cfg(heavy=64, persistent=persistent))
+    say("sssp grid+hub persistent", persistent, "delta", delta)
+    G = dg.Graph(n, s, d, w, config=cfg(heavy=64, persistent=persistent, delta=delta))
     q = G.sssp_attach(0)
+    dist, _ = q.read()
+    assert np.array_equal(dist, oracle.sssp(n, s, d, w, 0))
     cs, cd, cw = s, d, w
     for i in range(6):
         bs, bd, bw, bo = graphgen.update_batch(n, cs, cd, 60, 4000 + i, wmax=1000)
