@@ -74,8 +74,11 @@ typedef struct dg_config {
     int32_t heavy_degree;
     /* Workgroups of the persistent SSSP kernel; 0 = autotuned / built-in. */
     int32_t persistent_groups;
-    /* 1 = run SSSP fixed points with the persistent single-launch kernel,
-     * 0 = one launch per frontier step; default (-1 or 0 field) = automatic. */
+    /* SSSP update schedule: 0 = frontier steps launched one at a time from the
+     * host (default for single graphs); 1 = persistent work-queue kernels (one
+     * launch per phase); 2 = frontier steps with device-side counts, captured once
+     * into hipGraphs and replayed per batch (default for graph sets).  Same
+     * results; the static solve at attach always uses frontier steps unless 1. */
     int32_t sssp_persistent;
     /* PageRank iteration after a batch: 0 = automatic (global dangling-uniform
      * form when the affected set holds >= 20% of the edges, else the local

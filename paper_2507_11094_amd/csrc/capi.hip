@@ -188,13 +188,22 @@ int dg_graph_create(int32_t n, int64_t m, const int32_t *src, const int32_t *dst
     return DG_OK;
 }
 
+// Device and pinned memory of a query, then the query itself.
+static void query_free(dg_query *q) {
+    q->key.release(); q->inval.release(); q->x.release(); q->xn.release(); q->contrib.release();
+    q->qcnt.release(); q->srcs.release(); q->gstamp.release();
+    if (q->hpin) (void)hipHostFree(q->hpin);
+    if (q->own_cache) {
+        graph_cache_clear(q->own_cache);
+        delete q->own_cache;
+    }
+    delete q;
+}
+
 int dg_graph_destroy(dg_graph *g) {
     if (!g) return set_error(DG_EINVAL, "null graph");
     for (dg_query *q : g->queries) {
-        q->key.release(); q->inval.release(); q->x.release(); q->xn.release(); q->contrib.release();
-        q->qcnt.release(); q->srcs.release();
-        if (q->hpin) (void)hipHostFree(q->hpin);
-        delete q;
+        query_free(q);
     }
     g->queries.clear();
     (void)hipStreamSynchronize(g->stream);
@@ -313,10 +322,7 @@ int dg_snapshot_free(dg_snapshot *sn) {
 static int attach(dg_graph *g, dg_query *q, dg_query **out) {
     int rc = q->kind == Q_SSSP ? sssp_init(q) : (q->kind == Q_PR ? pr_init(q) : tc_count_static(g, &q->tc));
     if (rc != DG_OK) {
-        q->key.release(); q->inval.release(); q->x.release(); q->xn.release(); q->contrib.release();
-        q->qcnt.release(); q->srcs.release();
-        if (q->hpin) (void)hipHostFree(q->hpin);
-        delete q;
+        query_free(q);
         return mark_device_error(g, rc);
     }
     g->queries.push_back(q);
@@ -364,10 +370,7 @@ int dg_query_detach(dg_query *q) {
     if (it == g->queries.end()) return set_error(DG_EINVAL, "query not attached");
     g->queries.erase(it);
     (void)hipStreamSynchronize(g->stream);
-    q->key.release(); q->inval.release(); q->x.release(); q->xn.release(); q->contrib.release();
-        q->qcnt.release(); q->srcs.release();
-        if (q->hpin) (void)hipHostFree(q->hpin);
-    delete q;
+    query_free(q);
     return DG_OK;
 }
 

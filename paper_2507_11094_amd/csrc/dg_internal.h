@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <string>
+#include <functional>
 #include <vector>
 
 #include "../../include/dg.h"
@@ -186,7 +187,9 @@ struct dg_query {
     int64_t *hpin = nullptr;  // pinned staging for qcnt
     dg::DBuf<int32_t> srcs;   // device list of sources (multi-source: one per member graph)
     int64_t nsrc = 0;         // 0: single source `source`
-    dg::GraphCache *gcache = nullptr;  // set: replay the update from captured hipGraphs
+    dg::GraphCache *gcache = nullptr;  // replay the update from captured hipGraphs (owned by a set, or own_cache)
+    dg::GraphCache *own_cache = nullptr;
+    dg::DBuf<int32_t> gstamp;  // dedup stamps of the captured frontier rounds (device-side stamp counter)
     // PageRank: unnormalised x of the dangling-dropped system, x/outdeg cache
     double damping = 0.85, tol = 1e-9;
     int32_t max_iter = 1000;
@@ -218,6 +221,7 @@ void ws_free(dg_graph *g);
 void dir_free(Dir &d);
 int next_stamp(dg_graph *g, int32_t *stamp);
 int fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
+int fill_i64(int64_t *p, int64_t v, int64_t n, hipStream_t s);
 int scan_excl(dg_graph *g, const int64_t *in, int64_t *out, int64_t n);  // exclusive prefix sum
 
 // SSSP (sssp.hip)
@@ -242,6 +246,10 @@ int sssp_post_graph(dg_graph *g, GraphCache *cache, uint64_t *key, const int32_t
                     const int64_t *nseeds_dev, int32_t *cut, const int64_t *ains_dev, int64_t *ncut_out,
                     int64_t *edges_out);
 void graph_cache_clear(GraphCache *cache);
+// Launch the hipGraph cached under `sig`, capturing `enqueue` on g->stream first
+// if there is none (enqueue must not allocate or synchronise).
+int graph_replay(dg_graph *g, GraphCache *cache, const std::vector<const void *> &sig,
+                 const std::function<int()> &enqueue);
 int wl_prepare(dg_graph *g);
 int wl_groups(dg_graph *g);
 int sssp_static_multi(dg_graph *g, uint64_t *key, const int32_t *srcs, int64_t ns, dg_batch_stats *st);

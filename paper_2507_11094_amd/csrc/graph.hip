@@ -44,7 +44,7 @@ int fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s) {
     DG_HIP(hipGetLastError());
     return DG_OK;
 }
-static int fill_i64(int64_t *p, int64_t v, int64_t n, hipStream_t s) {
+int fill_i64(int64_t *p, int64_t v, int64_t n, hipStream_t s) {
     if (n <= 0) return DG_OK;
     hipLaunchKernelGGL(k_fill_i64, dim3(grid_for(n)), dim3(256), 0, s, p, v, n);
     DG_HIP(hipGetLastError());

@@ -2,10 +2,11 @@
 //
 // A set keeps its member graphs as ONE device-resident store (the disjoint union,
 // vertex ids offset by per-member bases), so a batch for every member is one
-// batch for the store and all members' shortest paths move together in one
-// persistent work-queue launch (worklist.hip), replayed from a captured hipGraph.
-// Members never share an edge, so each member's result is exactly what it would
-// be alone.
+// batch for the store and all members' shortest paths move together: the cut
+// walk and the push run as frontier rounds captured once into hipGraphs and
+// replayed for every batch (sssp.hip), or, on request (sssp_persistent = 1), as
+// persistent work-queue kernels (worklist.hip).  Members never share an edge, so
+// each member's result is exactly what it would be alone.
 #include <algorithm>
 #include <chrono>
 #include <cstring>
@@ -204,7 +205,7 @@ int dg_set_create(int32_t count, const int32_t *n, const int64_t *m, const int32
     if (rc == DG_OK) rc = stage_into(w, na, (flags & DG_DEVICE_PTRS) != 0, S->stream, hw, &dw);
     dg_config c{};
     if (cfg) c = *cfg;
-    c.sssp_persistent = 1;
+    if (c.sssp_persistent != 1) c.sssp_persistent = 2;  // captured frontier rounds unless the queue is asked for
     if (rc == DG_OK) rc = graph_create_dev((int32_t)nv, na, os, od, dw, &c, S->stream, &S->g);
     hw.release();
     S->ts.release();

@@ -24,6 +24,8 @@
 // point of a Bellman-Ford started from achievable upper bounds and all possibly
 // violated edges is the exact distance (Section 3.1: only the affected part moves).
 #include <algorithm>
+#include <cstring>
+#include <vector>
 
 #include "traverse.h"
 
@@ -416,16 +418,269 @@ int sssp_pre_delete(dg_query *q, int64_t adel) {
     return DG_OK;
 }
 
+// ---- frontier rounds captured in hipGraphs ---------------------------------------------
+// The same four steps as the host-driven path, with every count, frontier length
+// and dedup stamp kept in device memory, so a fixed number of frontier steps can
+// be captured once into a hipGraph and replayed for every batch: the cut walk (up
+// to CUT_LEVELS levels) in one graph, the pull, the seeding and up to PUSH_ROUNDS
+// push rounds in another.  A step whose frontier is empty does nothing, so the
+// graphs fit any batch; if a frontier is still non-empty at the end of a graph the
+// host continues the same steps one launch at a time.  Kernel boundaries are the
+// only grid-wide barriers, and no counter is contended beyond one append per wave.
+enum { R_CA = 8, R_CB, R_LIST, R_PA, R_PB, R_STAMP, R_STEPS, R_END };  // slots of q->qcnt
+constexpr int CUT_LEVELS = 8, PUSH_ROUNDS = 16;
+static_assert(R_END <= 16, "round counters must fit the pinned staging block");
+
+// Next step: zero the output count and the heavy-chunk count, advance the stamp,
+// count the step if its input frontier is non-empty.
+__global__ void k_round_prep(int64_t *out_cnt, int64_t *hcount, int64_t *ctr, const int64_t *in_cnt) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        if (out_cnt) *out_cnt = 0;
+        *hcount = 0;
+        ctr[R_STAMP] += 1;
+        if (in_cnt && *in_cnt > 0) ctr[R_STEPS] += 1;
+    }
+}
+
+__global__ void k_rounds_init(int64_t *ctr) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        ctr[R_LIST] = ctr[0];  // the cut list starts with the pre-hook's seeds
+        ctr[R_STEPS] = 0;
+    }
+}
+
+// Cut walk that also appends every cut vertex to the cut list.
+struct CutListOp {
+    uint64_t *key;
+    int32_t *next;
+    int64_t *ncount;
+    int32_t *list;
+    int64_t *lcount;
+    __device__ bool vtx(int32_t, int32_t &pay) const { pay = 0; return true; }
+    __device__ void edge(bool valid, int32_t v, int32_t, int32_t x, int32_t) const {
+        bool cut = false;
+        if (valid) {
+            uint64_t k = key[x];
+            if (sssp_parent(k) == v) {
+                key[x] = sssp_pack(INF, -1);
+                cut = true;
+            }
+        }
+        int64_t slot = wave_append(ncount, cut);
+        if (cut) next[slot] = x;
+        int64_t ls = wave_append(lcount, cut);
+        if (cut) list[ls] = x;
+    }
+};
+
+// RelaxOp with the round's stamp read from device memory.
+struct RelaxOpD {
+    uint64_t *key;
+    int32_t *stamp;
+    const int64_t *stp;
+    int32_t *next;
+    int64_t *ncount;
+    __device__ bool vtx(int32_t v, int32_t &pay) const {
+        int32_t d = sssp_dist(__atomic_load_n(&key[v], __ATOMIC_RELAXED));
+        pay = d;
+        return d < INF;
+    }
+    __device__ void edge(bool valid, int32_t v, int32_t d, int32_t x, int32_t w) const {
+        bool push = false;
+        if (valid) {
+            uint64_t cand = sssp_pack(d + w, v);
+            if (cand < __atomic_load_n(&key[x], __ATOMIC_RELAXED)) {
+                uint64_t old = atomicMin((unsigned long long *)&key[x], (unsigned long long)cand);
+                if (cand < old && sssp_dist(cand) < sssp_dist(old)) {
+                    const int32_t st = (int32_t)*stp;
+                    push = atomicExch(&stamp[x], st) != st;
+                }
+            }
+        }
+        int64_t slot = wave_append(ncount, push);
+        if (push) next[slot] = x;
+    }
+};
+
+__global__ void k_sssp_pulled_d(const int64_t *nc_p, const int32_t *cut, const uint64_t *key, int32_t *stamp,
+                                const int64_t *stp, int32_t *front, int64_t *count) {
+    const int64_t nc = *nc_p;
+    const int32_t st = (int32_t)*stp;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < nc; base += gstride()) {
+        int64_t i = base + threadIdx.x;
+        bool p = false;
+        int32_t v = 0;
+        if (i < nc) {
+            v = cut[i];
+            p = sssp_dist(key[v]) < INF && atomicExch(&stamp[v], st) != st;
+        }
+        int64_t slot = wave_append(count, p);
+        if (p) front[slot] = v;
+    }
+}
+
+__global__ void k_sssp_on_add_d(const int64_t *na_p, const int32_t *aiu, const int32_t *aiv, const int32_t *aiw,
+                                uint64_t *key, int32_t *stamp, const int64_t *stp, int32_t *front, int64_t *count) {
+    const int64_t na = *na_p;
+    const int32_t st = (int32_t)*stp;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < na; base += gstride()) {
+        int64_t i = base + threadIdx.x;
+        bool p = false;
+        int32_t v = 0;
+        if (i < na) {
+            int32_t u = aiu[i];
+            v = aiv[i];
+            int32_t du = sssp_dist(key[u]);
+            if (du < INF) {
+                uint64_t cand = sssp_pack(du + aiw[i], u);
+                uint64_t old = atomicMin((unsigned long long *)&key[v], (unsigned long long)cand);
+                if (cand < old && sssp_dist(cand) < sssp_dist(old)) p = atomicExch(&stamp[v], st) != st;
+            }
+        }
+        int64_t slot = wave_append(count, p);
+        if (p) front[slot] = v;
+    }
+}
+
+static ExpandArgs dev_args(dg_graph *g, const Dir &d, const int32_t *F, const int64_t *nfp) {
+    ExpandArgs a = make_args(g, d, F, 0);
+    a.nfp = nfp;
+    return a;
+}
+
+// Cut level: frontier F (count at *cf) -> N (count at *cn), cut list appended.
+static int cut_level(dg_query *q, const int32_t *F, const int64_t *cf, int32_t *N, int64_t *cn) {
+    dg_graph *g = q->g;
+    int64_t *ctr = q->qcnt.p;
+    hipLaunchKernelGGL(k_round_prep, dim3(1), dim3(64), 0, g->stream, cn, g->ws.dcnt + C_HEAVY, ctr, nullptr);
+    CutListOp op{q->key.p, N, cn, q->inval.p, ctr + R_LIST};
+    return launch_expand(g->stream, dev_args(g, g->fwd, F, cf), op, 1024);
+}
+
+// Push round: frontier F (count at *cf) -> N (count at *cn).
+static int push_round(dg_query *q, const int32_t *F, const int64_t *cf, int32_t *N, int64_t *cn) {
+    dg_graph *g = q->g;
+    int64_t *ctr = q->qcnt.p;
+    hipLaunchKernelGGL(k_round_prep, dim3(1), dim3(64), 0, g->stream, cn, g->ws.dcnt + C_HEAVY, ctr, cf);
+    RelaxOpD op{q->key.p, q->gstamp.p, ctr + R_STAMP, N, cn};
+    return launch_expand(g->stream, dev_args(g, g->fwd, F, cf), op, 1024);
+}
+
+static int rounds_cut_enqueue(dg_query *q) {
+    dg_graph *g = q->g;
+    int64_t *ctr = q->qcnt.p;
+    hipLaunchKernelGGL(k_rounds_init, dim3(1), dim3(64), 0, g->stream, ctr);
+    // level 0 walks the seeds (the head of the cut list); then f0 <-> f1
+    DG_TRY(cut_level(q, q->inval.p, ctr + 0, g->ws.f0.p, ctr + R_CA));
+    for (int l = 1; l < CUT_LEVELS; ++l) {
+        const bool odd = l & 1;
+        DG_TRY(cut_level(q, odd ? g->ws.f0.p : g->ws.f1.p, ctr + (odd ? R_CA : R_CB), odd ? g->ws.f1.p : g->ws.f0.p,
+                         ctr + (odd ? R_CB : R_CA)));
+    }
+    DG_HIP(hipGetLastError());
+    return DG_OK;
+}
+
+static int rounds_push_enqueue(dg_query *q) {
+    dg_graph *g = q->g;
+    Work &ws = g->ws;
+    hipStream_t s = g->stream;
+    int64_t *ctr = q->qcnt.p;
+    // pull once at every cut vertex
+    hipLaunchKernelGGL(k_round_prep, dim3(1), dim3(64), 0, s, nullptr, ws.dcnt + C_HEAVY, ctr, nullptr);
+    DG_TRY(launch_expand(s, dev_args(g, *g->rev, q->inval.p, ctr + R_LIST), PullOp{q->key.p}, 1024));
+    // seeds: pulled cut vertices and improved heads of inserted arcs
+    hipLaunchKernelGGL(k_round_prep, dim3(1), dim3(64), 0, s, ctr + R_PA, ws.dcnt + C_HEAVY, ctr, nullptr);
+    hipLaunchKernelGGL(k_sssp_pulled_d, dim3(1024), dim3(256), 0, s, ctr + R_LIST, q->inval.p, q->key.p,
+                       q->gstamp.p, ctr + R_STAMP, ws.f0.p, ctr + R_PA);
+    hipLaunchKernelGGL(k_sssp_on_add_d, dim3(1024), dim3(256), 0, s, ctr + 1, ws.aiu.p, ws.aiv.p, ws.aiw.p,
+                       q->key.p, q->gstamp.p, ctr + R_STAMP, ws.f0.p, ctr + R_PA);
+    for (int r = 0; r < PUSH_ROUNDS; ++r) {
+        const bool even = (r & 1) == 0;
+        DG_TRY(push_round(q, even ? ws.f0.p : ws.f1.p, ctr + (even ? R_PA : R_PB), even ? ws.f1.p : ws.f0.p,
+                          ctr + (even ? R_PB : R_PA)));
+    }
+    DG_HIP(hipGetLastError());
+    return DG_OK;
+}
+
+static int rounds_read(dg_query *q, int64_t *h) {
+    dg_graph *g = q->g;
+    DG_HIP(hipMemcpyAsync(q->hpin, q->qcnt.p, R_END * sizeof(int64_t), hipMemcpyDeviceToHost, g->stream));
+    DG_HIP(hipStreamSynchronize(g->stream));
+    std::memcpy(h, q->hpin, R_END * sizeof(int64_t));
+    return DG_OK;
+}
+
+static int sssp_post_rounds(dg_query *q, int64_t ains, dg_batch_stats *st) {
+    dg_graph *g = q->g;
+    Work &ws = g->ws;
+    DG_TRY(ensure_frontiers(g));
+    if (!q->hpin) DG_HIP(hipHostMalloc((void **)&q->hpin, 16 * sizeof(int64_t), hipHostMallocDefault));
+    if (!q->gstamp.p || q->gstamp.cap < (size_t)g->n + 1 || q->qcnt.cap < (size_t)R_END) {
+        // stamps and their counter start together (a stamp is never reused)
+        DG_TRY(q->qcnt.ensure(R_END, true, g->stream));
+        DG_TRY(q->gstamp.ensure((size_t)g->n + 1));
+        DG_TRY(fill_i32(q->gstamp.p, 0, g->n + 1, g->stream));
+        DG_TRY(fill_i64(q->qcnt.p + R_STAMP, 0, 1, g->stream));
+    }
+    if (!q->gcache) {
+        q->own_cache = new GraphCache();
+        q->gcache = q->own_cache;
+    }
+    q->hpin[0] = q->nseeds;
+    q->hpin[1] = ains;
+    DG_HIP(hipMemcpyAsync(q->qcnt.p, q->hpin, 2 * sizeof(int64_t), hipMemcpyHostToDevice, g->stream));
+    const Dir &R = *g->rev;
+    std::vector<const void *> sig = {q->key.p, q->inval.p, q->qcnt.p, q->gstamp.p, ws.f0.p, ws.f1.p, ws.heavy.p,
+                                     ws.dcnt, g->fwd.off.p, g->fwd.col.p, g->fwd.w.p, g->fwd.doff.p,
+                                     g->fwd.dcol.p, g->fwd.dw.p, R.off.p, R.col.p, R.w.p, R.doff.p, R.dcol.p, R.dw.p,
+                                     ws.aiu.p, ws.aiv.p, ws.aiw.p,
+                                     reinterpret_cast<const void *>((intptr_t)heavy_deg(g))};
+    int64_t h[R_END];
+    // 1. cut walk
+    sig.push_back("cut");
+    DG_TRY(graph_replay(g, q->gcache, sig, [&]() { return rounds_cut_enqueue(q); }));
+    DG_TRY(rounds_read(q, h));
+    int last = (CUT_LEVELS & 1) ? R_CA : R_CB;  // output count of the last captured level
+    while (h[last] > 0) {
+        const bool from_a = last == R_CA;
+        DG_TRY(cut_level(q, from_a ? ws.f0.p : ws.f1.p, q->qcnt.p + last, from_a ? ws.f1.p : ws.f0.p,
+                         q->qcnt.p + (from_a ? R_CB : R_CA)));
+        last = from_a ? R_CB : R_CA;
+        DG_TRY(rounds_read(q, h));
+    }
+    const int64_t ncut = h[R_LIST];
+    // 2-4. pull, seeds, push rounds
+    sig.back() = "push";
+    DG_TRY(graph_replay(g, q->gcache, sig, [&]() { return rounds_push_enqueue(q); }));
+    DG_TRY(rounds_read(q, h));
+    last = (PUSH_ROUNDS & 1) ? R_PB : R_PA;
+    while (h[last] > 0) {
+        const bool from_a = last == R_PA;
+        DG_TRY(push_round(q, from_a ? ws.f0.p : ws.f1.p, q->qcnt.p + last, from_a ? ws.f1.p : ws.f0.p,
+                          q->qcnt.p + (from_a ? R_PB : R_PA)));
+        last = from_a ? R_PB : R_PA;
+        DG_TRY(rounds_read(q, h));
+    }
+    if (st) {
+        st->sssp_invalidated += ncut;
+        st->sssp_steps += (int32_t)h[R_STEPS];
+    }
+    return DG_OK;
+}
+
 int sssp_post_update(dg_query *q, int64_t adel, int64_t ains, dg_batch_stats *st) {
     (void)adel;
     dg_graph *g = q->g;
     hipStream_t s = g->stream;
     Work &ws = g->ws;
     DG_TRY(ensure_frontiers(g));
+    if (g->cfg.sssp_persistent == 2 && g->cfg.sssp_delta <= 0) return sssp_post_rounds(q, ains, st);
     if (g->cfg.sssp_persistent == 1) {
         // the same four steps on device work queues, without host round trips
         DG_TRY(q->qcnt.ensure(4));
-        if (!q->hpin) DG_HIP(hipHostMalloc((void **)&q->hpin, 4 * sizeof(int64_t), hipHostMallocDefault));
+        if (!q->hpin) DG_HIP(hipHostMalloc((void **)&q->hpin, 16 * sizeof(int64_t), hipHostMallocDefault));
         q->hpin[0] = q->nseeds;
         q->hpin[1] = ains;
         DG_HIP(hipMemcpyAsync(q->qcnt.p, q->hpin, 2 * sizeof(int64_t), hipMemcpyHostToDevice, s));

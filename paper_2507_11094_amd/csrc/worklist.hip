@@ -22,6 +22,8 @@
 // Every wait (empty queue, slot not yet written) checks an error flag and a spin
 // limit, so a wave always leaves the loop.
 #include <algorithm>
+#include <functional>
+#include <vector>
 
 #include "traverse.h"
 
@@ -570,42 +572,54 @@ int sssp_post_persistent(dg_graph *g, uint64_t *key, const int32_t *seeds, const
 // Same work replayed from a captured hipGraph.  The graph bakes pointers in, so it
 // is cached under the set of pointers it uses (the diff level alternates between
 // two buffers, so two graphs cover steady state); a new layout captures again.
-int sssp_post_graph(dg_graph *g, GraphCache *cache, uint64_t *key, const int32_t *seeds,
-                    const int64_t *nseeds_dev, int32_t *cut, const int64_t *ains_dev, int64_t *ncut_out,
-                    int64_t *edges_out) {
-    DG_TRY(wl_prepare(g));
+int graph_replay(dg_graph *g, GraphCache *cache, const std::vector<const void *> &sig,
+                 const std::function<int()> &enqueue) {
     if (!g->stream) return set_error(DG_ESTATE, "graph capture needs a non-null stream");
-    std::vector<const void *> sig = {key, seeds, nseeds_dev, cut, ains_dev, g->fwd.off.p, g->fwd.col.p,
-                                     g->fwd.w.p, g->fwd.doff.p, g->fwd.dcol.p, g->fwd.dw.p, g->rev->off.p,
-                                     g->rev->col.p, g->rev->w.p, g->rev->doff.p, g->rev->dcol.p, g->rev->dw.p,
-                                     g->ws.wq.p, g->ws.wseq.p, g->ws.wctr.p, g->ws.inq.p, g->ws.heavy.p,
-                                     g->ws.dcnt, g->ws.aiu.p, g->ws.aiv.p, g->ws.aiw.p};
-    sig.push_back(reinterpret_cast<const void *>((intptr_t)g->cfg.heavy_degree));
-    sig.push_back(reinterpret_cast<const void *>((intptr_t)g->cfg.persistent_groups));
     hipGraphExec_t exec = nullptr;
     for (auto &e : cache->entries)
         if (e.sig == sig) exec = e.exec;
     if (!exec) {
         hipGraph_t graph = nullptr;
         DG_HIP(hipStreamBeginCapture(g->stream, hipStreamCaptureModeRelaxed));
-        int rc = sssp_post_enqueue(g, key, seeds, nseeds_dev, cut, ains_dev);
+        int rc = enqueue();
         hipError_t e = hipStreamEndCapture(g->stream, &graph);
-        if (rc != DG_OK) return rc;
+        if (rc != DG_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc;
+        }
         if (e != hipSuccess) return set_error(DG_EDEVICE, "stream capture failed: %s", hipGetErrorString(e));
         e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
         if (e != hipSuccess) return set_error(DG_EDEVICE, "graph instantiate failed: %s", hipGetErrorString(e));
-        if (cache->entries.size() >= 4) {
+        if (cache->entries.size() >= 8) {
             (void)hipGraphExecDestroy(cache->entries.front().exec);
             cache->entries.erase(cache->entries.begin());
         }
         cache->entries.push_back({sig, exec});
         cache->captures += 1;
     }
-    int ps = prof_begin("sssp_worklist", g->stream);
     DG_HIP(hipGraphLaunch(exec, g->stream));
-    prof_end(ps, g->stream, 0.0);
     cache->launches += 1;
+    return DG_OK;
+}
+
+// Same work replayed from a captured hipGraph.  The graph bakes pointers in, so it
+// is cached under the set of pointers it uses (the diff level alternates between
+// two buffers, so two graphs cover steady state); a new layout captures again.
+int sssp_post_graph(dg_graph *g, GraphCache *cache, uint64_t *key, const int32_t *seeds,
+                    const int64_t *nseeds_dev, int32_t *cut, const int64_t *ains_dev, int64_t *ncut_out,
+                    int64_t *edges_out) {
+    DG_TRY(wl_prepare(g));
+    std::vector<const void *> sig = {"wl", key, seeds, nseeds_dev, cut, ains_dev, g->fwd.off.p, g->fwd.col.p,
+                                     g->fwd.w.p, g->fwd.doff.p, g->fwd.dcol.p, g->fwd.dw.p, g->rev->off.p,
+                                     g->rev->col.p, g->rev->w.p, g->rev->doff.p, g->rev->dcol.p, g->rev->dw.p,
+                                     g->ws.wq.p, g->ws.wseq.p, g->ws.wctr.p, g->ws.inq.p, g->ws.heavy.p,
+                                     g->ws.dcnt, g->ws.aiu.p, g->ws.aiv.p, g->ws.aiw.p};
+    sig.push_back(reinterpret_cast<const void *>((intptr_t)g->cfg.heavy_degree));
+    sig.push_back(reinterpret_cast<const void *>((intptr_t)g->cfg.persistent_groups));
+    int ps = prof_begin("sssp_worklist", g->stream);
+    DG_TRY(graph_replay(g, cache, sig, [&]() { return sssp_post_enqueue(g, key, seeds, nseeds_dev, cut, ains_dev); }));
+    prof_end(ps, g->stream, 0.0);
     return sssp_post_finish(g, ps, ncut_out, edges_out);
 }
 

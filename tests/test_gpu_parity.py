@@ -161,7 +161,7 @@ def test_build_rejects_bad_edge_lists():
 
 # ------------------------------------------------------------------ SSSP
 
-@pytest.mark.parametrize("heavy,persistent", [(0, 0), (8, 0), (1 << 20, 0), (0, 1), (8, 1)])
+@pytest.mark.parametrize("heavy,persistent", [(0, 0), (8, 0), (1 << 20, 0), (0, 1), (8, 1), (0, 2), (8, 2)])
 def test_sssp_c1_dynamic(heavy, persistent):
     n, s, d, w, (bs, bd, bw, bo) = graphgen.c1_workload()
     say("sssp C1 heavy", heavy, "persistent", persistent)
@@ -180,7 +180,7 @@ def test_sssp_c1_dynamic(heavy, persistent):
     assert_tree(n, cs, cd, cw, 0, sd, sp)
 
 
-@pytest.mark.parametrize("persistent,delta", [(0, 0), (1, 0), (0, 15)])
+@pytest.mark.parametrize("persistent,delta", [(0, 0), (1, 0), (0, 15), (2, 0)])
 def test_sssp_many_batches_with_merges(persistent, delta):
     n, s, d, w = rmat_small(12, 8, 33)
     say("sssp sequence persistent", persistent, "delta", delta)
@@ -209,7 +209,7 @@ def test_sssp_many_batches_with_merges(persistent, delta):
     assert merges >= 2
 
 
-@pytest.mark.parametrize("persistent,delta", [(0, 0), (1, 0), (0, 1), (0, 700), (0, 6000)])
+@pytest.mark.parametrize("persistent,delta", [(0, 0), (1, 0), (0, 1), (0, 700), (0, 6000), (2, 0)])
 def test_sssp_grid_and_hub(persistent, delta):
     """High-diameter grid (many frontier steps) plus a hub above the heavy limit."""
     n, s, d, w = graphgen.grid4(40, 40, 9, 1000)
