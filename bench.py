@@ -342,6 +342,8 @@ def set_members(count: int, seed: int):
         sc = int(scales[i])
         members.append(graphgen.rmat_directed(sc, 16 << sc, graphgen.config_seed(3, i)))
         ks.append(int(frac[i] * (16 << sc)))
+        if (i + 1) % 1024 == 0:
+            log(f"  {i + 1}/{count} members")
     return members, ks
 
 
@@ -475,8 +477,12 @@ def serve_graphs(count: int, seed: int):
     import graphgen
 
     scales = graphgen.uniform_int(graphgen.stream_seed(seed, "scale"), 0, count, 12, 20)
-    return [graphgen.rmat_directed(int(sc), 16 << int(sc), graphgen.config_seed(4, i))
-            for i, sc in enumerate(scales)]
+    out = []
+    for i, sc in enumerate(scales):
+        out.append(graphgen.rmat_directed(int(sc), 16 << int(sc), graphgen.config_seed(4, i)))
+        if (i + 1) % 16 == 0:
+            log(f"  {i + 1}/{count} graphs")
+    return out
 
 
 def serve_requests(graphs, seed: int, rate: float, duration: float):
@@ -510,6 +516,8 @@ def serve_requests(graphs, seed: int, rate: float, duration: float):
             b = graphgen.update_batch(n, s, d, k, graphgen.config_seed(4, 10000 + i), existing=index[g].keys)
             pending_inverse[g] = inverse(b, index[g])
         kind = 0 if qu[i] < 0.4 else (1 if qu[i] < 0.8 else 2)
+        if (i + 1) % 100 == 0:
+            log(f"  {i + 1}/{count} requests drawn")
         reqs.append((float(at[i]), g, kind, int(su[i] * n), b))
     return reqs
 

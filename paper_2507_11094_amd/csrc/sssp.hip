@@ -25,6 +25,7 @@
 // violated edges is the exact distance (Section 3.1: only the affected part moves).
 #include <algorithm>
 #include <cstring>
+#include <functional>
 #include <vector>
 
 #include "traverse.h"
@@ -638,9 +639,13 @@ static int sssp_post_rounds(dg_query *q, int64_t ains, dg_batch_stats *st) {
                                      ws.aiu.p, ws.aiv.p, ws.aiw.p,
                                      reinterpret_cast<const void *>((intptr_t)heavy_deg(g))};
     int64_t h[R_END];
+    // the legacy null stream cannot be captured: launch the same steps directly
+    auto run = [&](const std::function<int()> &enqueue) {
+        return g->stream ? graph_replay(g, q->gcache, sig, enqueue) : enqueue();
+    };
     // 1. cut walk
     sig.push_back("cut");
-    DG_TRY(graph_replay(g, q->gcache, sig, [&]() { return rounds_cut_enqueue(q); }));
+    DG_TRY(run([&]() { return rounds_cut_enqueue(q); }));
     DG_TRY(rounds_read(q, h));
     int last = (CUT_LEVELS & 1) ? R_CA : R_CB;  // output count of the last captured level
     while (h[last] > 0) {
@@ -653,7 +658,7 @@ static int sssp_post_rounds(dg_query *q, int64_t ains, dg_batch_stats *st) {
     const int64_t ncut = h[R_LIST];
     // 2-4. pull, seeds, push rounds
     sig.back() = "push";
-    DG_TRY(graph_replay(g, q->gcache, sig, [&]() { return rounds_push_enqueue(q); }));
+    DG_TRY(run([&]() { return rounds_push_enqueue(q); }));
     DG_TRY(rounds_read(q, h));
     last = (PUSH_ROUNDS & 1) ? R_PB : R_PA;
     while (h[last] > 0) {

@@ -65,21 +65,26 @@ __global__ __launch_bounds__(256) void k_tc_delta(int64_t ne, const int32_t *eu,
                                                   const int32_t *__restrict__ col,
                                                   const int64_t *__restrict__ doff,
                                                   const int32_t *__restrict__ dcol,
-                                                  unsigned long long *sum6) {
+                                                  unsigned long long *sum6, unsigned long long *work) {
     const int64_t wave_global = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / WAVE;
     const int l = lane_id();
-    uint64_t acc = 0;
+    uint64_t acc = 0, walked = 0, probes = 0;
     for (int64_t i = wave_global; i < ne; i += nwaves) {
         int32_t a = eu[i], b = ev[i];
         RowRef ra = row_ref(off, doff, a), rb = row_ref(off, doff, b);
         if (ra.db + ra.dd > rb.db + rb.dd) {
             RowRef t = ra; ra = rb; rb = t;
         }
+        // depth of the binary searches in the larger row (base level, diff level)
+        const int depth = (rb.db > 0 ? 64 - __clzll((unsigned long long)rb.db) : 0) +
+                          (rb.dd > 0 ? 64 - __clzll((unsigned long long)rb.dd) : 0);
         const int64_t tot = ra.db + ra.dd;
         for (int64_t j = l; j < tot; j += WAVE) {
             uint32_t e = j < ra.db ? (uint32_t)col[ra.ob + j] : (uint32_t)dcol[ra.od + (j - ra.db)];
+            ++walked;
             if (e & DEAD) continue;
+            probes += depth;
             uint32_t c = e & ID_MASK;
             uint32_t e2;
             if (!row_find(col, dcol, rb, c, e2)) continue;
@@ -88,7 +93,13 @@ __global__ __launch_bounds__(256) void k_tc_delta(int64_t ne, const int32_t *eu,
         }
     }
     acc = wave_sum(acc);
-    if (l == 0 && acc) atomicAdd(sum6, (unsigned long long)acc);
+    walked = wave_sum(walked);
+    probes = wave_sum(probes);
+    if (l == 0) {
+        if (acc) atomicAdd(sum6, (unsigned long long)acc);
+        atomicAdd(&work[0], (unsigned long long)walked);
+        atomicAdd(&work[1], (unsigned long long)probes);
+    }
 }
 
 int tc_delta(dg_graph *g, const int32_t *eu, const int32_t *ev, int64_t ne, uint64_t *sum6) {
@@ -98,12 +109,18 @@ int tc_delta(dg_graph *g, const int32_t *eu, const int32_t *ev, int64_t ne, uint
     Dir &F = g->fwd;
     DG_TRY(counters_clear(g));
     unsigned long long *acc = reinterpret_cast<unsigned long long *>(g->ws.dcnt + C_TC0);
+    unsigned long long *work = reinterpret_cast<unsigned long long *>(g->ws.dcnt + C_AUX2);
     int64_t blocks = std::min<int64_t>((ne + 3) / 4, 16384);
+    int ps = prof_begin("tc_delta", s);
     hipLaunchKernelGGL(k_tc_delta, dim3((unsigned)blocks), dim3(256), 0, s, ne, eu, ev, F.off.p, F.col.p,
-                       F.doff.p, F.dcol.p, acc);
+                       F.doff.p, F.dcol.p, acc, work);
+    prof_end(ps, s, 0.0);
     DG_HIP(hipGetLastError());
     DG_TRY(counters_read(g));
     *sum6 = (uint64_t)g->ws.hcnt[C_TC0];
+    // per changed edge its endpoints' offsets (32 B); per walked entry 4 B; per
+    // binary-search step 4 B
+    prof_add(ps, 32.0 * (double)ne + 4.0 * (double)g->ws.hcnt[C_AUX2] + 4.0 * (double)g->ws.hcnt[C_AUX3]);
     return DG_OK;
 }
 

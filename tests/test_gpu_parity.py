@@ -233,6 +233,28 @@ def test_sssp_grid_and_hub(persistent, delta):
         assert_tree(n, cs, cd, cw, 0, dist, par)
 
 
+def test_sssp_rounds_captured_on_a_stream():
+    """Frontier rounds captured into hipGraphs (a non-null stream) and replayed for
+    every batch, with the host finishing long walks past the captured depth."""
+    import torch
+
+    n, s, d, w = rmat_small(12, 8, 35)
+    say("sssp captured rounds on a stream")
+    G = dg.Graph(n, s, d, w, config=cfg(persistent=2))
+    stream = torch.cuda.Stream()
+    G.set_stream(stream.cuda_stream)
+    q = G.sssp_attach(0)
+    cs, cd, cw = s, d, w
+    for i in range(8):
+        bs, bd, bw, bo = graphgen.update_batch(n, cs, cd, [40, 900, 5, 3000][i % 4], 5100 + i)
+        G.apply(bs, bd, bw, bo)
+        cs, cd, cw, _ = oracle.apply(n, cs, cd, cw, bs, bd, bw, bo)
+        dist, par = q.read()
+        assert np.array_equal(dist, oracle.sssp(n, cs, cd, cw, 0)), i
+    assert_tree(n, cs, cd, cw, 0, dist, par)
+    torch.cuda.synchronize()
+
+
 def test_sssp_fig_dynsssp_reconstructed():
     g = json.load(open(os.path.join(GOLDEN, "fig_dynsssp.json")))
     say("fig dynsssp")
