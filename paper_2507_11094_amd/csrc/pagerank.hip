@@ -412,12 +412,18 @@ __global__ __launch_bounds__(MP_THREADS) void k_pr_tiles(const int32_t *__restri
     const int32_t nr = r1 - r0;
     const int t = threadIdx.x;
     if (t == 0) s_nlong = 0;
-    // stage the entries: all column loads first, then all gathers (MP_IPT in flight)
+    // stage the entries: all column loads first, the row starts while they are in
+    // flight, then all gathers (MP_IPT in flight per lane)
     uint32_t c[MP_IPT];
 #pragma unroll
     for (int u = 0; u < MP_IPT; ++u) {
         const int j = t + u * MP_THREADS;
         c[u] = j < ne ? (uint32_t)col[e0 + j] : DEAD;
+    }
+    // row starts relative to the tile (-1: the row began in an earlier tile)
+    for (int i = t; i <= nr; i += MP_THREADS) {
+        const int64_t o = off[r0 + i] - e0;
+        s_off[i] = (int32_t)(o < 0 ? -1 : o);
     }
     double v[MP_IPT];
 #pragma unroll
@@ -426,11 +432,6 @@ __global__ __launch_bounds__(MP_THREADS) void k_pr_tiles(const int32_t *__restri
     for (int u = 0; u < MP_IPT; ++u) {
         const int j = t + u * MP_THREADS;
         if (j < ne) s_val[j] = v[u];
-    }
-    // row starts relative to the tile (-1: the row began in an earlier tile)
-    for (int i = t; i <= nr; i += MP_THREADS) {
-        const int64_t o = off[r0 + i] - e0;
-        s_off[i] = (int32_t)(o < 0 ? -1 : o);
     }
     __syncthreads();
     const double base = *cterm;
