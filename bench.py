@@ -49,10 +49,15 @@ CSRC = os.path.join(ROOT, "paper_2507_11094_amd", "csrc")
 
 # HBM bytes per launch read from rocprofv3 FETCH_SIZE / WRITE_SIZE (KiB per
 # dispatch) for the named kernel and workload, divided by what the same counters
-# read per byte of a plain device copy (FETCH 2.0, WRITE 1.0).  Each entry holds
+# read per byte of a plain 256 MiB device copy (FETCH_SIZE 0.5, WRITE_SIZE 1.0
+# counted bytes per byte moved).  Each entry holds
 # the SHA-1 of the kernel's source file at the time the counters were taken; a
 # changed source makes the figure stale and it is reported as null.
-MEASURED_TRAFFIC: dict = {}
+MEASURED_TRAFFIC: dict = {
+    ("k_pr_tiles", "rmat22-dynamic-sssp+pagerank"): {
+        "source": "pagerank.hip", "sha1": "7d259e2ae10ee64aac09752080eea907292cfec1",
+        "fetch_kib": 993906.2, "write_kib": 34740.9, "fetch_factor": 0.5, "write_factor": 1.0},
+}
 
 # Serving objective stated up front: 99th percentile latency (submit -> result
 # on the host) at the default arrival rate.

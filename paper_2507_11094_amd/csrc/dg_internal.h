@@ -27,7 +27,7 @@ constexpr uint32_t ID_MASK = 0x3FFFFFFFu;
 constexpr uint32_t MARK = 0x40000000u;
 constexpr uint32_t DEAD = 0x80000000u;
 constexpr int32_t INF = DG_INF;
-constexpr int TILE = 2048;  // base entries per merge tile (tombstone counters per tile)
+constexpr int TILE = 256;   // base entries per tombstone counter block (ttomb)
 
 // ---- errors ------------------------------------------------------------------------
 int set_error(int code, const char *fmt, ...);

@@ -262,94 +262,145 @@ __global__ void k_deg_to_i64(int32_t n, const int32_t *deg, int64_t *out) {
     for (int64_t i = gtid(); i <= n; i += gstride()) out[i] = i < n ? deg[i] : 0;
 }
 
-// Tile-parallel merge of one direction: every workgroup streams TILE consecutive
-// base entries (4 waves x 8 x 64, coalesced), drops tombstones and interleaves
-// the diff entries of the rows it touches.  Output positions come from
-//   off2[r] + (live base entries of row r before i) + (diff entries of r below col)
-// where the live count uses tombstone prefix counts that the delete step keeps per
-// row (RB = scan of ntomb) and per tile (TS = scan of ttomb), so no extra pass over
-// the base arrays is needed.
-__global__ __launch_bounds__(256) void k_merge_base(
-    int32_t n, int64_t m, const int64_t *__restrict__ off, const int32_t *__restrict__ col,
-    const int32_t *__restrict__ w, const int64_t *__restrict__ doff, const int32_t *__restrict__ dcol,
-    const int32_t *__restrict__ dw, const int64_t *__restrict__ off2, const int64_t *__restrict__ RB,
-    const int64_t *__restrict__ TS, int32_t *__restrict__ col2, int32_t *__restrict__ w2, int64_t cap,
-    int64_t *cnt) {
-    constexpr int PER_WAVE = TILE / 4;
-    constexpr int IT = PER_WAVE / WAVE;
-    __shared__ int64_t wdead[4];
-    const int t = blockIdx.x;
-    const int wv = threadIdx.x / WAVE;
-    const int l = lane_id();
-    const int64_t e0 = (int64_t)t * TILE;
-    const int64_t wbase = e0 + (int64_t)wv * PER_WAVE;
-    int32_t c[IT];
-    uint64_t deadm[IT];
-    int ndead = 0;
-#pragma unroll
-    for (int it = 0; it < IT; ++it) {
-        int64_t i = wbase + it * WAVE + l;
-        bool valid = i < m;
-        c[it] = valid ? col[i] : 0;
-        deadm[it] = ballot(valid && ((uint32_t)c[it] & DEAD));
-        ndead += __popcll(deadm[it]);
-    }
-    if (l == 0) wdead[wv] = ndead;
-    __syncthreads();
-    if (wbase >= m) return;
-    int64_t tb = TS[t];
-    for (int j = 0; j < wv; ++j) tb += wdead[j];
-    const int64_t wlast = min(wbase + PER_WAVE - 1, m - 1);
-    const int32_t r_lo = row_of(off, 0, n - 1, wbase);
-    const int32_t r_hi = row_of(off, r_lo, n - 1, wlast);
-#pragma unroll
-    for (int it = 0; it < IT; ++it) {
-        const int64_t i = wbase + it * WAVE + l;
-        const int64_t tb_i = tb + __popcll(deadm[it] & lanemask_lt());
-        if (i < m) {
-            const int32_t r = row_of(off, r_lo, r_hi, i);
-            const int64_t ro = off[r], re = off[r + 1];
-            const int64_t rank = (i - ro) - (tb_i - RB[r]);
-            const uint32_t cu = (uint32_t)c[it];
-            const uint32_t cur = cu & ID_MASK;
-            const bool dead = cu & DEAD;
-            const int64_t dlo = doff[r], dhi = doff[r + 1];
-            const int64_t ob = off2[r];
-            if (!dead) {
-                int64_t ndl = dlo < dhi ? lower_sorted(dcol, dlo, dhi, cur) - dlo : 0;
-                int64_t o = ob + rank + ndl;
-                if (o >= 0 && o < cap) {
-                    col2[o] = (int32_t)cu;
-                    w2[o] = w[i];
-                } else {
-                    atomicOr((unsigned long long *)&cnt[C_ERR], 4ull);
-                }
-            }
-            if (dlo < dhi) {
-                // diff entries whose insertion point is entry i ...
-                int64_t a = dlo;
-                if (i > ro) a = lower_sorted(dcol, dlo, dhi, ((uint32_t)col[i - 1] & ID_MASK) + 1);
-                int64_t b = lower_sorted(dcol, dlo, dhi, cur);
-                for (int64_t j = a; j < b; ++j) {
-                    int64_t o = ob + rank + (j - dlo);
-                    if (o < 0 || o >= cap) { atomicOr((unsigned long long *)&cnt[C_ERR], 4ull); break; }
-                    col2[o] = dcol[j];
-                    w2[o] = dw[j];
-                }
-                // ... and, after the row's last base entry, the diff tail
-                if (i == re - 1) {
-                    int64_t a2 = lower_sorted(dcol, dlo, dhi, cur + 1);
-                    int64_t after = rank + (dead ? 0 : 1);
-                    for (int64_t j = a2; j < dhi; ++j) {
-                        int64_t o = ob + after + (j - dlo);
-                        if (o < 0 || o >= cap) { atomicOr((unsigned long long *)&cnt[C_ERR], 4ull); break; }
-                        col2[o] = dcol[j];
-                        w2[o] = dw[j];
-                    }
-                }
-            }
+// Merge of one direction on merge-path tiles: the row ends and the base entries
+// form one sequence of n + m items and each workgroup takes MG_ITEMS of them, so
+// every workgroup moves the same amount whatever the row lengths.  A tile stages
+// its rows' data in LDS (start, output start off2, tombstones before the row RB,
+// diff count), reads its entries once (coalesced), and writes each live entry to
+//   off2[r] + (live base entries of row r before it) + (diff entries of r below it)
+// where the live count is (position in row) - (tombstones between row start and
+// entry): global tombstones before the entry come from the per-block counters
+// (ttomb, TILE entries each, kept by the delete step) plus a ballot count inside
+// the tile.  Diff entries are written at their insertion points by the base
+// entries of their row (rows with an empty base part: k_merge_diff_empty).
+constexpr int MG_THREADS = 256;
+constexpr int MG_ITEMS = 1024;
+constexpr int MG_IPT = MG_ITEMS / MG_THREADS;
+constexpr int MG_WAVES = MG_THREADS / WAVE;
+
+__global__ void k_mg_partition(const int64_t *__restrict__ off, int32_t n, int64_t m, int64_t nb,
+                               int32_t *mp_row, int64_t *mp_edge) {
+    for (int64_t b = gtid(); b <= nb; b += gstride()) {
+        const int64_t diag = min(b * (int64_t)MG_ITEMS, (int64_t)n + m);
+        int64_t lo = max(diag - m, (int64_t)0), hi = min(diag, (int64_t)n);
+        while (lo < hi) {
+            const int64_t p = (lo + hi) >> 1;
+            if (off[p + 1] <= diag - p - 1) lo = p + 1;
+            else hi = p;
         }
-        tb += __popcll(deadm[it]);
+        mp_row[b] = (int32_t)lo;
+        mp_edge[b] = diag - lo;
+    }
+}
+
+__device__ __forceinline__ void merge_put(int32_t *col2, int32_t *w2, int64_t cap, int64_t o, int32_t c,
+                                          int32_t wt, int64_t *cnt) {
+    if (o >= 0 && o < cap) {
+        col2[o] = c;
+        w2[o] = wt;
+    } else {
+        atomicOr((unsigned long long *)&cnt[C_ERR], 4ull);
+    }
+}
+
+__global__ __launch_bounds__(MG_THREADS) void k_merge_tiles(
+    int32_t n, const int32_t *__restrict__ mp_row, const int64_t *__restrict__ mp_edge,
+    const int64_t *__restrict__ off, const int32_t *__restrict__ col, const int32_t *__restrict__ w,
+    const int64_t *__restrict__ doff, const int32_t *__restrict__ dcol, const int32_t *__restrict__ dw,
+    const int64_t *__restrict__ off2, const int64_t *__restrict__ RB, const int64_t *__restrict__ TB,
+    int32_t *__restrict__ col2, int32_t *__restrict__ w2, int64_t cap, int64_t *cnt) {
+    __shared__ int32_t s_off[MG_ITEMS + 1];  // row start - e0 (row 0: -1 when it began earlier)
+    __shared__ int32_t s_o2[MG_ITEMS + 1];   // off2[r] - off2[r0]
+    __shared__ int32_t s_rb[MG_ITEMS + 1];   // RB[r] - RB[r0]
+    __shared__ int32_t s_dn[MG_ITEMS + 1];   // diff entries of row r
+    __shared__ int32_t s_wd[MG_IPT][MG_WAVES];
+    __shared__ int64_t s_base[4];            // off[r0], off2[r0], RB[r0], tombstones before e0
+    const int64_t b = blockIdx.x;
+    const int32_t r0 = mp_row[b], r1 = mp_row[b + 1];
+    const int64_t e0 = mp_edge[b];
+    const int32_t ne = (int32_t)(mp_edge[b + 1] - e0);
+    const int32_t nr = r1 - r0;
+    const int t = threadIdx.x, wv = t / WAVE, l = lane_id();
+    // entries (coalesced) and their tombstone ballots
+    uint32_t c[MG_IPT];
+    int32_t wt[MG_IPT];
+    int32_t lp[MG_IPT];
+#pragma unroll
+    for (int u = 0; u < MG_IPT; ++u) {
+        const int j = u * MG_THREADS + t;
+        const bool valid = j < ne;
+        c[u] = valid ? (uint32_t)col[e0 + j] : 0u;
+        wt[u] = valid ? w[e0 + j] : 0;
+        const uint64_t bm = ballot(valid && (c[u] & DEAD));
+        lp[u] = __popcll(bm & lanemask_lt());
+        if (l == 0) s_wd[u][wv] = __popcll(bm);
+    }
+    // rows r0 .. r1 (r1: the row still open at the tile's end, if any)
+    for (int i = t; i <= nr; i += MG_THREADS) {
+        const int32_t r = r0 + i;
+        const int64_t o = off[r] - e0;
+        s_off[i] = (int32_t)(o < 0 ? -1 : o);
+        s_o2[i] = (int32_t)(off2[r] - off2[r0]);
+        s_rb[i] = (int32_t)(RB[r] - RB[r0]);
+        s_dn[i] = r < n ? (int32_t)(doff[r + 1] - doff[r]) : 0;
+    }
+    if (wv == 0) {
+        // tombstones before e0: counter blocks before its block + a ballot count inside it
+        const int64_t st = (e0 / TILE) * TILE;
+        int cd = 0;
+        for (int64_t q = st; q < e0; q += WAVE) {
+            const int64_t idx = q + l;
+            cd += __popcll(ballot(idx < e0 && ((uint32_t)col[idx] & DEAD)));
+        }
+        if (l == 0) {
+            s_base[0] = off[r0];
+            s_base[1] = off2[r0];
+            s_base[2] = RB[r0];
+            s_base[3] = TB[e0 / TILE] + cd;
+        }
+    }
+    __syncthreads();
+    int64_t pre = s_base[3];
+#pragma unroll
+    for (int u = 0; u < MG_IPT; ++u) {
+        int64_t pu = pre;
+        for (int q = 0; q < wv; ++q) pu += s_wd[u][q];
+        for (int q = 0; q < MG_WAVES; ++q) pre += s_wd[u][q];
+        const int j = u * MG_THREADS + t;
+        if (j >= ne) continue;
+        const int64_t i = e0 + j;
+        const int64_t deadG = pu + lp[u];  // tombstones before entry i
+        // row of the entry: last row of the tile that starts at or before j
+        int lo = 0, hi = nr;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_off[mid] <= j) lo = mid;
+            else hi = mid - 1;
+        }
+        const int32_t r = r0 + lo;
+        const int64_t ro = lo == 0 ? s_base[0] : e0 + s_off[lo];
+        const int64_t rank = (i - ro) - (deadG - (s_base[2] + s_rb[lo]));
+        const int64_t ob = s_base[1] + s_o2[lo];
+        const uint32_t cu = c[u];
+        const uint32_t cur = cu & ID_MASK;
+        const bool dead = cu & DEAD;
+        if (s_dn[lo] == 0) {
+            if (!dead) merge_put(col2, w2, cap, ob + rank, (int32_t)cu, wt[u], cnt);
+            continue;
+        }
+        // rows with diff entries: interleave them at their insertion points
+        const int64_t dlo = doff[r], dhi = doff[r + 1];
+        if (!dead) merge_put(col2, w2, cap, ob + rank + (lower_sorted(dcol, dlo, dhi, cur) - dlo), (int32_t)cu,
+                             wt[u], cnt);
+        int64_t a = dlo;
+        if (i > ro) a = lower_sorted(dcol, dlo, dhi, ((uint32_t)col[i - 1] & ID_MASK) + 1);
+        const int64_t bq = lower_sorted(dcol, dlo, dhi, cur);
+        for (int64_t q = a; q < bq; ++q) merge_put(col2, w2, cap, ob + rank + (q - dlo), dcol[q], dw[q], cnt);
+        if (i == off[r + 1] - 1) {  // after the row's last base entry: the diff tail
+            const int64_t after = rank + (dead ? 0 : 1);
+            for (int64_t q = lower_sorted(dcol, dlo, dhi, cur + 1); q < dhi; ++q)
+                merge_put(col2, w2, cap, ob + after + (q - dlo), dcol[q], dw[q], cnt);
+        }
     }
 }
 
@@ -373,30 +424,36 @@ static int merge_into(dg_graph *g, Dir &d, int64_t *off2, int32_t *col2, int32_t
     hipStream_t s = g->stream;
     Work &ws = g->ws;
     const int32_t n = g->n;
-    const int64_t ntiles = ntiles_for(d.m);
-    DG_TRY(ws.scan64.ensure(2 * ((size_t)n + 1) + 2 * (ntiles + 1)));
+    const int64_t nblk = ntiles_for(d.m);
+    DG_TRY(ws.scan64.ensure(2 * ((size_t)n + 1) + 2 * (nblk + 2)));
     int64_t *tmpa = ws.scan64.p;
     int64_t *RB = tmpa + (n + 1);
     int64_t *tsin = RB + (n + 1);
-    int64_t *TS = tsin + (ntiles + 1);
+    int64_t *TB = tsin + (nblk + 2);
     // off2 = exclusive scan of live degrees
     hipLaunchKernelGGL(k_deg_to_i64, dim3(grid_for(n + 1)), dim3(256), 0, s, n, d.deg.p, tmpa);
     DG_TRY(scan_excl(g, tmpa, off2, n + 1));
-    // RB = tombstones before each row, TS = tombstones before each tile
+    // RB = tombstones before each row, TB = tombstones before each counter block
     hipLaunchKernelGGL(k_deg_to_i64, dim3(grid_for(n + 1)), dim3(256), 0, s, n, d.ntomb.p, tmpa);
     DG_TRY(scan_excl(g, tmpa, RB, n + 1));
-    hipLaunchKernelGGL(k_deg_to_i64, dim3(grid_for(ntiles + 1)), dim3(256), 0, s, (int32_t)ntiles,
-                       d.ttomb.p, tsin);
-    DG_TRY(scan_excl(g, tsin, TS, ntiles + 1));
+    hipLaunchKernelGGL(k_deg_to_i64, dim3(grid_for(nblk + 2)), dim3(256), 0, s, (int32_t)(nblk + 1), d.ttomb.p,
+                       tsin);
+    DG_TRY(scan_excl(g, tsin, TB, nblk + 2));
+    // merge-path tiles
+    const int64_t nb = ((int64_t)n + d.m + MG_ITEMS - 1) / MG_ITEMS;
+    DG_TRY(ws.mp_row.ensure((size_t)nb + 1));
+    DG_TRY(ws.mp_edge.ensure((size_t)nb + 1));
+    hipLaunchKernelGGL(k_mg_partition, dim3(grid_for(nb + 1)), dim3(256), 0, s, d.off.p, n, d.m, nb, ws.mp_row.p,
+                       ws.mp_edge.p);
     DG_HIP(hipGetLastError());
     DG_TRY(counters_clear(g));
-    // merge_base bytes: col+w read 8 per old entry, write 8 per new entry, and per
-    // row off, doff, off2 and the tombstone prefix (8 each)
+    // merge bytes: col+w read 8 per old entry, write 8 per new entry, and per row
+    // off, doff, off2 and the tombstone prefix (8 each)
     int pm = prof_begin("merge_base", s);
-    if (d.m > 0)
-        hipLaunchKernelGGL(k_merge_base, dim3((unsigned)ntiles), dim3(256), 0, s, n, d.m, d.off.p,
-                           d.col.p, d.w.p, d.doff.p, d.dcol.p, d.dw.p, off2, RB, TS, col2, w2, m2,
-                           ws.dcnt);
+    if (nb > 0)
+        hipLaunchKernelGGL(k_merge_tiles, dim3((unsigned)nb), dim3(MG_THREADS), 0, s, n, ws.mp_row.p,
+                           ws.mp_edge.p, d.off.p, d.col.p, d.w.p, d.doff.p, d.dcol.p, d.dw.p, off2, RB, TB, col2, w2,
+                           m2, ws.dcnt);
     prof_end(pm, s, 8.0 * (double)d.m + 8.0 * (double)m2 + 32.0 * (double)n + 8.0 * (double)d.dm);
     if (d.dm > 0)
         hipLaunchKernelGGL(k_merge_diff_empty, dim3(grid_for(d.dm)), dim3(256), 0, s, d.dm, d.dkey.p,

@@ -80,11 +80,13 @@ __global__ __launch_bounds__(256) void k_tc_delta(int64_t ne, const int32_t *eu,
         const int depth = (rb.db > 0 ? 64 - __clzll((unsigned long long)rb.db) : 0) +
                           (rb.dd > 0 ? 64 - __clzll((unsigned long long)rb.dd) : 0);
         const int64_t tot = ra.db + ra.dd;
+        if (l == 0) {
+            walked += tot;
+            probes += tot * depth;
+        }
         for (int64_t j = l; j < tot; j += WAVE) {
             uint32_t e = j < ra.db ? (uint32_t)col[ra.ob + j] : (uint32_t)dcol[ra.od + (j - ra.db)];
-            ++walked;
             if (e & DEAD) continue;
-            probes += depth;
             uint32_t c = e & ID_MASK;
             uint32_t e2;
             if (!row_find(col, dcol, rb, c, e2)) continue;
@@ -118,8 +120,8 @@ int tc_delta(dg_graph *g, const int32_t *eu, const int32_t *ev, int64_t ne, uint
     DG_HIP(hipGetLastError());
     DG_TRY(counters_read(g));
     *sum6 = (uint64_t)g->ws.hcnt[C_TC0];
-    // per changed edge its endpoints' offsets (32 B); per walked entry 4 B; per
-    // binary-search step 4 B
+    // per changed edge its endpoints' offsets (32 B); per entry of the shorter row
+    // 4 B; per binary-search step into the longer row 4 B
     prof_add(ps, 32.0 * (double)ne + 4.0 * (double)g->ws.hcnt[C_AUX2] + 4.0 * (double)g->ws.hcnt[C_AUX3]);
     return DG_OK;
 }
