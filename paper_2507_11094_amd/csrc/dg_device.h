@@ -114,6 +114,58 @@ __device__ __forceinline__ void wave_count(int64_t *counter, bool pred) {
         atomicAdd((unsigned long long *)counter, (unsigned long long)__popcll(b));
 }
 
+// ---- block-aggregated counters ------------------------------------------------------
+// Atomics on one address serialise (tens of ns each), so kernels over millions of
+// elements take their output slots once per block and chunk instead of once per
+// wave: every thread handles CH_IPT consecutive elements, the block scans the
+// per-thread counts in LDS and one thread reserves the block's total.  All
+// threads of the block (blockDim == CH_T) must make the same calls.
+constexpr int CH_T = 256;
+constexpr int CH_IPT = 8;
+constexpr int CH = CH_T * CH_IPT;
+
+struct BlockScratch {
+    int64_t w[CH_T / WAVE];
+    int64_t base;
+};
+
+// Exclusive prefix of v over the block (thread order); *total = block sum.
+__device__ __forceinline__ int64_t block_scan_excl(int64_t v, int64_t *total, BlockScratch &s) {
+    const int l = lane_id(), wv = threadIdx.x / WAVE;
+    const int64_t incl = wave_incl_scan(v);
+    if (l == WAVE - 1) s.w[wv] = incl;
+    __syncthreads();
+    int64_t before = 0, tot = 0;
+#pragma unroll
+    for (int q = 0; q < CH_T / WAVE; ++q) {
+        const int64_t x = s.w[q];
+        if (q < wv) before += x;
+        tot += x;
+    }
+    __syncthreads();
+    *total = tot;
+    return before + incl - v;
+}
+
+// First of v consecutive slots of `counter` for this thread (one atomic per block).
+__device__ __forceinline__ int64_t block_reserve(int64_t *counter, int64_t v, BlockScratch &s) {
+    int64_t tot;
+    const int64_t ex = block_scan_excl(v, &tot, s);
+    if (threadIdx.x == 0)
+        s.base = tot > 0 ? (int64_t)atomicAdd((unsigned long long *)counter, (unsigned long long)tot) : 0;
+    __syncthreads();
+    const int64_t r = s.base + ex;
+    __syncthreads();
+    return r;
+}
+
+// counter += sum of v over the block (one atomic per block).
+__device__ __forceinline__ void block_count(int64_t *counter, int64_t v, BlockScratch &s) {
+    int64_t tot;
+    (void)block_scan_excl(v, &tot, s);
+    if (threadIdx.x == 0 && tot) atomicAdd((unsigned long long *)counter, (unsigned long long)tot);
+}
+
 __device__ __forceinline__ uint64_t sssp_pack(int32_t dist, int32_t parent) {
     return ((uint64_t)(uint32_t)dist << 32) | (uint64_t)(uint32_t)parent;
 }

@@ -124,6 +124,7 @@ struct Work {
     DBuf<int32_t> f0, f1, heavy;          // frontiers and heavy-chunk queue
     DBuf<int32_t> stamp;                  // per-vertex dedup stamps
     DBuf<int32_t> farflag, far0, far1;    // near-far SSSP: far-pile membership stamps and piles
+    DBuf<int64_t> bpart;                  // per-block partial counts (summed in block order)
     int32_t far_ctr = 0;
     int32_t stamp_ctr = 0;
     DBuf<double> part;                    // partial sums of split rows

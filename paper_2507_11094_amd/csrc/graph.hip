@@ -29,6 +29,9 @@ static inline int grid_for(int64_t n, int block = 256, int cap = 8192) {
     return (int)g;
 }
 
+// Blocks for the chunked kernels (CH elements per block and pass).
+static inline int grid_ch(int64_t n) { return grid_for(n, CH, 8192); }
+
 // ---------------------------------------------------------------- small kernels
 
 __global__ void k_fill_i32(int32_t *p, int32_t v, int64_t n) {
@@ -112,7 +115,7 @@ void ws_free(dg_graph *g) {
     w.scan64.release(); w.tscan.release(); w.f0.release(); w.f1.release(); w.heavy.release();
     w.stamp.release(); w.part.release(); w.prs.release();
     w.mp_row.release(); w.mp_edge.release(); w.mp_part.release();
-    w.farflag.release(); w.far0.release(); w.far1.release();
+    w.farflag.release(); w.far0.release(); w.far1.release(); w.bpart.release();
     w.wq.release(); w.wseq.release(); w.wctr.release(); w.inq.release();
     if (w.dcnt) dfree(w.dcnt);
     if (w.hcnt) (void)hipHostFree(w.hcnt);
@@ -545,44 +548,65 @@ int graph_export(dg_graph *g, int64_t *m, int32_t *src, int32_t *dst, int32_t *w
 
 // Validation of a whole chunk before any change (rejects self-loops, ids outside
 // [0, n), ops other than 0/1 and insert weights outside [1, 2^30)).
-__global__ void k_validate_batch(int64_t k, const int32_t *s, const int32_t *d, const int32_t *w,
-                                 const uint8_t *op, int32_t n, int64_t *cnt) {
-    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < k; base += gstride()) {
-        int64_t i = base + threadIdx.x;
-        bool valid = i < k;
-        bool bad = false, del = false, ins = false;
-        if (valid) {
-            int32_t u = s[i], v = d[i];
-            uint8_t o = op[i];
-            bad = u < 0 || u >= n || v < 0 || v >= n || u == v || o > 1;
-            if (o == 1 && w) bad |= (w[i] < 1 || w[i] >= (1 << 30));
-            del = !bad && o == 0;
-            ins = !bad && o == 1;
-        }
-        if (bad) atomicOr((unsigned long long *)&cnt[C_ERR], 1ull);
-        wave_count(&cnt[C_NDEL], del);
-        wave_count(&cnt[C_NINS], ins);
+__global__ __launch_bounds__(CH_T) void k_validate_batch(int64_t k, const int32_t *s, const int32_t *d,
+                                                         const int32_t *w, const uint8_t *op, int32_t n,
+                                                         int64_t *cnt) {
+    __shared__ BlockScratch sc;
+    int64_t nd = 0, ni = 0;
+    bool anybad = false;
+    for (int64_t i = gtid(); i < k; i += gstride()) {
+        int32_t u = s[i], v = d[i];
+        uint8_t o = op[i];
+        bool bad = u < 0 || u >= n || v < 0 || v >= n || u == v || o > 1;
+        if (o == 1 && w) bad |= (w[i] < 1 || w[i] >= (1 << 30));
+        anybad |= bad;
+        nd += !bad && o == 0;
+        ni += !bad && o == 1;
     }
+    if (anybad) atomicOr((unsigned long long *)&cnt[C_ERR], 1ull);
+    block_count(&cnt[C_NDEL], nd, sc);
+    block_count(&cnt[C_NINS], ni, sc);
 }
 
 // Split the chunk into deletion arcs and insertion keys (undirected updates give
 // both arcs).
-__global__ void k_expand_batch(int64_t k, const int32_t *s, const int32_t *d, const int32_t *w,
-                               const uint8_t *op, int B, int undirected, int32_t *ddu, int32_t *ddv,
-                               uint64_t *ikey, int32_t *iw, int64_t *cnt) {
-    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < k; base += gstride()) {
-        int64_t i = base + threadIdx.x;
-        bool valid = i < k;
-        bool del = valid && op[i] == 0;
-        bool ins = valid && op[i] == 1;
-        uint32_t u0 = valid ? (uint32_t)s[i] : 0, v0 = valid ? (uint32_t)d[i] : 0;
-        int32_t wt = (valid && w) ? w[i] : 1;
-        for (int r = 0; r < (undirected ? 2 : 1); ++r) {
-            uint32_t u = r ? v0 : u0, v = r ? u0 : v0;
-            int64_t pd = wave_append(&cnt[C_AUX0], del);
-            if (del) { ddu[pd] = (int32_t)u; ddv[pd] = (int32_t)v; }
-            int64_t pi = wave_append(&cnt[C_AUX1], ins);
-            if (ins) { ikey[pi] = ((uint64_t)u << B) | v; iw[pi] = wt; }
+__global__ __launch_bounds__(CH_T) void k_expand_batch(int64_t k, const int32_t *s, const int32_t *d,
+                                                       const int32_t *w, const uint8_t *op, int B,
+                                                       int undirected, int32_t *ddu, int32_t *ddv,
+                                                       uint64_t *ikey, int32_t *iw, int64_t *cnt) {
+    __shared__ BlockScratch sc;
+    const int rep = undirected ? 2 : 1;
+    for (int64_t c0 = (int64_t)blockIdx.x * CH; c0 < k; c0 += (int64_t)gridDim.x * CH) {
+        const int64_t i0 = c0 + (int64_t)threadIdx.x * CH_IPT;
+        int64_t nd = 0, ni = 0;
+#pragma unroll
+        for (int q = 0; q < CH_IPT; ++q) {
+            const int64_t i = i0 + q;
+            if (i < k) {
+                nd += op[i] == 0;
+                ni += op[i] == 1;
+            }
+        }
+        int64_t pd = block_reserve(&cnt[C_AUX0], nd * rep, sc);
+        int64_t pi = block_reserve(&cnt[C_AUX1], ni * rep, sc);
+        for (int q = 0; q < CH_IPT; ++q) {
+            const int64_t i = i0 + q;
+            if (i >= k) break;
+            const uint8_t o = op[i];
+            const uint32_t u0 = (uint32_t)s[i], v0 = (uint32_t)d[i];
+            const int32_t wt = w ? w[i] : 1;
+            for (int r = 0; r < rep; ++r) {
+                const uint32_t u = r ? v0 : u0, v = r ? u0 : v0;
+                if (o == 0) {
+                    ddu[pd] = (int32_t)u;
+                    ddv[pd] = (int32_t)v;
+                    ++pd;
+                } else if (o == 1) {
+                    ikey[pi] = ((uint64_t)u << B) | v;
+                    iw[pi] = wt;
+                    ++pi;
+                }
+            }
         }
     }
 }
@@ -596,33 +620,52 @@ __global__ void k_mark_deletes(int64_t na, const int32_t *ddu, const int32_t *dd
                                const int64_t *__restrict__ doff, int32_t *dcol, int undirected,
                                int32_t *adu, int32_t *adv, int64_t *adpos, int32_t *tcu, int32_t *tcv,
                                int64_t *cnt) {
-    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < na; base += gstride()) {
-        int64_t i = base + threadIdx.x;
-        bool applied = false;
-        int64_t pos = 0;
-        int32_t u = 0, v = 0;
-        if (i < na) {
-            u = ddu[i];
-            v = ddv[i];
+    __shared__ BlockScratch sc;
+    for (int64_t c0 = (int64_t)blockIdx.x * CH; c0 < na; c0 += (int64_t)gridDim.x * CH) {
+        const int64_t i0 = c0 + (int64_t)threadIdx.x * CH_IPT;
+        int64_t pos[CH_IPT];
+        int64_t nap = 0, ntc = 0;
+#pragma unroll
+        for (int q = 0; q < CH_IPT; ++q) {
+            const int64_t i = i0 + q;
+            pos[q] = -1;  // -1: not applied
+            if (i >= na) continue;
+            const int32_t u = ddu[i], v = ddv[i];
             int64_t p = find_sorted(col, off[u], off[u + 1], (uint32_t)v);
             if (p >= 0) {
                 if (!((uint32_t)col[p] & DEAD)) {
                     uint32_t old = atomicOr((unsigned int *)&col[p], MARK);
-                    if (!(old & MARK)) { applied = true; pos = p; }
+                    if (!(old & MARK)) pos[q] = p;
                 }
             } else {
-                int64_t q = find_sorted(dcol, doff[u], doff[u + 1], (uint32_t)v);
-                if (q >= 0 && !((uint32_t)dcol[q] & DEAD)) {
-                    uint32_t old = atomicOr((unsigned int *)&dcol[q], MARK);
-                    if (!(old & MARK)) { applied = true; pos = -2 - q; }
+                int64_t r = find_sorted(dcol, doff[u], doff[u + 1], (uint32_t)v);
+                if (r >= 0 && !((uint32_t)dcol[r] & DEAD)) {
+                    uint32_t old = atomicOr((unsigned int *)&dcol[r], MARK);
+                    if (!(old & MARK)) pos[q] = -2 - r;
                 }
             }
+            if (pos[q] != -1) {
+                ++nap;
+                ntc += undirected && u < v;
+            }
         }
-        int64_t slot = wave_append(&cnt[C_ADEL], applied);
-        if (applied) { adu[slot] = u; adv[slot] = v; adpos[slot] = pos; }
-        bool tc = applied && undirected && u < v;
-        int64_t ts = wave_append(&cnt[C_TCDEL], tc);
-        if (tc) { tcu[ts] = u; tcv[ts] = v; }
+        int64_t slot = block_reserve(&cnt[C_ADEL], nap, sc);
+        int64_t ts = block_reserve(&cnt[C_TCDEL], ntc, sc);
+#pragma unroll
+        for (int q = 0; q < CH_IPT; ++q) {
+            if (pos[q] == -1) continue;
+            const int64_t i = i0 + q;
+            const int32_t u = ddu[i], v = ddv[i];
+            adu[slot] = u;
+            adv[slot] = v;
+            adpos[slot] = pos[q];
+            ++slot;
+            if (undirected && u < v) {
+                tcu[ts] = u;
+                tcv[ts] = v;
+                ++ts;
+            }
+        }
     }
 }
 
@@ -635,43 +678,62 @@ __global__ void k_classify_inserts(int64_t ni, const uint64_t *key, int32_t *iw,
                                    const int64_t *__restrict__ doff, const int32_t *__restrict__ dcol,
                                    int undirected, int64_t *isnew, int32_t *aiu, int32_t *aiv,
                                    int32_t *aiw, int64_t *aipos, int64_t *cnt) {
+    __shared__ BlockScratch sc;
     const uint64_t mask = (1ull << B) - 1;
-    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < ni; base += gstride()) {
-        int64_t i = base + threadIdx.x;
-        bool valid = i < ni;
-        bool head = valid && (i == 0 || key[i] != key[i - 1]);
-        int act = 0;  // 0 none, 1 new, 2 revive, 3 ignore
-        int64_t pos = -1;
-        int32_t u = 0, v = 0, wt = 0;
-        if (head) {
-            uint64_t kk = key[i];
-            wt = iw[i];
-            for (int64_t j = i + 1; j < ni && key[j] == kk; ++j) wt = min(wt, iw[j]);
-            iw[i] = wt;
-            u = (int32_t)(kk >> B);
-            v = (int32_t)(kk & mask);
-            int64_t p = find_sorted(col, off[u], off[u + 1], (uint32_t)v);
-            if (p >= 0) {
-                if ((uint32_t)col[p] & (DEAD | MARK)) { act = 2; pos = p; }
-                else act = 3;
-            } else {
-                int64_t q = find_sorted(dcol, doff[u], doff[u + 1], (uint32_t)v);
-                if (q >= 0) {
-                    if ((uint32_t)dcol[q] & (DEAD | MARK)) { act = 2; pos = -2 - q; }
-                    else act = 3;
+    int64_t nnew = 0, nign = 0, ndist = 0;
+    for (int64_t c0 = (int64_t)blockIdx.x * CH; c0 < ni; c0 += (int64_t)gridDim.x * CH) {
+        const int64_t i0 = c0 + (int64_t)threadIdx.x * CH_IPT;
+        int64_t pos[CH_IPT];
+        int8_t act[CH_IPT];  // 0 none, 1 new, 2 revive, 3 ignore
+        int64_t napp = 0;
+#pragma unroll
+        for (int q = 0; q < CH_IPT; ++q) {
+            const int64_t i = i0 + q;
+            act[q] = 0;
+            pos[q] = -1;
+            if (i >= ni) continue;
+            const uint64_t kk = key[i];
+            const bool head = i == 0 || kk != key[i - 1];
+            if (head) {
+                int32_t wt = iw[i];
+                for (int64_t j = i + 1; j < ni && key[j] == kk; ++j) wt = min(wt, iw[j]);
+                iw[i] = wt;
+                const int32_t u = (int32_t)(kk >> B), v = (int32_t)(kk & mask);
+                int64_t p = find_sorted(col, off[u], off[u + 1], (uint32_t)v);
+                if (p >= 0) {
+                    if ((uint32_t)col[p] & (DEAD | MARK)) { act[q] = 2; pos[q] = p; }
+                    else act[q] = 3;
                 } else {
-                    act = 1;
+                    int64_t r = find_sorted(dcol, doff[u], doff[u + 1], (uint32_t)v);
+                    if (r >= 0) {
+                        if ((uint32_t)dcol[r] & (DEAD | MARK)) { act[q] = 2; pos[q] = -2 - r; }
+                        else act[q] = 3;
+                    } else {
+                        act[q] = 1;
+                    }
                 }
+                ++ndist;
             }
+            isnew[i] = act[q] == 1;
+            napp += act[q] == 1 || act[q] == 2;
+            nnew += act[q] == 1;
+            nign += act[q] != 1 && act[q] != 2;
         }
-        if (valid) isnew[i] = act == 1;
-        bool applied = act == 1 || act == 2;
-        int64_t slot = wave_append(&cnt[C_AINS], applied);
-        if (applied) { aiu[slot] = u; aiv[slot] = v; aiw[slot] = wt; aipos[slot] = pos; }
-        wave_count(&cnt[C_NEW], act == 1);
-        wave_count(&cnt[C_IGNINS], valid && act != 1 && act != 2);
-        wave_count(&cnt[C_DISTINCT], head);
+        int64_t slot = block_reserve(&cnt[C_AINS], napp, sc);
+#pragma unroll
+        for (int q = 0; q < CH_IPT; ++q) {
+            if (act[q] != 1 && act[q] != 2) continue;
+            const uint64_t kk = key[i0 + q];
+            aiu[slot] = (int32_t)(kk >> B);
+            aiv[slot] = (int32_t)(kk & mask);
+            aiw[slot] = iw[i0 + q];
+            aipos[slot] = pos[q];
+            ++slot;
+        }
     }
+    block_count(&cnt[C_NEW], nnew, sc);
+    block_count(&cnt[C_IGNINS], nign, sc);
+    block_count(&cnt[C_DISTINCT], ndist, sc);
     (void)undirected;
 }
 
@@ -682,13 +744,22 @@ __global__ void k_compact_new(int64_t ni, const uint64_t *key, const int32_t *iw
 }
 
 // TC needs the inserted undirected edges once each.
-__global__ void k_list_tc_inserts(int64_t na, const int32_t *aiu, const int32_t *aiv, int32_t *tcu,
-                                  int32_t *tcv, int64_t *cnt) {
-    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < na; base += gstride()) {
-        int64_t i = base + threadIdx.x;
-        bool p = i < na && aiu[i] < aiv[i];
-        int64_t s = wave_append(&cnt[C_TCINS], p);
-        if (p) { tcu[s] = aiu[i]; tcv[s] = aiv[i]; }
+__global__ __launch_bounds__(CH_T) void k_list_tc_inserts(int64_t na, const int32_t *aiu, const int32_t *aiv,
+                                                          int32_t *tcu, int32_t *tcv, int64_t *cnt) {
+    __shared__ BlockScratch sc;
+    for (int64_t c0 = (int64_t)blockIdx.x * CH; c0 < na; c0 += (int64_t)gridDim.x * CH) {
+        const int64_t i0 = c0 + (int64_t)threadIdx.x * CH_IPT;
+        int64_t np = 0;
+        for (int q = 0; q < CH_IPT; ++q) np += i0 + q < na && aiu[i0 + q] < aiv[i0 + q];
+        int64_t s = block_reserve(&cnt[C_TCINS], np, sc);
+        for (int q = 0; q < CH_IPT; ++q) {
+            const int64_t i = i0 + q;
+            if (i < na && aiu[i] < aiv[i]) {
+                tcu[s] = aiu[i];
+                tcv[s] = aiv[i];
+                ++s;
+            }
+        }
     }
 }
 
@@ -696,6 +767,8 @@ __global__ void k_list_tc_inserts(int64_t na, const int32_t *aiu, const int32_t 
 __global__ void k_commit_deletes(int64_t na, const int32_t *adu, const int64_t *adpos, int32_t *col,
                                  int32_t *dcol, int32_t *deg, int32_t *ntomb, int32_t *ttomb,
                                  int64_t *cnt) {
+    __shared__ BlockScratch sc;
+    int64_t nbase = 0, ndiff = 0;
     for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < na; base += gstride()) {
         int64_t i = base + threadIdx.x;
         bool inbase = false, indiff = false;
@@ -714,9 +787,11 @@ __global__ void k_commit_deletes(int64_t na, const int32_t *adu, const int64_t *
             }
             atomicSub(&deg[u], 1);
         }
-        wave_count(&cnt[C_AUX2], inbase);
-        wave_count(&cnt[C_AUX3], indiff);
+        nbase += inbase;
+        ndiff += indiff;
     }
+    block_count(&cnt[C_AUX2], nbase, sc);
+    block_count(&cnt[C_AUX3], ndiff, sc);
 }
 
 // Reverse direction of a directed graph: find (v, u) in row v and tombstone it.
@@ -724,6 +799,8 @@ __global__ void k_commit_deletes_rev(int64_t na, const int32_t *adu, const int32
                                      const int64_t *__restrict__ off, int32_t *col,
                                      const int64_t *__restrict__ doff, int32_t *dcol, int32_t *deg,
                                      int32_t *ntomb, int32_t *ttomb, int64_t *cnt) {
+    __shared__ BlockScratch sc;
+    int64_t nbase = 0, ndiff = 0;
     for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < na; base += gstride()) {
         int64_t i = base + threadIdx.x;
         bool inbase = false, indiff = false;
@@ -744,9 +821,11 @@ __global__ void k_commit_deletes_rev(int64_t na, const int32_t *adu, const int32
             }
             if (inbase || indiff) atomicSub(&deg[v], 1);
         }
-        wave_count(&cnt[C_AUX2], inbase);
-        wave_count(&cnt[C_AUX3], indiff);
+        nbase += inbase;
+        ndiff += indiff;
     }
+    block_count(&cnt[C_AUX2], nbase, sc);
+    block_count(&cnt[C_AUX3], ndiff, sc);
 }
 
 // updateCSRAdd for slots that already exist: revive a tombstone in place
@@ -757,8 +836,13 @@ __global__ void k_revive(int64_t na, const int32_t *aiu, const int32_t *aiv, con
                          int32_t *w, const int64_t *__restrict__ doff, int32_t *dcol, int32_t *dw,
                          int32_t *deg, int32_t *ntomb, int32_t *ttomb, int B, uint64_t *rkey,
                          int32_t *rw, int64_t *cnt) {
-    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < na; base += gstride()) {
-        int64_t i = base + threadIdx.x;
+    __shared__ BlockScratch sc;
+    int64_t nrev = 0;
+    for (int64_t c0 = (int64_t)blockIdx.x * CH; c0 < na; c0 += (int64_t)gridDim.x * CH) {
+      const int64_t i0 = c0 + (int64_t)threadIdx.x * CH_IPT;
+      int64_t nnew = 0;
+      for (int qq = 0; qq < CH_IPT; ++qq) {
+        const int64_t i = i0 + qq;
         bool revived_base = false, is_new = false;
         int32_t r = 0, c = 0, wt = 0;
         if (i < na) {
@@ -793,12 +877,24 @@ __global__ void k_revive(int64_t na, const int32_t *aiu, const int32_t *aiv, con
             }
             atomicAdd(&deg[r], 1);
         }
-        wave_count(&cnt[C_AUX2], revived_base);
-        if (rkey) {
-            int64_t s = wave_append(&cnt[C_AUX1], is_new);
-            if (is_new) { rkey[s] = ((uint64_t)(uint32_t)r << B) | (uint32_t)c; rw[s] = wt; }
+        nrev += revived_base;
+        nnew += is_new;
+      }
+      if (rkey) {
+        // NEW arcs of this thread's elements, in element order, for the reverse diff
+        int64_t s = block_reserve(&cnt[C_AUX1], nnew, sc);
+        for (int qq = 0; qq < CH_IPT; ++qq) {
+            const int64_t i = i0 + qq;
+            if (i < na && aipos[i] == -1) {
+                const int32_t r = reverse ? aiv[i] : aiu[i], c = reverse ? aiu[i] : aiv[i];
+                rkey[s] = ((uint64_t)(uint32_t)r << B) | (uint32_t)c;
+                rw[s] = aiw[i];
+                ++s;
+            }
         }
+      }
     }
+    block_count(&cnt[C_AUX2], nrev, sc);
 }
 
 // Drop MARK from the entries this chunk inserted.
@@ -958,18 +1054,18 @@ int apply_chunk(dg_graph *g, int64_t k, const int32_t *src, const int32_t *dst, 
     DG_TRY(ws.rw.ensure(nia + 1)); DG_TRY(ws.rw_s.ensure(nia + 1));
     DG_TRY(ws.tcu.ensure(nda + nia + 1)); DG_TRY(ws.tcv.ensure(nda + nia + 1));
     DG_TRY(ws.scan64.ensure(2 * ((size_t)nia + 1)));
-    hipLaunchKernelGGL(k_expand_batch, dim3(grid_for(k)), dim3(256), 0, s, k, ds, dd, dw, dop, B,
+    hipLaunchKernelGGL(k_expand_batch, dim3(grid_ch(k)), dim3(256), 0, s, k, ds, dd, dw, dop, B,
                        (int)und, ws.ddu.p, ws.ddv.p, ws.ikey.p, ws.iw.p, ws.dcnt);
     DG_HIP(hipGetLastError());
     DG_TRY(sort_pairs(g, ws.ikey.p, ws.ikey_s.p, ws.iw.p, ws.iw_s.p, nia, 2 * B));
     // ---- updateCSRDel (mark) and insert classification against the old graph
     if (nda > 0)
-        hipLaunchKernelGGL(k_mark_deletes, dim3(grid_for(nda)), dim3(256), 0, s, nda, ws.ddu.p, ws.ddv.p,
+        hipLaunchKernelGGL(k_mark_deletes, dim3(grid_ch(nda)), dim3(256), 0, s, nda, ws.ddu.p, ws.ddv.p,
                            F.off.p, F.col.p, F.doff.p, F.dcol.p, (int)und, ws.adu.p, ws.adv.p, ws.adpos.p,
                            ws.tcu.p, ws.tcv.p, ws.dcnt);
     int64_t *isnew = ws.scan64.p, *newpos = ws.scan64.p + (nia + 1);
     if (nia > 0)
-        hipLaunchKernelGGL(k_classify_inserts, dim3(grid_for(nia)), dim3(256), 0, s, nia, ws.ikey_s.p,
+        hipLaunchKernelGGL(k_classify_inserts, dim3(grid_ch(nia)), dim3(256), 0, s, nia, ws.ikey_s.p,
                            ws.iw_s.p, B, F.off.p, F.col.p, F.doff.p, F.dcol.p, (int)und, isnew, ws.aiu.p,
                            ws.aiv.p, ws.aiw.p, ws.aipos.p, ws.dcnt);
     DG_HIP(hipGetLastError());
@@ -1017,17 +1113,17 @@ int apply_chunk(dg_graph *g, int64_t k, const int32_t *src, const int32_t *dst, 
     const int64_t killed_base_r = und ? 0 : ws.hcnt[C_AUX2 + 8], killed_diff_r = und ? 0 : ws.hcnt[C_AUX3 + 8];
     DG_TRY(counters_clear(g));
     if (ains > 0) {
-        hipLaunchKernelGGL(k_revive, dim3(grid_for(ains)), dim3(256), 0, s, ains, ws.aiu.p, ws.aiv.p,
+        hipLaunchKernelGGL(k_revive, dim3(grid_ch(ains)), dim3(256), 0, s, ains, ws.aiu.p, ws.aiv.p,
                            ws.aiw.p, ws.aipos.p, 0, F.off.p, F.col.p, F.w.p, F.doff.p, F.dcol.p, F.dw.p,
                            F.deg.p, F.ntomb.p, F.ttomb.p, B, (uint64_t *)nullptr, (int32_t *)nullptr,
                            ws.dcnt);
         if (!und)
-            hipLaunchKernelGGL(k_revive, dim3(grid_for(ains)), dim3(256), 0, s, ains, ws.aiu.p, ws.aiv.p,
+            hipLaunchKernelGGL(k_revive, dim3(grid_ch(ains)), dim3(256), 0, s, ains, ws.aiu.p, ws.aiv.p,
                                ws.aiw.p, ws.aipos.p, 1, R.off.p, R.col.p, R.w.p, R.doff.p, R.dcol.p,
                                R.dw.p, R.deg.p, R.ntomb.p, R.ttomb.p, B, ws.rkey.p, ws.rw.p,
                                ws.dcnt + 8);
         if (und)
-            hipLaunchKernelGGL(k_list_tc_inserts, dim3(grid_for(ains)), dim3(256), 0, s, ains, ws.aiu.p,
+            hipLaunchKernelGGL(k_list_tc_inserts, dim3(grid_ch(ains)), dim3(256), 0, s, ains, ws.aiu.p,
                                ws.aiv.p, ws.tcu.p + tcdel, ws.tcv.p + tcdel, ws.dcnt);
     }
     DG_HIP(hipGetLastError());

@@ -64,8 +64,7 @@ __global__ __launch_bounds__(256) void k_tc_delta(int64_t ne, const int32_t *eu,
                                                   const int64_t *__restrict__ off,
                                                   const int32_t *__restrict__ col,
                                                   const int64_t *__restrict__ doff,
-                                                  const int32_t *__restrict__ dcol,
-                                                  unsigned long long *sum6, unsigned long long *work) {
+                                                  const int32_t *__restrict__ dcol, int64_t *part) {
     const int64_t wave_global = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / WAVE;
     const int l = lane_id();
@@ -94,13 +93,38 @@ __global__ __launch_bounds__(256) void k_tc_delta(int64_t ne, const int32_t *eu,
             acc += (uint64_t)(6 / k);
         }
     }
+    // per-block partials (no contended atomics; summed in block order by k_tc_sum)
+    __shared__ uint64_t s_p[3][256 / WAVE];
     acc = wave_sum(acc);
     walked = wave_sum(walked);
     probes = wave_sum(probes);
+    const int wv = threadIdx.x / WAVE;
     if (l == 0) {
-        if (acc) atomicAdd(sum6, (unsigned long long)acc);
-        atomicAdd(&work[0], (unsigned long long)walked);
-        atomicAdd(&work[1], (unsigned long long)probes);
+        s_p[0][wv] = acc;
+        s_p[1][wv] = walked;
+        s_p[2][wv] = probes;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        uint64_t s = 0;
+        for (int q = 0; q < (int)blockDim.x / WAVE; ++q) s += s_p[threadIdx.x][q];
+        part[3 * (int64_t)blockIdx.x + threadIdx.x] = (int64_t)s;
+    }
+}
+
+// Sum of the per-block partials (triangle weight, entries walked, search steps).
+__global__ void k_tc_sum(const int64_t *part, int64_t nblocks, int64_t *out) {
+    __shared__ int64_t s[3][256];
+    for (int c = 0; c < 3; ++c) {
+        int64_t a = 0;
+        for (int64_t b = threadIdx.x; b < nblocks; b += blockDim.x) a += part[3 * b + c];
+        s[c][threadIdx.x] = a;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        int64_t a = 0;
+        for (int q = 0; q < (int)blockDim.x; ++q) a += s[threadIdx.x][q];
+        out[threadIdx.x] = a;
     }
 }
 
@@ -110,16 +134,18 @@ int tc_delta(dg_graph *g, const int32_t *eu, const int32_t *ev, int64_t ne, uint
     hipStream_t s = g->stream;
     Dir &F = g->fwd;
     DG_TRY(counters_clear(g));
-    unsigned long long *acc = reinterpret_cast<unsigned long long *>(g->ws.dcnt + C_TC0);
-    unsigned long long *work = reinterpret_cast<unsigned long long *>(g->ws.dcnt + C_AUX2);
     int64_t blocks = std::min<int64_t>((ne + 3) / 4, 16384);
+    DG_TRY(g->ws.bpart.ensure(3 * (size_t)blocks + 8));
     int ps = prof_begin("tc_delta", s);
     hipLaunchKernelGGL(k_tc_delta, dim3((unsigned)blocks), dim3(256), 0, s, ne, eu, ev, F.off.p, F.col.p,
-                       F.doff.p, F.dcol.p, acc, work);
+                       F.doff.p, F.dcol.p, g->ws.bpart.p);
     prof_end(ps, s, 0.0);
+    // counters C_AUX1, C_AUX2, C_AUX3 = 6 x changed triangles, entries walked, search steps
+    static_assert(C_AUX2 == C_AUX1 + 1 && C_AUX3 == C_AUX1 + 2, "three consecutive counters");
+    hipLaunchKernelGGL(k_tc_sum, dim3(1), dim3(256), 0, s, g->ws.bpart.p, blocks, g->ws.dcnt + C_AUX1);
     DG_HIP(hipGetLastError());
     DG_TRY(counters_read(g));
-    *sum6 = (uint64_t)g->ws.hcnt[C_TC0];
+    *sum6 = (uint64_t)g->ws.hcnt[C_AUX1];
     // per changed edge its endpoints' offsets (32 B); per entry of the shorter row
     // 4 B; per binary-search step into the longer row 4 B
     prof_add(ps, 32.0 * (double)ne + 4.0 * (double)g->ws.hcnt[C_AUX2] + 4.0 * (double)g->ws.hcnt[C_AUX3]);
