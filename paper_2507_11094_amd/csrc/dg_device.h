@@ -159,6 +159,11 @@ __device__ __forceinline__ int64_t block_reserve(int64_t *counter, int64_t v, Bl
     return r;
 }
 
+// Slot of a true predicate (one atomic per block and call; all threads call).
+__device__ __forceinline__ int64_t block_append(int64_t *counter, bool pred, BlockScratch &s) {
+    return block_reserve(counter, pred ? 1 : 0, s);
+}
+
 // counter += sum of v over the block (one atomic per block).
 __device__ __forceinline__ void block_count(int64_t *counter, int64_t v, BlockScratch &s) {
     int64_t tot;

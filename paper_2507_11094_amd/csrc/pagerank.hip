@@ -308,17 +308,17 @@ struct ReachOp {
     int32_t *next;
     int64_t *ncount;
     __device__ bool vtx(int32_t, int32_t &pay) const { pay = 0; return true; }
-    __device__ void edge(bool valid, int32_t, int32_t, int32_t x, int32_t) const {
+    __device__ bool edge(bool valid, int32_t, int32_t, int32_t x, int32_t) const {
         // plain load first: most edges reach vertices that are already marked
-        bool p = valid && stamp[x] != st && atomicExch(&stamp[x], st) != st;
-        int64_t slot = wave_append(ncount, p);
-        if (p) next[slot] = x;
+        return valid && stamp[x] != st && atomicExch(&stamp[x], st) != st;
     }
+    __device__ SinkTarget sink() const { return SinkTarget{next, ncount}; }
 };
 
 // Mark a list of vertices with stamp st; append the first-time ones to out.
 __global__ void k_mark_list(int64_t n, const int32_t *a, int32_t *stamp, int32_t st, int32_t *out,
                             int64_t *count) {
+    __shared__ BlockScratch sc;
     for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += gstride()) {
         int64_t i = base + threadIdx.x;
         bool p = false;
@@ -327,7 +327,7 @@ __global__ void k_mark_list(int64_t n, const int32_t *a, int32_t *stamp, int32_t
             v = a[i];
             p = atomicExch(&stamp[v], st) != st;
         }
-        int64_t slot = wave_append(count, p);
+        int64_t slot = block_append(count, p, sc);
         if (p) out[slot] = v;
     }
 }

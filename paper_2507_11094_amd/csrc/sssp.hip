@@ -46,7 +46,7 @@ struct RelaxOp {
         pay = d;
         return d < INF;
     }
-    __device__ void edge(bool valid, int32_t v, int32_t d, int32_t x, int32_t w) const {
+    __device__ bool edge(bool valid, int32_t v, int32_t d, int32_t x, int32_t w) const {
         bool push = false;
         if (valid) {
             uint64_t cand = sssp_pack(d + w, v);
@@ -58,9 +58,9 @@ struct RelaxOp {
                     push = atomicExch(&stamp[x], st) != st;
             }
         }
-        int64_t slot = wave_append(ncount, push);
-        if (push) next[slot] = x;
+        return push;
     }
+    __device__ SinkTarget sink() const { return SinkTarget{next, ncount}; }
 };
 
 // Decremental phase 1: cut children whose tree parent is the frontier vertex.
@@ -69,7 +69,7 @@ struct CutOp {
     int32_t *next;
     int64_t *ncount;
     __device__ bool vtx(int32_t, int32_t &pay) const { pay = 0; return true; }
-    __device__ void edge(bool valid, int32_t v, int32_t, int32_t x, int32_t) const {
+    __device__ bool edge(bool valid, int32_t v, int32_t, int32_t x, int32_t) const {
         bool cut = false;
         if (valid) {
             uint64_t k = key[x];
@@ -78,9 +78,9 @@ struct CutOp {
                 cut = true;
             }
         }
-        int64_t slot = wave_append(ncount, cut);
-        if (cut) next[slot] = x;
+        return cut;
     }
+    __device__ SinkTarget sink() const { return SinkTarget{next, ncount}; }
 };
 
 // Decremental phase 2: pull over in-edges (reverse store); the frontier holds the
@@ -88,12 +88,14 @@ struct CutOp {
 struct PullOp {
     uint64_t *key;
     __device__ bool vtx(int32_t, int32_t &pay) const { pay = 0; return true; }
-    __device__ void edge(bool valid, int32_t v, int32_t, int32_t x, int32_t w) const {
-        if (!valid) return;
+    __device__ bool edge(bool valid, int32_t v, int32_t, int32_t x, int32_t w) const {
+        if (!valid) return false;
         int32_t dx = sssp_dist(__atomic_load_n(&key[x], __ATOMIC_RELAXED));
-        if (dx >= INF) return;
+        if (dx >= INF) return false;
         atomicMin((unsigned long long *)&key[v], (unsigned long long)sssp_pack(dx + w, x));
+        return false;
     }
+    __device__ SinkTarget sink() const { return SinkTarget{}; }
 };
 
 // ---- plain kernels ---------------------------------------------------------------
@@ -105,6 +107,7 @@ __global__ void k_sssp_init(int32_t n, uint64_t *key, int32_t source) {
 // OnDelete: (u, v) deleted and parent[v] == u  ->  v := (INF, -1), v is a seed.
 __global__ void k_sssp_on_delete(int64_t na, const int32_t *adu, const int32_t *adv, uint64_t *key,
                                  int32_t *seeds, int64_t *count) {
+    __shared__ BlockScratch sc;
     for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < na; base += gstride()) {
         int64_t i = base + threadIdx.x;
         bool cut = false;
@@ -116,7 +119,7 @@ __global__ void k_sssp_on_delete(int64_t na, const int32_t *adu, const int32_t *
                 cut = true;
             }
         }
-        int64_t slot = wave_append(count, cut);
+        int64_t slot = block_append(count, cut, sc);
         if (cut) seeds[slot] = v;
     }
 }
@@ -124,6 +127,7 @@ __global__ void k_sssp_on_delete(int64_t na, const int32_t *adu, const int32_t *
 // After the pull: cut vertices that now have a finite distance start the push.
 __global__ void k_sssp_pulled(int64_t nc, const int32_t *cut, const uint64_t *key, int32_t *stamp,
                               int32_t st, int32_t *front, int64_t *count) {
+    __shared__ BlockScratch sc;
     for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < nc; base += gstride()) {
         int64_t i = base + threadIdx.x;
         bool p = false;
@@ -132,7 +136,7 @@ __global__ void k_sssp_pulled(int64_t nc, const int32_t *cut, const uint64_t *ke
             v = cut[i];
             p = sssp_dist(key[v]) < INF && atomicExch(&stamp[v], st) != st;
         }
-        int64_t slot = wave_append(count, p);
+        int64_t slot = block_append(count, p, sc);
         if (p) front[slot] = v;
     }
 }
@@ -141,6 +145,7 @@ __global__ void k_sssp_pulled(int64_t nc, const int32_t *cut, const uint64_t *ke
 __global__ void k_sssp_on_add(int64_t na, const int32_t *aiu, const int32_t *aiv, const int32_t *aiw,
                               uint64_t *key, int32_t *stamp, int32_t st, int32_t *front,
                               int64_t *count) {
+    __shared__ BlockScratch sc;
     for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < na; base += gstride()) {
         int64_t i = base + threadIdx.x;
         bool p = false;
@@ -155,7 +160,7 @@ __global__ void k_sssp_on_add(int64_t na, const int32_t *aiu, const int32_t *aiv
                 if (cand < old && sssp_dist(cand) < sssp_dist(old)) p = atomicExch(&stamp[v], st) != st;
             }
         }
-        int64_t slot = wave_append(count, p);
+        int64_t slot = block_append(count, p, sc);
         if (p) front[slot] = v;
     }
 }
@@ -216,6 +221,7 @@ static ExpandArgs make_args(dg_graph *g, const Dir &d, const int32_t *F, int64_t
 // Improved vertices (count on the device) -> near (dist < T) or the far pile.
 __global__ void k_nf_split(const int64_t *nn_p, const int32_t *N, const uint64_t *key, int32_t T, int32_t *near,
                            int64_t *nnear, int32_t *far, int64_t *nfar, int32_t *farflag, int32_t fst) {
+    __shared__ BlockScratch sc;
     const int64_t nn = *nn_p;
     for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < nn; base += gstride()) {
         const int64_t i = base + threadIdx.x;
@@ -226,9 +232,9 @@ __global__ void k_nf_split(const int64_t *nn_p, const int32_t *N, const uint64_t
             pn = sssp_dist(key[v]) < T;
             pf = !pn && atomicExch(&farflag[v], fst) != fst;
         }
-        const int64_t sn = wave_append(nnear, pn);
+        const int64_t sn = block_append(nnear, pn, sc);
         if (pn) near[sn] = v;
-        const int64_t sf = wave_append(nfar, pf);
+        const int64_t sf = block_append(nfar, pf, sc);
         if (pf) far[sf] = v;
     }
 }
@@ -247,6 +253,7 @@ __global__ void k_nf_min(int64_t nf, const int32_t *far, const uint64_t *key, in
 // Next bucket: entries in [T0, T1) go near, entries >= T1 stay, the rest are stale.
 __global__ void k_nf_refill(int64_t nf, const int32_t *far, const uint64_t *key, int32_t T0, int32_t T1,
                             int32_t *near, int64_t *nnear, int32_t *far2, int64_t *nfar2, int32_t *farflag) {
+    __shared__ BlockScratch sc;
     for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < nf; base += gstride()) {
         const int64_t i = base + threadIdx.x;
         bool pn = false, pk = false;
@@ -258,9 +265,9 @@ __global__ void k_nf_refill(int64_t nf, const int32_t *far, const uint64_t *key,
             pn = !pk && d >= T0;
             if (!pk) farflag[v] = 0;
         }
-        const int64_t sn = wave_append(nnear, pn);
+        const int64_t sn = block_append(nnear, pn, sc);
         if (pn) near[sn] = v;
-        const int64_t sk = wave_append(nfar2, pk);
+        const int64_t sk = block_append(nfar2, pk, sc);
         if (pk) far2[sk] = v;
     }
 }
@@ -458,7 +465,7 @@ struct CutListOp {
     int32_t *list;
     int64_t *lcount;
     __device__ bool vtx(int32_t, int32_t &pay) const { pay = 0; return true; }
-    __device__ void edge(bool valid, int32_t v, int32_t, int32_t x, int32_t) const {
+    __device__ bool edge(bool valid, int32_t v, int32_t, int32_t x, int32_t) const {
         bool cut = false;
         if (valid) {
             uint64_t k = key[x];
@@ -467,11 +474,9 @@ struct CutListOp {
                 cut = true;
             }
         }
-        int64_t slot = wave_append(ncount, cut);
-        if (cut) next[slot] = x;
-        int64_t ls = wave_append(lcount, cut);
-        if (cut) list[ls] = x;
+        return cut;
     }
+    __device__ SinkTarget sink() const { return SinkTarget{next, ncount, list, lcount}; }
 };
 
 // RelaxOp with the round's stamp read from device memory.
@@ -486,7 +491,7 @@ struct RelaxOpD {
         pay = d;
         return d < INF;
     }
-    __device__ void edge(bool valid, int32_t v, int32_t d, int32_t x, int32_t w) const {
+    __device__ bool edge(bool valid, int32_t v, int32_t d, int32_t x, int32_t w) const {
         bool push = false;
         if (valid) {
             uint64_t cand = sssp_pack(d + w, v);
@@ -498,13 +503,14 @@ struct RelaxOpD {
                 }
             }
         }
-        int64_t slot = wave_append(ncount, push);
-        if (push) next[slot] = x;
+        return push;
     }
+    __device__ SinkTarget sink() const { return SinkTarget{next, ncount}; }
 };
 
 __global__ void k_sssp_pulled_d(const int64_t *nc_p, const int32_t *cut, const uint64_t *key, int32_t *stamp,
                                 const int64_t *stp, int32_t *front, int64_t *count) {
+    __shared__ BlockScratch sc;
     const int64_t nc = *nc_p;
     const int32_t st = (int32_t)*stp;
     for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < nc; base += gstride()) {
@@ -515,13 +521,14 @@ __global__ void k_sssp_pulled_d(const int64_t *nc_p, const int32_t *cut, const u
             v = cut[i];
             p = sssp_dist(key[v]) < INF && atomicExch(&stamp[v], st) != st;
         }
-        int64_t slot = wave_append(count, p);
+        int64_t slot = block_append(count, p, sc);
         if (p) front[slot] = v;
     }
 }
 
 __global__ void k_sssp_on_add_d(const int64_t *na_p, const int32_t *aiu, const int32_t *aiv, const int32_t *aiw,
                                 uint64_t *key, int32_t *stamp, const int64_t *stp, int32_t *front, int64_t *count) {
+    __shared__ BlockScratch sc;
     const int64_t na = *na_p;
     const int32_t st = (int32_t)*stp;
     for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < na; base += gstride()) {
@@ -538,7 +545,7 @@ __global__ void k_sssp_on_add_d(const int64_t *na_p, const int32_t *aiu, const i
                 if (cand < old && sssp_dist(cand) < sssp_dist(old)) p = atomicExch(&stamp[v], st) != st;
             }
         }
-        int64_t slot = wave_append(count, p);
+        int64_t slot = block_append(count, p, sc);
         if (p) front[slot] = v;
     }
 }

@@ -35,13 +35,60 @@ struct ExpandArgs {
     int chunk;
 };
 
+// Output of an expansion: vertices the op selects go to `out` (and `out2`, when
+// set) with their lengths in `count` / `count2`.
+struct SinkTarget {
+    int32_t *out = nullptr;
+    int64_t *count = nullptr;
+    int32_t *out2 = nullptr;
+    int64_t *count2 = nullptr;
+};
+
+// Per-wave staging of selected vertices in LDS: one atomic per WB_CAP entries
+// instead of one per 64-edge step (same-address atomics serialise).
+constexpr int WB_CAP = 256;
+struct WaveSink {
+    int32_t *buf;
+    int n;
+    SinkTarget t;
+    __device__ __forceinline__ void flush() {
+        if (n == 0) return;
+        __builtin_amdgcn_wave_barrier();
+        int64_t b1 = 0, b2 = 0;
+        if (lane_id() == 0) {
+            b1 = (int64_t)atomicAdd((unsigned long long *)t.count, (unsigned long long)n);
+            if (t.out2) b2 = (int64_t)atomicAdd((unsigned long long *)t.count2, (unsigned long long)n);
+        }
+        b1 = __shfl(b1, 0, WAVE);
+        b2 = __shfl(b2, 0, WAVE);
+        for (int j = lane_id(); j < n; j += WAVE) {
+            const int32_t x = buf[j];
+            t.out[b1 + j] = x;
+            if (t.out2) t.out2[b2 + j] = x;
+        }
+        __builtin_amdgcn_wave_barrier();
+        n = 0;
+    }
+    __device__ __forceinline__ void push(bool p, int32_t x) {
+        const uint64_t m = ballot(p);
+        const int c = __popcll(m);
+        if (c == 0) return;
+        if (n + c > WB_CAP) flush();
+        if (p) buf[n + __popcll(m & lanemask_lt())] = x;
+        n += c;
+    }
+};
+
 // Op interface:
 //   __device__ bool vtx(int32_t v, int32_t &payload)  -- false: skip v
-//   __device__ void edge(bool valid, int32_t v, int32_t payload, int32_t x, int32_t w)
-// edge() is called by every lane of the wave in lock-step (valid marks real edges)
-// so it may use wave-wide appends.
+//   __device__ bool edge(bool valid, int32_t v, int32_t payload, int32_t x, int32_t w)
+//        -- true: x goes to the op's sink
+//   __device__ SinkTarget sink() const                 -- out == nullptr: no output
+// edge() is called by every lane of the wave in lock-step (valid marks real edges).
 template <class Op>
 __global__ __launch_bounds__(256) void k_expand(ExpandArgs a, Op op) {
+    __shared__ int32_t s_sink[256 / WAVE][WB_CAP];
+    WaveSink sk{s_sink[threadIdx.x / WAVE], 0, op.sink()};
     const int64_t wave_global = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / WAVE;
     const int l = lane_id();
@@ -100,14 +147,18 @@ __global__ __launch_bounds__(256) void k_expand(ExpandArgs a, Op op) {
                 valid = !(c & DEAD);
                 x = (int32_t)(c & ID_MASK);
             }
-            op.edge(valid, vo, po, x, wt);
+            const bool p = op.edge(valid, vo, po, x, wt);
+            if (sk.t.out) sk.push(p, x);
         }
     }
+    if (sk.t.out) sk.flush();
 }
 
 // One wave per heavy chunk (grid-stride over the queue).
 template <class Op>
 __global__ __launch_bounds__(256) void k_expand_heavy(ExpandArgs a, Op op) {
+    __shared__ int32_t s_sink[256 / WAVE][WB_CAP];
+    WaveSink sk{s_sink[threadIdx.x / WAVE], 0, op.sink()};
     const int64_t wave_global = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / WAVE;
     const int l = lane_id();
@@ -135,9 +186,11 @@ __global__ __launch_bounds__(256) void k_expand_heavy(ExpandArgs a, Op op) {
                 valid = !(cc & DEAD);
                 x = (int32_t)(cc & ID_MASK);
             }
-            op.edge(valid, v, pay, x, wt);
+            const bool p = op.edge(valid, v, pay, x, wt);
+            if (sk.t.out) sk.push(p, x);
         }
     }
+    if (sk.t.out) sk.flush();
 }
 
 // Host side: run one expansion step of `op` over frontier F (nf entries).

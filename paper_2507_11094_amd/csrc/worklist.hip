@@ -386,12 +386,14 @@ __global__ void k_wl_seed_sources(WorkQ wq, const int32_t *src, int64_t ns, int3
 struct WlPullOp {
     uint64_t *key;
     __device__ bool vtx(int32_t, int32_t &pay) const { pay = 0; return true; }
-    __device__ void edge(bool valid, int32_t v, int32_t, int32_t x, int32_t w) const {
-        if (!valid) return;
+    __device__ bool edge(bool valid, int32_t v, int32_t, int32_t x, int32_t w) const {
+        if (!valid) return false;
         int32_t dx = sssp_dist(__atomic_load_n(&key[x], __ATOMIC_RELAXED));
-        if (dx >= INF) return;
+        if (dx >= INF) return false;
         atomicMin((unsigned long long *)&key[v], (unsigned long long)sssp_pack(dx + w, x));
+        return false;
     }
+    __device__ SinkTarget sink() const { return SinkTarget{}; }
 };
 
 // ---- host side ---------------------------------------------------------------------------
