@@ -306,6 +306,17 @@ __device__ __forceinline__ void merge_put(int32_t *col2, int32_t *w2, int64_t ca
     }
 }
 
+constexpr int MG_DCAP = 1024;  // diff entries of a tile's rows staged in LDS (else read from memory)
+
+__device__ __forceinline__ int lds_lower(const int32_t *a, int lo, int hi, uint32_t v) {
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (((uint32_t)a[mid] & ID_MASK) < v) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
 __global__ __launch_bounds__(MG_THREADS) void k_merge_tiles(
     int32_t n, const int32_t *__restrict__ mp_row, const int64_t *__restrict__ mp_edge,
     const int64_t *__restrict__ off, const int32_t *__restrict__ col, const int32_t *__restrict__ w,
@@ -315,9 +326,11 @@ __global__ __launch_bounds__(MG_THREADS) void k_merge_tiles(
     __shared__ int32_t s_off[MG_ITEMS + 1];  // row start - e0 (row 0: -1 when it began earlier)
     __shared__ int32_t s_o2[MG_ITEMS + 1];   // off2[r] - off2[r0]
     __shared__ int32_t s_rb[MG_ITEMS + 1];   // RB[r] - RB[r0]
-    __shared__ int32_t s_dn[MG_ITEMS + 1];   // diff entries of row r
+    __shared__ int32_t s_dlo[MG_ITEMS + 2];  // doff[r] - doff[r0]
+    __shared__ int32_t s_col[MG_ITEMS];      // the tile's entries
+    __shared__ int32_t s_dc[MG_DCAP], s_dw[MG_DCAP];
     __shared__ int32_t s_wd[MG_IPT][MG_WAVES];
-    __shared__ int64_t s_base[4];            // off[r0], off2[r0], RB[r0], tombstones before e0
+    __shared__ int64_t s_base[5];            // off[r0], off2[r0], RB[r0], tombstones before e0, doff[r0]
     const int64_t b = blockIdx.x;
     const int32_t r0 = mp_row[b], r1 = mp_row[b + 1];
     const int64_t e0 = mp_edge[b];
@@ -334,19 +347,30 @@ __global__ __launch_bounds__(MG_THREADS) void k_merge_tiles(
         const bool valid = j < ne;
         c[u] = valid ? (uint32_t)col[e0 + j] : 0u;
         wt[u] = valid ? w[e0 + j] : 0;
+        if (valid) s_col[j] = (int32_t)c[u];
         const uint64_t bm = ballot(valid && (c[u] & DEAD));
         lp[u] = __popcll(bm & lanemask_lt());
         if (l == 0) s_wd[u][wv] = __popcll(bm);
     }
     // rows r0 .. r1 (r1: the row still open at the tile's end, if any)
-    for (int i = t; i <= nr; i += MG_THREADS) {
+    const int64_t dbase = doff[r0];
+    for (int i = t; i <= nr + 1; i += MG_THREADS) {
         const int32_t r = r0 + i;
+        if (r <= n) s_dlo[i] = (int32_t)(doff[r] - dbase);
+        if (i > nr) continue;
         const int64_t o = off[r] - e0;
         s_off[i] = (int32_t)(o < 0 ? -1 : o);
         s_o2[i] = (int32_t)(off2[r] - off2[r0]);
         s_rb[i] = (int32_t)(RB[r] - RB[r0]);
-        s_dn[i] = r < n ? (int32_t)(doff[r + 1] - doff[r]) : 0;
     }
+    // the diff entries of the tile's rows (one contiguous range of the diff level)
+    const int64_t ndt = doff[min(r1 + 1, n)] - dbase;
+    const bool dlds = ndt <= MG_DCAP;
+    if (dlds)
+        for (int q = t; q < ndt; q += MG_THREADS) {
+            s_dc[q] = dcol[dbase + q];
+            s_dw[q] = dw[dbase + q];
+        }
     if (wv == 0) {
         // tombstones before e0: counter blocks before its block + a ballot count inside it
         const int64_t st = (e0 / TILE) * TILE;
@@ -360,6 +384,7 @@ __global__ __launch_bounds__(MG_THREADS) void k_merge_tiles(
             s_base[1] = off2[r0];
             s_base[2] = RB[r0];
             s_base[3] = TB[e0 / TILE] + cd;
+            s_base[4] = dbase;
         }
     }
     __syncthreads();
@@ -380,29 +405,33 @@ __global__ __launch_bounds__(MG_THREADS) void k_merge_tiles(
             if (s_off[mid] <= j) lo = mid;
             else hi = mid - 1;
         }
-        const int32_t r = r0 + lo;
         const int64_t ro = lo == 0 ? s_base[0] : e0 + s_off[lo];
         const int64_t rank = (i - ro) - (deadG - (s_base[2] + s_rb[lo]));
         const int64_t ob = s_base[1] + s_o2[lo];
         const uint32_t cu = c[u];
         const uint32_t cur = cu & ID_MASK;
         const bool dead = cu & DEAD;
-        if (s_dn[lo] == 0) {
+        const int dl = s_dlo[lo], dh = s_dlo[lo + 1];  // this row's diff entries (tile-relative)
+        if (dl == dh) {
             if (!dead) merge_put(col2, w2, cap, ob + rank, (int32_t)cu, wt[u], cnt);
             continue;
         }
         // rows with diff entries: interleave them at their insertion points
-        const int64_t dlo = doff[r], dhi = doff[r + 1];
-        if (!dead) merge_put(col2, w2, cap, ob + rank + (lower_sorted(dcol, dlo, dhi, cur) - dlo), (int32_t)cu,
-                             wt[u], cnt);
-        int64_t a = dlo;
-        if (i > ro) a = lower_sorted(dcol, dlo, dhi, ((uint32_t)col[i - 1] & ID_MASK) + 1);
-        const int64_t bq = lower_sorted(dcol, dlo, dhi, cur);
-        for (int64_t q = a; q < bq; ++q) merge_put(col2, w2, cap, ob + rank + (q - dlo), dcol[q], dw[q], cnt);
-        if (i == off[r + 1] - 1) {  // after the row's last base entry: the diff tail
+        auto lower = [&](uint32_t v) -> int {
+            return dlds ? lds_lower(s_dc, dl, dh, v) : (int)(lower_sorted(dcol, dbase + dl, dbase + dh, v) - dbase);
+        };
+        auto put_diff = [&](int q, int64_t o) {
+            merge_put(col2, w2, cap, o, dlds ? s_dc[q] : dcol[dbase + q], dlds ? s_dw[q] : dw[dbase + q], cnt);
+        };
+        const int bq = lower(cur);
+        if (!dead) merge_put(col2, w2, cap, ob + rank + (bq - dl), (int32_t)cu, wt[u], cnt);
+        int a = dl;
+        if (i > ro) a = lower(((uint32_t)(j > 0 ? s_col[j - 1] : col[i - 1]) & ID_MASK) + 1);
+        for (int q = a; q < bq; ++q) put_diff(q, ob + rank + (q - dl));
+        const int64_t rend = lo < nr ? e0 + s_off[lo + 1] : off[r0 + lo + 1];
+        if (i == rend - 1) {  // after the row's last base entry: the diff tail
             const int64_t after = rank + (dead ? 0 : 1);
-            for (int64_t q = lower_sorted(dcol, dlo, dhi, cur + 1); q < dhi; ++q)
-                merge_put(col2, w2, cap, ob + after + (q - dlo), dcol[q], dw[q], cnt);
+            for (int q = lower(cur + 1); q < dh; ++q) put_diff(q, ob + after + (q - dl));
         }
     }
 }
