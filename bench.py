@@ -274,7 +274,7 @@ def run_single(args, kind: str) -> int:
               "batch": k, "insert_fraction": 0.5, "parallelism": "1 gpu",
               "heavy_degree": args.heavy_degree or 512, "sssp_persistent": persistent, "sssp_delta": delta,
               "pr_mode": args.pr_mode,
-              "pr_pull": ["merge-path tiles", "vertex waves"][args.pr_pull]}
+              "pr_pull": ["merge-path tiles", "vertex waves", "merge-path tiles, non-temporal streams"][args.pr_pull]}
     if kind == "tc":
         config.update({"undirected_edges": int(s.size), "batch_fraction": args.pct, "queries": ["triangles"]})
     else:
@@ -421,8 +421,9 @@ def run_batched(args) -> int:
 
     static = None
     if not args.no_static:
-        # static comparator: the same batch applied, then every member's SSSP from scratch
-        kk, cols = dfwd if (W + K) % 2 == 0 else dbwd
+        # static comparator: a fresh set (the initial graphs), the forward batches
+        # applied, then every member's SSSP from scratch
+        kk, cols = dfwd
         cfg2 = dg.Config()
         S2 = dg.GraphSet(members, config=cfg2)
         torch.cuda.synchronize()
@@ -679,7 +680,7 @@ def main() -> int:
                     help="near-far bucket width of the frontier SSSP (0: plain rounds; -1: grid 8000, else 0)")
     ap.add_argument("--pr-mode", type=int, default=0, help="PageRank form after a batch: 0 auto, 1 local, 2 global")
     ap.add_argument("--pr-pull", type=int, default=0,
-                    help="whole-graph PageRank pull: 0 merge-path tiles, 1 per-vertex waves")
+                    help="whole-graph PageRank pull: 0 merge-path tiles, 1 per-vertex waves, 2 tiles with non-temporal streams")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run five plain 256 MiB device-to-device copies (reference for the "
                          "FETCH_SIZE / WRITE_SIZE counter scale) and exit")

@@ -86,7 +86,9 @@ typedef struct dg_config {
     int32_t pr_mode;
     /* Whole-graph PageRank pull (static solve and the global form): 0 = merge-path
      * tiles (equal rows + entries per workgroup, default), 1 = the per-vertex wave
-     * kernel that the affected-set iteration uses.  Same results up to rounding. */
+     * kernel that the affected-set iteration uses, 2 = merge-path tiles reading the
+     * column and offset streams with non-temporal hints.  Same results up to
+     * rounding (0 and 2: bit-identical). */
     int32_t pr_pull;
     /* Frontier-step SSSP schedule: 0 = plain Bellman-Ford rounds (default);
      * > 0 = near-far buckets of this width (vertices at distance >= the current

@@ -393,6 +393,24 @@ __global__ void k_mp_partition(const int64_t *__restrict__ off, int32_t n, int64
     }
 }
 
+// STREAM: the column and offset streams are read, and the results written, with
+// non-temporal hints, so that they do not displace the gathered contributions
+// from L2.
+template <bool STREAM>
+__device__ __forceinline__ int32_t ld_stream(const int32_t *p) {
+    return STREAM ? __builtin_nontemporal_load(p) : *p;
+}
+template <bool STREAM>
+__device__ __forceinline__ int64_t ld_stream(const int64_t *p) {
+    return STREAM ? __builtin_nontemporal_load(p) : *p;
+}
+template <bool STREAM>
+__device__ __forceinline__ void st_stream(double *p, double v) {
+    if (STREAM) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
+template <bool STREAM>
 __global__ __launch_bounds__(MP_THREADS) void k_pr_tiles(const int32_t *__restrict__ mp_row,
                                                          const int64_t *__restrict__ mp_edge,
                                                          const int64_t *__restrict__ off,
@@ -418,11 +436,11 @@ __global__ __launch_bounds__(MP_THREADS) void k_pr_tiles(const int32_t *__restri
 #pragma unroll
     for (int u = 0; u < MP_IPT; ++u) {
         const int j = t + u * MP_THREADS;
-        c[u] = j < ne ? (uint32_t)col[e0 + j] : DEAD;
+        c[u] = j < ne ? (uint32_t)ld_stream<STREAM>(&col[e0 + j]) : DEAD;
     }
     // row starts relative to the tile (-1: the row began in an earlier tile)
     for (int i = t; i <= nr; i += MP_THREADS) {
-        const int64_t o = off[r0 + i] - e0;
+        const int64_t o = ld_stream<STREAM>(&off[r0 + i]) - e0;
         s_off[i] = (int32_t)(o < 0 ? -1 : o);
     }
     double v[MP_IPT];
@@ -445,7 +463,7 @@ __global__ __launch_bounds__(MP_THREADS) void k_pr_tiles(const int32_t *__restri
         double acc = 0.0;
         for (int32_t j = lo; j < hi; ++j) acc += s_val[j];
         if (s_off[i] < 0) pf[b] = acc;
-        else xn[r0 + i] = base + damp * acc;
+        else st_stream<STREAM>(&xn[r0 + i], base + damp * acc);
     }
     __syncthreads();
     // long pieces, then the piece of the row left open at the tile's end, one wave each
@@ -466,7 +484,7 @@ __global__ __launch_bounds__(MP_THREADS) void k_pr_tiles(const int32_t *__restri
         if (l == 0) {
             if (k == nlong) pl[b] = acc;
             else if (s_off[s_long[k]] < 0) pf[b] = acc;
-            else xn[r0 + s_long[k]] = base + damp * acc;
+            else st_stream<STREAM>(&xn[r0 + s_long[k]], base + damp * acc);
         }
     }
 }
@@ -563,7 +581,7 @@ static int pr_iterate(dg_graph *g, const int32_t *A, int64_t na, int64_t edges, 
     DG_HIP(hipGetLastError());
     // every vertex pulled: merge-path tiles over the base level, then the diff level
     const Dir &R = *g->rev;
-    const bool tiles = A == nullptr && g->cfg.pr_pull == 0;
+    const bool tiles = A == nullptr && g->cfg.pr_pull != 1;
     int64_t nb = 0;
     if (tiles) {
         nb = ((int64_t)g->n + R.m + MP_ITEMS - 1) / MP_ITEMS;
@@ -592,7 +610,8 @@ static int pr_iterate(dg_graph *g, const int32_t *A, int64_t na, int64_t edges, 
             if (tiles) {
                 // tiles: off 8 + xn 8 per row, col 4 + contrib 8 per base entry
                 ps = prof_begin("pr_tiles", s);
-                hipLaunchKernelGGL(k_pr_tiles, dim3((unsigned)nb), dim3(MP_THREADS), 0, s, ws.mp_row.p,
+                hipLaunchKernelGGL(g->cfg.pr_pull == 2 ? k_pr_tiles<true> : k_pr_tiles<false>, dim3((unsigned)nb),
+                                   dim3(MP_THREADS), 0, s, ws.mp_row.p,
                                    ws.mp_edge.p, R.off.p, R.col.p, contrib, prs + 2, damping, xn, pf, pl, done);
                 prof_end(ps, s, 16.0 * (double)g->n + 12.0 * (double)R.m);
                 hipLaunchKernelGGL(k_pr_fixup, dim3(grid_for(nb)), dim3(256), 0, s, nb, ws.mp_row.p,

@@ -336,10 +336,11 @@ def hub_graph(n=1 << 14, hub_in=12000, seed=11):
     return n, s, d, w
 
 
-@pytest.mark.parametrize("pull", [0, 1])
+@pytest.mark.parametrize("pull", [0, 1, 2])
 def test_pagerank_whole_graph_pull(pull):
-    """Static solve and global-form updates, merge-path tiles (0) or per-vertex
-    waves (1), with a live diff level (no merges), against the oracle."""
+    """Static solve and global-form updates, merge-path tiles (0), per-vertex waves
+    (1) or tiles with non-temporal streams (2), with a live diff level (no merges),
+    against the oracle."""
     n, s, d, w = hub_graph()
     say("pagerank whole-graph pull", pull, "arcs", s.size)
     c = cfg(merge=1e9)
