@@ -274,7 +274,7 @@ def run_single(args, kind: str) -> int:
               "batch": k, "insert_fraction": 0.5, "parallelism": "1 gpu",
               "heavy_degree": args.heavy_degree or 512, "sssp_persistent": persistent, "sssp_delta": delta,
               "pr_mode": args.pr_mode,
-              "pr_pull": ["merge-path tiles", "vertex waves", "merge-path tiles, non-temporal streams"][args.pr_pull]}
+              "pr_pull": ["merge-path tiles, non-temporal streams", "vertex waves", "merge-path tiles"][args.pr_pull]}
     if kind == "tc":
         config.update({"undirected_edges": int(s.size), "batch_fraction": args.pct, "queries": ["triangles"]})
     else:
@@ -680,7 +680,8 @@ def main() -> int:
                     help="near-far bucket width of the frontier SSSP (0: plain rounds; -1: grid 8000, else 0)")
     ap.add_argument("--pr-mode", type=int, default=0, help="PageRank form after a batch: 0 auto, 1 local, 2 global")
     ap.add_argument("--pr-pull", type=int, default=0,
-                    help="whole-graph PageRank pull: 0 merge-path tiles, 1 per-vertex waves, 2 tiles with non-temporal streams")
+                    help="whole-graph PageRank pull: 0 merge-path tiles with non-temporal streams, 1 per-vertex "
+                         "waves, 2 merge-path tiles without the hints")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run five plain 256 MiB device-to-device copies (reference for the "
                          "FETCH_SIZE / WRITE_SIZE counter scale) and exit")

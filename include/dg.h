@@ -55,6 +55,8 @@ extern "C" {
 #define DG_DIRECTED 0u
 #define DG_UNDIRECTED 1u     /* graph_create: each edge given once, stored both ways */
 #define DG_DEVICE_PTRS 2u    /* pointer arguments of this call are device memory     */
+#define DG_INCREMENTAL 4u    /* apply_batch: every update is an insertion (op may be NULL) */
+#define DG_DECREMENTAL 8u    /* apply_batch: every update is a deletion (op may be NULL)   */
 
 typedef struct dg_graph dg_graph;
 typedef struct dg_query dg_query;
@@ -85,17 +87,21 @@ typedef struct dg_config {
      * restricted form), 1 = always local, 2 = always global. */
     int32_t pr_mode;
     /* Whole-graph PageRank pull (static solve and the global form): 0 = merge-path
-     * tiles (equal rows + entries per workgroup, default), 1 = the per-vertex wave
-     * kernel that the affected-set iteration uses, 2 = merge-path tiles reading the
-     * column and offset streams with non-temporal hints.  Same results up to
-     * rounding (0 and 2: bit-identical). */
+     * tiles (equal rows + entries per workgroup; column and offset streams read
+     * with non-temporal hints so they do not evict the gathered values from L2;
+     * default), 1 = the per-vertex wave kernel that the affected-set iteration
+     * uses, 2 = merge-path tiles without the hints.  Same results up to rounding
+     * (0 and 2: bit-identical). */
     int32_t pr_pull;
     /* Frontier-step SSSP schedule: 0 = plain Bellman-Ford rounds (default);
      * > 0 = near-far buckets of this width (vertices at distance >= the current
      * threshold wait in a far pile until the nearer ones settle), which cuts the
      * re-relaxations of high-diameter graphs such as road networks.  Same result. */
     int32_t sssp_delta;
-    int32_t reserved[4];
+    /* > 0: also merge after this many batches since the last merge (Section 3.5
+     * merges after a configurable number of batches); 0 = threshold only. */
+    int32_t merge_period;
+    int32_t reserved[3];
 } dg_config;
 
 /* Per-batch statistics and phase timings (HIP events on the graph's stream). */
@@ -167,7 +173,10 @@ int dg_graph_merge(dg_graph *g);
  * take unordered pairs.  A self-loop, an id outside [0, n), an op other than 0/1
  * or a weight outside [1, 2^30) anywhere in a chunk rejects that chunk with
  * DG_EINVAL before any change (earlier chunks stay applied).  flags may hold
- * DG_DEVICE_PTRS.  stats may be NULL. */
+ * DG_DEVICE_PTRS and one of DG_INCREMENTAL / DG_DECREMENTAL (the paper's
+ * partially dynamic cases, Section 3.2: only additions or only deletions); with
+ * a mode op may be NULL, and an op that differs from the mode rejects the chunk.
+ * stats may be NULL. */
 int dg_apply_batch(dg_graph *g, int64_t k, const int32_t *src, const int32_t *dst,
                    const int32_t *w, const uint8_t *op, int64_t batch_size, uint32_t flags,
                    dg_batch_stats *stats);

@@ -30,6 +30,8 @@ DG_INF = 1073741823
 DG_DIRECTED = 0
 DG_UNDIRECTED = 1
 DG_DEVICE_PTRS = 2
+DG_INCREMENTAL = 4
+DG_DECREMENTAL = 8
 
 # Every symbol include/dg.h declares (checked by the tests against the .so).
 EXPORTS = (
@@ -56,7 +58,8 @@ class Config(ctypes.Structure):
     _fields_ = [("merge_threshold", ctypes.c_double), ("pr_tol_scale", ctypes.c_double),
                 ("heavy_degree", ctypes.c_int32), ("persistent_groups", ctypes.c_int32),
                 ("sssp_persistent", ctypes.c_int32), ("pr_mode", ctypes.c_int32),
-                ("pr_pull", ctypes.c_int32), ("sssp_delta", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+                ("pr_pull", ctypes.c_int32), ("sssp_delta", ctypes.c_int32), ("merge_period", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 3)]
 
 
 class KernelProf(ctypes.Structure):
@@ -185,7 +188,8 @@ def dg_graph_create(n, src, dst, w=None, flags=DG_DIRECTED, cfg: Config | None =
     return out
 
 
-def dg_apply_batch(g, src, dst, w, op, batch_size=0):
+def dg_apply_batch(g, src, dst, w, op, batch_size=0, mode=0):
+    """mode: 0, DG_INCREMENTAL or DG_DECREMENTAL (op may then be None)."""
     lib = load_library()
     ps, ks, dev = _arr(src, np.int32)
     pd, kd, _ = _arr(dst, np.int32)
@@ -194,7 +198,7 @@ def dg_apply_batch(g, src, dst, w, op, batch_size=0):
     k = int(ks.numel() if _is_torch(ks) else ks.size)
     st = BatchStats()
     _check(lib.dg_apply_batch(g, k, ps, pd, pw, po, int(batch_size),
-                              DG_DEVICE_PTRS if dev else 0, ctypes.byref(st)))
+                              (DG_DEVICE_PTRS if dev else 0) | int(mode), ctypes.byref(st)))
     return st
 
 
@@ -284,8 +288,16 @@ class Graph:
     def set_stream(self, stream_ptr: int):
         _check(load_library().dg_graph_set_stream(self.handle, ctypes.c_void_p(stream_ptr)))
 
-    def apply(self, src, dst, w, op, batch_size=0) -> BatchStats:
-        return dg_apply_batch(self.handle, src, dst, w, op, batch_size)
+    def apply(self, src, dst, w, op, batch_size=0, mode=0) -> BatchStats:
+        return dg_apply_batch(self.handle, src, dst, w, op, batch_size, mode)
+
+    def insert(self, src, dst, w=None, batch_size=0) -> BatchStats:
+        """Incremental-only batch (DG_INCREMENTAL): every update is an insertion."""
+        return dg_apply_batch(self.handle, src, dst, w, None, batch_size, DG_INCREMENTAL)
+
+    def delete(self, src, dst, batch_size=0) -> BatchStats:
+        """Decremental-only batch (DG_DECREMENTAL): every update is a deletion."""
+        return dg_apply_batch(self.handle, src, dst, None, None, batch_size, DG_DECREMENTAL)
 
     def info(self):
         n = ctypes.c_int32()

@@ -246,14 +246,31 @@ int dg_apply_batch(dg_graph *g, int64_t k, const int32_t *src, const int32_t *ds
                    const uint8_t *op, int64_t batch_size, uint32_t flags, dg_batch_stats *stats) {
     DG_TRY(check_graph(g));
     if (stats) std::memset(stats, 0, sizeof(*stats));
-    if (k < 0 || (k > 0 && (!src || !dst || !op))) return set_error(DG_EINVAL, "bad batch arguments");
-    if (flags & ~(DG_DEVICE_PTRS)) return set_error(DG_EINVAL, "unknown flags");
+    if (flags & ~(DG_DEVICE_PTRS | DG_INCREMENTAL | DG_DECREMENTAL)) return set_error(DG_EINVAL, "unknown flags");
+    const uint32_t mode = flags & (DG_INCREMENTAL | DG_DECREMENTAL);
+    if (mode == (DG_INCREMENTAL | DG_DECREMENTAL))
+        return set_error(DG_EINVAL, "DG_INCREMENTAL and DG_DECREMENTAL together");
+    const int expect = mode == DG_INCREMENTAL ? 1 : (mode == DG_DECREMENTAL ? 0 : -1);
+    if (k < 0 || (k > 0 && (!src || !dst || (!op && expect < 0)))) return set_error(DG_EINVAL, "bad batch arguments");
     if (k > INT32_MAX / 4) return set_error(DG_EINVAL, "batch chunk too large");
     const bool dev = (flags & DG_DEVICE_PTRS) != 0;
+    // a mode without an op array: every update gets the mode's op
+    std::vector<uint8_t> hop;
+    DBuf<uint8_t> dop;
+    if (!op && k > 0) {
+        if (dev) {
+            DG_TRY(dop.ensure((size_t)k));
+            DG_HIP(hipMemsetAsync(dop.p, expect, (size_t)k, g->stream));
+            op = dop.p;
+        } else {
+            hop.assign((size_t)k, (uint8_t)expect);
+            op = hop.data();
+        }
+    }
     const int64_t bs = batch_size <= 0 ? std::max<int64_t>(k, 1) : batch_size;
     for (int64_t o = 0; o < k; o += bs) {
         int64_t kk = std::min(bs, k - o);
-        int rc = apply_chunk(g, kk, src + o, dst + o, w ? w + o : nullptr, op + o, dev, stats);
+        int rc = apply_chunk(g, kk, src + o, dst + o, w ? w + o : nullptr, op + o, dev, stats, expect);
         if (rc != DG_OK) return mark_device_error(g, rc);
     }
     return DG_OK;

@@ -168,6 +168,7 @@ struct dg_graph {
     dg::Dir fwd, rev_own;
     dg::Dir *rev = nullptr;  // == &fwd for undirected graphs
     int64_t m_live = 0;      // live arcs in fwd
+    int32_t since_merge = 0; // batches applied since the last merge
     hipStream_t stream = nullptr;
     dg_config cfg{};
     dg::Work ws;
@@ -213,8 +214,9 @@ namespace dg {
 int graph_build(dg_graph *g, int64_t m, const int32_t *src, const int32_t *dst, const int32_t *w);
 int graph_export(dg_graph *g, int64_t *m, int32_t *src, int32_t *dst, int32_t *w);
 int graph_merge(dg_graph *g);
+// expect_op >= 0: every op must equal it (partially dynamic modes), else DG_EINVAL.
 int apply_chunk(dg_graph *g, int64_t k, const int32_t *src, const int32_t *dst, const int32_t *w,
-                const uint8_t *op, bool dev, dg_batch_stats *st);
+                const uint8_t *op, bool dev, dg_batch_stats *st, int expect_op = -1);
 int counters_read(dg_graph *g);
 int counters_clear(dg_graph *g);
 int ws_init(dg_graph *g);

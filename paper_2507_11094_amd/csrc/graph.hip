@@ -579,14 +579,14 @@ int graph_export(dg_graph *g, int64_t *m, int32_t *src, int32_t *dst, int32_t *w
 // [0, n), ops other than 0/1 and insert weights outside [1, 2^30)).
 __global__ __launch_bounds__(CH_T) void k_validate_batch(int64_t k, const int32_t *s, const int32_t *d,
                                                          const int32_t *w, const uint8_t *op, int32_t n,
-                                                         int64_t *cnt) {
+                                                         int expect, int64_t *cnt) {
     __shared__ BlockScratch sc;
     int64_t nd = 0, ni = 0;
     bool anybad = false;
     for (int64_t i = gtid(); i < k; i += gstride()) {
         int32_t u = s[i], v = d[i];
         uint8_t o = op[i];
-        bool bad = u < 0 || u >= n || v < 0 || v >= n || u == v || o > 1;
+        bool bad = u < 0 || u >= n || v < 0 || v >= n || u == v || o > 1 || (expect >= 0 && o != expect);
         if (o == 1 && w) bad |= (w[i] < 1 || w[i] >= (1 << 30));
         anybad |= bad;
         nd += !bad && o == 0;
@@ -1028,7 +1028,7 @@ struct PhaseTimer {
 };
 
 int apply_chunk(dg_graph *g, int64_t k, const int32_t *src, const int32_t *dst, const int32_t *w,
-                const uint8_t *op, bool dev, dg_batch_stats *st) {
+                const uint8_t *op, bool dev, dg_batch_stats *st, int expect_op) {
     hipStream_t s = g->stream;
     Work &ws = g->ws;
     Dir &F = g->fwd;
@@ -1062,13 +1062,14 @@ int apply_chunk(dg_graph *g, int64_t k, const int32_t *src, const int32_t *dst, 
     // ---- validate and count (no change to the graph before this passes)
     DG_TRY(counters_clear(g));
     hipLaunchKernelGGL(k_validate_batch, dim3(grid_for(k)), dim3(256), 0, s, k, ds, dd, dw, dop, g->n,
-                       ws.dcnt);
+                       expect_op, ws.dcnt);
     DG_HIP(hipGetLastError());
     DG_TRY(counters_read(g));
     if (ws.hcnt[C_ERR]) {
         t_val.stop();
         t_all.stop();
-        return set_error(DG_EINVAL, "batch holds a self-loop, an id outside [0,n), an op other than 0/1 or a weight outside [1,2^30)");
+        return set_error(DG_EINVAL, "batch holds a self-loop, an id outside [0,n), an op other than 0/1 (or "
+                                    "other than the partially dynamic mode's) or a weight outside [1,2^30)");
     }
     const int rep = und ? 2 : 1;
     const int64_t nda = ws.hcnt[C_NDEL] * rep, nia = ws.hcnt[C_NINS] * rep;
@@ -1177,7 +1178,13 @@ int apply_chunk(dg_graph *g, int64_t k, const int32_t *src, const int32_t *dst, 
         bool need = thr < 0 ? (F.dm + F.tomb_base > 0)
                             : ((double)(F.dm + F.tomb_base) > thr * live ||
                                (!und && (double)(R.dm + R.tomb_base) > thr * live));
+        // merge period: also merge after cfg.merge_period batches since the last one
+        g->since_merge += 1;
+        if (g->cfg.merge_period > 0 && g->since_merge >= g->cfg.merge_period &&
+            (F.dm + F.tomb_base > 0 || (!und && R.dm + R.tomb_base > 0)))
+            need = true;
         if (need) {
+            g->since_merge = 0;
             PhaseTimer t(g, 3, &st->t_merge_ms);
             DG_TRY(merge_dir(g, F, g->m_live));
             if (!und) DG_TRY(merge_dir(g, g->rev_own, g->m_live));

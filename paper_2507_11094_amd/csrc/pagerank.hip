@@ -610,7 +610,7 @@ static int pr_iterate(dg_graph *g, const int32_t *A, int64_t na, int64_t edges, 
             if (tiles) {
                 // tiles: off 8 + xn 8 per row, col 4 + contrib 8 per base entry
                 ps = prof_begin("pr_tiles", s);
-                hipLaunchKernelGGL(g->cfg.pr_pull == 2 ? k_pr_tiles<true> : k_pr_tiles<false>, dim3((unsigned)nb),
+                hipLaunchKernelGGL(g->cfg.pr_pull == 2 ? k_pr_tiles<false> : k_pr_tiles<true>, dim3((unsigned)nb),
                                    dim3(MP_THREADS), 0, s, ws.mp_row.p,
                                    ws.mp_edge.p, R.off.p, R.col.p, contrib, prs + 2, damping, xn, pf, pl, done);
                 prof_end(ps, s, 16.0 * (double)g->n + 12.0 * (double)R.m);

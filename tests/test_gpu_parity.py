@@ -338,9 +338,9 @@ def hub_graph(n=1 << 14, hub_in=12000, seed=11):
 
 @pytest.mark.parametrize("pull", [0, 1, 2])
 def test_pagerank_whole_graph_pull(pull):
-    """Static solve and global-form updates, merge-path tiles (0), per-vertex waves
-    (1) or tiles with non-temporal streams (2), with a live diff level (no merges),
-    against the oracle."""
+    """Static solve and global-form updates, merge-path tiles with non-temporal
+    streams (0), per-vertex waves (1) or tiles without the hints (2), with a live
+    diff level (no merges), against the oracle."""
     n, s, d, w = hub_graph()
     say("pagerank whole-graph pull", pull, "arcs", s.size)
     c = cfg(merge=1e9)
@@ -475,3 +475,52 @@ def test_device_pointer_batch():
     torch.cuda.synchronize()
     cs, cd, cw, _ = oracle.apply(n, s, d, w, bs, bd, bw, bo)
     assert np.array_equal(out.cpu().numpy(), oracle.sssp(n, cs, cd, cw, 0))
+
+
+def test_partially_dynamic_modes():
+    """Incremental-only and decremental-only batches (no op array) against the
+    oracle; an op that contradicts the mode rejects the batch before any change."""
+    n, s, d, w = rmat_small(11, 8, 41)
+    say("incremental / decremental modes")
+    G = dg.Graph(n, s, d, w)
+    qs, qp = G.sssp_attach(0), G.pr_attach(0.85, PR_TOL, 1000)
+    b = graphgen.update_batch(n, s, d, 600, 4100)
+    ins = b[3] == 1
+    G.insert(b[0][ins], b[1][ins], b[2][ins])
+    cs, cd, cw, ost = oracle.apply(n, s, d, w, b[0][ins], b[1][ins], b[2][ins], b[3][ins])
+    assert np.array_equal(qs.read()[0], oracle.sssp(n, cs, cd, cw, 0))
+    pr_check(qp.read()[0], n, cs, cd)
+    G.delete(cs[:300], cd[:300])
+    cs, cd, cw, _ = oracle.apply(n, cs, cd, cw, cs[:300], cd[:300], np.zeros(300, np.int32),
+                                 np.zeros(300, np.uint8))
+    assert_edges(G, cs, cd, cw)
+    assert np.array_equal(qs.read()[0], oracle.sssp(n, cs, cd, cw, 0))
+    pr_check(qp.read()[0], n, cs, cd)
+    before = G.export()
+    with pytest.raises(dg.DGError) as e:  # an insertion in a decremental batch
+        G.apply(cs[:4], cd[:4], cw[:4], np.array([0, 0, 1, 0], np.uint8), mode=dg.DG_DECREMENTAL)
+    assert e.value.code == dg.DG_EINVAL
+    with pytest.raises(dg.DGError) as e:
+        G.apply(cs[:4], cd[:4], cw[:4], None, mode=dg.DG_DECREMENTAL | dg.DG_INCREMENTAL)
+    assert e.value.code == dg.DG_EINVAL
+    for x, y in zip(before, G.export()):
+        assert np.array_equal(x, y)
+
+
+def test_merge_period():
+    """merge_period = 3 with the size threshold off: every third batch merges."""
+    n, s, d, w = rmat_small(10, 8, 43)
+    say("merge period")
+    c = cfg(merge=1e9)
+    c.merge_period = 3
+    G = dg.Graph(n, s, d, w, config=c)
+    q = G.sssp_attach(0)
+    cs, cd, cw = s, d, w
+    merged = []
+    for i in range(7):
+        bs, bd, bw, bo = graphgen.update_batch(n, cs, cd, 80, 4200 + i)
+        merged.append(G.apply(bs, bd, bw, bo).merged)
+        cs, cd, cw, _ = oracle.apply(n, cs, cd, cw, bs, bd, bw, bo)
+        assert_edges(G, cs, cd, cw)
+        assert np.array_equal(q.read()[0], oracle.sssp(n, cs, cd, cw, 0))
+    assert merged == [0, 0, 1, 0, 0, 1, 0]
