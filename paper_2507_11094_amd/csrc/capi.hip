@@ -416,7 +416,7 @@ int dg_tc_read(dg_query *q, uint64_t *count) {
 int dg_sssp_static(dg_graph *g, int32_t source, int32_t *dist, int32_t *parent, uint32_t flags) {
     DG_TRY(check_graph(g));
     if (source < 0 || source >= g->n || !dist) return set_error(DG_EINVAL, "bad arguments");
-    DBuf<uint64_t> key;
+    DBuf<uint64_t> &key = g->ws.skey;
     DG_TRY(key.ensure((size_t)g->n + 1));
     int rc = sssp_static_solve(g, key.p, source, nullptr);
     if (rc == DG_OK) {
@@ -428,7 +428,6 @@ int dg_sssp_static(dg_graph *g, int32_t source, int32_t *dist, int32_t *parent, 
         tmp.key.p = nullptr;
         tmp.key.cap = 0;
     }
-    key.release();
     return mark_device_error(g, rc);
 }
 
@@ -437,7 +436,7 @@ int dg_pr_static(dg_graph *g, double damping, double tol, int32_t max_iter, doub
     DG_TRY(check_graph(g));
     if (!rank || !(damping > 0.0 && damping < 1.0) || !(tol > 0.0) || max_iter < 1)
         return set_error(DG_EINVAL, "bad PageRank parameters");
-    DBuf<double> x, c, xn;
+    DBuf<double> &x = g->ws.sx, &c = g->ws.sc, &xn = g->ws.sxn;
     int rc = x.ensure((size_t)g->n + 1);
     if (rc == DG_OK) rc = c.ensure((size_t)g->n + 1);
     if (rc == DG_OK) rc = xn.ensure((size_t)g->n + 1);
@@ -445,9 +444,6 @@ int dg_pr_static(dg_graph *g, double damping, double tol, int32_t max_iter, doub
     if (rc == DG_OK) rc = pr_static_solve(g, damping, tol * g->cfg.pr_tol_scale, max_iter, x.p, c.p, xn.p, &it, &conv);
     if (rc == DG_OK) rc = pr_normalize(g, x.p, rank, (flags & DG_DEVICE_PTRS) != 0);
     if (iters) *iters = it;
-    x.release();
-    c.release();
-    xn.release();
     return mark_device_error(g, rc);
 }
 

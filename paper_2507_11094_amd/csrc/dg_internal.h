@@ -125,6 +125,11 @@ struct Work {
     DBuf<int32_t> stamp;                  // per-vertex dedup stamps
     DBuf<int32_t> farflag, far0, far1;    // near-far SSSP: far-pile membership stamps and piles
     DBuf<int64_t> bpart;                  // per-block partial counts (summed in block order)
+    // kept between calls (device frees synchronise the whole device): result
+    // staging for host reads and the state of the static comparators
+    DBuf<double> rbuf;                    // n + 1 doubles (or 2n + 2 int32)
+    DBuf<uint64_t> skey;
+    DBuf<double> sx, sc, sxn;
     int32_t far_ctr = 0;
     int32_t stamp_ctr = 0;
     DBuf<double> part;                    // partial sums of split rows

@@ -116,6 +116,7 @@ void ws_free(dg_graph *g) {
     w.stamp.release(); w.part.release(); w.prs.release();
     w.mp_row.release(); w.mp_edge.release(); w.mp_part.release();
     w.farflag.release(); w.far0.release(); w.far1.release(); w.bpart.release();
+    w.rbuf.release(); w.skey.release(); w.sx.release(); w.sc.release(); w.sxn.release();
     w.wq.release(); w.wseq.release(); w.wctr.release(); w.inq.release();
     if (w.dcnt) dfree(w.dcnt);
     if (w.hcnt) (void)hipHostFree(w.hcnt);

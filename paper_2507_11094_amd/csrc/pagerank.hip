@@ -847,13 +847,12 @@ int pr_normalize(dg_graph *g, const double *x, double *rank, bool dev) {
         DG_HIP(hipStreamSynchronize(s));
         return DG_OK;
     }
-    DBuf<double> tmp;
+    DBuf<double> &tmp = g->ws.rbuf;
     DG_TRY(tmp.ensure((size_t)g->n + 1));
     hipLaunchKernelGGL(k_scale, dim3(grid_for(g->n)), dim3(256), 0, s, x, (int64_t)g->n, dsum, tmp.p);
     hipError_t e1 = hipGetLastError();
     hipError_t e2 = hipMemcpyAsync(rank, tmp.p, (size_t)g->n * sizeof(double), hipMemcpyDeviceToHost, s);
     hipError_t e3 = hipStreamSynchronize(s);
-    tmp.release();
     if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess)
         return set_error(DG_EDEVICE, "pagerank read failed");
     return DG_OK;

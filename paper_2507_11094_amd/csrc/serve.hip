@@ -83,6 +83,10 @@ struct Entry {
     int32_t n = 0;
     bool busy = false;
     std::deque<Req *> fifo;
+    // staging of the symmetrised-copy filter, kept across requests (a device free
+    // synchronises the whole device and would serialise the workers)
+    DBuf<int32_t> ss, sd;
+    DBuf<uint8_t> sop, skeep;
 };
 
 }  // namespace
@@ -117,8 +121,8 @@ int run_request(dg_server *S, Entry &E, Req *r, hipStream_t stream) {
         DG_TRY(dg_apply_batch(E.g, k, r->src.data(), r->dst.data(), r->w.data(), r->op.data(), 0, 0, &st));
         r->applied = st.deleted + st.inserted;
         // symmetrised copy: insert {u,v}; delete {u,v} unless (v,u) is still live
-        DBuf<int32_t> ds, dd;
-        DBuf<uint8_t> dop, keep;
+        DBuf<int32_t> &ds = E.ss, &dd = E.sd;
+        DBuf<uint8_t> &dop = E.sop, &keep = E.skeep;
         int rc = ds.ensure(k + 1);
         if (rc == DG_OK) rc = dd.ensure(k + 1);
         if (rc == DG_OK) rc = dop.ensure(k + 1);
@@ -133,7 +137,6 @@ int run_request(dg_server *S, Entry &E, Req *r, hipStream_t stream) {
         if (rc == DG_OK && hipMemcpyAsync(hk.data(), keep.p, k, hipMemcpyDeviceToHost, stream) != hipSuccess)
             rc = set_error(DG_EDEVICE, "copy failed");
         if (rc == DG_OK && hipStreamSynchronize(stream) != hipSuccess) rc = set_error(DG_EDEVICE, "sync failed");
-        ds.release(); dd.release(); dop.release(); keep.release();
         if (rc != DG_OK) return rc;
         std::vector<int32_t> us, vs;
         std::vector<uint8_t> os;
@@ -358,6 +361,7 @@ int dg_server_destroy(dg_server *S) {
         for (auto *r : E.fifo) (void)r;  // owned by reqs (already deleted)
         if (E.g) dg_graph_destroy(E.g);
         if (E.gu) dg_graph_destroy(E.gu);
+        E.ss.release(); E.sd.release(); E.sop.release(); E.skeep.release();
     }
     for (auto st : S->streams) (void)hipStreamDestroy(st);
     delete S;

@@ -307,15 +307,14 @@ int dg_set_sssp_read(dg_set *S, int32_t member, int32_t *dist, int32_t *parent, 
         DG_HIP(hipStreamSynchronize(s));
         return DG_OK;
     }
-    DBuf<int32_t> tmp;
-    DG_TRY(tmp.ensure(2 * (size_t)nl + 2));
-    hipLaunchKernelGGL(k_set_unpack, dim3(grid_for(nl)), dim3(256), 0, s, nl, S->q->key.p, base, tmp.p,
-                       parent ? tmp.p + nl : nullptr);
+    DG_TRY(S->g->ws.rbuf.ensure((size_t)nl + 1));
+    int32_t *tmp = reinterpret_cast<int32_t *>(S->g->ws.rbuf.p);  // 2 nl + 2 int32
+    hipLaunchKernelGGL(k_set_unpack, dim3(grid_for(nl)), dim3(256), 0, s, nl, S->q->key.p, base, tmp,
+                       parent ? tmp + nl : nullptr);
     hipError_t e1 = hipGetLastError();
-    hipError_t e2 = hipMemcpyAsync(dist, tmp.p, nl * 4, hipMemcpyDeviceToHost, s);
-    hipError_t e3 = parent ? hipMemcpyAsync(parent, tmp.p + nl, nl * 4, hipMemcpyDeviceToHost, s) : hipSuccess;
+    hipError_t e2 = hipMemcpyAsync(dist, tmp, nl * 4, hipMemcpyDeviceToHost, s);
+    hipError_t e3 = parent ? hipMemcpyAsync(parent, tmp + nl, nl * 4, hipMemcpyDeviceToHost, s) : hipSuccess;
     hipError_t e4 = hipStreamSynchronize(s);
-    tmp.release();
     if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess)
         return set_error(DG_EDEVICE, "set read failed");
     return DG_OK;

@@ -757,15 +757,13 @@ int sssp_read(dg_query *q, int32_t *dist, int32_t *parent, bool dev) {
     if (dev) {
         DG_TRY(sssp_unpack(g, q->key.p, dist, parent, s));
     } else {
-        DBuf<int32_t> tmp;
-        DG_TRY(tmp.ensure(2 * (size_t)g->n + 2));
-        DG_TRY(sssp_unpack(g, q->key.p, tmp.p, tmp.p + g->n, s));
-        hipError_t e1 = hipMemcpyAsync(dist, tmp.p, (size_t)g->n * 4, hipMemcpyDeviceToHost, s);
-        hipError_t e2 = parent ? hipMemcpyAsync(parent, tmp.p + g->n, (size_t)g->n * 4,
-                                                hipMemcpyDeviceToHost, s)
+        DG_TRY(g->ws.rbuf.ensure((size_t)g->n + 1));
+        int32_t *tmp = reinterpret_cast<int32_t *>(g->ws.rbuf.p);  // 2n + 2 int32
+        DG_TRY(sssp_unpack(g, q->key.p, tmp, tmp + g->n, s));
+        hipError_t e1 = hipMemcpyAsync(dist, tmp, (size_t)g->n * 4, hipMemcpyDeviceToHost, s);
+        hipError_t e2 = parent ? hipMemcpyAsync(parent, tmp + g->n, (size_t)g->n * 4, hipMemcpyDeviceToHost, s)
                                : hipSuccess;
         hipError_t e3 = hipStreamSynchronize(s);
-        tmp.release();
         if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess)
             return set_error(DG_EDEVICE, "sssp read copy failed");
         return DG_OK;
