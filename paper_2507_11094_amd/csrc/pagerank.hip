@@ -364,17 +364,12 @@ static int heavy_deg(dg_graph *g) { return g->cfg.heavy_degree > 0 ? g->cfg.heav
 //   k_mp_partition  tile start coordinates (row, entry), once per iteration call;
 //   k_pr_tiles      entries staged through LDS (column reads coalesced, one
 //                   contribution gather per entry), then each row that ends in
-//                   the tile is summed in entry order (short pieces by one lane,
-//                   long pieces by a wave), its diff-level entries added in key
-//                   order, and the Jacobi step applied at once: x[v] takes the
-//                   new value and the contribution goes to the other buffer of a
-//                   double-buffered pair (the gathers of this step read the old
-//                   one), with the L1 step and the dangling mass summed per tile;
-//                   rows that began in an earlier tile leave their piece in
-//                   pf[b], the row still open at the tile's end leaves its piece
-//                   in pl[b];
-//   k_pr_fixup      rows split across tiles: pieces added in tile order, then the
-//                   same step.
+//                   the tile is summed in entry order: short pieces by one lane,
+//                   long pieces by a wave; rows that began in an earlier tile
+//                   leave their piece in pf[b], the row still open at the tile's
+//                   end leaves its piece in pl[b];
+//   k_pr_fixup      rows split across tiles: pieces added in tile order;
+//   k_pr_diff_add   diff-level entries added per row in key order.
 // Every sum has a fixed order, so results are bit-reproducible.
 constexpr int MP_THREADS = 256;
 constexpr int MP_ITEMS = 2048;
@@ -398,8 +393,9 @@ __global__ void k_mp_partition(const int64_t *__restrict__ off, int32_t n, int64
     }
 }
 
-// STREAM: the column and offset streams are read with non-temporal hints, so that
-// they do not displace the gathered contributions from L2.
+// STREAM: the column and offset streams are read, and the results written, with
+// non-temporal hints, so that they do not displace the gathered contributions
+// from L2.
 template <bool STREAM>
 __device__ __forceinline__ int32_t ld_stream(const int32_t *p) {
     return STREAM ? __builtin_nontemporal_load(p) : *p;
@@ -408,29 +404,10 @@ template <bool STREAM>
 __device__ __forceinline__ int64_t ld_stream(const int64_t *p) {
     return STREAM ? __builtin_nontemporal_load(p) : *p;
 }
-
-// One Jacobi step at vertex v with pulled sum s (fused apply): accumulates the L1
-// step and the new mass on dangling vertices.
-__device__ __forceinline__ void pr_step(int32_t v, double xnew, double *x, double *cout, const int32_t *deg,
-                                        double &l1, double &dang) {
-    const double old = x[v];
-    x[v] = xnew;
-    const int32_t dg = deg[v];
-    cout[v] = dg > 0 ? xnew / (double)dg : 0.0;
-    l1 += fabs(xnew - old);
-    if (dg == 0) dang += xnew;
-}
-
-// Live diff-level contributions of row v, in key order.
-__device__ __forceinline__ double pr_diff_sum(int32_t v, const int64_t *__restrict__ doff,
-                                              const int32_t *__restrict__ dcol, const double *__restrict__ cin) {
-    double a = 0.0;
-    const int64_t e = doff[v + 1];
-    for (int64_t q = doff[v]; q < e; ++q) {
-        const uint32_t c = (uint32_t)dcol[q];
-        if (!(c & DEAD)) a += cin[c & ID_MASK];
-    }
-    return a;
+template <bool STREAM>
+__device__ __forceinline__ void st_stream(double *p, double v) {
+    if (STREAM) __builtin_nontemporal_store(v, p);
+    else *p = v;
 }
 
 template <bool STREAM>
@@ -438,12 +415,9 @@ __global__ __launch_bounds__(MP_THREADS) void k_pr_tiles(const int32_t *__restri
                                                          const int64_t *__restrict__ mp_edge,
                                                          const int64_t *__restrict__ off,
                                                          const int32_t *__restrict__ col,
-                                                         const int64_t *__restrict__ doff,
-                                                         const int32_t *__restrict__ dcol, int has_diff,
-                                                         const double *__restrict__ cin, const double *cterm,
-                                                         double damp, double *x, double *cout,
-                                                         const int32_t *__restrict__ deg, double *pf, double *pl,
-                                                         double *red, const double *done) {
+                                                         const double *__restrict__ contrib, const double *cterm,
+                                                         double damp, double *xn, double *pf, double *pl,
+                                                         const double *done) {
     if (*done != 0.0) return;
     __shared__ double s_val[MP_ITEMS];
     __shared__ int32_t s_off[MP_ITEMS + 1];
@@ -471,7 +445,7 @@ __global__ __launch_bounds__(MP_THREADS) void k_pr_tiles(const int32_t *__restri
     }
     double v[MP_IPT];
 #pragma unroll
-    for (int u = 0; u < MP_IPT; ++u) v[u] = (c[u] & DEAD) ? 0.0 : cin[c[u] & ID_MASK];
+    for (int u = 0; u < MP_IPT; ++u) v[u] = (c[u] & DEAD) ? 0.0 : contrib[c[u] & ID_MASK];
 #pragma unroll
     for (int u = 0; u < MP_IPT; ++u) {
         const int j = t + u * MP_THREADS;
@@ -479,7 +453,6 @@ __global__ __launch_bounds__(MP_THREADS) void k_pr_tiles(const int32_t *__restri
     }
     __syncthreads();
     const double base = *cterm;
-    double l1 = 0.0, dang = 0.0;
     // rows that end in this tile: short pieces one lane each
     for (int i = t; i < nr; i += MP_THREADS) {
         const int32_t lo = max(s_off[i], 0), hi = s_off[i + 1];
@@ -489,12 +462,8 @@ __global__ __launch_bounds__(MP_THREADS) void k_pr_tiles(const int32_t *__restri
         }
         double acc = 0.0;
         for (int32_t j = lo; j < hi; ++j) acc += s_val[j];
-        if (s_off[i] < 0) {
-            pf[b] = acc;
-        } else {
-            if (has_diff) acc += pr_diff_sum(r0 + i, doff, dcol, cin);
-            pr_step(r0 + i, base + damp * acc, x, cout, deg, l1, dang);
-        }
+        if (s_off[i] < 0) pf[b] = acc;
+        else st_stream<STREAM>(&xn[r0 + i], base + damp * acc);
     }
     __syncthreads();
     // long pieces, then the piece of the row left open at the tile's end, one wave each
@@ -513,59 +482,47 @@ __global__ __launch_bounds__(MP_THREADS) void k_pr_tiles(const int32_t *__restri
         for (int32_t j = lo + l; j < hi; j += WAVE) acc += s_val[j];
         acc = wave_sum(acc);
         if (l == 0) {
-            if (k == nlong) {
-                pl[b] = acc;
-            } else if (s_off[s_long[k]] < 0) {
-                pf[b] = acc;
-            } else {
-                const int32_t r = r0 + s_long[k];
-                if (has_diff) acc += pr_diff_sum(r, doff, dcol, cin);
-                pr_step(r, base + damp * acc, x, cout, deg, l1, dang);
-            }
+            if (k == nlong) pl[b] = acc;
+            else if (s_off[s_long[k]] < 0) pf[b] = acc;
+            else st_stream<STREAM>(&xn[r0 + s_long[k]], base + damp * acc);
         }
-    }
-    // this tile's L1 step and dangling mass, summed in a fixed order
-    __syncthreads();
-    s_val[t] = l1;
-    s_val[MP_THREADS + t] = dang;
-    __syncthreads();
-    for (int h = MP_THREADS / 2; h > 0; h >>= 1) {
-        if (t < h) {
-            s_val[t] += s_val[t + h];
-            s_val[MP_THREADS + t] += s_val[MP_THREADS + t + h];
-        }
-        __syncthreads();
-    }
-    if (t == 0) {
-        red[2 * b] = s_val[0];
-        red[2 * b + 1] = s_val[MP_THREADS];
     }
 }
 
 // Rows that began in an earlier tile and end in tile b: the open pieces of the
-// tiles before (pl, in tile order) plus the closing piece (pf[b]) plus the diff
-// level, then the same step; red_fix[b] holds its L1 step and dangling mass.
+// tiles before (pl, in tile order) plus the closing piece (pf[b]).
 __global__ void k_pr_fixup(int64_t nb, const int32_t *__restrict__ mp_row, const int64_t *__restrict__ mp_edge,
-                           const int64_t *__restrict__ off, const int64_t *__restrict__ doff,
-                           const int32_t *__restrict__ dcol, int has_diff, const double *__restrict__ cin,
-                           const double *pf, const double *pl, const double *cterm, double damp, double *x,
-                           double *cout, const int32_t *__restrict__ deg, double *red_fix, const double *done) {
+                           const int64_t *__restrict__ off, const double *pf, const double *pl,
+                           const double *cterm, double damp, double *xn, const double *done) {
     if (*done != 0.0) return;
     const double base = *cterm;
     for (int64_t b = gtid(); b < nb; b += gstride()) {
-        double l1 = 0.0, dang = 0.0;
         const int32_t R = mp_row[b];
-        if (R < mp_row[b + 1] && off[R] < mp_edge[b]) {
-            int64_t first = b - 1;  // tile b-1 ends inside row R
-            while (first > 0 && mp_row[first] == R) --first;
-            double acc = 0.0;
-            for (int64_t j = first; j < b; ++j) acc += pl[j];
-            acc += pf[b];
-            if (has_diff) acc += pr_diff_sum(R, doff, dcol, cin);
-            pr_step(R, base + damp * acc, x, cout, deg, l1, dang);
+        if (R >= mp_row[b + 1] || off[R] >= mp_edge[b]) continue;
+        int64_t first = b - 1;  // tile b-1 ends inside row R
+        while (first > 0 && mp_row[first] == R) --first;
+        double acc = 0.0;
+        for (int64_t j = first; j < b; ++j) acc += pl[j];
+        acc += pf[b];
+        xn[R] = base + damp * acc;
+    }
+}
+
+// Diff-level entries: the first entry of each row's run adds the run's live
+// contributions, in key order.
+__global__ void k_pr_diff_add(int64_t dm, const uint64_t *__restrict__ dkey, const int32_t *__restrict__ dcol,
+                              int keybits, const double *__restrict__ contrib, double damp, double *xn,
+                              const double *done) {
+    if (*done != 0.0) return;
+    for (int64_t j = gtid(); j < dm; j += gstride()) {
+        const int32_t r = (int32_t)(dkey[j] >> keybits);
+        if (j > 0 && (int32_t)(dkey[j - 1] >> keybits) == r) continue;
+        double acc = 0.0;
+        for (int64_t q = j; q < dm && (int32_t)(dkey[q] >> keybits) == r; ++q) {
+            const uint32_t cc = (uint32_t)dcol[q];
+            if (!(cc & DEAD)) acc += contrib[cc & ID_MASK];
         }
-        red_fix[2 * b] = l1;
-        red_fix[2 * b + 1] = dang;
+        if (acc != 0.0) xn[r] += damp * acc;
     }
 }
 
@@ -622,26 +579,20 @@ static int pr_iterate(dg_graph *g, const int32_t *A, int64_t na, int64_t edges, 
     hipLaunchKernelGGL(k_pr_reduce, dim3(1), dim3(256), 0, s, partials, global ? APPLY_GROUPS : 1,
                        (int)global, S, damping, ninv, tol, 1, prs, step_out);
     DG_HIP(hipGetLastError());
-    // every vertex pulled: merge-path tiles with the step fused in, contributions
-    // double-buffered (cbuf[it % 2] holds those of step it)
+    // every vertex pulled: merge-path tiles over the base level, then the diff level
     const Dir &R = *g->rev;
     const bool tiles = A == nullptr && g->cfg.pr_pull != 1;
     int64_t nb = 0;
-    double *cbuf[2] = {contrib, contrib};
     if (tiles) {
         nb = ((int64_t)g->n + R.m + MP_ITEMS - 1) / MP_ITEMS;
         DG_TRY(ws.mp_row.ensure((size_t)nb + 1));
         DG_TRY(ws.mp_edge.ensure((size_t)nb + 1));
-        DG_TRY(ws.mp_part.ensure(2 * (size_t)nb + 2 + 4 * (size_t)nb));
-        DG_TRY(ws.cbuf.ensure((size_t)g->n + 1));
-        cbuf[1] = ws.cbuf.p;
+        DG_TRY(ws.mp_part.ensure(2 * (size_t)nb + 2));
         hipLaunchKernelGGL(k_mp_partition, dim3(grid_for(nb + 1)), dim3(256), 0, s, R.off.p, g->n, R.m, nb,
                            ws.mp_row.p, ws.mp_edge.p);
         DG_HIP(hipGetLastError());
     }
     double *pf = ws.mp_part.p, *pl = ws.mp_part.p + nb + 1;
-    double *red = ws.mp_part.p + 2 * nb + 2;  // per-tile (L1, dangling), then per-fix-up pairs
-    const int has_diff = R.dm > 0;
     const double *done = prs + 3;
     // Steps are launched in groups without a host round trip; the convergence
     // test runs on the device (k_pr_reduce), and once it passes the remaining
@@ -654,28 +605,21 @@ static int pr_iterate(dg_graph *g, const int32_t *A, int64_t na, int64_t edges, 
         const int grp = std::min(GROUP, max_iter - launched);
         slots.clear();
         for (int j = 0; j < grp; ++j) {
-            int ps = -1, pa = -1;
+            DG_TRY(counters_clear(g));
+            int ps;
             if (tiles) {
-                const int k = launched + j;  // this step reads cbuf[k % 2], writes the other
-                // tiles: per row off 8, x read 8 + write 8, contribution write 8, outdeg 4
-                // (+ doff 8 with a diff level); col 4 + contribution 8 per base and diff entry
+                // tiles: off 8 + xn 8 per row, col 4 + contrib 8 per base entry
                 ps = prof_begin("pr_tiles", s);
                 hipLaunchKernelGGL(g->cfg.pr_pull == 2 ? k_pr_tiles<false> : k_pr_tiles<true>, dim3((unsigned)nb),
-                                   dim3(MP_THREADS), 0, s, ws.mp_row.p, ws.mp_edge.p, R.off.p, R.col.p, R.doff.p,
-                                   R.dcol.p, has_diff, cbuf[k & 1], prs + 2, damping, x, cbuf[(k + 1) & 1],
-                                   g->fwd.deg.p, pf, pl, red, done);
-                prof_end(ps, s, (36.0 + (has_diff ? 8.0 : 0.0)) * (double)g->n + 12.0 * (double)(R.m + R.dm));
+                                   dim3(MP_THREADS), 0, s, ws.mp_row.p,
+                                   ws.mp_edge.p, R.off.p, R.col.p, contrib, prs + 2, damping, xn, pf, pl, done);
+                prof_end(ps, s, 16.0 * (double)g->n + 12.0 * (double)R.m);
                 hipLaunchKernelGGL(k_pr_fixup, dim3(grid_for(nb)), dim3(256), 0, s, nb, ws.mp_row.p,
-                                   ws.mp_edge.p, R.off.p, R.doff.p, R.dcol.p, has_diff, cbuf[k & 1], pf, pl, prs + 2,
-                                   damping, x, cbuf[(k + 1) & 1], g->fwd.deg.p, red + 2 * nb, done);
-                hipLaunchKernelGGL(k_pr_reduce, dim3(1), dim3(256), 0, s, red, (int)(2 * nb), (int)global, S,
-                                   damping, ninv, tol, 0, prs, step_out);
-                DG_HIP(hipGetLastError());
-                slots.emplace_back(ps, pa);
-                continue;
-            }
-            DG_TRY(counters_clear(g));
-            {
+                                   ws.mp_edge.p, R.off.p, pf, pl, prs + 2, damping, xn, done);
+                if (R.dm > 0)
+                    hipLaunchKernelGGL(k_pr_diff_add, dim3(grid_for(R.dm)), dim3(256), 0, s, R.dm, R.dkey.p,
+                                       R.dcol.p, R.keybits, contrib, damping, xn, done);
+            } else {
                 int64_t blocks = std::min<int64_t>((na + 255) / 256, 65535);
                 ps = prof_begin("pr_pull", s);
                 hipLaunchKernelGGL(k_pr_pull, dim3((unsigned)blocks), dim3(256), 0, s, A, na, rv, contrib,
@@ -687,7 +631,7 @@ static int pr_iterate(dg_graph *g, const int32_t *A, int64_t na, int64_t edges, 
                 hipLaunchKernelGGL(k_pr_finish, dim3(64), dim3(256), 0, s, hv, ws.dcnt + C_AUX3, ws.part.p,
                                    prs + 2, damping, xn);
             }
-            pa = prof_begin("pr_apply", s);
+            int pa = prof_begin("pr_apply", s);
             hipLaunchKernelGGL(k_pr_apply, dim3(APPLY_GROUPS), dim3(256), 0, s, A, na, xn, x, contrib,
                                g->fwd.deg.p, partials, done);
             prof_end(pa, s, 40.0 * (double)na);
@@ -715,8 +659,6 @@ static int pr_iterate(dg_graph *g, const int32_t *A, int64_t na, int64_t edges, 
     }
     if (na == 0) *conv = 1;
     *iters = it;
-    if (tiles && (it & 1))  // the last step's contributions are in the second buffer
-        DG_HIP(hipMemcpyAsync(contrib, cbuf[1], (size_t)g->n * sizeof(double), hipMemcpyDeviceToDevice, s));
     if (global && na > 0) {
         hipLaunchKernelGGL(k_pr_rescale, dim3(grid_for(g->n)), dim3(256), 0, s, g->n, x, contrib, g->fwd.deg.p,
                            prs, S, damping);
