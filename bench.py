@@ -224,6 +224,7 @@ def run_single(args, kind: str) -> int:
     cfg.sssp_delta = delta
     cfg.pr_mode = args.pr_mode
     cfg.pr_pull = args.pr_pull
+    cfg.pr_tile = args.pr_tile
     t = time.perf_counter()
     G = dg.Graph(n, s, d, w, undirected=undirected, config=cfg)
     log(f"graph built on device in {time.perf_counter() - t:.2f}s")
@@ -698,6 +699,7 @@ def main() -> int:
     ap.add_argument("--pr-pull", type=int, default=0,
                     help="whole-graph PageRank pull: 0 merge-path tiles with non-temporal streams, 1 per-vertex "
                          "waves, 2 merge-path tiles without the hints")
+    ap.add_argument("--pr-tile", type=int, default=0, help="rows + entries per pull tile: 1024, 2048 (0) or 4096")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run five plain 256 MiB device-to-device copies (reference for the "
                          "FETCH_SIZE / WRITE_SIZE counter scale) and exit")

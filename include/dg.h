@@ -101,7 +101,10 @@ typedef struct dg_config {
     /* > 0: also merge after this many batches since the last merge (Section 3.5
      * merges after a configurable number of batches); 0 = threshold only. */
     int32_t merge_period;
-    int32_t reserved[3];
+    /* Rows + entries per merge-path tile of the whole-graph pull: 1024, 2048 or
+     * 4096 (0 or anything else: 2048). */
+    int32_t pr_tile;
+    int32_t reserved[2];
 } dg_config;
 
 /* Per-batch statistics and phase timings (HIP events on the graph's stream). */

@@ -372,14 +372,13 @@ static int heavy_deg(dg_graph *g) { return g->cfg.heavy_degree > 0 ? g->cfg.heav
 //   k_pr_diff_add   diff-level entries added per row in key order.
 // Every sum has a fixed order, so results are bit-reproducible.
 constexpr int MP_THREADS = 256;
-constexpr int MP_ITEMS = 2048;
-constexpr int MP_IPT = MP_ITEMS / MP_THREADS;
-constexpr int MP_LONG = 64;  // row pieces longer than this are summed by a whole wave
+constexpr int MP_ITEMS = 2048;  // default items per tile (cfg.pr_tile picks 1024 / 2048 / 4096)
+constexpr int MP_LONG = 64;     // row pieces longer than this are summed by a whole wave
 
-__global__ void k_mp_partition(const int64_t *__restrict__ off, int32_t n, int64_t m, int64_t nb,
+__global__ void k_mp_partition(const int64_t *__restrict__ off, int32_t n, int64_t m, int64_t nb, int items,
                                int32_t *mp_row, int64_t *mp_edge) {
     for (int64_t b = gtid(); b <= nb; b += gstride()) {
-        const int64_t diag = min(b * (int64_t)MP_ITEMS, (int64_t)n + m);
+        const int64_t diag = min(b * (int64_t)items, (int64_t)n + m);
         // rows consumed at this diagonal: the largest r with off[r] <= diag - r
         // (a row's end is taken before the entry that starts the next row)
         int64_t lo = max(diag - m, (int64_t)0), hi = min(diag, (int64_t)n);
@@ -410,7 +409,7 @@ __device__ __forceinline__ void st_stream(double *p, double v) {
     else *p = v;
 }
 
-template <bool STREAM>
+template <bool STREAM, int ITEMS>
 __global__ __launch_bounds__(MP_THREADS) void k_pr_tiles(const int32_t *__restrict__ mp_row,
                                                          const int64_t *__restrict__ mp_edge,
                                                          const int64_t *__restrict__ off,
@@ -419,9 +418,10 @@ __global__ __launch_bounds__(MP_THREADS) void k_pr_tiles(const int32_t *__restri
                                                          double damp, double *xn, double *pf, double *pl,
                                                          const double *done) {
     if (*done != 0.0) return;
-    __shared__ double s_val[MP_ITEMS];
-    __shared__ int32_t s_off[MP_ITEMS + 1];
-    __shared__ int32_t s_long[MP_ITEMS / MP_LONG + 2];
+    constexpr int IPT = ITEMS / MP_THREADS;
+    __shared__ double s_val[ITEMS];
+    __shared__ int32_t s_off[ITEMS + 1];
+    __shared__ int32_t s_long[ITEMS / MP_LONG + 2];
     __shared__ int32_t s_nlong;
     const int64_t b = blockIdx.x;
     const int32_t r0 = mp_row[b], r1 = mp_row[b + 1];
@@ -431,10 +431,10 @@ __global__ __launch_bounds__(MP_THREADS) void k_pr_tiles(const int32_t *__restri
     const int t = threadIdx.x;
     if (t == 0) s_nlong = 0;
     // stage the entries: all column loads first, the row starts while they are in
-    // flight, then all gathers (MP_IPT in flight per lane)
-    uint32_t c[MP_IPT];
+    // flight, then all gathers (IPT in flight per lane)
+    uint32_t c[IPT];
 #pragma unroll
-    for (int u = 0; u < MP_IPT; ++u) {
+    for (int u = 0; u < IPT; ++u) {
         const int j = t + u * MP_THREADS;
         c[u] = j < ne ? (uint32_t)ld_stream<STREAM>(&col[e0 + j]) : DEAD;
     }
@@ -443,11 +443,11 @@ __global__ __launch_bounds__(MP_THREADS) void k_pr_tiles(const int32_t *__restri
         const int64_t o = ld_stream<STREAM>(&off[r0 + i]) - e0;
         s_off[i] = (int32_t)(o < 0 ? -1 : o);
     }
-    double v[MP_IPT];
+    double v[IPT];
 #pragma unroll
-    for (int u = 0; u < MP_IPT; ++u) v[u] = (c[u] & DEAD) ? 0.0 : contrib[c[u] & ID_MASK];
+    for (int u = 0; u < IPT; ++u) v[u] = (c[u] & DEAD) ? 0.0 : contrib[c[u] & ID_MASK];
 #pragma unroll
-    for (int u = 0; u < MP_IPT; ++u) {
+    for (int u = 0; u < IPT; ++u) {
         const int j = t + u * MP_THREADS;
         if (j < ne) s_val[j] = v[u];
     }
@@ -582,13 +582,18 @@ static int pr_iterate(dg_graph *g, const int32_t *A, int64_t na, int64_t edges, 
     // every vertex pulled: merge-path tiles over the base level, then the diff level
     const Dir &R = *g->rev;
     const bool tiles = A == nullptr && g->cfg.pr_pull != 1;
+    const int items = g->cfg.pr_tile == 1024 || g->cfg.pr_tile == 4096 ? g->cfg.pr_tile : MP_ITEMS;
+    const bool nt = g->cfg.pr_pull != 2;
+    auto tiles_kernel = items == 1024 ? (nt ? k_pr_tiles<true, 1024> : k_pr_tiles<false, 1024>)
+                      : items == 4096 ? (nt ? k_pr_tiles<true, 4096> : k_pr_tiles<false, 4096>)
+                                      : (nt ? k_pr_tiles<true, 2048> : k_pr_tiles<false, 2048>);
     int64_t nb = 0;
     if (tiles) {
-        nb = ((int64_t)g->n + R.m + MP_ITEMS - 1) / MP_ITEMS;
+        nb = ((int64_t)g->n + R.m + items - 1) / items;
         DG_TRY(ws.mp_row.ensure((size_t)nb + 1));
         DG_TRY(ws.mp_edge.ensure((size_t)nb + 1));
         DG_TRY(ws.mp_part.ensure(2 * (size_t)nb + 2));
-        hipLaunchKernelGGL(k_mp_partition, dim3(grid_for(nb + 1)), dim3(256), 0, s, R.off.p, g->n, R.m, nb,
+        hipLaunchKernelGGL(k_mp_partition, dim3(grid_for(nb + 1)), dim3(256), 0, s, R.off.p, g->n, R.m, nb, items,
                            ws.mp_row.p, ws.mp_edge.p);
         DG_HIP(hipGetLastError());
     }
@@ -610,7 +615,7 @@ static int pr_iterate(dg_graph *g, const int32_t *A, int64_t na, int64_t edges, 
             if (tiles) {
                 // tiles: off 8 + xn 8 per row, col 4 + contrib 8 per base entry
                 ps = prof_begin("pr_tiles", s);
-                hipLaunchKernelGGL(g->cfg.pr_pull == 2 ? k_pr_tiles<false> : k_pr_tiles<true>, dim3((unsigned)nb),
+                hipLaunchKernelGGL(tiles_kernel, dim3((unsigned)nb),
                                    dim3(MP_THREADS), 0, s, ws.mp_row.p,
                                    ws.mp_edge.p, R.off.p, R.col.p, contrib, prs + 2, damping, xn, pf, pl, done);
                 prof_end(ps, s, 16.0 * (double)g->n + 12.0 * (double)R.m);

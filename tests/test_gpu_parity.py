@@ -336,8 +336,8 @@ def hub_graph(n=1 << 14, hub_in=12000, seed=11):
     return n, s, d, w
 
 
-@pytest.mark.parametrize("pull", [0, 1, 2])
-def test_pagerank_whole_graph_pull(pull):
+@pytest.mark.parametrize("pull,tile", [(0, 0), (1, 0), (2, 0), (0, 1024), (0, 4096)])
+def test_pagerank_whole_graph_pull(pull, tile):
     """Static solve and global-form updates, merge-path tiles with non-temporal
     streams (0), per-vertex waves (1) or tiles without the hints (2), with a live
     diff level (no merges), against the oracle."""
@@ -346,6 +346,7 @@ def test_pagerank_whole_graph_pull(pull):
     c = cfg(merge=1e9)
     c.pr_mode = 2
     c.pr_pull = pull
+    c.pr_tile = tile
     G = dg.Graph(n, s, d, w, config=c)
     q = G.pr_attach(0.85, PR_TOL, 1000)
     r, it, conv = q.read()
