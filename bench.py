@@ -50,13 +50,16 @@ CSRC = os.path.join(ROOT, "paper_2507_11094_amd", "csrc")
 # HBM bytes per launch read from rocprofv3 FETCH_SIZE / WRITE_SIZE (KiB per
 # dispatch) for the named kernel and workload, divided by what the same counters
 # read per byte of a plain 256 MiB device copy (FETCH_SIZE 0.5, WRITE_SIZE 1.0
-# counted bytes per byte moved).  Each entry holds
-# the SHA-1 of the kernel's source file at the time the counters were taken; a
-# changed source makes the figure stale and it is reported as null.
+# counted bytes per byte moved).  Each entry holds the SHA-1 of the kernel's own
+# source text (its template line, signature and body) at the time the counters
+# were taken; a changed kernel makes the figure stale and it is reported as null.
 MEASURED_TRAFFIC: dict = {
     ("k_pr_tiles", "rmat22-dynamic-sssp+pagerank"): {
-        "source": "pagerank.hip", "sha1": "51cca71f7849c97bf3150fa70155803c0d178d61",
-        "fetch_kib": 938280.0, "write_kib": 35908.8, "fetch_factor": 0.5, "write_factor": 1.0},
+        "source": "pagerank.hip", "sha1": "7629ea5d8434680f962621e3514f53012baa1018",
+        "fetch_kib": 938314.0, "write_kib": 35898.3, "fetch_factor": 0.5, "write_factor": 1.0},
+    ("k_merge_tiles", "batched4096-rmat10to14-dynamic-sssp"): {
+        "source": "graph.hip", "sha1": "ee55ed07154bb1a5b07db5162f6b434817d37359",
+        "fetch_kib": 3040372.4, "write_kib": 3291721.6, "fetch_factor": 0.5, "write_factor": 1.0},
     ("k_tc_delta", "rmat20-undirected-dynamic-tc"): {
         "source": "tc.hip", "sha1": "9fd8d87e3bfcaa15f061353446808f472d110b52",
         "fetch_kib": 281933.3, "write_kib": 768.0, "fetch_factor": 0.5, "write_factor": 1.0},
@@ -98,7 +101,7 @@ def traffic_for(kernel: str, workload: str):
 
 KERNEL_SOURCE = {"pr_pull": ("k_pr_pull", "pagerank.hip"), "pr_tiles": ("k_pr_tiles", "pagerank.hip"),
                  "pr_apply": ("k_pr_apply", "pagerank.hip"),
-                 "merge_base": ("k_merge_base", "graph.hip"),
+                 "merge_base": ("k_merge_tiles", "graph.hip"),
                  "sssp_worklist": ("k_wl_cut + pull + k_wl_push", "worklist.hip"),
                  "tc_delta": ("k_tc_delta", "tc.hip")}
 
@@ -225,6 +228,7 @@ def run_single(args, kind: str) -> int:
     cfg.pr_mode = args.pr_mode
     cfg.pr_pull = args.pr_pull
     cfg.pr_tile = args.pr_tile
+    cfg.merge_tile = args.merge_tile
     t = time.perf_counter()
     G = dg.Graph(n, s, d, w, undirected=undirected, config=cfg)
     log(f"graph built on device in {time.perf_counter() - t:.2f}s")
@@ -400,6 +404,7 @@ def run_batched(args) -> int:
     torch.cuda.synchronize()
     cfg = dg.Config()
     cfg.heavy_degree = args.heavy_degree
+    cfg.merge_tile = args.merge_tile
     t = time.perf_counter()
     S = dg.GraphSet(members, config=cfg)
     info = S.info()
@@ -442,6 +447,7 @@ def run_batched(args) -> int:
         # applied, then every member's SSSP from scratch
         kk, cols = dfwd
         cfg2 = dg.Config()
+        cfg2.merge_tile = args.merge_tile
         S2 = dg.GraphSet(members, config=cfg2)
         torch.cuda.synchronize()
         t = time.perf_counter()
@@ -700,6 +706,8 @@ def main() -> int:
                     help="whole-graph PageRank pull: 0 merge-path tiles with non-temporal streams, 1 per-vertex "
                          "waves, 2 merge-path tiles without the hints")
     ap.add_argument("--pr-tile", type=int, default=0, help="rows + entries per pull tile: 1024, 2048 (0) or 4096")
+    ap.add_argument("--merge-tile", type=int, default=0,
+                    help="rows + entries per merge-path tile of the CSR merge: 512 (0), 1024 or 2048")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run five plain 256 MiB device-to-device copies (reference for the "
                          "FETCH_SIZE / WRITE_SIZE counter scale) and exit")

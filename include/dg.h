@@ -104,7 +104,10 @@ typedef struct dg_config {
     /* Rows + entries per merge-path tile of the whole-graph pull: 1024, 2048 or
      * 4096 (0 or anything else: 2048). */
     int32_t pr_tile;
-    int32_t reserved[2];
+    /* Rows + entries per merge-path tile of the CSR merge: 512, 1024 or 2048
+     * (0 or anything else: 512). */
+    int32_t merge_tile;
+    int32_t reserved[1];
 } dg_config;
 
 /* Per-batch statistics and phase timings (HIP events on the graph's stream). */

@@ -137,6 +137,7 @@ struct Work {
     DBuf<int32_t> mp_row;                 // merge-path tile starts (row, entry) of the whole-graph pull
     DBuf<int64_t> mp_edge;
     DBuf<double> mp_part;                 // per-tile partial sums of rows split across tiles
+    DBuf<int64_t> mp_doff;                // merge tiles: diff-level bounds of each tile's first row
     // device work queue of the persistent traversals (worklist.hip)
     DBuf<int64_t> wq;
     DBuf<uint64_t> wseq, wctr;

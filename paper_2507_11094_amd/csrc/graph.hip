@@ -114,7 +114,7 @@ void ws_free(dg_graph *g) {
     w.nkey.release(); w.nw.release(); w.tcu.release(); w.tcv.release(); w.tmp.release();
     w.scan64.release(); w.tscan.release(); w.f0.release(); w.f1.release(); w.heavy.release();
     w.stamp.release(); w.part.release(); w.prs.release();
-    w.mp_row.release(); w.mp_edge.release(); w.mp_part.release();
+    w.mp_row.release(); w.mp_edge.release(); w.mp_part.release(); w.mp_doff.release();
     w.farflag.release(); w.far0.release(); w.far1.release(); w.bpart.release();
     w.rbuf.release(); w.skey.release(); w.sx.release(); w.sc.release(); w.sxn.release();
     w.wq.release(); w.wseq.release(); w.wctr.release(); w.inq.release();
@@ -278,14 +278,17 @@ __global__ void k_deg_to_i64(int32_t n, const int32_t *deg, int64_t *out) {
 // the tile.  Diff entries are written at their insertion points by the base
 // entries of their row (rows with an empty base part: k_merge_diff_empty).
 constexpr int MG_THREADS = 256;
-constexpr int MG_ITEMS = 1024;
-constexpr int MG_IPT = MG_ITEMS / MG_THREADS;
+constexpr int MG_ITEMS = 512;  // default items per tile (cfg.merge_tile picks 512 / 1024 / 2048)
 constexpr int MG_WAVES = MG_THREADS / WAVE;
 
-__global__ void k_mg_partition(const int64_t *__restrict__ off, int32_t n, int64_t m, int64_t nb,
-                               int32_t *mp_row, int64_t *mp_edge) {
+// Tile b starts at (mp_row[b], mp_edge[b]); mp_dlo[b] = doff[row] and mp_dhi[b] =
+// doff[row + 1] (clamped to n) bound the diff entries of its rows without a
+// dependent load inside the tile kernel.
+__global__ void k_mg_partition(const int64_t *__restrict__ off, const int64_t *__restrict__ doff, int32_t n,
+                               int64_t m, int64_t nb, int items, int32_t *mp_row, int64_t *mp_edge,
+                               int64_t *mp_dlo, int64_t *mp_dhi) {
     for (int64_t b = gtid(); b <= nb; b += gstride()) {
-        const int64_t diag = min(b * (int64_t)MG_ITEMS, (int64_t)n + m);
+        const int64_t diag = min(b * (int64_t)items, (int64_t)n + m);
         int64_t lo = max(diag - m, (int64_t)0), hi = min(diag, (int64_t)n);
         while (lo < hi) {
             const int64_t p = (lo + hi) >> 1;
@@ -294,6 +297,8 @@ __global__ void k_mg_partition(const int64_t *__restrict__ off, int32_t n, int64
         }
         mp_row[b] = (int32_t)lo;
         mp_edge[b] = diag - lo;
+        mp_dlo[b] = doff[lo];
+        mp_dhi[b] = doff[min(lo + 1, (int64_t)n)];
     }
 }
 
@@ -307,7 +312,6 @@ __device__ __forceinline__ void merge_put(int32_t *col2, int32_t *w2, int64_t ca
     }
 }
 
-constexpr int MG_DCAP = 1024;  // diff entries of a tile's rows staged in LDS (else read from memory)
 
 __device__ __forceinline__ int lds_lower(const int32_t *a, int lo, int hi, uint32_t v) {
     while (lo < hi) {
@@ -318,19 +322,24 @@ __device__ __forceinline__ int lds_lower(const int32_t *a, int lo, int hi, uint3
     return lo;
 }
 
+// ITEMS rows + entries per tile; up to ITEMS diff entries of its rows are staged in
+// LDS (more are read from memory).
+template <int ITEMS>
 __global__ __launch_bounds__(MG_THREADS) void k_merge_tiles(
     int32_t n, const int32_t *__restrict__ mp_row, const int64_t *__restrict__ mp_edge,
+    const int64_t *__restrict__ mp_dlo, const int64_t *__restrict__ mp_dhi,
     const int64_t *__restrict__ off, const int32_t *__restrict__ col, const int32_t *__restrict__ w,
     const int64_t *__restrict__ doff, const int32_t *__restrict__ dcol, const int32_t *__restrict__ dw,
     const int64_t *__restrict__ off2, const int64_t *__restrict__ RB, const int64_t *__restrict__ TB,
     int32_t *__restrict__ col2, int32_t *__restrict__ w2, int64_t cap, int64_t *cnt) {
-    __shared__ int32_t s_off[MG_ITEMS + 1];  // row start - e0 (row 0: -1 when it began earlier)
-    __shared__ int32_t s_o2[MG_ITEMS + 1];   // off2[r] - off2[r0]
-    __shared__ int32_t s_rb[MG_ITEMS + 1];   // RB[r] - RB[r0]
-    __shared__ int32_t s_dlo[MG_ITEMS + 2];  // doff[r] - doff[r0]
-    __shared__ int32_t s_col[MG_ITEMS];      // the tile's entries
-    __shared__ int32_t s_dc[MG_DCAP], s_dw[MG_DCAP];
-    __shared__ int32_t s_wd[MG_IPT][MG_WAVES];
+    constexpr int IPT = ITEMS / MG_THREADS;
+    __shared__ int32_t s_off[ITEMS + 1];  // row start - e0 (row 0: -1 when it began earlier)
+    __shared__ int32_t s_o2[ITEMS + 1];   // off2[r] - off2[r0]
+    __shared__ int32_t s_rb[ITEMS + 1];   // RB[r] - RB[r0]
+    __shared__ int32_t s_dlo[ITEMS + 2];  // doff[r] - doff[r0]
+    __shared__ int32_t s_col[ITEMS];      // the tile's entries
+    __shared__ int32_t s_dc[ITEMS], s_dw[ITEMS];
+    __shared__ int32_t s_wd[IPT][MG_WAVES];
     __shared__ int64_t s_base[5];            // off[r0], off2[r0], RB[r0], tombstones before e0, doff[r0]
     const int64_t b = blockIdx.x;
     const int32_t r0 = mp_row[b], r1 = mp_row[b + 1];
@@ -339,11 +348,11 @@ __global__ __launch_bounds__(MG_THREADS) void k_merge_tiles(
     const int32_t nr = r1 - r0;
     const int t = threadIdx.x, wv = t / WAVE, l = lane_id();
     // entries (coalesced) and their tombstone ballots
-    uint32_t c[MG_IPT];
-    int32_t wt[MG_IPT];
-    int32_t lp[MG_IPT];
+    uint32_t c[IPT];
+    int32_t wt[IPT];
+    int32_t lp[IPT];
 #pragma unroll
-    for (int u = 0; u < MG_IPT; ++u) {
+    for (int u = 0; u < IPT; ++u) {
         const int j = u * MG_THREADS + t;
         const bool valid = j < ne;
         c[u] = valid ? (uint32_t)col[e0 + j] : 0u;
@@ -354,7 +363,7 @@ __global__ __launch_bounds__(MG_THREADS) void k_merge_tiles(
         if (l == 0) s_wd[u][wv] = __popcll(bm);
     }
     // rows r0 .. r1 (r1: the row still open at the tile's end, if any)
-    const int64_t dbase = doff[r0];
+    const int64_t dbase = mp_dlo[b];
     for (int i = t; i <= nr + 1; i += MG_THREADS) {
         const int32_t r = r0 + i;
         if (r <= n) s_dlo[i] = (int32_t)(doff[r] - dbase);
@@ -365,8 +374,8 @@ __global__ __launch_bounds__(MG_THREADS) void k_merge_tiles(
         s_rb[i] = (int32_t)(RB[r] - RB[r0]);
     }
     // the diff entries of the tile's rows (one contiguous range of the diff level)
-    const int64_t ndt = doff[min(r1 + 1, n)] - dbase;
-    const bool dlds = ndt <= MG_DCAP;
+    const int64_t ndt = mp_dhi[b + 1] - dbase;
+    const bool dlds = ndt <= ITEMS;
     if (dlds)
         for (int q = t; q < ndt; q += MG_THREADS) {
             s_dc[q] = dcol[dbase + q];
@@ -376,8 +385,9 @@ __global__ __launch_bounds__(MG_THREADS) void k_merge_tiles(
         // tombstones before e0: counter blocks before its block + a ballot count inside it
         const int64_t st = (e0 / TILE) * TILE;
         int cd = 0;
-        for (int64_t q = st; q < e0; q += WAVE) {
-            const int64_t idx = q + l;
+#pragma unroll
+        for (int q = 0; q < TILE / WAVE; ++q) {
+            const int64_t idx = st + q * WAVE + l;
             cd += __popcll(ballot(idx < e0 && ((uint32_t)col[idx] & DEAD)));
         }
         if (l == 0) {
@@ -391,7 +401,7 @@ __global__ __launch_bounds__(MG_THREADS) void k_merge_tiles(
     __syncthreads();
     int64_t pre = s_base[3];
 #pragma unroll
-    for (int u = 0; u < MG_IPT; ++u) {
+    for (int u = 0; u < IPT; ++u) {
         int64_t pu = pre;
         for (int q = 0; q < wv; ++q) pu += s_wd[u][q];
         for (int q = 0; q < MG_WAVES; ++q) pre += s_wd[u][q];
@@ -473,19 +483,23 @@ static int merge_into(dg_graph *g, Dir &d, int64_t *off2, int32_t *col2, int32_t
                        tsin);
     DG_TRY(scan_excl(g, tsin, TB, nblk + 2));
     // merge-path tiles
-    const int64_t nb = ((int64_t)n + d.m + MG_ITEMS - 1) / MG_ITEMS;
+    const int items = g->cfg.merge_tile == 512 || g->cfg.merge_tile == 2048 ? g->cfg.merge_tile : MG_ITEMS;
+    const int64_t nb = ((int64_t)n + d.m + items - 1) / items;
     DG_TRY(ws.mp_row.ensure((size_t)nb + 1));
     DG_TRY(ws.mp_edge.ensure((size_t)nb + 1));
-    hipLaunchKernelGGL(k_mg_partition, dim3(grid_for(nb + 1)), dim3(256), 0, s, d.off.p, n, d.m, nb, ws.mp_row.p,
-                       ws.mp_edge.p);
+    DG_TRY(ws.mp_doff.ensure(2 * ((size_t)nb + 1)));
+    int64_t *mp_dlo = ws.mp_doff.p, *mp_dhi = mp_dlo + (nb + 1);
+    hipLaunchKernelGGL(k_mg_partition, dim3(grid_for(nb + 1)), dim3(256), 0, s, d.off.p, d.doff.p, n, d.m, nb,
+                       items, ws.mp_row.p, ws.mp_edge.p, mp_dlo, mp_dhi);
     DG_HIP(hipGetLastError());
     DG_TRY(counters_clear(g));
     // merge bytes: col+w read 8 per old entry, write 8 per new entry, and per row
     // off, doff, off2 and the tombstone prefix (8 each)
     int pm = prof_begin("merge_base", s);
+    auto tiles_kernel = items == 512 ? k_merge_tiles<512> : (items == 2048 ? k_merge_tiles<2048> : k_merge_tiles<1024>);
     if (nb > 0)
-        hipLaunchKernelGGL(k_merge_tiles, dim3((unsigned)nb), dim3(MG_THREADS), 0, s, n, ws.mp_row.p,
-                           ws.mp_edge.p, d.off.p, d.col.p, d.w.p, d.doff.p, d.dcol.p, d.dw.p, off2, RB, TB, col2, w2,
+        hipLaunchKernelGGL(tiles_kernel, dim3((unsigned)nb), dim3(MG_THREADS), 0, s, n, ws.mp_row.p,
+                           ws.mp_edge.p, mp_dlo, mp_dhi, d.off.p, d.col.p, d.w.p, d.doff.p, d.dcol.p, d.dw.p, off2, RB, TB, col2, w2,
                            m2, ws.dcnt);
     prof_end(pm, s, 8.0 * (double)d.m + 8.0 * (double)m2 + 32.0 * (double)n + 8.0 * (double)d.dm);
     if (d.dm > 0)

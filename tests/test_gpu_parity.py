@@ -369,6 +369,32 @@ def test_pagerank_whole_graph_pull(pull, tile):
     pr_check(rs, n, cs, cd)
 
 
+@pytest.mark.parametrize("tile", [512, 1024, 2048])
+def test_merge_tile_sizes(tile):
+    """CSR merge with 512 / 1024 / 2048 rows + entries per merge-path tile: a hub
+    row longer than every tile, diff rows with more entries than the tile's LDS
+    staging (read from memory instead), runs of empty rows; every batch merges."""
+    n, s, d, w = hub_graph()
+    say("merge tile", tile, "arcs", s.size)
+    c = cfg(merge=-1.0)
+    c.merge_tile = tile
+    G = dg.Graph(n, s, d, w, config=c)
+    q = G.sssp_attach(1)
+    cs, cd, cw = s, d, w
+    for i, (k, hub) in enumerate([(3000, 2500), (500, 0), (9000, 700)]):
+        bs, bd, bw, bo = graphgen.update_batch(n, cs, cd, k, 7300 + i)
+        lo = 12500 + 800 * i
+        extra_s = np.arange(lo, min(lo + hub, n), dtype=np.int32)
+        bs = np.concatenate([bs, extra_s]); bd = np.concatenate([bd, np.zeros(extra_s.size, np.int32)])
+        bw = np.concatenate([bw, np.full(extra_s.size, 5, np.int32)])
+        bo = np.concatenate([bo, np.ones(extra_s.size, np.uint8)])
+        st = G.apply(bs, bd, bw, bo)
+        assert st.merged
+        cs, cd, cw, _ = oracle.apply(n, cs, cd, cw, bs, bd, bw, bo)
+        assert_edges(G, cs, cd, cw)
+        assert np.array_equal(q.read()[0], oracle.sssp(n, cs, cd, cw, 1))
+
+
 def test_pagerank_dangling_and_isolated():
     say("pagerank dangling")
     # 0->1, 1 dangling, 2 isolated, 3->0, 3->1
