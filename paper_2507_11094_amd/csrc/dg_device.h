@@ -58,6 +58,14 @@ __device__ __forceinline__ int32_t row_of(const int64_t *__restrict__ off, int32
     return lo;
 }
 
+// Orders the LDS writes of a wave's lanes before the reads that follow (all lanes
+// of the wave must reach it).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Wave-wide inclusive scan (Hillis-Steele over 64 lanes).
 template <class T>
 __device__ __forceinline__ T wave_incl_scan(T x) {

@@ -12,10 +12,11 @@
 // modified_add of the listing.
 //
 // Static (comparator; Appendix A staticTC counts every triangle once by vertex
-// order): here vertices are ordered by (degree, id) so every triangle is counted
-// once from its lowest-ranked edge, and each intersection walks the row of the
-// lower-ranked endpoint -- the standard degree ordering that bounds work on
-// skewed graphs.
+// order): here vertices are ranked by (degree, id), every edge is oriented from
+// its lower- to its higher-ranked end, and a triangle is counted once at its
+// lowest-ranked vertex by intersecting two forward lists -- the standard forward
+// algorithm, whose degree ordering bounds every forward list by sqrt(2m) on skewed
+// graphs.
 #include <algorithm>
 
 #include "dg_device.h"
@@ -158,31 +159,105 @@ __device__ __forceinline__ bool rank_lt(int32_t du, int32_t u, int32_t dv, int32
     return du < dv || (du == dv && u < v);
 }
 
-// For every arc (x, y) with rank(x) < rank(y): common neighbours c of x and y with
-// rank(c) > rank(y).  One wave per row x; lanes walk N(x) for each oriented arc.
-__global__ __launch_bounds__(256) void k_tc_static(int32_t n, const int64_t *__restrict__ off,
+// Forward (oriented) lists: N+(x) = the neighbours of x ranked above x, kept in id
+// order.  One wave per row; pass 1 writes |N+(x)| to odeg, pass 2 fills ocol
+// from the scanned offsets ooff (ballot compaction keeps the order).
+template <bool FILL>
+__global__ __launch_bounds__(256) void k_tc_orient(int32_t n, const int64_t *__restrict__ off,
                                                    const int32_t *__restrict__ col,
-                                                   const int32_t *__restrict__ deg,
-                                                   unsigned long long *total) {
+                                                   const int32_t *__restrict__ deg, int64_t *odeg,
+                                                   const int64_t *__restrict__ ooff, int32_t *ocol) {
     const int64_t wave_global = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / WAVE;
     const int l = lane_id();
-    uint64_t acc = 0;
     for (int64_t x = wave_global; x < n; x += nwaves) {
         const int64_t xs = off[x], xe = off[x + 1];
         const int32_t dx = deg[x];
-        for (int64_t p = xs; p < xe; ++p) {
-            const int32_t y = col[p] & (int32_t)ID_MASK;
-            const int32_t dy = deg[y];
-            if (!rank_lt(dx, (int32_t)x, dy, y)) continue;
-            const int64_t ys = off[y], ye = off[y + 1];
-            for (int64_t j = xs + l; j < xe; j += WAVE) {
-                const int32_t c = col[j] & (int32_t)ID_MASK;
-                const int32_t dc = deg[c];
-                if (!rank_lt(dy, y, dc, c)) continue;
-                if (find_sorted(col, ys, ye, (uint32_t)c) >= 0) ++acc;
+        int64_t cnt = 0;
+        const int64_t base = FILL ? ooff[x] : 0;
+        for (int64_t j0 = xs; j0 < xe; j0 += WAVE) {
+            const int64_t j = j0 + l;
+            bool up = false;
+            int32_t y = 0;
+            if (j < xe) {
+                const uint32_t c = (uint32_t)col[j];
+                y = (int32_t)(c & ID_MASK);
+                up = !(c & DEAD) && rank_lt(dx, (int32_t)x, deg[y], y);
+            }
+            const uint64_t b = ballot(up);
+            if (FILL && up) ocol[base + cnt + __popcll(b & lanemask_lt())] = y;
+            cnt += __popcll(b);
+        }
+        if (!FILL && l == 0) odeg[x] = cnt;
+    }
+}
+
+// Every triangle, ranked a < b < c, is counted once: at x = a and y = b, as the
+// common element c of N+(a) and N+(b).  One wave per row x copies N+(x) to LDS
+// (when it fits) and walks y over N+(x).  For each y the lanes either stream
+// N+(y) and binary-search the LDS copy (one coalesced load per 64 elements), or,
+// when N+(y) is much longer, take the elements of N+(x) and binary-search N+(y)
+// in memory.
+constexpr int TCF_CAP = 1024;  // forward-list entries of a row staged in LDS, per wave
+
+__device__ __forceinline__ bool lds_has(const int32_t *a, int len, int32_t v) {
+    int lo = 0, hi = len;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (a[mid] < v) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo < len && a[lo] == v;
+}
+
+__global__ __launch_bounds__(256) void k_tc_forward(int32_t n, const int64_t *__restrict__ ooff,
+                                                    const int32_t *__restrict__ ocol,
+                                                    unsigned long long *total) {
+    __shared__ int32_t s_nx[256 / WAVE][TCF_CAP];
+    const int64_t wave_global = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / WAVE;
+    const int l = lane_id();
+    int32_t *sx = s_nx[threadIdx.x / WAVE];
+    uint64_t acc = 0;
+    for (int64_t x = wave_global; x < n; x += nwaves) {
+        const int64_t xs = ooff[x], xe = ooff[x + 1];
+        const int64_t dx = xe - xs;
+        if (dx < 2) continue;
+        const bool staged = dx <= TCF_CAP;
+        if (staged) {
+            for (int64_t j = l; j < dx; j += WAVE) sx[j] = ocol[xs + j];
+            wave_sync();
+        }
+        const int64_t rx = (dx + WAVE - 1) / WAVE;
+        for (int64_t p0 = 0; p0 < dx; p0 += WAVE) {
+            // lane k fetches the list bounds of the k-th y of this chunk of N+(x)
+            int64_t mys = 0, mye = 0;
+            if (p0 + l < dx) {
+                const int32_t y = staged ? sx[p0 + l] : ocol[xs + p0 + l];
+                mys = ooff[y];
+                mye = ooff[y + 1];
+            }
+            const int cnt = (int)(dx - p0 < WAVE ? dx - p0 : WAVE);
+            for (int k = 0; k < cnt; ++k) {
+                const int64_t ys = __shfl(mys, k, WAVE), ye = __shfl(mye, k, WAVE);
+                const int64_t dy = ye - ys;
+                if (staged && (dy + WAVE - 1) / WAVE <= 4 * rx) {
+                    // four loads in flight per lane before the LDS searches
+                    for (int64_t j0 = ys + l; j0 < ye; j0 += 4 * WAVE) {
+                        int32_t v[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) v[u] = j0 + u * WAVE < ye ? ocol[j0 + u * WAVE] : -1;
+#pragma unroll
+                        for (int u = 0; u < 4; ++u)
+                            if (v[u] >= 0 && lds_has(sx, (int)dx, v[u])) ++acc;
+                    }
+                } else {
+                    for (int64_t j = xs + l; j < xe; j += WAVE)
+                        if (find_sorted(ocol, ys, ye, (uint32_t)ocol[j]) >= 0) ++acc;
+                }
             }
         }
+        if (staged) wave_sync();  // the next row overwrites the staging
     }
     acc = wave_sum(acc);
     if (l == 0 && acc) atomicAdd(total, (unsigned long long)acc);
@@ -192,11 +267,23 @@ int tc_count_static(dg_graph *g, uint64_t *count) {
     DG_TRY(graph_merge(g));
     hipStream_t s = g->stream;
     Dir &F = g->fwd;
+    const int32_t n = g->n;
+    // the merge's spare target buffers hold the oriented lists (m / 2 entries)
+    DG_TRY(F.off2.ensure((size_t)n + 1));
+    DG_TRY(F.col2.ensure((size_t)(F.m / 2) + 1));
+    DG_TRY(g->ws.scan64.ensure((size_t)n + 1));
+    int64_t *odeg = g->ws.scan64.p, *ooff = F.off2.p;
+    int32_t *ocol = F.col2.p;
+    const int blocks = (int)std::min<int64_t>(((int64_t)n + 3) / 4, 32768);
+    hipLaunchKernelGGL(k_tc_orient<false>, dim3(blocks), dim3(256), 0, s, n, F.off.p, F.col.p, F.deg.p, odeg,
+                       nullptr, nullptr);
+    DG_TRY(fill_i64(odeg + n, 0, 1, s));
+    DG_TRY(scan_excl(g, odeg, ooff, (int64_t)n + 1));
+    hipLaunchKernelGGL(k_tc_orient<true>, dim3(blocks), dim3(256), 0, s, n, F.off.p, F.col.p, F.deg.p, nullptr,
+                       ooff, ocol);
     DG_TRY(counters_clear(g));
     unsigned long long *acc = reinterpret_cast<unsigned long long *>(g->ws.dcnt + C_TC1);
-    int64_t blocks = std::min<int64_t>(((int64_t)g->n + 3) / 4, 32768);
-    hipLaunchKernelGGL(k_tc_static, dim3((unsigned)blocks), dim3(256), 0, s, g->n, F.off.p, F.col.p,
-                       F.deg.p, acc);
+    hipLaunchKernelGGL(k_tc_forward, dim3(blocks), dim3(256), 0, s, n, ooff, ocol, acc);
     DG_HIP(hipGetLastError());
     DG_TRY(counters_read(g));
     *count = (uint64_t)g->ws.hcnt[C_TC1];
