@@ -106,6 +106,40 @@ KERNEL_SOURCE = {"pr_pull": ("k_pr_pull", "pagerank.hip"), "pr_tiles": ("k_pr_ti
                  "tc_delta": ("k_tc_delta", "tc.hip")}
 
 
+_COPY_GBS = None
+
+
+def copy_peak_gbs() -> float:
+    """Device-to-device copy bandwidth measured here (1 GiB, read + write bytes per
+    second, best of 10), reported beside the 8 TB/s vendor peak."""
+    global _COPY_GBS
+    if _COPY_GBS is None:
+        import torch
+
+        a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda:0")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        best = float("inf")
+        for _ in range(10):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            b.copy_(a)
+            e1.record()
+            e1.synchronize()
+            best = min(best, e0.elapsed_time(e1))
+        _COPY_GBS = round(2 * a.numel() / (best * 1e-3) / 1e9, 1)
+        del a, b
+        torch.cuda.empty_cache()
+    return _COPY_GBS
+
+
+def step_spread(ms: list) -> dict:
+    """Median, p10 and p90 of the per-step times (library phase timer)."""
+    v = np.asarray(ms, dtype=np.float64)
+    return {"median_ms": round(float(np.median(v)), 3), "p10_ms": round(float(np.percentile(v, 10)), 3),
+            "p90_ms": round(float(np.percentile(v, 90)), 3)}
+
+
 def roofline_of(prof: dict, workload: str, prefer: str | None = None) -> dict | None:
     """Roofline of the dominant profiled kernel (largest total time), or `prefer`."""
     if not prof:
@@ -115,6 +149,7 @@ def roofline_of(prof: dict, workload: str, prefer: str | None = None) -> dict | 
     launches = max(p["launches"], 1)
     achieved = p["bytes"] / (p["ms"] * 1e-3) / 1e9 if p["ms"] > 0 else 0.0
     kname = KERNEL_SOURCE.get(name, (name, None))[0]
+    copy = copy_peak_gbs()
     return {
         "kernel": kname,
         "bound": "hbm",
@@ -122,6 +157,8 @@ def roofline_of(prof: dict, workload: str, prefer: str | None = None) -> dict | 
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "copy_measured": copy,
+        "frac_of_copy": round(achieved / copy, 4) if copy else None,
         "traffic": traffic_for(kname, workload),
         "launches": p["launches"],
         "avg_launch_us": round(1e3 * p["ms"] / launches, 2),
@@ -311,6 +348,7 @@ def run_single(args, kind: str) -> int:
                       "tc_removed": avg("tc_removed"), "tc_added": avg("tc_added"),
                       "merged": sum(x["merged"] for x in stats)},
         "gteps": round(sum(x["edges_traversed"] for x in stats) / elapsed / 1e9, 3),
+        "step_ms": step_spread([x["t_total_ms"] for x in stats]),
         "kernels": kernel_table(prof),
     }
     if kind == "tc":
@@ -497,6 +535,7 @@ def run_batched(args) -> int:
                per_step={"sssp_invalidated": avg("sssp_invalidated"), "deleted": avg("deleted"),
                          "inserted": avg("inserted"), "merged": sum(x["merged"] for x in stats)},
                gteps=round(sum(x["edges_traversed"] for x in stats) / elapsed / 1e9, 3),
+               step_ms=step_spread([x["t_total_ms"] for x in stats]),
                graph_launches=gstats, kernels=kernel_table(prof))
     print(json.dumps(out), flush=True)
     S.close()
@@ -724,8 +763,8 @@ def main() -> int:
         return 0
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures the dynamic-graph hot path on one GPU; this build runs on a single "
-              "MI355X, so --gpus must be 1 (multi-GPU sharding is a design note, not a measured path).",
+        print("bench.py measures the dynamic-graph hot path on one MI355X, so --gpus must be 1; "
+              "sharding over several GPUs is designed (vertex partition, RCCL exchanges) but not built.",
               file=sys.stderr)
         return 2
     if args.workload in ("rmat", "grid", "tc"):
