@@ -610,7 +610,7 @@ static int pr_iterate(dg_graph *g, const int32_t *A, int64_t na, int64_t edges, 
         const int grp = std::min(GROUP, max_iter - launched);
         slots.clear();
         for (int j = 0; j < grp; ++j) {
-            DG_TRY(counters_clear(g));
+            if (!tiles) DG_TRY(counters_clear(g));  // the heavy-row queue counters of the pull
             int ps;
             if (tiles) {
                 // tiles: off 8 + xn 8 per row, col 4 + contrib 8 per base entry

@@ -1,0 +1,173 @@
+"""GPU parity at the full benchmark sizes, in the configuration bench.py times.
+
+* R-MAT scale 22 (4,194,304 vertices, 67,108,864 arcs), two 100k batches:
+  distances bit-exact against the oracle's Dijkstra, the parent array a tight
+  shortest-path tree, PageRank within max-abs 1e-10 of the oracle's power
+  iteration.
+* 4096 x 4096 grid, one 100k batch, near-far SSSP (bucket width 8000):
+  distances bit-exact against Dijkstra; PageRank by a property that holds at any
+  size: one step of the dangling-uniform power iteration, built here from the
+  oracle's edge list, moves the result by at most the L1 tolerance, and the
+  ranks sum to 1.
+* Undirected R-MAT scale 20, three 1 % batches: the maintained triangle count
+  equals the static forward count of the same graph (a different algorithm and
+  kernel).  The exact oracle count runs at scale 17 (a scale-20 recount takes
+  minutes on one core).
+* 4,096 R-MAT graphs (415 M arcs), one step: every member of a seeded sample of
+  64, plus the largest, bit-exact against the oracle.
+"""
+import sys
+import time
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import graphgen
+import oracle
+import paper_2507_11094_amd as dg
+
+pytestmark = pytest.mark.gpu
+
+INF = dg.DG_INF
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def check_tree(n, s, d, w, src, dist, par):
+    """Parents of reachable vertices are tight arcs of (s, d, w), sorted by (s, d)."""
+    keys = (s.astype(np.int64) << 32) | d.astype(np.int64)
+    assert np.all(keys[1:] > keys[:-1])
+    reach = dist < INF
+    assert dist[src] == 0 and par[src] == -1
+    assert np.all(par[~reach] == -1)
+    v = np.nonzero(reach)[0]
+    v = v[v != src]
+    q = (par[v].astype(np.int64) << 32) | v.astype(np.int64)
+    pos = np.searchsorted(keys, q)
+    assert np.all(pos < keys.size) and np.all(keys[np.minimum(pos, keys.size - 1)] == q)
+    assert np.all(dist[par[v]].astype(np.int64) + w[pos] == dist[v].astype(np.int64))
+
+
+def batches_for(n, s, d, k, config, count, wmax, undirected=False):
+    keys = graphgen.edge_keys(s, d, undirected)
+    return [graphgen.update_batch(n, s, d, k, graphgen.config_seed(config, 100 + i), wmax=wmax,
+                                  undirected=undirected, existing=keys) for i in range(count)]
+
+
+def test_fullsize_rmat22_sssp_pagerank():
+    t0 = time.perf_counter()
+    n, s, d, w = graphgen.c2r_graph(22)
+    bats = batches_for(n, s, d, 100000, 1, 2, 100)
+    say("R-MAT 22 SSSP + PageRank, two 100k batches; inputs", round(time.perf_counter() - t0, 1), "s")
+    G = dg.Graph(n, s, d, w)  # the default configuration bench.py runs
+    qs = G.sssp_attach(0)
+    qp = G.pr_attach(0.85, 1e-9, 1000)
+    cs, cd, cw = s, d, w
+    for b in bats:
+        st = G.apply(*b)
+        cs, cd, cw, ost = oracle.apply(n, cs, cd, cw, *b)
+        assert (st.deleted, st.inserted) == (ost[0], ost[1])
+    dist, par = qs.read()
+    rank, _, conv = qp.read()
+    G.close()
+    say("oracle Dijkstra + power iteration at full size")
+    assert np.array_equal(dist, oracle.sssp(n, cs, cd, cw, 0))
+    check_tree(n, cs, cd, cw, 0, dist, par)
+    want, _, oconv = oracle.pagerank(n, cs, cd, 0.85, 1e-9, 1000)
+    assert conv and oconv
+    assert float(np.max(np.abs(rank - want))) <= 1e-10
+    assert abs(float(rank.sum()) - 1.0) <= 1e-12
+
+
+def test_fullsize_grid_sssp_pagerank():
+    t0 = time.perf_counter()
+    n, s, d, w = graphgen.c2g_graph(4096)
+    bats = batches_for(n, s, d, 100000, 1, 1, 1000)
+    say("grid 4096^2 near-far SSSP + PageRank, one 100k batch; inputs", round(time.perf_counter() - t0, 1), "s")
+    c = dg.Config()
+    c.sssp_delta = 8000
+    G = dg.Graph(n, s, d, w, config=c)
+    qs = G.sssp_attach(0)
+    qp = G.pr_attach(0.85, 1e-9, 1000)
+    G.apply(*bats[0])
+    dist, par = qs.read()
+    rank, _, conv = qp.read()
+    G.close()
+    cs, cd, cw, _ = oracle.apply(n, s, d, w, *bats[0])
+    say("oracle Dijkstra; PageRank fixed-point residual")
+    assert np.array_equal(dist, oracle.sssp(n, cs, cd, cw, 0))
+    check_tree(n, cs, cd, cw, 0, dist, par)
+    assert conv
+    assert abs(float(rank.sum()) - 1.0) <= 1e-12
+    outdeg = np.bincount(cs, minlength=n).astype(np.float64)
+    A = sp.csr_matrix((np.ones(cs.size), (cd, cs)), shape=(n, n))
+    contrib = np.where(outdeg > 0, rank / np.maximum(outdeg, 1.0), 0.0)
+    dang = float(rank[outdeg == 0].sum())
+    step = (1.0 - 0.85) / n + 0.85 * (A @ contrib + dang / n)
+    assert float(np.abs(step - rank).sum()) <= 1.5e-9
+
+
+def test_fullsize_tc_rmat20_dynamic_equals_recount():
+    t0 = time.perf_counter()
+    n, s, d = graphgen.c3_graph(20)[:3]
+    k = int(0.01 * s.size)
+    bats = batches_for(n, s, d, k, 2, 3, 100, undirected=True)
+    say("undirected R-MAT 20 TC, three 1 % batches; inputs", round(time.perf_counter() - t0, 1), "s")
+    G = dg.Graph(n, s, d, None, undirected=True)
+    q = G.tc_attach()
+    for i, b in enumerate(bats):
+        G.apply(*b)
+        dyn = q.read()
+        assert dyn == G.tc_static(), i
+    G.close()
+
+
+def test_tc_rmat17_against_oracle():
+    n, s, d = graphgen.c3_graph(17)[:3]
+    k = int(0.01 * s.size)
+    bats = batches_for(n, s, d, k, 2, 2, 100, undirected=True)
+    say("undirected R-MAT 17 TC against the oracle, two 1 % batches")
+    G = dg.Graph(n, s, d, None, undirected=True)
+    q = G.tc_attach()
+    cs, cd = s, d
+    for b in bats:
+        G.apply(*b)
+        cs, cd, _, _ = oracle.apply(n, cs, cd, np.ones(cs.size, np.int32), *b, undirected=True)
+    assert q.read() == oracle.triangles(n, cs, cd)
+    G.close()
+
+
+def test_fullsize_batched4096_sssp_sample():
+    t0 = time.perf_counter()
+    count = 4096
+    seed = graphgen.config_seed(3, 0)
+    scales = graphgen.uniform_int(graphgen.stream_seed(seed, "scale"), 0, count, 10, 14)
+    frac = 0.01 + 0.09 * graphgen.uniform01(graphgen.stream_seed(seed, "frac"), 0, count)
+    members, bats = [], []
+    for i in range(count):
+        sc = int(scales[i])
+        n, s, d, w = graphgen.rmat_directed(sc, 16 << sc, graphgen.config_seed(3, i))
+        members.append((n, s, d, w))
+        k = int(frac[i] * (16 << sc))
+        bats.append(graphgen.update_batch(n, s, d, k, graphgen.config_seed(3, 100000 + i),
+                                          existing=graphgen.edge_keys(s, d, False)))
+    say("batched set of", count, "R-MAT graphs, one step; inputs", round(time.perf_counter() - t0, 1), "s")
+    S = dg.GraphSet(members)  # captured frontier rounds, the set's default
+    info = S.info()
+    assert info["count"] == count and info["arcs"] == sum(m[1].size for m in members)
+    S.sssp_attach(np.zeros(count, np.int32))
+    st = S.apply(bats)
+    assert st.updates == sum(b[0].size for b in bats)
+    pick = graphgen.uniform_int(graphgen.stream_seed(seed, 991), 0, 64, 0, count - 1).tolist()
+    pick.append(int(np.argmax([m[0] for m in members])))
+    for i in sorted(set(pick)):
+        n, s, d, w = members[i]
+        s2, d2, w2, _ = oracle.apply(n, s, d, w, *bats[i])
+        dist, par = S.read(i)
+        assert np.array_equal(dist, oracle.sssp(n, s2, d2, w2, 0)), i
+        check_tree(n, s2, d2, w2, 0, dist, par)
+    S.close()
