@@ -47,6 +47,59 @@ __device__ __forceinline__ int64_t lower_key(const uint64_t *__restrict__ k, int
     return lo;
 }
 
+// Searches for items q0 .. q0+K-1 of an N-item chunk, run in lockstep so that a
+// lane keeps K loads in flight instead of one: for each item with act[q], v[q] is
+// looked up in the sorted range [off[row[q]], off[row[q] + 1]) of col, and out[q]
+// is its position (flags ignored, so tombstones are found too) or -1.
+template <int K, int N>
+__device__ __forceinline__ void find_rows_k(const int64_t *__restrict__ off, const int32_t *__restrict__ col,
+                                            const int32_t (&row)[N], const uint32_t (&v)[N],
+                                            const bool (&act)[N], int64_t (&out)[N], int q0) {
+    int64_t lo[K], hi[K], end[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        lo[j] = act[q0 + j] ? off[row[q0 + j]] : 0;
+        end[j] = act[q0 + j] ? off[row[q0 + j] + 1] : 0;
+        hi[j] = end[j];
+    }
+    for (;;) {
+        uint32_t c[K];
+#pragma unroll
+        for (int j = 0; j < K; ++j) c[j] = lo[j] < hi[j] ? ((uint32_t)col[(lo[j] + hi[j]) >> 1] & ID_MASK) : 0u;
+        bool more = false;
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            if (lo[j] < hi[j]) {
+                const int64_t mid = (lo[j] + hi[j]) >> 1;
+                if (c[j] < v[q0 + j]) lo[j] = mid + 1;
+                else hi[j] = mid;
+            }
+            more |= lo[j] < hi[j];
+        }
+        if (!more) break;
+    }
+    uint32_t c[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) c[j] = lo[j] < end[j] ? ((uint32_t)col[lo[j]] & ID_MASK) : ~0u;
+#pragma unroll
+    for (int j = 0; j < K; ++j) out[q0 + j] = lo[j] < end[j] && c[j] == v[q0 + j] ? lo[j] : -1;
+}
+
+// Base level, then the diff level for the items the base level lacks, K at a time.
+constexpr int FIND_K = 4;
+template <int N>
+__device__ __forceinline__ void find_arcs(const int64_t *off, const int32_t *col, const int64_t *doff,
+                                          const int32_t *dcol, const int32_t (&row)[N], const uint32_t (&v)[N],
+                                          const bool (&act)[N], int64_t (&pb)[N], int64_t (&pd)[N]) {
+#pragma unroll
+    for (int h = 0; h < N; h += FIND_K) find_rows_k<FIND_K>(off, col, row, v, act, pb, h);
+    bool miss[N];
+#pragma unroll
+    for (int q = 0; q < N; ++q) miss[q] = act[q] && pb[q] < 0;
+#pragma unroll
+    for (int h = 0; h < N; h += FIND_K) find_rows_k<FIND_K>(doff, dcol, row, v, miss, pd, h);
+}
+
 // Largest r in [lo, hi] with off[r] <= i: the row holding entry i.
 __device__ __forceinline__ int32_t row_of(const int64_t *__restrict__ off, int32_t lo, int32_t hi,
                                           int64_t i) {

@@ -176,6 +176,8 @@ struct dg_graph {
     int64_t m_live = 0;      // live arcs in fwd
     int32_t since_merge = 0; // batches applied since the last merge
     hipStream_t stream = nullptr;
+    hipStream_t aux = nullptr;                      // second stream: SSSP beside the PageRank steps
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     dg_config cfg{};
     dg::Work ws;
     std::vector<dg_query *> queries;
@@ -267,7 +269,24 @@ int sssp_static_multi(dg_graph *g, uint64_t *key, const int32_t *srcs, int64_t n
 int pr_init(dg_query *q);
 int pr_static_solve(dg_graph *g, double damping, double tol, int32_t max_iter, double *x,
                     double *contrib, double *xn, int32_t *iters, int32_t *conv);
-int pr_post_update(dg_query *q, int64_t n_applied_del, int64_t n_applied_ins, dg_batch_stats *st);
+// Work run once while PageRank steps are in flight on the graph's stream (or, where
+// they cannot overlap it, after them); its return code is kept in rc.
+struct SideWork {
+    std::function<int()> fn;
+    bool beside = false;  // set when it runs while the steps are in flight
+    bool done = false;
+    int rc = DG_OK;
+    void run() {
+        if (!done) {
+            done = true;
+            rc = fn();
+        }
+    }
+};
+// side (nullable) runs exactly once: right after the first group of whole-graph
+// tile steps is enqueued, else after the update.
+int pr_post_update(dg_query *q, int64_t n_applied_del, int64_t n_applied_ins, dg_batch_stats *st,
+                   SideWork *side = nullptr);
 int pr_read(dg_query *q, double *rank, bool dev);
 int pr_normalize(dg_graph *g, const double *x, double *rank, bool dev);
 

@@ -92,7 +92,8 @@ int counters_read(dg_graph *g) {
 int ws_init(dg_graph *g) {
     g->ws.dcnt = static_cast<int64_t *>(dmalloc(sizeof(int64_t) * C_COUNT));
     if (!g->ws.dcnt) return set_error(DG_ENOMEM, "counter allocation failed");
-    DG_HIP(hipHostMalloc((void **)&g->ws.hcnt, sizeof(int64_t) * C_COUNT, hipHostMallocDefault));
+    // C_COUNT counter slots, then 8 slots of PageRank step state
+    DG_HIP(hipHostMalloc((void **)&g->ws.hcnt, sizeof(int64_t) * (C_COUNT + 8), hipHostMallocDefault));
     for (auto &e : g->ws.ev) DG_HIP(hipEventCreate(&e));
     return counters_clear(g);
 }
@@ -120,6 +121,11 @@ void ws_free(dg_graph *g) {
     w.wq.release(); w.wseq.release(); w.wctr.release(); w.inq.release();
     if (w.dcnt) dfree(w.dcnt);
     if (w.hcnt) (void)hipHostFree(w.hcnt);
+    if (g->aux) (void)hipStreamDestroy(g->aux);
+    if (g->ev_fork) (void)hipEventDestroy(g->ev_fork);
+    if (g->ev_join) (void)hipEventDestroy(g->ev_join);
+    g->aux = nullptr;
+    g->ev_fork = g->ev_join = nullptr;
     for (auto &e : w.ev)
         if (e) (void)hipEventDestroy(e);
     w.dcnt = nullptr;
@@ -659,38 +665,44 @@ __global__ __launch_bounds__(CH_T) void k_expand_batch(int64_t k, const int32_t 
 // still intact for the pre-hooks).  The atomic MARK also dedups repeated
 // deletions of one arc.  Applied arcs are listed with their slot
 // (>= 0: base position, <= -2: diff position -2-p).
-__global__ void k_mark_deletes(int64_t na, const int32_t *ddu, const int32_t *ddv,
-                               const int64_t *__restrict__ off, int32_t *col,
-                               const int64_t *__restrict__ doff, int32_t *dcol, int undirected,
-                               int32_t *adu, int32_t *adv, int64_t *adpos, int32_t *tcu, int32_t *tcv,
-                               int64_t *cnt) {
+__global__ __launch_bounds__(CH_T) void k_mark_deletes(int64_t na, const int32_t *ddu, const int32_t *ddv,
+                                                       const int64_t *__restrict__ off, int32_t *col,
+                                                       const int64_t *__restrict__ doff, int32_t *dcol,
+                                                       int undirected, int32_t *adu, int32_t *adv,
+                                                       int64_t *adpos, int32_t *tcu, int32_t *tcv,
+                                                       int64_t *cnt) {
     __shared__ BlockScratch sc;
     for (int64_t c0 = (int64_t)blockIdx.x * CH; c0 < na; c0 += (int64_t)gridDim.x * CH) {
         const int64_t i0 = c0 + (int64_t)threadIdx.x * CH_IPT;
+        int32_t u[CH_IPT];
+        uint32_t v[CH_IPT];
+        bool ok[CH_IPT];
+        int64_t p[CH_IPT], r[CH_IPT];
+#pragma unroll
+        for (int q = 0; q < CH_IPT; ++q) {
+            ok[q] = i0 + q < na;
+            u[q] = ok[q] ? ddu[i0 + q] : 0;
+            v[q] = ok[q] ? (uint32_t)ddv[i0 + q] : 0u;
+        }
+        find_arcs(off, col, doff, dcol, u, v, ok, p, r);  // the diff level only where the base lacks the arc
         int64_t pos[CH_IPT];
         int64_t nap = 0, ntc = 0;
 #pragma unroll
         for (int q = 0; q < CH_IPT; ++q) {
-            const int64_t i = i0 + q;
             pos[q] = -1;  // -1: not applied
-            if (i >= na) continue;
-            const int32_t u = ddu[i], v = ddv[i];
-            int64_t p = find_sorted(col, off[u], off[u + 1], (uint32_t)v);
-            if (p >= 0) {
-                if (!((uint32_t)col[p] & DEAD)) {
-                    uint32_t old = atomicOr((unsigned int *)&col[p], MARK);
-                    if (!(old & MARK)) pos[q] = p;
+            if (i0 + q >= na) continue;
+            if (p[q] >= 0) {
+                if (!((uint32_t)col[p[q]] & DEAD)) {
+                    const uint32_t old = atomicOr((unsigned int *)&col[p[q]], MARK);
+                    if (!(old & MARK)) pos[q] = p[q];
                 }
-            } else {
-                int64_t r = find_sorted(dcol, doff[u], doff[u + 1], (uint32_t)v);
-                if (r >= 0 && !((uint32_t)dcol[r] & DEAD)) {
-                    uint32_t old = atomicOr((unsigned int *)&dcol[r], MARK);
-                    if (!(old & MARK)) pos[q] = -2 - r;
-                }
+            } else if (r[q] >= 0 && !((uint32_t)dcol[r[q]] & DEAD)) {
+                const uint32_t old = atomicOr((unsigned int *)&dcol[r[q]], MARK);
+                if (!(old & MARK)) pos[q] = -2 - r[q];
             }
             if (pos[q] != -1) {
                 ++nap;
-                ntc += undirected && u < v;
+                ntc += undirected && (uint32_t)u[q] < v[q];
             }
         }
         int64_t slot = block_reserve(&cnt[C_ADEL], nap, sc);
@@ -698,15 +710,13 @@ __global__ void k_mark_deletes(int64_t na, const int32_t *ddu, const int32_t *dd
 #pragma unroll
         for (int q = 0; q < CH_IPT; ++q) {
             if (pos[q] == -1) continue;
-            const int64_t i = i0 + q;
-            const int32_t u = ddu[i], v = ddv[i];
-            adu[slot] = u;
-            adv[slot] = v;
+            adu[slot] = u[q];
+            adv[slot] = (int32_t)v[q];
             adpos[slot] = pos[q];
             ++slot;
-            if (undirected && u < v) {
-                tcu[ts] = u;
-                tcv[ts] = v;
+            if (undirected && (uint32_t)u[q] < v[q]) {
+                tcu[ts] = u[q];
+                tcv[ts] = (int32_t)v[q];
                 ++ts;
             }
         }
@@ -717,7 +727,7 @@ __global__ void k_mark_deletes(int64_t na, const int32_t *ddu, const int32_t *dd
 // smallest weight of the run; it is IGNORED if the edge is live and not being
 // deleted, REVIVED in place if its slot is a tombstone or is being deleted in this
 // chunk (delete + insert ends present with the new weight), otherwise NEW.
-__global__ void k_classify_inserts(int64_t ni, const uint64_t *key, int32_t *iw, int B,
+__global__ __launch_bounds__(CH_T) void k_classify_inserts(int64_t ni, const uint64_t *key, int32_t *iw, int B,
                                    const int64_t *__restrict__ off, const int32_t *__restrict__ col,
                                    const int64_t *__restrict__ doff, const int32_t *__restrict__ dcol,
                                    int undirected, int64_t *isnew, int32_t *aiu, int32_t *aiv,
@@ -730,31 +740,43 @@ __global__ void k_classify_inserts(int64_t ni, const uint64_t *key, int32_t *iw,
         int64_t pos[CH_IPT];
         int8_t act[CH_IPT];  // 0 none, 1 new, 2 revive, 3 ignore
         int64_t napp = 0;
+        bool head[CH_IPT];
+        int32_t u[CH_IPT];
+        uint32_t v[CH_IPT];
+        int64_t p[CH_IPT], r[CH_IPT];
+        // run heads: the smallest weight of the run, then the row bounds
+#pragma unroll
+        for (int q = 0; q < CH_IPT; ++q) {
+            const int64_t i = i0 + q;
+            head[q] = false;
+            u[q] = 0;
+            v[q] = 0u;
+            if (i >= ni) continue;
+            const uint64_t kk = key[i];
+            head[q] = i == 0 || kk != key[i - 1];
+            if (!head[q]) continue;
+            int32_t wt = iw[i];
+            for (int64_t j = i + 1; j < ni && key[j] == kk; ++j) wt = min(wt, iw[j]);
+            iw[i] = wt;
+            u[q] = (int32_t)(kk >> B);
+            v[q] = (uint32_t)(kk & mask);
+        }
+        find_arcs(off, col, doff, dcol, u, v, head, p, r);
 #pragma unroll
         for (int q = 0; q < CH_IPT; ++q) {
             const int64_t i = i0 + q;
             act[q] = 0;
             pos[q] = -1;
             if (i >= ni) continue;
-            const uint64_t kk = key[i];
-            const bool head = i == 0 || kk != key[i - 1];
-            if (head) {
-                int32_t wt = iw[i];
-                for (int64_t j = i + 1; j < ni && key[j] == kk; ++j) wt = min(wt, iw[j]);
-                iw[i] = wt;
-                const int32_t u = (int32_t)(kk >> B), v = (int32_t)(kk & mask);
-                int64_t p = find_sorted(col, off[u], off[u + 1], (uint32_t)v);
-                if (p >= 0) {
-                    if ((uint32_t)col[p] & (DEAD | MARK)) { act[q] = 2; pos[q] = p; }
+            if (head[q]) {
+                if (p[q] >= 0) {
+                    if ((uint32_t)col[p[q]] & (DEAD | MARK)) { act[q] = 2; pos[q] = p[q]; }
+                    else act[q] = 3;
+                } else if (r[q] >= 0) {
+                    if ((uint32_t)dcol[r[q]] & (DEAD | MARK)) { act[q] = 2; pos[q] = -2 - r[q]; }
                     else act[q] = 3;
                 } else {
-                    int64_t r = find_sorted(dcol, doff[u], doff[u + 1], (uint32_t)v);
-                    if (r >= 0) {
-                        if ((uint32_t)dcol[r] & (DEAD | MARK)) { act[q] = 2; pos[q] = -2 - r; }
-                        else act[q] = 3;
-                    } else {
-                        act[q] = 1;
-                    }
+                    act[q] = 1;
                 }
                 ++ndist;
             }
@@ -875,68 +897,77 @@ __global__ void k_commit_deletes_rev(int64_t na, const int32_t *adu, const int32
 // updateCSRAdd for slots that already exist: revive a tombstone in place
 // (sorted hole reuse) with the new weight; NEW arcs only bump the degree here.
 // Inserted entries carry MARK until the post-hooks have run.
-__global__ void k_revive(int64_t na, const int32_t *aiu, const int32_t *aiv, const int32_t *aiw,
-                         const int64_t *aipos, int reverse, const int64_t *__restrict__ off, int32_t *col,
-                         int32_t *w, const int64_t *__restrict__ doff, int32_t *dcol, int32_t *dw,
-                         int32_t *deg, int32_t *ntomb, int32_t *ttomb, int B, uint64_t *rkey,
-                         int32_t *rw, int64_t *cnt) {
+__global__ __launch_bounds__(CH_T) void k_revive(int64_t na, const int32_t *aiu, const int32_t *aiv,
+                                                 const int32_t *aiw, const int64_t *aipos, int reverse,
+                                                 const int64_t *__restrict__ off, int32_t *col, int32_t *w,
+                                                 const int64_t *__restrict__ doff, int32_t *dcol, int32_t *dw,
+                                                 int32_t *deg, int32_t *ntomb, int32_t *ttomb, int B,
+                                                 uint64_t *rkey, int32_t *rw, int64_t *cnt) {
     __shared__ BlockScratch sc;
     int64_t nrev = 0;
     for (int64_t c0 = (int64_t)blockIdx.x * CH; c0 < na; c0 += (int64_t)gridDim.x * CH) {
-      const int64_t i0 = c0 + (int64_t)threadIdx.x * CH_IPT;
-      int64_t nnew = 0;
-      for (int qq = 0; qq < CH_IPT; ++qq) {
-        const int64_t i = i0 + qq;
-        bool revived_base = false, is_new = false;
-        int32_t r = 0, c = 0, wt = 0;
-        if (i < na) {
-            int32_t u = aiu[i], v = aiv[i];
-            wt = aiw[i];
-            r = reverse ? v : u;
-            c = reverse ? u : v;
-            int64_t p = aipos[i];
-            if (p == -1) {
-                is_new = true;
-            } else {
-                if (reverse) {  // locate the slot in the reverse store
-                    p = find_sorted(col, off[r], off[r + 1], (uint32_t)c);
-                    if (p < 0) {
-                        int64_t q = find_sorted(dcol, doff[r], doff[r + 1], (uint32_t)c);
-                        p = q >= 0 ? -2 - q : -1;
-                    }
-                }
-                if (p == -1) {
-                    // not present in the reverse store: cannot happen for a consistent graph
-                } else if (p >= 0) {
-                    col[p] = (int32_t)((uint32_t)c | MARK);
-                    w[p] = wt;
-                    atomicSub(&ntomb[r], 1);
-                    atomicSub(&ttomb[p / TILE], 1);
-                    revived_base = true;
-                } else {
-                    int64_t q = -2 - p;
-                    dcol[q] = (int32_t)((uint32_t)c | MARK);
-                    dw[q] = wt;
+        const int64_t i0 = c0 + (int64_t)threadIdx.x * CH_IPT;
+        int32_t r[CH_IPT];
+        uint32_t c[CH_IPT];
+        int64_t p[CH_IPT];
+        int64_t nnew = 0;
+#pragma unroll
+        for (int q = 0; q < CH_IPT; ++q) {
+            const bool ok = i0 + q < na;
+            const int32_t u = ok ? aiu[i0 + q] : 0, v = ok ? aiv[i0 + q] : 0;
+            r[q] = reverse ? v : u;
+            c[q] = (uint32_t)(reverse ? u : v);
+            p[q] = ok ? aipos[i0 + q] : -1;
+            nnew += ok && p[q] == -1;
+        }
+        if (reverse) {  // locate the revived slots in the reverse store
+            int64_t pb[CH_IPT], pd[CH_IPT];
+            bool look[CH_IPT];
+#pragma unroll
+            for (int q = 0; q < CH_IPT; ++q) look[q] = p[q] != -1;
+            find_arcs(off, col, doff, dcol, r, c, look, pb, pd);
+#pragma unroll
+            for (int q = 0; q < CH_IPT; ++q)
+                if (p[q] != -1) p[q] = pb[q] >= 0 ? pb[q] : (pd[q] >= 0 ? -2 - pd[q] : -3);
+        }
+        // degree bumps are summed over runs of one row within the thread's elements
+        int32_t run_r = -1, run_n = 0;
+#pragma unroll
+        for (int q = 0; q < CH_IPT; ++q) {
+            if (i0 + q >= na) continue;
+            const int32_t wt = aiw[i0 + q];
+            if (p[q] >= 0) {
+                col[p[q]] = (int32_t)(c[q] | MARK);
+                w[p[q]] = wt;
+                atomicSub(&ntomb[r[q]], 1);
+                atomicSub(&ttomb[p[q] / TILE], 1);
+                ++nrev;
+            } else if (p[q] <= -2) {
+                const int64_t d = -2 - p[q];
+                dcol[d] = (int32_t)(c[q] | MARK);
+                dw[d] = wt;
+            }
+            // p == -3 (slot absent from the reverse store) cannot happen for a consistent graph
+            if (r[q] != run_r) {
+                if (run_n) atomicAdd(&deg[run_r], run_n);
+                run_r = r[q];
+                run_n = 0;
+            }
+            ++run_n;
+        }
+        if (run_n) atomicAdd(&deg[run_r], run_n);
+        if (rkey) {
+            // NEW arcs of this thread's elements, in element order, for the reverse diff
+            int64_t s = block_reserve(&cnt[C_AUX1], nnew, sc);
+#pragma unroll
+            for (int q = 0; q < CH_IPT; ++q) {
+                if (i0 + q < na && p[q] == -1) {
+                    rkey[s] = ((uint64_t)(uint32_t)r[q] << B) | c[q];
+                    rw[s] = aiw[i0 + q];
+                    ++s;
                 }
             }
-            atomicAdd(&deg[r], 1);
         }
-        nrev += revived_base;
-        nnew += is_new;
-      }
-      if (rkey) {
-        // NEW arcs of this thread's elements, in element order, for the reverse diff
-        int64_t s = block_reserve(&cnt[C_AUX1], nnew, sc);
-        for (int qq = 0; qq < CH_IPT; ++qq) {
-            const int64_t i = i0 + qq;
-            if (i < na && aipos[i] == -1) {
-                const int32_t r = reverse ? aiv[i] : aiu[i], c = reverse ? aiu[i] : aiv[i];
-                rkey[s] = ((uint64_t)(uint32_t)r << B) | (uint32_t)c;
-                rw[s] = aiw[i];
-                ++s;
-            }
-        }
-      }
     }
     block_count(&cnt[C_AUX2], nrev, sc);
 }
@@ -1209,7 +1240,48 @@ int apply_chunk(dg_graph *g, int64_t k, const int32_t *src, const int32_t *dst, 
     }
 
     // ---- post-hooks on the new graph
+    // With PageRank and frontier-step SSSP queries both attached, the SSSP updates
+    // run on a second stream while the PageRank steps stream on this one: the
+    // SSSP rounds are latency-bound and leave the device mostly idle.
+    dg_query *prq = nullptr;
+    bool has_sssp = false;
     for (dg_query *q : g->queries) {
+        if (q->kind == Q_PR && !prq) prq = q;
+        has_sssp |= q->kind == Q_SSSP;
+    }
+    if (prq && has_sssp && g->cfg.sssp_persistent == 0) {
+        if (!g->aux) {
+            DG_HIP(hipStreamCreateWithFlags(&g->aux, hipStreamNonBlocking));
+            DG_HIP(hipEventCreateWithFlags(&g->ev_fork, hipEventDisableTiming));
+            DG_HIP(hipEventCreateWithFlags(&g->ev_join, hipEventDisableTiming));
+        }
+        DG_HIP(hipEventRecord(g->ev_fork, s));  // the updated graph
+        SideWork side;
+        side.fn = [&]() -> int {
+            // beside the steps: wait for the update only; after them: for everything so far
+            if (!side.beside) DG_HIP(hipEventRecord(g->ev_fork, s));
+            DG_HIP(hipStreamWaitEvent(g->aux, g->ev_fork, 0));
+            g->stream = g->aux;
+            int rc = DG_OK;
+            for (dg_query *q : g->queries) {
+                if (q->kind != Q_SSSP) continue;
+                PhaseTimer t(g, 2, &st->t_sssp_ms);
+                rc = sssp_post_update(q, adel, ains, st);
+                t.stop();
+                if (rc != DG_OK) break;
+            }
+            (void)hipEventRecord(g->ev_join, g->aux);
+            (void)hipStreamSynchronize(g->aux);
+            g->stream = s;
+            if (rc == DG_OK) DG_HIP(hipStreamWaitEvent(s, g->ev_join, 0));
+            return rc;
+        };
+        PhaseTimer t(g, 5, &st->t_pr_ms);
+        DG_TRY(pr_post_update(prq, adel, ains, st, &side));
+        t.stop();
+    }
+    for (dg_query *q : g->queries) {
+        if (prq && has_sssp && g->cfg.sssp_persistent == 0 && (q == prq || q->kind == Q_SSSP)) continue;
         if (q->kind == Q_SSSP) {
             PhaseTimer t(g, 2, &st->t_sssp_ms);
             DG_TRY(sssp_post_update(q, adel, ains, st));

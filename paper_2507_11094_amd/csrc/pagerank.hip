@@ -558,7 +558,8 @@ __global__ void k_sum_degrees(const int32_t *A, int64_t na, const int64_t *off, 
 //   apply: A[i] 4 + xn 8 + x read 8 + x write 8 + contrib write 8 + outdeg 4 per vertex
 static int pr_iterate(dg_graph *g, const int32_t *A, int64_t na, int64_t edges, double damping,
                       double tol, int32_t max_iter, bool global, double S, double *x, double *xn,
-                      double *contrib, int32_t *iters, int32_t *conv) {
+                      double *contrib, int32_t *iters, int32_t *conv, SideWork *side = nullptr,
+                      int32_t first_group = 0) {
     hipStream_t s = g->stream;
     Work &ws = g->ws;
     const int64_t qcap = 2 * (std::max(g->fwd.m + g->fwd.dm, g->rev->m + g->rev->dm) / heavy_deg(g) + 2) +
@@ -569,7 +570,7 @@ static int pr_iterate(dg_graph *g, const int32_t *A, int64_t na, int64_t edges, 
     const double ninv = 1.0 / (double)g->n;
     DirView rv = view(*g->rev);
     double *prs = ws.prs.p;
-    double *step_out = reinterpret_cast<double *>(ws.dcnt + C_RED0);
+    double *step_out = prs + 5;  // not in the shared counters: SSSP may run beside these steps
     // constant term of the first step
     if (global)
         hipLaunchKernelGGL(k_sum_vec2, dim3(APPLY_GROUPS), dim3(256), 0, s, x, g->fwd.deg.p, (int64_t)g->n,
@@ -607,7 +608,10 @@ static int pr_iterate(dg_graph *g, const int32_t *A, int64_t na, int64_t edges, 
     *conv = 0;
     std::vector<std::pair<int, int>> slots;  // profiled launches of the group (pull, apply)
     while (launched < max_iter && na > 0) {
-        const int grp = std::min(GROUP, max_iter - launched);
+        // the first group may be sized from the previous update's step count: one
+        // host round trip instead of several (launches past convergence return at once)
+        const int want = launched == 0 && first_group > GROUP ? std::min(first_group, 256) : GROUP;
+        const int grp = std::min(want, max_iter - launched);
         slots.clear();
         for (int j = 0; j < grp; ++j) {
             if (!tiles) DG_TRY(counters_clear(g));  // the heavy-row queue counters of the pull
@@ -647,9 +651,15 @@ static int pr_iterate(dg_graph *g, const int32_t *A, int64_t na, int64_t edges, 
         }
         launched += grp;
         double hp[5];
-        DG_HIP(hipMemcpyAsync(ws.hcnt + 32, prs, sizeof(hp), hipMemcpyDeviceToHost, s));
+        // the host slots after the counters: a counter read of a side stream leaves them alone
+        DG_HIP(hipMemcpyAsync(ws.hcnt + C_COUNT, prs, sizeof(hp), hipMemcpyDeviceToHost, s));
+        // tile steps touch no state the SSSP update uses: run it while they stream
+        if (side && tiles && !side->done) {
+            side->beside = true;
+            side->run();
+        }
         DG_HIP(hipStreamSynchronize(s));
-        std::memcpy(hp, ws.hcnt + 32, sizeof(hp));
+        std::memcpy(hp, ws.hcnt + C_COUNT, sizeof(hp));
         const int32_t total = (int32_t)hp[4];
         // launches after convergence did no work: keep them out of the timings
         for (int j = total - it; j < (int)slots.size(); ++j) {
@@ -697,7 +707,18 @@ int pr_init(dg_query *q) {
                            &q->last_iters, &q->converged);
 }
 
-int pr_post_update(dg_query *q, int64_t adel, int64_t ains, dg_batch_stats *st) {
+static int pr_update(dg_query *q, int64_t adel, int64_t ains, dg_batch_stats *st, SideWork *side);
+
+int pr_post_update(dg_query *q, int64_t adel, int64_t ains, dg_batch_stats *st, SideWork *side) {
+    const int rc = pr_update(q, adel, ains, st, side);
+    if (side) {
+        side->run();  // not yet run if the steps could not overlap it
+        if (rc == DG_OK) return side->rc;
+    }
+    return rc;
+}
+
+static int pr_update(dg_query *q, int64_t adel, int64_t ains, dg_batch_stats *st, SideWork *side) {
     dg_graph *g = q->g;
     hipStream_t s = g->stream;
     Work &ws = g->ws;
@@ -813,7 +834,7 @@ int pr_post_update(dg_query *q, int64_t adel, int64_t ains, dg_batch_stats *st) 
         hipLaunchKernelGGL(k_sum_vec2, dim3(APPLY_GROUPS), dim3(256), 0, s, q->x.p, g->fwd.deg.p,
                            (int64_t)g->n, partials);
         hipLaunchKernelGGL(k_pr_reduce, dim3(1), dim3(256), 0, s, partials, APPLY_GROUPS, 0, 0.0, q->damping,
-                           1.0, 0.0, 1, ws.prs.p, reinterpret_cast<double *>(ws.dcnt + C_RED0));
+                           1.0, 0.0, 1, ws.prs.p, ws.prs.p + 5);
         DG_HIP(hipGetLastError());
         double Ssum;
         DG_HIP(hipMemcpyAsync(&Ssum, ws.prs.p, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -822,7 +843,7 @@ int pr_post_update(dg_query *q, int64_t adel, int64_t ains, dg_batch_stats *st) 
         na = g->n;
         edges = all_edges;
         DG_TRY(pr_iterate(g, nullptr, na, edges, q->damping, tol_of(q) * Ssum, q->max_iter, true, Ssum,
-                          q->x.p, q->xn.p, q->contrib.p, &iters, &conv));
+                          q->x.p, q->xn.p, q->contrib.p, &iters, &conv, side, q->last_iters));
     } else {
         DG_TRY(pr_iterate(g, Alist, na, edges, q->damping, tol_of(q), q->max_iter, false, 0.0, q->x.p,
                           q->xn.p, q->contrib.p, &iters, &conv));

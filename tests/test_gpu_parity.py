@@ -395,6 +395,32 @@ def test_merge_tile_sizes(tile):
         assert np.array_equal(q.read()[0], oracle.sssp(n, cs, cd, cw, 1))
 
 
+@pytest.mark.parametrize("mode,pull,delta", [(2, 0, 0), (0, 0, 0), (1, 0, 0), (2, 1, 0), (2, 0, 40)])
+def test_sssp_and_pagerank_together(mode, pull, delta):
+    """Two SSSP queries and PageRank on one graph: the SSSP updates run on a second
+    stream beside the whole-graph tile steps (global form, pull 0), or after the
+    steps where they cannot overlap (local form, per-vertex waves)."""
+    n, s, d, w = hub_graph(seed=13)
+    say("sssp + pagerank together, pr_mode", mode, "pull", pull, "delta", delta)
+    c = cfg(merge=0.02, delta=delta)
+    c.pr_mode = mode
+    c.pr_pull = pull
+    G = dg.Graph(n, s, d, w, config=c)
+    qs = [G.sssp_attach(0), G.sssp_attach(5)]
+    qp = G.pr_attach(0.85, PR_TOL, 1000)
+    cs, cd, cw = s, d, w
+    for i, k in enumerate([3000, 40, 12000, 700]):
+        bs, bd, bw, bo = graphgen.update_batch(n, cs, cd, k, 7500 + i)
+        G.apply(bs, bd, bw, bo)
+        cs, cd, cw, _ = oracle.apply(n, cs, cd, cw, bs, bd, bw, bo)
+        for q, src in zip(qs, (0, 5)):
+            dist, par = q.read()
+            assert np.array_equal(dist, oracle.sssp(n, cs, cd, cw, src)), (i, src)
+        r, it, conv = qp.read()
+        assert conv
+        pr_check(r, n, cs, cd)
+
+
 def test_pagerank_dangling_and_isolated():
     say("pagerank dangling")
     # 0->1, 1 dangling, 2 isolated, 3->0, 3->1
