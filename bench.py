@@ -150,6 +150,9 @@ def roofline_of(prof: dict, workload: str, prefer: str | None = None) -> dict | 
     achieved = p["bytes"] / (p["ms"] * 1e-3) / 1e9 if p["ms"] > 0 else 0.0
     kname = KERNEL_SOURCE.get(name, (name, None))[0]
     copy = copy_peak_gbs()
+    traffic = traffic_for(kname, workload)
+    # HBM bytes the counters saw per launch, over the same launch time
+    moved = traffic / (1e-3 * p["ms"] / launches) / 1e9 if traffic and p["ms"] > 0 else None
     return {
         "kernel": kname,
         "bound": "hbm",
@@ -159,7 +162,9 @@ def roofline_of(prof: dict, workload: str, prefer: str | None = None) -> dict | 
         "frac": round(achieved / HBM_PEAK_GBS, 4),
         "copy_measured": copy,
         "frac_of_copy": round(achieved / copy, 4) if copy else None,
-        "traffic": traffic_for(kname, workload),
+        "traffic": traffic,
+        "traffic_GBs": round(moved, 1) if moved else None,
+        "traffic_frac": round(moved / HBM_PEAK_GBS, 4) if moved else None,
         "launches": p["launches"],
         "avg_launch_us": round(1e3 * p["ms"] / launches, 2),
         "alg_bytes_per_launch": round(p["bytes"] / launches),
@@ -719,8 +724,8 @@ def run_serve(args) -> int:
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=8)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="rmat", choices=["rmat", "grid", "tc", "batched", "serve"])
     ap.add_argument("--scale", type=int, default=22, help="rmat: R-MAT scale")
     ap.add_argument("--side", type=int, default=4096, help="grid: side length")
