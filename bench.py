@@ -52,17 +52,18 @@ CSRC = os.path.join(ROOT, "paper_2507_11094_amd", "csrc")
 # read per byte of a plain 256 MiB device copy (FETCH_SIZE 0.5, WRITE_SIZE 1.0
 # counted bytes per byte moved).  Each entry holds the SHA-1 of the kernel's own
 # source text (its template line, signature and body) at the time the counters
-# were taken; a changed kernel makes the figure stale and it is reported as null.
+# were taken, and the vertex order the graph had (single graphs); a changed kernel
+# or another order makes the figure stale and it is reported as null.
 MEASURED_TRAFFIC: dict = {
     ("k_pr_tiles", "rmat22-dynamic-sssp+pagerank"): {
-        "source": "pagerank.hip", "sha1": "7629ea5d8434680f962621e3514f53012baa1018",
-        "fetch_kib": 938314.0, "write_kib": 35898.3, "fetch_factor": 0.5, "write_factor": 1.0},
+        "source": "pagerank.hip", "sha1": "7629ea5d8434680f962621e3514f53012baa1018", "vertex_order": 0,
+        "fetch_kib": 585895.5, "write_kib": 33195.3, "fetch_factor": 0.5, "write_factor": 1.0},
     ("k_merge_tiles", "batched4096-rmat10to14-dynamic-sssp"): {
         "source": "graph.hip", "sha1": "ee55ed07154bb1a5b07db5162f6b434817d37359",
         "fetch_kib": 3040372.4, "write_kib": 3291721.6, "fetch_factor": 0.5, "write_factor": 1.0},
     ("k_tc_delta", "rmat20-undirected-dynamic-tc"): {
-        "source": "tc.hip", "sha1": "9fd8d87e3bfcaa15f061353446808f472d110b52",
-        "fetch_kib": 281933.3, "write_kib": 768.0, "fetch_factor": 0.5, "write_factor": 1.0},
+        "source": "tc.hip", "sha1": "9fd8d87e3bfcaa15f061353446808f472d110b52", "vertex_order": 0,
+        "fetch_kib": 277462.1, "write_kib": 768.0, "fetch_factor": 0.5, "write_factor": 1.0},
 }
 
 # Serving objective stated up front: 99th percentile latency (submit -> result
@@ -92,9 +93,9 @@ def kernel_sha1(fname: str, kernel: str) -> str:
     return ""
 
 
-def traffic_for(kernel: str, workload: str):
+def traffic_for(kernel: str, workload: str, order=None):
     e = MEASURED_TRAFFIC.get((kernel, workload))
-    if not e or kernel_sha1(e["source"], kernel) != e["sha1"]:
+    if not e or kernel_sha1(e["source"], kernel) != e["sha1"] or e.get("vertex_order") != order:
         return None
     return round(e["fetch_kib"] * 1024 / e["fetch_factor"] + e["write_kib"] * 1024 / e["write_factor"])
 
@@ -140,7 +141,7 @@ def step_spread(ms: list) -> dict:
             "p90_ms": round(float(np.percentile(v, 90)), 3)}
 
 
-def roofline_of(prof: dict, workload: str, prefer: str | None = None) -> dict | None:
+def roofline_of(prof: dict, workload: str, prefer: str | None = None, order=None) -> dict | None:
     """Roofline of the dominant profiled kernel (largest total time), or `prefer`."""
     if not prof:
         return None
@@ -150,7 +151,7 @@ def roofline_of(prof: dict, workload: str, prefer: str | None = None) -> dict | 
     achieved = p["bytes"] / (p["ms"] * 1e-3) / 1e9 if p["ms"] > 0 else 0.0
     kname = KERNEL_SOURCE.get(name, (name, None))[0]
     copy = copy_peak_gbs()
-    traffic = traffic_for(kname, workload)
+    traffic = traffic_for(kname, workload, order)
     # HBM bytes the counters saw per launch, over the same launch time
     moved = traffic / (1e-3 * p["ms"] / launches) / 1e9 if traffic and p["ms"] > 0 else None
     return {
@@ -271,6 +272,7 @@ def run_single(args, kind: str) -> int:
     cfg.pr_pull = args.pr_pull
     cfg.pr_tile = args.pr_tile
     cfg.merge_tile = args.merge_tile
+    cfg.vertex_order = args.vertex_order
     t = time.perf_counter()
     G = dg.Graph(n, s, d, w, undirected=undirected, config=cfg)
     log(f"graph built on device in {time.perf_counter() - t:.2f}s")
@@ -336,7 +338,7 @@ def run_single(args, kind: str) -> int:
     config = {"workload": wl, "vertices": n, "arcs": int(s.size) * (2 if undirected else 1),
               "batch": k, "insert_fraction": 0.5, "parallelism": "1 gpu",
               "heavy_degree": args.heavy_degree or 512, "sssp_persistent": persistent, "sssp_delta": delta,
-              "pr_mode": args.pr_mode,
+              "pr_mode": args.pr_mode, "vertex_order": ["by degree", "as given"][args.vertex_order],
               "pr_pull": ["merge-path tiles, non-temporal streams", "vertex waves", "merge-path tiles"][args.pr_pull]}
     if kind == "tc":
         config.update({"undirected_edges": int(s.size), "batch_fraction": args.pct, "queries": ["triangles"]})
@@ -359,7 +361,7 @@ def run_single(args, kind: str) -> int:
     if kind == "tc":
         extra["triangles"] = {"initial": int(tc0), "final": int(qt.read())}
     out = line(args, value, "updates/s", 1e3 * elapsed / K, "u64" if kind == "tc" else "i32+f64", config,
-               roofline_of(prof, wl), cpu, **extra)
+               roofline_of(prof, wl, order=args.vertex_order), cpu, **extra)
     print(json.dumps(out), flush=True)
     G.close()
     return 0
@@ -752,6 +754,8 @@ def main() -> int:
     ap.add_argument("--pr-tile", type=int, default=0, help="rows + entries per pull tile: 1024, 2048 (0) or 4096")
     ap.add_argument("--merge-tile", type=int, default=0,
                     help="rows + entries per merge-path tile of the CSR merge: 512 (0), 1024 or 2048")
+    ap.add_argument("--vertex-order", type=int, default=0,
+                    help="vertex order inside the library: 0 by degree (default), 1 as given")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run five plain 256 MiB device-to-device copies (reference for the "
                          "FETCH_SIZE / WRITE_SIZE counter scale) and exit")

@@ -107,7 +107,11 @@ typedef struct dg_config {
     /* Rows + entries per merge-path tile of the CSR merge: 512, 1024 or 2048
      * (0 or anything else: 512). */
     int32_t merge_tile;
-    int32_t reserved[1];
+    /* Vertex order inside the library (dg_graph_create only; sets keep the order
+     * given): 0 = by degree, highest first, so that the hot rows and the values
+     * gathered from them share cache lines; 1 = as given.  Every id the caller
+     * passes or reads back is the caller's own either way. */
+    int32_t vertex_order;
 } dg_config;
 
 /* Per-batch statistics and phase timings (HIP events on the graph's stream). */

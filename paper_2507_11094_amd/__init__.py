@@ -59,7 +59,7 @@ class Config(ctypes.Structure):
                 ("heavy_degree", ctypes.c_int32), ("persistent_groups", ctypes.c_int32),
                 ("sssp_persistent", ctypes.c_int32), ("pr_mode", ctypes.c_int32),
                 ("pr_pull", ctypes.c_int32), ("sssp_delta", ctypes.c_int32), ("merge_period", ctypes.c_int32),
-                ("pr_tile", ctypes.c_int32), ("merge_tile", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1)]
+                ("pr_tile", ctypes.c_int32), ("merge_tile", ctypes.c_int32), ("vertex_order", ctypes.c_int32)]
 
 
 class KernelProf(ctypes.Structure):

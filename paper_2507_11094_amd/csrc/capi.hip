@@ -160,6 +160,7 @@ int dg_graph_create(int32_t n, int64_t m, const int32_t *src, const int32_t *dst
     g->n = n;
     g->undirected = (flags & DG_UNDIRECTED) != 0;
     g->cfg = defaults(cfg);
+    g->relabeled = g->cfg.vertex_order == 0;
     g->rev = g->undirected ? &g->fwd : &g->rev_own;
     int rc = ws_init(g);
     const bool dev = (flags & DG_DEVICE_PTRS) != 0;
@@ -350,10 +351,12 @@ static int attach(dg_graph *g, dg_query *q, dg_query **out) {
 int dg_sssp_attach(dg_graph *g, int32_t source, dg_query **q) {
     DG_TRY(check_graph(g));
     if (!q || source < 0 || source >= g->n) return set_error(DG_EINVAL, "bad source");
+    int32_t iv = source;
+    DG_TRY(vertex_in(g, source, &iv));
     dg_query *x = new dg_query();
     x->g = g;
     x->kind = Q_SSSP;
-    x->source = source;
+    x->source = iv;
     return attach(g, x, q);
 }
 
@@ -418,7 +421,9 @@ int dg_sssp_static(dg_graph *g, int32_t source, int32_t *dist, int32_t *parent, 
     if (source < 0 || source >= g->n || !dist) return set_error(DG_EINVAL, "bad arguments");
     DBuf<uint64_t> &key = g->ws.skey;
     DG_TRY(key.ensure((size_t)g->n + 1));
-    int rc = sssp_static_solve(g, key.p, source, nullptr);
+    int32_t iv = source;
+    DG_TRY(vertex_in(g, source, &iv));
+    int rc = sssp_static_solve(g, key.p, iv, nullptr);
     if (rc == DG_OK) {
         dg_query tmp;
         tmp.g = g;

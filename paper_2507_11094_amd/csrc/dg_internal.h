@@ -176,6 +176,10 @@ struct dg_graph {
     int64_t m_live = 0;      // live arcs in fwd
     int32_t since_merge = 0; // batches applied since the last merge
     hipStream_t stream = nullptr;
+    // vertex order (cfg.vertex_order 0): internal id = perm[caller's id], caller's
+    // id = iperm[internal id]; empty when the ids are kept as given
+    dg::DBuf<int32_t> perm, iperm;
+    bool relabeled = false;
     hipStream_t aux = nullptr;                      // second stream: SSSP beside the PageRank steps
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     dg_config cfg{};
@@ -285,6 +289,8 @@ struct SideWork {
 };
 // side (nullable) runs exactly once: right after the first group of whole-graph
 // tile steps is enqueued, else after the update.
+// Internal id of a caller's vertex id (identity when the ids are kept as given).
+int vertex_in(dg_graph *g, int32_t v, int32_t *out);
 int pr_post_update(dg_query *q, int64_t n_applied_del, int64_t n_applied_ins, dg_batch_stats *st,
                    SideWork *side = nullptr);
 int pr_read(dg_query *q, double *rank, bool dev);

@@ -119,6 +119,7 @@ void ws_free(dg_graph *g) {
     w.farflag.release(); w.far0.release(); w.far1.release(); w.bpart.release();
     w.rbuf.release(); w.skey.release(); w.sx.release(); w.sc.release(); w.sxn.release();
     w.wq.release(); w.wseq.release(); w.wctr.release(); w.inq.release();
+    g->perm.release(); g->iperm.release();
     if (w.dcnt) dfree(w.dcnt);
     if (w.hcnt) (void)hipHostFree(w.hcnt);
     if (g->aux) (void)hipStreamDestroy(g->aux);
@@ -157,9 +158,13 @@ __global__ void k_validate_edges(int64_t m, const int32_t *s, const int32_t *d, 
 }
 
 __global__ void k_make_keys(int64_t m, const int32_t *s, const int32_t *d, const int32_t *w, int B,
-                            int reverse, int both, uint64_t *keys, int32_t *vals) {
+                            int reverse, int both, const int32_t *perm, uint64_t *keys, int32_t *vals) {
     for (int64_t i = gtid(); i < m; i += gstride()) {
         uint32_t u = (uint32_t)s[i], v = (uint32_t)d[i];
+        if (perm) {
+            u = (uint32_t)perm[u];
+            v = (uint32_t)perm[v];
+        }
         if (reverse) { uint32_t t = u; u = v; v = t; }
         int32_t wt = w ? w[i] : 1;
         keys[i] = ((uint64_t)u << B) | v;
@@ -225,6 +230,65 @@ static int dir_from_sorted(dg_graph *g, Dir &d, const uint64_t *keys, const int3
     return DG_OK;
 }
 
+// Vertex order by degree: key = (INT32_MAX - degree) above the id, so that an
+// ascending sort puts the highest degree first and breaks ties by id.
+__global__ void k_order_keys(int32_t n, const int64_t *off, int B, uint64_t *keys, int32_t *vals) {
+    for (int64_t v = gtid(); v < n; v += gstride()) {
+        const int64_t deg = off[v + 1] - off[v];
+        keys[v] = ((uint64_t)(INT32_MAX - (int32_t)min(deg, (int64_t)INT32_MAX)) << B) | (uint64_t)v;
+        vals[v] = (int32_t)v;
+    }
+}
+
+__global__ void k_perm_from_order(int32_t n, const int32_t *order, int32_t *perm, int32_t *iperm) {
+    for (int64_t i = gtid(); i < n; i += gstride()) {
+        const int32_t v = order[i];
+        iperm[i] = v;
+        perm[v] = (int32_t)i;
+    }
+}
+
+// perm / iperm of the degree order of a validated edge list: the out-degree (the
+// degree, undirected) of every given id, then a sort of (degree, id).
+static int vertex_order_build(dg_graph *g, int64_t m, const int32_t *src, const int32_t *dst, int B) {
+    hipStream_t s = g->stream;
+    Work &ws = g->ws;
+    const int32_t n = g->n;
+    const int64_t arcs = g->undirected ? 2 * m : m;
+    const size_t cap = (size_t)std::max<int64_t>(arcs, n) + 1;
+    DG_TRY(ws.ikey.ensure(cap));
+    DG_TRY(ws.ikey_s.ensure(cap));
+    DG_TRY(ws.iw.ensure(cap));
+    DG_TRY(ws.iw_s.ensure(cap));
+    DG_TRY(ws.scan64.ensure((size_t)n + 1));
+    DG_TRY(g->perm.ensure((size_t)n + 1));
+    DG_TRY(g->iperm.ensure((size_t)n + 1));
+    if (m > 0)
+        hipLaunchKernelGGL(k_make_keys, dim3(grid_for(m)), dim3(256), 0, s, m, src, dst, (const int32_t *)nullptr,
+                           B, 0, (int)g->undirected, (const int32_t *)nullptr, ws.ikey.p, ws.iw.p);
+    DG_HIP(hipGetLastError());
+    DG_TRY(sort_pairs(g, ws.ikey.p, ws.ikey_s.p, ws.iw.p, ws.iw_s.p, arcs, 2 * B));
+    hipLaunchKernelGGL(k_row_offsets, dim3(grid_for(n + 1)), dim3(256), 0, s, n, ws.ikey_s.p, arcs, B,
+                       ws.scan64.p);
+    hipLaunchKernelGGL(k_order_keys, dim3(grid_for(n)), dim3(256), 0, s, n, ws.scan64.p, B, ws.ikey.p, ws.iw.p);
+    DG_HIP(hipGetLastError());
+    DG_TRY(sort_pairs(g, ws.ikey.p, ws.ikey_s.p, ws.iw.p, ws.iw_s.p, n, B + 31));
+    hipLaunchKernelGGL(k_perm_from_order, dim3(grid_for(n)), dim3(256), 0, s, n, ws.iw_s.p, g->perm.p,
+                       g->iperm.p);
+    DG_HIP(hipGetLastError());
+    return DG_OK;
+}
+
+int vertex_in(dg_graph *g, int32_t v, int32_t *out) {
+    if (!g->relabeled) {
+        *out = v;
+        return DG_OK;
+    }
+    DG_HIP(hipMemcpyAsync(out, g->perm.p + v, sizeof(int32_t), hipMemcpyDeviceToHost, g->stream));
+    DG_HIP(hipStreamSynchronize(g->stream));
+    return DG_OK;
+}
+
 int graph_build(dg_graph *g, int64_t m, const int32_t *src, const int32_t *dst, const int32_t *w) {
     hipStream_t s = g->stream;
     Work &ws = g->ws;
@@ -238,6 +302,8 @@ int graph_build(dg_graph *g, int64_t m, const int32_t *src, const int32_t *dst, 
     if (ws.hcnt[C_ERR]) return set_error(DG_EINVAL, "edge list holds a self-loop, an id outside [0,n) or a weight outside [1,2^30)");
     const int64_t arcs = g->undirected ? 2 * m : m;
     if (arcs > INT32_MAX) return set_error(DG_EINVAL, "more than 2^31 arcs");
+    if (g->relabeled) DG_TRY(vertex_order_build(g, m, src, dst, B));
+    const int32_t *perm = g->relabeled ? g->perm.p : nullptr;
     DG_TRY(ws.ikey.ensure(arcs + 1));
     DG_TRY(ws.ikey_s.ensure(arcs + 1));
     DG_TRY(ws.iw.ensure(arcs + 1));
@@ -245,7 +311,7 @@ int graph_build(dg_graph *g, int64_t m, const int32_t *src, const int32_t *dst, 
     for (int dir = 0; dir < (g->undirected ? 1 : 2); ++dir) {
         if (m > 0)
             hipLaunchKernelGGL(k_make_keys, dim3(grid_for(m)), dim3(256), 0, s, m, src, dst, w, B, dir,
-                               (int)g->undirected, ws.ikey.p, ws.iw.p);
+                               (int)g->undirected, perm, ws.ikey.p, ws.iw.p);
         DG_HIP(hipGetLastError());
         DG_TRY(sort_pairs(g, ws.ikey.p, ws.ikey_s.p, ws.iw.p, ws.iw_s.p, arcs, 2 * B));
         if (dir == 0) {
@@ -571,26 +637,48 @@ int graph_export(dg_graph *g, int64_t *m, int32_t *src, int32_t *dst, int32_t *w
     if (rc == DG_OK && arcs > 0)
         hipLaunchKernelGGL(k_rows_of_entries, dim3(grid_for(arcs)), dim3(256), 0, s, g->n, arcs, off2.p,
                            row.p);
-    std::vector<int32_t> hr(arcs), hc(arcs), hw(arcs);
+    std::vector<int32_t> hr(arcs), hc(arcs), hw(arcs), hi;
     if (rc == DG_OK && arcs > 0) {
         (void)hipMemcpyAsync(hr.data(), row.p, arcs * 4, hipMemcpyDeviceToHost, s);
         (void)hipMemcpyAsync(hc.data(), col2.p, arcs * 4, hipMemcpyDeviceToHost, s);
         (void)hipMemcpyAsync(hw.data(), w2.p, arcs * 4, hipMemcpyDeviceToHost, s);
+        if (g->relabeled) {
+            hi.resize(g->n);
+            (void)hipMemcpyAsync(hi.data(), g->iperm.p, (size_t)g->n * 4, hipMemcpyDeviceToHost, s);
+        }
     }
     hipError_t e = hipStreamSynchronize(s);
     off2.release(); col2.release(); w2.release(); row.release();
     if (rc != DG_OK) return rc;
     if (e != hipSuccess) return set_error(DG_EDEVICE, "export copy failed: %s", hipGetErrorString(e));
-    int64_t o = 0;
-    for (int64_t i = 0; i < arcs; ++i) {
-        int32_t u = hr[i], v = (int32_t)((uint32_t)hc[i] & ID_MASK);
-        if (g->undirected && u > v) continue;
-        src[o] = u;
-        dst[o] = v;
-        if (w) w[o] = hw[i];
-        ++o;
+    if (!g->relabeled) {
+        int64_t o = 0;
+        for (int64_t i = 0; i < arcs; ++i) {
+            int32_t u = hr[i], v = (int32_t)((uint32_t)hc[i] & ID_MASK);
+            if (g->undirected && u > v) continue;
+            src[o] = u;
+            dst[o] = v;
+            if (w) w[o] = hw[i];
+            ++o;
+        }
+        *m = o;
+        return DG_OK;
     }
-    *m = o;
+    // caller's ids, sorted again by (src, dst)
+    std::vector<std::pair<uint64_t, int32_t>> ed;
+    ed.reserve((size_t)count);
+    for (int64_t i = 0; i < arcs; ++i) {
+        const uint32_t u = (uint32_t)hi[hr[i]], v = (uint32_t)hi[(uint32_t)hc[i] & ID_MASK];
+        if (g->undirected && u > v) continue;
+        ed.emplace_back(((uint64_t)u << 32) | v, hw[i]);
+    }
+    std::sort(ed.begin(), ed.end());
+    for (size_t o = 0; o < ed.size(); ++o) {
+        src[o] = (int32_t)(ed[o].first >> 32);
+        dst[o] = (int32_t)(ed[o].first & 0xffffffffu);
+        if (w) w[o] = ed[o].second;
+    }
+    *m = (int64_t)ed.size();
     return DG_OK;
 }
 
@@ -622,8 +710,8 @@ __global__ __launch_bounds__(CH_T) void k_validate_batch(int64_t k, const int32_
 // both arcs).
 __global__ __launch_bounds__(CH_T) void k_expand_batch(int64_t k, const int32_t *s, const int32_t *d,
                                                        const int32_t *w, const uint8_t *op, int B,
-                                                       int undirected, int32_t *ddu, int32_t *ddv,
-                                                       uint64_t *ikey, int32_t *iw, int64_t *cnt) {
+                                                       int undirected, const int32_t *perm, int32_t *ddu,
+                                                       int32_t *ddv, uint64_t *ikey, int32_t *iw, int64_t *cnt) {
     __shared__ BlockScratch sc;
     const int rep = undirected ? 2 : 1;
     for (int64_t c0 = (int64_t)blockIdx.x * CH; c0 < k; c0 += (int64_t)gridDim.x * CH) {
@@ -643,7 +731,7 @@ __global__ __launch_bounds__(CH_T) void k_expand_batch(int64_t k, const int32_t 
             const int64_t i = i0 + q;
             if (i >= k) break;
             const uint8_t o = op[i];
-            const uint32_t u0 = (uint32_t)s[i], v0 = (uint32_t)d[i];
+            const uint32_t u0 = (uint32_t)(perm ? perm[s[i]] : s[i]), v0 = (uint32_t)(perm ? perm[d[i]] : d[i]);
             const int32_t wt = w ? w[i] : 1;
             for (int r = 0; r < rep; ++r) {
                 const uint32_t u = r ? v0 : u0, v = r ? u0 : v0;
@@ -1130,8 +1218,9 @@ int apply_chunk(dg_graph *g, int64_t k, const int32_t *src, const int32_t *dst, 
     DG_TRY(ws.rw.ensure(nia + 1)); DG_TRY(ws.rw_s.ensure(nia + 1));
     DG_TRY(ws.tcu.ensure(nda + nia + 1)); DG_TRY(ws.tcv.ensure(nda + nia + 1));
     DG_TRY(ws.scan64.ensure(2 * ((size_t)nia + 1)));
-    hipLaunchKernelGGL(k_expand_batch, dim3(grid_ch(k)), dim3(256), 0, s, k, ds, dd, dw, dop, B,
-                       (int)und, ws.ddu.p, ws.ddv.p, ws.ikey.p, ws.iw.p, ws.dcnt);
+    const int32_t *perm = g->relabeled ? g->perm.p : nullptr;  // caller's ids to internal ids
+    hipLaunchKernelGGL(k_expand_batch, dim3(grid_ch(k)), dim3(256), 0, s, k, ds, dd, dw, dop, B, (int)und, perm,
+                       ws.ddu.p, ws.ddv.p, ws.ikey.p, ws.iw.p, ws.dcnt);
     DG_HIP(hipGetLastError());
     DG_TRY(sort_pairs(g, ws.ikey.p, ws.ikey_s.p, ws.iw.p, ws.iw_s.p, nia, 2 * B));
     // ---- updateCSRDel (mark) and insert classification against the old graph

@@ -296,9 +296,10 @@ __global__ __launch_bounds__(256) void k_sum_vec(const double *x, int64_t n, dou
     if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
 }
 
-__global__ void k_scale(const double *x, int64_t n, const double *sum, double *out) {
+// out[i] = x[perm[i]] / sum: ranks in the caller's ids (perm null: ids kept).
+__global__ void k_scale(const double *x, const int32_t *perm, int64_t n, const double *sum, double *out) {
     const double s = *sum;
-    for (int64_t i = gtid(); i < n; i += gstride()) out[i] = x[i] / s;
+    for (int64_t i = gtid(); i < n; i += gstride()) out[i] = x[perm ? perm[i] : i] / s;
 }
 
 // Reach closure and seeds.
@@ -864,18 +865,19 @@ int pr_normalize(dg_graph *g, const double *x, double *rank, bool dev) {
     DG_TRY(ensure_pr_ws(g));
     double *partials = g->ws.part.p;
     double *dsum = reinterpret_cast<double *>(g->ws.dcnt + C_RED0);
+    const int32_t *perm = g->relabeled ? g->perm.p : nullptr;
     hipLaunchKernelGGL(k_sum_vec, dim3(APPLY_GROUPS), dim3(256), 0, s, x, (int64_t)g->n, partials);
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, partials, APPLY_GROUPS, dsum);
     DG_HIP(hipGetLastError());
     if (dev) {
-        hipLaunchKernelGGL(k_scale, dim3(grid_for(g->n)), dim3(256), 0, s, x, (int64_t)g->n, dsum, rank);
+        hipLaunchKernelGGL(k_scale, dim3(grid_for(g->n)), dim3(256), 0, s, x, perm, (int64_t)g->n, dsum, rank);
         DG_HIP(hipGetLastError());
         DG_HIP(hipStreamSynchronize(s));
         return DG_OK;
     }
     DBuf<double> &tmp = g->ws.rbuf;
     DG_TRY(tmp.ensure((size_t)g->n + 1));
-    hipLaunchKernelGGL(k_scale, dim3(grid_for(g->n)), dim3(256), 0, s, x, (int64_t)g->n, dsum, tmp.p);
+    hipLaunchKernelGGL(k_scale, dim3(grid_for(g->n)), dim3(256), 0, s, x, perm, (int64_t)g->n, dsum, tmp.p);
     hipError_t e1 = hipGetLastError();
     hipError_t e2 = hipMemcpyAsync(rank, tmp.p, (size_t)g->n * sizeof(double), hipMemcpyDeviceToHost, s);
     hipError_t e3 = hipStreamSynchronize(s);

@@ -26,13 +26,15 @@ namespace dg {
 
 // Directed deletions (u, v) whose reverse arc (v, u) is still live: in the
 // symmetrised copy the edge {u, v} stays (T4 reading: {u,v} is an edge while
-// either arc is).  keep[i] = 0 for those, 1 otherwise.
-__global__ void k_sym_keep(int64_t k, const int32_t *s, const int32_t *d, const uint8_t *op, const int64_t *off,
-                           const int32_t *col, const int64_t *doff, const int32_t *dcol, uint8_t *keep) {
+// either arc is).  keep[i] = 0 for those, 1 otherwise.  perm maps the caller's
+// ids to the directed graph's internal ids (null: kept as given).
+__global__ void k_sym_keep(int64_t k, const int32_t *s, const int32_t *d, const uint8_t *op, const int32_t *perm,
+                           const int64_t *off, const int32_t *col, const int64_t *doff, const int32_t *dcol,
+                           uint8_t *keep) {
     for (int64_t i = gtid(); i < k; i += gstride()) {
         uint8_t kp = 1;
         if (op[i] == 0) {
-            const int32_t u = s[i], v = d[i];
+            const int32_t u = perm ? perm[s[i]] : s[i], v = perm ? perm[d[i]] : d[i];
             int64_t p = find_sorted(col, off[v], off[v + 1], (uint32_t)u);
             bool live = p >= 0 && !((uint32_t)col[p] & DEAD);
             if (p < 0) {
@@ -48,8 +50,9 @@ __global__ void k_sym_keep(int64_t k, const int32_t *s, const int32_t *d, const 
 int sym_keep_mask(dg_graph *g, int64_t k, const int32_t *ds, const int32_t *dd, const uint8_t *dop, uint8_t *keep) {
     if (k <= 0) return DG_OK;
     int64_t blocks = std::min<int64_t>((k + 255) / 256, 4096);
-    hipLaunchKernelGGL(k_sym_keep, dim3((unsigned)blocks), dim3(256), 0, g->stream, k, ds, dd, dop, g->fwd.off.p,
-                       g->fwd.col.p, g->fwd.doff.p, g->fwd.dcol.p, keep);
+    hipLaunchKernelGGL(k_sym_keep, dim3((unsigned)blocks), dim3(256), 0, g->stream, k, ds, dd, dop,
+                       g->relabeled ? (const int32_t *)g->perm.p : nullptr, g->fwd.off.p, g->fwd.col.p,
+                       g->fwd.doff.p, g->fwd.dcol.p, keep);
     DG_HIP(hipGetLastError());
     return DG_OK;
 }

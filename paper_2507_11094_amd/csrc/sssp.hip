@@ -165,12 +165,18 @@ __global__ void k_sssp_on_add(int64_t na, const int32_t *aiu, const int32_t *aiv
     }
 }
 
-__global__ void k_sssp_unpack(int32_t n, const uint64_t *key, int32_t *dist, int32_t *parent) {
+// Distances and parents in the caller's ids: vertex v reads internal slot perm[v]
+// and a parent id p comes back as iperm[p] (both null when the ids are kept).
+__global__ void k_sssp_unpack(int32_t n, const uint64_t *key, const int32_t *perm, const int32_t *iperm,
+                              int32_t *dist, int32_t *parent) {
     for (int64_t v = gtid(); v < n; v += gstride()) {
-        uint64_t k = key[v];
+        uint64_t k = key[perm ? perm[v] : v];
         int32_t d = sssp_dist(k);
         if (dist) dist[v] = d >= INF ? INF : d;
-        if (parent) parent[v] = d >= INF ? -1 : sssp_parent(k);
+        if (parent) {
+            const int32_t p = sssp_parent(k);
+            parent[v] = d >= INF ? -1 : (iperm && p >= 0 ? iperm[p] : p);
+        }
     }
 }
 
@@ -746,7 +752,10 @@ int sssp_post_update(dg_query *q, int64_t adel, int64_t ains, dg_batch_stats *st
 }
 
 int sssp_unpack(dg_graph *g, const uint64_t *key, int32_t *dist, int32_t *parent, hipStream_t s) {
-    hipLaunchKernelGGL(k_sssp_unpack, dim3(grid_for(g->n)), dim3(256), 0, s, g->n, key, dist, parent);
+    const bool r = g->relabeled;
+    hipLaunchKernelGGL(k_sssp_unpack, dim3(grid_for(g->n)), dim3(256), 0, s, g->n, key,
+                       r ? (const int32_t *)g->perm.p : nullptr, r ? (const int32_t *)g->iperm.p : nullptr, dist,
+                       parent);
     DG_HIP(hipGetLastError());
     return DG_OK;
 }

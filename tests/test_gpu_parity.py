@@ -421,6 +421,54 @@ def test_sssp_and_pagerank_together(mode, pull, delta):
         pr_check(r, n, cs, cd)
 
 
+@pytest.mark.parametrize("order,undirected", [(0, False), (1, False), (0, True)])
+def test_vertex_order(order, undirected):
+    """Vertex order inside the library (0: by degree, 1: as given): batches, SSSP
+    distances and parents, PageRank, triangles and the exported edge list all come
+    back in the caller's ids, equal to the oracle's.  The ids are shuffled first so
+    that the degree order is far from the given one."""
+    n, s, d, w = rmat_small(11, 12, 51)
+    rng = np.random.default_rng(3)
+    shuffle = rng.permutation(n).astype(np.int32)
+    s, d = shuffle[s], shuffle[d]
+    if undirected:
+        key = np.unique((np.minimum(s, d).astype(np.int64) << 32) | np.maximum(s, d))
+        s, d = (key >> 32).astype(np.int32), (key & 0xFFFFFFFF).astype(np.int32)
+        w = np.ones(s.size, np.int32)
+    else:
+        o = np.lexsort((d, s))
+        s, d, w = s[o], d[o], w[o]
+    src = int(shuffle[0])
+    say("vertex order", order, "undirected", undirected)
+    c = cfg(merge=0.02)
+    c.vertex_order = order
+    G = dg.Graph(n, s, d, w if not undirected else None, undirected=undirected, config=c)
+    if undirected:
+        qt = G.tc_attach()
+        assert qt.read() == oracle.triangles(n, s, d)
+    else:
+        qs = G.sssp_attach(src)
+        qp = G.pr_attach(0.85, PR_TOL, 1000)
+    cs, cd, cw = s, d, w
+    for i, k in enumerate([300, 2000, 50, 900]):
+        bs, bd, bw, bo = graphgen.update_batch(n, cs, cd, k, 8100 + i, undirected=undirected)
+        G.apply(bs, bd, bw, bo)
+        cs, cd, cw, _ = oracle.apply(n, cs, cd, cw, bs, bd, bw, bo, undirected=undirected)
+        assert_edges(G, cs, cd, cw, undirected=undirected)
+        if undirected:
+            assert qt.read() == oracle.triangles(n, cs, cd)
+            continue
+        dist, par = qs.read()
+        assert np.array_equal(dist, oracle.sssp(n, cs, cd, cw, src)), i
+        assert_tree(n, cs, cd, cw, src, dist, par)
+        r, _, conv = qp.read()
+        pr_check(r, n, cs, cd)
+        sd, sp_ = G.sssp_static(src)
+        assert np.array_equal(sd, dist)
+        rs, _ = G.pr_static(0.85, PR_TOL, 1000)
+        pr_check(rs, n, cs, cd)
+
+
 def test_pagerank_dangling_and_isolated():
     say("pagerank dangling")
     # 0->1, 1 dangling, 2 isolated, 3->0, 3->1
