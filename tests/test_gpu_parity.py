@@ -469,6 +469,40 @@ def test_vertex_order(order, undirected):
         pr_check(rs, n, cs, cd)
 
 
+@pytest.mark.parametrize("order", [0, 1])
+def test_empty_graph_and_empty_batch(order):
+    """An edgeless graph (every vertex dangling and isolated), an empty batch, a
+    batch that inserts every edge, and one that deletes them all again."""
+    n = 7
+    e = np.zeros(0, np.int32)
+    say("empty graph, vertex order", order)
+    c = cfg()
+    c.vertex_order = order
+    G = dg.Graph(n, e, e, e, config=c)
+    qs = G.sssp_attach(3)
+    qp = G.pr_attach(0.85, PR_TOL, 1000)
+    dist, par = qs.read()
+    assert dist.tolist() == [INF, INF, INF, 0, INF, INF, INF] and par.tolist() == [-1] * n
+    r, _, _ = qp.read()
+    assert np.allclose(r, 1.0 / n, atol=1e-15)
+    st = G.apply(e, e, e, np.zeros(0, np.uint8))
+    assert st.updates == 0
+    s = np.array([3, 3, 0, 4, 6, 2], np.int32)
+    d = np.array([0, 4, 1, 5, 3, 6], np.int32)
+    w = np.array([5, 1, 2, 2, 7, 1], np.int32)
+    G.apply(s, d, w, np.ones(6, np.uint8))
+    cs, cd, cw, _ = oracle.apply(n, e, e, e, s, d, w, np.ones(6, np.uint8))
+    assert_edges(G, cs, cd, cw)
+    assert np.array_equal(qs.read()[0], oracle.sssp(n, cs, cd, cw, 3))
+    pr_check(qp.read()[0], n, cs, cd)
+    G.apply(s, d, w, np.zeros(6, np.uint8))
+    assert G.info()["m"] == 0
+    dist, par = qs.read()
+    assert dist.tolist() == [INF, INF, INF, 0, INF, INF, INF] and par.tolist() == [-1] * n
+    assert np.allclose(qp.read()[0], 1.0 / n, atol=1e-15)
+    G.close()
+
+
 def test_pagerank_dangling_and_isolated():
     say("pagerank dangling")
     # 0->1, 1 dangling, 2 isolated, 3->0, 3->1
