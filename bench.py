@@ -58,6 +58,9 @@ MEASURED_TRAFFIC: dict = {
     ("k_pr_tiles", "rmat22-dynamic-sssp+pagerank"): {
         "source": "pagerank.hip", "sha1": "7629ea5d8434680f962621e3514f53012baa1018", "vertex_order": 0,
         "fetch_kib": 585895.5, "write_kib": 33195.3, "fetch_factor": 0.5, "write_factor": 1.0},
+    ("k_pr_tiles", "grid4096x4096-dynamic-sssp+pagerank"): {
+        "source": "pagerank.hip", "sha1": "7629ea5d8434680f962621e3514f53012baa1018", "vertex_order": 0,
+        "fetch_kib": 396397.8, "write_kib": 131599.9, "fetch_factor": 0.5, "write_factor": 1.0},
     ("k_merge_tiles", "batched4096-rmat10to14-dynamic-sssp"): {
         "source": "graph.hip", "sha1": "ee55ed07154bb1a5b07db5162f6b434817d37359",
         "fetch_kib": 3040372.4, "write_kib": 3291721.6, "fetch_factor": 0.5, "write_factor": 1.0},

@@ -609,9 +609,10 @@ static int pr_iterate(dg_graph *g, const int32_t *A, int64_t na, int64_t edges, 
     *conv = 0;
     std::vector<std::pair<int, int>> slots;  // profiled launches of the group (pull, apply)
     while (launched < max_iter && na > 0) {
-        // the first group may be sized from the previous update's step count: one
-        // host round trip instead of several (launches past convergence return at once)
-        const int want = launched == 0 && first_group > GROUP ? std::min(first_group, 256) : GROUP;
+        // the first group may be sized from the previous update's step count (at most
+        // 64): one host round trip instead of several; launches past convergence
+        // return at once
+        const int want = launched == 0 && first_group > GROUP ? std::min(first_group, 64) : GROUP;
         const int grp = std::min(want, max_iter - launched);
         slots.clear();
         for (int j = 0; j < grp; ++j) {
