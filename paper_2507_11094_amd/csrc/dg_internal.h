@@ -145,6 +145,10 @@ struct Work {
     // counters: device block + pinned host mirror
     int64_t *dcnt = nullptr;
     int64_t *hcnt = nullptr;
+    // a merge on the second stream keeps its own error counter and scan scratch
+    int64_t *dcnt_m = nullptr;
+    int64_t *hcnt_m = nullptr;
+    DBuf<uint8_t> tmp_m;
     hipEvent_t ev[16] = {};
 };
 

@@ -56,6 +56,15 @@ int fill_i64(int64_t *p, int64_t v, int64_t n, hipStream_t s) {
 
 // ---------------------------------------------------------------- library primitives
 
+static int scan_excl_on(hipStream_t s, DBuf<uint8_t> &tmp, const int64_t *in, int64_t *out, int64_t n) {
+    if (n <= 0) return DG_OK;
+    size_t bytes = 0;
+    DG_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, bytes, in, out, (int)n, s));
+    DG_TRY(tmp.ensure(bytes));
+    DG_HIP(hipcub::DeviceScan::ExclusiveSum(tmp.p, bytes, in, out, (int)n, s));
+    return DG_OK;
+}
+
 static int sort_pairs(dg_graph *g, const uint64_t *kin, uint64_t *kout, const int32_t *vin,
                       int32_t *vout, int64_t n, int bits) {
     if (n <= 0) return DG_OK;
@@ -70,12 +79,7 @@ static int sort_pairs(dg_graph *g, const uint64_t *kin, uint64_t *kout, const in
 }
 
 int scan_excl(dg_graph *g, const int64_t *in, int64_t *out, int64_t n) {
-    if (n <= 0) return DG_OK;
-    size_t bytes = 0;
-    DG_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, bytes, in, out, (int)n, g->stream));
-    DG_TRY(g->ws.tmp.ensure(bytes));
-    DG_HIP(hipcub::DeviceScan::ExclusiveSum(g->ws.tmp.p, bytes, in, out, (int)n, g->stream));
-    return DG_OK;
+    return scan_excl_on(g->stream, g->ws.tmp, in, out, n);
 }
 
 // ---------------------------------------------------------------- counters
@@ -94,6 +98,9 @@ int ws_init(dg_graph *g) {
     if (!g->ws.dcnt) return set_error(DG_ENOMEM, "counter allocation failed");
     // C_COUNT counter slots, then 8 slots of PageRank step state
     DG_HIP(hipHostMalloc((void **)&g->ws.hcnt, sizeof(int64_t) * (C_COUNT + 8), hipHostMallocDefault));
+    g->ws.dcnt_m = static_cast<int64_t *>(dmalloc(sizeof(int64_t) * C_COUNT));
+    if (!g->ws.dcnt_m) return set_error(DG_ENOMEM, "counter allocation failed");
+    DG_HIP(hipHostMalloc((void **)&g->ws.hcnt_m, sizeof(int64_t) * C_COUNT, hipHostMallocDefault));
     for (auto &e : g->ws.ev) DG_HIP(hipEventCreate(&e));
     return counters_clear(g);
 }
@@ -122,6 +129,11 @@ void ws_free(dg_graph *g) {
     g->perm.release(); g->iperm.release();
     if (w.dcnt) dfree(w.dcnt);
     if (w.hcnt) (void)hipHostFree(w.hcnt);
+    if (w.dcnt_m) dfree(w.dcnt_m);
+    if (w.hcnt_m) (void)hipHostFree(w.hcnt_m);
+    w.tmp_m.release();
+    w.dcnt_m = nullptr;
+    w.hcnt_m = nullptr;
     if (g->aux) (void)hipStreamDestroy(g->aux);
     if (g->ev_fork) (void)hipEventDestroy(g->ev_fork);
     if (g->ev_join) (void)hipEventDestroy(g->ev_join);
@@ -534,10 +546,15 @@ __global__ void k_merge_diff_empty(int64_t dm, const uint64_t *dkey, int B, cons
     }
 }
 
-// Merge direction d into (off2, col2, w2); returns the new entry count.
-static int merge_into(dg_graph *g, Dir &d, int64_t *off2, int32_t *col2, int32_t *w2, int64_t m2) {
-    hipStream_t s = g->stream;
+// Merge direction d into (off2, col2, w2).  side: on the graph's second stream,
+// with the merge's own error counter and scan scratch, and without waiting for it
+// (merge_side_check reads the counter once the stream is done).
+static int merge_into(dg_graph *g, Dir &d, int64_t *off2, int32_t *col2, int32_t *w2, int64_t m2,
+                      bool side = false) {
+    hipStream_t s = side ? g->aux : g->stream;
     Work &ws = g->ws;
+    int64_t *cnt = side ? ws.dcnt_m : ws.dcnt;
+    DBuf<uint8_t> &tmp = side ? ws.tmp_m : ws.tmp;
     const int32_t n = g->n;
     const int64_t nblk = ntiles_for(d.m);
     DG_TRY(ws.scan64.ensure(2 * ((size_t)n + 1) + 2 * (nblk + 2)));
@@ -547,13 +564,13 @@ static int merge_into(dg_graph *g, Dir &d, int64_t *off2, int32_t *col2, int32_t
     int64_t *TB = tsin + (nblk + 2);
     // off2 = exclusive scan of live degrees
     hipLaunchKernelGGL(k_deg_to_i64, dim3(grid_for(n + 1)), dim3(256), 0, s, n, d.deg.p, tmpa);
-    DG_TRY(scan_excl(g, tmpa, off2, n + 1));
+    DG_TRY(scan_excl_on(s, tmp, tmpa, off2, n + 1));
     // RB = tombstones before each row, TB = tombstones before each counter block
     hipLaunchKernelGGL(k_deg_to_i64, dim3(grid_for(n + 1)), dim3(256), 0, s, n, d.ntomb.p, tmpa);
-    DG_TRY(scan_excl(g, tmpa, RB, n + 1));
+    DG_TRY(scan_excl_on(s, tmp, tmpa, RB, n + 1));
     hipLaunchKernelGGL(k_deg_to_i64, dim3(grid_for(nblk + 2)), dim3(256), 0, s, (int32_t)(nblk + 1), d.ttomb.p,
                        tsin);
-    DG_TRY(scan_excl(g, tsin, TB, nblk + 2));
+    DG_TRY(scan_excl_on(s, tmp, tsin, TB, nblk + 2));
     // merge-path tiles
     const int items = g->cfg.merge_tile == 512 || g->cfg.merge_tile == 2048 ? g->cfg.merge_tile : MG_ITEMS;
     const int64_t nb = ((int64_t)n + d.m + items - 1) / items;
@@ -564,7 +581,7 @@ static int merge_into(dg_graph *g, Dir &d, int64_t *off2, int32_t *col2, int32_t
     hipLaunchKernelGGL(k_mg_partition, dim3(grid_for(nb + 1)), dim3(256), 0, s, d.off.p, d.doff.p, n, d.m, nb,
                        items, ws.mp_row.p, ws.mp_edge.p, mp_dlo, mp_dhi);
     DG_HIP(hipGetLastError());
-    DG_TRY(counters_clear(g));
+    DG_TRY(fill_i64(cnt, 0, C_COUNT, s));
     // merge bytes: col+w read 8 per old entry, write 8 per new entry, and per row
     // off, doff, off2 and the tombstone prefix (8 each)
     int pm = prof_begin("merge_base", s);
@@ -572,24 +589,29 @@ static int merge_into(dg_graph *g, Dir &d, int64_t *off2, int32_t *col2, int32_t
     if (nb > 0)
         hipLaunchKernelGGL(tiles_kernel, dim3((unsigned)nb), dim3(MG_THREADS), 0, s, n, ws.mp_row.p,
                            ws.mp_edge.p, mp_dlo, mp_dhi, d.off.p, d.col.p, d.w.p, d.doff.p, d.dcol.p, d.dw.p, off2, RB, TB, col2, w2,
-                           m2, ws.dcnt);
+                           m2, cnt);
     prof_end(pm, s, 8.0 * (double)d.m + 8.0 * (double)m2 + 32.0 * (double)n + 8.0 * (double)d.dm);
     if (d.dm > 0)
         hipLaunchKernelGGL(k_merge_diff_empty, dim3(grid_for(d.dm)), dim3(256), 0, s, d.dm, d.dkey.p,
-                           d.keybits, d.off.p, d.doff.p, d.dcol.p, d.dw.p, off2, col2, w2, m2, ws.dcnt);
+                           d.keybits, d.off.p, d.doff.p, d.dcol.p, d.dw.p, off2, col2, w2, m2, cnt);
     DG_HIP(hipGetLastError());
+    if (side) return DG_OK;
     DG_TRY(counters_read(g));
     if (ws.hcnt[C_ERR]) return set_error(DG_EDEVICE, "merge: inconsistent degree counts (internal error)");
     return DG_OK;
 }
 
-static int merge_dir(dg_graph *g, Dir &d, int64_t live) {
+// The merge's error counter after a merge on the second stream (waits for it).
+static int merge_side_check(dg_graph *g) {
+    DG_HIP(hipMemcpyAsync(g->ws.hcnt_m, g->ws.dcnt_m, sizeof(int64_t) * C_COUNT, hipMemcpyDeviceToHost, g->aux));
+    DG_HIP(hipStreamSynchronize(g->aux));
+    if (g->ws.hcnt_m[C_ERR]) return set_error(DG_EDEVICE, "merge: inconsistent degree counts (internal error)");
+    return DG_OK;
+}
+
+// Merged arrays become the base; the diff level and the tombstone counters empty.
+static int merge_dir_commit(dg_graph *g, Dir &d, int64_t live) {
     hipStream_t s = g->stream;
-    if (d.dm == 0 && d.tomb_base == 0) return DG_OK;
-    DG_TRY(d.off2.ensure(g->n + 1));
-    DG_TRY(d.col2.ensure(live + 1));
-    DG_TRY(d.w2.ensure(live + 1));
-    DG_TRY(merge_into(g, d, d.off2.p, d.col2.p, d.w2.p, live));
     d.off.swap(d.off2);
     d.col.swap(d.col2);
     d.w.swap(d.w2);
@@ -602,6 +624,22 @@ static int merge_dir(dg_graph *g, Dir &d, int64_t live) {
     DG_TRY(d.ttomb.ensure(ntiles_for(live) + 2));
     DG_TRY(fill_i32(d.ttomb.p, 0, ntiles_for(live) + 2, s));
     return DG_OK;
+}
+
+static bool merge_needed(const Dir &d) { return d.dm != 0 || d.tomb_base != 0; }
+
+// Merged arrays of direction d into its spare buffers (side: on the second stream).
+static int merge_dir_start(dg_graph *g, Dir &d, int64_t live, bool side) {
+    DG_TRY(d.off2.ensure(g->n + 1));
+    DG_TRY(d.col2.ensure(live + 1));
+    DG_TRY(d.w2.ensure(live + 1));
+    return merge_into(g, d, d.off2.p, d.col2.p, d.w2.p, live, side);
+}
+
+static int merge_dir(dg_graph *g, Dir &d, int64_t live) {
+    if (!merge_needed(d)) return DG_OK;
+    DG_TRY(merge_dir_start(g, d, live, false));
+    return merge_dir_commit(g, d, live);
 }
 
 int graph_merge(dg_graph *g) {
@@ -1307,6 +1345,9 @@ int apply_chunk(dg_graph *g, int64_t k, const int32_t *src, const int32_t *dst, 
     t_upd.stop();
 
     // ---- merge policy (Section 3.5)
+    // With only SSSP queries attached, a merge runs beside their updates.
+    bool side_merge = !g->queries.empty(), merge_pending = false, merge_f = false, merge_r = false;
+    for (dg_query *q : g->queries) side_merge &= q->kind == Q_SSSP;
     {
         double thr = g->cfg.merge_threshold;
         double live = (double)(g->m_live > 0 ? g->m_live : 1);
@@ -1320,11 +1361,30 @@ int apply_chunk(dg_graph *g, int64_t k, const int32_t *src, const int32_t *dst, 
             need = true;
         if (need) {
             g->since_merge = 0;
-            PhaseTimer t(g, 3, &st->t_merge_ms);
-            DG_TRY(merge_dir(g, F, g->m_live));
-            if (!und) DG_TRY(merge_dir(g, g->rev_own, g->m_live));
+            if (side_merge) {
+                // the merge writes the spare arrays on the second stream while the
+                // SSSP updates read the unmerged ones; the swap waits for both
+                if (!g->aux) {
+                    DG_HIP(hipStreamCreateWithFlags(&g->aux, hipStreamNonBlocking));
+                    DG_HIP(hipEventCreateWithFlags(&g->ev_fork, hipEventDisableTiming));
+                    DG_HIP(hipEventCreateWithFlags(&g->ev_join, hipEventDisableTiming));
+                }
+                merge_f = merge_needed(F);
+                merge_r = !und && merge_needed(g->rev_own);
+                DG_HIP(hipEventRecord(g->ev_fork, s));
+                DG_HIP(hipStreamWaitEvent(g->aux, g->ev_fork, 0));
+                DG_HIP(hipEventRecord(ws.ev[6], g->aux));
+                if (merge_f) DG_TRY(merge_dir_start(g, F, g->m_live, true));
+                if (merge_r) DG_TRY(merge_dir_start(g, g->rev_own, g->m_live, true));
+                DG_HIP(hipEventRecord(ws.ev[7], g->aux));
+                merge_pending = true;
+            } else {
+                PhaseTimer t(g, 3, &st->t_merge_ms);
+                DG_TRY(merge_dir(g, F, g->m_live));
+                if (!und) DG_TRY(merge_dir(g, g->rev_own, g->m_live));
+                t.stop();
+            }
             st->merged += 1;
-            t.stop();
         }
     }
 
@@ -1387,6 +1447,14 @@ int apply_chunk(dg_graph *g, int64_t k, const int32_t *src, const int32_t *dst, 
             st->tc_added += (int64_t)(sum6 / 6);
             t.stop();
         }
+    }
+    // ---- a merge beside the SSSP updates: check it, then swap in the merged arrays
+    if (merge_pending) {
+        DG_TRY(merge_side_check(g));
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, ws.ev[6], ws.ev[7]) == hipSuccess) st->t_merge_ms += ms;
+        if (merge_f) DG_TRY(merge_dir_commit(g, F, g->m_live));
+        if (merge_r) DG_TRY(merge_dir_commit(g, g->rev_own, g->m_live));
     }
     // ---- drop the MARKs of inserted entries
     if (ains > 0) {
