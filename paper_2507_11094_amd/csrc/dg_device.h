@@ -169,11 +169,6 @@ __device__ __forceinline__ int64_t wave_append(int64_t *counter, bool pred) {
     return base + __popcll(b & lanemask_lt());
 }
 
-__device__ __forceinline__ void wave_count(int64_t *counter, bool pred) {
-    uint64_t b = ballot(pred);
-    if (b && lane_id() == __ffsll((long long)b) - 1)
-        atomicAdd((unsigned long long *)counter, (unsigned long long)__popcll(b));
-}
 
 // ---- block-aggregated counters ------------------------------------------------------
 // Atomics on one address serialise (tens of ns each), so kernels over millions of
