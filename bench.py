@@ -264,6 +264,8 @@ def run_single(args, kind: str) -> int:
     log(f"{W + K} batches of {k} drawn in {time.perf_counter() - t:.1f}s")
     dbatches = [tuple(torch.from_numpy(np.ascontiguousarray(x)).to(dev) for x in b) for b in batches]
     torch.cuda.synchronize()
+    # --host-batches: the library copies each batch from host memory inside the timed steps
+    ubatches = [tuple(np.ascontiguousarray(x) for x in b) for b in batches] if args.host_batches else dbatches
 
     persistent = max(args.sssp_persistent, 0)
     delta = args.sssp_delta if args.sssp_delta >= 0 else (8000 if kind == "grid" else 0)
@@ -289,7 +291,7 @@ def run_single(args, kind: str) -> int:
     log(f"queries attached (static solves) in {time.perf_counter() - t:.2f}s")
 
     for i in range(W):
-        G.apply(*dbatches[i])
+        G.apply(*ubatches[i])
         log(f"warmup {i + 1}/{W}")
     dg.dg_profile_enable(True)
     dg.dg_profile_reset()
@@ -297,7 +299,7 @@ def run_single(args, kind: str) -> int:
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(K):
-        st = G.apply(*dbatches[W + i])
+        st = G.apply(*ubatches[W + i])
         stats.append(st.as_dict())
         log(f"step {i + 1}/{K}: {st.t_total_ms:.2f} ms (sssp {st.t_sssp_ms:.2f}, pr {st.t_pr_ms:.2f}, "
             f"tc {st.t_tc_ms:.2f}, update {st.t_update_ms + st.t_validate_ms:.2f}, merge {st.t_merge_ms:.2f}, "
@@ -342,6 +344,7 @@ def run_single(args, kind: str) -> int:
               "batch": k, "insert_fraction": 0.5, "parallelism": "1 gpu",
               "heavy_degree": args.heavy_degree or 512, "sssp_persistent": persistent, "sssp_delta": delta,
               "pr_mode": args.pr_mode, "vertex_order": ["by degree", "as given"][args.vertex_order],
+              "batches_in": "host memory (copied inside the timed steps)" if args.host_batches else "HBM",
               "pr_pull": ["merge-path tiles, non-temporal streams", "vertex waves", "merge-path tiles"][args.pr_pull]}
     if kind == "tc":
         config.update({"undirected_edges": int(s.size), "batch_fraction": args.pct, "queries": ["triangles"]})
@@ -744,6 +747,9 @@ def main() -> int:
     ap.add_argument("--budget-gib", type=int, default=64, help="serve: device-memory admission budget")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-static", action="store_true")
+    ap.add_argument("--host-batches", action="store_true",
+                    help="hand the library host arrays (copied over PCIe inside the timed steps) instead of "
+                         "batches already in HBM")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--heavy-degree", type=int, default=0, help="rows longer than this are split (0: library default)")
     ap.add_argument("--sssp-persistent", type=int, default=0,
