@@ -421,6 +421,39 @@ def test_sssp_and_pagerank_together(mode, pull, delta):
         pr_check(r, n, cs, cd)
 
 
+def test_undirected_all_queries_together():
+    """SSSP, PageRank and triangles on one undirected graph: the SSSP update runs
+    beside the PageRank steps, the triangle deltas before and after, merges
+    included."""
+    n, s, d = graphgen.rmat_undirected(11, 8 << 11, graphgen.config_seed(2, 77))[:3]
+    w = graphgen.uniform_int(graphgen.config_seed(2, 78), 0, s.size, 1, 100).astype(np.int32)
+    say("undirected sssp + pagerank + triangles")
+    # Reading P7: on this graph (259 vertices of degree one) Jacobi stopped at an L1
+    # step of 1e-9 can sit up to 1.4e-9 (max-abs) from the converged ranks, the oracle
+    # run at 1e-9 included, so the ranks are pinned to the tight oracle (1e-14) and
+    # the library's steps run to a hundredth of the tolerance.
+    G = dg.Graph(n, s, d, w, undirected=True, config=cfg(merge=0.02, tol_scale=0.01))
+    qs = G.sssp_attach(0)
+    qp = G.pr_attach(0.85, PR_TOL, 1000)
+    qt = G.tc_attach()
+    us, ud, uw = s, d, w
+    merged = 0
+    for i, k in enumerate([200, 1500, 30, 800]):
+        bs, bd, bw, bo = graphgen.update_batch(n, us, ud, k, 8300 + i, undirected=True)
+        merged += G.apply(bs, bd, bw, bo).merged
+        us, ud, uw, _ = oracle.apply(n, us, ud, uw, bs, bd, bw, bo, undirected=True)
+        both_s = np.concatenate([us, ud]); both_d = np.concatenate([ud, us]); both_w = np.concatenate([uw, uw])
+        o = np.lexsort((both_d, both_s))
+        cs, cd, cw = both_s[o], both_d[o], both_w[o]
+        assert np.array_equal(qs.read()[0], oracle.sssp(n, cs, cd, cw, 0)), i
+        r, _, conv = qp.read()
+        tight, _, _ = oracle.pagerank(n, cs, cd, 0.85, 1e-14, 5000)
+        assert conv and abs(r.sum() - 1.0) < 1e-12
+        assert float(np.max(np.abs(r - tight))) <= PR_MAXABS, i
+        assert qt.read() == oracle.triangles(n, us, ud), i
+    assert merged >= 1
+
+
 @pytest.mark.parametrize("order,undirected", [(0, False), (1, False), (0, True)])
 def test_vertex_order(order, undirected):
     """Vertex order inside the library (0: by degree, 1: as given): batches, SSSP
