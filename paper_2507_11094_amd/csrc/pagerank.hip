@@ -200,21 +200,42 @@ __device__ __forceinline__ void block_sum2(double a, double b, double *out_a, do
     }
 }
 
-// x := xn, contrib := x / outdeg on A; fixed-order partials of the L1 step and of
-// the new mass on dangling vertices.
-__global__ __launch_bounds__(256) void k_pr_apply(const int32_t *A, int64_t na, const double *xn, double *x,
-                                                  double *contrib, const int32_t *deg, double *partials,
-                                                  const double *done) {
+// contrib := xn / outdeg on A, and x := xn unless x_w is null (the whole-graph
+// steps alternate two buffers instead of copying); fixed-order partials of the L1
+// step |xn - x_o| and of the new mass on dangling vertices.
+__global__ __launch_bounds__(256) void k_pr_apply(const int32_t *A, int64_t na, const double *xn,
+                                                  const double *x_o, double *x_w, double *contrib,
+                                                  const int32_t *deg, double *partials, const double *done) {
     if (*done != 0.0) return;
     double acc = 0.0, dang = 0.0;
-    for (int64_t i = gtid(); i < na; i += gstride()) {
-        int32_t v = A ? A[i] : (int32_t)i;
-        double nv = xn[v];
-        acc += fabs(nv - x[v]);
-        x[v] = nv;
-        int32_t dg = deg[v];
-        contrib[v] = dg > 0 ? nv / (double)dg : 0.0;
-        if (dg == 0) dang += nv;
+    // four strided elements per pass, every load issued before the stores (x_w may be
+    // x_o, so the compiler could not reorder them itself); the sums keep the order
+    // of a plain strided loop
+    constexpr int U = 4;
+    const int64_t st = gstride();
+    for (int64_t i0 = gtid(); i0 < na; i0 += U * st) {
+        int32_t v[U], dg[U];
+        double nv[U], ov[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t i = i0 + u * st;
+            v[u] = i < na ? (A ? A[i] : (int32_t)i) : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (v[u] < 0) continue;
+            nv[u] = xn[v[u]];
+            ov[u] = x_o[v[u]];
+            dg[u] = deg[v[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (v[u] < 0) continue;
+            acc += fabs(nv[u] - ov[u]);
+            if (x_w) x_w[v[u]] = nv[u];
+            contrib[v[u]] = dg[u] > 0 ? nv[u] / (double)dg[u] : 0.0;
+            if (dg[u] == 0) dang += nv[u];
+        }
     }
     block_sum2(acc, dang, &partials[2 * blockIdx.x], &partials[2 * blockIdx.x + 1]);
 }
@@ -556,7 +577,9 @@ __global__ void k_sum_degrees(const int32_t *A, int64_t na, const int64_t *off, 
 // otherwise the local form.  `edges` = entries scanned per pull (for the
 // algorithmic byte count):
 //   pull:  A[i] 4 + off 8 + doff 8 + xn write 8 per vertex, col 4 + contrib 8 per entry
-//   apply: A[i] 4 + xn 8 + x read 8 + x write 8 + contrib write 8 + outdeg 4 per vertex
+//   apply: A[i] 4 + xn 8 + x read 8 + x write 8 + contrib write 8 + outdeg 4 per vertex;
+//          whole-graph tiles: xn 8 + x read 8 + contrib write 8 + outdeg 4 (no A, and
+//          the two vectors trade places instead of a copy)
 static int pr_iterate(dg_graph *g, const int32_t *A, int64_t na, int64_t edges, double damping,
                       double tol, int32_t max_iter, bool global, double S, double *x, double *xn,
                       double *contrib, int32_t *iters, int32_t *conv, SideWork *side = nullptr,
@@ -571,6 +594,7 @@ static int pr_iterate(dg_graph *g, const int32_t *A, int64_t na, int64_t edges, 
     const double ninv = 1.0 / (double)g->n;
     DirView rv = view(*g->rev);
     double *prs = ws.prs.p;
+    double *const x_home = x, *const xn_home = xn;
     double *step_out = prs + 5;  // not in the shared counters: SSSP may run beside these steps
     // constant term of the first step
     if (global)
@@ -643,9 +667,17 @@ static int pr_iterate(dg_graph *g, const int32_t *A, int64_t na, int64_t edges, 
                                    prs + 2, damping, xn);
             }
             int pa = prof_begin("pr_apply", s);
-            hipLaunchKernelGGL(k_pr_apply, dim3(APPLY_GROUPS), dim3(256), 0, s, A, na, xn, x, contrib,
-                               g->fwd.deg.p, partials, done);
-            prof_end(pa, s, 40.0 * (double)na);
+            if (tiles) {
+                // the step just written becomes the current vector: no copy
+                hipLaunchKernelGGL(k_pr_apply, dim3(APPLY_GROUPS), dim3(256), 0, s, A, na, xn, x,
+                                   (double *)nullptr, contrib, g->fwd.deg.p, partials, done);
+                prof_end(pa, s, 28.0 * (double)na);
+                std::swap(x, xn);
+            } else {
+                hipLaunchKernelGGL(k_pr_apply, dim3(APPLY_GROUPS), dim3(256), 0, s, A, na, xn, x, x, contrib,
+                                   g->fwd.deg.p, partials, done);
+                prof_end(pa, s, 40.0 * (double)na);
+            }
             hipLaunchKernelGGL(k_pr_reduce, dim3(1), dim3(256), 0, s, partials, APPLY_GROUPS, (int)global, S,
                                damping, ninv, tol, 0, prs, step_out);
             DG_HIP(hipGetLastError());
@@ -676,6 +708,10 @@ static int pr_iterate(dg_graph *g, const int32_t *A, int64_t na, int64_t edges, 
     }
     if (na == 0) *conv = 1;
     *iters = it;
+    // whole-graph steps alternate the buffers: step k wrote xn if k is odd
+    x = x_home;
+    xn = xn_home;
+    if (tiles && (it & 1)) DG_HIP(hipMemcpyAsync(x, xn, (size_t)g->n * sizeof(double), hipMemcpyDeviceToDevice, s));
     if (global && na > 0) {
         hipLaunchKernelGGL(k_pr_rescale, dim3(grid_for(g->n)), dim3(256), 0, s, g->n, x, contrib, g->fwd.deg.p,
                            prs, S, damping);
