@@ -130,7 +130,8 @@ typedef struct dg_batch_stats {
     int32_t sssp_steps;         /* frontier steps                                       */
     int32_t pr_iterations;      /* Jacobi iterations                                    */
     int64_t pr_affected;        /* vertices in the affected set                         */
-    int64_t edges_traversed;    /* adjacency entries examined by all maintained queries */
+    int64_t edges_traversed;    /* adjacency entries examined: PageRank pulls (entries x steps) and the
+                                   worklist SSSP rounds; the frontier SSSP and triangle kernels add 0 */
     int64_t tc_removed;         /* triangles removed by the deletions                   */
     int64_t tc_added;           /* triangles added by the insertions                    */
     float t_validate_ms, t_update_ms, t_merge_ms, t_sssp_ms, t_pr_ms, t_tc_ms, t_total_ms;
