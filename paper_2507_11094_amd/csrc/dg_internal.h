@@ -117,6 +117,7 @@ struct Work {
     DBuf<uint64_t> nkey;                  // NEW forward keys (sorted)
     DBuf<int32_t> nw;
     DBuf<int32_t> tcu, tcv;               // undirected edges for TC (deleted / inserted)
+    DBuf<int64_t> tcitems;                // TC delta: work items per changed edge, then their scan
     DBuf<uint8_t> tmp;                    // hipcub temp storage
     DBuf<int64_t> scan64;                 // merge scans
     DBuf<int64_t> tscan;

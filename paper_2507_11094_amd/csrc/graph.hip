@@ -122,7 +122,7 @@ void ws_free(dg_graph *g) {
     w.nkey.release(); w.nw.release(); w.tcu.release(); w.tcv.release(); w.tmp.release();
     w.scan64.release(); w.tscan.release(); w.f0.release(); w.f1.release(); w.heavy.release();
     w.stamp.release(); w.part.release(); w.prs.release();
-    w.mp_row.release(); w.mp_edge.release(); w.mp_part.release(); w.mp_doff.release();
+    w.mp_row.release(); w.mp_edge.release(); w.mp_part.release(); w.mp_doff.release(); w.tcitems.release();
     w.farflag.release(); w.far0.release(); w.far1.release(); w.bpart.release();
     w.rbuf.release(); w.skey.release(); w.sx.release(); w.sc.release(); w.sxn.release();
     w.wq.release(); w.wseq.release(); w.wctr.release(); w.inq.release();

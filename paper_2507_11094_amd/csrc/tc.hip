@@ -60,36 +60,128 @@ __device__ __forceinline__ bool row_find(const int32_t *col, const int32_t *dcol
     return false;
 }
 
-// One wave per changed edge; lanes walk the smaller row, probe the larger one.
+// Fenced search of a long base row: every stride-th neighbour id of the row is
+// copied to LDS once per changed edge (stride: the smallest power of two from
+// TC_FSTRIDE_MIN that needs at most TC_FCAP fences); a probe searches those
+// fences in LDS and then only the stride-entry segment they select in global
+// memory.  Rows of at most TC_FMIN entries, or longer than TC_FCAP *
+// TC_FSTRIDE_MAX, are searched whole.
+constexpr int TC_FSTRIDE_MIN = 8;
+constexpr int TC_FSTRIDE_MAX = 256;
+constexpr int TC_FCAP = 1536;  // fences per wave
+constexpr int TC_FMIN = 128;
+
+// Position of neighbour x in the base row [ob, ob + db) whose fences f[k] =
+// id(col[ob + k * stride]), k < nf, are in LDS; -1 if absent.
+__device__ __forceinline__ int64_t find_fenced(const int32_t *__restrict__ col, int64_t ob, int64_t db,
+                                               int stride, const uint32_t *f, int nf, uint32_t x) {
+    if (x < f[0]) return -1;
+    int lo = 0, hi = nf - 1;  // the last k with f[k] <= x
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (f[mid] <= x) lo = mid;
+        else hi = mid - 1;
+    }
+    const int64_t s0 = ob + (int64_t)lo * stride;
+    return find_sorted(col, s0, min(s0 + stride, ob + db), x);
+}
+
+// Work items: a changed edge's shorter row is cut into pieces of TC_CHUNK entries,
+// so that an edge between two hubs (tens of thousands of common candidates) is
+// spread over many waves instead of holding one wave for the whole launch.
+constexpr int TC_CHUNK = 1024;
+
+// cnt[i] = pieces of changed edge i (0 when its shorter row is empty); cnt[ne] = 0.
+__global__ void k_tc_items(int64_t ne, const int32_t *__restrict__ eu, const int32_t *__restrict__ ev,
+                           const int64_t *__restrict__ off, const int64_t *__restrict__ doff, int64_t *cnt) {
+    for (int64_t i = gtid(); i <= ne; i += gstride()) {
+        if (i == ne) {
+            cnt[i] = 0;
+            continue;
+        }
+        const int32_t a = eu[i], b = ev[i];
+        const int64_t ta = (off[a + 1] - off[a]) + (doff[a + 1] - doff[a]);
+        const int64_t tb = (off[b + 1] - off[b]) + (doff[b + 1] - doff[b]);
+        cnt[i] = (min(ta, tb) + TC_CHUNK - 1) / TC_CHUNK;
+    }
+}
+
+// One wave per work item; lanes walk the item's piece of the smaller row and probe
+// the larger one.  start = exclusive scan of the piece counts (start[ne] = total).
 __global__ __launch_bounds__(256) void k_tc_delta(int64_t ne, const int32_t *eu, const int32_t *ev,
+                                                  const int64_t *__restrict__ start,
                                                   const int64_t *__restrict__ off,
                                                   const int32_t *__restrict__ col,
                                                   const int64_t *__restrict__ doff,
                                                   const int32_t *__restrict__ dcol, int64_t *part) {
+    __shared__ uint32_t s_fence[256 / WAVE][TC_FCAP];
     const int64_t wave_global = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / WAVE;
     const int l = lane_id();
+    uint32_t *f = s_fence[threadIdx.x / WAVE];
     uint64_t acc = 0, walked = 0, probes = 0;
-    for (int64_t i = wave_global; i < ne; i += nwaves) {
+    const int64_t items = start[ne];
+    for (int64_t it = wave_global; it < items; it += nwaves) {
+        // the edge of item it: start[i] <= it < start[i + 1], found by a 64-way
+        // search (each lane probes one point, a ballot keeps the prefix at or below it)
+        int64_t lo = 0, hi = ne;  // start[lo] <= it < start[hi]
+        while (hi - lo > 1) {
+            const int64_t step = (hi - lo + WAVE - 1) / WAVE;
+            const int64_t p = lo + (int64_t)(l + 1) * step;
+            const uint64_t le = __ballot(p < hi && start[p] <= it);
+            lo += (int64_t)__popcll(le) * step;
+            hi = min(hi, lo + step);
+        }
+        const int64_t i = lo, piece = it - start[i];
         int32_t a = eu[i], b = ev[i];
         RowRef ra = row_ref(off, doff, a), rb = row_ref(off, doff, b);
         if (ra.db + ra.dd > rb.db + rb.dd) {
             RowRef t = ra; ra = rb; rb = t;
         }
-        // depth of the binary searches in the larger row (base level, diff level)
-        const int depth = (rb.db > 0 ? 64 - __clzll((unsigned long long)rb.db) : 0) +
-                          (rb.dd > 0 ? 64 - __clzll((unsigned long long)rb.dd) : 0);
-        const int64_t tot = ra.db + ra.dd;
-        if (l == 0) {
-            walked += tot;
-            probes += tot * depth;
+        const int64_t j0 = piece * TC_CHUNK, j1 = min(ra.db + ra.dd, j0 + TC_CHUNK);
+        int stride = TC_FSTRIDE_MIN;
+        while ((int64_t)stride * TC_FCAP < rb.db && stride < TC_FSTRIDE_MAX) stride <<= 1;
+        const int64_t nf64 = (rb.db + stride - 1) / stride;
+        const bool fenced = j1 > j0 && rb.db > TC_FMIN && nf64 <= TC_FCAP;
+        const int nf = fenced ? (int)nf64 : 0;
+        if (fenced) {
+            wave_sync();  // every lane is done with the previous edge's fences
+            for (int k = l; k < nf; k += WAVE) f[k] = (uint32_t)col[rb.ob + (int64_t)k * stride] & ID_MASK;
+            wave_sync();
         }
-        for (int64_t j = l; j < tot; j += WAVE) {
+        // global reads of one probe: the whole binary search, or the segment's
+        const int64_t seg = fenced ? stride : rb.db;
+        const int depth = (seg > 0 ? 64 - __clzll((unsigned long long)seg) : 0) +
+                          (rb.dd > 0 ? 64 - __clzll((unsigned long long)rb.dd) : 0);
+        if (l == 0) {
+            walked += (j1 - j0) + nf;
+            probes += (j1 - j0) * depth;
+        }
+        for (int64_t j = j0 + l; j < j1; j += WAVE) {
             uint32_t e = j < ra.db ? (uint32_t)col[ra.ob + j] : (uint32_t)dcol[ra.od + (j - ra.db)];
             if (e & DEAD) continue;
             uint32_t c = e & ID_MASK;
             uint32_t e2;
-            if (!row_find(col, dcol, rb, c, e2)) continue;
+            bool hit;
+            if (fenced) {
+                const int64_t p = find_fenced(col, rb.ob, rb.db, stride, f, nf, c);
+                if (p >= 0) {
+                    e2 = (uint32_t)col[p];
+                    hit = !(e2 & DEAD);
+                } else {
+                    hit = false;
+                    if (rb.dd > 0) {
+                        const int64_t q = find_sorted(dcol, rb.od, rb.od + rb.dd, c);
+                        if (q >= 0) {
+                            e2 = (uint32_t)dcol[q];
+                            hit = !(e2 & DEAD);
+                        }
+                    }
+                }
+            } else {
+                hit = row_find(col, dcol, rb, c, e2);
+            }
+            if (!hit) continue;
             int k = 1 + ((e & MARK) ? 1 : 0) + ((e2 & MARK) ? 1 : 0);
             acc += (uint64_t)(6 / k);
         }
@@ -137,8 +229,13 @@ int tc_delta(dg_graph *g, const int32_t *eu, const int32_t *ev, int64_t ne, uint
     DG_TRY(counters_clear(g));
     int64_t blocks = std::min<int64_t>((ne + 3) / 4, 16384);
     DG_TRY(g->ws.bpart.ensure(3 * (size_t)blocks + 8));
+    DG_TRY(g->ws.tcitems.ensure(2 * ((size_t)ne + 1)));
+    int64_t *cnt = g->ws.tcitems.p, *start = g->ws.tcitems.p + ne + 1;
+    hipLaunchKernelGGL(k_tc_items, dim3(grid_for(ne + 1)), dim3(256), 0, s, ne, eu, ev, F.off.p, F.doff.p, cnt);
+    DG_HIP(hipGetLastError());
+    DG_TRY(scan_excl(g, cnt, start, ne + 1));
     int ps = prof_begin("tc_delta", s);
-    hipLaunchKernelGGL(k_tc_delta, dim3((unsigned)blocks), dim3(256), 0, s, ne, eu, ev, F.off.p, F.col.p,
+    hipLaunchKernelGGL(k_tc_delta, dim3((unsigned)blocks), dim3(256), 0, s, ne, eu, ev, start, F.off.p, F.col.p,
                        F.doff.p, F.dcol.p, g->ws.bpart.p);
     prof_end(ps, s, 0.0);
     // counters C_AUX1, C_AUX2, C_AUX3 = 6 x changed triangles, entries walked, search steps
@@ -148,7 +245,8 @@ int tc_delta(dg_graph *g, const int32_t *eu, const int32_t *ev, int64_t ne, uint
     DG_TRY(counters_read(g));
     *sum6 = (uint64_t)g->ws.hcnt[C_AUX1];
     // per changed edge its endpoints' offsets (32 B); per entry of the shorter row
-    // 4 B; per binary-search step into the longer row 4 B
+    // and per fence of a long row 4 B; per global search step into the longer row
+    // (the whole row, or the segment a fence search selects) 4 B
     prof_add(ps, 32.0 * (double)ne + 4.0 * (double)g->ws.hcnt[C_AUX2] + 4.0 * (double)g->ws.hcnt[C_AUX3]);
     return DG_OK;
 }
