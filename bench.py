@@ -31,6 +31,7 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+import re
 import json
 import os
 import sys
@@ -56,17 +57,17 @@ CSRC = os.path.join(ROOT, "paper_2507_11094_amd", "csrc")
 # or another order makes the figure stale and it is reported as null.
 MEASURED_TRAFFIC: dict = {
     ("k_pr_tiles", "rmat22-dynamic-sssp+pagerank"): {
-        "source": "pagerank.hip", "sha1": "7629ea5d8434680f962621e3514f53012baa1018", "vertex_order": 0,
+        "source": "pagerank.hip", "sha1": "0574e0f730155f07581ee12981ec958cc4f34672", "vertex_order": 0,
         "fetch_kib": 585895.5, "write_kib": 33195.3, "fetch_factor": 0.5, "write_factor": 1.0},
     ("k_pr_tiles", "grid4096x4096-dynamic-sssp+pagerank"): {
-        "source": "pagerank.hip", "sha1": "7629ea5d8434680f962621e3514f53012baa1018", "vertex_order": 0,
+        "source": "pagerank.hip", "sha1": "0574e0f730155f07581ee12981ec958cc4f34672", "vertex_order": 0,
         "fetch_kib": 396397.8, "write_kib": 131599.9, "fetch_factor": 0.5, "write_factor": 1.0},
     ("k_merge_tiles", "batched4096-rmat10to14-dynamic-sssp"): {
-        "source": "graph.hip", "sha1": "ee55ed07154bb1a5b07db5162f6b434817d37359",
+        "source": "graph.hip", "sha1": "7ce1940139deb2fb551f07ab16bc4476034caa31",
         "fetch_kib": 3040372.4, "write_kib": 3291721.6, "fetch_factor": 0.5, "write_factor": 1.0},
     ("k_tc_delta", "rmat20-undirected-dynamic-tc"): {
-        "source": "tc.hip", "sha1": "9fd8d87e3bfcaa15f061353446808f472d110b52", "vertex_order": 0,
-        "fetch_kib": 277462.1, "write_kib": 768.0, "fetch_factor": 0.5, "write_factor": 1.0},
+        "source": "tc.hip", "sha1": "b5076bb4a16ebdc8ac0ef337fe1ae942a48ca96a", "vertex_order": 0,
+        "fetch_kib": 408466.4, "write_kib": 768.0, "fetch_factor": 0.5, "write_factor": 1.0},
 }
 
 # Serving objective stated up front: 99th percentile latency (submit -> result
@@ -78,22 +79,41 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def kernel_sha1(fname: str, kernel: str) -> str:
-    """SHA-1 of a kernel's own source text: from `void <kernel>(` to the brace
-    that closes its body (a template's parameter line before it is included)."""
-    with open(os.path.join(CSRC, fname)) as f:
-        text = f.read()
-    i = text.find(f"void {kernel}(")
-    if i < 0:
-        return ""
-    start = text.rfind("\n", 0, text.rfind("\n", 0, i)) + 1  # line before the signature
+def _body(text: str, i: int) -> tuple:
+    """(start, end) of the definition whose signature contains offset i: from the
+    line before the signature (a template's parameter line) to the closing brace."""
+    start = text.rfind("\n", 0, text.rfind("\n", 0, i)) + 1
     j = text.index("{", i)
     depth = 0
     for k in range(j, len(text)):
         depth += {"{": 1, "}": -1}.get(text[k], 0)
         if depth == 0:
-            return hashlib.sha1(text[start:k + 1].encode()).hexdigest()
-    return ""
+            return start, k + 1
+    return start, len(text)
+
+
+def kernel_sha1(fname: str, kernel: str) -> str:
+    """SHA-1 of what a kernel's code is made of in its own source file: its
+    definition, the definitions of the same file's device functions it calls, and
+    the file's constexpr lines whose names either of those use."""
+    with open(os.path.join(CSRC, fname)) as f:
+        text = f.read()
+    i = text.find(f"void {kernel}(")
+    if i < 0:
+        return ""
+    a, b = _body(text, i)
+    parts = [text[a:b]]
+    helpers = re.finditer(r"__device__[^;{(]*?\b(\w+)\s*\(", text)
+    for m in helpers:
+        name = m.group(1)
+        if name != kernel and re.search(rf"\b{name}\s*[<(]", parts[0]):
+            ha, hb = _body(text, m.start(1))
+            parts.append(text[ha:hb])
+    used = "\n".join(parts)
+    for m in re.finditer(r"^\s*constexpr[^=\n]*?\b(\w+)\s*=[^\n]*$", text, re.M):
+        if re.search(rf"\b{m.group(1)}\b", used):
+            parts.append(m.group(0).strip())
+    return hashlib.sha1("\n".join(parts).encode()).hexdigest()
 
 
 def traffic_for(kernel: str, workload: str, order=None):

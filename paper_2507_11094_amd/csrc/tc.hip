@@ -61,14 +61,14 @@ __device__ __forceinline__ bool row_find(const int32_t *col, const int32_t *dcol
 }
 
 // Fenced search of a long base row: every stride-th neighbour id of the row is
-// copied to LDS once per changed edge (stride: the smallest power of two from
+// copied to LDS once per work item (stride: the smallest power of two from
 // TC_FSTRIDE_MIN that needs at most TC_FCAP fences); a probe searches those
 // fences in LDS and then only the stride-entry segment they select in global
 // memory.  Rows of at most TC_FMIN entries, or longer than TC_FCAP *
 // TC_FSTRIDE_MAX, are searched whole.
 constexpr int TC_FSTRIDE_MIN = 8;
-constexpr int TC_FSTRIDE_MAX = 256;
-constexpr int TC_FCAP = 1536;  // fences per wave
+constexpr int TC_FSTRIDE_MAX = 2048;
+constexpr int TC_FCAP = 128;  // fences per wave (rows up to 262,144 entries are fenced)
 constexpr int TC_FMIN = 128;
 
 // Position of neighbour x in the base row [ob, ob + db) whose fences f[k] =
@@ -89,7 +89,7 @@ __device__ __forceinline__ int64_t find_fenced(const int32_t *__restrict__ col, 
 // Work items: a changed edge's shorter row is cut into pieces of TC_CHUNK entries,
 // so that an edge between two hubs (tens of thousands of common candidates) is
 // spread over many waves instead of holding one wave for the whole launch.
-constexpr int TC_CHUNK = 1024;
+constexpr int TC_CHUNK = 256;
 
 // cnt[i] = pieces of changed edge i (0 when its shorter row is empty); cnt[ne] = 0.
 __global__ void k_tc_items(int64_t ne, const int32_t *__restrict__ eu, const int32_t *__restrict__ ev,
@@ -206,17 +206,27 @@ __global__ __launch_bounds__(256) void k_tc_delta(int64_t ne, const int32_t *eu,
 }
 
 // Sum of the per-block partials (triangle weight, entries walked, search steps).
-__global__ void k_tc_sum(const int64_t *part, int64_t nblocks, int64_t *out) {
-    __shared__ int64_t s[3][256];
-    for (int c = 0; c < 3; ++c) {
-        int64_t a = 0;
-        for (int64_t b = threadIdx.x; b < nblocks; b += blockDim.x) a += part[3 * b + c];
-        s[c][threadIdx.x] = a;
+__global__ __launch_bounds__(1024) void k_tc_sum(const int64_t *part, int64_t nblocks, int64_t *out) {
+    __shared__ int64_t s[3][1024 / WAVE];
+    int64_t a0 = 0, a1 = 0, a2 = 0;
+    for (int64_t b = threadIdx.x; b < nblocks; b += blockDim.x) {
+        a0 += part[3 * b];
+        a1 += part[3 * b + 1];
+        a2 += part[3 * b + 2];
+    }
+    a0 = wave_sum(a0);
+    a1 = wave_sum(a1);
+    a2 = wave_sum(a2);
+    const int wv = threadIdx.x / WAVE;
+    if (lane_id() == 0) {
+        s[0][wv] = a0;
+        s[1][wv] = a1;
+        s[2][wv] = a2;
     }
     __syncthreads();
     if (threadIdx.x < 3) {
         int64_t a = 0;
-        for (int q = 0; q < (int)blockDim.x; ++q) a += s[threadIdx.x][q];
+        for (int q = 0; q < (int)blockDim.x / WAVE; ++q) a += s[threadIdx.x][q];
         out[threadIdx.x] = a;
     }
 }
@@ -227,6 +237,7 @@ int tc_delta(dg_graph *g, const int32_t *eu, const int32_t *ev, int64_t ne, uint
     hipStream_t s = g->stream;
     Dir &F = g->fwd;
     DG_TRY(counters_clear(g));
+    // four waves per block; 16,384 blocks measured faster than a resident-size grid
     int64_t blocks = std::min<int64_t>((ne + 3) / 4, 16384);
     DG_TRY(g->ws.bpart.ensure(3 * (size_t)blocks + 8));
     DG_TRY(g->ws.tcitems.ensure(2 * ((size_t)ne + 1)));
@@ -240,7 +251,7 @@ int tc_delta(dg_graph *g, const int32_t *eu, const int32_t *ev, int64_t ne, uint
     prof_end(ps, s, 0.0);
     // counters C_AUX1, C_AUX2, C_AUX3 = 6 x changed triangles, entries walked, search steps
     static_assert(C_AUX2 == C_AUX1 + 1 && C_AUX3 == C_AUX1 + 2, "three consecutive counters");
-    hipLaunchKernelGGL(k_tc_sum, dim3(1), dim3(256), 0, s, g->ws.bpart.p, blocks, g->ws.dcnt + C_AUX1);
+    hipLaunchKernelGGL(k_tc_sum, dim3(1), dim3(1024), 0, s, g->ws.bpart.p, blocks, g->ws.dcnt + C_AUX1);
     DG_HIP(hipGetLastError());
     DG_TRY(counters_read(g));
     *sum6 = (uint64_t)g->ws.hcnt[C_AUX1];
