@@ -576,6 +576,38 @@ def test_tc_dynamic(heavy):
     assert G.tc_static() == oracle.triangles(n, cu, cv)
 
 
+def test_tc_two_hubs_split_rows():
+    """Two hubs sharing 4,200 neighbours: the edge between them has a shorter row
+    of about 5,200 entries, so its delta is cut into many work items and its
+    longer row is searched through fences; batches mix it with edges of the same
+    triangles (weights 6/2 and 6/3)."""
+    say("tc two hubs, split rows")
+    n, common = 7000, np.arange(2, 4202)
+    only0, only1 = np.arange(4202, 5202), np.arange(5202, 6202)
+    ring = np.arange(2, 6201)
+    u = np.concatenate([[0], np.zeros(common.size + only0.size, np.int64), np.ones(common.size + only1.size, np.int64),
+                        ring]).astype(np.int32)
+    v = np.concatenate([[1], common, only0, common, only1, ring + 1]).astype(np.int32)
+    G = dg.Graph(n, u, v, None, undirected=True)
+    q = G.tc_attach()
+    assert q.read() == oracle.triangles(n, u, v)
+    cu, cv = u, v
+    batches = [
+        ([0], [1], [0]),                              # the hub edge alone: 4,200 triangles
+        ([0, 0, 1, 2], [1, 2, 2, 3], [1, 0, 0, 0]),   # back in, with edges of its triangles out
+        ([0, 0, 1, 5, 0], [1, 5, 5, 6, 2], [0, 1, 0, 0, 1]),
+        ([1, 0, 9, 3000], [2, 1, 10, 3001], [1, 1, 0, 0]),
+    ]
+    for i, (bs, bd, bo) in enumerate(batches):
+        bs, bd = np.array(bs, np.int32), np.array(bd, np.int32)
+        bo, bw = np.array(bo, np.uint8), np.ones(len(bs), np.int32)
+        G.apply(bs, bd, bw, bo)
+        cu, cv, _, _ = oracle.apply(n, cu, cv, None, bs, bd, bw, bo, undirected=True)
+        assert q.read() == oracle.triangles(n, cu, cv), i
+    assert G.tc_static() == oracle.triangles(n, cu, cv)
+    G.close()
+
+
 def test_tc_small_closed_forms():
     say("tc closed forms")
     k = 9
