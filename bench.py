@@ -51,10 +51,11 @@ CSRC = os.path.join(ROOT, "paper_2507_11094_amd", "csrc")
 # HBM bytes per launch read from rocprofv3 FETCH_SIZE / WRITE_SIZE (KiB per
 # dispatch) for the named kernel and workload, divided by what the same counters
 # read per byte of a plain 256 MiB device copy (FETCH_SIZE 0.5, WRITE_SIZE 1.0
-# counted bytes per byte moved).  Each entry holds the SHA-1 of the kernel's own
-# source text (its template line, signature and body) at the time the counters
-# were taken, and the vertex order the graph had (single graphs); a changed kernel
-# or another order makes the figure stale and it is reported as null.
+# counted bytes per byte moved).  Each entry holds the SHA-1 that kernel_sha1()
+# gives for the kernel (its definition, the same file's device functions it calls
+# and the constants they use) at the time the counters were taken, and the vertex
+# order the graph had (single graphs); a changed kernel or another order makes the
+# figure stale and it is reported as null.
 MEASURED_TRAFFIC: dict = {
     ("k_pr_tiles", "rmat22-dynamic-sssp+pagerank"): {
         "source": "pagerank.hip", "sha1": "0574e0f730155f07581ee12981ec958cc4f34672", "vertex_order": 0,
