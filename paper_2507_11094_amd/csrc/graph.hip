@@ -1162,7 +1162,14 @@ static int diff_rebuild(dg_graph *g, Dir &d, const uint64_t *nkey, const int32_t
     DG_TRY(scan_excl(g, flags, rank, dm + 1));
     const int64_t live = dm - killed;
     const int64_t dm2 = live + nk;
-    DG_TRY(d.dkey2.ensure(dm2 + 1));
+    // the diff level grows batch by batch until a merge: grow its spares by doubling,
+    // so that a device reallocation (whose free synchronises the device) is rare
+    if ((size_t)dm2 + 1 > d.dkey2.cap) {
+        const size_t want = std::max((size_t)dm2 + 1, 2 * d.dkey2.cap);
+        DG_TRY(d.dkey2.ensure(want));
+        DG_TRY(d.dcol2.ensure(want));
+        DG_TRY(d.dw2.ensure(want));
+    }
     DG_TRY(d.dcol2.ensure(dm2 + 1));
     DG_TRY(d.dw2.ensure(dm2 + 1));
     if (dm > 0)
