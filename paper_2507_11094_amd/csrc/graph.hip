@@ -1155,15 +1155,17 @@ static int diff_rebuild(dg_graph *g, Dir &d, const uint64_t *nkey, const int32_t
     hipStream_t s = g->stream;
     Work &ws = g->ws;
     const int64_t dm = d.dm;
-    DG_TRY(ws.scan64.ensure(2 * ((size_t)dm + 1)));
+    // the diff level grows batch by batch until a merge: grow its scratch and spares
+    // by doubling, so that a device reallocation (whose free synchronises the
+    // device) is rare
+    if (2 * ((size_t)dm + 1) > ws.scan64.cap)
+        DG_TRY(ws.scan64.ensure(std::max(2 * ((size_t)dm + 1), 2 * ws.scan64.cap)));
     int64_t *flags = ws.scan64.p;
     int64_t *rank = flags + (dm + 1);
     hipLaunchKernelGGL(k_live_flags, dim3(grid_for(dm + 1)), dim3(256), 0, s, dm, d.dcol.p, flags);
     DG_TRY(scan_excl(g, flags, rank, dm + 1));
     const int64_t live = dm - killed;
     const int64_t dm2 = live + nk;
-    // the diff level grows batch by batch until a merge: grow its spares by doubling,
-    // so that a device reallocation (whose free synchronises the device) is rare
     if ((size_t)dm2 + 1 > d.dkey2.cap) {
         const size_t want = std::max((size_t)dm2 + 1, 2 * d.dkey2.cap);
         DG_TRY(d.dkey2.ensure(want));
