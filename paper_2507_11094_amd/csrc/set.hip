@@ -38,10 +38,21 @@ static inline int grid_for(int64_t n) {
 
 // Member-local -> store ids.  off: element offsets per member (count + 1); an id
 // outside its member's [0, n_i) raises *err.
-__global__ void k_set_translate(int64_t total, const int64_t *off, int32_t count, const int64_t *vbase,
-                                const int32_t *s, const int32_t *d, int32_t *os, int32_t *od, int64_t *err) {
-    for (int64_t i = gtid(); i < total; i += gstride()) {
-        const int32_t mb = row_of(off, 0, count - 1, i);
+// Members hold runs of consecutive entries, so one search per block finds the member
+// of the block's first entry and each thread steps forward from it (members with no
+// entries are stepped over).
+__global__ __launch_bounds__(256) void k_set_translate(int64_t total, const int64_t *off, int32_t count,
+                                                       const int64_t *vbase, const int32_t *s, const int32_t *d,
+                                                       int32_t *os, int32_t *od, int64_t *err) {
+    __shared__ int32_t s_mb;
+    for (int64_t b0 = (int64_t)blockIdx.x * blockDim.x; b0 < total; b0 += (int64_t)gridDim.x * blockDim.x) {
+        if (threadIdx.x == 0) s_mb = row_of(off, 0, count - 1, b0);
+        __syncthreads();
+        int32_t mb = s_mb;
+        __syncthreads();  // s_mb is written again in the next pass
+        const int64_t i = b0 + threadIdx.x;
+        if (i >= total) continue;
+        while (mb + 1 < count && off[mb + 1] <= i) ++mb;
         const int64_t b = vbase[mb], nl = vbase[mb + 1] - b;
         const int32_t u = s[i], v = d[i];
         if (u < 0 || u >= nl || v < 0 || v >= nl) {
