@@ -48,7 +48,9 @@ extern "C" {
 #define DG_ENOTFOUND (-7)/* no such request / result not ready                      */
 
 /* Distance of a vertex the source cannot reach: INT_MAX / 2, the paper's INF
- * (Appendix A, Dynamic SSSP listing). */
+ * (Appendix A, Dynamic SSSP listing).  Distances saturate: a vertex whose
+ * shortest distance is DG_INF or more is reported as DG_INF with parent -1, like
+ * an unreachable one, and every other vertex keeps its exact distance. */
 #define DG_INF 1073741823
 
 /* ---- flags --------------------------------------------------------------------- */
@@ -233,8 +235,10 @@ int dg_tc_read(dg_query *q, uint64_t *count);
  * Member i has n[i] vertices and m[i] arcs; the arcs of all members are
  * concatenated in src/dst/w (w may be NULL: weight 1) with member-local vertex
  * ids.  flags may hold DG_DEVICE_PTRS for src/dst/w (n and m are host arrays).
- * Shortest paths run on the persistent work queue (cfg->sssp_persistent is forced
- * to 1) and each batch's update is replayed from a captured hipGraph. */
+ * Shortest-path updates run as frontier rounds with device-side counts, captured
+ * once into hipGraphs and replayed for every batch (cfg->sssp_persistent 2, the
+ * default for a set); cfg->sssp_persistent 1 asks for the persistent work queue
+ * instead, also replayed from a captured hipGraph. */
 typedef struct dg_set dg_set;
 int dg_set_create(int32_t count, const int32_t *n, const int64_t *m, const int32_t *src,
                   const int32_t *dst, const int32_t *w, uint32_t flags, const dg_config *cfg,

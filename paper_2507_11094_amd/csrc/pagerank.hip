@@ -866,24 +866,29 @@ static int pr_update(dg_query *q, int64_t adel, int64_t ains, dg_batch_stats *st
         if (mode == 0 && (double)edges >= 0.2 * (double)all_edges) global = true;
     }
     int32_t iters = 0, conv = 0;
-    if (global) {
-        // warm start from the current x; S = sum(x) is conserved by the global form
+    // S = sum(x) of the warm start.  Both forms stop on the L1 step of the
+    // normalised ranks x / S, so the tolerance on x is tol * S (the global form
+    // also conserves S).
+    double Ssum;
+    {
         double *partials = ws.part.p + qcap;
         hipLaunchKernelGGL(k_sum_vec2, dim3(APPLY_GROUPS), dim3(256), 0, s, q->x.p, g->fwd.deg.p,
                            (int64_t)g->n, partials);
         hipLaunchKernelGGL(k_pr_reduce, dim3(1), dim3(256), 0, s, partials, APPLY_GROUPS, 0, 0.0, q->damping,
                            1.0, 0.0, 1, ws.prs.p, ws.prs.p + 5);
         DG_HIP(hipGetLastError());
-        double Ssum;
-        DG_HIP(hipMemcpyAsync(&Ssum, ws.prs.p, sizeof(double), hipMemcpyDeviceToHost, s));
-        DG_HIP(hipStreamSynchronize(s));
         // prs[0] here holds the plain sum (first partial of each pair)
+        DG_HIP(hipMemcpyAsync(ws.hcnt + C_COUNT, ws.prs.p, sizeof(double), hipMemcpyDeviceToHost, s));
+        DG_HIP(hipStreamSynchronize(s));
+        std::memcpy(&Ssum, ws.hcnt + C_COUNT, sizeof(double));
+    }
+    if (global) {
         na = g->n;
         edges = all_edges;
         DG_TRY(pr_iterate(g, nullptr, na, edges, q->damping, tol_of(q) * Ssum, q->max_iter, true, Ssum,
                           q->x.p, q->xn.p, q->contrib.p, &iters, &conv, side, q->last_iters));
     } else {
-        DG_TRY(pr_iterate(g, Alist, na, edges, q->damping, tol_of(q), q->max_iter, false, 0.0, q->x.p,
+        DG_TRY(pr_iterate(g, Alist, na, edges, q->damping, tol_of(q) * Ssum, q->max_iter, false, 0.0, q->x.p,
                           q->xn.p, q->contrib.p, &iters, &conv));
     }
     q->last_iters = iters;

@@ -1,9 +1,12 @@
 // Single-source shortest paths: static solve and the dynamic update.
 //
 // State per query: key[v] = (dist << 32) | parent as one 64-bit word, so the
-// paper's Min construct -- "<dist, modified_nxt, parent> = <Min(dist, d+w), True,
-// v>" in the Dynamic SSSP listing of Appendix A -- is a single atomicMin; ties in
-// distance resolve to the smaller parent id, and any tie is a valid tree.
+// Min construct of the Dynamic SSSP listing of Appendix A (distance, modified
+// flag and parent updated together) is a single atomicMin; ties in distance
+// resolve to the smaller parent id, and any tie is a valid tree.  Distances
+// saturate at INF: a vertex whose shortest distance is INF or more reads as
+// unreachable (INF, parent -1) and is never expanded, which leaves every other
+// distance exact because weights are positive.
 //
 // Dynamic update for one batch (Appendix A, DynSSSP: OnDelete, updateCSRDel,
 // Decremental, OnAdd, updateCSRAdd, Incremental), scheduled for a GPU:
@@ -383,6 +386,57 @@ __global__ void k_sssp_set_sources(const int32_t *src, int64_t ns, uint64_t *key
     for (int64_t i = gtid(); i < ns; i += gstride()) key[src[i]] = sssp_pack(0, -1);
 }
 
+// ---- guard of the work-queue schedule --------------------------------------------------
+// The work queue relaxes in FIFO order.  On a graph whose shortest-path trees are
+// many hops deep and whose weights vary (a road network, a grid), FIFO order
+// improves a vertex about once per wave of improvements that sweeps past it, so the
+// work grows with the hop depth (a CPU model of a 4096 x 4096 grid improved every
+// vertex hundreds of times).  Before the queue runs a static solve, a breadth-first
+// probe from the sources counts hop levels; past WL_MAX_DEPTH levels the graph is
+// refused, and the frontier schedules (near-far buckets for such graphs) remain.
+constexpr int WL_MAX_DEPTH = 64;
+
+struct DepthOp {
+    int32_t *stamp;
+    int32_t st;
+    int32_t *next;
+    int64_t *ncount;
+    __device__ bool vtx(int32_t, int32_t &pay) const { pay = 0; return true; }
+    __device__ bool edge(bool valid, int32_t, int32_t, int32_t x, int32_t) const {
+        return valid && stamp[x] != st && atomicExch(&stamp[x], st) != st;
+    }
+    __device__ SinkTarget sink() const { return SinkTarget{next, ncount}; }
+};
+
+__global__ void k_stamp_all(const int32_t *a, int64_t n, int32_t *stamp, int32_t st) {
+    for (int64_t i = gtid(); i < n; i += gstride()) stamp[a[i]] = st;
+}
+
+// Hop levels of a breadth-first search from the ns sources in f0, up to
+// `limit` levels: *deep = true when vertices are still being discovered after it.
+static int hop_depth_exceeds(dg_graph *g, int64_t ns, int limit, bool *deep) {
+    hipStream_t s = g->stream;
+    Work &ws = g->ws;
+    int32_t st;
+    DG_TRY(next_stamp(g, &st));
+    hipLaunchKernelGGL(k_stamp_all, dim3(grid_for(ns)), dim3(256), 0, s, ws.f0.p, ns, ws.stamp.p, st);
+    DG_HIP(hipGetLastError());
+    int32_t *F = ws.f0.p, *N = ws.f1.p;
+    int64_t nf = ns;
+    int level = 0;
+    while (nf > 0 && level < limit) {
+        DG_TRY(counters_clear(g));
+        DepthOp op{ws.stamp.p, st, N, ws.dcnt + C_F1};
+        DG_TRY(launch_expand(s, make_args(g, g->fwd, F, nf), op, 8192));
+        DG_TRY(counters_read(g));
+        nf = ws.hcnt[C_F1];
+        std::swap(F, N);
+        ++level;
+    }
+    *deep = nf > 0;
+    return DG_OK;
+}
+
 // Static solve from ns distinct sources (device array) -- one per member graph
 // of a batched set, or a single source.
 int sssp_static_multi(dg_graph *g, uint64_t *key, const int32_t *srcs, int64_t ns, dg_batch_stats *st) {
@@ -392,6 +446,15 @@ int sssp_static_multi(dg_graph *g, uint64_t *key, const int32_t *srcs, int64_t n
     hipLaunchKernelGGL(k_sssp_set_sources, dim3(grid_for(ns)), dim3(256), 0, s, srcs, ns, key);
     DG_HIP(hipGetLastError());
     if (g->cfg.sssp_persistent == 1) {
+        if (srcs != g->ws.f0.p)
+            DG_HIP(hipMemcpyAsync(g->ws.f0.p, srcs, (size_t)ns * 4, hipMemcpyDeviceToDevice, s));
+        bool deep = false;
+        DG_TRY(hop_depth_exceeds(g, ns, WL_MAX_DEPTH, &deep));
+        if (deep)
+            return set_error(DG_EINVAL, "work-queue schedule refused: shortest-path trees deeper than %d hops "
+                                        "(FIFO relaxation would repeat work on such a graph); use "
+                                        "sssp_persistent 0 or 2, with sssp_delta > 0 for road-like graphs",
+                             WL_MAX_DEPTH);
         DG_TRY(sssp_static_persistent(g, key, srcs, ns));
         DG_HIP(hipStreamSynchronize(s));
         return DG_OK;

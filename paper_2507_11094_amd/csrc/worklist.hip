@@ -424,8 +424,9 @@ static int wl_ensure(dg_graph *g, WorkQ *wq) {
     wq->margin = 64ll * 4 * wl_groups(g) + 1024;
     wq->ctr = reinterpret_cast<unsigned long long *>(ws.wctr.p);
     // FIFO relaxation on high-diameter graphs can re-relax each vertex ~sqrt(n)
-    // times; past 16 items per vertex and arc the run stops with an error instead
-    wq->budget = 16ull * (unsigned long long)(g->n + edges) + (1ull << 20);
+    // times (static solves refuse such graphs up front); past 4 items per vertex
+    // and arc a run stops with an error instead, a fraction of a second of work
+    wq->budget = 4ull * (unsigned long long)(g->n + edges) + (1ull << 20);
     return DG_OK;
 }
 

@@ -4,24 +4,27 @@
   distances bit-exact against the oracle's Dijkstra, the parent array a tight
   shortest-path tree, PageRank within max-abs 1e-10 of the oracle's power
   iteration.
+* R-MAT scale 22 with four 1M-update batches (enough diff entries and
+  tombstones to pass the merge threshold) and then one 10k batch: distances
+  bit-exact, PageRank within max-abs 1e-10 of the oracle.
 * 4096 x 4096 grid, one 100k batch, near-far SSSP (bucket width 8000):
-  distances bit-exact against Dijkstra; PageRank by a property that holds at any
-  size: one step of the dangling-uniform power iteration, built here from the
-  oracle's edge list, moves the result by at most the L1 tolerance, and the
-  ranks sum to 1.
-* Undirected R-MAT scale 20, three 1 % batches: the maintained triangle count
-  equals the static forward count of the same graph (a different algorithm and
-  kernel).  The exact oracle count runs at scale 17 (a scale-20 recount takes
-  minutes on one core).
+  distances bit-exact against Dijkstra, PageRank within max-abs 1e-10 of the
+  oracle's power iteration.
+* Undirected R-MAT scale 20, batches of 0.1 %, 1 % and 5 % of the edges in a
+  row: the maintained triangle count equals the oracle's count after each
+  (stored in tests/golden/tc_rmat20.json by tests/golden/make_tc_rmat20.py, since
+  a scale-20 recount takes minutes on one core) and the static forward count of
+  the same graph.
 * 4,096 R-MAT graphs (415 M arcs), one step: every member of a seeded sample of
   64, plus the largest, bit-exact against the oracle.
 """
+import json
+import os
 import sys
 import time
 
 import numpy as np
 import pytest
-import scipy.sparse as sp
 
 import graphgen
 import oracle
@@ -83,6 +86,36 @@ def test_fullsize_rmat22_sssp_pagerank():
     assert abs(float(rank.sum()) - 1.0) <= 1e-12
 
 
+def test_fullsize_rmat22_large_batches_through_merge():
+    t0 = time.perf_counter()
+    n, s, d, w = graphgen.c2r_graph(22)
+    keys = graphgen.edge_keys(s, d, False)
+    bats = [graphgen.update_batch(n, s, d, k, graphgen.config_seed(1, 300 + i), wmax=100, existing=keys)
+            for i, k in enumerate([1000000] * 4 + [10000])]
+    say("R-MAT 22 SSSP + PageRank, four 1M batches and one 10k batch; inputs", round(time.perf_counter() - t0, 1), "s")
+    G = dg.Graph(n, s, d, w)
+    qs = G.sssp_attach(0)
+    qp = G.pr_attach(0.85, 1e-9, 1000)
+    merged = 0
+    for i, b in enumerate(bats):
+        st = G.apply(*b)
+        merged += st.merged
+        say("batch", i, "k", b[0].size, "merged", st.merged, "diff", st.diff_entries, "tombstones", st.tombstones)
+    assert merged >= 1
+    dist, par = qs.read()
+    rank, _, conv = qp.read()
+    G.close()
+    say("oracle: five edge-list applications, Dijkstra, power iteration")
+    cs, cd, cw = s, d, w
+    for b in bats:
+        cs, cd, cw, _ = oracle.apply(n, cs, cd, cw, *b)
+    assert np.array_equal(dist, oracle.sssp(n, cs, cd, cw, 0))
+    check_tree(n, cs, cd, cw, 0, dist, par)
+    want, _, oconv = oracle.pagerank(n, cs, cd, 0.85, 1e-9, 1000)
+    assert conv and oconv
+    assert float(np.max(np.abs(rank - want))) <= 1e-10
+
+
 def test_fullsize_grid_sssp_pagerank():
     t0 = time.perf_counter()
     n, s, d, w = graphgen.c2g_graph(4096)
@@ -98,31 +131,36 @@ def test_fullsize_grid_sssp_pagerank():
     rank, _, conv = qp.read()
     G.close()
     cs, cd, cw, _ = oracle.apply(n, s, d, w, *bats[0])
-    say("oracle Dijkstra; PageRank fixed-point residual")
+    say("oracle Dijkstra and power iteration on the grid")
     assert np.array_equal(dist, oracle.sssp(n, cs, cd, cw, 0))
     check_tree(n, cs, cd, cw, 0, dist, par)
-    assert conv
+    want, _, oconv = oracle.pagerank(n, cs, cd, 0.85, 1e-9, 1000)
+    err = float(np.max(np.abs(rank - want)))
+    say("grid PageRank max-abs vs oracle", err)
+    assert conv and oconv
     assert abs(float(rank.sum()) - 1.0) <= 1e-12
-    outdeg = np.bincount(cs, minlength=n).astype(np.float64)
-    A = sp.csr_matrix((np.ones(cs.size), (cd, cs)), shape=(n, n))
-    contrib = np.where(outdeg > 0, rank / np.maximum(outdeg, 1.0), 0.0)
-    dang = float(rank[outdeg == 0].sum())
-    step = (1.0 - 0.85) / n + 0.85 * (A @ contrib + dang / n)
-    assert float(np.abs(step - rank).sum()) <= 1.5e-9
+    assert err <= 1e-10
 
 
-def test_fullsize_tc_rmat20_dynamic_equals_recount():
+def test_fullsize_tc_rmat20_against_golden_counts():
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "tc_rmat20.json")))
     t0 = time.perf_counter()
     n, s, d = graphgen.c3_graph(20)[:3]
-    k = int(0.01 * s.size)
-    bats = batches_for(n, s, d, k, 2, 3, 100, undirected=True)
-    say("undirected R-MAT 20 TC, three 1 % batches; inputs", round(time.perf_counter() - t0, 1), "s")
+    assert (n, s.size) == (gold["graph"]["vertices"], gold["graph"]["edges"])
+    keys = graphgen.edge_keys(s, d, True)
+    bats = [graphgen.update_batch(n, s, d, b["k"], b["seed"], undirected=True, existing=keys)
+            for b in gold["batches"]]
+    say("undirected R-MAT 20 TC, batches of 0.1 %, 1 % and 5 %; inputs", round(time.perf_counter() - t0, 1), "s")
     G = dg.Graph(n, s, d, None, undirected=True)
     q = G.tc_attach()
-    for i, b in enumerate(bats):
-        G.apply(*b)
+    assert q.read() == gold["counts"][0]
+    for i, (b, want) in enumerate(zip(bats, gold["counts"][1:])):
+        st = G.apply(*b)
+        assert (st.deleted, st.inserted) == (gold["batches"][i]["deleted"], gold["batches"][i]["inserted"])
         dyn = q.read()
-        assert dyn == G.tc_static(), i
+        say("batch", i, "k", b[0].size, "count", dyn, "want", want)
+        assert dyn == want, i
+        assert G.tc_static() == want, i
     G.close()
 
 

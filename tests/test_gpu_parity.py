@@ -233,6 +233,23 @@ def test_sssp_grid_and_hub(persistent, delta):
         assert_tree(n, cs, cd, cw, 0, dist, par)
 
 
+def test_work_queue_refuses_deep_graphs():
+    """The work-queue schedule refuses a graph whose breadth-first levels from the
+    source pass 64 (a 100 x 100 grid: 198 levels) before its queue runs; the
+    frontier schedules solve the same graph."""
+    n, s, d, w = graphgen.grid4(100, 100, 9, 1000)
+    say("work queue guard on a 100x100 grid")
+    G = dg.Graph(n, s, d, w, config=cfg(persistent=1))
+    with pytest.raises(dg.DGError) as e:
+        G.sssp_attach(0)
+    assert e.value.code == dg.DG_EINVAL and "64 hops" in str(e.value)
+    G.close()
+    G = dg.Graph(n, s, d, w, config=cfg(persistent=0, delta=3000))
+    q = G.sssp_attach(0)
+    assert np.array_equal(q.read()[0], oracle.sssp(n, s, d, w, 0))
+    G.close()
+
+
 def test_sssp_rounds_captured_on_a_stream():
     """Frontier rounds captured into hipGraphs (a non-null stream) and replayed for
     every batch, with the host finishing long walks past the captured depth."""
@@ -268,6 +285,37 @@ def test_sssp_fig_dynsssp_reconstructed():
     dist, _ = q.read()
     for name, val in g["printed_after"].items():
         assert dist[V[name]] == val
+
+
+def test_sssp_distance_saturates_at_inf():
+    """A vertex whose shortest distance is INF or more reads as unreachable
+    (INF, parent -1); every other distance stays exact.  Hand-computed: the only
+    path to 1 weighs 2^30 - 1 = INF; 3 is reached through 2 at 5 + (2^30 - 10)."""
+    W = (1 << 30) - 1
+    s = [0, 0, 2, 1, 3, 2]
+    d = [1, 2, 3, 3, 4, 5]
+    w = [W, 5, (1 << 30) - 10, 1, 1, 7]
+    say("sssp saturation at INF")
+    for order in (0, 1):
+        c = cfg()
+        c.vertex_order = order
+        G = dg.Graph(6, s, d, w, config=c)
+        q = G.sssp_attach(0)
+        want = np.array([0, INF, 5, (1 << 30) - 5, (1 << 30) - 4, 12], np.int32)
+        dist, par = q.read()
+        assert np.array_equal(dist, want)
+        assert par.tolist() == [-1, -1, 0, 2, 3, 2]
+        # without 0->2, every path to 2..5 weighs INF or more (3 and 4 through 1)
+        G.apply([0], [2], [0], [0])
+        dist, par = q.read()
+        assert dist.tolist() == [0, INF, INF, INF, INF, INF]
+        assert par.tolist() == [-1] * 6
+        # 0->1 deleted and re-inserted with weight 3 in one batch: 1, 3, 4 come back
+        G.apply([0, 0], [1, 1], [0, 3], [0, 1])
+        dist, par = q.read()
+        assert dist.tolist() == [0, 3, INF, 4, 5, INF]
+        assert par.tolist() == [-1, 0, -1, 1, 3, -1]
+        G.close()
 
 
 def test_sssp_unreachable_and_disconnect():
@@ -548,6 +596,32 @@ def test_pagerank_dangling_and_isolated():
     r, _, _ = q.read()
     want, _, _ = oracle.pagerank(4, [0, 3, 1], [1, 1, 2], 0.85, 1e-14, 5000)
     assert np.max(np.abs(r - want)) < 1e-11
+
+
+def test_pagerank_local_form_many_dangling():
+    """The local (listing) form stops on the L1 step of the normalised ranks, as
+    the oracle does.  Half of the vertices lose every out-arc, so the unnormalised
+    iterate sums to well below 1; the stopping rule must still match the oracle's
+    at the same tolerance."""
+    n, s, d, w = rmat_small(12, 16, 31)
+    drop = graphgen.uniform01(77, 0, n) < 0.5
+    keep = ~drop[s]
+    s, d, w = s[keep], d[keep], w[keep]
+    say("pagerank local form, many dangling vertices: n", n, "m", s.size, "dangling", int((np.bincount(s, minlength=n) == 0).sum()))
+    c = cfg()
+    c.pr_mode = 1
+    G = dg.Graph(n, s, d, w, config=c)
+    q = G.pr_attach(0.85, PR_TOL, 1000)
+    cs, cd, cw = s, d, w
+    for i, k in enumerate([40, 400, 4]):
+        b = graphgen.update_batch(n, cs, cd, k, 8100 + i)
+        st = G.apply(*b)
+        cs, cd, cw, _ = oracle.apply(n, cs, cd, cw, *b)
+        r, it, conv = q.read()
+        want, _, oconv = oracle.pagerank(n, cs, cd, 0.85, PR_TOL, 1000)
+        assert conv and oconv and st.pr_affected > 0
+        assert float(np.max(np.abs(r - want))) <= PR_MAXABS, i
+    G.close()
 
 
 # ------------------------------------------------------------------ triangles

@@ -23,8 +23,10 @@ def make_graphs(count, seed):
     return gs
 
 
-def make_requests(graphs, count, seed):
-    """Request stream: graph uniform, batch log-uniform in [4, 400], kinds 40/40/20."""
+def make_requests(graphs, count, seed, kmin=4, kmax=400, tc_max_n=None):
+    """Request stream: graph uniform, batch log-uniform in [kmin, kmax], kinds
+    40/40/20 (a triangle request on a graph above tc_max_n vertices becomes a
+    PageRank request, to keep the oracle's recount short)."""
     rng_g = graphgen.uniform_int(graphgen.stream_seed(seed, "misc"), 0, count, 0, len(graphs) - 1)
     rng_k = graphgen.uniform01(graphgen.stream_seed(seed, "w"), 0, count)
     rng_q = graphgen.uniform01(graphgen.stream_seed(seed, "perm"), 0, count)
@@ -33,10 +35,12 @@ def make_requests(graphs, count, seed):
     for i in range(count):
         gi = int(rng_g[i])
         n, s, d, w = cur[gi]
-        k = int(round(np.exp(np.log(4) + rng_k[i] * (np.log(400) - np.log(4)))))
+        k = int(round(np.exp(np.log(kmin) + rng_k[i] * (np.log(kmax) - np.log(kmin)))))
         k = min(k, 2 * s.size)
         b = graphgen.update_batch(n, s, d, k, seed * 1000 + i)
         kind = dg.SSSP if rng_q[i] < 0.4 else (dg.PAGERANK if rng_q[i] < 0.8 else dg.TRIANGLES)
+        if kind == dg.TRIANGLES and tc_max_n is not None and n > tc_max_n:
+            kind = dg.PAGERANK
         source = int((seed * 31 + i * 17) % n)
         s2, d2, w2, _ = oracle.apply(n, s, d, w, *b)
         cur[gi] = (n, s2, d2, w2)
@@ -61,13 +65,7 @@ def run(graphs, reqs, workers, all_at_once):
     return out
 
 
-def test_serve_mix_equals_alone_and_oracle():
-    graphs = make_graphs(6, 3)
-    reqs = make_requests(graphs, 40, 5)
-    say("serve alone")
-    alone = run(graphs, reqs, workers=1, all_at_once=False)
-    say("serve mix")
-    mix = run(graphs, reqs, workers=4, all_at_once=True)
+def check_answers(reqs, alone, mix):
     for i, ((gi, kind, src, b, (n, s2, d2, w2)), (ra, oa), (rm, om)) in enumerate(zip(reqs, alone, mix)):
         assert ra.status == 0 and rm.status == 0, i
         if kind == dg.SSSP:
@@ -82,6 +80,30 @@ def test_serve_mix_equals_alone_and_oracle():
             want = oracle.triangles(n, u, v)
             assert ra.tc == want and rm.tc == want, i
         assert ra.t_submit <= ra.t_start <= ra.t_end
+
+
+def test_serve_mix_equals_alone_and_oracle():
+    graphs = make_graphs(6, 3)
+    reqs = make_requests(graphs, 40, 5)
+    say("serve alone")
+    alone = run(graphs, reqs, workers=1, all_at_once=False)
+    say("serve mix")
+    mix = run(graphs, reqs, workers=4, all_at_once=True)
+    check_answers(reqs, alone, mix)
+
+
+def test_serve_config_sizes_sample():
+    """The serving workload's shapes on a sample of its graphs: R-MAT scales 12,
+    15, 17 and 20 with 16 arcs per vertex, batches log-uniform in [100, 10^5],
+    query kinds 40/40/20 (triangles on the graphs up to scale 17)."""
+    graphs = [graphgen.rmat_directed(sc, 16 << sc, graphgen.config_seed(4, 50 + sc)) for sc in (12, 15, 17, 20)]
+    reqs = make_requests(graphs, 14, 6, kmin=100, kmax=100000, tc_max_n=1 << 17)
+    say("serve at the workload's sizes: batches", [len(r[3][0]) for r in reqs], "kinds", [r[1] for r in reqs])
+    alone = run(graphs, reqs, workers=1, all_at_once=False)
+    say("serve at the workload's sizes, mixed")
+    mix = run(graphs, reqs, workers=4, all_at_once=True)
+    say("oracle answers")
+    check_answers(reqs, alone, mix)
 
 
 def test_serve_admission_errors():

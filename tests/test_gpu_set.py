@@ -67,6 +67,32 @@ def test_set_matches_oracle_over_batches(mode):
     assert gs["launches"] == 4 * (2 if mode == 2 else 1) and 1 <= gs["captures"] <= gs["launches"]
 
 
+@pytest.mark.parametrize("mode", [2, 1])
+def test_set_members_with_empty_batches(mode):
+    """Members with no updates: a leading one, a trailing one and a run of ten in
+    the middle, with enough updates in total that the 256-entry translation blocks
+    begin inside and next to the empty members."""
+    mem = members(40, 17, 6, 9)
+    bats = member_batches(mem, 300)
+    empty = [0, *range(12, 22), 39]
+    e = (np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0, np.uint8))
+    for i in empty:
+        bats[i] = e
+    total = sum(len(b[0]) for b in bats)
+    say("set with empty member batches, mode", mode, "updates", total)
+    assert total > 4 * 256
+    c = dg.Config()
+    c.sssp_persistent = mode
+    S = dg.GraphSet(mem, config=c)
+    S.sssp_attach(np.zeros(len(mem), np.int32))
+    st = S.apply(bats)
+    assert st.updates == total
+    for i, (n, s, d, w) in enumerate(mem):
+        s2, d2, w2, _ = oracle.apply(n, s, d, w, *bats[i])
+        assert np.array_equal(S.read(i)[0], oracle.sssp(n, s2, d2, w2, 0)), i
+    S.close()
+
+
 def test_set_member_equals_alone():
     mem = members(6, 12, 8, 10)
     say("set vs alone")
