@@ -412,16 +412,22 @@ __global__ void k_stamp_all(const int32_t *a, int64_t n, int32_t *stamp, int32_t
     for (int64_t i = gtid(); i < n; i += gstride()) stamp[a[i]] = st;
 }
 
-// Hop levels of a breadth-first search from the ns sources in f0, up to
+// Hop levels of a breadth-first search from the ns sources in srcs, up to
 // `limit` levels: *deep = true when vertices are still being discovered after it.
-static int hop_depth_exceeds(dg_graph *g, int64_t ns, int limit, bool *deep) {
+// The levels alternate between the near-far pile buffers (idle during a static
+// solve), so srcs -- which may be the frontier buffer f0 -- is only read.
+static int hop_depth_exceeds(dg_graph *g, const int32_t *srcs, int64_t ns, int limit, bool *deep) {
     hipStream_t s = g->stream;
     Work &ws = g->ws;
+    const size_t cap = (size_t)g->n + 1;
+    DG_TRY(ws.far0.ensure(cap));
+    DG_TRY(ws.far1.ensure(cap));
     int32_t st;
     DG_TRY(next_stamp(g, &st));
-    hipLaunchKernelGGL(k_stamp_all, dim3(grid_for(ns)), dim3(256), 0, s, ws.f0.p, ns, ws.stamp.p, st);
+    hipLaunchKernelGGL(k_stamp_all, dim3(grid_for(ns)), dim3(256), 0, s, srcs, ns, ws.stamp.p, st);
     DG_HIP(hipGetLastError());
-    int32_t *F = ws.f0.p, *N = ws.f1.p;
+    DG_HIP(hipMemcpyAsync(ws.far0.p, srcs, (size_t)ns * 4, hipMemcpyDeviceToDevice, s));
+    int32_t *F = ws.far0.p, *N = ws.far1.p;
     int64_t nf = ns;
     int level = 0;
     while (nf > 0 && level < limit) {
@@ -446,10 +452,8 @@ int sssp_static_multi(dg_graph *g, uint64_t *key, const int32_t *srcs, int64_t n
     hipLaunchKernelGGL(k_sssp_set_sources, dim3(grid_for(ns)), dim3(256), 0, s, srcs, ns, key);
     DG_HIP(hipGetLastError());
     if (g->cfg.sssp_persistent == 1) {
-        if (srcs != g->ws.f0.p)
-            DG_HIP(hipMemcpyAsync(g->ws.f0.p, srcs, (size_t)ns * 4, hipMemcpyDeviceToDevice, s));
         bool deep = false;
-        DG_TRY(hop_depth_exceeds(g, ns, WL_MAX_DEPTH, &deep));
+        DG_TRY(hop_depth_exceeds(g, srcs, ns, WL_MAX_DEPTH, &deep));
         if (deep)
             return set_error(DG_EINVAL, "work-queue schedule refused: shortest-path trees deeper than %d hops "
                                         "(FIFO relaxation would repeat work on such a graph); use "
