@@ -228,6 +228,35 @@ int dg_pr_read(dg_query *q, double *rank, int32_t *iters, int32_t *converged, ui
 
 int dg_tc_read(dg_query *q, uint64_t *count);
 
+/* ---- checkpoint / resume of query state ---------------------------------------------- */
+
+/* Serialise an attached query of a single graph (not of a set) into a host byte
+ * buffer that dg_query_import accepts, also in another process, on a graph
+ * re-created from dg_graph_export's edge list (the paper maintains these values
+ * across batches, Section "StarPlat Dynamic: Programming Model"; saving them lets
+ * that maintenance resume without a static recompute).  Contents, all in the
+ * caller's vertex ids: a 64-byte header (kind, n, live edge count, parameters,
+ * iteration count, triangle count) and then SSSP dist[n] and parent[n] (int32),
+ * PageRank x[n] (double: the unnormalised values the Jacobi iteration keeps,
+ * rank = x / sum(x)), or nothing for triangles.  Call with buf == NULL to get the
+ * size in *bytes; otherwise *bytes holds the capacity on entry (DG_EINVAL if too
+ * small) and receives the size written.  The caller owns buf. */
+int dg_query_export(dg_query *q, void *buf, int64_t *bytes);
+
+/* Attach a query to g from an exported buffer (host memory, read only during the
+ * call), without the static solve.  DG_EINVAL, with nothing attached, when the
+ * buffer is not an export, or its n or live edge count differ from g's, or:
+ *   - SSSP: the distances and parents are not the shortest-path solution of g
+ *     from the source (checked in one pass over g's arcs: no arc improves a
+ *     distance, and every reachable vertex has a tight arc from its parent);
+ *   - PageRank: a value is negative or not finite.  The values are a warm start:
+ *     the Jacobi iteration runs until its L1 step meets the tolerance again (one
+ *     step for a state exported from this edge set);
+ *   - triangles: g is directed.  The count is taken as given, so it must come
+ *     from an export of the same edge set.
+ * On success *q is attached as by dg_*_attach. */
+int dg_query_import(dg_graph *g, const void *buf, int64_t bytes, dg_query **q);
+
 /* ---- batched sets of independent graphs ------------------------------------------------ */
 
 /* Many independent directed graphs kept as one device-resident store and updated
@@ -365,6 +394,16 @@ int dg_profile_reset(void);
 int dg_profile_read(dg_kernel_prof *out, int32_t cap, int32_t *count);
 
 /* ---- static recompute on the current graph (comparators) -------------------------- */
+
+/* The "static" baseline of the paper's Experimental Evaluation section: the
+ * updates are applied first and the property is then computed from scratch on
+ * the updated graph (staticSSSP, staticPR and staticTC of Appendix A).  These
+ * calls do the from-scratch part on the graph as it stands and leave attached
+ * queries untouched.  dg_sssp_static: distances and parents from source, as
+ * dg_sssp_read (flags: DG_DEVICE_PTRS).  dg_pr_static: Jacobi from 1/n to the L1
+ * tolerance, ranks normalised as dg_pr_read, iterations in *iters (nullable).
+ * dg_tc_static: undirected graphs only; merges the diff level first, then counts
+ * each triangle once at its lowest-ranked vertex (forward algorithm). */
 
 int dg_sssp_static(dg_graph *g, int32_t source, int32_t *dist, int32_t *parent, uint32_t flags);
 int dg_pr_static(dg_graph *g, double damping, double tol, int32_t max_iter, double *rank,

@@ -39,6 +39,7 @@ EXPORTS = (
     "dg_graph_set_stream", "dg_graph_info", "dg_graph_export", "dg_graph_merge",
     "dg_apply_batch", "dg_snapshot_save", "dg_snapshot_restore", "dg_snapshot_free",
     "dg_sssp_attach", "dg_pr_attach", "dg_tc_attach", "dg_query_detach", "dg_sssp_read",
+    "dg_query_export", "dg_query_import",
     "dg_pr_read", "dg_tc_read", "dg_sssp_static", "dg_pr_static", "dg_tc_static",
     "dg_profile_enable", "dg_profile_reset", "dg_profile_read",
     "dg_set_create", "dg_set_destroy", "dg_set_info", "dg_set_sssp_attach", "dg_set_apply_sssp",
@@ -126,6 +127,8 @@ def load_library() -> ctypes.CDLL:
         "dg_sssp_read": ([P, P, P, U32], ctypes.c_int),
         "dg_pr_read": ([P, P, P, P, U32], ctypes.c_int),
         "dg_tc_read": ([P, P], ctypes.c_int),
+        "dg_query_export": ([P, P, P], ctypes.c_int),
+        "dg_query_import": ([P, P, I64, ctypes.POINTER(P)], ctypes.c_int),
         "dg_sssp_static": ([P, I32, P, P, U32], ctypes.c_int),
         "dg_pr_static": ([P, D, D, I32, P, P, U32], ctypes.c_int),
         "dg_tc_static": ([P, P], ctypes.c_int),
@@ -220,6 +223,68 @@ def dg_profile_read() -> dict:
             for i in range(min(cnt.value, 64))}
 
 
+# ---------------------------------------------------------------------------- allocator
+
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+_hook = None
+
+
+class TorchAllocatorHook:
+    """dg_set_allocator callbacks that take the library's device memory from
+    torch's caching allocator (on the current device and stream).  A free first
+    waits for the device, as hipFree does, because the library may free a buffer
+    that queued kernels still use.  Counts allocations, frees and live bytes."""
+
+    def __init__(self):
+        import torch
+
+        self._torch = torch
+        self.allocs = 0
+        self.frees = 0
+        self._live = {}
+        self.c_alloc = _ALLOC_FN(self._alloc)
+        self.c_free = _FREE_FN(self._free)
+
+    def _alloc(self, nbytes, _ctx):
+        try:
+            p = self._torch.cuda.caching_allocator_alloc(int(nbytes))
+        except Exception:
+            return None
+        self.allocs += 1
+        self._live[int(p)] = int(nbytes)
+        return p
+
+    def _free(self, p, _ctx):
+        if not p:
+            return
+        self._torch.cuda.synchronize()
+        self._torch.cuda.caching_allocator_delete(int(p))
+        self.frees += 1
+        self._live.pop(int(p), None)
+
+    def live_bytes(self) -> int:
+        return sum(self._live.values())
+
+
+def use_torch_allocator() -> TorchAllocatorHook:
+    """Route every device allocation of the library through torch's caching
+    allocator (dg_set_allocator; only while no graph, set or server exists)."""
+    global _hook
+    h = TorchAllocatorHook()
+    _check(load_library().dg_set_allocator(ctypes.cast(h.c_alloc, ctypes.c_void_p),
+                                           ctypes.cast(h.c_free, ctypes.c_void_p), None))
+    _hook = h  # the callbacks must outlive their use
+    return h
+
+
+def use_default_allocator() -> None:
+    """Back to hipMalloc / hipFree (only while no graph, set or server exists)."""
+    global _hook
+    _check(load_library().dg_set_allocator(None, None, None))
+    _hook = None
+
+
 # ---------------------------------------------------------------------------- classes
 
 class Query:
@@ -253,6 +318,15 @@ class Query:
         c = ctypes.c_uint64()
         _check(lib.dg_tc_read(self.handle, ctypes.byref(c)))
         return int(c.value)
+
+    def export(self) -> bytes:
+        """The query's state as bytes (dg_query_export), for Graph.import_query."""
+        lib = load_library()
+        size = ctypes.c_int64()
+        _check(lib.dg_query_export(self.handle, None, ctypes.byref(size)))
+        buf = ctypes.create_string_buffer(size.value)
+        _check(lib.dg_query_export(self.handle, buf, ctypes.byref(size)))
+        return buf.raw[:size.value]
 
     def detach(self):
         if self.handle:
@@ -348,6 +422,13 @@ class Graph:
         q = ctypes.c_void_p()
         _check(load_library().dg_tc_attach(self.handle, ctypes.byref(q)))
         return Query(self, q, "tc")
+
+    def import_query(self, blob: bytes) -> Query:
+        """Attach a query from Query.export() bytes (dg_query_import)."""
+        q = ctypes.c_void_p()
+        _check(load_library().dg_query_import(self.handle, blob, len(blob), ctypes.byref(q)))
+        kind = {1: "sssp", 2: "pr", 3: "tc"}[int.from_bytes(blob[4:8], "little")]
+        return Query(self, q, kind)
 
     def sssp_static(self, source: int):
         dist = np.empty(self.n, np.int32)

@@ -394,6 +394,116 @@ int dg_query_detach(dg_query *q) {
     return DG_OK;
 }
 
+// ---- checkpoint / resume of query state ---------------------------------------------------
+
+namespace {
+// Host byte layout of an exported query: this header, then the payload (SSSP:
+// int32 dist[n] and int32 parent[n]; PageRank: double x[n]; triangles: none),
+// everything in the caller's vertex ids.
+struct QueryBlob {
+    uint32_t magic;
+    int32_t kind;
+    int32_t n;
+    int32_t source;     // SSSP: caller's id
+    int64_t m_live;     // live edges of the graph at export
+    double damping, tol;
+    int32_t max_iter, last_iters, converged, reserved;
+    uint64_t tc;
+};
+constexpr uint32_t BLOB_MAGIC = 0x31515344u;  // "DSQ1"
+
+int64_t blob_payload(int kind, int32_t n) {
+    return kind == Q_SSSP ? 8 * (int64_t)n : (kind == Q_PR ? 8 * (int64_t)n : 0);
+}
+}  // namespace
+
+int dg_query_export(dg_query *q, void *buf, int64_t *bytes) {
+    if (!q || !bytes) return set_error(DG_EINVAL, "null query or size");
+    dg_graph *g = q->g;
+    DG_TRY(check_graph(g));
+    if (q->nsrc > 0) return set_error(DG_EINVAL, "queries of a graph set are not exported");
+    const int64_t need = (int64_t)sizeof(QueryBlob) + blob_payload(q->kind, g->n);
+    if (!buf) {
+        *bytes = need;
+        return DG_OK;
+    }
+    if (*bytes < need) return set_error(DG_EINVAL, "export buffer holds %lld bytes, %lld needed",
+                                        (long long)*bytes, (long long)need);
+    QueryBlob h{};
+    h.magic = BLOB_MAGIC;
+    h.kind = q->kind;
+    h.n = g->n;
+    h.m_live = g->undirected ? g->m_live / 2 : g->m_live;
+    h.damping = q->damping;
+    h.tol = q->tol;
+    h.max_iter = q->max_iter;
+    h.last_iters = q->last_iters;
+    h.converged = q->converged;
+    h.tc = q->tc;
+    h.source = q->source;
+    if (q->kind == Q_SSSP && g->relabeled) {
+        int32_t c = 0;
+        DG_HIP(hipMemcpy(&c, g->iperm.p + q->source, 4, hipMemcpyDeviceToHost));
+        h.source = c;
+    }
+    char *out = static_cast<char *>(buf);
+    std::memcpy(out, &h, sizeof(h));
+    int rc = DG_OK;
+    if (q->kind == Q_SSSP) {
+        int32_t *dist = reinterpret_cast<int32_t *>(out + sizeof(h));
+        rc = sssp_read(q, dist, dist + g->n, false);
+    } else if (q->kind == Q_PR) {
+        rc = pr_export(q, reinterpret_cast<double *>(out + sizeof(h)));
+    }
+    if (rc == DG_OK) *bytes = need;
+    return mark_device_error(g, rc);
+}
+
+int dg_query_import(dg_graph *g, const void *buf, int64_t bytes, dg_query **q) {
+    DG_TRY(check_graph(g));
+    if (!buf || !q || bytes < (int64_t)sizeof(QueryBlob)) return set_error(DG_EINVAL, "bad import arguments");
+    QueryBlob h;
+    std::memcpy(&h, buf, sizeof(h));
+    if (h.magic != BLOB_MAGIC || (h.kind != Q_SSSP && h.kind != Q_PR && h.kind != Q_TC))
+        return set_error(DG_EINVAL, "not an exported query");
+    if (bytes < (int64_t)sizeof(QueryBlob) + blob_payload(h.kind, h.n))
+        return set_error(DG_EINVAL, "import buffer shorter than its query");
+    const int64_t m_live = g->undirected ? g->m_live / 2 : g->m_live;
+    if (h.n != g->n || h.m_live != m_live)
+        return set_error(DG_EINVAL, "query exported from another graph (n %d, %lld edges; this graph: n %d, %lld "
+                                    "edges)", h.n, (long long)h.m_live, g->n, (long long)m_live);
+    const char *payload = static_cast<const char *>(buf) + sizeof(h);
+    dg_query *x = new dg_query();
+    x->g = g;
+    x->kind = static_cast<QueryKind>(h.kind);
+    int rc = DG_OK;
+    if (h.kind == Q_SSSP) {
+        if (h.source < 0 || h.source >= g->n) rc = set_error(DG_EINVAL, "bad source in the import");
+        int32_t iv = h.source;
+        if (rc == DG_OK) rc = vertex_in(g, h.source, &iv);
+        x->source = iv;
+        const int32_t *dist = reinterpret_cast<const int32_t *>(payload);
+        if (rc == DG_OK) rc = sssp_import(x, dist, dist + g->n);
+    } else if (h.kind == Q_PR) {
+        if (!(h.damping > 0.0 && h.damping < 1.0) || !(h.tol > 0.0) || h.max_iter < 1)
+            rc = set_error(DG_EINVAL, "bad PageRank parameters in the import");
+        x->damping = h.damping;
+        x->tol = h.tol;
+        x->max_iter = h.max_iter;
+        if (rc == DG_OK) rc = pr_import(x, reinterpret_cast<const double *>(payload));
+    } else {
+        if (!g->undirected) rc = set_error(DG_EINVAL, "triangle counting needs an undirected graph");
+        x->tc = h.tc;
+    }
+    if (rc != DG_OK) {
+        query_free(x);
+        return mark_device_error(g, rc);
+    }
+    g->queries.push_back(x);
+    *q = x;
+    return DG_OK;
+}
+
 int dg_sssp_read(dg_query *q, int32_t *dist, int32_t *parent, uint32_t flags) {
     if (!q || q->kind != Q_SSSP) return set_error(DG_EINVAL, "not a shortest-path query");
     DG_TRY(check_graph(q->g));

@@ -251,6 +251,9 @@ int sssp_pre_delete(dg_query *q, int64_t n_applied_del);
 int sssp_post_update(dg_query *q, int64_t n_applied_del, int64_t n_applied_ins, dg_batch_stats *st);
 int sssp_read(dg_query *q, int32_t *dist, int32_t *parent, bool dev);
 int sssp_unpack(dg_graph *g, const uint64_t *key, int32_t *dist, int32_t *parent, hipStream_t s);
+// Checkpoint/resume: keys from host (dist, parent) in the caller's ids, checked
+// against the current graph (DG_EINVAL unless they are its shortest paths).
+int sssp_import(dg_query *q, const int32_t *dist, const int32_t *parent);
 
 // handles (capi.hip)
 int graph_create_dev(int32_t n, int64_t m, const int32_t *ds, const int32_t *dd, const int32_t *dw,
@@ -300,6 +303,10 @@ int pr_post_update(dg_query *q, int64_t n_applied_del, int64_t n_applied_ins, dg
                    SideWork *side = nullptr);
 int pr_read(dg_query *q, double *rank, bool dev);
 int pr_normalize(dg_graph *g, const double *x, double *rank, bool dev);
+// Checkpoint/resume: x in the caller's order to and from host memory; an import
+// converges from the given values (one step when they are already converged).
+int pr_export(dg_query *q, double *x);
+int pr_import(dg_query *q, const double *x);
 
 // launch timing (prof.hip)
 bool prof_on();

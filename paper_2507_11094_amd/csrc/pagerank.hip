@@ -747,6 +747,26 @@ int pr_init(dg_query *q) {
 
 static int pr_update(dg_query *q, int64_t adel, int64_t ains, dg_batch_stats *st, SideWork *side);
 
+// *S = sum(x) of the query's current values (fixed block order, so deterministic).
+static int pr_mass(dg_query *q, double *S) {
+    dg_graph *g = q->g;
+    hipStream_t s = g->stream;
+    Work &ws = g->ws;
+    const int64_t qcap = 2 * (std::max(g->fwd.m + g->fwd.dm, g->rev->m + g->rev->dm) / heavy_deg(g) + 2) +
+                         g->n / 8 + 64;
+    double *partials = ws.part.p + qcap;
+    hipLaunchKernelGGL(k_sum_vec2, dim3(APPLY_GROUPS), dim3(256), 0, s, q->x.p, g->fwd.deg.p, (int64_t)g->n,
+                       partials);
+    hipLaunchKernelGGL(k_pr_reduce, dim3(1), dim3(256), 0, s, partials, APPLY_GROUPS, 0, 0.0, q->damping, 1.0,
+                       0.0, 1, ws.prs.p, ws.prs.p + 5);
+    DG_HIP(hipGetLastError());
+    // prs[0] here holds the plain sum (first partial of each pair)
+    DG_HIP(hipMemcpyAsync(ws.hcnt + C_COUNT, ws.prs.p, sizeof(double), hipMemcpyDeviceToHost, s));
+    DG_HIP(hipStreamSynchronize(s));
+    std::memcpy(S, ws.hcnt + C_COUNT, sizeof(double));
+    return DG_OK;
+}
+
 int pr_post_update(dg_query *q, int64_t adel, int64_t ains, dg_batch_stats *st, SideWork *side) {
     const int rc = pr_update(q, adel, ains, st, side);
     if (side) {
@@ -870,18 +890,7 @@ static int pr_update(dg_query *q, int64_t adel, int64_t ains, dg_batch_stats *st
     // normalised ranks x / S, so the tolerance on x is tol * S (the global form
     // also conserves S).
     double Ssum;
-    {
-        double *partials = ws.part.p + qcap;
-        hipLaunchKernelGGL(k_sum_vec2, dim3(APPLY_GROUPS), dim3(256), 0, s, q->x.p, g->fwd.deg.p,
-                           (int64_t)g->n, partials);
-        hipLaunchKernelGGL(k_pr_reduce, dim3(1), dim3(256), 0, s, partials, APPLY_GROUPS, 0, 0.0, q->damping,
-                           1.0, 0.0, 1, ws.prs.p, ws.prs.p + 5);
-        DG_HIP(hipGetLastError());
-        // prs[0] here holds the plain sum (first partial of each pair)
-        DG_HIP(hipMemcpyAsync(ws.hcnt + C_COUNT, ws.prs.p, sizeof(double), hipMemcpyDeviceToHost, s));
-        DG_HIP(hipStreamSynchronize(s));
-        std::memcpy(&Ssum, ws.hcnt + C_COUNT, sizeof(double));
-    }
+    DG_TRY(pr_mass(q, &Ssum));
     if (global) {
         na = g->n;
         edges = all_edges;
@@ -929,5 +938,77 @@ int pr_normalize(dg_graph *g, const double *x, double *rank, bool dev) {
 }
 
 int pr_read(dg_query *q, double *rank, bool dev) { return pr_normalize(q->g, q->x.p, rank, dev); }
+
+// ---- checkpoint / resume -----------------------------------------------------------------
+// The exported state is x itself (the dangling-dropped system's unnormalised
+// values) in the caller's vertex order.  An import takes any non-negative finite x
+// as a warm start and runs the global form until the L1 step meets the tolerance,
+// so a state exported from this graph resumes after one confirming step, and any
+// other start still converges to the same ranks.
+
+// x[perm[c]] = X[c], contrib = x / outdeg; *bad counts negative or non-finite values.
+__global__ void k_pr_import(int32_t n, const double *X, const int32_t *perm, const int32_t *deg, double *x,
+                            double *contrib, int64_t *bad) {
+    int64_t nbad = 0;
+    for (int64_t c = gtid(); c < n; c += gstride()) {
+        double v = X[c];
+        if (!(v >= 0.0 && v <= 1.0e300)) {
+            ++nbad;
+            v = 0.0;
+        }
+        const int64_t i = perm ? perm[c] : c;
+        x[i] = v;
+        contrib[i] = deg[i] > 0 ? v / (double)deg[i] : 0.0;
+    }
+    nbad = wave_sum(nbad);
+    if (lane_id() == 0 && nbad) atomicAdd((unsigned long long *)bad, (unsigned long long)nbad);
+}
+
+__global__ void k_pr_export(int32_t n, const double *x, const int32_t *perm, double *X) {
+    for (int64_t c = gtid(); c < n; c += gstride()) X[c] = x[perm ? perm[c] : c];
+}
+
+int pr_export(dg_query *q, double *xh) {
+    dg_graph *g = q->g;
+    hipStream_t s = g->stream;
+    DG_TRY(g->ws.rbuf.ensure((size_t)g->n + 1));
+    hipLaunchKernelGGL(k_pr_export, dim3(grid_for(g->n)), dim3(256), 0, s, g->n, q->x.p,
+                       g->relabeled ? (const int32_t *)g->perm.p : nullptr, g->ws.rbuf.p);
+    DG_HIP(hipGetLastError());
+    DG_HIP(hipMemcpyAsync(xh, g->ws.rbuf.p, (size_t)g->n * sizeof(double), hipMemcpyDeviceToHost, s));
+    DG_HIP(hipStreamSynchronize(s));
+    return DG_OK;
+}
+
+int pr_import(dg_query *q, const double *xh) {
+    dg_graph *g = q->g;
+    hipStream_t s = g->stream;
+    DG_TRY(q->x.ensure((size_t)g->n + 1));
+    DG_TRY(q->xn.ensure((size_t)g->n + 1));
+    DG_TRY(q->contrib.ensure((size_t)g->n + 1));
+    DG_TRY(ensure_pr_ws(g));
+    DG_TRY(g->ws.rbuf.ensure((size_t)g->n + 1));
+    DG_HIP(hipMemcpyAsync(g->ws.rbuf.p, xh, (size_t)g->n * sizeof(double), hipMemcpyHostToDevice, s));
+    DG_TRY(counters_clear(g));
+    hipLaunchKernelGGL(k_pr_import, dim3(grid_for(g->n)), dim3(256), 0, s, g->n, g->ws.rbuf.p,
+                       g->relabeled ? (const int32_t *)g->perm.p : nullptr, g->fwd.deg.p, q->x.p, q->contrib.p,
+                       g->ws.dcnt + C_AUX0);
+    DG_HIP(hipGetLastError());
+    DG_TRY(counters_read(g));
+    if (g->ws.hcnt[C_AUX0] != 0)
+        return set_error(DG_EINVAL, "imported PageRank state: %lld negative or non-finite values",
+                         (long long)g->ws.hcnt[C_AUX0]);
+    double Ssum = 0.0;
+    DG_TRY(pr_mass(q, &Ssum));
+    if (!(Ssum > 0.0)) return set_error(DG_EINVAL, "imported PageRank state sums to zero");
+    int32_t iters = 0, conv = 0;
+    DG_TRY(pr_iterate(g, nullptr, g->n, g->rev->m + g->rev->dm, q->damping, tol_of(q) * Ssum, q->max_iter, true,
+                      Ssum, q->x.p, q->xn.p, q->contrib.p, &iters, &conv));
+    q->last_iters = iters;
+    q->converged = conv;
+    return DG_OK;
+}
+
+
 
 }  // namespace dg

@@ -827,6 +827,95 @@ int sssp_unpack(dg_graph *g, const uint64_t *key, int32_t *dist, int32_t *parent
     return DG_OK;
 }
 
+// ---- checkpoint / resume -----------------------------------------------------------------
+// A resumed query must hold the shortest-path solution of the graph it is attached
+// to, since the dynamic update only repairs what a batch disturbs.  So an imported
+// (dist, parent) pair is packed into keys and then checked against the current
+// graph in one pass over its in-rows, which is much cheaper than a static solve:
+//   - the source has (0, -1);
+//   - no live arc u -> v with d[u] + w < INF improves on d[v] (optimality);
+//   - every other vertex with d[v] < INF has a live in-arc from parent[v] with
+//     d[parent] + w == d[v] (a tight tree arc), and every vertex with d[v] == INF
+//     has parent -1.
+// With positive weights the tight parent arcs strictly decrease d, so they form
+// a tree rooted at the source, and the pair is exactly the saturated static result.
+
+// dist/parent in the caller's ids -> keys in internal ids; *bad counts values
+// outside [0, INF] or parents outside [-1, n).
+__global__ void k_sssp_pack(int32_t n, const int32_t *dist, const int32_t *parent, const int32_t *perm,
+                            uint64_t *key, int64_t *bad) {
+    int64_t nbad = 0;
+    for (int64_t c = gtid(); c < n; c += gstride()) {
+        const int32_t d = dist[c], p = parent[c];
+        const bool ok = d >= 0 && d <= INF && p >= -1 && p < n;
+        nbad += ok ? 0 : 1;
+        const int32_t pi = ok && p >= 0 ? (perm ? perm[p] : p) : -1;
+        key[perm ? perm[c] : c] = sssp_pack(ok ? d : INF, pi);
+    }
+    nbad = wave_sum(nbad);
+    if (lane_id() == 0 && nbad) atomicAdd((unsigned long long *)bad, (unsigned long long)nbad);
+}
+
+// One wave per in-row v (grid-stride); *bad counts the rows that break a rule above.
+__global__ __launch_bounds__(256) void k_sssp_verify(int32_t n, int32_t source, DirView r, const uint64_t *key,
+                                                     int64_t *bad) {
+    const int64_t nwaves = gstride() / WAVE;
+    const int l = lane_id();
+    int64_t nbad = 0;
+    for (int64_t v = gtid() / WAVE; v < n; v += nwaves) {
+        const uint64_t kv = key[v];
+        const int64_t dv = sssp_dist(kv);
+        const int32_t pv = sssp_parent(kv);
+        bool improves = false, tight = false;
+        auto check = [&](uint32_t c, int32_t w) {
+            if (c & DEAD) return;
+            const int32_t u = (int32_t)(c & ID_MASK);
+            const int64_t du = sssp_dist(key[u]);
+            if (du >= INF) return;
+            const int64_t s = du + (int64_t)w;
+            if (s < INF && s < dv) improves = true;
+            if (u == pv && s == dv) tight = true;
+        };
+        for (int64_t e = r.off[v] + l; e < r.off[v + 1]; e += WAVE) check((uint32_t)r.col[e], r.w[e]);
+        for (int64_t e = r.doff[v] + l; e < r.doff[v + 1]; e += WAVE) check((uint32_t)r.dcol[e], r.dw[e]);
+        improves = ballot(improves) != 0;
+        tight = ballot(tight) != 0;
+        bool ok;
+        if (v == source) ok = dv == 0 && pv == -1;
+        else if (dv < INF) ok = !improves && pv >= 0 && tight;
+        else ok = !improves && pv == -1;
+        if (l == 0 && !ok) ++nbad;
+    }
+    if (l == 0 && nbad) atomicAdd((unsigned long long *)bad, (unsigned long long)nbad);
+}
+
+int sssp_import(dg_query *q, const int32_t *dist, const int32_t *parent) {
+    dg_graph *g = q->g;
+    hipStream_t s = g->stream;
+    DG_TRY(q->key.ensure((size_t)g->n + 1));
+    DG_TRY(q->inval.ensure((size_t)g->n + 1));
+    q->nseeds = 0;
+    DG_TRY(g->ws.rbuf.ensure((size_t)g->n + 1));
+    int32_t *tmp = reinterpret_cast<int32_t *>(g->ws.rbuf.p);  // 2n + 2 int32
+    DG_HIP(hipMemcpyAsync(tmp, dist, (size_t)g->n * 4, hipMemcpyHostToDevice, s));
+    DG_HIP(hipMemcpyAsync(tmp + g->n, parent, (size_t)g->n * 4, hipMemcpyHostToDevice, s));
+    DG_TRY(counters_clear(g));
+    hipLaunchKernelGGL(k_sssp_pack, dim3(grid_for(g->n)), dim3(256), 0, s, g->n, tmp, tmp + g->n,
+                       g->relabeled ? (const int32_t *)g->perm.p : nullptr, q->key.p, g->ws.dcnt + C_AUX0);
+    hipLaunchKernelGGL(k_sssp_verify, dim3(grid_for((int64_t)g->n * WAVE)), dim3(256), 0, s, g->n, q->source,
+                       view(*g->rev), q->key.p, g->ws.dcnt + C_AUX1);
+    DG_HIP(hipGetLastError());
+    DG_TRY(counters_read(g));
+    if (g->ws.hcnt[C_AUX0] != 0)
+        return set_error(DG_EINVAL, "imported shortest paths: %lld values out of range",
+                         (long long)g->ws.hcnt[C_AUX0]);
+    if (g->ws.hcnt[C_AUX1] != 0)
+        return set_error(DG_EINVAL, "imported shortest paths do not solve this graph from its source (%lld "
+                                    "vertices break optimality or tree tightness)",
+                         (long long)g->ws.hcnt[C_AUX1]);
+    return DG_OK;
+}
+
 int sssp_read(dg_query *q, int32_t *dist, int32_t *parent, bool dev) {
     dg_graph *g = q->g;
     hipStream_t s = g->stream;
