@@ -228,6 +228,18 @@ int dg_pr_read(dg_query *q, double *rank, int32_t *iters, int32_t *converged, ui
 
 int dg_tc_read(dg_query *q, uint64_t *count);
 
+/* dg_pr_read for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): same arguments
+ * and the same ranks, bit for bit, but no allocation of any kind.  Its partial
+ * sums and the staging of a host copy use a fixed 4 MiB array in device memory,
+ * one per GPU, held until the process ends.  With DG_DEVICE_PTRS any n is
+ * accepted; a host rank buffer is staged through that array, so n above
+ * DG_NOALLOC_MAX_HOST_N gives DG_EINVAL.  Calls share the array: the library
+ * runs them one at a time per process (each returns after its copy is done);
+ * other processes have their own copy. */
+#define DG_NOALLOC_MAX_HOST_N 522240
+int dg_pr_read_noalloc(dg_query *q, double *rank, int32_t *iters, int32_t *converged, uint32_t flags);
+
 /* ---- checkpoint / resume of query state ---------------------------------------------- */
 
 /* Serialise an attached query of a single graph (not of a set) into a host byte

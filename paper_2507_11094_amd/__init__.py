@@ -32,6 +32,7 @@ DG_UNDIRECTED = 1
 DG_DEVICE_PTRS = 2
 DG_INCREMENTAL = 4
 DG_DECREMENTAL = 8
+DG_NOALLOC_MAX_HOST_N = 522240
 
 # Every symbol include/dg.h declares (checked by the tests against the .so).
 EXPORTS = (
@@ -39,7 +40,7 @@ EXPORTS = (
     "dg_graph_set_stream", "dg_graph_info", "dg_graph_export", "dg_graph_merge",
     "dg_apply_batch", "dg_snapshot_save", "dg_snapshot_restore", "dg_snapshot_free",
     "dg_sssp_attach", "dg_pr_attach", "dg_tc_attach", "dg_query_detach", "dg_sssp_read",
-    "dg_query_export", "dg_query_import",
+    "dg_query_export", "dg_query_import", "dg_pr_read_noalloc",
     "dg_pr_read", "dg_tc_read", "dg_sssp_static", "dg_pr_static", "dg_tc_static",
     "dg_profile_enable", "dg_profile_reset", "dg_profile_read",
     "dg_set_create", "dg_set_destroy", "dg_set_info", "dg_set_sssp_attach", "dg_set_apply_sssp",
@@ -128,6 +129,7 @@ def load_library() -> ctypes.CDLL:
         "dg_pr_read": ([P, P, P, P, U32], ctypes.c_int),
         "dg_tc_read": ([P, P], ctypes.c_int),
         "dg_query_export": ([P, P, P], ctypes.c_int),
+        "dg_pr_read_noalloc": ([P, P, P, P, U32], ctypes.c_int),
         "dg_query_import": ([P, P, I64, ctypes.POINTER(P)], ctypes.c_int),
         "dg_sssp_static": ([P, I32, P, P, U32], ctypes.c_int),
         "dg_pr_static": ([P, D, D, I32, P, P, U32], ctypes.c_int),

@@ -520,6 +520,16 @@ int dg_pr_read(dg_query *q, double *rank, int32_t *iters, int32_t *converged, ui
     return mark_device_error(q->g, pr_read(q, rank, (flags & DG_DEVICE_PTRS) != 0));
 }
 
+int dg_pr_read_noalloc(dg_query *q, double *rank, int32_t *iters, int32_t *converged, uint32_t flags) {
+    if (!q || q->kind != Q_PR) return set_error(DG_EINVAL, "not a PageRank query");
+    DG_TRY(check_graph(q->g));
+    if (!rank) return set_error(DG_EINVAL, "null rank");
+    if (flags & ~DG_DEVICE_PTRS) return set_error(DG_EINVAL, "unknown flags");
+    if (iters) *iters = q->last_iters;
+    if (converged) *converged = q->converged;
+    return mark_device_error(q->g, pr_read_noalloc(q, rank, (flags & DG_DEVICE_PTRS) != 0));
+}
+
 int dg_tc_read(dg_query *q, uint64_t *count) {
     if (!q || q->kind != Q_TC || !count) return set_error(DG_EINVAL, "not a triangle-count query");
     *count = q->tc;

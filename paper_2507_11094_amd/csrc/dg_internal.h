@@ -306,6 +306,8 @@ int pr_normalize(dg_graph *g, const double *x, double *rank, bool dev);
 // Checkpoint/resume: x in the caller's order to and from host memory; an import
 // converges from the given values (one step when they are already converged).
 int pr_export(dg_query *q, double *x);
+// pr_read without any device allocation (fixed per-device scratch array).
+int pr_read_noalloc(dg_query *q, double *rank, bool dev);
 int pr_import(dg_query *q, const double *x);
 
 // launch timing (prof.hip)

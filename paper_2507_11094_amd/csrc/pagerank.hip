@@ -36,6 +36,7 @@
 //          can continue locally.
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "traverse.h"
@@ -938,6 +939,63 @@ int pr_normalize(dg_graph *g, const double *x, double *rank, bool dev) {
 }
 
 int pr_read(dg_query *q, double *rank, bool dev) { return pr_normalize(q->g, q->x.p, rank, dev); }
+
+// ---- reading ranks without allocating -------------------------------------------------
+// The same normalisation as pr_normalize, for callers that cannot allocate device
+// memory: the partial sums, their total and the staging of a host copy live in a
+// fixed array in device memory, one copy per GPU, held until the process ends.
+// Layout (doubles): [0, APPLY_GROUPS) partial sums, [APPLY_GROUPS] the total,
+// [NOALLOC_STAGE, NOALLOC_DOUBLES) staging of a host copy.
+constexpr int64_t NOALLOC_DOUBLES = 1 << 19;  // 4 MiB
+constexpr int64_t NOALLOC_STAGE = 2048;
+static_assert(NOALLOC_DOUBLES - NOALLOC_STAGE == DG_NOALLOC_MAX_HOST_N, "header limit matches the scratch");
+static_assert(APPLY_GROUPS + 1 <= NOALLOC_STAGE, "partials fit below the staging area");
+static __device__ __align__(256) double scratch[NOALLOC_DOUBLES];
+
+constexpr int MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;       // one call at a time per process: calls share the array
+static double *g_scratch_ptr[MAX_DEVICES] = {};
+
+// Device address of this GPU's copy of `scratch` (looked up once per device, with
+// that device current; the array's host-side name is not a device address).
+static int scratch_of_current_device(double **out) {
+    int dev = 0;
+    DG_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_DEVICES) return set_error(DG_EDEVICE, "device %d beyond the scratch table", dev);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return set_error(DG_EDEVICE, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+        g_scratch_ptr[dev] = static_cast<double *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return DG_OK;
+}
+
+int pr_read_noalloc(dg_query *q, double *rank, bool dev) {
+    dg_graph *g = q->g;
+    if (!dev && (int64_t)g->n > DG_NOALLOC_MAX_HOST_N)
+        return set_error(DG_EINVAL, "no-allocation read into host memory holds at most %lld ranks (n = %d); pass "
+                                    "a device buffer with DG_DEVICE_PTRS",
+                         (long long)DG_NOALLOC_MAX_HOST_N, g->n);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    double *sp = nullptr;
+    DG_TRY(scratch_of_current_device(&sp));
+    hipStream_t s = g->stream;
+    const int32_t *perm = g->relabeled ? g->perm.p : nullptr;
+    // every slot the kernels read is written first in this call (partials by
+    // k_sum_vec, the total by k_sum_partials), so nothing needs clearing
+    hipLaunchKernelGGL(k_sum_vec, dim3(APPLY_GROUPS), dim3(256), 0, s, q->x.p, (int64_t)g->n, sp);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, sp, APPLY_GROUPS, sp + APPLY_GROUPS);
+    double *out = dev ? rank : sp + NOALLOC_STAGE;
+    hipLaunchKernelGGL(k_scale, dim3(grid_for(g->n)), dim3(256), 0, s, q->x.p, perm, (int64_t)g->n,
+                       sp + APPLY_GROUPS, out);
+    DG_HIP(hipGetLastError());
+    if (!dev) DG_HIP(hipMemcpyAsync(rank, out, (size_t)g->n * sizeof(double), hipMemcpyDeviceToHost, s));
+    DG_HIP(hipStreamSynchronize(s));
+    return DG_OK;
+}
 
 // ---- checkpoint / resume -----------------------------------------------------------------
 // The exported state is x itself (the dangling-dropped system's unnormalised
