@@ -405,6 +405,26 @@ int dg_profile_reset(void);
  * number of kernels with totals. */
 int dg_profile_read(dg_kernel_prof *out, int32_t cap, int32_t *count);
 
+/* ---- sort and scan primitives (device memory) ---------------------------------------- */
+
+/* The primitives the batch canonicalisation and the CSR maintenance are built on
+ * (the sorted update batches that updateCSRDel / updateCSRAdd consume, Section
+ * "Modified Graph Representation: diff-CSR"), exposed for callers and tests.
+ * All pointers are device memory; work runs on `stream` (NULL: null stream) and
+ * the call returns when it is done.  Calls are serialised within the process
+ * (they share one workspace, allocated on first use and grown as needed).
+ *
+ * dg_sort_pairs: stable sort of n (key, value) pairs by the low `bits` bits of the
+ * keys (1..64; higher bits are ignored for ordering but kept), least significant
+ * digit first.  kin/vin are not modified; kout/vout receive the sorted pairs and
+ * must not alias the inputs.  n < 2^31.
+ *
+ * dg_scan_exclusive: out[i] = in[0] + ... + in[i-1] for non-negative values whose
+ * total stays below 2^48; out may equal in. */
+int dg_sort_pairs(const uint64_t *kin, uint64_t *kout, const int32_t *vin, int32_t *vout, int64_t n, int32_t bits,
+                  void *stream);
+int dg_scan_exclusive(const int64_t *in, int64_t *out, int64_t n, void *stream);
+
 /* ---- static recompute on the current graph (comparators) -------------------------- */
 
 /* The "static" baseline of the paper's Experimental Evaluation section: the

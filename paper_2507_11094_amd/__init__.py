@@ -40,7 +40,7 @@ EXPORTS = (
     "dg_graph_set_stream", "dg_graph_info", "dg_graph_export", "dg_graph_merge",
     "dg_apply_batch", "dg_snapshot_save", "dg_snapshot_restore", "dg_snapshot_free",
     "dg_sssp_attach", "dg_pr_attach", "dg_tc_attach", "dg_query_detach", "dg_sssp_read",
-    "dg_query_export", "dg_query_import", "dg_pr_read_noalloc",
+    "dg_query_export", "dg_query_import", "dg_pr_read_noalloc", "dg_sort_pairs", "dg_scan_exclusive",
     "dg_pr_read", "dg_tc_read", "dg_sssp_static", "dg_pr_static", "dg_tc_static",
     "dg_profile_enable", "dg_profile_reset", "dg_profile_read",
     "dg_set_create", "dg_set_destroy", "dg_set_info", "dg_set_sssp_attach", "dg_set_apply_sssp",
@@ -130,6 +130,8 @@ def load_library() -> ctypes.CDLL:
         "dg_tc_read": ([P, P], ctypes.c_int),
         "dg_query_export": ([P, P, P], ctypes.c_int),
         "dg_pr_read_noalloc": ([P, P, P, P, U32], ctypes.c_int),
+        "dg_sort_pairs": ([P, P, P, P, I64, I32, P], ctypes.c_int),
+        "dg_scan_exclusive": ([P, P, I64, P], ctypes.c_int),
         "dg_query_import": ([P, P, I64, ctypes.POINTER(P)], ctypes.c_int),
         "dg_sssp_static": ([P, I32, P, P, U32], ctypes.c_int),
         "dg_pr_static": ([P, D, D, I32, P, P, U32], ctypes.c_int),
@@ -223,6 +225,30 @@ def dg_profile_read() -> dict:
     _check(lib.dg_profile_read(buf, 64, ctypes.byref(cnt)))
     return {buf[i].name.decode(): {"launches": buf[i].launches, "ms": buf[i].ms, "bytes": buf[i].bytes}
             for i in range(min(cnt.value, 64))}
+
+
+def dg_sort_pairs(keys, vals, bits=64):
+    """Stable radix sort of device tensors (uint64 keys as int64, int32 values) by
+    the low `bits` bits of the keys; returns new (keys, values) tensors."""
+    import torch
+
+    n = int(keys.numel())
+    ko = torch.empty_like(keys)
+    vo = torch.empty_like(vals)
+    _check(load_library().dg_sort_pairs(ctypes.c_void_p(keys.data_ptr()), ctypes.c_void_p(ko.data_ptr()),
+                                        ctypes.c_void_p(vals.data_ptr()), ctypes.c_void_p(vo.data_ptr()), n,
+                                        int(bits), None))
+    return ko, vo
+
+
+def dg_scan_exclusive(x):
+    """Exclusive prefix sum of an int64 device tensor (new tensor)."""
+    import torch
+
+    out = torch.empty_like(x)
+    _check(load_library().dg_scan_exclusive(ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                            int(x.numel()), None))
+    return out
 
 
 # ---------------------------------------------------------------------------- allocator

@@ -5,6 +5,7 @@
 #include <atomic>
 #include <cstdarg>
 #include <cstring>
+#include <mutex>
 
 #include "dg_internal.h"
 
@@ -534,6 +535,53 @@ int dg_tc_read(dg_query *q, uint64_t *count) {
     if (!q || q->kind != Q_TC || !count) return set_error(DG_EINVAL, "not a triangle-count query");
     *count = q->tc;
     return DG_OK;
+}
+
+// ---- sort and scan primitives ---------------------------------------------------------------
+
+namespace {
+std::mutex g_prim_mu;
+SortWork g_prim_ws;
+int64_t *g_prim_err = nullptr;
+
+int prim_begin(hipStream_t s) {
+    if (!g_prim_err) {
+        g_prim_err = static_cast<int64_t *>(dmalloc(sizeof(int64_t)));
+        if (!g_prim_err) return set_error(DG_ENOMEM, "error word allocation failed");
+        DG_TRY(fill_i64(g_prim_err, 0, 1, s));
+    }
+    return DG_OK;
+}
+
+int prim_end(hipStream_t s) {
+    int64_t e = 0;
+    DG_HIP(hipMemcpyAsync(&e, g_prim_err, sizeof(e), hipMemcpyDeviceToHost, s));
+    DG_HIP(hipStreamSynchronize(s));
+    if (e) return set_error(DG_EDEVICE, "sort or scan look-back did not finish (internal error)");
+    return DG_OK;
+}
+}  // namespace
+
+int dg_sort_pairs(const uint64_t *kin, uint64_t *kout, const int32_t *vin, int32_t *vout, int64_t n, int32_t bits,
+                  void *stream) {
+    if (n < 0 || (n > 0 && (!kin || !kout || !vin || !vout))) return set_error(DG_EINVAL, "bad sort arguments");
+    if (bits < 1 || bits > 64) return set_error(DG_EINVAL, "bits must be in [1, 64]");
+    if (n > 0 && ((const void *)kin == (const void *)kout || (const void *)vin == (const void *)vout))
+        return set_error(DG_EINVAL, "sort outputs must not alias its inputs");
+    std::lock_guard<std::mutex> lock(g_prim_mu);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    DG_TRY(prim_begin(s));
+    DG_TRY(radix_sort_pairs(s, g_prim_ws, kin, kout, vin, vout, n, bits, g_prim_err));
+    return prim_end(s);
+}
+
+int dg_scan_exclusive(const int64_t *in, int64_t *out, int64_t n, void *stream) {
+    if (n < 0 || (n > 0 && (!in || !out))) return set_error(DG_EINVAL, "bad scan arguments");
+    std::lock_guard<std::mutex> lock(g_prim_mu);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    DG_TRY(prim_begin(s));
+    DG_TRY(scan_excl_i64(s, g_prim_ws, in, out, n, g_prim_err));
+    return prim_end(s);
 }
 
 int dg_sssp_static(dg_graph *g, int32_t source, int32_t *dist, int32_t *parent, uint32_t flags) {

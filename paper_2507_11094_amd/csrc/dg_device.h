@@ -1,6 +1,8 @@
 // Device-side helpers shared by the kernels (64-wide CDNA wavefronts).
 #pragma once
 
+#include <type_traits>
+
 #include "dg_internal.h"
 
 namespace dg {
@@ -119,15 +121,42 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Wave-wide inclusive scan (Hillis-Steele over 64 lanes).
+// DPP lane moves (the data-parallel-primitive operand modifier of gfx9 VALU
+// instructions): lane i receives the value of another lane without going through
+// LDS.  Controls used here: row_shr:k (0x110 + k; from lane i - k of the same
+// 16-lane row), row_bcast:15 (0x142; lane 15 of a row into every lane of the next
+// row) and row_bcast:31 (0x143; lane 31 into rows 2 and 3).  Lanes of rows
+// outside ROW_MASK, and lanes whose source is outside the row when BOUND_ZERO is
+// set, receive 0.  Every lane of the wave must be active.
+template <int CTRL, int ROW_MASK, bool BOUND_ZERO>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, ROW_MASK, 0xf, BOUND_ZERO);
+}
+template <int CTRL, int ROW_MASK, bool BOUND_ZERO, class T>
+__device__ __forceinline__ T dpp_move(T x) {
+    static_assert(sizeof(T) == 4 || sizeof(T) == 8, "32- or 64-bit integers");
+    if constexpr (sizeof(T) == 8) {
+        const uint64_t u = (uint64_t)x;
+        const uint64_t lo = dpp_u32<CTRL, ROW_MASK, BOUND_ZERO>((uint32_t)u);
+        const uint64_t hi = dpp_u32<CTRL, ROW_MASK, BOUND_ZERO>((uint32_t)(u >> 32));
+        return (T)((hi << 32) | lo);
+    } else {
+        return (T)dpp_u32<CTRL, ROW_MASK, BOUND_ZERO>((uint32_t)x);
+    }
+}
+
+// Wave-wide inclusive scan of integers: Hillis-Steele inside each 16-lane row by
+// DPP row shifts, then the row totals carried across rows by the two DPP row
+// broadcasts.  Six DPP moves per 32 bits, no LDS traffic.  All lanes must be active.
 template <class T>
 __device__ __forceinline__ T wave_incl_scan(T x) {
-    int l = lane_id();
-#pragma unroll
-    for (int d = 1; d < WAVE; d <<= 1) {
-        T y = __shfl_up(x, d, WAVE);
-        if (l >= d) x += y;
-    }
+    static_assert(std::is_integral<T>::value, "integer scan");
+    x += dpp_move<0x111, 0xf, true>(x);   // row_shr:1
+    x += dpp_move<0x112, 0xf, true>(x);   // row_shr:2
+    x += dpp_move<0x114, 0xf, true>(x);   // row_shr:4
+    x += dpp_move<0x118, 0xf, true>(x);   // row_shr:8
+    x += dpp_move<0x142, 0xa, false>(x);  // row_bcast:15 into rows 1 and 3
+    x += dpp_move<0x143, 0xc, false>(x);  // row_bcast:31 into rows 2 and 3
     return x;
 }
 

@@ -103,6 +103,23 @@ struct Dir {
     DBuf<int32_t> dcol2, dw2;
 };
 
+// Workspace of the radix sort and the scan (sort.hip): one device pool holding
+// look-back status words, digit counts and the sort's ping-pong keys and values.
+struct SortWork {
+    DBuf<uint8_t> pool;
+    uint32_t epoch = 0;         // look-back generation of the last pass or scan
+    int64_t status_words = 0;   // status words the pool's layout reserves
+    int64_t key_cap = 0;        // keys the pool's layout reserves
+    uint64_t calls = 0;         // sorts so far: picks which of two digit-count sets a sort uses
+    void release() {
+        pool.release();
+        epoch = 0;
+        calls = 0;
+        status_words = 0;
+        key_cap = 0;
+    }
+};
+
 // Workspace: scratch grown on demand, reused across batches.
 struct Work {
     DBuf<int32_t> bsrc, bdst, bw;
@@ -118,7 +135,7 @@ struct Work {
     DBuf<int32_t> nw;
     DBuf<int32_t> tcu, tcv;               // undirected edges for TC (deleted / inserted)
     DBuf<int64_t> tcitems;                // TC delta: work items per changed edge, then their scan
-    DBuf<uint8_t> tmp;                    // hipcub temp storage
+    SortWork sw;                          // radix sort / scan workspace (sort.hip)
     DBuf<int64_t> scan64;                 // merge scans
     DBuf<int64_t> tscan;
     // frontier machinery shared by the traversals
@@ -149,7 +166,7 @@ struct Work {
     // a merge on the second stream keeps its own error counter and scan scratch
     int64_t *dcnt_m = nullptr;
     int64_t *hcnt_m = nullptr;
-    DBuf<uint8_t> tmp_m;
+    SortWork sw_m;
     hipEvent_t ev[16] = {};
 };
 
@@ -166,7 +183,10 @@ struct GraphCache {
 enum Counter {
     C_ERR = 0, C_NDEL, C_NINS, C_ADEL, C_IGNDEL, C_DISTINCT, C_AINS, C_IGNINS, C_NEW,
     C_TCDEL, C_TCINS, C_F0, C_F1, C_HEAVY, C_AUX0, C_AUX1, C_AUX2, C_AUX3,
-    C_TC0, C_TC1, C_RED0 = 24, C_COUNT = 40
+    C_TC0, C_TC1, C_RED0 = 24,
+    // set by a sort or scan whose look-back hit its spin limit; counters_clear
+    // leaves it alone, counters_read reports it
+    C_SORT_ERR = 39, C_COUNT = 40
 };
 
 }  // namespace dg
@@ -243,6 +263,15 @@ int next_stamp(dg_graph *g, int32_t *stamp);
 int fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
 int fill_i64(int64_t *p, int64_t v, int64_t n, hipStream_t s);
 int scan_excl(dg_graph *g, const int64_t *in, int64_t *out, int64_t n);  // exclusive prefix sum
+
+// sort.hip: stable LSD radix sort of (key, value) pairs on the low `bits` bits of
+// the keys (kin/vin are not modified; kout/vout must not alias them), and an
+// exclusive scan of non-negative int64 values (total below 2^48).  On a look-back
+// spin-limit exit they OR a bit into *err (device memory).
+int radix_sort_pairs(hipStream_t s, SortWork &w, const uint64_t *kin, uint64_t *kout, const int32_t *vin,
+                     int32_t *vout, int64_t n, int bits, int64_t *err);
+int scan_excl_i64(hipStream_t s, SortWork &w, const int64_t *in, int64_t *out, int64_t n, int64_t *err);
+int fill_u64_on(uint64_t *p, uint64_t v, int64_t n, hipStream_t s);
 
 // SSSP (sssp.hip)
 int sssp_init(dg_query *q);

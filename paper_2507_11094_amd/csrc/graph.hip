@@ -7,8 +7,6 @@
 // batch); when diff entries plus tombstones pass a threshold the diff and the
 // tombstones are merged into a fresh base CSR by a coalesced tile-parallel stream
 // (Section 3.5: the chain is merged after a configurable number of batches).
-#include <hipcub/hipcub.hpp>
-
 #include <algorithm>
 #include <cstring>
 
@@ -54,42 +52,38 @@ int fill_i64(int64_t *p, int64_t v, int64_t n, hipStream_t s) {
     return DG_OK;
 }
 
-// ---------------------------------------------------------------- library primitives
+// ---------------------------------------------------------------- sort and scan (sort.hip)
 
-static int scan_excl_on(hipStream_t s, DBuf<uint8_t> &tmp, const int64_t *in, int64_t *out, int64_t n) {
-    if (n <= 0) return DG_OK;
-    size_t bytes = 0;
-    DG_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, bytes, in, out, (int)n, s));
-    DG_TRY(tmp.ensure(bytes));
-    DG_HIP(hipcub::DeviceScan::ExclusiveSum(tmp.p, bytes, in, out, (int)n, s));
-    return DG_OK;
+// Timed as whole calls (all their launches): 8 B read + 8 B written per value of a
+// scan, 12 B read + 12 B written per pair of a sort (each pass moves them again).
+static int scan_excl_on(hipStream_t s, SortWork &w, int64_t *err, const int64_t *in, int64_t *out, int64_t n) {
+    const int ps = prof_begin("scan", s);
+    const int rc = scan_excl_i64(s, w, in, out, n, err);
+    prof_end(ps, s, 16.0 * (double)n);
+    return rc;
 }
 
 static int sort_pairs(dg_graph *g, const uint64_t *kin, uint64_t *kout, const int32_t *vin,
                       int32_t *vout, int64_t n, int bits) {
-    if (n <= 0) return DG_OK;
-    if (n > INT32_MAX) return set_error(DG_EINVAL, "sort of more than 2^31 keys");
-    size_t bytes = 0;
-    DG_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, kin, kout, vin, vout, (int)n, 0, bits,
-                                              g->stream));
-    DG_TRY(g->ws.tmp.ensure(bytes));
-    DG_HIP(hipcub::DeviceRadixSort::SortPairs(g->ws.tmp.p, bytes, kin, kout, vin, vout, (int)n, 0,
-                                              bits, g->stream));
-    return DG_OK;
+    const int ps = prof_begin("sort_pairs", g->stream);
+    const int rc = radix_sort_pairs(g->stream, g->ws.sw, kin, kout, vin, vout, n, bits, g->ws.dcnt + C_SORT_ERR);
+    prof_end(ps, g->stream, 24.0 * (double)n);
+    return rc;
 }
 
 int scan_excl(dg_graph *g, const int64_t *in, int64_t *out, int64_t n) {
-    return scan_excl_on(g->stream, g->ws.tmp, in, out, n);
+    return scan_excl_on(g->stream, g->ws.sw, g->ws.dcnt + C_SORT_ERR, in, out, n);
 }
 
 // ---------------------------------------------------------------- counters
 
-int counters_clear(dg_graph *g) { return fill_i64(g->ws.dcnt, 0, C_COUNT, g->stream); }
+int counters_clear(dg_graph *g) { return fill_i64(g->ws.dcnt, 0, C_SORT_ERR, g->stream); }
 
 int counters_read(dg_graph *g) {
     DG_HIP(hipMemcpyAsync(g->ws.hcnt, g->ws.dcnt, sizeof(int64_t) * C_COUNT, hipMemcpyDeviceToHost,
                           g->stream));
     DG_HIP(hipStreamSynchronize(g->stream));
+    if (g->ws.hcnt[C_SORT_ERR]) return set_error(DG_EDEVICE, "sort or scan look-back did not finish (internal error)");
     return DG_OK;
 }
 
@@ -102,7 +96,8 @@ int ws_init(dg_graph *g) {
     if (!g->ws.dcnt_m) return set_error(DG_ENOMEM, "counter allocation failed");
     DG_HIP(hipHostMalloc((void **)&g->ws.hcnt_m, sizeof(int64_t) * C_COUNT, hipHostMallocDefault));
     for (auto &e : g->ws.ev) DG_HIP(hipEventCreate(&e));
-    return counters_clear(g);
+    DG_TRY(fill_i64(g->ws.dcnt_m, 0, C_COUNT, g->stream));
+    return fill_i64(g->ws.dcnt, 0, C_COUNT, g->stream);
 }
 
 void dir_free(Dir &d) {
@@ -119,7 +114,7 @@ void ws_free(dg_graph *g) {
     w.iw.release(); w.iw_s.release(); w.rw.release(); w.rw_s.release();
     w.ddu.release(); w.ddv.release(); w.adu.release(); w.adv.release(); w.adpos.release();
     w.aiu.release(); w.aiv.release(); w.aiw.release(); w.aipos.release();
-    w.nkey.release(); w.nw.release(); w.tcu.release(); w.tcv.release(); w.tmp.release();
+    w.nkey.release(); w.nw.release(); w.tcu.release(); w.tcv.release(); w.sw.release();
     w.scan64.release(); w.tscan.release(); w.f0.release(); w.f1.release(); w.heavy.release();
     w.stamp.release(); w.part.release(); w.prs.release();
     w.mp_row.release(); w.mp_edge.release(); w.mp_part.release(); w.mp_doff.release(); w.tcitems.release();
@@ -131,7 +126,7 @@ void ws_free(dg_graph *g) {
     if (w.hcnt) (void)hipHostFree(w.hcnt);
     if (w.dcnt_m) dfree(w.dcnt_m);
     if (w.hcnt_m) (void)hipHostFree(w.hcnt_m);
-    w.tmp_m.release();
+    w.sw_m.release();
     w.dcnt_m = nullptr;
     w.hcnt_m = nullptr;
     if (g->aux) (void)hipStreamDestroy(g->aux);
@@ -339,7 +334,7 @@ int graph_build(dg_graph *g, int64_t m, const int32_t *src, const int32_t *dst, 
     g->rev = g->undirected ? &g->fwd : &g->rev_own;
     g->m_live = arcs;
     // the build-sized scratch is not needed again
-    ws.ikey.release(); ws.ikey_s.release(); ws.iw.release(); ws.iw_s.release(); ws.tmp.release();
+    ws.ikey.release(); ws.ikey_s.release(); ws.iw.release(); ws.iw_s.release(); ws.sw.release();
     DG_HIP(hipStreamSynchronize(s));
     return DG_OK;
 }
@@ -554,7 +549,7 @@ static int merge_into(dg_graph *g, Dir &d, int64_t *off2, int32_t *col2, int32_t
     hipStream_t s = side ? g->aux : g->stream;
     Work &ws = g->ws;
     int64_t *cnt = side ? ws.dcnt_m : ws.dcnt;
-    DBuf<uint8_t> &tmp = side ? ws.tmp_m : ws.tmp;
+    SortWork &sw = side ? ws.sw_m : ws.sw;
     const int32_t n = g->n;
     const int64_t nblk = ntiles_for(d.m);
     DG_TRY(ws.scan64.ensure(2 * ((size_t)n + 1) + 2 * (nblk + 2)));
@@ -564,13 +559,13 @@ static int merge_into(dg_graph *g, Dir &d, int64_t *off2, int32_t *col2, int32_t
     int64_t *TB = tsin + (nblk + 2);
     // off2 = exclusive scan of live degrees
     hipLaunchKernelGGL(k_deg_to_i64, dim3(grid_for(n + 1)), dim3(256), 0, s, n, d.deg.p, tmpa);
-    DG_TRY(scan_excl_on(s, tmp, tmpa, off2, n + 1));
+    DG_TRY(scan_excl_on(s, sw, cnt + C_SORT_ERR, tmpa, off2, n + 1));
     // RB = tombstones before each row, TB = tombstones before each counter block
     hipLaunchKernelGGL(k_deg_to_i64, dim3(grid_for(n + 1)), dim3(256), 0, s, n, d.ntomb.p, tmpa);
-    DG_TRY(scan_excl_on(s, tmp, tmpa, RB, n + 1));
+    DG_TRY(scan_excl_on(s, sw, cnt + C_SORT_ERR, tmpa, RB, n + 1));
     hipLaunchKernelGGL(k_deg_to_i64, dim3(grid_for(nblk + 2)), dim3(256), 0, s, (int32_t)(nblk + 1), d.ttomb.p,
                        tsin);
-    DG_TRY(scan_excl_on(s, tmp, tsin, TB, nblk + 2));
+    DG_TRY(scan_excl_on(s, sw, cnt + C_SORT_ERR, tsin, TB, nblk + 2));
     // merge-path tiles
     const int items = g->cfg.merge_tile == 512 || g->cfg.merge_tile == 2048 ? g->cfg.merge_tile : MG_ITEMS;
     const int64_t nb = ((int64_t)n + d.m + items - 1) / items;
@@ -581,7 +576,7 @@ static int merge_into(dg_graph *g, Dir &d, int64_t *off2, int32_t *col2, int32_t
     hipLaunchKernelGGL(k_mg_partition, dim3(grid_for(nb + 1)), dim3(256), 0, s, d.off.p, d.doff.p, n, d.m, nb,
                        items, ws.mp_row.p, ws.mp_edge.p, mp_dlo, mp_dhi);
     DG_HIP(hipGetLastError());
-    DG_TRY(fill_i64(cnt, 0, C_COUNT, s));
+    DG_TRY(fill_i64(cnt, 0, C_SORT_ERR, s));
     // merge bytes: col+w read 8 per old entry, write 8 per new entry, and per row
     // off, doff, off2 and the tombstone prefix (8 each)
     int pm = prof_begin("merge_base", s);
@@ -606,6 +601,7 @@ static int merge_side_check(dg_graph *g) {
     DG_HIP(hipMemcpyAsync(g->ws.hcnt_m, g->ws.dcnt_m, sizeof(int64_t) * C_COUNT, hipMemcpyDeviceToHost, g->aux));
     DG_HIP(hipStreamSynchronize(g->aux));
     if (g->ws.hcnt_m[C_ERR]) return set_error(DG_EDEVICE, "merge: inconsistent degree counts (internal error)");
+    if (g->ws.hcnt_m[C_SORT_ERR]) return set_error(DG_EDEVICE, "merge: scan look-back did not finish (internal error)");
     return DG_OK;
 }
 
