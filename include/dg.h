@@ -114,6 +114,12 @@ typedef struct dg_config {
      * gathered from them share cache lines; 1 = as given.  Every id the caller
      * passes or reads back is the caller's own either way. */
     int32_t vertex_order;
+    /* Placement of a new edge (Section "Modified Graph Representation: diff-CSR"):
+     * 0 = in a tombstoned slot of its row when one lies next to its sorted
+     * position (the row stays sorted; among new edges wanting one slot, the
+     * smallest takes it), else in the diff level (default); 1 = always in the diff
+     * level (a slot of the same edge is still revived). */
+    int32_t diff_only;
 } dg_config;
 
 /* Per-batch statistics and phase timings (HIP events on the graph's stream). */

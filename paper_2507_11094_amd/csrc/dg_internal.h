@@ -134,6 +134,9 @@ struct Work {
     DBuf<uint64_t> nkey;                  // NEW forward keys (sorted)
     DBuf<int32_t> nw;
     DBuf<int32_t> tcu, tcv;               // undirected edges for TC (deleted / inserted)
+    DBuf<int64_t> vslot, vpos;            // hole reuse: slot taken per NEW key (+ diff flags), their scan
+    DBuf<uint64_t> vkey;                  // hole reuse: NEW keys left for the diff level
+    DBuf<int32_t> vw;
     DBuf<int64_t> tcitems;                // TC delta: work items per changed edge, then their scan
     SortWork sw;                          // radix sort / scan workspace (sort.hip)
     DBuf<int64_t> scan64;                 // merge scans

@@ -120,6 +120,7 @@ void ws_free(dg_graph *g) {
     w.mp_row.release(); w.mp_edge.release(); w.mp_part.release(); w.mp_doff.release(); w.tcitems.release();
     w.farflag.release(); w.far0.release(); w.far1.release(); w.bpart.release();
     w.rbuf.release(); w.skey.release(); w.sx.release(); w.sc.release(); w.sxn.release();
+    w.vslot.release(); w.vpos.release(); w.vkey.release(); w.vw.release();
     w.wq.release(); w.wseq.release(); w.wctr.release(); w.inq.release();
     g->perm.release(); g->iperm.release();
     if (w.dcnt) dfree(w.dcnt);
@@ -1094,6 +1095,75 @@ __global__ __launch_bounds__(CH_T) void k_revive(int64_t na, const int32_t *aiu,
     block_count(&cnt[C_AUX2], nrev, sc);
 }
 
+// Sorted hole reuse (Section "Modified Graph Representation: diff-CSR": a new edge
+// takes a vacant, tombstoned slot of its row when one is available, and goes to
+// the diff-CSR otherwise).  Rows stay sorted by neighbour id, tombstones included,
+// so a NEW key v of row u may take a tombstone only next to its sorted position:
+// the slot just before it (the largest id below v) or just after it (the smallest
+// id above v).  NEW keys are sorted and distinct, and the slot a key wants never
+// decreases along a row, so the keys wanting one slot are consecutive and the
+// first of them takes it.  Runs after the revivals (a revived slot is live again
+// and no longer wanted) and reads only: the writes follow in k_vacancy_fill.
+__device__ __forceinline__ int64_t vacancy_of(const int64_t *__restrict__ off, const int32_t *__restrict__ col,
+                                              int32_t u, uint32_t v) {
+    const int64_t lo = off[u], hi = off[u + 1];
+    if (lo == hi) return -1;
+    const int64_t p = lower_sorted(col, lo, hi, v);
+    if (p > lo && ((uint32_t)col[p - 1] & DEAD)) return p - 1;
+    if (p < hi && ((uint32_t)col[p] & DEAD)) return p;
+    return -1;
+}
+
+// slot[j] = the base slot NEW key j takes, or -1 (it goes to the diff level);
+// todiff[j] = 1 for the latter (the compaction's flags, with todiff[nk] = 0).
+__global__ void k_vacancy_claim(int64_t nk, const uint64_t *nkey, int B, const int64_t *__restrict__ off,
+                                const int32_t *__restrict__ col, int64_t *slot, int64_t *todiff) {
+    const uint64_t mask = (1ull << B) - 1;
+    for (int64_t j = gtid(); j <= nk; j += gstride()) {
+        if (j == nk) {
+            todiff[j] = 0;
+            continue;
+        }
+        const uint64_t k = nkey[j];
+        const int32_t u = (int32_t)(k >> B);
+        int64_t c = vacancy_of(off, col, u, (uint32_t)(k & mask));
+        if (c >= 0 && j > 0 && (int32_t)(nkey[j - 1] >> B) == u &&
+            vacancy_of(off, col, u, (uint32_t)(nkey[j - 1] & mask)) == c)
+            c = -1;  // an earlier key of the row takes this slot
+        slot[j] = c;
+        todiff[j] = c < 0;
+    }
+}
+
+// Write the taken slots (MARKed like every fresh insert until the post-hooks end).
+__global__ void k_vacancy_fill(int64_t nk, const uint64_t *nkey, const int32_t *nw, int B, const int64_t *slot,
+                               int32_t *col, int32_t *w, int32_t *ntomb, int32_t *ttomb, int64_t *cnt) {
+    __shared__ BlockScratch sc;
+    const uint64_t mask = (1ull << B) - 1;
+    int64_t filled = 0;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < nk; base += gstride()) {
+        const int64_t j = base + threadIdx.x;
+        if (j < nk && slot[j] >= 0) {
+            const int64_t c = slot[j];
+            col[c] = (int32_t)((uint32_t)(nkey[j] & mask) | MARK);
+            w[c] = nw[j];
+            atomicSub(&ntomb[(int32_t)(nkey[j] >> B)], 1);
+            atomicSub(&ttomb[c / TILE], 1);
+            ++filled;
+        }
+    }
+    block_count(&cnt[C_AUX1], filled, sc);
+}
+
+__global__ void k_vacancy_rest(int64_t nk, const uint64_t *nkey, const int32_t *nw, const int64_t *todiff,
+                               const int64_t *pos, uint64_t *okey, int32_t *ow) {
+    for (int64_t j = gtid(); j < nk; j += gstride())
+        if (todiff[j]) {
+            okey[pos[j]] = nkey[j];
+            ow[pos[j]] = nw[j];
+        }
+}
+
 // Drop MARK from the entries this chunk inserted.
 __global__ void k_clear_marks(int64_t na, const int32_t *aiu, const int32_t *aiv, int reverse,
                               const int64_t *__restrict__ off, int32_t *col,
@@ -1184,6 +1254,41 @@ static int diff_rebuild(dg_graph *g, Dir &d, const uint64_t *nkey, const int32_t
     d.dw.swap(d.dw2);
     d.dm = dm2;
     d.tomb_diff = 0;
+    return DG_OK;
+}
+
+// Hole reuse for one direction: NEW keys (sorted, distinct) take the tombstoned
+// slots next to their sorted positions where they can; *out / *out_w / *out_n are
+// the keys left for the diff level.
+static int fill_vacancies(dg_graph *g, Dir &d, const uint64_t *nkey, const int32_t *nw, int64_t nk,
+                          const uint64_t **out, const int32_t **out_w, int64_t *out_n) {
+    *out = nkey;
+    *out_w = nw;
+    *out_n = nk;
+    if (nk <= 0 || d.tomb_base <= 0 || g->cfg.diff_only) return DG_OK;
+    hipStream_t s = g->stream;
+    Work &ws = g->ws;
+    DG_TRY(ws.vslot.ensure(2 * ((size_t)nk + 1)));
+    DG_TRY(ws.vkey.ensure((size_t)nk + 1));
+    DG_TRY(ws.vw.ensure((size_t)nk + 1));
+    int64_t *slot = ws.vslot.p, *todiff = ws.vslot.p + (nk + 1);
+    DG_TRY(ws.vpos.ensure((size_t)nk + 1));
+    DG_TRY(counters_clear(g));
+    hipLaunchKernelGGL(k_vacancy_claim, dim3(grid_for(nk + 1)), dim3(256), 0, s, nk, nkey, d.keybits, d.off.p,
+                       d.col.p, slot, todiff);
+    hipLaunchKernelGGL(k_vacancy_fill, dim3(grid_for(nk)), dim3(256), 0, s, nk, nkey, nw, d.keybits, slot,
+                       d.col.p, d.w.p, d.ntomb.p, d.ttomb.p, ws.dcnt);
+    DG_HIP(hipGetLastError());
+    DG_TRY(scan_excl(g, todiff, ws.vpos.p, nk + 1));
+    hipLaunchKernelGGL(k_vacancy_rest, dim3(grid_for(nk)), dim3(256), 0, s, nk, nkey, nw, todiff, ws.vpos.p,
+                       ws.vkey.p, ws.vw.p);
+    DG_HIP(hipGetLastError());
+    DG_TRY(counters_read(g));
+    const int64_t filled = g->ws.hcnt[C_AUX1];
+    d.tomb_base -= filled;
+    *out = ws.vkey.p;
+    *out_w = ws.vw.p;
+    *out_n = nk - filled;
     return DG_OK;
 }
 
@@ -1340,11 +1445,21 @@ int apply_chunk(dg_graph *g, int64_t k, const int32_t *src, const int32_t *dst, 
     const int64_t revived_base_r = und ? 0 : ws.hcnt[C_AUX2 + 8];
     const int64_t tcins = ws.hcnt[C_TCINS];
     F.tomb_base += killed_base_f - revived_base_f;
-    DG_TRY(diff_rebuild(g, F, ws.nkey.p, ws.nw.p, nnew, killed_diff_f));
+    {
+        const uint64_t *fk;
+        const int32_t *fw;
+        int64_t fn;
+        DG_TRY(fill_vacancies(g, F, ws.nkey.p, ws.nw.p, nnew, &fk, &fw, &fn));
+        DG_TRY(diff_rebuild(g, F, fk, fw, fn, killed_diff_f));
+    }
     if (!und) {
         R.tomb_base += killed_base_r - revived_base_r;
         DG_TRY(sort_pairs(g, ws.rkey.p, ws.rkey_s.p, ws.rw.p, ws.rw_s.p, nnew, 2 * B));
-        DG_TRY(diff_rebuild(g, R, ws.rkey_s.p, ws.rw_s.p, nnew, killed_diff_r));
+        const uint64_t *rk;
+        const int32_t *rw;
+        int64_t rn;
+        DG_TRY(fill_vacancies(g, R, ws.rkey_s.p, ws.rw_s.p, nnew, &rk, &rw, &rn));
+        DG_TRY(diff_rebuild(g, R, rk, rw, rn, killed_diff_r));
     }
     g->m_live += ains - adel;
     t_upd.stop();

@@ -94,6 +94,83 @@ def test_diffcsr_figure_example():
     assert list(zip(es.tolist(), ed.tolist())) == sorted([(A, B), (B, C), (C, A), (D, E), (E, C), (E, F), (F, D)])
 
 
+@pytest.mark.parametrize("diff_only", [0, 1])
+def test_diffcsr_figure_vacancy(diff_only):
+    """Section 3.5 example continued: after B->D left a tombstone, a later insert of
+    B->E takes that vacant slot (B's row stays sorted: C, E) instead of the diff;
+    with diff_only the diff level takes it."""
+    say("diff-CSR figure example, vacancy reuse, diff_only", diff_only)
+    A, B, C, D, E, F = range(6)
+    s = np.array([A, B, B, C, D, E, F]); d = np.array([B, C, D, A, E, F, D])
+    c = cfg(merge=1e9)
+    c.diff_only = diff_only
+    c.vertex_order = 1  # keep the figure's ids, so B's row is the figure's
+    G = dg.Graph(6, s, d, None, config=c)
+    G.apply([B, E], [D, C], [0, 1], [0, 1])
+    G.apply([B], [E], [4], [1])
+    info = G.info()
+    if diff_only:
+        assert info["tombstones"] == 1 and info["diff_entries"] == 2
+    else:
+        assert info["tombstones"] == 0 and info["diff_entries"] == 1
+    es, ed, ew = G.export()
+    want = sorted([(A, B), (B, C), (B, E), (C, A), (D, E), (E, C), (E, F), (F, D)])
+    assert list(zip(es.tolist(), ed.tolist())) == want
+    assert ew[want.index((B, E))] == 4
+    q = G.sssp_attach(A)
+    assert q.read()[0].tolist() == oracle.sssp(6, es, ed, ew, A).tolist()
+    G.close()
+
+
+@pytest.mark.parametrize("undirected", [False, True])
+def test_vacancy_reuse_matches_diff_only(undirected):
+    """Batches on graphs full of tombstones (no merges): new edges fill vacant
+    slots next to their sorted positions.  The edge set, SSSP, PageRank and triangle
+    counts equal the oracle after every batch, the diff level stays smaller than
+    with diff_only, and tombstones + diff entries add up the same way."""
+    say("vacancy reuse vs diff_only, undirected", undirected)
+    if undirected:
+        n, u, v = graphgen.rmat_undirected(11, 8 << 11, graphgen.config_seed(2, 70))
+        s, d, w = u, v, None
+    else:
+        n, s, d, w = rmat_small(11, 16, 70)
+    runs = {}
+    for diff_only in (0, 1):
+        c = cfg(merge=1e9)
+        c.diff_only = diff_only
+        G = dg.Graph(n, s, d, w, undirected=undirected, config=c)
+        qt = G.tc_attach() if undirected else None
+        qs = None if undirected else G.sssp_attach(0)
+        qp = None if undirected else G.pr_attach(0.85, PR_TOL, 1000)
+        cs, cd, cw = s, d, (w if w is not None else np.ones(s.size, np.int32))
+        infos = []
+        for i, k in enumerate([3000, 2000, 4000, 1000]):
+            b = graphgen.update_batch(n, cs, cd, k, graphgen.config_seed(0, 700 + i), undirected=undirected)
+            st = G.apply(*b)
+            cs, cd, cw, ost = oracle.apply(n, cs, cd, cw, *b, undirected=undirected)
+            assert (st.deleted, st.inserted) == (ost[0], ost[1])
+            infos.append(G.info())
+            es, ed, ew = G.export()
+            assert np.array_equal(es, cs) and np.array_equal(ed, cd)
+            if not undirected:
+                assert np.array_equal(ew, cw)
+                assert np.array_equal(qs.read()[0], oracle.sssp(n, cs, cd, cw, 0))
+                want, _, _ = oracle.pagerank(n, cs, cd, 0.85, PR_TOL, 1000)
+                assert float(np.max(np.abs(qp.read()[0] - want))) <= PR_MAXABS
+            else:
+                assert qt.read() == oracle.triangles(n, cs, cd)
+        runs[diff_only] = infos
+        G.close()
+    filled = 0
+    for a, b in zip(runs[0], runs[1]):
+        assert a["m"] == b["m"]
+        # a filled vacancy is one tombstone fewer and one diff entry fewer
+        assert a["tombstones"] + a["diff_entries"] <= b["tombstones"] + b["diff_entries"]
+        assert b["tombstones"] - a["tombstones"] == b["diff_entries"] - a["diff_entries"]
+        filled = b["diff_entries"] - a["diff_entries"]
+    assert filled > 0
+
+
 @pytest.mark.parametrize("merge", [0.0, -1.0, 1e9])
 def test_batch_sequence_matches_oracle(merge):
     n, s, d, w = rmat_small(11, 16, 21)
