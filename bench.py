@@ -266,7 +266,18 @@ def inverse(batch, index: EdgeIndex):
 
 # ----------------------------------------------------------------------------- one graph
 
-def run_single(args, kind: str) -> int:
+# graphs generated once per process (the R-MAT 22 graph serves three batch sizes)
+_GRAPHS: dict = {}
+
+
+def cached_graph(key, make):
+    if key not in _GRAPHS:
+        _GRAPHS.clear()
+        _GRAPHS[key] = make()
+    return _GRAPHS[key]
+
+
+def run_single(args, kind: str) -> dict:
     import torch
 
     import graphgen
@@ -277,19 +288,19 @@ def run_single(args, kind: str) -> int:
     t = time.perf_counter()
     undirected = kind == "tc"
     if kind == "rmat":
-        n, s, d, w = graphgen.c2r_graph(args.scale)
+        n, s, d, w = cached_graph(("rmat", args.scale), lambda: graphgen.c2r_graph(args.scale))
         k, wmax = args.batch, 100
         wl = f"rmat{args.scale}-dynamic-sssp+pagerank"
     elif kind == "grid":
-        n, s, d, w = graphgen.c2g_graph(args.side)
+        n, s, d, w = cached_graph(("grid", args.side), lambda: graphgen.c2g_graph(args.side))
         k, wmax = args.batch, 1000
         wl = f"grid{args.side}x{args.side}-dynamic-sssp+pagerank"
     else:
-        n, s, d = graphgen.c3_graph(args.tc_scale)
+        n, s, d = cached_graph(("tc", args.tc_scale), lambda: graphgen.c3_graph(args.tc_scale))[:3]
         w = None
         k, wmax = int(args.pct * s.size), 100
         wl = f"rmat{args.tc_scale}-undirected-dynamic-tc"
-    log(f"{wl}: n={n} m={s.size} generated in {time.perf_counter() - t:.1f}s")
+    log(f"{wl}: n={n} m={s.size} ready in {time.perf_counter() - t:.1f}s")
     keys = graphgen.edge_keys(s, d, undirected)
     t = time.perf_counter()
     batches = [graphgen.update_batch(n, s, d, k, graphgen.config_seed(1 if kind != "tc" else 2, 100 + i),
@@ -326,6 +337,7 @@ def run_single(args, kind: str) -> int:
     for i in range(W):
         G.apply(*ubatches[i])
         log(f"warmup {i + 1}/{W}")
+    info_start = G.info()
     dg.dg_profile_enable(True)
     dg.dg_profile_reset()
     stats = []
@@ -342,9 +354,32 @@ def run_single(args, kind: str) -> int:
     prof = dg.dg_profile_read()
     dg.dg_profile_enable(False)
     value = K * k / elapsed
+    info_end = G.info()
 
     def avg(key):
         return float(np.mean([x[key] for x in stats]))
+
+    # The merge (diff level and tombstones back into plain CSR) runs once the two
+    # pass 5 % of the live edges, every few dozen batches, so a short timed window
+    # may hold none.  Its cost per batch: one forced merge, timed, spread over the
+    # batches that fill the threshold at the growth rate of the timed steps.
+    merge = None
+    growth = ((info_end["diff_entries"] + info_end["tombstones"]) -
+              (info_start["diff_entries"] + info_start["tombstones"])) / K
+    merged_in_window = sum(x["merged"] for x in stats)
+    if merged_in_window == 0 and growth > 0:
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        G.merge()
+        torch.cuda.synchronize()
+        merge_s = time.perf_counter() - t
+        arcs_fwd = info_end["m"] * (2 if undirected else 1)
+        per_merge = 0.05 * arcs_fwd / growth
+        amort = merge_s / per_merge
+        merge = {"forced_merge_ms": round(1e3 * merge_s, 3), "fwd_growth_per_batch": round(growth, 1),
+                 "batches_per_merge": round(per_merge, 1), "amortised_ms_per_batch": round(1e3 * amort, 4),
+                 "value_with_amortised_merge": round(K * k / (elapsed + K * amort), 1)}
+        log(f"merge: {merge}")
 
     static = None
     if not args.no_static:
@@ -400,11 +435,32 @@ def run_single(args, kind: str) -> int:
     }
     if kind == "tc":
         extra["triangles"] = {"initial": int(tc0), "final": int(qt.read())}
+    if merge:
+        extra["merge"] = merge
     out = line(args, value, "updates/s", 1e3 * elapsed / K, "u64" if kind == "tc" else "i32+f64", config,
                roofline_of(prof, wl, order=args.vertex_order), cpu, **extra)
-    print(json.dumps(out), flush=True)
     G.close()
-    return 0
+    return out
+
+
+def host_facts() -> dict:
+    """nproc and CPU model of the host the oracle runs on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "cpu_model": model}
+
+
+# Dijkstra + power iteration time of the last full-graph oracle sample, by graph:
+# the R-MAT 22 lines at 10k and 1M updates reuse it (it does not depend on the
+# batch size) and time only their own edge-list apply.
+_CPU_RECOMPUTE: dict = {}
 
 
 def cpu_single(args, kind, n, s, d, w, batch, k):
@@ -426,17 +482,46 @@ def cpu_single(args, kind, n, s, d, w, batch, k):
         t_cpu = time.perf_counter() - t
         sample = (f"one {k}-update batch ({args.pct:g} of |E|) on the undirected R-MAT recipe at scale {sc}: "
                   f"edge-list apply and a full triangle recount (single thread)")
-    else:
+    elif kind == "grid":
+        # a bounded sample: the same recipe on a quarter-size grid with a quarter of
+        # the batch (the full grid's power iteration alone takes about half a minute)
+        import graphgen
+
+        side = min(args.side, 2048)
+        kk = max(2, k * side * side // (args.side * args.side))
+        if side != args.side:
+            n, s, d, w = graphgen.c2g_graph(side)
+            batch = graphgen.update_batch(n, s, d, kk, graphgen.config_seed(1, 100), wmax=1000)
         t = time.perf_counter()
         s2, d2, w2, _ = oracle.apply(n, s, d, w, *batch)
         oracle.sssp(n, s2, d2, w2, 0)
         oracle.pagerank(n, s2, d2, 0.85, 1e-9, 1000)
         t_cpu = time.perf_counter() - t
-        sample = (f"one {k}-update batch on the full graph: edge-list apply, Dijkstra from 0, FP64 power "
-                  f"iteration to L1 1e-9 (single thread)")
+        k = kk
+        sample = (f"one {kk}-update batch on the {side}x{side} grid recipe: edge-list apply, Dijkstra from 0, "
+                  f"FP64 power iteration to L1 1e-9 (single thread)")
+    else:
+        key = (kind, args.scale)
+        t = time.perf_counter()
+        s2, d2, w2, _ = oracle.apply(n, s, d, w, *batch)
+        t_apply = time.perf_counter() - t
+        if key in _CPU_RECOMPUTE:
+            t_cpu = t_apply + _CPU_RECOMPUTE[key]
+            sample = (f"one {k}-update batch on the full graph: edge-list apply timed "
+                      f"({t_apply:.2f} s), plus the Dijkstra from 0 and FP64 power iteration time of the "
+                      f"100k-update sample on the same graph (single thread)")
+        else:
+            t = time.perf_counter()
+            oracle.sssp(n, s2, d2, w2, 0)
+            oracle.pagerank(n, s2, d2, 0.85, 1e-9, 1000)
+            t_re = time.perf_counter() - t
+            _CPU_RECOMPUTE[key] = t_re
+            t_cpu = t_apply + t_re
+            sample = (f"one {k}-update batch on the full graph: edge-list apply, Dijkstra from 0, FP64 power "
+                      f"iteration to L1 1e-9 (single thread)")
     log(f"cpu oracle: {t_cpu:.1f}s")
     return {"value": round(k / t_cpu, 1), "unit": "updates/s", "cores": 1, "kind": "oracle",
-            "seconds": round(t_cpu, 2), "sample": sample}
+            "seconds": round(t_cpu, 2), "sample": sample, **host_facts()}
 
 
 # ----------------------------------------------------------------------------- batched set
@@ -458,7 +543,7 @@ def set_members(count: int, seed: int):
     return members, ks
 
 
-def run_batched(args) -> int:
+def run_batched(args) -> dict:
     import torch
 
     import graphgen
@@ -552,7 +637,7 @@ def run_batched(args) -> int:
     if not args.no_cpu_baseline:
         import oracle
 
-        sample = min(count, 256)
+        sample = min(count, args.cpu_members)
         t = time.perf_counter()
         upd = 0
         for i in range(sample):
@@ -564,7 +649,7 @@ def run_batched(args) -> int:
         cpu = {"value": round(upd / t_cpu, 1), "unit": "updates/s", "cores": 1, "kind": "oracle",
                "seconds": round(t_cpu, 2),
                "sample": f"the first {sample} members of the set: edge-list apply of each member's batch and "
-                         f"Dijkstra from 0 (single thread)"}
+                         f"Dijkstra from 0 (single thread)", **host_facts()}
         log(f"cpu oracle: {cpu}")
 
     def avg(key):
@@ -584,9 +669,8 @@ def run_batched(args) -> int:
                gteps=gteps_of(stats, elapsed), gteps_counts=GTEPS_COUNTS,
                step_ms=step_spread([x["t_total_ms"] for x in stats]),
                graph_launches=gstats, kernels=kernel_table(prof))
-    print(json.dumps(out), flush=True)
     S.close()
-    return 0
+    return out
 
 
 # ----------------------------------------------------------------------------- serving
@@ -640,7 +724,7 @@ def serve_requests(graphs, seed: int, rate: float, duration: float):
     return reqs
 
 
-def run_serve(args) -> int:
+def run_serve(args) -> dict:
     import torch
 
     import graphgen
@@ -657,8 +741,12 @@ def run_serve(args) -> int:
     log(f"{len(reqs)} requests drawn in {time.perf_counter() - t:.1f}s")
     S = dg.Server(workers=args.workers, budget_bytes=args.budget_gib << 30)
     t = time.perf_counter()
+    gcfg = None
+    if args.diff_only:
+        gcfg = dg.Config()
+        gcfg.diff_only = 1
     for n, s, d, w in graphs:
-        S.add_graph(n, s, d, w)
+        S.add_graph(n, s, d, w, config=gcfg)
     torch.cuda.synchronize()
     log(f"graphs resident in {time.perf_counter() - t:.1f}s")
     S.start()
@@ -690,6 +778,9 @@ def run_serve(args) -> int:
                 continue
             res, _ = S.wait(tk[0])
             results.append((tk[1], res.status, res.t_submit, res.t_start, res.t_end, tk[2]))
+            if res.status != 0:
+                log(f"request {i} (kind {tk[1]}, {tk[2]} updates) failed: [{res.status}] "
+                    f"{res.error.decode(errors='replace')}")
             i += 1
 
     th = threading.Thread(target=collector)
@@ -737,13 +828,13 @@ def run_serve(args) -> int:
                 oracle.triangles(n, u, v)
             upd_c += b[0].size
             done_c += 1
-            if time.perf_counter() - t > 20.0:
+            if time.perf_counter() - t > args.cpu_seconds:
                 break
         t_cpu = time.perf_counter() - t
         cpu = {"value": round(upd_c / t_cpu, 1), "unit": "updates/s", "cores": 1, "kind": "oracle",
                "seconds": round(t_cpu, 2),
                "sample": f"the first {done_c} requests of the stream, each: edge-list apply against the "
-                         f"graph's initial state and a full recompute of its query (single thread)"}
+                         f"graph's initial state and a full recompute of its query (single thread)", **host_facts()}
         log(f"cpu oracle: {cpu}")
 
     config = {"workload": f"serve{count}-rmat12to20-poisson", "graphs": count,
@@ -759,8 +850,7 @@ def run_serve(args) -> int:
                                  "errors": len(bad), "by_kind": by_kind})
     out["steps"] = len(results)
     out["warmup"] = 4
-    print(json.dumps(out), flush=True)
-    return 0
+    return out
 
 
 def main() -> int:
@@ -780,6 +870,10 @@ def main() -> int:
     ap.add_argument("--workers", type=int, default=4, help="serve: worker streams")
     ap.add_argument("--budget-gib", type=int, default=64, help="serve: device-memory admission budget")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-workloads", action="store_true",
+                    help="rmat: skip the other configurations (reported under \"workloads\" by default)")
+    ap.add_argument("--cpu-members", type=int, default=256, help="batched: members in the oracle sample")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0, help="serve: seconds of oracle sample")
     ap.add_argument("--no-static", action="store_true")
     ap.add_argument("--host-batches", action="store_true",
                     help="hand the library host arrays (copied over PCIe inside the timed steps) instead of "
@@ -797,6 +891,8 @@ def main() -> int:
     ap.add_argument("--pr-tile", type=int, default=0, help="rows + entries per pull tile: 1024, 2048 (0) or 4096")
     ap.add_argument("--merge-tile", type=int, default=0,
                     help="rows + entries per merge-path tile of the CSR merge: 512 (0), 1024 or 2048")
+    ap.add_argument("--diff-only", action="store_true",
+                    help="serve: new edges always go to the diff level (no reuse of tombstoned slots)")
     ap.add_argument("--vertex-order", type=int, default=0,
                     help="vertex order inside the library: 0 by degree (default), 1 as given")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -820,10 +916,53 @@ def main() -> int:
               file=sys.stderr)
         return 2
     if args.workload in ("rmat", "grid", "tc"):
-        return run_single(args, args.workload)
-    if args.workload == "batched":
-        return run_batched(args)
-    return run_serve(args)
+        out = run_single(args, args.workload)
+    elif args.workload == "batched":
+        out = run_batched(args)
+    else:
+        out = run_serve(args)
+    if args.workload == "rmat" and not args.no_workloads:
+        out["workloads"] = run_workloads(args)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+# The other configurations, each measured in the same run with fewer steps and a
+# bounded oracle sample, reported under "workloads" of the R-MAT 22 line.
+WORKLOADS = [
+    ("rmat22-10k", "rmat", {"batch": 10_000, "steps": 10, "warmup": 3}),
+    ("rmat22-1M", "rmat", {"batch": 1_000_000, "steps": 5, "warmup": 2}),
+    ("grid4096-100k", "grid", {"batch": 100_000, "steps": 5, "warmup": 2}),
+    ("tc-rmat20-1pct", "tc", {"pct": 0.01, "steps": 10, "warmup": 3}),
+    ("batched4096", "batched", {"steps": 4, "warmup": 2, "cpu_members": 64}),
+    ("serve64", "serve", {"duration": 10.0, "rate": 20.0, "cpu_seconds": 8.0}),
+]
+# keys of a workload line that repeat the R-MAT 22 line's
+_SHARED = ("metric", "n_gpus", "higher_is_better", "scaling", "vs_baseline", "data")
+
+
+def run_workloads(args) -> dict:
+    import copy
+
+    out = {}
+    for name, kind, over in WORKLOADS:
+        a = copy.copy(args)
+        for key, v in over.items():
+            setattr(a, key, v)
+        if kind in ("rmat", "grid"):
+            a.sssp_delta = -1  # the grid's near-far default
+        log(f"---- workload {name}")
+        t = time.perf_counter()
+        if kind in ("rmat", "grid", "tc"):
+            res = run_single(a, kind)
+        elif kind == "batched":
+            res = run_batched(a)
+        else:
+            res = run_serve(a)
+        res = {key: v for key, v in res.items() if key not in _SHARED}
+        res["wall_s"] = round(time.perf_counter() - t, 1)
+        out[name] = res
+    return out
 
 
 if __name__ == "__main__":

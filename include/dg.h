@@ -86,7 +86,14 @@ typedef struct dg_config {
     int32_t sssp_persistent;
     /* PageRank iteration after a batch: 0 = automatic (global dangling-uniform
      * form when the affected set holds >= 20% of the edges, else the local
-     * restricted form), 1 = always local, 2 = always global. */
+     * restricted form), 1 = always local, 2 = always global, 3 = residual push
+     * (the in-place alternative the paper's evaluation discusses): every vertex
+     * keeps the residual of the local system, a batch recomputes it where an
+     * equation changed, and rounds push every vertex whose residual exceeds
+     * tol * sum(x) / (4 n) to its out-neighbours until none does.  Same ranks
+     * within the tolerance; work stays near the batch where the residual fades
+     * before it spreads (long paths, few dangling vertices); last bits vary run
+     * to run (FP64 atomics). */
     int32_t pr_mode;
     /* Whole-graph PageRank pull (static solve and the global form): 0 = merge-path
      * tiles (equal rows + entries per workgroup; column and offset streams read
@@ -358,6 +365,7 @@ typedef struct dg_result {
     double t_submit, t_start, t_end;
     int64_t applied;       /* edges deleted + inserted in the directed graph */
     uint64_t tc;
+    char error[96];        /* message of a failed request (status != DG_OK), else "" */
 } dg_result;
 int dg_server_create(const dg_server_config *cfg, dg_server **out);
 /* Add a directed graph (host arrays; see dg_graph_create) before start. */

@@ -596,7 +596,7 @@ class Request(ctypes.Structure):
 class Result(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("pr_iters", ctypes.c_int32), ("t_submit", ctypes.c_double),
                 ("t_start", ctypes.c_double), ("t_end", ctypes.c_double), ("applied", ctypes.c_int64),
-                ("tc", ctypes.c_uint64)]
+                ("tc", ctypes.c_uint64), ("error", ctypes.c_char * 96)]
 
 
 SSSP, PAGERANK, TRIANGLES = 0, 1, 2

@@ -192,7 +192,7 @@ int dg_graph_create(int32_t n, int64_t m, const int32_t *src, const int32_t *dst
 
 // Device and pinned memory of a query, then the query itself.
 static void query_free(dg_query *q) {
-    q->key.release(); q->inval.release(); q->x.release(); q->xn.release(); q->contrib.release();
+    q->key.release(); q->inval.release(); q->x.release(); q->xn.release(); q->contrib.release(); q->res.release();
     q->qcnt.release(); q->srcs.release(); q->gstamp.release();
     if (q->hpin) (void)hipHostFree(q->hpin);
     if (q->own_cache) {
@@ -294,6 +294,7 @@ int dg_snapshot_save(dg_graph *g, dg_snapshot **out) {
         else if (q->kind == Q_PR) {
             rc = snap_save(sn, q->x, g->n, s);
             if (rc == DG_OK) rc = snap_save(sn, q->contrib, g->n, s);
+            if (rc == DG_OK) rc = snap_save(sn, q->res, q->res.p ? g->n : 0, s);
             sn->scalars.push_back(q->last_iters);
             sn->scalars.push_back(q->converged);
         } else sn->scalars.push_back((int64_t)q->tc);
@@ -321,6 +322,8 @@ int dg_snapshot_restore(dg_graph *g, const dg_snapshot *sn) {
         else if (q->kind == Q_PR) {
             DG_TRY(snap_load(sn, idx, q->x, s));
             DG_TRY(snap_load(sn, idx, q->contrib, s));
+            if (sn->bufs[idx].second > 0) DG_TRY(snap_load(sn, idx, q->res, s));
+            else ++idx;
             q->last_iters = (int32_t)sn->scalars[si++];
             q->converged = (int32_t)sn->scalars[si++];
         } else q->tc = (uint64_t)sn->scalars[si++];

@@ -236,6 +236,7 @@ struct dg_query {
     double damping = 0.85, tol = 1e-9;
     int32_t max_iter = 1000;
     dg::DBuf<double> x, xn, contrib;
+    dg::DBuf<double> res;     // residual of every vertex (residual push, cfg.pr_mode 3)
     int32_t last_iters = 0;
     int32_t converged = 0;
     // triangle count

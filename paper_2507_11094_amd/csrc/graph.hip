@@ -1049,9 +1049,16 @@ __global__ __launch_bounds__(CH_T) void k_revive(int64_t na, const int32_t *aiu,
 #pragma unroll
             for (int q = 0; q < CH_IPT; ++q) look[q] = p[q] != -1;
             find_arcs(off, col, doff, dcol, r, c, look, pb, pd);
+            // A tombstone revived in the forward store may have no counterpart in the
+            // reverse store: each direction reuses its vacant slots on its own, so the
+            // reverse tombstone of this arc may hold another arc by now.  Such an arc
+            // is new to the reverse store (-1: it joins the reverse NEW keys).
 #pragma unroll
             for (int q = 0; q < CH_IPT; ++q)
-                if (p[q] != -1) p[q] = pb[q] >= 0 ? pb[q] : (pd[q] >= 0 ? -2 - pd[q] : -3);
+                if (p[q] != -1) p[q] = pb[q] >= 0 ? pb[q] : (pd[q] >= 0 ? -2 - pd[q] : -1);
+            nnew = 0;
+#pragma unroll
+            for (int q = 0; q < CH_IPT; ++q) nnew += i0 + q < na && p[q] == -1;
         }
         // degree bumps are summed over runs of one row within the thread's elements
         int32_t run_r = -1, run_n = 0;
@@ -1070,7 +1077,6 @@ __global__ __launch_bounds__(CH_T) void k_revive(int64_t na, const int32_t *aiu,
                 dcol[d] = (int32_t)(c[q] | MARK);
                 dw[d] = wt;
             }
-            // p == -3 (slot absent from the reverse store) cannot happen for a consistent graph
             if (r[q] != run_r) {
                 if (run_n) atomicAdd(&deg[run_r], run_n);
                 run_r = r[q];
@@ -1109,6 +1115,9 @@ __device__ __forceinline__ int64_t vacancy_of(const int64_t *__restrict__ off, c
     const int64_t lo = off[u], hi = off[u + 1];
     if (lo == hi) return -1;
     const int64_t p = lower_sorted(col, lo, hi, v);
+    // the key's own tombstone first (a reverse-store arc whose forward tombstone was
+    // revived while this one was not taken): reviving it keeps ids distinct
+    if (p < hi && ((uint32_t)col[p] & (DEAD | ID_MASK)) == (DEAD | v)) return p;
     if (p > lo && ((uint32_t)col[p - 1] & DEAD)) return p - 1;
     if (p < hi && ((uint32_t)col[p] & DEAD)) return p;
     return -1;
@@ -1443,6 +1452,9 @@ int apply_chunk(dg_graph *g, int64_t k, const int32_t *src, const int32_t *dst, 
     DG_TRY(counters_read(g));
     const int64_t revived_base_f = ws.hcnt[C_AUX2];
     const int64_t revived_base_r = und ? 0 : ws.hcnt[C_AUX2 + 8];
+    // arcs new to the reverse store: the forward NEW arcs plus revivals whose reverse
+    // tombstone another arc has taken since
+    const int64_t nnew_r = und ? 0 : ws.hcnt[C_AUX1 + 8];
     const int64_t tcins = ws.hcnt[C_TCINS];
     F.tomb_base += killed_base_f - revived_base_f;
     {
@@ -1454,11 +1466,11 @@ int apply_chunk(dg_graph *g, int64_t k, const int32_t *src, const int32_t *dst, 
     }
     if (!und) {
         R.tomb_base += killed_base_r - revived_base_r;
-        DG_TRY(sort_pairs(g, ws.rkey.p, ws.rkey_s.p, ws.rw.p, ws.rw_s.p, nnew, 2 * B));
+        DG_TRY(sort_pairs(g, ws.rkey.p, ws.rkey_s.p, ws.rw.p, ws.rw_s.p, nnew_r, 2 * B));
         const uint64_t *rk;
         const int32_t *rw;
         int64_t rn;
-        DG_TRY(fill_vacancies(g, R, ws.rkey_s.p, ws.rw_s.p, nnew, &rk, &rw, &rn));
+        DG_TRY(fill_vacancies(g, R, ws.rkey_s.p, ws.rw_s.p, nnew_r, &rk, &rw, &rn));
         DG_TRY(diff_rebuild(g, R, rk, rw, rn, killed_diff_r));
     }
     g->m_live += ains - adel;

@@ -732,9 +732,233 @@ int pr_static_solve(dg_graph *g, double damping, double tol, int32_t max_iter, d
                       contrib, iters, conv);
 }
 
+// ---- residual push (pr_mode 3) ------------------------------------------------------
+// The in-place / residual alternative to the Jacobi sweeps (the paper's
+// evaluation credits in-place PageRank with faster convergence; its Dynamic PR
+// listing iterates only flagged vertices).  It works on the local, dangling-dropped
+// system x = (1-d)/n + d P^T x, whose residual r = (1-d)/n + d P^T x - x the query
+// keeps for every vertex.  Pushing vertex v moves its residual into x[v] and hands
+// d r[v] / outdeg(v) to each out-neighbour's residual, so total residual mass drops
+// by at least (1 - d) r[v] per push.  After a batch, only the vertices whose
+// equation changed get a new residual (heads of changed arcs and out-neighbours of
+// tails whose out-degree changed); rounds push every candidate whose |r| exceeds
+// theta = tol * sum(x) / (4 n) (the next candidates are the out-neighbours of the
+// pushed vertices) until none does, which leaves ||r||_1 <= tol *
+// sum(x) / 4 -- the Jacobi stopping rule (its L1 step is exactly ||r||_1) with
+// room to spare; a final reduction confirms it.  Unlike the Jacobi sweeps, work
+// stays near the batch on graphs whose residual fades before it spreads (long
+// paths, no dangling mass to spread uniformly); on small-diameter graphs it
+// reaches everything like the sweeps.  Sums use FP64 atomics, so the last bits
+// vary from run to run (results stay within the same tolerance).
+
+// r[v] = (1-d)/n + d * sum of contrib over live in-entries - x[v], one wave per
+// vertex of L (L == nullptr: every vertex), in a fixed lane order.
+__global__ __launch_bounds__(256) void k_push_resid(const int32_t *L, int64_t nl, DirView r,
+                                                    const double *__restrict__ contrib, const double *x,
+                                                    double damp, double base, double *res) {
+    const int64_t nwaves = gstride() / WAVE;
+    const int l = lane_id();
+    for (int64_t i = gtid() / WAVE; i < nl; i += nwaves) {
+        const int32_t v = L ? L[i] : (int32_t)i;
+        double acc = 0.0;
+        for (int64_t e = r.off[v] + l; e < r.off[v + 1]; e += WAVE) {
+            const uint32_t c = (uint32_t)r.col[e];
+            if (!(c & DEAD)) acc += contrib[c & ID_MASK];
+        }
+        for (int64_t e = r.doff[v] + l; e < r.doff[v + 1]; e += WAVE) {
+            const uint32_t c = (uint32_t)r.dcol[e];
+            if (!(c & DEAD)) acc += contrib[c & ID_MASK];
+        }
+        acc = wave_sum(acc);
+        if (l == 0) res[v] = base + damp * acc - x[v];
+    }
+}
+
+// Vertices of L (nullptr: all) with |r| > theta, appended once each (stamp st).
+__global__ void k_push_select(const int32_t *L, int64_t nl, const double *res, double theta, int32_t *stamp,
+                              int32_t st, int32_t *out, int64_t *count) {
+    __shared__ BlockScratch sc;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < nl; base += gstride()) {
+        const int64_t i = base + threadIdx.x;
+        bool p = false;
+        int32_t v = 0;
+        if (i < nl) {
+            v = L ? L[i] : (int32_t)i;
+            p = fabs(res[v]) > theta && atomicExch(&stamp[v], st) != st;
+        }
+        const int64_t slot = block_append(count, p, sc);
+        if (p) out[slot] = v;
+    }
+}
+
+// Take the residual of each frontier vertex whose |r| exceeds theta into x (no
+// push of this round is in flight: the expansion that adds to residuals runs
+// after this launch).  The others keep their residual and push nothing (share 0).
+__global__ void k_push_take(const int32_t *F, int64_t nf, double *res, double *x, double *contrib, double *share,
+                            const int32_t *deg, double damp, double theta, int64_t *edges) {
+    __shared__ BlockScratch sc;
+    int64_t e = 0;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < nf; base += gstride()) {
+        const int64_t i = base + threadIdx.x;
+        if (i < nf) {
+            const int32_t v = F[i];
+            const double t = res[v];
+            const int32_t dg = deg[v];
+            if (fabs(t) > theta) {
+                res[v] = 0.0;
+                const double xv = x[v] + t;
+                x[v] = xv;
+                contrib[v] = dg > 0 ? xv / (double)dg : 0.0;
+                share[v] = dg > 0 ? damp * t / (double)dg : 0.0;
+                e += dg;
+            } else {
+                share[v] = 0.0;
+            }
+        }
+    }
+    block_count(edges, e, sc);
+}
+
+// Hand each pushed vertex's share to its out-neighbours (atomics whose result is
+// not needed); every neighbour joins the next round's candidates (once, stamp
+// st), where the take decides whether its residual is worth pushing.
+struct PushOp {
+    double *res;
+    const double *share;
+    int32_t *stamp;
+    int32_t st;
+    int32_t *next;
+    int64_t *ncount;
+    __device__ bool vtx(int32_t v, int32_t &pay) const {
+        pay = 0;
+        return share[v] != 0.0;
+    }
+    __device__ bool edge(bool valid, int32_t v, int32_t, int32_t x, int32_t) const {
+        if (!valid) return false;
+        unsafeAtomicAdd(&res[x], share[v]);
+        // plain load first: most neighbours are already candidates
+        return stamp[x] != st && atomicExch(&stamp[x], st) != st;
+    }
+    __device__ SinkTarget sink() const { return SinkTarget{next, ncount}; }
+};
+
+__global__ __launch_bounds__(256) void k_abs_sum(const double *x, int64_t n, double *partials) {
+    __shared__ double red[256];
+    double acc = 0.0;
+    for (int64_t i = gtid(); i < n; i += gstride()) acc += fabs(x[i]);
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
+}
+
 static double tol_of(dg_query *q) {
     double sc = q->g->cfg.pr_tol_scale > 0 ? q->g->cfg.pr_tol_scale : 1.0;
     return q->tol * sc;
+}
+
+static int pr_mass(dg_query *q, double *S);
+
+// sum |v| over n entries into *out (fixed block order).
+static int abs_sum(dg_graph *g, const double *v, double *out) {
+    hipStream_t s = g->stream;
+    double *partials = g->ws.part.p;
+    double *dsum = reinterpret_cast<double *>(g->ws.dcnt + C_RED0);
+    hipLaunchKernelGGL(k_abs_sum, dim3(APPLY_GROUPS), dim3(256), 0, s, v, (int64_t)g->n, partials);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, partials, APPLY_GROUPS, dsum);
+    DG_HIP(hipGetLastError());
+    DG_TRY(counters_read(g));
+    std::memcpy(out, g->ws.hcnt + C_RED0, sizeof(double));
+    return DG_OK;
+}
+
+// Residual push from the residuals of L (recomputed first; L == nullptr with
+// nl == n: every vertex) until no |r| exceeds theta and ||r||_1 <= tol * sum(x).
+static int pr_push_run(dg_query *q, const int32_t *L, int64_t nl, dg_batch_stats *st) {
+    dg_graph *g = q->g;
+    hipStream_t s = g->stream;
+    Work &ws = g->ws;
+    DG_TRY(ensure_pr_ws(g));
+    DG_TRY(q->res.ensure((size_t)g->n + 1));
+    const double d = q->damping, base = (1.0 - d) / (double)g->n;
+    double S = 0.0;
+    DG_TRY(pr_mass(q, &S));
+    const double tol = tol_of(q) * S;
+    const double theta = tol / (4.0 * (double)g->n);
+    if (nl > 0)
+        hipLaunchKernelGGL(k_push_resid, dim3(grid_for(nl * WAVE)), dim3(256), 0, s, L, nl, view(*g->rev),
+                           q->contrib.p, q->x.p, d, base, q->res.p);
+    DG_HIP(hipGetLastError());
+    int32_t *F = ws.f0.p, *N = ws.f1.p;
+    int32_t stamp;
+    DG_TRY(next_stamp(g, &stamp));
+    DG_TRY(counters_clear(g));
+    if (nl > 0)
+        hipLaunchKernelGGL(k_push_select, dim3(grid_for(nl)), dim3(256), 0, s, L, nl, q->res.p, theta, ws.stamp.p,
+                           stamp, F, ws.dcnt + C_F0);
+    DG_HIP(hipGetLastError());
+    DG_TRY(counters_read(g));
+    int64_t nf = ws.hcnt[C_F0];
+    int32_t rounds = 0, conv = 0;
+    int64_t edges = 0;
+    ExpandArgs a;
+    a.g = view(g->fwd);
+    a.hq = reinterpret_cast<int64_t *>(ws.heavy.p);
+    a.hcount = ws.dcnt + C_HEAVY;
+    a.heavy_deg = heavy_deg(g);
+    a.chunk = heavy_deg(g);
+    double *share = q->xn.p;  // scratch between calls
+    for (;;) {
+        while (nf > 0 && rounds < q->max_iter) {
+            DG_TRY(counters_clear(g));
+            const int ps = prof_begin("pr_push", s);
+            hipLaunchKernelGGL(k_push_take, dim3(grid_for(nf)), dim3(256), 0, s, F, nf, q->res.p, q->x.p,
+                               q->contrib.p, share, g->fwd.deg.p, d, theta, ws.dcnt + C_AUX0);
+            DG_HIP(hipGetLastError());
+            DG_TRY(next_stamp(g, &stamp));
+            a.F = F;
+            a.nf = nf;
+            PushOp op{q->res.p, share, ws.stamp.p, stamp, N, ws.dcnt + C_F1};
+            DG_TRY(launch_expand(s, a, op, 8192));
+            DG_TRY(counters_read(g));
+            // per pushed vertex: F entry 4, residual 8 read + 8 written, x 8 + 8, contrib 8, share 8,
+            // degree 4 and offsets 16; per arc: col 4, residual atomic 8 + 8
+            prof_end(ps, s, 0.0);
+            prof_add(ps, 72.0 * (double)nf + 20.0 * (double)ws.hcnt[C_AUX0]);
+            edges += ws.hcnt[C_AUX0];
+            nf = ws.hcnt[C_F1];
+            std::swap(F, N);
+            ++rounds;
+        }
+        double r1 = 0.0;
+        DG_TRY(abs_sum(g, q->res.p, &r1));
+        DG_TRY(pr_mass(q, &S));
+        if (r1 <= tol_of(q) * S) {
+            conv = 1;
+            break;
+        }
+        if (rounds >= q->max_iter) break;
+        // residual left above the bound (the threshold of earlier batches differed):
+        // push every vertex above theta
+        DG_TRY(next_stamp(g, &stamp));
+        DG_TRY(counters_clear(g));
+        hipLaunchKernelGGL(k_push_select, dim3(grid_for(g->n)), dim3(256), 0, s, (const int32_t *)nullptr,
+                           (int64_t)g->n, q->res.p, theta, ws.stamp.p, stamp, F, ws.dcnt + C_F0);
+        DG_HIP(hipGetLastError());
+        DG_TRY(counters_read(g));
+        nf = ws.hcnt[C_F0];
+        if (nf == 0) break;
+    }
+    q->last_iters = rounds;
+    q->converged = conv;
+    if (st) {
+        st->pr_iterations += rounds;
+        st->edges_traversed += edges;
+    }
+    return DG_OK;
 }
 
 int pr_init(dg_query *q) {
@@ -742,8 +966,15 @@ int pr_init(dg_query *q) {
     DG_TRY(q->x.ensure((size_t)g->n + 1));
     DG_TRY(q->xn.ensure((size_t)g->n + 1));
     DG_TRY(q->contrib.ensure((size_t)g->n + 1));
-    return pr_static_solve(g, q->damping, tol_of(q), q->max_iter, q->x.p, q->contrib.p, q->xn.p,
-                           &q->last_iters, &q->converged);
+    DG_TRY(pr_static_solve(g, q->damping, tol_of(q), q->max_iter, q->x.p, q->contrib.p, q->xn.p,
+                           &q->last_iters, &q->converged));
+    // residual push keeps the residual of every vertex from here on
+    if (g->cfg.pr_mode == 3) {
+        const int32_t it = q->last_iters;
+        DG_TRY(pr_push_run(q, nullptr, g->n, nullptr));
+        q->last_iters += it;
+    }
+    return DG_OK;
 }
 
 static int pr_update(dg_query *q, int64_t adel, int64_t ains, dg_batch_stats *st, SideWork *side);
@@ -808,7 +1039,7 @@ static int pr_update(dg_query *q, int64_t adel, int64_t ains, dg_batch_stats *st
     hipLaunchKernelGGL(k_refresh_contrib, dim3(grid_for(ns)), dim3(256), 0, s, ns, S, q->x.p, g->fwd.deg.p,
                        q->contrib.p);
     DG_HIP(hipGetLastError());
-    const int mode = g->cfg.pr_mode;  // 0 auto, 1 local, 2 global
+    const int mode = g->cfg.pr_mode;  // 0 auto, 1 local, 2 global, 3 residual push
     const int64_t vlimit = (int64_t)(0.2 * (double)g->n);
     bool global = mode == 2;
     if (mode == 0) {
@@ -851,6 +1082,12 @@ static int pr_update(dg_query *q, int64_t adel, int64_t ains, dg_batch_stats *st
         DG_TRY(launch_expand(s, a, op, 8192));
         DG_TRY(counters_read(g));
         na += ws.hcnt[C_F1];
+        if (mode == 3) {
+            // residual push from the seeds instead of the reach closure and sweeps
+            DG_TRY(pr_push_run(q, Alist, na, st));
+            if (st) st->pr_affected += na;
+            return DG_OK;
+        }
         if (mode == 0 && na >= vlimit) global = true;
     }
     // forward closure (propagateNodeFlags): levels appended to Alist.  In the
@@ -1064,6 +1301,10 @@ int pr_import(dg_query *q, const double *xh) {
                       Ssum, q->x.p, q->xn.p, q->contrib.p, &iters, &conv));
     q->last_iters = iters;
     q->converged = conv;
+    if (g->cfg.pr_mode == 3) {
+        DG_TRY(pr_push_run(q, nullptr, g->n, nullptr));
+        q->last_iters += iters;
+    }
     return DG_OK;
 }
 

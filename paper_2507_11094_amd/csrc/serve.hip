@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
+#include <cstdio>
 #include <cstring>
 #include <deque>
 #include <mutex>
@@ -78,6 +79,7 @@ struct Req {
     uint64_t tc = 0;
     int32_t pr_iters = 0;
     int64_t applied = 0;
+    char error[96] = "";  // the worker's error message when status != DG_OK
 };
 
 struct Entry {
@@ -202,6 +204,7 @@ void worker(dg_server *S, size_t wi) {
         lk.lock();
         r->t_end = S->now();
         r->status = rc;
+        if (rc != DG_OK) std::snprintf(r->error, sizeof(r->error), "%s", dg_last_error());
         r->done = true;
         E.busy = false;
         S->inflight_bytes -= r->bytes;
@@ -322,6 +325,7 @@ static void fill_result(const Req *r, dg_result *res) {
     res->applied = r->applied;
     res->tc = r->tc;
     res->pr_iters = r->pr_iters;
+    std::memcpy(res->error, r->error, sizeof(res->error));
 }
 
 int dg_server_wait(dg_server *S, int64_t ticket, double timeout_s, dg_result *res) {

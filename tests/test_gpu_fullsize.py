@@ -142,6 +142,27 @@ def test_fullsize_grid_sssp_pagerank():
     assert err <= 1e-10
 
 
+def test_fullsize_grid_pagerank_residual_push():
+    """4096 x 4096 grid, one 10k batch, PageRank by residual push (pr_mode 3):
+    within max-abs 1e-10 of the oracle's power iteration."""
+    n, s, d, w = graphgen.c2g_graph(4096)
+    b = batches_for(n, s, d, 10000, 1, 1, 1000)[0]
+    say("grid 4096^2 PageRank residual push, one 10k batch")
+    c = dg.Config()
+    c.pr_mode = 3
+    G = dg.Graph(n, s, d, w, config=c)
+    qp = G.pr_attach(0.85, 1e-9, 1000)
+    st = G.apply(*b)
+    rank, it, conv = qp.read()
+    G.close()
+    say("push rounds", it, "arcs pushed", st.edges_traversed)
+    cs, cd, cw, _ = oracle.apply(n, s, d, w, *b)
+    want, _, oconv = oracle.pagerank(n, cs, cd, 0.85, 1e-9, 1000)
+    err = float(np.max(np.abs(rank - want)))
+    say("grid push PageRank max-abs vs oracle", err)
+    assert conv and oconv and err <= 1e-10
+
+
 def test_fullsize_tc_rmat20_against_golden_counts():
     gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "tc_rmat20.json")))
     t0 = time.perf_counter()

@@ -171,6 +171,70 @@ def test_vacancy_reuse_matches_diff_only(undirected):
     assert filled > 0
 
 
+@pytest.mark.parametrize("diff_only", [0, 1])
+def test_reinsert_after_reverse_vacancy_taken(diff_only):
+    """Directed graph: u->v is deleted (tombstones in u's forward row and v's
+    reverse row), then w->v takes v's reverse vacancy (w sits next to u in v's
+    row), then u->v is inserted again: its forward tombstone is revived while its
+    reverse slot is gone, so the reverse store takes it as a new arc.  A merge then
+    rebuilds both directions; the edge set, SSSP and PageRank equal the oracle.
+    (A serving run of batches followed by their inverses met this case.)"""
+    say("re-insert after the reverse vacancy was taken, diff_only", diff_only)
+    n = 64
+    rng = np.random.default_rng(5)
+    pairs = set()
+    while len(pairs) < 400:
+        a, b = int(rng.integers(0, n)), int(rng.integers(0, n))
+        if a != b:
+            pairs.add((a, b))
+    pairs.discard((11, 40))
+    pairs |= {(10, 40), (12, 40), (10, 41)}
+    s = np.array([p[0] for p in sorted(pairs)], np.int32)
+    d = np.array([p[1] for p in sorted(pairs)], np.int32)
+    w = rng.integers(1, 50, size=s.size).astype(np.int32)
+    c = cfg(merge=1e9)
+    c.diff_only = diff_only
+    c.vertex_order = 1
+    G = dg.Graph(n, s, d, w, config=c)
+    qs = G.sssp_attach(10)
+    qp = G.pr_attach(0.85, PR_TOL, 1000)
+    cs, cd, cw = s, d, w
+    steps = [
+        ([10], [40], [0], [0]),          # delete 10->40: vacancies at 10's row and at 40's reverse row
+        ([11], [40], [7], [1]),          # 11->40 is new; in 40's reverse row 11 sits right after 10
+        ([10, 3], [40, 9], [5, 2], [1, 1]),  # 10->40 again: forward revive, reverse slot taken
+    ]
+    for b in steps:
+        b = tuple(np.asarray(x, dt) for x, dt in zip(b, (np.int32, np.int32, np.int32, np.uint8)))
+        G.apply(*b)
+        cs, cd, cw, _ = oracle.apply(n, cs, cd, cw, *b)
+        assert_edges(G, cs, cd, cw)
+    G.merge()
+    assert_edges(G, cs, cd, cw)
+    assert np.array_equal(qs.read()[0], oracle.sssp(n, cs, cd, cw, 10))
+    want, _, _ = oracle.pagerank(n, cs, cd, 0.85, PR_TOL, 1000)
+    assert float(np.max(np.abs(qp.read()[0] - want))) <= PR_MAXABS
+    # and a longer run of batches followed by their exact inverses, with merges
+    m0 = G.info()["m"]
+    for i in range(6):
+        b = graphgen.update_batch(n, cs, cd, 60, graphgen.config_seed(0, 900 + i))
+        dels = b[3] == 0
+        keys = (cs.astype(np.int64) << 32) | cd
+        pos = np.searchsorted(keys, (b[0][dels].astype(np.int64) << 32) | b[1][dels])
+        inv_w = np.zeros(b[0].size, np.int32)
+        inv_w[dels] = cw[pos]
+        inv = (b[0], b[1], inv_w, dels.astype(np.uint8))
+        for bb in (b, inv):
+            G.apply(*bb)
+            cs, cd, cw, _ = oracle.apply(n, cs, cd, cw, *bb)
+            assert_edges(G, cs, cd, cw)
+        if i == 3:
+            G.merge()
+    assert G.info()["m"] == m0
+    assert np.array_equal(qs.read()[0], oracle.sssp(n, cs, cd, cw, 10))
+    G.close()
+
+
 @pytest.mark.parametrize("merge", [0.0, -1.0, 1e9])
 def test_batch_sequence_matches_oracle(merge):
     n, s, d, w = rmat_small(11, 16, 21)
@@ -875,3 +939,100 @@ def test_merge_period():
         assert_edges(G, cs, cd, cw)
         assert np.array_equal(q.read()[0], oracle.sssp(n, cs, cd, cw, 0))
     assert merged == [0, 0, 1, 0, 0, 1, 0]
+
+# ------------------------------------------------------------------ residual push (pr_mode 3)
+
+def pr_cfg(mode, **kw):
+    c = cfg(**kw)
+    c.pr_mode = mode
+    return c
+
+
+@pytest.mark.parametrize("kind", ["rmat", "grid", "undirected"])
+def test_pagerank_residual_push_matches_oracle(kind):
+    """Residual push after each batch: ranks within max-abs 1e-10 of the oracle's
+    power iteration, converged, on a directed R-MAT with dangling vertices, a grid
+    (batches with long-range inserts) and an undirected graph, with SSSP attached
+    on the directed ones (it runs after the push)."""
+    say("pagerank residual push", kind)
+    und = kind == "undirected"
+    if kind == "rmat":
+        n, s, d, w = rmat_small(12, 8, 81)
+        sizes = [400, 40, 4, 1200]
+    elif kind == "grid":
+        n, s, d, w = graphgen.c2g_graph(96)
+        sizes = [60, 6, 600, 1]
+    else:
+        n, s, d = graphgen.rmat_undirected(11, 8 << 11, graphgen.config_seed(2, 81))
+        w = None
+        sizes = [300, 30, 3]
+    # the undirected R-MAT has hundreds of degree-one vertices: the reading of the
+    # tolerance pair that its all-queries test follows applies (steps at a
+    # hundredth of the tolerance, ranks pinned to the tight oracle)
+    G = dg.Graph(n, s, d, w, undirected=und, config=pr_cfg(3, tol_scale=0.01 if und else 0.0))
+    otol = 1e-14 if und else PR_TOL
+    qp = G.pr_attach(0.85, PR_TOL, 1000)
+    qs = None if und else G.sssp_attach(0)
+    cs, cd, cw = s, d, (w if w is not None else np.ones(s.size, np.int32))
+
+    def arcs(a, b):  # an undirected edge is an arc each way for PageRank
+        return (np.concatenate([a, b]), np.concatenate([b, a])) if und else (a, b)
+
+    rank, _, conv = qp.read()
+    want, _, _ = oracle.pagerank(n, *arcs(cs, cd), 0.85, otol, 1000)
+    assert conv and float(np.max(np.abs(rank - want))) <= PR_MAXABS
+    for i, k in enumerate(sizes):
+        b = graphgen.update_batch(n, cs, cd, k, graphgen.config_seed(0, 810 + i), wmax=1000 if kind == "grid" else 100,
+                                  undirected=und)
+        st = G.apply(*b)
+        cs, cd, cw, _ = oracle.apply(n, cs, cd, cw, *b, undirected=und)
+        rank, it, conv = qp.read()
+        want, _, oconv = oracle.pagerank(n, *arcs(cs, cd), 0.85, otol, 1000)
+        err = float(np.max(np.abs(rank - want)))
+        say("  batch", i, "k", k, "rounds", it, "pushed arcs", st.edges_traversed, "max-abs", err)
+        assert conv and oconv and err <= PR_MAXABS
+        assert abs(float(rank.sum()) - 1.0) <= 1e-12
+        if qs is not None:
+            assert np.array_equal(qs.read()[0], oracle.sssp(n, cs, cd, cw, 0))
+    G.close()
+
+
+def test_pagerank_residual_push_stays_local_on_grid():
+    """On a grid (no dangling mass, long paths) a small batch's push examines far
+    fewer arcs than the sweeps of the global form, which pull every arc per step;
+    both land within the tolerance of the oracle."""
+    n, s, d, w = graphgen.c2g_graph(128)
+    b = graphgen.update_batch(n, s, d, 4, graphgen.config_seed(0, 820), wmax=1000)
+    cs, cd, cw, _ = oracle.apply(n, s, d, w, *b)
+    want, _, _ = oracle.pagerank(n, cs, cd, 0.85, PR_TOL, 1000)
+    say("residual push locality on a 128^2 grid, 4 updates")
+    arcs = {}
+    for mode in (2, 3):
+        G = dg.Graph(n, s, d, w, config=pr_cfg(mode))
+        qp = G.pr_attach(0.85, PR_TOL, 1000)
+        st = G.apply(*b)
+        rank, _, conv = qp.read()
+        assert conv and float(np.max(np.abs(rank - want))) <= PR_MAXABS
+        arcs[mode] = st.edges_traversed
+        G.close()
+    say("  arcs examined: global sweeps", arcs[2], "push", arcs[3])
+    assert 0 < arcs[3] < arcs[2] / 3
+
+
+def test_pagerank_residual_push_snapshot_restore():
+    n, s, d, w = rmat_small(11, 8, 83)
+    b1 = graphgen.update_batch(n, s, d, 300, graphgen.config_seed(0, 830))
+    say("residual push snapshot/restore")
+    G = dg.Graph(n, s, d, w, config=pr_cfg(3))
+    qp = G.pr_attach(0.85, PR_TOL, 1000)
+    G.snapshot()
+    G.apply(*b1)
+    r1, _, _ = qp.read()
+    G.restore()
+    G.apply(*b1)
+    r2, _, _ = qp.read()
+    cs, cd, _, _ = oracle.apply(n, s, d, w, *b1)
+    want, _, _ = oracle.pagerank(n, cs, cd, 0.85, PR_TOL, 1000)
+    assert float(np.max(np.abs(r1 - want))) <= PR_MAXABS and float(np.max(np.abs(r2 - want))) <= PR_MAXABS
+    assert float(np.max(np.abs(r1 - r2))) <= 1e-13  # atomics reorder sums: equal up to rounding
+    G.close()
