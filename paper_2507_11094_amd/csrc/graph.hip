@@ -1242,7 +1242,15 @@ static int diff_rebuild(dg_graph *g, Dir &d, const uint64_t *nkey, const int32_t
     const int64_t live = dm - killed;
     const int64_t dm2 = live + nk;
     if ((size_t)dm2 + 1 > d.dkey2.cap) {
-        const size_t want = std::max((size_t)dm2 + 1, 2 * d.dkey2.cap);
+        // Both generations of the level (it alternates with its spare every batch)
+        // are sized at their first growth for a full level at the merge threshold,
+        // plus two batches: otherwise a level that grows by one batch's new keys
+        // each time reallocates almost every batch, and each free synchronises
+        // the device.  (A threshold outside (0, 1) falls back to doubling.)
+        size_t want = std::max((size_t)dm2 + 1, 2 * d.dkey2.cap);
+        const double thr = g->cfg.merge_threshold;
+        if (thr > 0.0 && thr < 1.0)
+            want = std::max(want, (size_t)(thr * (double)std::max<int64_t>(g->m_live, 1)) + 2 * (size_t)nk + 1);
         DG_TRY(d.dkey2.ensure(want));
         DG_TRY(d.dcol2.ensure(want));
         DG_TRY(d.dw2.ensure(want));
