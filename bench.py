@@ -30,6 +30,7 @@ One GPU only.
 from __future__ import annotations
 
 import argparse
+import ctypes
 import hashlib
 import re
 import json
@@ -900,14 +901,29 @@ def main() -> int:
                          "FETCH_SIZE / WRITE_SIZE counter scale) and exit")
     args = ap.parse_args()
     if args.calibrate_copy:
+        # Known-traffic launches for scaling the FETCH_SIZE / WRITE_SIZE counters:
+        # five plain 256 MiB device copies (torch), then the library's calibration
+        # kernels on a 1 GiB buffer: a stream read, a stream write and a gather of
+        # one word per 128-byte line (8 Mi lines).
         import torch
+
+        import paper_2507_11094_amd as dg
 
         a = torch.ones(256 << 20, dtype=torch.uint8, device="cuda:0")
         b = torch.empty_like(a)
         for _ in range(5):
             b.copy_(a)
         torch.cuda.synchronize()
-        print(json.dumps({"calibrate_copy_bytes": int(a.numel()), "copies": 5}), flush=True)
+        del a, b
+        big = torch.ones(1 << 30, dtype=torch.uint8, device="cuda:0")
+        lib = dg.load_library()
+        for kind in (0, 1, 2):
+            for _ in range(3):
+                dg._check(lib.dg_calibrate(kind, ctypes.c_void_p(big.data_ptr()), big.numel(), None))
+        print(json.dumps({"calibrate_copy_bytes": 256 << 20, "copies": 5, "calibrate_kernel_bytes": 1 << 30,
+                          "kernels": {"k_cal_read": "reads 1 GiB", "k_cal_write": "writes 1 GiB",
+                                      "k_cal_gather": "reads one word of each of 8 Mi 128-byte lines"}}),
+              flush=True)
         return 0
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

@@ -439,6 +439,16 @@ int dg_sort_pairs(const uint64_t *kin, uint64_t *kout, const int32_t *vin, int32
                   void *stream);
 int dg_scan_exclusive(const int64_t *in, int64_t *out, int64_t n, void *stream);
 
+/* ---- measurement ---------------------------------------------------------------------- */
+
+/* Kernels with known memory traffic, for scaling hardware byte counters (the
+ * roofline figures of the Experimental Evaluation comparisons rest on them):
+ * kind 0 reads `bytes` bytes of device buffer `buf` once, kind 1 writes them once,
+ * kind 2 reads one 4-byte word from each 128-byte line of them.  bytes must be a
+ * multiple of 4 KiB; the buffer's contents are overwritten (kinds 1, 2) or kept
+ * (kind 0).  Runs on `stream` (NULL: null stream) and returns when done. */
+int dg_calibrate(int32_t kind, void *buf, int64_t bytes, void *stream);
+
 /* ---- static recompute on the current graph (comparators) -------------------------- */
 
 /* The "static" baseline of the paper's Experimental Evaluation section: the

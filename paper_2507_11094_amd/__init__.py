@@ -40,7 +40,7 @@ EXPORTS = (
     "dg_graph_set_stream", "dg_graph_info", "dg_graph_export", "dg_graph_merge",
     "dg_apply_batch", "dg_snapshot_save", "dg_snapshot_restore", "dg_snapshot_free",
     "dg_sssp_attach", "dg_pr_attach", "dg_tc_attach", "dg_query_detach", "dg_sssp_read",
-    "dg_query_export", "dg_query_import", "dg_pr_read_noalloc", "dg_sort_pairs", "dg_scan_exclusive",
+    "dg_query_export", "dg_query_import", "dg_pr_read_noalloc", "dg_sort_pairs", "dg_scan_exclusive", "dg_calibrate",
     "dg_pr_read", "dg_tc_read", "dg_sssp_static", "dg_pr_static", "dg_tc_static",
     "dg_profile_enable", "dg_profile_reset", "dg_profile_read",
     "dg_set_create", "dg_set_destroy", "dg_set_info", "dg_set_sssp_attach", "dg_set_apply_sssp",
@@ -133,6 +133,7 @@ def load_library() -> ctypes.CDLL:
         "dg_pr_read_noalloc": ([P, P, P, P, U32], ctypes.c_int),
         "dg_sort_pairs": ([P, P, P, P, I64, I32, P], ctypes.c_int),
         "dg_scan_exclusive": ([P, P, I64, P], ctypes.c_int),
+        "dg_calibrate": ([I32, P, I64, P], ctypes.c_int),
         "dg_query_import": ([P, P, I64, ctypes.POINTER(P)], ctypes.c_int),
         "dg_sssp_static": ([P, I32, P, P, U32], ctypes.c_int),
         "dg_pr_static": ([P, D, D, I32, P, P, U32], ctypes.c_int),

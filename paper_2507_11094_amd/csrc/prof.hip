@@ -117,6 +117,61 @@ void prof_add(int slot, double bytes) {
     if (p) p->bytes += bytes;
 }
 
+
+// ---- counter calibration ----------------------------------------------------------------
+// Kernels with a known number of bytes, to scale the hardware byte counters
+// (FETCH_SIZE, WRITE_SIZE) that the roofline's traffic figures come from:
+//   kind 0: read every 16-byte word of the buffer once (a stream of `bytes` bytes);
+//   kind 1: write every 16-byte word once;
+//   kind 2: read one 4-byte word from each 128-byte line (bytes / 128 lines).
+// Each workgroup writes one 16-byte word of its reduction (kinds 0, 2) at the
+// buffer's start, so the extra writes stay below 16 bytes per workgroup.
+__global__ __launch_bounds__(256) void k_cal_read(const int4 *__restrict__ p, int64_t n16, int4 *sink) {
+    int4 acc = make_int4(0, 0, 0, 0);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += (int64_t)gridDim.x * blockDim.x) {
+        const int4 v = p[i];
+        acc.x ^= v.x; acc.y ^= v.y; acc.z ^= v.z; acc.w ^= v.w;
+    }
+    __shared__ int s[4];
+    if (threadIdx.x < 4) s[threadIdx.x] = 0;
+    __syncthreads();
+    atomicXor(&s[0], acc.x); atomicXor(&s[1], acc.y); atomicXor(&s[2], acc.z); atomicXor(&s[3], acc.w);
+    __syncthreads();
+    if (threadIdx.x == 0 && (s[0] | s[1] | s[2] | s[3]) == 0x7fffffff) sink[blockIdx.x] = make_int4(s[0], s[1], s[2], s[3]);
+}
+__global__ __launch_bounds__(256) void k_cal_write(int4 *p, int64_t n16) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = make_int4((int)i, 1, 2, 3);
+}
+__global__ __launch_bounds__(256) void k_cal_gather(const int32_t *__restrict__ p, int64_t nlines, int32_t *sink) {
+    int acc = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nlines; i += (int64_t)gridDim.x * blockDim.x)
+        acc ^= p[i * 32 + (i & 31)];
+    if (acc == 0x7fffffff) sink[0] = acc;
+}
+
+}  // namespace dg
+
+extern "C" int dg_calibrate(int32_t kind, void *buf, int64_t bytes, void *stream) {
+    using namespace dg;
+    if (!buf || bytes < 4096 || (bytes & 4095) || kind < 0 || kind > 2)
+        return set_error(DG_EINVAL, "calibration needs kind 0..2 and a device buffer of a multiple of 4 KiB");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int blocks = 4096;
+    if (kind == 0)
+        hipLaunchKernelGGL(k_cal_read, dim3(blocks), dim3(256), 0, s, static_cast<const int4 *>(buf), bytes / 16,
+                           static_cast<int4 *>(buf));
+    else if (kind == 1)
+        hipLaunchKernelGGL(k_cal_write, dim3(blocks), dim3(256), 0, s, static_cast<int4 *>(buf), bytes / 16);
+    else
+        hipLaunchKernelGGL(k_cal_gather, dim3(blocks), dim3(256), 0, s, static_cast<const int32_t *>(buf),
+                           bytes / 128, static_cast<int32_t *>(buf));
+    DG_HIP(hipGetLastError());
+    DG_HIP(hipStreamSynchronize(s));
+    return DG_OK;
+}
+
+namespace dg {
 }  // namespace dg
 
 extern "C" {
