@@ -1036,3 +1036,31 @@ def test_pagerank_residual_push_snapshot_restore():
     assert float(np.max(np.abs(r1 - want))) <= PR_MAXABS and float(np.max(np.abs(r2 - want))) <= PR_MAXABS
     assert float(np.max(np.abs(r1 - r2))) <= 1e-13  # atomics reorder sums: equal up to rounding
     G.close()
+
+
+def test_tc_random_sequences_match_recount():
+    """Random batch sequences on small undirected graphs (merge thresholds 0.05,
+    every batch, never and 0.2; slot reuse on and off; every third batch followed
+    by its exact inverse): after every batch the maintained count equals the
+    static forward recount, and after each sequence the oracle's count."""
+    rng = np.random.default_rng(17)
+    for trial in range(16):
+        sc = int(rng.integers(7, 12))
+        n, u, v = graphgen.rmat_undirected(sc, int(rng.integers(4, 16)) << sc, int(rng.integers(1, 1 << 30)))
+        c = cfg(merge=float(rng.choice([0.05, -1.0, 1e9, 0.2])))
+        c.diff_only = int(rng.integers(0, 2))
+        say("tc random sequence", trial, "scale", sc, "merge", c.merge_threshold, "diff_only", c.diff_only)
+        G = dg.Graph(n, u, v, None, undirected=True, config=c)
+        q = G.tc_attach()
+        cu, cv = u, v
+        for i in range(10):
+            k = int(np.exp(rng.uniform(np.log(4), np.log(min(2000, max(8, cu.size))))))
+            b = graphgen.update_batch(n, cu, cv, k, int(rng.integers(1, 1 << 30)), undirected=True)
+            inv = (b[0].copy(), b[1].copy(), np.ones(b[0].size, np.int32), (b[3] == 0).astype(np.uint8))
+            for bb in ((b, inv) if i % 3 == 0 else (b,)):
+                G.apply(*bb)
+                cu, cv, _, _ = oracle.apply(n, cu, cv, None, *bb, undirected=True)
+                assert q.read() == G.tc_static(), (trial, i)
+        assert q.read() == oracle.triangles(n, cu, cv), trial
+        G.close()
+
