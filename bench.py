@@ -323,6 +323,7 @@ def run_single(args, kind: str) -> dict:
     cfg.pr_tile = args.pr_tile
     cfg.merge_tile = args.merge_tile
     cfg.vertex_order = args.vertex_order
+    cfg.pr_extrapolate = 0 if args.pr_plain else 1
     t = time.perf_counter()
     G = dg.Graph(n, s, d, w, undirected=undirected, config=cfg)
     log(f"graph built on device in {time.perf_counter() - t:.2f}s")
@@ -412,7 +413,8 @@ def run_single(args, kind: str) -> dict:
     config = {"workload": wl, "vertices": n, "arcs": int(s.size) * (2 if undirected else 1),
               "batch": k, "insert_fraction": 0.5, "parallelism": "1 gpu",
               "heavy_degree": args.heavy_degree or 512, "sssp_persistent": persistent, "sssp_delta": delta,
-              "pr_mode": args.pr_mode, "vertex_order": ["by degree", "as given"][args.vertex_order],
+              "pr_mode": args.pr_mode, "pr_steps": "plain Jacobi" if args.pr_plain else "extrapolated Jacobi",
+              "vertex_order": ["by degree", "as given"][args.vertex_order],
               "batches_in": "host memory (copied inside the timed steps)" if args.host_batches else "HBM",
               "pr_pull": ["merge-path tiles, non-temporal streams", "vertex waves", "merge-path tiles"][args.pr_pull]}
     if kind == "tc":
@@ -894,6 +896,8 @@ def main() -> int:
                     help="rows + entries per merge-path tile of the CSR merge: 512 (0), 1024 or 2048")
     ap.add_argument("--diff-only", action="store_true",
                     help="serve: new edges always go to the diff level (no reuse of tombstoned slots)")
+    ap.add_argument("--pr-plain", action="store_true",
+                    help="plain Jacobi PageRank steps (default: extrapolated steps, same stopping rule)")
     ap.add_argument("--vertex-order", type=int, default=0,
                     help="vertex order inside the library: 0 by degree (default), 1 as given")
     ap.add_argument("--calibrate-copy", action="store_true",

@@ -127,6 +127,17 @@ typedef struct dg_config {
      * smallest takes it), else in the diff level (default); 1 = always in the diff
      * level (a slot of the same edge is still revived). */
     int32_t diff_only;
+    /* Jacobi PageRank steps: 0 = plain steps, as in the Appendix A listings
+     * (default); 1 = extrapolated steps: when two successive step vectors are
+     * parallel (a least-squares fit s_k = lam s_{k-1} leaves at most 2 % of s_k
+     * unexplained, twice in a row with ratios within 5 %, 0 < lam <= 0.9), the
+     * error is dominated by one eigenvector and the next step also moves
+     * lam / (1 - lam) times its own length further, which removes that component
+     * (Aitken's process along the step).  Convergence is still declared only on a
+     * plain step, so the stopping rule bounds the error as in plain Jacobi; the
+     * ranks differ from the plain iterates within that bound (they are usually
+     * closer to the fixed point).  Costs one more vector of n doubles. */
+    int32_t pr_extrapolate;
 } dg_config;
 
 /* Per-batch statistics and phase timings (HIP events on the graph's stream). */

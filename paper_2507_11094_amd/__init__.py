@@ -62,7 +62,7 @@ class Config(ctypes.Structure):
                 ("sssp_persistent", ctypes.c_int32), ("pr_mode", ctypes.c_int32),
                 ("pr_pull", ctypes.c_int32), ("sssp_delta", ctypes.c_int32), ("merge_period", ctypes.c_int32),
                 ("pr_tile", ctypes.c_int32), ("merge_tile", ctypes.c_int32), ("vertex_order", ctypes.c_int32),
-                ("diff_only", ctypes.c_int32)]
+                ("diff_only", ctypes.c_int32), ("pr_extrapolate", ctypes.c_int32)]
 
 
 class KernelProf(ctypes.Structure):

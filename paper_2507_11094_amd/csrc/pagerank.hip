@@ -201,14 +201,40 @@ __device__ __forceinline__ void block_sum2(double a, double b, double *out_a, do
     }
 }
 
+// Fixed-order block sums of two more values (after block_sum2 in the same kernel).
+__device__ __forceinline__ void block_sum2b(double a, double b, double *out_a, double *out_b) {
+    __shared__ double ra[256], rb[256];
+    __syncthreads();
+    ra[threadIdx.x] = a;
+    rb[threadIdx.x] = b;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            ra[threadIdx.x] += ra[threadIdx.x + s];
+            rb[threadIdx.x] += rb[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        *out_a = ra[0];
+        *out_b = rb[0];
+    }
+}
+
 // contrib := xn / outdeg on A, and x := xn unless x_w is null (the whole-graph
 // steps alternate two buffers instead of copying); fixed-order partials of the L1
 // step |xn - x_o| and of the new mass on dangling vertices.
-__global__ __launch_bounds__(256) void k_pr_apply(const int32_t *A, int64_t na, const double *xn,
+__global__ __launch_bounds__(256) void k_pr_apply(const int32_t *A, int64_t na, double *xn,
                                                   const double *x_o, double *x_w, double *contrib,
-                                                  const int32_t *deg, double *partials, const double *done) {
+                                                  const int32_t *deg, double *partials, const double *done,
+                                                  const double *fx, double *dprev, double *partials2) {
     if (*done != 0.0) return;
-    double acc = 0.0, dang = 0.0;
+    // dprev (extrapolation on): the previous step's vector is read and this step's
+    // written, and partials2 gets the block sums of |step|^2 and <step, previous
+    // step>.  f != 0: the new vector also moves f times this step further (decided
+    // by k_pr_reduce); the L1 step summed is the plain one.
+    const double f = *fx;
+    double acc = 0.0, dang = 0.0, sq = 0.0, dot = 0.0;
     // four strided elements per pass, every load issued before the stores (x_w may be
     // x_o, so the compiler could not reorder them itself); the sums keep the order
     // of a plain strided loop
@@ -216,7 +242,7 @@ __global__ __launch_bounds__(256) void k_pr_apply(const int32_t *A, int64_t na, 
     const int64_t st = gstride();
     for (int64_t i0 = gtid(); i0 < na; i0 += U * st) {
         int32_t v[U], dg[U];
-        double nv[U], ov[U];
+        double nv[U], ov[U], pv[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t i = i0 + u * st;
@@ -228,43 +254,113 @@ __global__ __launch_bounds__(256) void k_pr_apply(const int32_t *A, int64_t na, 
             nv[u] = xn[v[u]];
             ov[u] = x_o[v[u]];
             dg[u] = deg[v[u]];
+            pv[u] = dprev ? dprev[v[u]] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             if (v[u] < 0) continue;
-            acc += fabs(nv[u] - ov[u]);
-            if (x_w) x_w[v[u]] = nv[u];
-            contrib[v[u]] = dg[u] > 0 ? nv[u] / (double)dg[u] : 0.0;
-            if (dg[u] == 0) dang += nv[u];
+            const double dl = nv[u] - ov[u];
+            acc += fabs(dl);
+            if (dprev) {
+                sq += dl * dl;
+                dot += dl * pv[u];
+                dprev[v[u]] = dl;
+            }
+            double y = nv[u];
+            if (f != 0.0) {
+                y = nv[u] + f * dl;
+                if (!x_w) xn[v[u]] = y;
+            }
+            if (x_w) x_w[v[u]] = y;
+            contrib[v[u]] = dg[u] > 0 ? y / (double)dg[u] : 0.0;
+            if (dg[u] == 0) dang += y;
         }
     }
     block_sum2(acc, dang, &partials[2 * blockIdx.x], &partials[2 * blockIdx.x + 1]);
+    if (dprev) block_sum2b(sq, dot, &partials2[2 * blockIdx.x], &partials2[2 * blockIdx.x + 1]);
 }
 
 // prs[0] = L1 step, prs[1] = dangling mass, prs[2] = constant term of the next
 // step (global form: ((1-d) S + d D) / n; local form: (1-d) / n), prs[3] = 1 once
 // the step is <= tol (every later kernel of the iteration then returns at once),
-// prs[4] = steps taken.  first = 1: the set-up call before the first step (resets
-// prs[3], prs[4]).  The step is also copied to *step_out.
-__global__ void k_pr_reduce(const double *partials, int np, int global, double S, double damp,
-                            double ninv, double tol, int first, double *prs, double *step_out) {
+// prs[4] = steps taken, prs[5] = the step (copied for the host), prs[6] = |previous
+// step|^2 (0: none comparable), prs[7] = the previous aligned ratio (0: none),
+// prs[8] = the extrapolation factor the next apply uses (0: plain step),
+// prs[9] = plain steps since the last move, prs[10] = moves taken.
+// first = 1: the set-up call before the first step (resets the flags and counts).
+//
+// Extrapolation (extrap = 1, partials2 holds the block sums of |step|^2 and
+// <step, previous step>): the step vectors of a linear fixed-point iteration
+// shrink like e_{k+1} = M e_k.  When the error is dominated by one eigenvector of
+// M with eigenvalue lam, successive steps are parallel, s_k = lam s_{k-1}, and
+// x + lam / (1 - lam) (x' - x) removes that component (Aitken's delta-squared
+// process along the step).  lam is fitted by least squares, lam = <s_k, s_{k-1}> /
+// |s_{k-1}|^2, and the move is taken only when the fit leaves at most EX_FIT of
+// |s_k| unexplained at two successive steps whose fits agree within EX_MATCH, and
+// 0 < lam <= EX_MAX_LAM: modes of the opposite sign (bipartite graphs such as
+// grids have eigenvalues near -d) or several modes of similar size leave the steps
+// unaligned, and no move happens.  The next apply takes the move; a step that moved
+// is never taken as converged, and the fits restart after it.  Convergence is only
+// declared on a plain step, whose L1 size bounds the error exactly as in plain
+// Jacobi, and the move keeps sum(x) (an affine combination of two vectors of equal
+// sum).
+constexpr double EX_FIT = 0.02;     // unexplained fraction of |s_k| (L2) at most
+constexpr double EX_MATCH = 0.05;   // two fitted ratios agree within this fraction
+constexpr double EX_MAX_LAM = 0.9;  // no move for slower ratios (factor <= 9)
+__global__ void k_pr_reduce(const double *partials, const double *partials2, int np, int global, double S,
+                            double damp, double ninv, double tol, int first, int extrap, double *prs,
+                            double *step_out) {
     if (!first && prs[3] != 0.0) return;
-    double a = 0.0, b = 0.0;
+    double a = 0.0, b = 0.0, sq = 0.0, dot = 0.0;
+    const bool fit = extrap && !first;
     for (int i = threadIdx.x; i < np; i += blockDim.x) {
         a += partials[2 * i];
         b += partials[2 * i + 1];
+        if (fit) {
+            sq += partials2[2 * i];
+            dot += partials2[2 * i + 1];
+        }
     }
+    __shared__ double fs[2];
     block_sum2(a, b, &prs[0], &prs[1]);
+    if (fit) block_sum2b(sq, dot, &fs[0], &fs[1]);
+    __syncthreads();
     if (threadIdx.x == 0) {
         prs[2] = global ? ((1.0 - damp) * S + damp * prs[1]) * ninv : (1.0 - damp) * ninv;
         *step_out = prs[0];
         if (first) {
             prs[3] = 0.0;
             prs[4] = 0.0;
-        } else {
-            prs[4] += 1.0;
-            if (prs[0] <= tol) prs[3] = 1.0;
+            for (int k = 6; k <= 10; ++k) prs[k] = 0.0;
+            return;
         }
+        prs[4] += 1.0;
+        const double step = prs[0];
+        const bool moved = prs[8] != 0.0;
+        prs[8] = 0.0;
+        if (moved) {
+            // the step just taken moved further than Jacobi: the fits start again
+            prs[6] = 0.0;
+            prs[7] = 0.0;
+            prs[9] = 0.0;
+            return;
+        }
+        if (step <= tol) {
+            prs[3] = 1.0;
+            return;
+        }
+        if (!fit) return;
+        prs[9] += 1.0;
+        const double s2 = fs[0], sd = fs[1], p2 = prs[6];
+        const double lam = p2 > 0.0 ? sd / p2 : 0.0;
+        const bool aligned = p2 > 0.0 && s2 - sd * lam <= EX_FIT * EX_FIT * s2;
+        if (aligned && lam > 0.0 && lam <= EX_MAX_LAM && prs[7] > 0.0 && fabs(lam - prs[7]) <= EX_MATCH * lam &&
+            prs[9] >= 2.0 && lam * step > 2.0 * tol) {
+            prs[8] = lam / (1.0 - lam);
+            prs[10] += 1.0;
+        }
+        prs[7] = aligned ? lam : 0.0;
+        prs[6] = s2;
     }
 }
 
@@ -556,8 +652,8 @@ static int ensure_pr_ws(dg_graph *g) {
     int64_t edges = std::max(g->fwd.m + g->fwd.dm, g->rev->m + g->rev->dm);
     const int64_t qcap = 2 * (edges / heavy_deg(g) + 2) + g->n / 8 + 64;
     DG_TRY(ws.heavy.ensure((size_t)qcap * 2 + 2 * (size_t)qcap * 2));
-    DG_TRY(ws.part.ensure((size_t)qcap + 2 * APPLY_GROUPS + 8));
-    DG_TRY(ws.prs.ensure(8));
+    DG_TRY(ws.part.ensure((size_t)qcap + 4 * APPLY_GROUPS + 8));
+    DG_TRY(ws.prs.ensure(16));
     return DG_OK;
 }
 
@@ -603,8 +699,16 @@ static int pr_iterate(dg_graph *g, const int32_t *A, int64_t na, int64_t edges, 
                            partials);
     else
         hipLaunchKernelGGL(k_sum_vec2, dim3(1), dim3(256), 0, s, x, g->fwd.deg.p, (int64_t)0, partials);
-    hipLaunchKernelGGL(k_pr_reduce, dim3(1), dim3(256), 0, s, partials, global ? APPLY_GROUPS : 1,
-                       (int)global, S, damping, ninv, tol, 1, prs, step_out);
+    // extrapolated steps keep the previous step vector (n doubles) and two more sums
+    const int extrap = g->cfg.pr_extrapolate ? 1 : 0;
+    double *partials2 = partials + 2 * APPLY_GROUPS;
+    double *dprev = nullptr;
+    if (extrap) {
+        DG_TRY(ws.prstep.ensure((size_t)g->n + 1));
+        dprev = ws.prstep.p;
+    }
+    hipLaunchKernelGGL(k_pr_reduce, dim3(1), dim3(256), 0, s, partials, partials2, global ? APPLY_GROUPS : 1,
+                       (int)global, S, damping, ninv, tol, 1, extrap, prs, step_out);
     DG_HIP(hipGetLastError());
     // every vertex pulled: merge-path tiles over the base level, then the diff level
     const Dir &R = *g->rev;
@@ -671,16 +775,17 @@ static int pr_iterate(dg_graph *g, const int32_t *A, int64_t na, int64_t edges, 
             if (tiles) {
                 // the step just written becomes the current vector: no copy
                 hipLaunchKernelGGL(k_pr_apply, dim3(APPLY_GROUPS), dim3(256), 0, s, A, na, xn, x,
-                                   (double *)nullptr, contrib, g->fwd.deg.p, partials, done);
+                                   (double *)nullptr, contrib, g->fwd.deg.p, partials, done, prs + 8, dprev,
+                                   partials2);
                 prof_end(pa, s, 28.0 * (double)na);
                 std::swap(x, xn);
             } else {
                 hipLaunchKernelGGL(k_pr_apply, dim3(APPLY_GROUPS), dim3(256), 0, s, A, na, xn, x, x, contrib,
-                                   g->fwd.deg.p, partials, done);
+                                   g->fwd.deg.p, partials, done, prs + 8, dprev, partials2);
                 prof_end(pa, s, 40.0 * (double)na);
             }
-            hipLaunchKernelGGL(k_pr_reduce, dim3(1), dim3(256), 0, s, partials, APPLY_GROUPS, (int)global, S,
-                               damping, ninv, tol, 0, prs, step_out);
+            hipLaunchKernelGGL(k_pr_reduce, dim3(1), dim3(256), 0, s, partials, partials2, APPLY_GROUPS,
+                               (int)global, S, damping, ninv, tol, 0, extrap, prs, step_out);
             DG_HIP(hipGetLastError());
             slots.emplace_back(ps, pa);
         }
@@ -989,8 +1094,8 @@ static int pr_mass(dg_query *q, double *S) {
     double *partials = ws.part.p + qcap;
     hipLaunchKernelGGL(k_sum_vec2, dim3(APPLY_GROUPS), dim3(256), 0, s, q->x.p, g->fwd.deg.p, (int64_t)g->n,
                        partials);
-    hipLaunchKernelGGL(k_pr_reduce, dim3(1), dim3(256), 0, s, partials, APPLY_GROUPS, 0, 0.0, q->damping, 1.0,
-                       0.0, 1, ws.prs.p, ws.prs.p + 5);
+    hipLaunchKernelGGL(k_pr_reduce, dim3(1), dim3(256), 0, s, partials, partials, APPLY_GROUPS, 0, 0.0, q->damping,
+                       1.0, 0.0, 1, 0, ws.prs.p, ws.prs.p + 5);
     DG_HIP(hipGetLastError());
     // prs[0] here holds the plain sum (first partial of each pair)
     DG_HIP(hipMemcpyAsync(ws.hcnt + C_COUNT, ws.prs.p, sizeof(double), hipMemcpyDeviceToHost, s));

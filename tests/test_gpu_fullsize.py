@@ -1,6 +1,7 @@
 """GPU parity at the full benchmark sizes, in the configuration bench.py times.
 
-* R-MAT scale 22 (4,194,304 vertices, 67,108,864 arcs), two 100k batches:
+* R-MAT scale 22 (4,194,304 vertices, 67,108,864 arcs), two 100k batches, with
+  extrapolated (the bench's setting) and with plain Jacobi PageRank steps:
   distances bit-exact against the oracle's Dijkstra, the parent array a tight
   shortest-path tree, PageRank within max-abs 1e-10 of the oracle's power
   iteration.
@@ -61,29 +62,50 @@ def batches_for(n, s, d, k, config, count, wmax, undirected=False):
                                   undirected=undirected, existing=keys) for i in range(count)]
 
 
+def bench_config(**kw):
+    """The configuration bench.py runs: extrapolated PageRank steps, the rest default."""
+    c = dg.Config()
+    c.pr_extrapolate = 1
+    for k, v in kw.items():
+        setattr(c, k, v)
+    return c
+
+
 def test_fullsize_rmat22_sssp_pagerank():
+    """The bench's configuration (extrapolated PageRank steps) and plain Jacobi
+    steps on the same batches, both against one oracle run."""
     t0 = time.perf_counter()
     n, s, d, w = graphgen.c2r_graph(22)
     bats = batches_for(n, s, d, 100000, 1, 2, 100)
     say("R-MAT 22 SSSP + PageRank, two 100k batches; inputs", round(time.perf_counter() - t0, 1), "s")
-    G = dg.Graph(n, s, d, w)  # the default configuration bench.py runs
-    qs = G.sssp_attach(0)
-    qp = G.pr_attach(0.85, 1e-9, 1000)
+    got = {}
+    for extrap in (1, 0):
+        G = dg.Graph(n, s, d, w, config=bench_config(pr_extrapolate=extrap))
+        qs = G.sssp_attach(0)
+        qp = G.pr_attach(0.85, 1e-9, 1000)
+        steps = 0
+        for b in bats:
+            st = G.apply(*b)
+            steps += st.pr_iterations
+        dist, par = qs.read()
+        rank, _, conv = qp.read()
+        G.close()
+        say("extrapolated" if extrap else "plain", "PageRank steps over the batches", steps)
+        got[extrap] = (dist, par, rank, conv)
     cs, cd, cw = s, d, w
     for b in bats:
-        st = G.apply(*b)
         cs, cd, cw, ost = oracle.apply(n, cs, cd, cw, *b)
-        assert (st.deleted, st.inserted) == (ost[0], ost[1])
-    dist, par = qs.read()
-    rank, _, conv = qp.read()
-    G.close()
     say("oracle Dijkstra + power iteration at full size")
-    assert np.array_equal(dist, oracle.sssp(n, cs, cd, cw, 0))
-    check_tree(n, cs, cd, cw, 0, dist, par)
+    want_d = oracle.sssp(n, cs, cd, cw, 0)
     want, _, oconv = oracle.pagerank(n, cs, cd, 0.85, 1e-9, 1000)
-    assert conv and oconv
-    assert float(np.max(np.abs(rank - want))) <= 1e-10
-    assert abs(float(rank.sum()) - 1.0) <= 1e-12
+    assert oconv
+    for extrap, (dist, par, rank, conv) in got.items():
+        assert np.array_equal(dist, want_d)
+        check_tree(n, cs, cd, cw, 0, dist, par)
+        err = float(np.max(np.abs(rank - want)))
+        say("extrapolated" if extrap else "plain", "PageRank max-abs vs oracle", err)
+        assert conv and err <= 1e-10
+        assert abs(float(rank.sum()) - 1.0) <= 1e-12
 
 
 def test_fullsize_rmat22_large_batches_through_merge():
@@ -93,7 +115,7 @@ def test_fullsize_rmat22_large_batches_through_merge():
     bats = [graphgen.update_batch(n, s, d, k, graphgen.config_seed(1, 300 + i), wmax=100, existing=keys)
             for i, k in enumerate([1000000] * 4 + [10000])]
     say("R-MAT 22 SSSP + PageRank, four 1M batches and one 10k batch; inputs", round(time.perf_counter() - t0, 1), "s")
-    G = dg.Graph(n, s, d, w)
+    G = dg.Graph(n, s, d, w, config=bench_config())
     qs = G.sssp_attach(0)
     qp = G.pr_attach(0.85, 1e-9, 1000)
     merged = 0
@@ -121,9 +143,7 @@ def test_fullsize_grid_sssp_pagerank():
     n, s, d, w = graphgen.c2g_graph(4096)
     bats = batches_for(n, s, d, 100000, 1, 1, 1000)
     say("grid 4096^2 near-far SSSP + PageRank, one 100k batch; inputs", round(time.perf_counter() - t0, 1), "s")
-    c = dg.Config()
-    c.sssp_delta = 8000
-    G = dg.Graph(n, s, d, w, config=c)
+    G = dg.Graph(n, s, d, w, config=bench_config(sssp_delta=8000))
     qs = G.sssp_attach(0)
     qp = G.pr_attach(0.85, 1e-9, 1000)
     G.apply(*bats[0])

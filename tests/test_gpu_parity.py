@@ -558,6 +558,47 @@ def test_pagerank_whole_graph_pull(pull, tile):
     pr_check(rs, n, cs, cd)
 
 
+@pytest.mark.parametrize("kind,mode,pull", [("rmat", 2, 0), ("rmat", 2, 1), ("rmat", 1, 0), ("rmat", 0, 0),
+                                            ("grid", 2, 0), ("grid", 1, 0)])
+def test_pagerank_extrapolated_steps(kind, mode, pull):
+    """Extrapolated Jacobi steps (pr_extrapolate = 1) against plain ones: both
+    reach the oracle's ranks after the static solve and after every batch (global
+    form over tiles or vertex waves, the local form on the affected set, automatic
+    choice), and the extrapolated runs take no more steps in total.  R-MAT scale
+    13 with uniform insertions has a slow, steady error mode for the move to
+    remove; the grid is bipartite (eigenvalues near -d as well as +d), where a
+    move taken on the L1 step ratio alone diverges."""
+    if kind == "rmat":
+        n, s, d, w = rmat_small(scale=13)
+    else:
+        n, s, d, w = graphgen.grid4(48, 48, 5)
+    say("pagerank extrapolated vs plain,", kind, "mode", mode, "pull", pull)
+    steps = {}
+    for extrap in (1, 0):
+        c = cfg()
+        c.pr_mode = mode
+        c.pr_pull = pull
+        c.pr_extrapolate = extrap
+        G = dg.Graph(n, s, d, w, config=c)
+        q = G.pr_attach(0.85, PR_TOL, 1000)
+        r, it, conv = q.read()
+        assert conv
+        pr_check(r, n, s, d)
+        total = it
+        cs, cd, cw = s, d, w
+        for i, k in enumerate([40, 3000, 12000] if kind == "rmat" else [6, 200, 900]):
+            bs, bd, bw, bo = graphgen.update_batch(n, cs, cd, k, 7700 + i)
+            G.apply(bs, bd, bw, bo)
+            cs, cd, cw, _ = oracle.apply(n, cs, cd, cw, bs, bd, bw, bo)
+            r, it, conv = q.read()
+            assert conv
+            pr_check(r, n, cs, cd)
+            total += it
+        steps[extrap] = total
+    print(f"    steps extrapolated {steps[1]}, plain {steps[0]}", flush=True)
+    assert steps[1] <= steps[0]
+
+
 @pytest.mark.parametrize("tile", [512, 1024, 2048])
 def test_merge_tile_sizes(tile):
     """CSR merge with 512 / 1024 / 2048 rows + entries per merge-path tile: a hub
