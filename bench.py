@@ -357,6 +357,8 @@ def run_single(args, kind: str) -> dict:
     dg.dg_profile_enable(False)
     value = K * k / elapsed
     info_end = G.info()
+    # floor under the pull: the same column stream and gathers with nothing else
+    floor_us = G.pr_gather_floor(10) if kind != "tc" else None
 
     def avg(key):
         return float(np.mean([x[key] for x in stats]))
@@ -440,8 +442,12 @@ def run_single(args, kind: str) -> dict:
         extra["triangles"] = {"initial": int(tc0), "final": int(qt.read())}
     if merge:
         extra["merge"] = merge
+    roof = roofline_of(prof, wl, order=args.vertex_order)
+    if roof and roof["kernel"] == "k_pr_tiles" and floor_us:
+        roof["gather_floor_us"] = round(floor_us, 2)
+        roof["frac_of_gather_floor"] = round(floor_us / roof["avg_launch_us"], 4)
     out = line(args, value, "updates/s", 1e3 * elapsed / K, "u64" if kind == "tc" else "i32+f64", config,
-               roofline_of(prof, wl, order=args.vertex_order), cpu, **extra)
+               roof, cpu, **extra)
     G.close()
     return out
 

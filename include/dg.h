@@ -129,7 +129,7 @@ typedef struct dg_config {
     int32_t diff_only;
     /* Jacobi PageRank steps: 0 = plain steps, as in the Appendix A listings
      * (default); 1 = extrapolated steps: when two successive step vectors are
-     * parallel (a least-squares fit s_k = lam s_{k-1} leaves at most 2 % of s_k
+     * parallel (a least-squares fit s_k = lam s_{k-1} leaves at most 5 % of s_k
      * unexplained, twice in a row with ratios within 5 %, 0 < lam <= 0.9), the
      * error is dominated by one eigenvector and the next step also moves
      * lam / (1 - lam) times its own length further, which removes that component
@@ -459,6 +459,15 @@ int dg_scan_exclusive(const int64_t *in, int64_t *out, int64_t n, void *stream);
  * multiple of 4 KiB; the buffer's contents are overwritten (kinds 1, 2) or kept
  * (kind 0).  Runs on `stream` (NULL: null stream) and returns when done. */
 int dg_calibrate(int32_t kind, void *buf, int64_t bytes, void *stream);
+
+/* Floor under the whole-graph PageRank pull (the Jacobi sweep of the Appendix A
+ * PR listings): a kernel that only streams the graph's base reverse columns (8
+ * per lane, coalesced) and gathers one 8-byte value at each column, summed per
+ * workgroup.  The pull does the same gathers plus the row sums and the stores, so
+ * the ratio of the two times says how far the pull is from its gather bound.
+ * Two warm-up launches, then `reps` (>= 1) timed ones with HIP events on the
+ * graph's stream; *us = microseconds per launch.  Uses library scratch only. */
+int dg_pr_gather_floor(dg_graph *g, int32_t reps, double *us);
 
 /* ---- static recompute on the current graph (comparators) -------------------------- */
 

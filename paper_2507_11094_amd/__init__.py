@@ -41,6 +41,7 @@ EXPORTS = (
     "dg_apply_batch", "dg_snapshot_save", "dg_snapshot_restore", "dg_snapshot_free",
     "dg_sssp_attach", "dg_pr_attach", "dg_tc_attach", "dg_query_detach", "dg_sssp_read",
     "dg_query_export", "dg_query_import", "dg_pr_read_noalloc", "dg_sort_pairs", "dg_scan_exclusive", "dg_calibrate",
+    "dg_pr_gather_floor",
     "dg_pr_read", "dg_tc_read", "dg_sssp_static", "dg_pr_static", "dg_tc_static",
     "dg_profile_enable", "dg_profile_reset", "dg_profile_read",
     "dg_set_create", "dg_set_destroy", "dg_set_info", "dg_set_sssp_attach", "dg_set_apply_sssp",
@@ -134,6 +135,7 @@ def load_library() -> ctypes.CDLL:
         "dg_sort_pairs": ([P, P, P, P, I64, I32, P], ctypes.c_int),
         "dg_scan_exclusive": ([P, P, I64, P], ctypes.c_int),
         "dg_calibrate": ([I32, P, I64, P], ctypes.c_int),
+        "dg_pr_gather_floor": ([P, I32, ctypes.POINTER(D)], ctypes.c_int),
         "dg_query_import": ([P, P, I64, ctypes.POINTER(P)], ctypes.c_int),
         "dg_sssp_static": ([P, I32, P, P, U32], ctypes.c_int),
         "dg_pr_static": ([P, D, D, I32, P, P, U32], ctypes.c_int),
@@ -411,6 +413,13 @@ class Graph:
         _check(load_library().dg_graph_info(self.handle, ctypes.byref(n), ctypes.byref(m),
                                             ctypes.byref(d), ctypes.byref(t)))
         return {"n": n.value, "m": m.value, "diff_entries": d.value, "tombstones": t.value}
+
+    def pr_gather_floor(self, reps: int = 10) -> float:
+        """Microseconds per launch of a bare gather over the base reverse columns
+        (the floor under the whole-graph PageRank pull)."""
+        us = ctypes.c_double()
+        _check(load_library().dg_pr_gather_floor(self.handle, int(reps), ctypes.byref(us)))
+        return us.value
 
     def export(self):
         lib = load_library()

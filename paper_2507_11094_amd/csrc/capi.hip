@@ -534,6 +534,12 @@ int dg_pr_read_noalloc(dg_query *q, double *rank, int32_t *iters, int32_t *conve
     return mark_device_error(q->g, pr_read_noalloc(q, rank, (flags & DG_DEVICE_PTRS) != 0));
 }
 
+int dg_pr_gather_floor(dg_graph *g, int32_t reps, double *us) {
+    DG_TRY(check_graph(g));
+    if (!us || reps < 1) return set_error(DG_EINVAL, "gather floor needs reps >= 1 and an output");
+    return mark_device_error(g, pr_gather_floor(g, reps, us));
+}
+
 int dg_tc_read(dg_query *q, uint64_t *count) {
     if (!q || q->kind != Q_TC || !count) return set_error(DG_EINVAL, "not a triangle-count query");
     *count = q->tc;

@@ -342,6 +342,7 @@ int pr_normalize(dg_graph *g, const double *x, double *rank, bool dev);
 int pr_export(dg_query *q, double *x);
 // pr_read without any device allocation (fixed per-device scratch array).
 int pr_read_noalloc(dg_query *q, double *rank, bool dev);
+int pr_gather_floor(dg_graph *g, int32_t reps, double *us);
 int pr_import(dg_query *q, const double *x);
 
 // launch timing (prof.hip)

@@ -1105,3 +1105,17 @@ def test_tc_random_sequences_match_recount():
         assert q.read() == oracle.triangles(n, cu, cv), trial
         G.close()
 
+
+
+def test_pr_gather_floor():
+    """dg_pr_gather_floor: a positive time on a graph with edges, zero on an
+    edgeless one, and a refusal of reps < 1."""
+    n, s, d, w = rmat_small(scale=12)
+    say("gather floor")
+    G = dg.Graph(n, s, d, w)
+    assert G.pr_gather_floor(3) > 0.0
+    with pytest.raises(dg.DGError):
+        G.pr_gather_floor(0)
+    e = np.zeros(0, np.int32)
+    E = dg.Graph(5, e, e, e)
+    assert E.pr_gather_floor(1) == 0.0
