@@ -155,7 +155,7 @@ struct Work {
     int32_t stamp_ctr = 0;
     DBuf<double> part;                    // partial sums of split rows
     DBuf<double> prs;                     // PageRank scalars: step, dangling mass, constant term
-    DBuf<double> prstep;                  // previous PageRank step vector (extrapolated steps)
+    DBuf<float> prstep;                   // previous PageRank step vector (extrapolated steps' fits)
     DBuf<int32_t> mp_row;                 // merge-path tile starts (row, entry) of the whole-graph pull
     DBuf<int64_t> mp_edge;
     DBuf<double> mp_part;                 // per-tile partial sums of rows split across tiles

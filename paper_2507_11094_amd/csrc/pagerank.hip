@@ -227,13 +227,15 @@ __device__ __forceinline__ void block_sum2b(double a, double b, double *out_a, d
 __global__ __launch_bounds__(256) void k_pr_apply(const int32_t *A, int64_t na, double *xn,
                                                   const double *x_o, double *x_w, double *contrib,
                                                   const int32_t *deg, double *partials, const double *done,
-                                                  const double *fx, double *dprev, double *partials2) {
+                                                  const double *fx, float *dprev, double *partials2) {
     if (*done != 0.0) return;
-    // dprev (extrapolation on): the previous step's vector is read and this step's
-    // written, and partials2 gets the block sums of |step|^2 and <step, previous
-    // step>.  f != 0: the new vector also moves f times this step further (decided
-    // by k_pr_reduce); the L1 step summed is the plain one.
-    const double f = *fx;
+    // dprev (extrapolation on) while fx[3] != 0: the previous step's vector is read
+    // and this step's written (FP32: it only feeds the fit), and partials2 gets the
+    // block sums of |step|^2 and <step, previous step>.  f = fx[0] != 0: the new
+    // vector also moves f times this step further (decided by k_pr_reduce); the L1
+    // step summed is the plain one.
+    const double f = fx[0];
+    if (dprev && fx[3] == 0.0) dprev = nullptr;
     double acc = 0.0, dang = 0.0, sq = 0.0, dot = 0.0;
     // four strided elements per pass, every load issued before the stores (x_w may be
     // x_o, so the compiler could not reorder them itself); the sums keep the order
@@ -254,7 +256,7 @@ __global__ __launch_bounds__(256) void k_pr_apply(const int32_t *A, int64_t na, 
             nv[u] = xn[v[u]];
             ov[u] = x_o[v[u]];
             dg[u] = deg[v[u]];
-            pv[u] = dprev ? dprev[v[u]] : 0.0;
+            pv[u] = dprev ? (double)dprev[v[u]] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -264,7 +266,7 @@ __global__ __launch_bounds__(256) void k_pr_apply(const int32_t *A, int64_t na, 
             if (dprev) {
                 sq += dl * dl;
                 dot += dl * pv[u];
-                dprev[v[u]] = dl;
+                dprev[v[u]] = (float)dl;
             }
             double y = nv[u];
             if (f != 0.0) {
@@ -286,7 +288,10 @@ __global__ __launch_bounds__(256) void k_pr_apply(const int32_t *A, int64_t na, 
 // prs[4] = steps taken, prs[5] = the step (copied for the host), prs[6] = |previous
 // step|^2 (0: none comparable), prs[7] = the previous aligned ratio (0: none),
 // prs[8] = the extrapolation factor the next apply uses (0: plain step),
-// prs[9] = plain steps since the last move, prs[10] = moves taken.
+// prs[9] = plain steps since the last move, prs[10] = moves taken, prs[11] = 1
+// while the applies keep the step vector for the fits (stops after EX_TRACK plain
+// steps without a move: error spread over many modes, as on grids, never lines
+// up, and the extra vector traffic would be paid on every step).
 // first = 1: the set-up call before the first step (resets the flags and counts).
 //
 // Extrapolation (extrap = 1, partials2 holds the block sums of |step|^2 and
@@ -307,12 +312,13 @@ __global__ __launch_bounds__(256) void k_pr_apply(const int32_t *A, int64_t na, 
 constexpr double EX_FIT = 0.05;     // unexplained fraction of |s_k| (L2) at most
 constexpr double EX_MATCH = 0.05;   // two fitted ratios agree within this fraction
 constexpr double EX_MAX_LAM = 0.9;  // no move for slower ratios (factor <= 9)
+constexpr int EX_TRACK = 24;        // plain steps without a move before the fits stop
 __global__ void k_pr_reduce(const double *partials, const double *partials2, int np, int global, double S,
                             double damp, double ninv, double tol, int first, int extrap, double *prs,
                             double *step_out) {
     if (!first && prs[3] != 0.0) return;
     double a = 0.0, b = 0.0, sq = 0.0, dot = 0.0;
-    const bool fit = extrap && !first;
+    const bool fit = extrap && !first && prs[11] != 0.0;  // the apply just run kept the step vector
     for (int i = threadIdx.x; i < np; i += blockDim.x) {
         a += partials[2 * i];
         b += partials[2 * i + 1];
@@ -332,6 +338,7 @@ __global__ void k_pr_reduce(const double *partials, const double *partials2, int
             prs[3] = 0.0;
             prs[4] = 0.0;
             for (int k = 6; k <= 10; ++k) prs[k] = 0.0;
+            prs[11] = extrap ? 1.0 : 0.0;
             return;
         }
         prs[4] += 1.0;
@@ -343,6 +350,7 @@ __global__ void k_pr_reduce(const double *partials, const double *partials2, int
             prs[6] = 0.0;
             prs[7] = 0.0;
             prs[9] = 0.0;
+            prs[11] = extrap ? 1.0 : 0.0;
             return;
         }
         if (step <= tol) {
@@ -351,6 +359,7 @@ __global__ void k_pr_reduce(const double *partials, const double *partials2, int
         }
         if (!fit) return;
         prs[9] += 1.0;
+        if (prs[9] >= (double)EX_TRACK) prs[11] = 0.0;
         const double s2 = fs[0], sd = fs[1], p2 = prs[6];
         const double lam = p2 > 0.0 ? sd / p2 : 0.0;
         const bool aligned = p2 > 0.0 && s2 - sd * lam <= EX_FIT * EX_FIT * s2;
@@ -680,9 +689,9 @@ int pr_gather_floor(dg_graph *g, int32_t reps, double *us) {
     const Dir &R = *g->rev;
     const int64_t m = R.m;
     const int64_t blocks = (m + 2047) / 2048;
-    DG_TRY(ws.prstep.ensure((size_t)g->n + 1));
+    DG_TRY(ws.rbuf.ensure((size_t)g->n + 1));
     DG_TRY(ws.sx.ensure((size_t)std::max<int64_t>(blocks, 1)));
-    DG_HIP(hipMemsetAsync(ws.prstep.p, 0, ((size_t)g->n + 1) * sizeof(double), s));
+    DG_HIP(hipMemsetAsync(ws.rbuf.p, 0, ((size_t)g->n + 1) * sizeof(double), s));
     *us = 0.0;
     if (m == 0 || reps <= 0) return DG_OK;
     hipEvent_t e0, e1;
@@ -691,7 +700,7 @@ int pr_gather_floor(dg_graph *g, int32_t reps, double *us) {
     int rc = DG_OK;
     for (int i = 0; i < 2 + reps; ++i) {
         if (i == 2 && hipEventRecord(e0, s) != hipSuccess) rc = DG_EDEVICE;
-        hipLaunchKernelGGL(k_gather_floor, dim3((unsigned)blocks), dim3(256), 0, s, R.col.p, m, ws.prstep.p, ws.sx.p);
+        hipLaunchKernelGGL(k_gather_floor, dim3((unsigned)blocks), dim3(256), 0, s, R.col.p, m, ws.rbuf.p, ws.sx.p);
     }
     if (rc == DG_OK && (hipGetLastError() != hipSuccess || hipEventRecord(e1, s) != hipSuccess ||
                         hipEventSynchronize(e1) != hipSuccess))
@@ -762,7 +771,7 @@ static int pr_iterate(dg_graph *g, const int32_t *A, int64_t na, int64_t edges, 
     // extrapolated steps keep the previous step vector (n doubles) and two more sums
     const int extrap = g->cfg.pr_extrapolate ? 1 : 0;
     double *partials2 = partials + 2 * APPLY_GROUPS;
-    double *dprev = nullptr;
+    float *dprev = nullptr;
     if (extrap) {
         DG_TRY(ws.prstep.ensure((size_t)g->n + 1));
         dprev = ws.prstep.p;
