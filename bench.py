@@ -350,7 +350,7 @@ def run_single(args, kind: str) -> dict:
         stats.append(st.as_dict())
         log(f"step {i + 1}/{K}: {st.t_total_ms:.2f} ms (sssp {st.t_sssp_ms:.2f}, pr {st.t_pr_ms:.2f}, "
             f"tc {st.t_tc_ms:.2f}, update {st.t_update_ms + st.t_validate_ms:.2f}, merge {st.t_merge_ms:.2f}, "
-            f"pr_iters {st.pr_iterations}, |A| {st.pr_affected})")
+            f"pr_iters {st.pr_iterations} ({st.pr_moves} moves), |A| {st.pr_affected})")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     prof = dg.dg_profile_read()
@@ -428,7 +428,8 @@ def run_single(args, kind: str) -> dict:
         "phases_ms": {key: round(avg(key), 3) for key in
                       ("t_validate_ms", "t_update_ms", "t_merge_ms", "t_sssp_ms", "t_pr_ms", "t_tc_ms",
                        "t_total_ms")},
-        "per_batch": {"pr_iterations": avg("pr_iterations"), "pr_affected": avg("pr_affected"),
+        "per_batch": {"pr_iterations": avg("pr_iterations"), "pr_moves": avg("pr_moves"),
+                      "pr_affected": avg("pr_affected"),
                       "sssp_invalidated": avg("sssp_invalidated"), "sssp_steps": avg("sssp_steps"),
                       "deleted": avg("deleted"), "inserted": avg("inserted"),
                       "tc_removed": avg("tc_removed"), "tc_added": avg("tc_added"),

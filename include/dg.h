@@ -164,7 +164,7 @@ typedef struct dg_batch_stats {
     int64_t tc_removed;         /* triangles removed by the deletions                   */
     int64_t tc_added;           /* triangles added by the insertions                    */
     float t_validate_ms, t_update_ms, t_merge_ms, t_sssp_ms, t_pr_ms, t_tc_ms, t_total_ms;
-    float reserved_f;
+    int32_t pr_moves;           /* extrapolation moves of the PageRank steps            */
 } dg_batch_stats;
 
 const char *dg_last_error(void);

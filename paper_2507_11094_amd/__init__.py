@@ -84,7 +84,7 @@ class BatchStats(ctypes.Structure):
                 ("t_update_ms", ctypes.c_float), ("t_merge_ms", ctypes.c_float),
                 ("t_sssp_ms", ctypes.c_float), ("t_pr_ms", ctypes.c_float),
                 ("t_tc_ms", ctypes.c_float), ("t_total_ms", ctypes.c_float),
-                ("reserved_f", ctypes.c_float)]
+                ("pr_moves", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_ if not name.startswith("reserved")}

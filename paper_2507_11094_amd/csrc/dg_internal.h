@@ -153,6 +153,7 @@ struct Work {
     DBuf<double> sx, sc, sxn;
     int32_t far_ctr = 0;
     int32_t stamp_ctr = 0;
+    int32_t pr_moves = 0;                 // extrapolation moves of the last PageRank iteration
     DBuf<double> part;                    // partial sums of split rows
     DBuf<double> prs;                     // PageRank scalars: step, dangling mass, constant term
     DBuf<float> prstep;                   // previous PageRank step vector (extrapolated steps' fits)

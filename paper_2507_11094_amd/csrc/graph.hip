@@ -91,7 +91,7 @@ int ws_init(dg_graph *g) {
     g->ws.dcnt = static_cast<int64_t *>(dmalloc(sizeof(int64_t) * C_COUNT));
     if (!g->ws.dcnt) return set_error(DG_ENOMEM, "counter allocation failed");
     // C_COUNT counter slots, then 8 slots of PageRank step state
-    DG_HIP(hipHostMalloc((void **)&g->ws.hcnt, sizeof(int64_t) * (C_COUNT + 8), hipHostMallocDefault));
+    DG_HIP(hipHostMalloc((void **)&g->ws.hcnt, sizeof(int64_t) * (C_COUNT + 16), hipHostMallocDefault));
     g->ws.dcnt_m = static_cast<int64_t *>(dmalloc(sizeof(int64_t) * C_COUNT));
     if (!g->ws.dcnt_m) return set_error(DG_ENOMEM, "counter allocation failed");
     DG_HIP(hipHostMalloc((void **)&g->ws.hcnt_m, sizeof(int64_t) * C_COUNT, hipHostMallocDefault));

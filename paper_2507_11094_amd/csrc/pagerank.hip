@@ -221,67 +221,6 @@ __device__ __forceinline__ void block_sum2b(double a, double b, double *out_a, d
     }
 }
 
-// contrib := xn / outdeg on A, and x := xn unless x_w is null (the whole-graph
-// steps alternate two buffers instead of copying); fixed-order partials of the L1
-// step |xn - x_o| and of the new mass on dangling vertices.
-__global__ __launch_bounds__(256) void k_pr_apply(const int32_t *A, int64_t na, double *xn,
-                                                  const double *x_o, double *x_w, double *contrib,
-                                                  const int32_t *deg, double *partials, const double *done,
-                                                  const double *fx, float *dprev, double *partials2) {
-    if (*done != 0.0) return;
-    // dprev (extrapolation on) while fx[3] != 0: the previous step's vector is read
-    // and this step's written (FP32: it only feeds the fit), and partials2 gets the
-    // block sums of |step|^2 and <step, previous step>.  f = fx[0] != 0: the new
-    // vector also moves f times this step further (decided by k_pr_reduce); the L1
-    // step summed is the plain one.
-    const double f = fx[0];
-    if (dprev && fx[3] == 0.0) dprev = nullptr;
-    double acc = 0.0, dang = 0.0, sq = 0.0, dot = 0.0;
-    // four strided elements per pass, every load issued before the stores (x_w may be
-    // x_o, so the compiler could not reorder them itself); the sums keep the order
-    // of a plain strided loop
-    constexpr int U = 4;
-    const int64_t st = gstride();
-    for (int64_t i0 = gtid(); i0 < na; i0 += U * st) {
-        int32_t v[U], dg[U];
-        double nv[U], ov[U], pv[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int64_t i = i0 + u * st;
-            v[u] = i < na ? (A ? A[i] : (int32_t)i) : -1;
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            if (v[u] < 0) continue;
-            nv[u] = xn[v[u]];
-            ov[u] = x_o[v[u]];
-            dg[u] = deg[v[u]];
-            pv[u] = dprev ? (double)dprev[v[u]] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            if (v[u] < 0) continue;
-            const double dl = nv[u] - ov[u];
-            acc += fabs(dl);
-            if (dprev) {
-                sq += dl * dl;
-                dot += dl * pv[u];
-                dprev[v[u]] = (float)dl;
-            }
-            double y = nv[u];
-            if (f != 0.0) {
-                y = nv[u] + f * dl;
-                if (!x_w) xn[v[u]] = y;
-            }
-            if (x_w) x_w[v[u]] = y;
-            contrib[v[u]] = dg[u] > 0 ? y / (double)dg[u] : 0.0;
-            if (dg[u] == 0) dang += y;
-        }
-    }
-    block_sum2(acc, dang, &partials[2 * blockIdx.x], &partials[2 * blockIdx.x + 1]);
-    if (dprev) block_sum2b(sq, dot, &partials2[2 * blockIdx.x], &partials2[2 * blockIdx.x + 1]);
-}
-
 // prs[0] = L1 step, prs[1] = dangling mass, prs[2] = constant term of the next
 // step (global form: ((1-d) S + d D) / n; local form: (1-d) / n), prs[3] = 1 once
 // the step is <= tol (every later kernel of the iteration then returns at once),
@@ -313,10 +252,9 @@ constexpr double EX_FIT = 0.05;     // unexplained fraction of |s_k| (L2) at mos
 constexpr double EX_MATCH = 0.05;   // two fitted ratios agree within this fraction
 constexpr double EX_MAX_LAM = 0.9;  // no move for slower ratios (factor <= 9)
 constexpr int EX_TRACK = 24;        // plain steps without a move before the fits stop
-__global__ void k_pr_reduce(const double *partials, const double *partials2, int np, int global, double S,
-                            double damp, double ninv, double tol, int first, int extrap, double *prs,
-                            double *step_out) {
-    if (!first && prs[3] != 0.0) return;
+__device__ __forceinline__ void pr_reduce_body(const double *partials, const double *partials2, int np, int global,
+                                               double S, double damp, double ninv, double tol, int first, int extrap,
+                                               double *prs, double *step_out) {
     double a = 0.0, b = 0.0, sq = 0.0, dot = 0.0;
     const bool fit = extrap && !first && prs[11] != 0.0;  // the apply just run kept the step vector
     for (int i = threadIdx.x; i < np; i += blockDim.x) {
@@ -371,6 +309,78 @@ __global__ void k_pr_reduce(const double *partials, const double *partials2, int
         prs[7] = aligned ? lam : 0.0;
         prs[6] = s2;
     }
+}
+
+__global__ void k_pr_reduce(const double *partials, const double *partials2, int np, int global, double S,
+                            double damp, double ninv, double tol, int first, int extrap, double *prs,
+                            double *step_out) {
+    if (!first && prs[3] != 0.0) return;
+    pr_reduce_body(partials, partials2, np, global, S, damp, ninv, tol, first, extrap, prs, step_out);
+}
+
+// contrib := xn / outdeg on A, and x := xn unless x_w is null (the whole-graph
+// steps alternate two buffers instead of copying); fixed-order partials of the L1
+// step |xn - x_o| and of the new mass on dangling vertices (k_pr_reduce sums
+// them).  Summing them in the last workgroup to finish instead (an atomic ticket
+// after a device-scope fence per workgroup) took 62-68 us per step against 22 + 4
+// us for the two launches: the fence writes the L2 back in every workgroup.
+__global__ __launch_bounds__(256) void k_pr_apply(const int32_t *A, int64_t na, double *xn,
+                                                  const double *x_o, double *x_w, double *contrib,
+                                                  const int32_t *deg, double *partials, double *partials2,
+                                                  float *dprev, const double *prs) {
+    if (prs[3] != 0.0) return;
+    const double *fx = prs + 8;
+    // dprev (extrapolation on) while fx[3] != 0: the previous step's vector is read
+    // and this step's written (FP32: it only feeds the fit), and partials2 gets the
+    // block sums of |step|^2 and <step, previous step>.  f = fx[0] != 0: the new
+    // vector also moves f times this step further (decided by k_pr_reduce); the L1
+    // step summed is the plain one.
+    const double f = fx[0];
+    if (dprev && fx[3] == 0.0) dprev = nullptr;
+    double acc = 0.0, dang = 0.0, sq = 0.0, dot = 0.0;
+    // four strided elements per pass, every load issued before the stores (x_w may be
+    // x_o, so the compiler could not reorder them itself); the sums keep the order
+    // of a plain strided loop
+    constexpr int U = 4;
+    const int64_t st = gstride();
+    for (int64_t i0 = gtid(); i0 < na; i0 += U * st) {
+        int32_t v[U], dg[U];
+        double nv[U], ov[U], pv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t i = i0 + u * st;
+            v[u] = i < na ? (A ? A[i] : (int32_t)i) : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (v[u] < 0) continue;
+            nv[u] = xn[v[u]];
+            ov[u] = x_o[v[u]];
+            dg[u] = deg[v[u]];
+            pv[u] = dprev ? (double)dprev[v[u]] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (v[u] < 0) continue;
+            const double dl = nv[u] - ov[u];
+            acc += fabs(dl);
+            if (dprev) {
+                sq += dl * dl;
+                dot += dl * pv[u];
+                dprev[v[u]] = (float)dl;
+            }
+            double y = nv[u];
+            if (f != 0.0) {
+                y = nv[u] + f * dl;
+                if (!x_w) xn[v[u]] = y;
+            }
+            if (x_w) x_w[v[u]] = y;
+            contrib[v[u]] = dg[u] > 0 ? y / (double)dg[u] : 0.0;
+            if (dg[u] == 0) dang += y;
+        }
+    }
+    block_sum2(acc, dang, &partials[2 * blockIdx.x], &partials[2 * blockIdx.x + 1]);
+    if (dprev) block_sum2b(sq, dot, &partials2[2 * blockIdx.x], &partials2[2 * blockIdx.x + 1]);
 }
 
 // Sum and dangling mass of a whole vector: partials for k_pr_reduce.
@@ -496,8 +506,9 @@ static int heavy_deg(dg_graph *g) { return g->cfg.heavy_degree > 0 ? g->cfg.heav
 //                   long pieces by a wave; rows that began in an earlier tile
 //                   leave their piece in pf[b], the row still open at the tile's
 //                   end leaves its piece in pl[b];
-//   k_pr_fixup      rows split across tiles: pieces added in tile order;
-//   k_pr_diff_add   diff-level entries added per row in key order.
+//   k_pr_rows       rows split across tiles: pieces added in tile order, then
+//                   their diff-level entries; the other rows' diff-level entries
+//                   added per row in key order.
 // Every sum has a fixed order, so results are bit-reproducible.
 constexpr int MP_THREADS = 256;
 constexpr int MP_ITEMS = 2048;  // default items per tile (cfg.pr_tile picks 1024 / 2048 / 4096)
@@ -617,40 +628,53 @@ __global__ __launch_bounds__(MP_THREADS) void k_pr_tiles(const int32_t *__restri
     }
 }
 
-// Rows that began in an earlier tile and end in tile b: the open pieces of the
-// tiles before (pl, in tile order) plus the closing piece (pf[b]).
-__global__ void k_pr_fixup(int64_t nb, const int32_t *__restrict__ mp_row, const int64_t *__restrict__ mp_edge,
-                           const int64_t *__restrict__ off, const double *pf, const double *pl,
-                           const double *cterm, double damp, double *xn, const double *done) {
+// After the tiles, one pass finishes two kinds of rows:
+//   k < nb:  rows that began in an earlier tile and end in tile k: the open pieces
+//            of the tiles before (pl, in tile order) plus the closing piece
+//            (pf[k]), then the row's diff-level entries;
+//   k >= nb: diff-level entries, the first entry of each row's run adding the
+//            run's live contributions in key order -- except for rows split
+//            across tiles, which the first kind finishes whole.
+// A row r is split when its first entry and its end fall in different tiles of the
+// merged sequence: items r + off[r] and r + off[r + 1] (a row's end comes after
+// its entries and before the next row's first entry).
+__global__ void k_pr_rows(int64_t nb, int items, const int32_t *__restrict__ mp_row,
+                          const int64_t *__restrict__ mp_edge, const int64_t *__restrict__ off, const double *pf,
+                          const double *pl, int64_t dm, const uint64_t *__restrict__ dkey,
+                          const int64_t *__restrict__ doff, const int32_t *__restrict__ dcol, int keybits,
+                          const double *__restrict__ contrib, const double *cterm, double damp, double *xn,
+                          const double *done) {
     if (*done != 0.0) return;
     const double base = *cterm;
-    for (int64_t b = gtid(); b < nb; b += gstride()) {
-        const int32_t R = mp_row[b];
-        if (R >= mp_row[b + 1] || off[R] >= mp_edge[b]) continue;
-        int64_t first = b - 1;  // tile b-1 ends inside row R
-        while (first > 0 && mp_row[first] == R) --first;
-        double acc = 0.0;
-        for (int64_t j = first; j < b; ++j) acc += pl[j];
-        acc += pf[b];
-        xn[R] = base + damp * acc;
-    }
-}
-
-// Diff-level entries: the first entry of each row's run adds the run's live
-// contributions, in key order.
-__global__ void k_pr_diff_add(int64_t dm, const uint64_t *__restrict__ dkey, const int32_t *__restrict__ dcol,
-                              int keybits, const double *__restrict__ contrib, double damp, double *xn,
-                              const double *done) {
-    if (*done != 0.0) return;
-    for (int64_t j = gtid(); j < dm; j += gstride()) {
-        const int32_t r = (int32_t)(dkey[j] >> keybits);
-        if (j > 0 && (int32_t)(dkey[j - 1] >> keybits) == r) continue;
-        double acc = 0.0;
-        for (int64_t q = j; q < dm && (int32_t)(dkey[q] >> keybits) == r; ++q) {
-            const uint32_t cc = (uint32_t)dcol[q];
-            if (!(cc & DEAD)) acc += contrib[cc & ID_MASK];
+    for (int64_t k = gtid(); k < nb + dm; k += gstride()) {
+        if (k < nb) {
+            const int32_t R = mp_row[k];
+            if (R >= mp_row[k + 1] || off[R] >= mp_edge[k]) continue;
+            int64_t first = k - 1;  // tile k-1 ends inside row R
+            while (first > 0 && mp_row[first] == R) --first;
+            double acc = 0.0;
+            for (int64_t j = first; j < k; ++j) acc += pl[j];
+            acc += pf[k];
+            double x = base + damp * acc;
+            double dacc = 0.0;
+            for (int64_t q = doff[R]; q < doff[R + 1]; ++q) {
+                const uint32_t cc = (uint32_t)dcol[q];
+                if (!(cc & DEAD)) dacc += contrib[cc & ID_MASK];
+            }
+            if (dacc != 0.0) x += damp * dacc;
+            xn[R] = x;
+        } else {
+            const int64_t j = k - nb;
+            const int32_t r = (int32_t)(dkey[j] >> keybits);
+            if (j > 0 && (int32_t)(dkey[j - 1] >> keybits) == r) continue;
+            if (((int64_t)r + off[r]) / items != ((int64_t)r + off[r + 1]) / items) continue;
+            double acc = 0.0;
+            for (int64_t q = j; q < dm && (int32_t)(dkey[q] >> keybits) == r; ++q) {
+                const uint32_t cc = (uint32_t)dcol[q];
+                if (!(cc & DEAD)) acc += contrib[cc & ID_MASK];
+            }
+            if (acc != 0.0) xn[r] += damp * acc;
         }
-        if (acc != 0.0) xn[r] += damp * acc;
     }
 }
 
@@ -762,6 +786,7 @@ static int pr_iterate(dg_graph *g, const int32_t *A, int64_t na, int64_t edges, 
     double *prs = ws.prs.p;
     double *const x_home = x, *const xn_home = xn;
     double *step_out = prs + 5;  // not in the shared counters: SSSP may run beside these steps
+    ws.pr_moves = 0;
     // constant term of the first step
     if (global)
         hipLaunchKernelGGL(k_sum_vec2, dim3(APPLY_GROUPS), dim3(256), 0, s, x, g->fwd.deg.p, (int64_t)g->n,
@@ -803,14 +828,25 @@ static int pr_iterate(dg_graph *g, const int32_t *A, int64_t na, int64_t edges, 
     // test runs on the device (k_pr_reduce), and once it passes the remaining
     // launches of the group return at once.  The host reads the flag per group.
     constexpr int GROUP = 4;
+    constexpr int SIDE_GROUP = 6;
     int32_t it = 0, launched = 0;
     *conv = 0;
     std::vector<std::pair<int, int>> slots;  // profiled launches of the group (pull, apply)
     while (launched < max_iter && na > 0) {
         // the first group may be sized from the previous update's step count (at most
         // 64): one host round trip instead of several; launches past convergence
-        // return at once
-        const int want = launched == 0 && first_group > GROUP ? std::min(first_group, 64) : GROUP;
+        // return at once.  With SSSP work waiting to run beside the steps, the first
+        // group is SIDE_GROUP steps (four launches each): the host can only queue
+        // about two dozen launches ahead of the device before a launch blocks, so a
+        // longer first group would hold the SSSP launches back until the steps are
+        // nearly done, and a shorter one would leave the device idle while the host
+        // drives the SSSP rounds.  The rest of the expected steps then go out as one
+        // group.
+        const bool side_waits = side && tiles && !side->done;
+        int want = GROUP;
+        if (launched == 0 && side_waits) want = SIDE_GROUP;
+        else if (launched == 0 && first_group > GROUP) want = std::min(first_group, 64);
+        else if (launched > 0 && first_group > launched + GROUP) want = std::min(first_group - launched, 64);
         const int grp = std::min(want, max_iter - launched);
         slots.clear();
         for (int j = 0; j < grp; ++j) {
@@ -823,11 +859,9 @@ static int pr_iterate(dg_graph *g, const int32_t *A, int64_t na, int64_t edges, 
                                    dim3(MP_THREADS), 0, s, ws.mp_row.p,
                                    ws.mp_edge.p, R.off.p, R.col.p, contrib, prs + 2, damping, xn, pf, pl, done);
                 prof_end(ps, s, 16.0 * (double)g->n + 12.0 * (double)R.m);
-                hipLaunchKernelGGL(k_pr_fixup, dim3(grid_for(nb)), dim3(256), 0, s, nb, ws.mp_row.p,
-                                   ws.mp_edge.p, R.off.p, pf, pl, prs + 2, damping, xn, done);
-                if (R.dm > 0)
-                    hipLaunchKernelGGL(k_pr_diff_add, dim3(grid_for(R.dm)), dim3(256), 0, s, R.dm, R.dkey.p,
-                                       R.dcol.p, R.keybits, contrib, damping, xn, done);
+                hipLaunchKernelGGL(k_pr_rows, dim3(grid_for(nb + R.dm)), dim3(256), 0, s, nb, items, ws.mp_row.p,
+                                   ws.mp_edge.p, R.off.p, pf, pl, R.dm, R.dkey.p, R.doff.p, R.dcol.p, R.keybits,
+                                   contrib, prs + 2, damping, xn, done);
             } else {
                 int64_t blocks = std::min<int64_t>((na + 255) / 256, 65535);
                 ps = prof_begin("pr_pull", s);
@@ -844,13 +878,12 @@ static int pr_iterate(dg_graph *g, const int32_t *A, int64_t na, int64_t edges, 
             if (tiles) {
                 // the step just written becomes the current vector: no copy
                 hipLaunchKernelGGL(k_pr_apply, dim3(APPLY_GROUPS), dim3(256), 0, s, A, na, xn, x,
-                                   (double *)nullptr, contrib, g->fwd.deg.p, partials, done, prs + 8, dprev,
-                                   partials2);
+                                   (double *)nullptr, contrib, g->fwd.deg.p, partials, partials2, dprev, prs);
                 prof_end(pa, s, 28.0 * (double)na);
                 std::swap(x, xn);
             } else {
                 hipLaunchKernelGGL(k_pr_apply, dim3(APPLY_GROUPS), dim3(256), 0, s, A, na, xn, x, x, contrib,
-                                   g->fwd.deg.p, partials, done, prs + 8, dprev, partials2);
+                                   g->fwd.deg.p, partials, partials2, dprev, prs);
                 prof_end(pa, s, 40.0 * (double)na);
             }
             hipLaunchKernelGGL(k_pr_reduce, dim3(1), dim3(256), 0, s, partials, partials2, APPLY_GROUPS,
@@ -859,7 +892,7 @@ static int pr_iterate(dg_graph *g, const int32_t *A, int64_t na, int64_t edges, 
             slots.emplace_back(ps, pa);
         }
         launched += grp;
-        double hp[5];
+        double hp[11];
         // the host slots after the counters: a counter read of a side stream leaves them alone
         DG_HIP(hipMemcpyAsync(ws.hcnt + C_COUNT, prs, sizeof(hp), hipMemcpyDeviceToHost, s));
         // tile steps touch no state the SSSP update uses: run it while they stream
@@ -870,6 +903,7 @@ static int pr_iterate(dg_graph *g, const int32_t *A, int64_t na, int64_t edges, 
         DG_HIP(hipStreamSynchronize(s));
         std::memcpy(hp, ws.hcnt + C_COUNT, sizeof(hp));
         const int32_t total = (int32_t)hp[4];
+        ws.pr_moves = (int32_t)hp[10];
         // launches after convergence did no work: keep them out of the timings
         for (int j = total - it; j < (int)slots.size(); ++j) {
             prof_drop(slots[j].first);
@@ -1316,6 +1350,7 @@ static int pr_update(dg_query *q, int64_t adel, int64_t ains, dg_batch_stats *st
     q->converged = conv;
     if (st) {
         st->pr_iterations += iters;
+        st->pr_moves += g->ws.pr_moves;
         st->pr_affected += na;
         st->edges_traversed += edges * iters;
     }
