@@ -78,11 +78,17 @@ typedef struct dg_config {
     int32_t heavy_degree;
     /* Workgroups of the persistent SSSP kernel; 0 = autotuned / built-in. */
     int32_t persistent_groups;
-    /* SSSP update schedule: 0 = frontier steps launched one at a time from the
-     * host (default for single graphs); 1 = persistent work-queue kernels (one
-     * launch per phase); 2 = frontier steps with device-side counts, captured once
-     * into hipGraphs and replayed per batch (default for graph sets).  Same
-     * results; the static solve at attach always uses frontier steps unless 1. */
+    /* SSSP update schedule (Appendix A, Dynamic SSSP: cut, pull, push to a fixed
+     * point): 0 (default) or 3 = frontier steps launched one at a time from the
+     * host with grids sized to each frontier, the host reading every step's count;
+     * 2 = frontier steps with device-side counts and termination: the steps
+     * (near-far rounds too, with the bucket threshold and the far pile on the
+     * device) are captured once into hipGraphs and replayed per batch, and the host
+     * reads the counts once per replay of 8-16 steps instead of once per step (the
+     * default for graph sets; on single graphs measured no faster, the replayed
+     * graph nodes costing more than the round trips they save); 1 = persistent
+     * work-queue kernels (one launch per phase).  Same results; the static solve
+     * at attach uses host-driven frontier steps unless 1. */
     int32_t sssp_persistent;
     /* PageRank iteration after a batch: 0 = automatic (global dangling-uniform
      * form when the affected set holds >= 20% of the edges, else the local

@@ -193,7 +193,7 @@ int dg_graph_create(int32_t n, int64_t m, const int32_t *src, const int32_t *dst
 // Device and pinned memory of a query, then the query itself.
 static void query_free(dg_query *q) {
     q->key.release(); q->inval.release(); q->x.release(); q->xn.release(); q->contrib.release(); q->res.release();
-    q->qcnt.release(); q->srcs.release(); q->gstamp.release();
+    q->qcnt.release(); q->srcs.release(); q->gstamp.release(); q->gfar.release();
     if (q->hpin) (void)hipHostFree(q->hpin);
     if (q->own_cache) {
         graph_cache_clear(q->own_cache);

@@ -145,6 +145,7 @@ struct Work {
     DBuf<int32_t> f0, f1, heavy;          // frontiers and heavy-chunk queue
     DBuf<int32_t> stamp;                  // per-vertex dedup stamps
     DBuf<int32_t> farflag, far0, far1;    // near-far SSSP: far-pile membership stamps and piles
+    DBuf<int32_t> nfout;                  // captured near-far rounds: the relaxation's output before the split
     DBuf<int64_t> bpart;                  // per-block partial counts (summed in block order)
     // kept between calls (device frees synchronise the whole device): result
     // staging for host reads and the state of the static comparators
@@ -173,6 +174,7 @@ struct Work {
     int64_t *hcnt_m = nullptr;
     SortWork sw_m;
     hipEvent_t ev[16] = {};
+    hipEvent_t step_ev[8] = {};  // completion of the last PageRank steps queued (ring)
 };
 
 // Captured hipGraphs of a launch sequence, keyed by the pointers they bake in.
@@ -206,6 +208,9 @@ struct dg_graph {
     int64_t m_live = 0;      // live arcs in fwd
     int32_t since_merge = 0; // batches applied since the last merge
     hipStream_t stream = nullptr;
+    // while SSSP work runs beside the PageRank steps: called whenever the host waits
+    // on the SSSP stream, to keep the PageRank stream queued (null otherwise)
+    std::function<void()> *pump = nullptr;
     // vertex order (cfg.vertex_order 0): internal id = perm[caller's id], caller's
     // id = iperm[internal id]; empty when the ids are kept as given
     dg::DBuf<int32_t> perm, iperm;
@@ -234,6 +239,7 @@ struct dg_query {
     dg::GraphCache *gcache = nullptr;  // replay the update from captured hipGraphs (owned by a set, or own_cache)
     dg::GraphCache *own_cache = nullptr;
     dg::DBuf<int32_t> gstamp;  // dedup stamps of the captured frontier rounds (device-side stamp counter)
+    dg::DBuf<int32_t> gfar;    // far-pile membership stamps of the captured near-far rounds
     // PageRank: unnormalised x of the dangling-dropped system, x/outdeg cache
     double damping = 0.85, tol = 1e-9;
     int32_t max_iter = 1000;
@@ -318,6 +324,16 @@ int pr_static_solve(dg_graph *g, double damping, double tol, int32_t max_iter, d
                     double *contrib, double *xn, int32_t *iters, int32_t *conv);
 // Work run once while PageRank steps are in flight on the graph's stream (or, where
 // they cannot overlap it, after them); its return code is kept in rc.
+// Wait for stream st.  While SSSP work runs beside the PageRank steps (g->pump
+// set), the host polls instead of blocking and keeps queuing the steps between
+// polls, so the PageRank stream does not run dry while the host drives the SSSP
+// rounds.
+inline hipError_t wait_stream(dg_graph *g, hipStream_t st) {
+    if (g->pump)
+        while (hipStreamQuery(st) == hipErrorNotReady) (*g->pump)();
+    return hipStreamSynchronize(st);
+}
+
 struct SideWork {
     std::function<int()> fn;
     bool beside = false;  // set when it runs while the steps are in flight

@@ -82,7 +82,7 @@ int counters_clear(dg_graph *g) { return fill_i64(g->ws.dcnt, 0, C_SORT_ERR, g->
 int counters_read(dg_graph *g) {
     DG_HIP(hipMemcpyAsync(g->ws.hcnt, g->ws.dcnt, sizeof(int64_t) * C_COUNT, hipMemcpyDeviceToHost,
                           g->stream));
-    DG_HIP(hipStreamSynchronize(g->stream));
+    DG_HIP(wait_stream(g, g->stream));
     if (g->ws.hcnt[C_SORT_ERR]) return set_error(DG_EDEVICE, "sort or scan look-back did not finish (internal error)");
     return DG_OK;
 }
@@ -118,7 +118,8 @@ void ws_free(dg_graph *g) {
     w.scan64.release(); w.tscan.release(); w.f0.release(); w.f1.release(); w.heavy.release();
     w.stamp.release(); w.part.release(); w.prs.release();
     w.mp_row.release(); w.mp_edge.release(); w.mp_part.release(); w.mp_doff.release(); w.tcitems.release();
-    w.farflag.release(); w.far0.release(); w.far1.release(); w.bpart.release();
+    w.farflag.release(); w.far0.release(); w.far1.release(); w.nfout.release(); w.bpart.release();
+    w.prstep.release();
     w.rbuf.release(); w.skey.release(); w.sx.release(); w.sc.release(); w.sxn.release();
     w.vslot.release(); w.vpos.release(); w.vkey.release(); w.vw.release();
     w.wq.release(); w.wseq.release(); w.wctr.release(); w.inq.release();
@@ -136,6 +137,8 @@ void ws_free(dg_graph *g) {
     g->aux = nullptr;
     g->ev_fork = g->ev_join = nullptr;
     for (auto &e : w.ev)
+        if (e) (void)hipEventDestroy(e);
+    for (auto &e : w.step_ev)
         if (e) (void)hipEventDestroy(e);
     w.dcnt = nullptr;
     w.hcnt = nullptr;
@@ -1538,7 +1541,7 @@ int apply_chunk(dg_graph *g, int64_t k, const int32_t *src, const int32_t *dst, 
         if (q->kind == Q_PR && !prq) prq = q;
         has_sssp |= q->kind == Q_SSSP;
     }
-    if (prq && has_sssp && g->cfg.sssp_persistent == 0) {
+    if (prq && has_sssp && g->cfg.sssp_persistent != 1) {
         if (!g->aux) {
             DG_HIP(hipStreamCreateWithFlags(&g->aux, hipStreamNonBlocking));
             DG_HIP(hipEventCreateWithFlags(&g->ev_fork, hipEventDisableTiming));
@@ -1560,7 +1563,7 @@ int apply_chunk(dg_graph *g, int64_t k, const int32_t *src, const int32_t *dst, 
                 if (rc != DG_OK) break;
             }
             (void)hipEventRecord(g->ev_join, g->aux);
-            (void)hipStreamSynchronize(g->aux);
+            (void)wait_stream(g, g->aux);
             g->stream = s;
             if (rc == DG_OK) DG_HIP(hipStreamWaitEvent(s, g->ev_join, 0));
             return rc;
@@ -1570,7 +1573,7 @@ int apply_chunk(dg_graph *g, int64_t k, const int32_t *src, const int32_t *dst, 
         t.stop();
     }
     for (dg_query *q : g->queries) {
-        if (prq && has_sssp && g->cfg.sssp_persistent == 0 && (q == prq || q->kind == Q_SSSP)) continue;
+        if (prq && has_sssp && g->cfg.sssp_persistent != 1 && (q == prq || q->kind == Q_SSSP)) continue;
         if (q->kind == Q_SSSP) {
             PhaseTimer t(g, 2, &st->t_sssp_ms);
             DG_TRY(sssp_post_update(q, adel, ains, st));

@@ -828,78 +828,100 @@ static int pr_iterate(dg_graph *g, const int32_t *A, int64_t na, int64_t edges, 
     // test runs on the device (k_pr_reduce), and once it passes the remaining
     // launches of the group return at once.  The host reads the flag per group.
     constexpr int GROUP = 4;
-    constexpr int SIDE_GROUP = 6;
+    constexpr int SIDE_GROUP = 6;  // steps queued before the SSSP work starts beside them
+    constexpr int AHEAD = 5;       // steps kept in flight while the host drives the SSSP rounds
+    constexpr int RING = (int)(sizeof(ws.step_ev) / sizeof(ws.step_ev[0]));
+    static_assert(RING > AHEAD, "the ring must hold the events of every step in flight");
     int32_t it = 0, launched = 0;
     *conv = 0;
     std::vector<std::pair<int, int>> slots;  // profiled launches of the group (pull, apply)
+    // one Jacobi step (four launches: pull, rows / heavy rows, apply, reduce)
+    auto launch_step = [&]() -> int {
+        if (!tiles) DG_TRY(counters_clear(g));  // the heavy-row queue counters of the pull
+        int ps;
+        if (tiles) {
+            // tiles: off 8 + xn 8 per row, col 4 + contrib 8 per base entry
+            ps = prof_begin("pr_tiles", s);
+            hipLaunchKernelGGL(tiles_kernel, dim3((unsigned)nb), dim3(MP_THREADS), 0, s, ws.mp_row.p, ws.mp_edge.p,
+                               R.off.p, R.col.p, contrib, prs + 2, damping, xn, pf, pl, done);
+            prof_end(ps, s, 16.0 * (double)g->n + 12.0 * (double)R.m);
+            hipLaunchKernelGGL(k_pr_rows, dim3(grid_for(nb + R.dm)), dim3(256), 0, s, nb, items, ws.mp_row.p,
+                               ws.mp_edge.p, R.off.p, pf, pl, R.dm, R.dkey.p, R.doff.p, R.dcol.p, R.keybits,
+                               contrib, prs + 2, damping, xn, done);
+        } else {
+            int64_t blocks = std::min<int64_t>((na + 255) / 256, 65535);
+            ps = prof_begin("pr_pull", s);
+            hipLaunchKernelGGL(k_pr_pull, dim3((unsigned)blocks), dim3(256), 0, s, A, na, rv, contrib, prs + 2,
+                               damping, xn, hq, ws.dcnt + C_HEAVY, hv, ws.dcnt + C_AUX3, heavy_deg(g),
+                               heavy_deg(g), done);
+            prof_end(ps, s, 28.0 * (double)na + 12.0 * (double)edges);
+            hipLaunchKernelGGL(k_pr_heavy, dim3(8192), dim3(256), 0, s, rv, contrib, hq, ws.dcnt + C_HEAVY,
+                               heavy_deg(g), ws.part.p);
+            hipLaunchKernelGGL(k_pr_finish, dim3(64), dim3(256), 0, s, hv, ws.dcnt + C_AUX3, ws.part.p, prs + 2,
+                               damping, xn);
+        }
+        int pa = prof_begin("pr_apply", s);
+        if (tiles) {
+            // the step just written becomes the current vector: no copy
+            hipLaunchKernelGGL(k_pr_apply, dim3(APPLY_GROUPS), dim3(256), 0, s, A, na, xn, x, (double *)nullptr,
+                               contrib, g->fwd.deg.p, partials, partials2, dprev, prs);
+            prof_end(pa, s, 28.0 * (double)na);
+            std::swap(x, xn);
+        } else {
+            hipLaunchKernelGGL(k_pr_apply, dim3(APPLY_GROUPS), dim3(256), 0, s, A, na, xn, x, x, contrib,
+                               g->fwd.deg.p, partials, partials2, dprev, prs);
+            prof_end(pa, s, 40.0 * (double)na);
+        }
+        hipLaunchKernelGGL(k_pr_reduce, dim3(1), dim3(256), 0, s, partials, partials2, APPLY_GROUPS, (int)global,
+                           S, damping, ninv, tol, 0, extrap, prs, step_out);
+        DG_HIP(hipGetLastError());
+        slots.emplace_back(ps, pa);
+        return DG_OK;
+    };
     while (launched < max_iter && na > 0) {
         // the first group may be sized from the previous update's step count (at most
         // 64): one host round trip instead of several; launches past convergence
-        // return at once.  With SSSP work waiting to run beside the steps, the first
-        // group is SIDE_GROUP steps (four launches each): the host can only queue
-        // about two dozen launches ahead of the device before a launch blocks, so a
-        // longer first group would hold the SSSP launches back until the steps are
-        // nearly done, and a shorter one would leave the device idle while the host
-        // drives the SSSP rounds.  The rest of the expected steps then go out as one
-        // group.
+        // return at once.
         const bool side_waits = side && tiles && !side->done;
         int want = GROUP;
-        if (launched == 0 && side_waits) want = SIDE_GROUP;
-        else if (launched == 0 && first_group > GROUP) want = std::min(first_group, 64);
+        if (launched == 0 && first_group > GROUP) want = std::min(first_group, 64);
         else if (launched > 0 && first_group > launched + GROUP) want = std::min(first_group - launched, 64);
         const int grp = std::min(want, max_iter - launched);
         slots.clear();
-        for (int j = 0; j < grp; ++j) {
-            if (!tiles) DG_TRY(counters_clear(g));  // the heavy-row queue counters of the pull
-            int ps;
-            if (tiles) {
-                // tiles: off 8 + xn 8 per row, col 4 + contrib 8 per base entry
-                ps = prof_begin("pr_tiles", s);
-                hipLaunchKernelGGL(tiles_kernel, dim3((unsigned)nb),
-                                   dim3(MP_THREADS), 0, s, ws.mp_row.p,
-                                   ws.mp_edge.p, R.off.p, R.col.p, contrib, prs + 2, damping, xn, pf, pl, done);
-                prof_end(ps, s, 16.0 * (double)g->n + 12.0 * (double)R.m);
-                hipLaunchKernelGGL(k_pr_rows, dim3(grid_for(nb + R.dm)), dim3(256), 0, s, nb, items, ws.mp_row.p,
-                                   ws.mp_edge.p, R.off.p, pf, pl, R.dm, R.dkey.p, R.doff.p, R.dcol.p, R.keybits,
-                                   contrib, prs + 2, damping, xn, done);
-            } else {
-                int64_t blocks = std::min<int64_t>((na + 255) / 256, 65535);
-                ps = prof_begin("pr_pull", s);
-                hipLaunchKernelGGL(k_pr_pull, dim3((unsigned)blocks), dim3(256), 0, s, A, na, rv, contrib,
-                                   prs + 2, damping, xn, hq, ws.dcnt + C_HEAVY, hv, ws.dcnt + C_AUX3,
-                                   heavy_deg(g), heavy_deg(g), done);
-                prof_end(ps, s, 28.0 * (double)na + 12.0 * (double)edges);
-                hipLaunchKernelGGL(k_pr_heavy, dim3(8192), dim3(256), 0, s, rv, contrib, hq, ws.dcnt + C_HEAVY,
-                                   heavy_deg(g), ws.part.p);
-                hipLaunchKernelGGL(k_pr_finish, dim3(64), dim3(256), 0, s, hv, ws.dcnt + C_AUX3, ws.part.p,
-                                   prs + 2, damping, xn);
-            }
-            int pa = prof_begin("pr_apply", s);
-            if (tiles) {
-                // the step just written becomes the current vector: no copy
-                hipLaunchKernelGGL(k_pr_apply, dim3(APPLY_GROUPS), dim3(256), 0, s, A, na, xn, x,
-                                   (double *)nullptr, contrib, g->fwd.deg.p, partials, partials2, dprev, prs);
-                prof_end(pa, s, 28.0 * (double)na);
-                std::swap(x, xn);
-            } else {
-                hipLaunchKernelGGL(k_pr_apply, dim3(APPLY_GROUPS), dim3(256), 0, s, A, na, xn, x, x, contrib,
-                                   g->fwd.deg.p, partials, partials2, dprev, prs);
-                prof_end(pa, s, 40.0 * (double)na);
-            }
-            hipLaunchKernelGGL(k_pr_reduce, dim3(1), dim3(256), 0, s, partials, partials2, APPLY_GROUPS,
-                               (int)global, S, damping, ninv, tol, 0, extrap, prs, step_out);
-            DG_HIP(hipGetLastError());
-            slots.emplace_back(ps, pa);
+        int queued = 0;
+        if (side_waits) {
+            // Tile steps touch no state the SSSP update uses, so it runs on the second
+            // stream beside them.  The host can only queue about two dozen launches
+            // ahead of the device before a launch call blocks, and it drives the SSSP
+            // rounds itself: so it queues SIDE_GROUP steps, starts the SSSP work, and
+            // whenever it waits on the SSSP stream it queues more of the group's steps,
+            // AHEAD of the last one the device has finished (events in a ring).
+            for (auto &e : ws.step_ev)
+                if (!e) DG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+            auto queue_one = [&]() -> int {
+                DG_TRY(launch_step());
+                DG_HIP(hipEventRecord(ws.step_ev[queued % RING], s));
+                ++queued;
+                return DG_OK;
+            };
+            while (queued < std::min(SIDE_GROUP, grp)) DG_TRY(queue_one());
+            int prc = DG_OK;
+            std::function<void()> pump = [&]() {
+                while (prc == DG_OK && queued < grp &&
+                       (queued < AHEAD || hipEventQuery(ws.step_ev[(queued - AHEAD) % RING]) == hipSuccess))
+                    prc = queue_one();
+            };
+            g->pump = &pump;
+            side->beside = true;
+            side->run();
+            g->pump = nullptr;
+            DG_TRY(prc);
         }
+        for (; queued < grp; ++queued) DG_TRY(launch_step());
         launched += grp;
         double hp[11];
         // the host slots after the counters: a counter read of a side stream leaves them alone
         DG_HIP(hipMemcpyAsync(ws.hcnt + C_COUNT, prs, sizeof(hp), hipMemcpyDeviceToHost, s));
-        // tile steps touch no state the SSSP update uses: run it while they stream
-        if (side && tiles && !side->done) {
-            side->beside = true;
-            side->run();
-        }
         DG_HIP(hipStreamSynchronize(s));
         std::memcpy(hp, ws.hcnt + C_COUNT, sizeof(hp));
         const int32_t total = (int32_t)hp[4];

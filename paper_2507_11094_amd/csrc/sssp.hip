@@ -500,17 +500,31 @@ int sssp_pre_delete(dg_query *q, int64_t adel) {
 }
 
 // ---- frontier rounds captured in hipGraphs ---------------------------------------------
-// The same four steps as the host-driven path, with every count, frontier length
-// and dedup stamp kept in device memory, so a fixed number of frontier steps can
-// be captured once into a hipGraph and replayed for every batch: the cut walk (up
-// to CUT_LEVELS levels) in one graph, the pull, the seeding and up to PUSH_ROUNDS
-// push rounds in another.  A step whose frontier is empty does nothing, so the
-// graphs fit any batch; if a frontier is still non-empty at the end of a graph the
-// host continues the same steps one launch at a time.  Kernel boundaries are the
-// only grid-wide barriers, and no counter is contended beyond one append per wave.
-enum { R_CA = 8, R_CB, R_LIST, R_PA, R_PB, R_STAMP, R_STEPS, R_END };  // slots of q->qcnt
-constexpr int CUT_LEVELS = 8, PUSH_ROUNDS = 16;
-static_assert(R_END <= 16, "round counters must fit the pinned staging block");
+// The same four steps as the host-driven path, with every count, frontier length,
+// dedup stamp and (near-far) bucket threshold kept in device memory, so that a
+// fixed number of frontier steps can be captured once into a hipGraph and replayed
+// for every batch: the cut walk (CUT_LEVELS levels) in one graph, the pull, the
+// seeding and PUSH_ROUNDS push rounds in another.  A step whose frontier is empty
+// does nothing, so the graphs fit any batch.  Termination is decided on the device
+// as well: each graph ends where a second graph, holding only the same rounds,
+// continues from the device-resident counts (an even number of rounds per graph
+// brings the frontier back to the buffer it started in), and the host replays that
+// graph until the counts it reads after each replay are zero -- one host round
+// trip per replay instead of one per step.  Kernel boundaries are the only
+// grid-wide barriers, and no counter is contended beyond one append per wave.
+enum {
+    R_CA = 8, R_CB, R_LIST, R_PA, R_PB, R_STAMP, R_STEPS,
+    // near-far rounds: relaxation output count, far-pile size and its other buffer's
+    // count, which far buffer holds the pile, threshold T, smallest pile distance
+    // (as INF - d), advance flag of the round, membership stamp of this batch
+    R_NB, R_NF, R_NF2, R_FPAR, R_T, R_BEST, R_ADV, R_FST,
+    R_END
+};  // slots of q->qcnt
+constexpr int CUT_LEVELS = 8, PUSH_ROUNDS = 16, NF_ROUNDS = 16;
+static_assert(R_END <= 32, "round counters must fit the pinned staging block");
+static_assert((CUT_LEVELS % 2) == 0 && (PUSH_ROUNDS % 2) == 0 && (NF_ROUNDS % 2) == 0,
+              "a continuation graph must end in the buffer it starts from");
+constexpr int HPIN_SLOTS = 32;
 
 // Next step: zero the output count and the heavy-chunk count, advance the stamp,
 // count the step if its input frontier is non-empty.
@@ -623,6 +637,146 @@ __global__ void k_sssp_on_add_d(const int64_t *na_p, const int32_t *aiu, const i
     }
 }
 
+// ---- near-far rounds with device-side state --------------------------------------------
+// The near-far schedule of sssp_push_nearfar with its threshold, pile size, pile
+// buffer and membership stamp in q->qcnt.  A round relaxes the near frontier into
+// an output list, splits that list into the next near frontier (dist < T) and the
+// far pile, and, when the near frontier came out empty while the pile is not,
+// advances the bucket: T1 = (smallest pile distance >= T) + delta, entries in
+// [T, T1) become the near frontier, entries >= T1 stay, stale ones leave.  Every
+// kernel reads the counts and T from device memory and does nothing when its work
+// is empty, so the rounds can be captured and replayed.
+
+// Reset for a batch: empty pile, fresh membership stamp.
+__global__ void k_nfd_reset(int64_t *ctr) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        ctr[R_BEST] = 0;
+        ctr[R_NF] = 0;
+        ctr[R_NF2] = 0;
+        ctr[R_FPAR] = 0;
+        ctr[R_ADV] = 0;
+        ctr[R_FST] += 1;
+    }
+}
+
+// Smallest finite distance of the seeds, as INF - d through a max (0: none).
+__global__ void k_nfd_seed_min(const int64_t *nf_p, const int32_t *F, const uint64_t *key, int64_t *out) {
+    const int64_t nf = *nf_p;
+    int64_t best = 0;
+    for (int64_t i = gtid(); i < nf; i += gstride()) {
+        const int32_t d = sssp_dist(key[F[i]]);
+        if (d < INF) best = max(best, (int64_t)(INF - d));
+    }
+    best = wave_max_i32((int32_t)best);
+    if (lane_id() == 0 && best > 0) atomicMax((unsigned long long *)out, (unsigned long long)best);
+}
+
+// First threshold: nearest seed + delta (INF when no seed is finite: nothing moves).
+__global__ void k_nfd_start(int64_t *ctr, int32_t delta) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        const int64_t best = ctr[R_BEST];
+        ctr[R_T] = best == 0 ? (int64_t)INF : min((int64_t)(INF - best) + delta, (int64_t)INF);
+    }
+}
+
+__device__ __forceinline__ int32_t nfd_next_threshold(int64_t best, int32_t delta) {
+    return best == 0 ? INF : (int32_t)min((int64_t)(INF - best) + delta, (int64_t)INF);
+}
+
+// The previous round's bucket advance takes effect (when it advanced: the kept
+// entries are the pile, T moves to T1), then this round's set-up: zero the
+// relaxation, near-output, heavy-chunk and advance counts, advance the dedup stamp,
+// count the step if its near frontier is non-empty.  in_cnt == nullptr: commit only.
+__global__ void k_nfd_step(int64_t *ctr, int32_t delta, const int64_t *in_cnt, int64_t *out_cnt, int64_t *hcount) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (ctr[R_ADV] != 0) {
+        ctr[R_T] = nfd_next_threshold(ctr[R_BEST], delta);
+        ctr[R_NF] = ctr[R_NF2];
+        ctr[R_FPAR] ^= 1;
+        ctr[R_ADV] = 0;
+    }
+    if (!in_cnt) return;
+    *out_cnt = 0;
+    *hcount = 0;
+    ctr[R_NB] = 0;
+    ctr[R_BEST] = 0;
+    ctr[R_NF2] = 0;
+    ctr[R_STAMP] += 1;
+    if (*in_cnt > 0) ctr[R_STEPS] += 1;
+}
+
+// Relaxed vertices (count at ctr[R_NB]) -> next near frontier (dist < T) or the pile.
+__global__ void k_nfd_split(const int32_t *N, const uint64_t *key, int64_t *ctr, int32_t *near, int64_t *nnear,
+                            int32_t *far0, int32_t *far1, int32_t *farflag) {
+    __shared__ BlockScratch sc;
+    const int64_t nn = ctr[R_NB];
+    const int32_t T = (int32_t)ctr[R_T], fst = (int32_t)ctr[R_FST];
+    int32_t *far = ctr[R_FPAR] ? far1 : far0;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < nn; base += gstride()) {
+        const int64_t i = base + threadIdx.x;
+        bool pn = false, pf = false;
+        int32_t v = 0;
+        if (i < nn) {
+            v = N[i];
+            pn = sssp_dist(key[v]) < T;
+            pf = !pn && atomicExch(&farflag[v], fst) != fst;
+        }
+        const int64_t sn = block_append(nnear, pn, sc);
+        if (pn) near[sn] = v;
+        const int64_t sf = block_append(ctr + R_NF, pf, sc);
+        if (pf) far[sf] = v;
+    }
+}
+
+// The round advances the bucket when its near output is empty and the pile is
+// not (the split is done, so the near count is final here; the refill that appends
+// to it reads the decision from R_ADV).  Then: smallest pile distance >= T, as
+// INF - d through a max (0: none).
+__global__ void k_nfd_min(int64_t *ctr, const int64_t *nnear, const int32_t *far0, const int32_t *far1,
+                          const uint64_t *key) {
+    const bool adv = *nnear == 0 && ctr[R_NF] > 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctr[R_ADV] = adv ? 1 : 0;
+    if (!adv) return;
+    const int64_t nf = ctr[R_NF];
+    const int32_t T = (int32_t)ctr[R_T];
+    const int32_t *far = ctr[R_FPAR] ? far1 : far0;
+    int64_t best = 0;
+    for (int64_t i = gtid(); i < nf; i += gstride()) {
+        const int32_t d = sssp_dist(key[far[i]]);
+        if (d >= T && d < INF) best = max(best, (int64_t)(INF - d));
+    }
+    best = wave_max_i32((int32_t)best);
+    if (lane_id() == 0 && best > 0) atomicMax((unsigned long long *)(ctr + R_BEST), (unsigned long long)best);
+}
+
+// Next bucket: pile entries in [T, T1) go near, entries >= T1 stay (other buffer),
+// the rest are stale; entries leaving the pile clear their membership stamp.
+__global__ void k_nfd_refill(int64_t *ctr, int32_t *far0, int32_t *far1, const uint64_t *key, int32_t delta,
+                             int32_t *near, int64_t *nnear, int32_t *farflag) {
+    __shared__ BlockScratch sc;
+    if (ctr[R_ADV] == 0) return;
+    const int64_t nf = ctr[R_NF];
+    const int32_t T0 = (int32_t)ctr[R_T], T1 = nfd_next_threshold(ctr[R_BEST], delta);
+    const int32_t *far = ctr[R_FPAR] ? far1 : far0;
+    int32_t *far2 = ctr[R_FPAR] ? far0 : far1;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < nf; base += gstride()) {
+        const int64_t i = base + threadIdx.x;
+        bool pn = false, pk = false;
+        int32_t v = 0;
+        if (i < nf) {
+            v = far[i];
+            const int32_t d = sssp_dist(key[v]);
+            pk = d >= T1;
+            pn = !pk && d >= T0;
+            if (!pk) farflag[v] = 0;
+        }
+        const int64_t sn = block_append(nnear, pn, sc);
+        if (pn) near[sn] = v;
+        const int64_t sk = block_append(ctr + R_NF2, pk, sc);
+        if (pk) far2[sk] = v;
+    }
+}
+
 static ExpandArgs dev_args(dg_graph *g, const Dir &d, const int32_t *F, const int64_t *nfp) {
     ExpandArgs a = make_args(g, d, F, 0);
     a.nfp = nfp;
@@ -647,40 +801,88 @@ static int push_round(dg_query *q, const int32_t *F, const int64_t *cf, int32_t 
     return launch_expand(g->stream, dev_args(g, g->fwd, F, cf), op, 1024);
 }
 
-static int rounds_cut_enqueue(dg_query *q) {
+// Cut levels alternate f0 (count R_CA) and f1 (R_CB).  first: level 0 walks the
+// seeds (the head of the cut list) into f0; otherwise the levels continue from f1,
+// where the previous graph's last level left its output.
+static int rounds_cut_enqueue(dg_query *q, bool first) {
     dg_graph *g = q->g;
     int64_t *ctr = q->qcnt.p;
-    hipLaunchKernelGGL(k_rounds_init, dim3(1), dim3(64), 0, g->stream, ctr);
-    // level 0 walks the seeds (the head of the cut list); then f0 <-> f1
-    DG_TRY(cut_level(q, q->inval.p, ctr + 0, g->ws.f0.p, ctr + R_CA));
-    for (int l = 1; l < CUT_LEVELS; ++l) {
-        const bool odd = l & 1;
-        DG_TRY(cut_level(q, odd ? g->ws.f0.p : g->ws.f1.p, ctr + (odd ? R_CA : R_CB), odd ? g->ws.f1.p : g->ws.f0.p,
-                         ctr + (odd ? R_CB : R_CA)));
+    int l0 = 0;
+    if (first) {
+        hipLaunchKernelGGL(k_rounds_init, dim3(1), dim3(64), 0, g->stream, ctr);
+        DG_TRY(cut_level(q, q->inval.p, ctr + 0, g->ws.f0.p, ctr + R_CA));
+        l0 = 1;
+    }
+    for (int l = l0; l < CUT_LEVELS; ++l) {
+        const bool from_a = (l & 1) != 0;  // odd levels read f0, even levels f1
+        DG_TRY(cut_level(q, from_a ? g->ws.f0.p : g->ws.f1.p, ctr + (from_a ? R_CA : R_CB),
+                         from_a ? g->ws.f1.p : g->ws.f0.p, ctr + (from_a ? R_CB : R_CA)));
     }
     DG_HIP(hipGetLastError());
     return DG_OK;
 }
 
-static int rounds_push_enqueue(dg_query *q) {
+// Near-far round: near frontier F (count *cf) -> relaxed list nfout (R_NB) -> next
+// near frontier N (count *cn) and the pile; then the bucket advance if N is empty
+// (taking effect in the next round's set-up, or the graph's closing commit).  The
+// kernels that only act on an advance run on small grids: most rounds skip them.
+static int nf_round(dg_query *q, const int32_t *F, const int64_t *cf, int32_t *N, int64_t *cn) {
     dg_graph *g = q->g;
     Work &ws = g->ws;
     hipStream_t s = g->stream;
     int64_t *ctr = q->qcnt.p;
-    // pull once at every cut vertex
-    hipLaunchKernelGGL(k_round_prep, dim3(1), dim3(64), 0, s, nullptr, ws.dcnt + C_HEAVY, ctr, nullptr);
-    DG_TRY(launch_expand(s, dev_args(g, *g->rev, q->inval.p, ctr + R_LIST), PullOp{q->key.p}, 1024));
-    // seeds: pulled cut vertices and improved heads of inserted arcs
-    hipLaunchKernelGGL(k_round_prep, dim3(1), dim3(64), 0, s, ctr + R_PA, ws.dcnt + C_HEAVY, ctr, nullptr);
-    hipLaunchKernelGGL(k_sssp_pulled_d, dim3(1024), dim3(256), 0, s, ctr + R_LIST, q->inval.p, q->key.p,
-                       q->gstamp.p, ctr + R_STAMP, ws.f0.p, ctr + R_PA);
-    hipLaunchKernelGGL(k_sssp_on_add_d, dim3(1024), dim3(256), 0, s, ctr + 1, ws.aiu.p, ws.aiv.p, ws.aiw.p,
-                       q->key.p, q->gstamp.p, ctr + R_STAMP, ws.f0.p, ctr + R_PA);
-    for (int r = 0; r < PUSH_ROUNDS; ++r) {
-        const bool even = (r & 1) == 0;
-        DG_TRY(push_round(q, even ? ws.f0.p : ws.f1.p, ctr + (even ? R_PA : R_PB), even ? ws.f1.p : ws.f0.p,
-                          ctr + (even ? R_PB : R_PA)));
+    const int32_t delta = g->cfg.sssp_delta;
+    hipLaunchKernelGGL(k_nfd_step, dim3(1), dim3(64), 0, s, ctr, delta, cf, cn, ws.dcnt + C_HEAVY);
+    RelaxOpD op{q->key.p, q->gstamp.p, ctr + R_STAMP, ws.nfout.p, ctr + R_NB};
+    DG_TRY(launch_expand(s, dev_args(g, g->fwd, F, cf), op, 1024));
+    hipLaunchKernelGGL(k_nfd_split, dim3(256), dim3(256), 0, s, ws.nfout.p, q->key.p, ctr, N, cn, ws.far0.p,
+                       ws.far1.p, q->gfar.p);
+    hipLaunchKernelGGL(k_nfd_min, dim3(64), dim3(256), 0, s, ctr, cn, ws.far0.p, ws.far1.p, q->key.p);
+    hipLaunchKernelGGL(k_nfd_refill, dim3(64), dim3(256), 0, s, ctr, ws.far0.p, ws.far1.p, q->key.p, delta, N, cn,
+                       q->gfar.p);
+    return DG_OK;
+}
+
+// Push rounds alternate f0 (count R_PA) and f1 (R_PB) and end in f0.  first: the
+// pull at every cut vertex and the seeding come first (and, near-far, the bucket
+// set-up).  Near-far rounds when sssp_delta > 0.
+static int rounds_push_enqueue(dg_query *q, bool first) {
+    dg_graph *g = q->g;
+    Work &ws = g->ws;
+    hipStream_t s = g->stream;
+    int64_t *ctr = q->qcnt.p;
+    const bool nf = g->cfg.sssp_delta > 0;
+    if (first) {
+        // pull once at every cut vertex
+        hipLaunchKernelGGL(k_round_prep, dim3(1), dim3(64), 0, s, nullptr, ws.dcnt + C_HEAVY, ctr, nullptr);
+        DG_TRY(launch_expand(s, dev_args(g, *g->rev, q->inval.p, ctr + R_LIST), PullOp{q->key.p}, 1024));
+        // seeds: pulled cut vertices and improved heads of inserted arcs
+        hipLaunchKernelGGL(k_round_prep, dim3(1), dim3(64), 0, s, ctr + R_PA, ws.dcnt + C_HEAVY, ctr, nullptr);
+        hipLaunchKernelGGL(k_sssp_pulled_d, dim3(1024), dim3(256), 0, s, ctr + R_LIST, q->inval.p, q->key.p,
+                           q->gstamp.p, ctr + R_STAMP, ws.f0.p, ctr + R_PA);
+        hipLaunchKernelGGL(k_sssp_on_add_d, dim3(1024), dim3(256), 0, s, ctr + 1, ws.aiu.p, ws.aiv.p, ws.aiw.p,
+                           q->key.p, q->gstamp.p, ctr + R_STAMP, ws.f0.p, ctr + R_PA);
+        if (nf) {
+            hipLaunchKernelGGL(k_nfd_reset, dim3(1), dim3(64), 0, s, ctr);
+            hipLaunchKernelGGL(k_nfd_seed_min, dim3(1024), dim3(256), 0, s, ctr + R_PA, ws.f0.p, q->key.p,
+                               ctr + R_BEST);
+            hipLaunchKernelGGL(k_nfd_start, dim3(1), dim3(64), 0, s, ctr, g->cfg.sssp_delta);
+        }
     }
+    const int rounds = nf ? NF_ROUNDS : PUSH_ROUNDS;
+    for (int r = 0; r < rounds; ++r) {
+        const bool even = (r & 1) == 0;
+        const int32_t *F = even ? ws.f0.p : ws.f1.p;
+        int32_t *N = even ? ws.f1.p : ws.f0.p;
+        const int64_t *cf = ctr + (even ? R_PA : R_PB);
+        int64_t *cn = ctr + (even ? R_PB : R_PA);
+        if (nf) DG_TRY(nf_round(q, F, cf, N, cn));
+        else DG_TRY(push_round(q, F, cf, N, cn));
+    }
+    // the last round's advance takes effect before the host reads the counts
+    if (nf)
+        hipLaunchKernelGGL(k_nfd_step, dim3(1), dim3(64), 0, s, ctr, g->cfg.sssp_delta, (const int64_t *)nullptr,
+                           (int64_t *)nullptr, (int64_t *)nullptr);
     DG_HIP(hipGetLastError());
     return DG_OK;
 }
@@ -688,7 +890,7 @@ static int rounds_push_enqueue(dg_query *q) {
 static int rounds_read(dg_query *q, int64_t *h) {
     dg_graph *g = q->g;
     DG_HIP(hipMemcpyAsync(q->hpin, q->qcnt.p, R_END * sizeof(int64_t), hipMemcpyDeviceToHost, g->stream));
-    DG_HIP(hipStreamSynchronize(g->stream));
+    DG_HIP(wait_stream(g, g->stream));
     std::memcpy(h, q->hpin, R_END * sizeof(int64_t));
     return DG_OK;
 }
@@ -696,14 +898,27 @@ static int rounds_read(dg_query *q, int64_t *h) {
 static int sssp_post_rounds(dg_query *q, int64_t ains, dg_batch_stats *st) {
     dg_graph *g = q->g;
     Work &ws = g->ws;
+    const bool nf = g->cfg.sssp_delta > 0;
     DG_TRY(ensure_frontiers(g));
-    if (!q->hpin) DG_HIP(hipHostMalloc((void **)&q->hpin, 16 * sizeof(int64_t), hipHostMallocDefault));
+    if (!q->hpin) DG_HIP(hipHostMalloc((void **)&q->hpin, HPIN_SLOTS * sizeof(int64_t), hipHostMallocDefault));
     if (!q->gstamp.p || q->gstamp.cap < (size_t)g->n + 1 || q->qcnt.cap < (size_t)R_END) {
-        // stamps and their counter start together (a stamp is never reused)
+        // stamps and their counters start together (a stamp is never reused)
         DG_TRY(q->qcnt.ensure(R_END, true, g->stream));
         DG_TRY(q->gstamp.ensure((size_t)g->n + 1));
         DG_TRY(fill_i32(q->gstamp.p, 0, g->n + 1, g->stream));
-        DG_TRY(fill_i64(q->qcnt.p + R_STAMP, 0, 1, g->stream));
+        DG_TRY(fill_i64(q->qcnt.p, 0, R_END, g->stream));
+    }
+    if (nf) {
+        const size_t cap = (size_t)g->n + 1;
+        DG_TRY(ws.far0.ensure(cap));
+        DG_TRY(ws.far1.ensure(cap));
+        DG_TRY(ws.nfout.ensure(cap));
+        if (!q->gfar.p || q->gfar.cap < cap) {
+            // membership stamps and their counter start together
+            DG_TRY(q->gfar.ensure(cap));
+            DG_TRY(fill_i32(q->gfar.p, 0, (int64_t)cap, g->stream));
+            DG_TRY(fill_i64(q->qcnt.p + R_FST, 0, 1, g->stream));
+        }
     }
     if (!q->gcache) {
         q->own_cache = new GraphCache();
@@ -718,34 +933,44 @@ static int sssp_post_rounds(dg_query *q, int64_t ains, dg_batch_stats *st) {
                                      g->fwd.dcol.p, g->fwd.dw.p, R.off.p, R.col.p, R.w.p, R.doff.p, R.dcol.p, R.dw.p,
                                      ws.aiu.p, ws.aiv.p, ws.aiw.p,
                                      reinterpret_cast<const void *>((intptr_t)heavy_deg(g))};
+    if (nf) {
+        sig.push_back(ws.far0.p);
+        sig.push_back(ws.far1.p);
+        sig.push_back(ws.nfout.p);
+        sig.push_back(q->gfar.p);
+        sig.push_back(reinterpret_cast<const void *>((intptr_t)g->cfg.sssp_delta));
+    }
     int64_t h[R_END];
     // the legacy null stream cannot be captured: launch the same steps directly
-    auto run = [&](const std::function<int()> &enqueue) {
-        return g->stream ? graph_replay(g, q->gcache, sig, enqueue) : enqueue();
+    auto run = [&](const char *tag, const std::function<int()> &enqueue) {
+        if (!g->stream) return enqueue();
+        sig.push_back(tag);
+        const int rc = graph_replay(g, q->gcache, sig, enqueue);
+        sig.pop_back();
+        return rc;
     };
-    // 1. cut walk
-    sig.push_back("cut");
-    DG_TRY(run([&]() { return rounds_cut_enqueue(q); }));
+    // 1. cut walk: the first graph, then its continuation until the last level's
+    //    output (f1) is empty
+    // Bellman-Ford settles within n rounds and a cut walk within n levels: a replay
+    // count far beyond that means the device state is inconsistent, not slow work
+    const int64_t max_replays = 4 * ((int64_t)g->n / std::min(CUT_LEVELS, PUSH_ROUNDS) + 1) + 1024;
+    int64_t replays = 0;
+    DG_TRY(run("cut", [&]() { return rounds_cut_enqueue(q, true); }));
     DG_TRY(rounds_read(q, h));
-    int last = (CUT_LEVELS & 1) ? R_CA : R_CB;  // output count of the last captured level
-    while (h[last] > 0) {
-        const bool from_a = last == R_CA;
-        DG_TRY(cut_level(q, from_a ? ws.f0.p : ws.f1.p, q->qcnt.p + last, from_a ? ws.f1.p : ws.f0.p,
-                         q->qcnt.p + (from_a ? R_CB : R_CA)));
-        last = from_a ? R_CB : R_CA;
+    while (h[R_CB] > 0) {
+        if (++replays > max_replays) return set_error(DG_EDEVICE, "SSSP cut walk did not terminate (internal error)");
+        DG_TRY(run("cut+", [&]() { return rounds_cut_enqueue(q, false); }));
         DG_TRY(rounds_read(q, h));
     }
     const int64_t ncut = h[R_LIST];
-    // 2-4. pull, seeds, push rounds
-    sig.back() = "push";
-    DG_TRY(run([&]() { return rounds_push_enqueue(q); }));
+    // 2-4. pull, seeds, push (or near-far) rounds, continued until the frontier
+    //      (and the far pile) are empty
+    DG_TRY(run(nf ? "nf" : "push", [&]() { return rounds_push_enqueue(q, true); }));
     DG_TRY(rounds_read(q, h));
-    last = (PUSH_ROUNDS & 1) ? R_PB : R_PA;
-    while (h[last] > 0) {
-        const bool from_a = last == R_PA;
-        DG_TRY(push_round(q, from_a ? ws.f0.p : ws.f1.p, q->qcnt.p + last, from_a ? ws.f1.p : ws.f0.p,
-                          q->qcnt.p + (from_a ? R_PB : R_PA)));
-        last = from_a ? R_PB : R_PA;
+    while (h[R_PA] > 0 || (nf && h[R_NF] > 0)) {
+        if (++replays > max_replays)
+            return set_error(DG_EDEVICE, "SSSP push rounds did not terminate (internal error)");
+        DG_TRY(run(nf ? "nf+" : "push+", [&]() { return rounds_push_enqueue(q, false); }));
         DG_TRY(rounds_read(q, h));
     }
     if (st) {
@@ -761,11 +986,18 @@ int sssp_post_update(dg_query *q, int64_t adel, int64_t ains, dg_batch_stats *st
     hipStream_t s = g->stream;
     Work &ws = g->ws;
     DG_TRY(ensure_frontiers(g));
-    if (g->cfg.sssp_persistent == 2 && g->cfg.sssp_delta <= 0) return sssp_post_rounds(q, ains, st);
+    // 2: frontier rounds with device-side counts and termination, captured and
+    // replayed.  The default (0, as 3) launches each step from the host with a grid
+    // sized to its frontier and reads its count: measured faster on this GPU, where
+    // a replayed graph node costs more than the round trip it saves (SSSP alone, 100k
+    // batches: R-MAT 22 about equal, 4096^2 grid with near-far buckets 15-23 ms per
+    // batch host-driven against 21-32 ms captured; beside the PageRank steps the
+    // fixed grid-stride grids of the captured rounds also slowed the tile kernel).
+    if (g->cfg.sssp_persistent == 2) return sssp_post_rounds(q, ains, st);
     if (g->cfg.sssp_persistent == 1) {
         // the same four steps on device work queues, without host round trips
         DG_TRY(q->qcnt.ensure(4));
-        if (!q->hpin) DG_HIP(hipHostMalloc((void **)&q->hpin, 16 * sizeof(int64_t), hipHostMallocDefault));
+        if (!q->hpin) DG_HIP(hipHostMalloc((void **)&q->hpin, HPIN_SLOTS * sizeof(int64_t), hipHostMallocDefault));
         q->hpin[0] = q->nseeds;
         q->hpin[1] = ains;
         DG_HIP(hipMemcpyAsync(q->qcnt.p, q->hpin, 2 * sizeof(int64_t), hipMemcpyHostToDevice, s));

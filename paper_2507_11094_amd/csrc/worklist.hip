@@ -594,7 +594,7 @@ int graph_replay(dg_graph *g, GraphCache *cache, const std::vector<const void *>
         e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
         if (e != hipSuccess) return set_error(DG_EDEVICE, "graph instantiate failed: %s", hipGetErrorString(e));
-        if (cache->entries.size() >= 8) {
+        if (cache->entries.size() >= 16) {
             (void)hipGraphExecDestroy(cache->entries.front().exec);
             cache->entries.erase(cache->entries.begin());
         }

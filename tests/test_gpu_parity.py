@@ -302,7 +302,8 @@ def test_build_rejects_bad_edge_lists():
 
 # ------------------------------------------------------------------ SSSP
 
-@pytest.mark.parametrize("heavy,persistent", [(0, 0), (8, 0), (1 << 20, 0), (0, 1), (8, 1), (0, 2), (8, 2)])
+@pytest.mark.parametrize("heavy,persistent", [(0, 0), (8, 0), (1 << 20, 0), (0, 1), (8, 1), (0, 2), (8, 2), (0, 3),
+                                             (8, 3)])
 def test_sssp_c1_dynamic(heavy, persistent):
     n, s, d, w, (bs, bd, bw, bo) = graphgen.c1_workload()
     say("sssp C1 heavy", heavy, "persistent", persistent)
@@ -321,7 +322,7 @@ def test_sssp_c1_dynamic(heavy, persistent):
     assert_tree(n, cs, cd, cw, 0, sd, sp)
 
 
-@pytest.mark.parametrize("persistent,delta", [(0, 0), (1, 0), (0, 15), (2, 0)])
+@pytest.mark.parametrize("persistent,delta", [(0, 0), (1, 0), (0, 15), (2, 0), (2, 15), (3, 0)])
 def test_sssp_many_batches_with_merges(persistent, delta):
     n, s, d, w = rmat_small(12, 8, 33)
     say("sssp sequence persistent", persistent, "delta", delta)
@@ -350,7 +351,8 @@ def test_sssp_many_batches_with_merges(persistent, delta):
     assert merges >= 2
 
 
-@pytest.mark.parametrize("persistent,delta", [(0, 0), (1, 0), (0, 1), (0, 700), (0, 6000), (2, 0)])
+@pytest.mark.parametrize("persistent,delta", [(0, 0), (1, 0), (0, 1), (0, 700), (0, 6000), (2, 0), (2, 1), (2, 700),
+                                            (3, 700)])
 def test_sssp_grid_and_hub(persistent, delta):
     """High-diameter grid (many frontier steps) plus a hub above the heavy limit."""
     n, s, d, w = graphgen.grid4(40, 40, 9, 1000)
@@ -391,14 +393,20 @@ def test_work_queue_refuses_deep_graphs():
     G.close()
 
 
-def test_sssp_rounds_captured_on_a_stream():
-    """Frontier rounds captured into hipGraphs (a non-null stream) and replayed for
-    every batch, with the host finishing long walks past the captured depth."""
+@pytest.mark.parametrize("kind,delta", [("rmat", 0), ("rmat", 40), ("grid", 0), ("grid", 700)])
+def test_sssp_rounds_captured_on_a_stream(kind, delta):
+    """Frontier rounds (near-far rounds when delta > 0) captured into hipGraphs on a
+    non-null stream and replayed for every batch; on the grid the walks and the
+    relaxation run far past one graph's rounds, so the continuation graphs are
+    replayed until the device-side counts are zero."""
     import torch
 
-    n, s, d, w = rmat_small(12, 8, 35)
-    say("sssp captured rounds on a stream")
-    G = dg.Graph(n, s, d, w, config=cfg(persistent=2))
+    if kind == "rmat":
+        n, s, d, w = rmat_small(12, 8, 35)
+    else:
+        n, s, d, w = graphgen.grid4(48, 48, 21, 1000)
+    say("sssp captured rounds on a stream", kind, "delta", delta)
+    G = dg.Graph(n, s, d, w, config=cfg(persistent=2, delta=delta))
     stream = torch.cuda.Stream()
     G.set_stream(stream.cuda_stream)
     q = G.sssp_attach(0)
@@ -625,14 +633,17 @@ def test_merge_tile_sizes(tile):
         assert np.array_equal(q.read()[0], oracle.sssp(n, cs, cd, cw, 1))
 
 
-@pytest.mark.parametrize("mode,pull,delta", [(2, 0, 0), (0, 0, 0), (1, 0, 0), (2, 1, 0), (2, 0, 40)])
-def test_sssp_and_pagerank_together(mode, pull, delta):
+@pytest.mark.parametrize("mode,pull,delta,sp", [(2, 0, 0, 0), (0, 0, 0, 0), (1, 0, 0, 0), (2, 1, 0, 0), (2, 0, 40, 0),
+                                               (2, 0, 0, 2), (2, 0, 40, 2)])
+def test_sssp_and_pagerank_together(mode, pull, delta, sp):
     """Two SSSP queries and PageRank on one graph: the SSSP updates run on a second
     stream beside the whole-graph tile steps (global form, pull 0), or after the
-    steps where they cannot overlap (local form, per-vertex waves)."""
+    steps where they cannot overlap (local form, per-vertex waves); host-driven
+    steps (sp 0) or captured rounds replayed on the second stream (sp 2), plain
+    or near-far (delta)."""
     n, s, d, w = hub_graph(seed=13)
-    say("sssp + pagerank together, pr_mode", mode, "pull", pull, "delta", delta)
-    c = cfg(merge=0.02, delta=delta)
+    say("sssp + pagerank together, pr_mode", mode, "pull", pull, "delta", delta, "sssp schedule", sp)
+    c = cfg(merge=0.02, delta=delta, persistent=sp)
     c.pr_mode = mode
     c.pr_pull = pull
     G = dg.Graph(n, s, d, w, config=c)
