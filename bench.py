@@ -907,10 +907,41 @@ def main() -> int:
                     help="plain Jacobi PageRank steps (default: extrapolated steps, same stopping rule)")
     ap.add_argument("--vertex-order", type=int, default=0,
                     help="vertex order inside the library: 0 by degree (default), 1 as given")
+    ap.add_argument("--gather-ladder", action="store_true",
+                    help="only time scattered 8-byte gathers over working sets from 64 KiB to 1 GiB "
+                         "(dg_calibrate kind 3) and print the rates")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run five plain 256 MiB device-to-device copies (reference for the "
                          "FETCH_SIZE / WRITE_SIZE counter scale) and exit")
     args = ap.parse_args()
+    if args.gather_ladder:
+        # Rate of scattered 8-byte gathers against the size of the set they hit: the
+        # library's calibration kind 3 (2^26 reads at hashed positions) over working
+        # sets from 64 KiB (cache-resident) to 1 GiB (HBM), HIP events on the stream.
+        import torch
+
+        import paper_2507_11094_amd as dg
+
+        lib = dg.load_library()
+        big = torch.zeros(1 << 30, dtype=torch.uint8, device="cuda:0")
+        st = torch.cuda.current_stream()
+        rows = []
+        for ws_bytes in (64 << 10, 512 << 10, 4 << 20, 32 << 20, 256 << 20, 1 << 30):
+            dg._check(lib.dg_calibrate(3, ctypes.c_void_p(big.data_ptr()), ws_bytes, ctypes.c_void_p(st.cuda_stream)))
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            reps = 5
+            e0.record(st)
+            for _ in range(reps):
+                dg._check(lib.dg_calibrate(3, ctypes.c_void_p(big.data_ptr()), ws_bytes,
+                                           ctypes.c_void_p(st.cuda_stream)))
+            e1.record(st)
+            e1.synchronize()
+            us = 1e3 * e0.elapsed_time(e1) / reps
+            rows.append({"working_set_bytes": ws_bytes, "us_per_launch": round(us, 2),
+                         "G_gathers_per_s": round((1 << 26) / us * 1e-3, 1)})
+            log(f"gather ladder: {rows[-1]}")
+        print(json.dumps({"gather_ladder": rows, "gathers_per_launch": 1 << 26, "bytes_per_gather": 8}), flush=True)
+        return 0
     if args.calibrate_copy:
         # Known-traffic launches for scaling the FETCH_SIZE / WRITE_SIZE counters:
         # five plain 256 MiB device copies (torch), then the library's calibration

@@ -464,9 +464,14 @@ int dg_scan_exclusive(const int64_t *in, int64_t *out, int64_t n, void *stream);
 /* Kernels with known memory traffic, for scaling hardware byte counters (the
  * roofline figures of the Experimental Evaluation comparisons rest on them):
  * kind 0 reads `bytes` bytes of device buffer `buf` once, kind 1 writes them once,
- * kind 2 reads one 4-byte word from each 128-byte line of them.  bytes must be a
- * multiple of 4 KiB; the buffer's contents are overwritten (kinds 1, 2) or kept
- * (kind 0).  Runs on `stream` (NULL: null stream) and returns when done. */
+ * kind 2 reads one 4-byte word from each 128-byte line of them, kind 3 makes 2^26
+ * 8-byte reads at pseudo-random positions (a SplitMix64 hash of the read index)
+ * within them, the access pattern of a scattered gather over a working set of
+ * `bytes` (the rate of the PageRank pull's contribution gathers depends on which
+ * cache level holds that set).  bytes must be a multiple of 4 KiB (kind 3: at
+ * least 64 KiB); the buffer's contents are overwritten (kinds 1, 2, and the first
+ * 64 KiB for kind 3) or kept (kind 0).  Runs on `stream` (NULL: null stream) and
+ * returns when done. */
 int dg_calibrate(int32_t kind, void *buf, int64_t bytes, void *stream);
 
 /* Floor under the whole-graph PageRank pull (the Jacobi sweep of the Appendix A

@@ -150,12 +150,49 @@ __global__ __launch_bounds__(256) void k_cal_gather(const int32_t *__restrict__ 
     if (acc == 0x7fffffff) sink[0] = acc;
 }
 
+// kind 3: CAL_GATHERS 8-byte reads at pseudo-random positions of the first `bytes`
+// bytes (SplitMix64 finaliser of the read index, modulo the word count), eight
+// independent reads in flight per lane, summed per workgroup; one 16-byte word of
+// the sum is written per workgroup at the buffer's start.
+constexpr int64_t CAL_GATHERS = 1ll << 26;
+__device__ __forceinline__ uint64_t cal_mix(uint64_t z) {
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+__global__ __launch_bounds__(256) void k_cal_rgather(const double *__restrict__ p, int64_t nwords, double *sink) {
+    constexpr int U = 8;
+    double acc = 0.0;
+    const int64_t st = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i0 < CAL_GATHERS; i0 += U * st) {
+        double v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t i = i0 + u * st;
+            v[u] = i < CAL_GATHERS ? p[cal_mix((uint64_t)i) % (uint64_t)nwords] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc += v[u];
+    }
+    __shared__ double red[256];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) sink[2 * blockIdx.x] = red[0];
+}
+
 }  // namespace dg
 
 extern "C" int dg_calibrate(int32_t kind, void *buf, int64_t bytes, void *stream) {
     using namespace dg;
-    if (!buf || bytes < 4096 || (bytes & 4095) || kind < 0 || kind > 2)
-        return set_error(DG_EINVAL, "calibration needs kind 0..2 and a device buffer of a multiple of 4 KiB");
+    if (!buf || bytes < 4096 || (bytes & 4095) || kind < 0 || kind > 3)
+        return set_error(DG_EINVAL, "calibration needs kind 0..3 and a device buffer of a multiple of 4 KiB");
+    if (kind == 3 && bytes < 4096 * 16)
+        return set_error(DG_EINVAL, "calibration kind 3 needs at least 64 KiB (one 16-byte sum per workgroup)");
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int blocks = 4096;
     if (kind == 0)
@@ -163,9 +200,12 @@ extern "C" int dg_calibrate(int32_t kind, void *buf, int64_t bytes, void *stream
                            static_cast<int4 *>(buf));
     else if (kind == 1)
         hipLaunchKernelGGL(k_cal_write, dim3(blocks), dim3(256), 0, s, static_cast<int4 *>(buf), bytes / 16);
-    else
+    else if (kind == 2)
         hipLaunchKernelGGL(k_cal_gather, dim3(blocks), dim3(256), 0, s, static_cast<const int32_t *>(buf),
                            bytes / 128, static_cast<int32_t *>(buf));
+    else
+        hipLaunchKernelGGL(k_cal_rgather, dim3(blocks), dim3(256), 0, s, static_cast<const double *>(buf), bytes / 8,
+                           static_cast<double *>(buf));
     DG_HIP(hipGetLastError());
     DG_HIP(hipStreamSynchronize(s));
     return DG_OK;

@@ -1130,3 +1130,24 @@ def test_pr_gather_floor():
     e = np.zeros(0, np.int32)
     E = dg.Graph(5, e, e, e)
     assert E.pr_gather_floor(1) == 0.0
+
+
+def test_calibration_kernels():
+    """dg_calibrate: every kind runs on a device buffer; the stream read keeps the
+    buffer, the stream write fills it; kinds outside 0..3, sizes that are not a
+    multiple of 4 KiB and kind 3 below 64 KiB are refused."""
+    import ctypes
+    import torch
+
+    say("calibration kernels")
+    lib = dg.load_library()
+    buf = torch.full((1 << 20,), 7, dtype=torch.uint8, device="cuda:0")
+    ptr = ctypes.c_void_p(buf.data_ptr())
+    dg._check(lib.dg_calibrate(0, ptr, buf.numel(), None))
+    assert int(buf[(1 << 19):].min()) == 7 and int(buf[(1 << 19):].max()) == 7
+    for kind in (1, 2, 3):
+        dg._check(lib.dg_calibrate(kind, ptr, buf.numel(), None))
+    torch.cuda.synchronize()
+    for kind, size in ((4, buf.numel()), (0, 5000), (3, 32 << 10)):
+        with pytest.raises(dg.DGError):
+            dg._check(lib.dg_calibrate(kind, ptr, size, None))
