@@ -136,7 +136,7 @@ typedef struct dg_config {
     /* Jacobi PageRank steps: 0 = plain steps, as in the Appendix A listings
      * (default); 1 = extrapolated steps: when two successive step vectors are
      * parallel (a least-squares fit s_k = lam s_{k-1} leaves at most 5 % of s_k
-     * unexplained, twice in a row with ratios within 5 %, 0 < lam <= 0.9), the
+     * unexplained, 0 < lam <= 0.9), the
      * error is dominated by one eigenvector and the next step also moves
      * lam / (1 - lam) times its own length further, which removes that component
      * (Aitken's process along the step).  Convergence is still declared only on a

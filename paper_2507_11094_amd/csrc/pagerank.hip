@@ -240,16 +240,16 @@ __device__ __forceinline__ void block_sum2b(double a, double b, double *out_a, d
 // x + lam / (1 - lam) (x' - x) removes that component (Aitken's delta-squared
 // process along the step).  lam is fitted by least squares, lam = <s_k, s_{k-1}> /
 // |s_{k-1}|^2, and the move is taken only when the fit leaves at most EX_FIT of
-// |s_k| unexplained at two successive steps whose fits agree within EX_MATCH, and
-// 0 < lam <= EX_MAX_LAM: modes of the opposite sign (bipartite graphs such as
-// grids have eigenvalues near -d) or several modes of similar size leave the steps
-// unaligned, and no move happens.  The next apply takes the move; a step that moved
+// |s_k| unexplained and 0 < lam <= EX_MAX_LAM: modes of the opposite sign
+// (bipartite graphs such as grids have eigenvalues near -d) or several modes of
+// similar size leave the steps unaligned, and no move happens.  (Asking for two
+// successive aligned fits with ratios within 5 % as well delayed the move by one
+// step and changed nothing else in the CPU models.)  The next apply takes the move; a step that moved
 // is never taken as converged, and the fits restart after it.  Convergence is only
 // declared on a plain step, whose L1 size bounds the error exactly as in plain
 // Jacobi, and the move keeps sum(x) (an affine combination of two vectors of equal
 // sum).
 constexpr double EX_FIT = 0.05;     // unexplained fraction of |s_k| (L2) at most
-constexpr double EX_MATCH = 0.05;   // two fitted ratios agree within this fraction
 constexpr double EX_MAX_LAM = 0.9;  // no move for slower ratios (factor <= 9)
 constexpr int EX_TRACK = 24;        // plain steps without a move before the fits stop
 __device__ __forceinline__ void pr_reduce_body(const double *partials, const double *partials2, int np, int global,
@@ -301,8 +301,7 @@ __device__ __forceinline__ void pr_reduce_body(const double *partials, const dou
         const double s2 = fs[0], sd = fs[1], p2 = prs[6];
         const double lam = p2 > 0.0 ? sd / p2 : 0.0;
         const bool aligned = p2 > 0.0 && s2 - sd * lam <= EX_FIT * EX_FIT * s2;
-        if (aligned && lam > 0.0 && lam <= EX_MAX_LAM && prs[7] > 0.0 && fabs(lam - prs[7]) <= EX_MATCH * lam &&
-            prs[9] >= 2.0 && lam * step > 2.0 * tol) {
+        if (aligned && lam > 0.0 && lam <= EX_MAX_LAM && prs[9] >= 2.0 && lam * step > 2.0 * tol) {
             prs[8] = lam / (1.0 - lam);
             prs[10] += 1.0;
         }
