@@ -270,6 +270,13 @@ __device__ __forceinline__ void pr_reduce_body(const double *partials, const dou
     if (fit) block_sum2b(sq, dot, &fs[0], &fs[1]);
     __syncthreads();
     if (threadIdx.x == 0) {
+        // S < 0: the conserved mass is prs[13], set by the set-up call (first) to the
+        // sum of the start vector (prs[0] then), and tol is relative to it
+        if (first && S < 0.0) prs[13] = prs[0];
+        if (S < 0.0) {
+            S = prs[13];
+            tol *= prs[13];
+        }
         prs[2] = global ? ((1.0 - damp) * S + damp * prs[1]) * ninv : (1.0 - damp) * ninv;
         *step_out = prs[0];
         if (first) {
@@ -397,6 +404,7 @@ __global__ __launch_bounds__(256) void k_sum_vec2(const double *x, const int32_t
 // x = (1-d) / ((1-d) S + d D(y)) * y, contrib = x / outdeg.
 __global__ void k_pr_rescale(int32_t n, double *x, double *contrib, const int32_t *deg, const double *prs,
                              double S, double damp) {
+    if (S < 0.0) S = prs[13];  // the mass kept on the device
     const double alpha = (1.0 - damp) / ((1.0 - damp) * S + damp * prs[1]);
     for (int64_t v = gtid(); v < n; v += gstride()) {
         double nv = x[v] * alpha;
@@ -478,8 +486,9 @@ __global__ void k_compact_flags(int32_t n, const int64_t *flags, const int64_t *
         if (flags[v]) out[pos[v]] = (int32_t)v;
 }
 
-__global__ void k_refresh_contrib(int64_t n, const int32_t *u, const double *x, const int32_t *deg,
+__global__ void k_refresh_contrib(const int64_t *n_p, const int32_t *u, const double *x, const int32_t *deg,
                                   double *contrib) {
+    const int64_t n = *n_p;
     for (int64_t i = gtid(); i < n; i += gstride()) {
         int32_t v = u[i];
         int32_t dg = deg[v];
@@ -750,8 +759,9 @@ static int ensure_pr_ws(dg_graph *g) {
 }
 
 // Total entries (base + diff, tombstones included) of the rows of A.
-__global__ void k_sum_degrees(const int32_t *A, int64_t na, const int64_t *off, const int64_t *doff,
-                              int64_t *out) {
+__global__ void k_sum_degrees(const int32_t *A, int64_t na, const int64_t *na_p, const int64_t *off,
+                              const int64_t *doff, int64_t *out) {
+    if (na_p) na = *na_p;
     int64_t acc = 0;
     for (int64_t i = gtid(); i < na; i += gstride()) {
         int32_t v = A[i];
@@ -763,7 +773,8 @@ __global__ void k_sum_degrees(const int32_t *A, int64_t na, const int64_t *off, 
 
 // Jacobi on A (nullptr = all n vertices) until the L1 step <= tol or max_iter.
 // global: the dangling-uniform form with conserved mass S (see the file header);
-// otherwise the local form.  `edges` = entries scanned per pull (for the
+// otherwise the local form.  S < 0: the mass is the sum of x at the start, kept on
+// the device, and tol is relative to it (no host round trip for it).  `edges` = entries scanned per pull (for the
 // algorithmic byte count):
 //   pull:  A[i] 4 + off 8 + doff 8 + xn write 8 per vertex, col 4 + contrib 8 per entry
 //   apply: A[i] 4 + xn 8 + x read 8 + x write 8 + contrib write 8 + outdeg 4 per vertex;
@@ -786,8 +797,8 @@ static int pr_iterate(dg_graph *g, const int32_t *A, int64_t na, int64_t edges, 
     double *const x_home = x, *const xn_home = xn;
     double *step_out = prs + 5;  // not in the shared counters: SSSP may run beside these steps
     ws.pr_moves = 0;
-    // constant term of the first step
-    if (global)
+    // constant term of the first step (and, S < 0, the mass of the start vector)
+    if (global || S < 0.0)
         hipLaunchKernelGGL(k_sum_vec2, dim3(APPLY_GROUPS), dim3(256), 0, s, x, g->fwd.deg.p, (int64_t)g->n,
                            partials);
     else
@@ -800,8 +811,9 @@ static int pr_iterate(dg_graph *g, const int32_t *A, int64_t na, int64_t edges, 
         DG_TRY(ws.prstep.ensure((size_t)g->n + 1));
         dprev = ws.prstep.p;
     }
-    hipLaunchKernelGGL(k_pr_reduce, dim3(1), dim3(256), 0, s, partials, partials2, global ? APPLY_GROUPS : 1,
-                       (int)global, S, damping, ninv, tol, 1, extrap, prs, step_out);
+    hipLaunchKernelGGL(k_pr_reduce, dim3(1), dim3(256), 0, s, partials, partials2,
+                       global || S < 0.0 ? APPLY_GROUPS : 1, (int)global, S, damping, ninv, tol, 1, extrap, prs,
+                       step_out);
     DG_HIP(hipGetLastError());
     // every vertex pulled: merge-path tiles over the base level, then the diff level
     const Dir &R = *g->rev;
@@ -1261,28 +1273,24 @@ static int pr_update(dg_query *q, int64_t adel, int64_t ains, dg_batch_stats *st
     if (ains > 0)
         hipLaunchKernelGGL(k_mark_list, dim3(grid_for(ains)), dim3(256), 0, s, ains, ws.aiu.p,
                            ws.stamp.p, st_s, S, ws.dcnt + C_AUX0);
-    DG_HIP(hipGetLastError());
-    DG_TRY(counters_read(g));
-    const int64_t ns = ws.hcnt[C_AUX0];
-    // the tails' share x / outdeg changed: refresh it before any Jacobi step
-    hipLaunchKernelGGL(k_refresh_contrib, dim3(grid_for(ns)), dim3(256), 0, s, ns, S, q->x.p, g->fwd.deg.p,
-                       q->contrib.p);
-    DG_HIP(hipGetLastError());
+    // the tails' share x / outdeg changed: refresh it before any Jacobi step (the
+    // count of distinct tails stays on the device; grids sized for every changed arc)
+    hipLaunchKernelGGL(k_refresh_contrib, dim3(grid_for(adel + ains)), dim3(256), 0, s, ws.dcnt + C_AUX0, S,
+                       q->x.p, g->fwd.deg.p, q->contrib.p);
     const int mode = g->cfg.pr_mode;  // 0 auto, 1 local, 2 global, 3 residual push
     const int64_t vlimit = (int64_t)(0.2 * (double)g->n);
     bool global = mode == 2;
-    if (mode == 0) {
-        // the seeds are the heads plus the tails' out-neighbours; when their count
-        // with repeats already passes 20% of the vertices, take the global form
-        // without expanding (both forms reach the same ranks; this only picks the
-        // cheaper one)
-        DG_TRY(counters_clear(g));
-        hipLaunchKernelGGL(k_sum_degrees, dim3(grid_for(ns)), dim3(256), 0, s, S, ns, g->fwd.off.p,
-                           g->fwd.doff.p, ws.dcnt + C_AUX1);
-        DG_HIP(hipGetLastError());
-        DG_TRY(counters_read(g));
-        if (adel + ains + ws.hcnt[C_AUX1] >= vlimit) global = true;
-    }
+    // the seeds are the heads plus the tails' out-neighbours; when their count with
+    // repeats already passes 20% of the vertices, the automatic mode takes the global
+    // form without expanding (both forms reach the same ranks; this only picks the
+    // cheaper one).  One read brings the tail count and that sum.
+    if (mode == 0)
+        hipLaunchKernelGGL(k_sum_degrees, dim3(grid_for(adel + ains)), dim3(256), 0, s, S, (int64_t)0,
+                           ws.dcnt + C_AUX0, g->fwd.off.p, g->fwd.doff.p, ws.dcnt + C_AUX1);
+    DG_HIP(hipGetLastError());
+    DG_TRY(counters_read(g));
+    const int64_t ns = ws.hcnt[C_AUX0];
+    if (mode == 0 && adel + ains + ws.hcnt[C_AUX1] >= vlimit) global = true;
     int64_t na = 0;
     ExpandArgs a;
     a.g = view(g->fwd);
@@ -1345,8 +1353,8 @@ static int pr_update(dg_query *q, int64_t adel, int64_t ains, dg_batch_stats *st
         DG_TRY(scan_excl(g, flags, pos, g->n + 1));
         hipLaunchKernelGGL(k_compact_flags, dim3(grid_for(g->n)), dim3(256), 0, s, g->n, flags, pos, Alist);
         DG_TRY(counters_clear(g));
-        hipLaunchKernelGGL(k_sum_degrees, dim3(grid_for(na)), dim3(256), 0, s, Alist, na, g->rev->off.p,
-                           g->rev->doff.p, ws.dcnt + C_AUX0);
+        hipLaunchKernelGGL(k_sum_degrees, dim3(grid_for(na)), dim3(256), 0, s, Alist, na, (const int64_t *)nullptr,
+                           g->rev->off.p, g->rev->doff.p, ws.dcnt + C_AUX0);
         DG_HIP(hipGetLastError());
         DG_TRY(counters_read(g));
         edges = ws.hcnt[C_AUX0];
@@ -1356,16 +1364,15 @@ static int pr_update(dg_query *q, int64_t adel, int64_t ains, dg_batch_stats *st
     // S = sum(x) of the warm start.  Both forms stop on the L1 step of the
     // normalised ranks x / S, so the tolerance on x is tol * S (the global form
     // also conserves S).
-    double Ssum;
-    DG_TRY(pr_mass(q, &Ssum));
+    // (S = -1: the mass stays on the device, summed by the iteration's set-up)
     if (global) {
         na = g->n;
         edges = all_edges;
-        DG_TRY(pr_iterate(g, nullptr, na, edges, q->damping, tol_of(q) * Ssum, q->max_iter, true, Ssum,
-                          q->x.p, q->xn.p, q->contrib.p, &iters, &conv, side, q->last_iters));
+        DG_TRY(pr_iterate(g, nullptr, na, edges, q->damping, tol_of(q), q->max_iter, true, -1.0, q->x.p, q->xn.p,
+                          q->contrib.p, &iters, &conv, side, q->last_iters));
     } else {
-        DG_TRY(pr_iterate(g, Alist, na, edges, q->damping, tol_of(q) * Ssum, q->max_iter, false, 0.0, q->x.p,
-                          q->xn.p, q->contrib.p, &iters, &conv));
+        DG_TRY(pr_iterate(g, Alist, na, edges, q->damping, tol_of(q), q->max_iter, false, -1.0, q->x.p, q->xn.p,
+                          q->contrib.p, &iters, &conv));
     }
     q->last_iters = iters;
     q->converged = conv;
