@@ -159,16 +159,29 @@ def copy_peak_gbs() -> float:
     return _COPY_GBS
 
 
-# What the library's edges_traversed tally covers: entries scanned by the PageRank
-# pulls (entries x steps) and arcs examined by the worklist SSSP rounds.  The
-# frontier SSSP kernels, the triangle kernels and the batched set keep no tally,
-# so a workload that runs only those reports null rather than zero.
-GTEPS_COUNTS = "PageRank pull entries x steps + worklist SSSP arcs; frontier SSSP, triangle and set kernels not counted"
+# What the library's edges_traversed tally covers: adjacency entries examined by
+# the PageRank pulls (entries x steps), the SSSP frontier steps (every entry of
+# every frontier vertex's row, base and diff level, in the cut walk, the pull and
+# the push rounds; the work-queue schedule counts arcs examined) and the triangle
+# kernel (entries of the shorter row intersected per changed edge).
+GTEPS_COUNTS = ("PageRank pull entries x steps + SSSP frontier-row entries (cut, pull, push) + "
+                "triangle shorter-row entries")
+# GTEPS as a fraction of the HBM roofline: an examined entry moves at least its
+# 4-byte column id and one 8-byte gathered value (the PageRank pull's 12 bytes; an
+# SSSP relaxation moves more), so 8 TB/s bounds the rate at 8000 / 12 G entries/s.
+GTEPS_BYTES_PER_EDGE = 12.0
 
 
 def gteps_of(stats, elapsed):
     e = sum(x["edges_traversed"] for x in stats)
     return round(e / elapsed / 1e9, 3) if e > 0 else None
+
+
+def gteps_roofline(gteps):
+    if gteps is None:
+        return None
+    peak = HBM_PEAK_GBS / GTEPS_BYTES_PER_EDGE
+    return {"bytes_per_edge": GTEPS_BYTES_PER_EDGE, "peak_gteps": round(peak, 1), "frac": round(gteps / peak, 4)}
 
 
 def step_spread(ms: list) -> dict:
@@ -435,6 +448,7 @@ def run_single(args, kind: str) -> dict:
                       "tc_removed": avg("tc_removed"), "tc_added": avg("tc_added"),
                       "merged": sum(x["merged"] for x in stats)},
         "gteps": gteps_of(stats, elapsed),
+        "gteps_roofline": gteps_roofline(gteps_of(stats, elapsed)),
         "gteps_counts": GTEPS_COUNTS,
         "step_ms": step_spread([x["t_total_ms"] for x in stats]),
         "kernels": kernel_table(prof),
@@ -676,7 +690,8 @@ def run_batched(args) -> dict:
                           ("t_validate_ms", "t_update_ms", "t_merge_ms", "t_sssp_ms", "t_total_ms")},
                per_step={"sssp_invalidated": avg("sssp_invalidated"), "deleted": avg("deleted"),
                          "inserted": avg("inserted"), "merged": sum(x["merged"] for x in stats)},
-               gteps=gteps_of(stats, elapsed), gteps_counts=GTEPS_COUNTS,
+               gteps=gteps_of(stats, elapsed), gteps_roofline=gteps_roofline(gteps_of(stats, elapsed)),
+               gteps_counts=GTEPS_COUNTS,
                step_ms=step_spread([x["t_total_ms"] for x in stats]),
                graph_launches=gstats, kernels=kernel_table(prof))
     S.close()

@@ -191,6 +191,7 @@ enum Counter {
     C_ERR = 0, C_NDEL, C_NINS, C_ADEL, C_IGNDEL, C_DISTINCT, C_AINS, C_IGNINS, C_NEW,
     C_TCDEL, C_TCINS, C_F0, C_F1, C_HEAVY, C_AUX0, C_AUX1, C_AUX2, C_AUX3,
     C_TC0, C_TC1, C_RED0 = 24,
+    C_EDGES = 30,  // adjacency entries examined by an SSSP step (base + diff, tombstones included)
     // set by a sort or scan whose look-back hit its spin limit; counters_clear
     // leaves it alone, counters_read reports it
     C_SORT_ERR = 39, C_COUNT = 40
@@ -373,5 +374,6 @@ void prof_drop(int slot);
 
 // triangle counting (tc.hip)
 int tc_count_static(dg_graph *g, uint64_t *count);
-int tc_delta(dg_graph *g, const int32_t *eu, const int32_t *ev, int64_t ne, uint64_t *sum6);
+int tc_delta(dg_graph *g, const int32_t *eu, const int32_t *ev, int64_t ne, uint64_t *sum6,
+             int64_t *entries = nullptr);
 }  // namespace dg

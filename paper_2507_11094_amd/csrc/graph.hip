@@ -1422,7 +1422,9 @@ int apply_chunk(dg_graph *g, int64_t k, const int32_t *src, const int32_t *dst, 
         } else if (q->kind == Q_TC && tcdel > 0) {
             PhaseTimer t(g, 4, &st->t_tc_ms);
             uint64_t sum6 = 0;
-            DG_TRY(tc_delta(g, ws.tcu.p, ws.tcv.p, tcdel, &sum6));
+            int64_t walked = 0;
+            DG_TRY(tc_delta(g, ws.tcu.p, ws.tcv.p, tcdel, &sum6, &walked));
+            st->edges_traversed += walked;
             q->tc -= sum6 / 6;
             st->tc_removed += (int64_t)(sum6 / 6);
             t.stop();
@@ -1585,7 +1587,9 @@ int apply_chunk(dg_graph *g, int64_t k, const int32_t *src, const int32_t *dst, 
         } else if (q->kind == Q_TC && tcins > 0) {
             PhaseTimer t(g, 4, &st->t_tc_ms);
             uint64_t sum6 = 0;
-            DG_TRY(tc_delta(g, ws.tcu.p + tcdel, ws.tcv.p + tcdel, tcins, &sum6));
+            int64_t walked = 0;
+            DG_TRY(tc_delta(g, ws.tcu.p + tcdel, ws.tcv.p + tcdel, tcins, &sum6, &walked));
+            st->edges_traversed += walked;
             q->tc += sum6 / 6;
             st->tc_added += (int64_t)(sum6 / 6);
             t.stop();

@@ -215,6 +215,28 @@ static ExpandArgs make_args(dg_graph *g, const Dir &d, const int32_t *F, int64_t
     return a;
 }
 
+// Adjacency entries (base + diff, tombstones included) of a frontier F of nf vertices
+// (nf_p: the count in device memory), added to *out: the edges a frontier step
+// examines, for the traversal tally (GTEPS).  One add per wave.
+__global__ void k_frontier_edges(const int32_t *F, int64_t nf, const int64_t *nf_p, const int64_t *__restrict__ off,
+                                 const int64_t *__restrict__ doff, int64_t *out) {
+    if (nf_p) nf = *nf_p;
+    int64_t acc = 0;
+    for (int64_t i = gtid(); i < nf; i += gstride()) {
+        const int32_t v = F[i];
+        acc += (off[v + 1] - off[v]) + (doff[v + 1] - doff[v]);
+    }
+    acc = wave_sum(acc);
+    if (lane_id() == 0 && acc) atomicAdd((unsigned long long *)out, (unsigned long long)acc);
+}
+
+static void tally_edges(dg_graph *g, const Dir &d, const int32_t *F, int64_t nf, const int64_t *nf_p,
+                        int64_t *out) {
+    const int grid = nf_p ? 256 : grid_for(nf);
+    if (!nf_p && nf <= 0) return;
+    hipLaunchKernelGGL(k_frontier_edges, dim3(grid), dim3(256), 0, g->stream, F, nf, nf_p, d.off.p, d.doff.p, out);
+}
+
 // ---- near-far schedule --------------------------------------------------------------
 // The push relaxes in Bellman-Ford rounds; on high-diameter graphs with spread
 // weights (road networks) a vertex is improved many times before its distance
@@ -313,7 +335,7 @@ static int sssp_push_nearfar(dg_graph *g, uint64_t *key, int64_t nf, int32_t del
     int32_t T = (int32_t)std::min<int64_t>((int64_t)(INF - ws.hcnt[C_AUX2]) + delta, INF);
     int64_t nnear = nf, nfar = 0;
     int steps = 0;
-    int64_t relaxed = 0;
+    int64_t relaxed = 0, edges = 0;
     for (;;) {
         while (nnear > 0) {
             int32_t stv;
@@ -321,11 +343,13 @@ static int sssp_push_nearfar(dg_graph *g, uint64_t *key, int64_t nf, int32_t del
             DG_TRY(counters_clear(g));
             RelaxOp op{key, ws.stamp.p, stv, B, ws.dcnt + C_F1};
             DG_TRY(launch_expand(s, make_args(g, g->fwd, A, nnear), op, 8192));
+            tally_edges(g, g->fwd, A, nnear, nullptr, ws.dcnt + C_EDGES);
             hipLaunchKernelGGL(k_nf_split, dim3(4096), dim3(256), 0, s, ws.dcnt + C_F1, B, key, T, A,
                                ws.dcnt + C_F0, far + nfar, ws.dcnt + C_AUX1, ws.farflag.p, fst);
             DG_HIP(hipGetLastError());
             DG_TRY(counters_read(g));
             relaxed += nnear;
+            edges += ws.hcnt[C_EDGES];
             nnear = ws.hcnt[C_F0];
             nfar += ws.hcnt[C_AUX1];
             ++steps;
@@ -351,6 +375,7 @@ static int sssp_push_nearfar(dg_graph *g, uint64_t *key, int64_t nf, int32_t del
     if (st) {
         st->sssp_steps += steps;
         st->sssp_relaxed += relaxed;
+        st->edges_traversed += edges;
     }
     return DG_OK;
 }
@@ -362,15 +387,17 @@ static int sssp_push(dg_graph *g, uint64_t *key, int64_t nf, dg_batch_stats *st)
     Work &ws = g->ws;
     int32_t *F = ws.f0.p, *N = ws.f1.p;
     int steps = 0;
-    int64_t relaxed = 0;
+    int64_t relaxed = 0, edges = 0;
     while (nf > 0) {
         int32_t stv;
         DG_TRY(next_stamp(g, &stv));
         DG_TRY(counters_clear(g));
         RelaxOp op{key, ws.stamp.p, stv, N, ws.dcnt + C_F1};
         DG_TRY(launch_expand(s, make_args(g, g->fwd, F, nf), op, 8192));
+        tally_edges(g, g->fwd, F, nf, nullptr, ws.dcnt + C_EDGES);
         DG_TRY(counters_read(g));
         relaxed += nf;
+        edges += ws.hcnt[C_EDGES];
         nf = ws.hcnt[C_F1];
         std::swap(F, N);
         ++steps;
@@ -378,6 +405,7 @@ static int sssp_push(dg_graph *g, uint64_t *key, int64_t nf, dg_batch_stats *st)
     if (st) {
         st->sssp_steps += steps;
         st->sssp_relaxed += relaxed;
+        st->edges_traversed += edges;
     }
     return DG_OK;
 }
@@ -518,6 +546,7 @@ enum {
     // count, which far buffer holds the pile, threshold T, smallest pile distance
     // (as INF - d), advance flag of the round, membership stamp of this batch
     R_NB, R_NF, R_NF2, R_FPAR, R_T, R_BEST, R_ADV, R_FST,
+    R_EDGES,  // adjacency entries the steps examined (the traversal tally)
     R_END
 };  // slots of q->qcnt
 constexpr int CUT_LEVELS = 8, PUSH_ROUNDS = 16, NF_ROUNDS = 16;
@@ -541,6 +570,7 @@ __global__ void k_rounds_init(int64_t *ctr) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         ctr[R_LIST] = ctr[0];  // the cut list starts with the pre-hook's seeds
         ctr[R_STEPS] = 0;
+        ctr[R_EDGES] = 0;
     }
 }
 
@@ -789,7 +819,9 @@ static int cut_level(dg_query *q, const int32_t *F, const int64_t *cf, int32_t *
     int64_t *ctr = q->qcnt.p;
     hipLaunchKernelGGL(k_round_prep, dim3(1), dim3(64), 0, g->stream, cn, g->ws.dcnt + C_HEAVY, ctr, nullptr);
     CutListOp op{q->key.p, N, cn, q->inval.p, ctr + R_LIST};
-    return launch_expand(g->stream, dev_args(g, g->fwd, F, cf), op, 1024);
+    DG_TRY(launch_expand(g->stream, dev_args(g, g->fwd, F, cf), op, 1024));
+    tally_edges(g, g->fwd, F, 0, cf, ctr + R_EDGES);
+    return DG_OK;
 }
 
 // Push round: frontier F (count at *cf) -> N (count at *cn).
@@ -798,7 +830,9 @@ static int push_round(dg_query *q, const int32_t *F, const int64_t *cf, int32_t 
     int64_t *ctr = q->qcnt.p;
     hipLaunchKernelGGL(k_round_prep, dim3(1), dim3(64), 0, g->stream, cn, g->ws.dcnt + C_HEAVY, ctr, cf);
     RelaxOpD op{q->key.p, q->gstamp.p, ctr + R_STAMP, N, cn};
-    return launch_expand(g->stream, dev_args(g, g->fwd, F, cf), op, 1024);
+    DG_TRY(launch_expand(g->stream, dev_args(g, g->fwd, F, cf), op, 1024));
+    tally_edges(g, g->fwd, F, 0, cf, ctr + R_EDGES);
+    return DG_OK;
 }
 
 // Cut levels alternate f0 (count R_CA) and f1 (R_CB).  first: level 0 walks the
@@ -835,6 +869,7 @@ static int nf_round(dg_query *q, const int32_t *F, const int64_t *cf, int32_t *N
     hipLaunchKernelGGL(k_nfd_step, dim3(1), dim3(64), 0, s, ctr, delta, cf, cn, ws.dcnt + C_HEAVY);
     RelaxOpD op{q->key.p, q->gstamp.p, ctr + R_STAMP, ws.nfout.p, ctr + R_NB};
     DG_TRY(launch_expand(s, dev_args(g, g->fwd, F, cf), op, 1024));
+    tally_edges(g, g->fwd, F, 0, cf, ctr + R_EDGES);
     hipLaunchKernelGGL(k_nfd_split, dim3(256), dim3(256), 0, s, ws.nfout.p, q->key.p, ctr, N, cn, ws.far0.p,
                        ws.far1.p, q->gfar.p);
     hipLaunchKernelGGL(k_nfd_min, dim3(64), dim3(256), 0, s, ctr, cn, ws.far0.p, ws.far1.p, q->key.p);
@@ -856,6 +891,7 @@ static int rounds_push_enqueue(dg_query *q, bool first) {
         // pull once at every cut vertex
         hipLaunchKernelGGL(k_round_prep, dim3(1), dim3(64), 0, s, nullptr, ws.dcnt + C_HEAVY, ctr, nullptr);
         DG_TRY(launch_expand(s, dev_args(g, *g->rev, q->inval.p, ctr + R_LIST), PullOp{q->key.p}, 1024));
+        tally_edges(g, *g->rev, q->inval.p, 0, ctr + R_LIST, ctr + R_EDGES);
         // seeds: pulled cut vertices and improved heads of inserted arcs
         hipLaunchKernelGGL(k_round_prep, dim3(1), dim3(64), 0, s, ctr + R_PA, ws.dcnt + C_HEAVY, ctr, nullptr);
         hipLaunchKernelGGL(k_sssp_pulled_d, dim3(1024), dim3(256), 0, s, ctr + R_LIST, q->inval.p, q->key.p,
@@ -976,6 +1012,7 @@ static int sssp_post_rounds(dg_query *q, int64_t ains, dg_batch_stats *st) {
     if (st) {
         st->sssp_invalidated += ncut;
         st->sssp_steps += (int32_t)h[R_STEPS];
+        st->edges_traversed += h[R_EDGES];
     }
     return DG_OK;
 }
@@ -1017,27 +1054,29 @@ int sssp_post_update(dg_query *q, int64_t adel, int64_t ains, dg_batch_stats *st
     }
     // 1. cut the subtrees below the seeds; q->inval collects every cut vertex
     int64_t ncut = q->nseeds;
-    int64_t lo = 0, hi = ncut;
+    int64_t lo = 0, hi = ncut, edges = 0;
     while (hi > lo) {
         DG_TRY(counters_clear(g));
         CutOp op{q->key.p, q->inval.p + hi, ws.dcnt + C_F1};
         DG_TRY(launch_expand(s, make_args(g, g->fwd, q->inval.p + lo, hi - lo), op, 8192));
+        tally_edges(g, g->fwd, q->inval.p + lo, hi - lo, nullptr, ws.dcnt + C_EDGES);
         DG_TRY(counters_read(g));
+        edges += ws.hcnt[C_EDGES];
         lo = hi;
         hi += ws.hcnt[C_F1];
     }
     ncut = hi;
     if (st) st->sssp_invalidated += ncut;
     // 2. one pull per cut vertex over its live in-edges
+    DG_TRY(counters_clear(g));
     if (ncut > 0) {
-        DG_TRY(counters_clear(g));
         PullOp op{q->key.p};
         DG_TRY(launch_expand(s, make_args(g, *g->rev, q->inval.p, ncut), op, 8192));
+        tally_edges(g, *g->rev, q->inval.p, ncut, nullptr, ws.dcnt + C_EDGES);
     }
     // 3. inserted arcs relax their heads; 2+3 seed the push frontier
     int32_t stv;
     DG_TRY(next_stamp(g, &stv));
-    DG_TRY(counters_clear(g));
     if (ncut > 0)
         hipLaunchKernelGGL(k_sssp_pulled, dim3(grid_for(ncut)), dim3(256), 0, s, ncut, q->inval.p,
                            q->key.p, ws.stamp.p, stv, ws.f0.p, ws.dcnt + C_F0);
@@ -1046,6 +1085,8 @@ int sssp_post_update(dg_query *q, int64_t adel, int64_t ains, dg_batch_stats *st
                            ws.aiv.p, ws.aiw.p, q->key.p, ws.stamp.p, stv, ws.f0.p, ws.dcnt + C_F0);
     DG_HIP(hipGetLastError());
     DG_TRY(counters_read(g));
+    edges += ws.hcnt[C_EDGES];  // the pull's entries
+    if (st) st->edges_traversed += edges;
     // 4. push to the fixed point
     return sssp_push(g, q->key.p, ws.hcnt[C_F0], st);
 }

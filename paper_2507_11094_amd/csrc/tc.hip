@@ -231,8 +231,9 @@ __global__ __launch_bounds__(1024) void k_tc_sum(const int64_t *part, int64_t nb
     }
 }
 
-int tc_delta(dg_graph *g, const int32_t *eu, const int32_t *ev, int64_t ne, uint64_t *sum6) {
+int tc_delta(dg_graph *g, const int32_t *eu, const int32_t *ev, int64_t ne, uint64_t *sum6, int64_t *entries) {
     *sum6 = 0;
+    if (entries) *entries = 0;
     if (ne <= 0) return DG_OK;
     hipStream_t s = g->stream;
     Dir &F = g->fwd;
@@ -255,6 +256,7 @@ int tc_delta(dg_graph *g, const int32_t *eu, const int32_t *ev, int64_t ne, uint
     DG_HIP(hipGetLastError());
     DG_TRY(counters_read(g));
     *sum6 = (uint64_t)g->ws.hcnt[C_AUX1];
+    if (entries) *entries = g->ws.hcnt[C_AUX2];  // shorter-row entries intersected
     // per changed edge its endpoints' offsets (32 B); per entry of the shorter row
     // and per fence of a long row 4 B; per global search step into the longer row
     // (the whole row, or the segment a fence search selects) 4 B

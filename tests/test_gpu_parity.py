@@ -1151,3 +1151,24 @@ def test_calibration_kernels():
     for kind, size in ((4, buf.numel()), (0, 5000), (3, 32 << 10)):
         with pytest.raises(dg.DGError):
             dg._check(lib.dg_calibrate(kind, ptr, size, None))
+
+
+@pytest.mark.parametrize("persistent", [0, 2])
+def test_traversal_tally(persistent):
+    """edges_traversed counts the entries the update examined: positive for an
+    SSSP-only batch (host-driven steps or captured rounds) and for a triangle
+    batch, and no more than every arc once per step."""
+    n, s, d, w = rmat_small(11, 8, 41)
+    say("traversal tally, sssp schedule", persistent)
+    G = dg.Graph(n, s, d, w, config=cfg(persistent=persistent))
+    G.sssp_attach(0)
+    bs, bd, bw, bo = graphgen.update_batch(n, s, d, 400, 4100)
+    st = G.apply(bs, bd, bw, bo)
+    assert st.sssp_steps > 0
+    assert 0 < st.edges_traversed <= (st.sssp_steps + 20) * (s.size + 400)
+    un, us, ud = graphgen.rmat_undirected(10, 4000, 42)
+    T = dg.Graph(un, us, ud, None, undirected=True)
+    T.tc_attach()
+    bs, bd, bw, bo = graphgen.update_batch(un, us, ud, 300, 4101, undirected=True)
+    st = T.apply(bs, bd, bw, bo)
+    assert st.edges_traversed > 0
