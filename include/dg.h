@@ -120,7 +120,7 @@ typedef struct dg_config {
      * 4096 (0 or anything else: 2048). */
     int32_t pr_tile;
     /* Rows + entries per merge-path tile of the CSR merge: 512, 1024 or 2048
-     * (0 or anything else: 512). */
+     * (0 or anything else: 2048). */
     int32_t merge_tile;
     /* Vertex order inside the library (dg_graph_create only; sets keep the order
      * given): 0 = by degree, highest first, so that the hot rows and the values
@@ -165,8 +165,9 @@ typedef struct dg_batch_stats {
     int32_t sssp_steps;         /* frontier steps                                       */
     int32_t pr_iterations;      /* Jacobi iterations                                    */
     int64_t pr_affected;        /* vertices in the affected set                         */
-    int64_t edges_traversed;    /* adjacency entries examined: PageRank pulls (entries x steps) and the
-                                   worklist SSSP rounds; the frontier SSSP and triangle kernels add 0 */
+    int64_t edges_traversed;    /* adjacency entries examined: PageRank pulls (entries x steps), the
+                                   SSSP rounds (entries of the frontier rows of the cut walk and of
+                                   every pull and push step) and the triangle kernel's intersections */
     int64_t tc_removed;         /* triangles removed by the deletions                   */
     int64_t tc_added;           /* triangles added by the insertions                    */
     float t_validate_ms, t_update_ms, t_merge_ms, t_sssp_ms, t_pr_ms, t_tc_ms, t_total_ms;

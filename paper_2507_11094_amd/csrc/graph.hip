@@ -352,16 +352,17 @@ __global__ void k_deg_to_i64(int32_t n, const int32_t *deg, int64_t *out) {
 // Merge of one direction on merge-path tiles: the row ends and the base entries
 // form one sequence of n + m items and each workgroup takes MG_ITEMS of them, so
 // every workgroup moves the same amount whatever the row lengths.  A tile stages
-// its rows' data in LDS (start, output start off2, tombstones before the row RB,
-// diff count), reads its entries once (coalesced), and writes each live entry to
-//   off2[r] + (live base entries of row r before it) + (diff entries of r below it)
-// where the live count is (position in row) - (tombstones between row start and
-// entry): global tombstones before the entry come from the per-block counters
-// (ttomb, TILE entries each, kept by the delete step) plus a ballot count inside
-// the tile.  Diff entries are written at their insertion points by the base
-// entries of their row (rows with an empty base part: k_merge_diff_empty).
+// its rows' starts and diff ranges in LDS, reads its entries once (coalesced), and
+// writes each live entry to
+//   (entry index) - (tombstones before it) + doff[r] + (diff entries of r below it)
+// which is its place in the merged level because the diff level holds live
+// entries only when the merge runs.  Tombstones before the entry come from the
+// per-block counters (ttomb, TILE entries each, kept by the delete step) plus a
+// ballot count inside the tile.  Diff entries are written at their insertion
+// points by the base entries of their row (rows with an empty base part:
+// k_merge_diff_empty).
 constexpr int MG_THREADS = 256;
-constexpr int MG_ITEMS = 512;  // default items per tile (cfg.merge_tile picks 512 / 1024 / 2048)
+constexpr int MG_ITEMS = 2048;  // default items per tile (cfg.merge_tile picks 512 / 1024 / 2048)
 constexpr int MG_WAVES = MG_THREADS / WAVE;
 
 // Tile b starts at (mp_row[b], mp_edge[b]); mp_dlo[b] = doff[row] and mp_dhi[b] =
@@ -405,93 +406,128 @@ __device__ __forceinline__ int lds_lower(const int32_t *a, int lo, int hi, uint3
     return lo;
 }
 
-// ITEMS rows + entries per tile; up to ITEMS diff entries of its rows are staged in
-// LDS (more are read from memory).
+// ITEMS rows + entries per tile; up to ITEMS / 4 diff column ids of its rows are
+// staged in LDS (more are read from memory).  Output positions need no per-row output
+// offsets: after the update the diff level holds live entries only, so
+//   off2[r] = (base entries before row r) - (tombstones before row r) + doff[r],
+// and a live base entry i of row r lands at
+//   i - (tombstones before i) + doff[r] + (diff entries of row r below it),
+// the tombstones before i coming from the per-block counters (TB) and a ballot
+// count inside the tile.  A tile keeps about 10 bytes of LDS per item (row
+// starts, diff ranges and a quarter item of diff entries); the entries stay in
+// registers and the column before an entry comes from the neighbouring lane (or
+// the wave before).  No global load follows the tile's first barrier except for
+// tiles whose diff entries exceed the staging: on this GPU a wave's load counter
+// also counts its stores, so a load after the first stores would wait for them.
 template <int ITEMS>
-__global__ __launch_bounds__(MG_THREADS) void k_merge_tiles(
+__global__ __launch_bounds__(MG_THREADS, 8) void k_merge_tiles(
     int32_t n, const int32_t *__restrict__ mp_row, const int64_t *__restrict__ mp_edge,
     const int64_t *__restrict__ mp_dlo, const int64_t *__restrict__ mp_dhi,
     const int64_t *__restrict__ off, const int32_t *__restrict__ col, const int32_t *__restrict__ w,
     const int64_t *__restrict__ doff, const int32_t *__restrict__ dcol, const int32_t *__restrict__ dw,
-    const int64_t *__restrict__ off2, const int64_t *__restrict__ RB, const int64_t *__restrict__ TB,
-    int32_t *__restrict__ col2, int32_t *__restrict__ w2, int64_t cap, int64_t *cnt) {
+    const int64_t *__restrict__ TB, int32_t *__restrict__ col2, int32_t *__restrict__ w2, int64_t cap, int64_t *cnt) {
     constexpr int IPT = ITEMS / MG_THREADS;
+    constexpr int DC = ITEMS / 4 < 256 ? ITEMS / 4 : 256;
     __shared__ int32_t s_off[ITEMS + 1];  // row start - e0 (row 0: -1 when it began earlier)
-    __shared__ int32_t s_o2[ITEMS + 1];   // off2[r] - off2[r0]
-    __shared__ int32_t s_rb[ITEMS + 1];   // RB[r] - RB[r0]
     __shared__ int32_t s_dlo[ITEMS + 2];  // doff[r] - doff[r0]
-    __shared__ int32_t s_col[ITEMS];      // the tile's entries
-    __shared__ int32_t s_dc[ITEMS], s_dw[ITEMS];
-    __shared__ int32_t s_wd[IPT][MG_WAVES];
-    __shared__ int64_t s_base[5];            // off[r0], off2[r0], RB[r0], tombstones before e0, doff[r0]
+    __shared__ int32_t s_dc[DC], s_dw[DC];  // the tile's diff entries
+    __shared__ int32_t s_wd[IPT][MG_WAVES];  // tombstones per wave and item round
+    __shared__ uint32_t s_last[IPT][MG_WAVES + 1];  // column of each wave's last entry; [0][0]: entry e0 - 1
+    __shared__ int64_t s_base[3];          // off[r0], tombstones before e0, off[r1 + 1]
     const int64_t b = blockIdx.x;
     const int32_t r0 = mp_row[b], r1 = mp_row[b + 1];
     const int64_t e0 = mp_edge[b];
     const int32_t ne = (int32_t)(mp_edge[b + 1] - e0);
     const int32_t nr = r1 - r0;
+    const int64_t dbase = mp_dlo[b];           // the diff entries of the tile's rows
+    const int64_t ndt = mp_dhi[b + 1] - dbase; // (one contiguous range of the diff level)
+    const bool dlds = ndt <= DC;
+    const int64_t st = (e0 / TILE) * TILE;     // counter block of e0
+    const int64_t tb0 = TB[e0 / TILE];
     const int t = threadIdx.x, wv = t / WAVE, l = lane_id();
-    // entries (coalesced) and their tombstone ballots
+    // Every load of the tile is issued before the first one is used, so the tile
+    // waits for one memory round trip after its partition entry, not one per item.
     uint32_t c[IPT];
     int32_t wt[IPT];
-    int32_t lp[IPT];
 #pragma unroll
     for (int u = 0; u < IPT; ++u) {
         const int j = u * MG_THREADS + t;
-        const bool valid = j < ne;
-        c[u] = valid ? (uint32_t)col[e0 + j] : 0u;
-        wt[u] = valid ? w[e0 + j] : 0;
-        if (valid) s_col[j] = (int32_t)c[u];
-        const uint64_t bm = ballot(valid && (c[u] & DEAD));
-        lp[u] = __popcll(bm & lanemask_lt());
+        c[u] = j < ne ? (uint32_t)col[e0 + j] : 0u;
+        wt[u] = j < ne ? w[e0 + j] : 0;
+    }
+    // row r0 + t (slot nr + 1: the end of the row still open at the tile's end)
+    const bool has_row = t <= nr + 1 && r0 + t <= n;
+    const int64_t ro_t = *(has_row ? off + r0 + t : mp_edge + b);
+    const int64_t rd_t = *(has_row ? doff + r0 + t : mp_edge + b);
+    // (lanes with nothing to load read the tile's own partition entry instead, so
+    // that no load sits behind a branch that would make the wave wait on it)
+    const bool has_dc = dlds && t < ndt;
+    const int32_t dc_raw = *(has_dc ? dcol + dbase + t : mp_row + b);
+    const int32_t dw_raw = *(has_dc ? dw + dbase + t : mp_row + b);
+    const int32_t prev_raw = *(t == 0 && e0 > 0 ? col + e0 - 1 : mp_row + b);
+    // wave 0: the entries of e0's counter block before e0
+    uint32_t tbc[TILE / WAVE];
+#pragma unroll
+    for (int q = 0; q < TILE / WAVE; ++q) {
+        const int64_t idx = st + q * WAVE + l;
+        tbc[q] = (uint32_t) * (wv == 0 && idx < e0 ? col + idx : mp_row + b);
+    }
+#pragma unroll
+    for (int u = 0; u < IPT; ++u) {
+        const uint64_t bm = ballot((c[u] & DEAD) != 0u);
         if (l == 0) s_wd[u][wv] = __popcll(bm);
+        if (l == WAVE - 1) s_last[u][wv + 1] = c[u];
     }
-    // rows r0 .. r1 (r1: the row still open at the tile's end, if any)
-    const int64_t dbase = mp_dlo[b];
-    for (int i = t; i <= nr + 1; i += MG_THREADS) {
-        const int32_t r = r0 + i;
-        if (r <= n) s_dlo[i] = (int32_t)(doff[r] - dbase);
-        if (i > nr) continue;
-        const int64_t o = off[r] - e0;
-        s_off[i] = (int32_t)(o < 0 ? -1 : o);
-        s_o2[i] = (int32_t)(off2[r] - off2[r0]);
-        s_rb[i] = (int32_t)(RB[r] - RB[r0]);
-    }
-    // the diff entries of the tile's rows (one contiguous range of the diff level)
-    const int64_t ndt = mp_dhi[b + 1] - dbase;
-    const bool dlds = ndt <= ITEMS;
-    if (dlds)
-        for (int q = t; q < ndt; q += MG_THREADS) {
+    if (t == 0) s_last[0][0] = (uint32_t)prev_raw;
+    auto put_row = [&](int i, int64_t ro, int64_t rd) {
+        if (r0 + i > n) return;
+        s_dlo[i] = (int32_t)(rd - dbase);
+        if (i <= nr) {
+            const int64_t o = ro - e0;
+            s_off[i] = (int32_t)(o < 0 ? -1 : o);
+        } else {
+            s_base[2] = ro;
+        }
+    };
+    if (has_row) put_row(t, ro_t, rd_t);
+    for (int i = t + MG_THREADS; i <= nr + 1; i += MG_THREADS)  // tiles of many short rows
+        if (r0 + i <= n) put_row(i, off[r0 + i], doff[r0 + i]);
+    if (dlds) {
+        if (has_dc) {
+            s_dc[t] = dc_raw;
+            s_dw[t] = dw_raw;
+        }
+        for (int q = t + MG_THREADS; q < ndt; q += MG_THREADS) {
             s_dc[q] = dcol[dbase + q];
             s_dw[q] = dw[dbase + q];
         }
+    }
     if (wv == 0) {
         // tombstones before e0: counter blocks before its block + a ballot count inside it
-        const int64_t st = (e0 / TILE) * TILE;
         int cd = 0;
 #pragma unroll
-        for (int q = 0; q < TILE / WAVE; ++q) {
-            const int64_t idx = st + q * WAVE + l;
-            cd += __popcll(ballot(idx < e0 && ((uint32_t)col[idx] & DEAD)));
-        }
+        for (int q = 0; q < TILE / WAVE; ++q)
+            cd += __popcll(ballot(st + q * WAVE + l < e0 && (tbc[q] & DEAD) != 0u));
         if (l == 0) {
-            s_base[0] = off[r0];
-            s_base[1] = off2[r0];
-            s_base[2] = RB[r0];
-            s_base[3] = TB[e0 / TILE] + cd;
-            s_base[4] = dbase;
+            s_base[0] = ro_t;  // off[r0]
+            s_base[1] = tb0 + cd;
         }
     }
     __syncthreads();
-    int64_t pre = s_base[3];
+    int64_t pre = s_base[1];
 #pragma unroll
     for (int u = 0; u < IPT; ++u) {
         int64_t pu = pre;
         for (int q = 0; q < wv; ++q) pu += s_wd[u][q];
         for (int q = 0; q < MG_WAVES; ++q) pre += s_wd[u][q];
         const int j = u * MG_THREADS + t;
+        // column of entry j - 1 (lane 0: the last entry of the wave before) and the
+        // tombstones before it in its wave (taken while every lane is active)
+        const uint32_t pc = (uint32_t)__shfl_up((int32_t)c[u], 1, WAVE);
+        const int lp = __popcll(ballot((c[u] & DEAD) != 0u) & lanemask_lt());
         if (j >= ne) continue;
         const int64_t i = e0 + j;
-        const int64_t deadG = pu + lp[u];  // tombstones before entry i
+        const int64_t deadG = pu + lp;  // tombstones before entry i
         // row of the entry: last row of the tile that starts at or before j
         int lo = 0, hi = nr;
         while (lo < hi) {
@@ -500,14 +536,14 @@ __global__ __launch_bounds__(MG_THREADS) void k_merge_tiles(
             else hi = mid - 1;
         }
         const int64_t ro = lo == 0 ? s_base[0] : e0 + s_off[lo];
-        const int64_t rank = (i - ro) - (deadG - (s_base[2] + s_rb[lo]));
-        const int64_t ob = s_base[1] + s_o2[lo];
         const uint32_t cu = c[u];
         const uint32_t cur = cu & ID_MASK;
         const bool dead = cu & DEAD;
         const int dl = s_dlo[lo], dh = s_dlo[lo + 1];  // this row's diff entries (tile-relative)
+        // where the entry would land with none of its row's diff entries before it
+        const int64_t base0 = i - deadG + dbase + dl;
         if (dl == dh) {
-            if (!dead) merge_put(col2, w2, cap, ob + rank, (int32_t)cu, wt[u], cnt);
+            if (!dead) merge_put(col2, w2, cap, base0, (int32_t)cu, wt[u], cnt);
             continue;
         }
         // rows with diff entries: interleave them at their insertion points
@@ -518,14 +554,17 @@ __global__ __launch_bounds__(MG_THREADS) void k_merge_tiles(
             merge_put(col2, w2, cap, o, dlds ? s_dc[q] : dcol[dbase + q], dlds ? s_dw[q] : dw[dbase + q], cnt);
         };
         const int bq = lower(cur);
-        if (!dead) merge_put(col2, w2, cap, ob + rank + (bq - dl), (int32_t)cu, wt[u], cnt);
+        if (!dead) merge_put(col2, w2, cap, base0 + (bq - dl), (int32_t)cu, wt[u], cnt);
         int a = dl;
-        if (i > ro) a = lower(((uint32_t)(j > 0 ? s_col[j - 1] : col[i - 1]) & ID_MASK) + 1);
-        for (int q = a; q < bq; ++q) put_diff(q, ob + rank + (q - dl));
-        const int64_t rend = lo < nr ? e0 + s_off[lo + 1] : off[r0 + lo + 1];
+        if (i > ro) {
+            const uint32_t p = l > 0 ? pc : (wv > 0 ? s_last[u][wv] : (u > 0 ? s_last[u - 1][MG_WAVES] : s_last[0][0]));
+            a = lower((p & ID_MASK) + 1);
+        }
+        for (int q = a; q < bq; ++q) put_diff(q, base0 + (q - dl));
+        const int64_t rend = lo < nr ? e0 + s_off[lo + 1] : s_base[2];
         if (i == rend - 1) {  // after the row's last base entry: the diff tail
-            const int64_t after = rank + (dead ? 0 : 1);
-            for (int q = lower(cur + 1); q < dh; ++q) put_diff(q, ob + after + (q - dl));
+            const int64_t after = dead ? 0 : 1;
+            for (int q = lower(cur + 1); q < dh; ++q) put_diff(q, base0 + after + (q - dl));
         }
     }
 }
@@ -556,22 +595,20 @@ static int merge_into(dg_graph *g, Dir &d, int64_t *off2, int32_t *col2, int32_t
     SortWork &sw = side ? ws.sw_m : ws.sw;
     const int32_t n = g->n;
     const int64_t nblk = ntiles_for(d.m);
-    DG_TRY(ws.scan64.ensure(2 * ((size_t)n + 1) + 2 * (nblk + 2)));
+    DG_TRY(ws.scan64.ensure((size_t)n + 1 + 2 * (nblk + 2)));
     int64_t *tmpa = ws.scan64.p;
-    int64_t *RB = tmpa + (n + 1);
-    int64_t *tsin = RB + (n + 1);
+    int64_t *tsin = tmpa + (n + 1);
     int64_t *TB = tsin + (nblk + 2);
     // off2 = exclusive scan of live degrees
     hipLaunchKernelGGL(k_deg_to_i64, dim3(grid_for(n + 1)), dim3(256), 0, s, n, d.deg.p, tmpa);
     DG_TRY(scan_excl_on(s, sw, cnt + C_SORT_ERR, tmpa, off2, n + 1));
-    // RB = tombstones before each row, TB = tombstones before each counter block
-    hipLaunchKernelGGL(k_deg_to_i64, dim3(grid_for(n + 1)), dim3(256), 0, s, n, d.ntomb.p, tmpa);
-    DG_TRY(scan_excl_on(s, sw, cnt + C_SORT_ERR, tmpa, RB, n + 1));
+    // TB = tombstones before each counter block
     hipLaunchKernelGGL(k_deg_to_i64, dim3(grid_for(nblk + 2)), dim3(256), 0, s, (int32_t)(nblk + 1), d.ttomb.p,
                        tsin);
     DG_TRY(scan_excl_on(s, sw, cnt + C_SORT_ERR, tsin, TB, nblk + 2));
     // merge-path tiles
-    const int items = g->cfg.merge_tile == 512 || g->cfg.merge_tile == 2048 ? g->cfg.merge_tile : MG_ITEMS;
+    const int mt = g->cfg.merge_tile;
+    const int items = mt == 512 || mt == 1024 || mt == 2048 ? mt : MG_ITEMS;
     const int64_t nb = ((int64_t)n + d.m + items - 1) / items;
     DG_TRY(ws.mp_row.ensure((size_t)nb + 1));
     DG_TRY(ws.mp_edge.ensure((size_t)nb + 1));
@@ -582,14 +619,14 @@ static int merge_into(dg_graph *g, Dir &d, int64_t *off2, int32_t *col2, int32_t
     DG_HIP(hipGetLastError());
     DG_TRY(fill_i64(cnt, 0, C_SORT_ERR, s));
     // merge bytes: col+w read 8 per old entry, write 8 per new entry, and per row
-    // off, doff, off2 and the tombstone prefix (8 each)
+    // off and doff (8 each)
     int pm = prof_begin("merge_base", s);
     auto tiles_kernel = items == 512 ? k_merge_tiles<512> : (items == 2048 ? k_merge_tiles<2048> : k_merge_tiles<1024>);
     if (nb > 0)
         hipLaunchKernelGGL(tiles_kernel, dim3((unsigned)nb), dim3(MG_THREADS), 0, s, n, ws.mp_row.p,
-                           ws.mp_edge.p, mp_dlo, mp_dhi, d.off.p, d.col.p, d.w.p, d.doff.p, d.dcol.p, d.dw.p, off2, RB, TB, col2, w2,
+                           ws.mp_edge.p, mp_dlo, mp_dhi, d.off.p, d.col.p, d.w.p, d.doff.p, d.dcol.p, d.dw.p, TB, col2, w2,
                            m2, cnt);
-    prof_end(pm, s, 8.0 * (double)d.m + 8.0 * (double)m2 + 32.0 * (double)n + 8.0 * (double)d.dm);
+    prof_end(pm, s, 8.0 * (double)d.m + 8.0 * (double)m2 + 16.0 * (double)n + 8.0 * (double)d.dm);
     if (d.dm > 0)
         hipLaunchKernelGGL(k_merge_diff_empty, dim3(grid_for(d.dm)), dim3(256), 0, s, d.dm, d.dkey.p,
                            d.keybits, d.off.p, d.doff.p, d.dcol.p, d.dw.p, off2, col2, w2, m2, cnt);
