@@ -136,16 +136,21 @@ typedef struct dg_config {
     /* Jacobi PageRank steps: 0 = plain steps, as in the Appendix A listings
      * (default); 1 = extrapolated steps: when two successive step vectors are
      * parallel (a least-squares fit s_k = lam s_{k-1} leaves at most 5 % of s_k
-     * unexplained, 0 < lam <= 0.9), the
-     * error is dominated by one eigenvector and the next step also moves
-     * lam / (1 - lam) times its own length further, which removes that component
-     * (Aitken's process along the step).  Convergence is still declared only on a
-     * plain step, so the stopping rule bounds the error as in plain Jacobi; the
-     * ranks differ from the plain iterates within that bound (they are usually
-     * closer to the fixed point).  The fits keep the previous step in n floats
-     * (4 bytes read and written per vertex and step) and stop after 24 plain steps
-     * without a move, so graphs whose error never lines up (grids) pay for at
-     * most 24 steps. */
+     * unexplained, 0 < lam <= 0.9), the error is dominated by one eigenvector and
+     * the next step also moves lam / (1 - lam) times its own length further, which
+     * removes that component (Aitken's process along the step).  Bipartite graphs
+     * such as grids carry their error in pairs of modes near +d and -d, whose
+     * successive steps never line up; there a fit of s_k against s_{k-2}
+     * (mu = lam^2, at most 15 % unexplained, 0 < mu <= 0.81) moves the two-step
+     * map instead, along the sum of the last two steps.  Convergence is still
+     * declared only on a plain step, so the stopping rule bounds the error as in
+     * plain Jacobi; the ranks differ from the plain iterates within that bound
+     * (they are usually closer to the fixed point).  The fits keep the previous
+     * step in n floats (4 bytes read and written per vertex and step), and the one
+     * before it in n more floats only once four plain steps without a move have
+     * passed and the one-step fit explains at most 5 % of |s_k|^2 (orthogonal
+     * successive steps, as on grids).  They stop after 24 plain steps without a
+     * move or once the step is too small for any move. */
     int32_t pr_extrapolate;
 } dg_config;
 

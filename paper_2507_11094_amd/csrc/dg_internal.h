@@ -158,6 +158,7 @@ struct Work {
     DBuf<double> part;                    // partial sums of split rows
     DBuf<double> prs;                     // PageRank scalars: step, dangling mass, constant term
     DBuf<float> prstep;                   // previous PageRank step vector (extrapolated steps' fits)
+    DBuf<float> prstep2;                  // the step vector before it (two-step fits)
     DBuf<int32_t> mp_row;                 // merge-path tile starts (row, entry) of the whole-graph pull
     DBuf<int64_t> mp_edge;
     DBuf<double> mp_part;                 // per-tile partial sums of rows split across tiles

@@ -120,6 +120,7 @@ void ws_free(dg_graph *g) {
     w.mp_row.release(); w.mp_edge.release(); w.mp_part.release(); w.mp_doff.release(); w.tcitems.release();
     w.farflag.release(); w.far0.release(); w.far1.release(); w.nfout.release(); w.bpart.release();
     w.prstep.release();
+    w.prstep2.release();
     w.rbuf.release(); w.skey.release(); w.sx.release(); w.sc.release(); w.sxn.release();
     w.vslot.release(); w.vpos.release(); w.vkey.release(); w.vw.release();
     w.wq.release(); w.wseq.release(); w.wctr.release(); w.inq.release();

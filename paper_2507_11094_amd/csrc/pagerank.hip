@@ -201,23 +201,24 @@ __device__ __forceinline__ void block_sum2(double a, double b, double *out_a, do
     }
 }
 
-// Fixed-order block sums of two more values (after block_sum2 in the same kernel).
-__device__ __forceinline__ void block_sum2b(double a, double b, double *out_a, double *out_b) {
-    __shared__ double ra[256], rb[256];
+// Fixed-order block sums of K more values (after block_sum2 in the same kernel).
+template <int K>
+__device__ __forceinline__ void block_sum_more(const double (&v)[K], double *out) {
+    __shared__ double r[K][256];
     __syncthreads();
-    ra[threadIdx.x] = a;
-    rb[threadIdx.x] = b;
+#pragma unroll
+    for (int k = 0; k < K; ++k) r[k][threadIdx.x] = v[k];
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {
         if ((int)threadIdx.x < s) {
-            ra[threadIdx.x] += ra[threadIdx.x + s];
-            rb[threadIdx.x] += rb[threadIdx.x + s];
+#pragma unroll
+            for (int k = 0; k < K; ++k) r[k][threadIdx.x] += r[k][threadIdx.x + s];
         }
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        *out_a = ra[0];
-        *out_b = rb[0];
+#pragma unroll
+        for (int k = 0; k < K; ++k) out[k] = r[k][0];
     }
 }
 
@@ -229,45 +230,66 @@ __device__ __forceinline__ void block_sum2b(double a, double b, double *out_a, d
 // prs[8] = the extrapolation factor the next apply uses (0: plain step),
 // prs[9] = plain steps since the last move, prs[10] = moves taken, prs[11] = 1
 // while the applies keep the step vector for the fits (stops after EX_TRACK plain
-// steps without a move: error spread over many modes, as on grids, never lines
-// up, and the extra vector traffic would be paid on every step).
+// steps without a move: error spread over many modes of different ratios never
+// lines up, and the extra vector traffic would be paid on every step),
+// prs[12] = |step before the previous|^2 (0: none comparable), prs[13] = the
+// conserved mass (S < 0), prs[14] = 1 when the move of the next apply is a
+// two-step move, prs[15] = 1 once the applies also keep the step before the
+// previous one (after EX_LAG2_AFTER plain steps without a move, on a step whose
+// one-step fit left at least EX_LAG2_RES of |s_k|^2 unexplained: on a grid the
+// successive steps are orthogonal, while on R-MAT graphs the fit explains more
+// than 20 % by the fourth step and the older vector is never kept).
 // first = 1: the set-up call before the first step (resets the flags and counts).
 //
-// Extrapolation (extrap = 1, partials2 holds the block sums of |step|^2 and
-// <step, previous step>): the step vectors of a linear fixed-point iteration
-// shrink like e_{k+1} = M e_k.  When the error is dominated by one eigenvector of
-// M with eigenvalue lam, successive steps are parallel, s_k = lam s_{k-1}, and
-// x + lam / (1 - lam) (x' - x) removes that component (Aitken's delta-squared
-// process along the step).  lam is fitted by least squares, lam = <s_k, s_{k-1}> /
-// |s_{k-1}|^2, and the move is taken only when the fit leaves at most EX_FIT of
-// |s_k| unexplained and 0 < lam <= EX_MAX_LAM: modes of the opposite sign
-// (bipartite graphs such as grids have eigenvalues near -d) or several modes of
-// similar size leave the steps unaligned, and no move happens.  (Asking for two
-// successive aligned fits with ratios within 5 % as well delayed the move by one
-// step and changed nothing else in the CPU models.)  The next apply takes the move; a step that moved
-// is never taken as converged, and the fits restart after it.  Convergence is only
-// declared on a plain step, whose L1 size bounds the error exactly as in plain
-// Jacobi, and the move keeps sum(x) (an affine combination of two vectors of equal
-// sum).
+// Extrapolation (extrap = 1, partials2 holds the block sums of |step|^2,
+// <step, previous step> and <step, step before the previous>): the step vectors of
+// a linear fixed-point iteration shrink like e_{k+1} = M e_k.  When the error is
+// dominated by one eigenvector of M with eigenvalue lam, successive steps are
+// parallel, s_k = lam s_{k-1}, and x + lam / (1 - lam) (x' - x) removes that
+// component (Aitken's delta-squared process along the step).  lam is fitted by
+// least squares, lam = <s_k, s_{k-1}> / |s_{k-1}|^2, and the move is taken only
+// when the fit leaves at most EX_FIT of |s_k| unexplained and
+// 0 < lam <= EX_MAX_LAM.  (Asking for two successive aligned fits with ratios
+// within 5 % as well delayed the move by one step and changed nothing else in the
+// CPU models.)
+// Bipartite graphs such as grids have their eigenvalues in pairs +-lam, so the
+// error of a batch sits in modes near +d and -d at once and successive steps never
+// line up.  Over two steps both modes of a pair shrink by mu = lam^2, so the fit
+// of s_k against s_{k-2} (mu = <s_k, s_{k-2}> / |s_{k-2}|^2, at most EX_FIT2
+// unexplained, 0 < mu <= EX_MAX_LAM^2) finds them, and the two-step map's Aitken
+// move x + mu / (1 - mu) (x'' - x) goes along the sum of the last two steps.  This
+// fit is only tried when the one-step fit is not taken.
+// The next apply takes the move; a step that moved is never taken as converged,
+// and the fits restart after it.  Convergence is only declared on a plain step,
+// whose L1 size bounds the error exactly as in plain Jacobi, and a one-step move
+// keeps sum(x) (an affine combination of two vectors of equal sum; the two-step
+// move adds the previous step in FP32, a change of sum far below the tolerance).
 constexpr double EX_FIT = 0.05;     // unexplained fraction of |s_k| (L2) at most
+constexpr double EX_FIT2 = 0.15;    // the same for the fit against s_{k-2}
 constexpr double EX_MAX_LAM = 0.9;  // no move for slower ratios (factor <= 9)
 constexpr int EX_TRACK = 24;        // plain steps without a move before the fits stop
+constexpr int EX_LAG2_AFTER = 4;    // plain steps without a move before s_{k-2} is kept,
+constexpr double EX_LAG2_RES = 0.95;  // and the one-step fit explaining at most 5 % of |s_k|^2
 __device__ __forceinline__ void pr_reduce_body(const double *partials, const double *partials2, int np, int global,
                                                double S, double damp, double ninv, double tol, int first, int extrap,
                                                double *prs, double *step_out) {
-    double a = 0.0, b = 0.0, sq = 0.0, dot = 0.0;
+    double a = 0.0, b = 0.0, sq = 0.0, dot = 0.0, dot2 = 0.0;
     const bool fit = extrap && !first && prs[11] != 0.0;  // the apply just run kept the step vector
     for (int i = threadIdx.x; i < np; i += blockDim.x) {
         a += partials[2 * i];
         b += partials[2 * i + 1];
         if (fit) {
-            sq += partials2[2 * i];
-            dot += partials2[2 * i + 1];
+            sq += partials2[3 * i];
+            dot += partials2[3 * i + 1];
+            dot2 += partials2[3 * i + 2];
         }
     }
-    __shared__ double fs[2];
+    __shared__ double fs[3];
     block_sum2(a, b, &prs[0], &prs[1]);
-    if (fit) block_sum2b(sq, dot, &fs[0], &fs[1]);
+    if (fit) {
+        const double v[3] = {sq, dot, dot2};
+        block_sum_more<3>(v, fs);
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
         // S < 0: the conserved mass is prs[13], set by the set-up call (first) to the
@@ -284,17 +306,22 @@ __device__ __forceinline__ void pr_reduce_body(const double *partials, const dou
             prs[4] = 0.0;
             for (int k = 6; k <= 10; ++k) prs[k] = 0.0;
             prs[11] = extrap ? 1.0 : 0.0;
+            prs[12] = 0.0;
+            prs[14] = 0.0;
+            prs[15] = 0.0;
             return;
         }
         prs[4] += 1.0;
         const double step = prs[0];
         const bool moved = prs[8] != 0.0;
         prs[8] = 0.0;
+        prs[14] = 0.0;
         if (moved) {
             // the step just taken moved further than Jacobi: the fits start again
             prs[6] = 0.0;
             prs[7] = 0.0;
             prs[9] = 0.0;
+            prs[12] = 0.0;
             prs[11] = extrap ? 1.0 : 0.0;
             return;
         }
@@ -304,16 +331,29 @@ __device__ __forceinline__ void pr_reduce_body(const double *partials, const dou
         }
         if (!fit) return;
         prs[9] += 1.0;
-        if (prs[9] >= (double)EX_TRACK) prs[11] = 0.0;
-        const double s2 = fs[0], sd = fs[1], p2 = prs[6];
+        const bool lag2 = prs[15] != 0.0;  // the apply just run kept s_{k-2} as well
+        const double s2 = fs[0], sd = fs[1], sd2 = fs[2], p2 = prs[6], q2 = prs[12];
         const double lam = p2 > 0.0 ? sd / p2 : 0.0;
         const bool aligned = p2 > 0.0 && s2 - sd * lam <= EX_FIT * EX_FIT * s2;
+        const double mu = q2 > 0.0 ? sd2 / q2 : 0.0;
+        const bool aligned2 = q2 > 0.0 && s2 - sd2 * mu <= EX_FIT2 * EX_FIT2 * s2;
         if (aligned && lam > 0.0 && lam <= EX_MAX_LAM && prs[9] >= 2.0 && lam * step > 2.0 * tol) {
             prs[8] = lam / (1.0 - lam);
             prs[10] += 1.0;
+        } else if (aligned2 && mu > 0.0 && mu <= EX_MAX_LAM * EX_MAX_LAM && mu * step > 2.0 * tol) {
+            prs[8] = mu / (1.0 - mu);
+            prs[14] = 1.0;
+            prs[10] += 1.0;
         }
         prs[7] = aligned ? lam : 0.0;
+        prs[12] = lag2 ? p2 : 0.0;  // the apply just run stored s_{k-1} as the older vector
         prs[6] = s2;
+        if (prs[9] >= (double)EX_LAG2_AFTER && p2 > 0.0 && s2 - sd * lam >= EX_LAG2_RES * s2) prs[15] = 1.0;
+        // a two-step move needs the step vector in the next apply: tracking stops
+        // only on a step that decided no move, after EX_TRACK plain steps or once
+        // the step is too small for any move (the move tests above fail for it)
+        if (prs[8] == 0.0 && (prs[9] >= (double)EX_TRACK || EX_MAX_LAM * EX_MAX_LAM * step <= 2.0 * tol))
+            prs[11] = 0.0;
     }
 }
 
@@ -333,17 +373,20 @@ __global__ void k_pr_reduce(const double *partials, const double *partials2, int
 __global__ __launch_bounds__(256) void k_pr_apply(const int32_t *A, int64_t na, double *xn,
                                                   const double *x_o, double *x_w, double *contrib,
                                                   const int32_t *deg, double *partials, double *partials2,
-                                                  float *dprev, const double *prs) {
+                                                  float *dprev, float *dprev2, const double *prs) {
     if (prs[3] != 0.0) return;
-    const double *fx = prs + 8;
-    // dprev (extrapolation on) while fx[3] != 0: the previous step's vector is read
-    // and this step's written (FP32: it only feeds the fit), and partials2 gets the
-    // block sums of |step|^2 and <step, previous step>.  f = fx[0] != 0: the new
-    // vector also moves f times this step further (decided by k_pr_reduce); the L1
-    // step summed is the plain one.
-    const double f = fx[0];
-    if (dprev && fx[3] == 0.0) dprev = nullptr;
-    double acc = 0.0, dang = 0.0, sq = 0.0, dot = 0.0;
+    // dprev (extrapolation on) while prs[11] != 0: the previous step's vector is read
+    // and this step's written (FP32: it only feeds the fits), and partials2 gets the
+    // block sums of |step|^2, <step, previous step> and <step, step before it>.
+    // dprev2 while prs[15] != 0 as well: the step before the previous one is read and
+    // the previous one moves into its place.  f = prs[8] != 0: the new vector also
+    // moves f times this step further, or f times the sum of this step and the
+    // previous one (prs[14] != 0, a two-step move); the L1 step summed is the plain one.
+    const double f = prs[8];
+    const bool two = prs[14] != 0.0;
+    if (dprev && prs[11] == 0.0) dprev = nullptr;
+    if (!dprev || prs[15] == 0.0) dprev2 = nullptr;
+    double acc = 0.0, dang = 0.0, sq = 0.0, dot = 0.0, dot2 = 0.0;
     // four strided elements per pass, every load issued before the stores (x_w may be
     // x_o, so the compiler could not reorder them itself); the sums keep the order
     // of a plain strided loop
@@ -351,7 +394,7 @@ __global__ __launch_bounds__(256) void k_pr_apply(const int32_t *A, int64_t na, 
     const int64_t st = gstride();
     for (int64_t i0 = gtid(); i0 < na; i0 += U * st) {
         int32_t v[U], dg[U];
-        double nv[U], ov[U], pv[U];
+        double nv[U], ov[U], pv[U], pv2[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t i = i0 + u * st;
@@ -364,6 +407,7 @@ __global__ __launch_bounds__(256) void k_pr_apply(const int32_t *A, int64_t na, 
             ov[u] = x_o[v[u]];
             dg[u] = deg[v[u]];
             pv[u] = dprev ? (double)dprev[v[u]] : 0.0;
+            pv2[u] = dprev2 ? (double)dprev2[v[u]] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -373,11 +417,15 @@ __global__ __launch_bounds__(256) void k_pr_apply(const int32_t *A, int64_t na, 
             if (dprev) {
                 sq += dl * dl;
                 dot += dl * pv[u];
+                if (dprev2) {
+                    dot2 += dl * pv2[u];
+                    dprev2[v[u]] = (float)pv[u];
+                }
                 dprev[v[u]] = (float)dl;
             }
             double y = nv[u];
             if (f != 0.0) {
-                y = nv[u] + f * dl;
+                y = nv[u] + f * (two ? dl + pv[u] : dl);
                 if (!x_w) xn[v[u]] = y;
             }
             if (x_w) x_w[v[u]] = y;
@@ -386,7 +434,14 @@ __global__ __launch_bounds__(256) void k_pr_apply(const int32_t *A, int64_t na, 
         }
     }
     block_sum2(acc, dang, &partials[2 * blockIdx.x], &partials[2 * blockIdx.x + 1]);
-    if (dprev) block_sum2b(sq, dot, &partials2[2 * blockIdx.x], &partials2[2 * blockIdx.x + 1]);
+    if (dprev2) {
+        const double v3[3] = {sq, dot, dot2};
+        block_sum_more<3>(v3, &partials2[3 * blockIdx.x]);
+    } else if (dprev) {
+        const double v2[2] = {sq, dot};
+        block_sum_more<2>(v2, &partials2[3 * blockIdx.x]);
+        if (threadIdx.x == 0) partials2[3 * blockIdx.x + 2] = 0.0;
+    }
 }
 
 // Sum and dangling mass of a whole vector: partials for k_pr_reduce.
@@ -753,7 +808,7 @@ static int ensure_pr_ws(dg_graph *g) {
     int64_t edges = std::max(g->fwd.m + g->fwd.dm, g->rev->m + g->rev->dm);
     const int64_t qcap = 2 * (edges / heavy_deg(g) + 2) + g->n / 8 + 64;
     DG_TRY(ws.heavy.ensure((size_t)qcap * 2 + 2 * (size_t)qcap * 2));
-    DG_TRY(ws.part.ensure((size_t)qcap + 4 * APPLY_GROUPS + 8));
+    DG_TRY(ws.part.ensure((size_t)qcap + 5 * APPLY_GROUPS + 8));
     DG_TRY(ws.prs.ensure(16));
     return DG_OK;
 }
@@ -803,13 +858,16 @@ static int pr_iterate(dg_graph *g, const int32_t *A, int64_t na, int64_t edges, 
                            partials);
     else
         hipLaunchKernelGGL(k_sum_vec2, dim3(1), dim3(256), 0, s, x, g->fwd.deg.p, (int64_t)0, partials);
-    // extrapolated steps keep the previous step vector (n doubles) and two more sums
+    // extrapolated steps keep the last two step vectors (n floats each) and three
+    // more sums per apply
     const int extrap = g->cfg.pr_extrapolate ? 1 : 0;
     double *partials2 = partials + 2 * APPLY_GROUPS;
-    float *dprev = nullptr;
+    float *dprev = nullptr, *dprev2 = nullptr;
     if (extrap) {
         DG_TRY(ws.prstep.ensure((size_t)g->n + 1));
+        DG_TRY(ws.prstep2.ensure((size_t)g->n + 1));
         dprev = ws.prstep.p;
+        dprev2 = ws.prstep2.p;
     }
     hipLaunchKernelGGL(k_pr_reduce, dim3(1), dim3(256), 0, s, partials, partials2,
                        global || S < 0.0 ? APPLY_GROUPS : 1, (int)global, S, damping, ninv, tol, 1, extrap, prs,
@@ -875,12 +933,12 @@ static int pr_iterate(dg_graph *g, const int32_t *A, int64_t na, int64_t edges, 
         if (tiles) {
             // the step just written becomes the current vector: no copy
             hipLaunchKernelGGL(k_pr_apply, dim3(APPLY_GROUPS), dim3(256), 0, s, A, na, xn, x, (double *)nullptr,
-                               contrib, g->fwd.deg.p, partials, partials2, dprev, prs);
+                               contrib, g->fwd.deg.p, partials, partials2, dprev, dprev2, prs);
             prof_end(pa, s, 28.0 * (double)na);
             std::swap(x, xn);
         } else {
             hipLaunchKernelGGL(k_pr_apply, dim3(APPLY_GROUPS), dim3(256), 0, s, A, na, xn, x, x, contrib,
-                               g->fwd.deg.p, partials, partials2, dprev, prs);
+                               g->fwd.deg.p, partials, partials2, dprev, dprev2, prs);
             prof_end(pa, s, 40.0 * (double)na);
         }
         hipLaunchKernelGGL(k_pr_reduce, dim3(1), dim3(256), 0, s, partials, partials2, APPLY_GROUPS, (int)global,
