@@ -171,8 +171,8 @@ typedef struct dg_batch_stats {
     int32_t pr_iterations;      /* Jacobi iterations                                    */
     int64_t pr_affected;        /* vertices in the affected set                         */
     int64_t edges_traversed;    /* adjacency entries examined: PageRank pulls (entries x steps), the
-                                   SSSP rounds (entries of the frontier rows of the cut walk and of
-                                   every pull and push step) and the triangle kernel's intersections */
+                                   SSSP rounds (entries of the rows each cut, pull and push step
+                                   walks) and the triangle kernel's intersections */
     int64_t tc_removed;         /* triangles removed by the deletions                   */
     int64_t tc_added;           /* triangles added by the insertions                    */
     float t_validate_ms, t_update_ms, t_merge_ms, t_sssp_ms, t_pr_ms, t_tc_ms, t_total_ms;

@@ -215,26 +215,12 @@ static ExpandArgs make_args(dg_graph *g, const Dir &d, const int32_t *F, int64_t
     return a;
 }
 
-// Adjacency entries (base + diff, tombstones included) of a frontier F of nf vertices
-// (nf_p: the count in device memory), added to *out: the edges a frontier step
-// examines, for the traversal tally (GTEPS).  One add per wave.
-__global__ void k_frontier_edges(const int32_t *F, int64_t nf, const int64_t *nf_p, const int64_t *__restrict__ off,
-                                 const int64_t *__restrict__ doff, int64_t *out) {
-    if (nf_p) nf = *nf_p;
-    int64_t acc = 0;
-    for (int64_t i = gtid(); i < nf; i += gstride()) {
-        const int32_t v = F[i];
-        acc += (off[v + 1] - off[v]) + (doff[v + 1] - doff[v]);
-    }
-    acc = wave_sum(acc);
-    if (lane_id() == 0 && acc) atomicAdd((unsigned long long *)out, (unsigned long long)acc);
-}
-
-static void tally_edges(dg_graph *g, const Dir &d, const int32_t *F, int64_t nf, const int64_t *nf_p,
-                        int64_t *out) {
-    const int grid = nf_p ? 256 : grid_for(nf);
-    if (!nf_p && nf <= 0) return;
-    hipLaunchKernelGGL(k_frontier_edges, dim3(grid), dim3(256), 0, g->stream, F, nf, nf_p, d.off.p, d.doff.p, out);
+// The traversal tally (GTEPS) counts the adjacency entries (base + diff,
+// tombstones included) of the rows each frontier step walks: the expansion adds
+// them up itself when its `tally` argument is set (with_tally).
+static ExpandArgs with_tally(ExpandArgs a, int64_t *tally) {
+    a.tally = tally;
+    return a;
 }
 
 // ---- near-far schedule --------------------------------------------------------------
@@ -342,8 +328,7 @@ static int sssp_push_nearfar(dg_graph *g, uint64_t *key, int64_t nf, int32_t del
             DG_TRY(next_stamp(g, &stv));
             DG_TRY(counters_clear(g));
             RelaxOp op{key, ws.stamp.p, stv, B, ws.dcnt + C_F1};
-            DG_TRY(launch_expand(s, make_args(g, g->fwd, A, nnear), op, 8192));
-            tally_edges(g, g->fwd, A, nnear, nullptr, ws.dcnt + C_EDGES);
+            DG_TRY(launch_expand(s, with_tally(make_args(g, g->fwd, A, nnear), ws.dcnt + C_EDGES), op, 8192));
             hipLaunchKernelGGL(k_nf_split, dim3(4096), dim3(256), 0, s, ws.dcnt + C_F1, B, key, T, A,
                                ws.dcnt + C_F0, far + nfar, ws.dcnt + C_AUX1, ws.farflag.p, fst);
             DG_HIP(hipGetLastError());
@@ -393,8 +378,7 @@ static int sssp_push(dg_graph *g, uint64_t *key, int64_t nf, dg_batch_stats *st)
         DG_TRY(next_stamp(g, &stv));
         DG_TRY(counters_clear(g));
         RelaxOp op{key, ws.stamp.p, stv, N, ws.dcnt + C_F1};
-        DG_TRY(launch_expand(s, make_args(g, g->fwd, F, nf), op, 8192));
-        tally_edges(g, g->fwd, F, nf, nullptr, ws.dcnt + C_EDGES);
+        DG_TRY(launch_expand(s, with_tally(make_args(g, g->fwd, F, nf), ws.dcnt + C_EDGES), op, 8192));
         DG_TRY(counters_read(g));
         relaxed += nf;
         edges += ws.hcnt[C_EDGES];
@@ -819,8 +803,7 @@ static int cut_level(dg_query *q, const int32_t *F, const int64_t *cf, int32_t *
     int64_t *ctr = q->qcnt.p;
     hipLaunchKernelGGL(k_round_prep, dim3(1), dim3(64), 0, g->stream, cn, g->ws.dcnt + C_HEAVY, ctr, nullptr);
     CutListOp op{q->key.p, N, cn, q->inval.p, ctr + R_LIST};
-    DG_TRY(launch_expand(g->stream, dev_args(g, g->fwd, F, cf), op, 1024));
-    tally_edges(g, g->fwd, F, 0, cf, ctr + R_EDGES);
+    DG_TRY(launch_expand(g->stream, with_tally(dev_args(g, g->fwd, F, cf), ctr + R_EDGES), op, 1024));
     return DG_OK;
 }
 
@@ -830,8 +813,7 @@ static int push_round(dg_query *q, const int32_t *F, const int64_t *cf, int32_t 
     int64_t *ctr = q->qcnt.p;
     hipLaunchKernelGGL(k_round_prep, dim3(1), dim3(64), 0, g->stream, cn, g->ws.dcnt + C_HEAVY, ctr, cf);
     RelaxOpD op{q->key.p, q->gstamp.p, ctr + R_STAMP, N, cn};
-    DG_TRY(launch_expand(g->stream, dev_args(g, g->fwd, F, cf), op, 1024));
-    tally_edges(g, g->fwd, F, 0, cf, ctr + R_EDGES);
+    DG_TRY(launch_expand(g->stream, with_tally(dev_args(g, g->fwd, F, cf), ctr + R_EDGES), op, 1024));
     return DG_OK;
 }
 
@@ -868,8 +850,7 @@ static int nf_round(dg_query *q, const int32_t *F, const int64_t *cf, int32_t *N
     const int32_t delta = g->cfg.sssp_delta;
     hipLaunchKernelGGL(k_nfd_step, dim3(1), dim3(64), 0, s, ctr, delta, cf, cn, ws.dcnt + C_HEAVY);
     RelaxOpD op{q->key.p, q->gstamp.p, ctr + R_STAMP, ws.nfout.p, ctr + R_NB};
-    DG_TRY(launch_expand(s, dev_args(g, g->fwd, F, cf), op, 1024));
-    tally_edges(g, g->fwd, F, 0, cf, ctr + R_EDGES);
+    DG_TRY(launch_expand(s, with_tally(dev_args(g, g->fwd, F, cf), ctr + R_EDGES), op, 1024));
     hipLaunchKernelGGL(k_nfd_split, dim3(256), dim3(256), 0, s, ws.nfout.p, q->key.p, ctr, N, cn, ws.far0.p,
                        ws.far1.p, q->gfar.p);
     hipLaunchKernelGGL(k_nfd_min, dim3(64), dim3(256), 0, s, ctr, cn, ws.far0.p, ws.far1.p, q->key.p);
@@ -890,8 +871,8 @@ static int rounds_push_enqueue(dg_query *q, bool first) {
     if (first) {
         // pull once at every cut vertex
         hipLaunchKernelGGL(k_round_prep, dim3(1), dim3(64), 0, s, nullptr, ws.dcnt + C_HEAVY, ctr, nullptr);
-        DG_TRY(launch_expand(s, dev_args(g, *g->rev, q->inval.p, ctr + R_LIST), PullOp{q->key.p}, 1024));
-        tally_edges(g, *g->rev, q->inval.p, 0, ctr + R_LIST, ctr + R_EDGES);
+        DG_TRY(launch_expand(s, with_tally(dev_args(g, *g->rev, q->inval.p, ctr + R_LIST), ctr + R_EDGES),
+                             PullOp{q->key.p}, 1024));
         // seeds: pulled cut vertices and improved heads of inserted arcs
         hipLaunchKernelGGL(k_round_prep, dim3(1), dim3(64), 0, s, ctr + R_PA, ws.dcnt + C_HEAVY, ctr, nullptr);
         hipLaunchKernelGGL(k_sssp_pulled_d, dim3(1024), dim3(256), 0, s, ctr + R_LIST, q->inval.p, q->key.p,
@@ -1058,8 +1039,8 @@ int sssp_post_update(dg_query *q, int64_t adel, int64_t ains, dg_batch_stats *st
     while (hi > lo) {
         DG_TRY(counters_clear(g));
         CutOp op{q->key.p, q->inval.p + hi, ws.dcnt + C_F1};
-        DG_TRY(launch_expand(s, make_args(g, g->fwd, q->inval.p + lo, hi - lo), op, 8192));
-        tally_edges(g, g->fwd, q->inval.p + lo, hi - lo, nullptr, ws.dcnt + C_EDGES);
+        DG_TRY(launch_expand(s, with_tally(make_args(g, g->fwd, q->inval.p + lo, hi - lo), ws.dcnt + C_EDGES), op,
+                             8192));
         DG_TRY(counters_read(g));
         edges += ws.hcnt[C_EDGES];
         lo = hi;
@@ -1071,8 +1052,7 @@ int sssp_post_update(dg_query *q, int64_t adel, int64_t ains, dg_batch_stats *st
     DG_TRY(counters_clear(g));
     if (ncut > 0) {
         PullOp op{q->key.p};
-        DG_TRY(launch_expand(s, make_args(g, *g->rev, q->inval.p, ncut), op, 8192));
-        tally_edges(g, *g->rev, q->inval.p, ncut, nullptr, ws.dcnt + C_EDGES);
+        DG_TRY(launch_expand(s, with_tally(make_args(g, *g->rev, q->inval.p, ncut), ws.dcnt + C_EDGES), op, 8192));
     }
     // 3. inserted arcs relax their heads; 2+3 seed the push frontier
     int32_t stv;

@@ -33,6 +33,7 @@ struct ExpandArgs {
     int64_t *hcount;    // its length
     int heavy_deg;
     int chunk;
+    int64_t *tally = nullptr;  // when set: += entries of the rows this step walks (traversal tally)
 };
 
 // Output of an expansion: vertices the op selects go to `out` (and `out2`, when
@@ -93,6 +94,7 @@ __global__ __launch_bounds__(256) void k_expand(ExpandArgs a, Op op) {
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / WAVE;
     const int l = lane_id();
     const int64_t nf = a.nfp ? *a.nfp : a.nf;
+    int64_t walked = 0;  // entries of this lane's rows (heavy rows too, walked by k_expand_heavy)
     for (int64_t wb = wave_global * WAVE; wb < nf; wb += nwaves * WAVE) {
         const int64_t fi = wb + l;
         int32_t v = -1, pay = 0;
@@ -107,6 +109,7 @@ __global__ __launch_bounds__(256) void k_expand(ExpandArgs a, Op op) {
                 tot = db + (int32_t)(a.g.doff[v + 1] - od);
             }
         }
+        walked += tot;
         // split heavy vertices into grid-wide chunks
         const bool heavy = tot > a.heavy_deg;
         int32_t nch = heavy ? (tot + a.chunk - 1) / a.chunk : 0;
@@ -152,6 +155,17 @@ __global__ __launch_bounds__(256) void k_expand(ExpandArgs a, Op op) {
         }
     }
     if (sk.t.out) sk.flush();
+    if (a.tally) {  // uniform: one add per block
+        __shared__ int64_t s_walked[256 / WAVE];
+        walked = wave_sum(walked);
+        if (l == 0) s_walked[threadIdx.x / WAVE] = walked;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int64_t t = 0;
+            for (int w = 0; w < 256 / WAVE; ++w) t += s_walked[w];
+            if (t) atomicAdd((unsigned long long *)a.tally, (unsigned long long)t);
+        }
+    }
 }
 
 // One wave per heavy chunk (grid-stride over the queue).
