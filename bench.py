@@ -65,8 +65,8 @@ MEASURED_TRAFFIC: dict = {
         "source": "pagerank.hip", "sha1": "0574e0f730155f07581ee12981ec958cc4f34672", "vertex_order": 0,
         "fetch_kib": 396397.8, "write_kib": 131599.9, "fetch_factor": 0.5, "write_factor": 1.0},
     ("k_merge_tiles", "batched4096-rmat10to14-dynamic-sssp"): {
-        "source": "graph.hip", "sha1": "4084d3a80f90548fc0d9d1e9df33efa8334f87aa",
-        "fetch_kib": 2135267.7, "write_kib": 3507970.5, "fetch_factor": 0.5, "write_factor": 1.0},
+        "source": "graph.hip", "sha1": "42eb1ae1802d55bcf79c17e2dad7845aa22a545e",
+        "fetch_kib": 2160799.4, "write_kib": 3510049.5, "fetch_factor": 0.5, "write_factor": 1.0},
     ("k_tc_delta", "rmat20-undirected-dynamic-tc"): {
         "source": "tc.hip", "sha1": "b5076bb4a16ebdc8ac0ef337fe1ae942a48ca96a", "vertex_order": 0,
         "fetch_kib": 408466.4, "write_kib": 768.0, "fetch_factor": 0.5, "write_factor": 1.0},

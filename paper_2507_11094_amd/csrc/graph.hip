@@ -426,7 +426,8 @@ __global__ __launch_bounds__(MG_THREADS, 8) void k_merge_tiles(
     const int64_t *__restrict__ mp_dlo, const int64_t *__restrict__ mp_dhi,
     const int64_t *__restrict__ off, const int32_t *__restrict__ col, const int32_t *__restrict__ w,
     const int64_t *__restrict__ doff, const int32_t *__restrict__ dcol, const int32_t *__restrict__ dw,
-    const int64_t *__restrict__ TB, int32_t *__restrict__ col2, int32_t *__restrict__ w2, int64_t cap, int64_t *cnt) {
+    const int64_t *__restrict__ TB, int32_t *__restrict__ col2, int32_t *__restrict__ w2, int64_t cap, uint32_t keep,
+    int64_t *cnt) {
     constexpr int IPT = ITEMS / MG_THREADS;
     constexpr int DC = ITEMS / 4 < 256 ? ITEMS / 4 : 256;
     __shared__ int32_t s_off[ITEMS + 1];  // row start - e0 (row 0: -1 when it began earlier)
@@ -544,7 +545,7 @@ __global__ __launch_bounds__(MG_THREADS, 8) void k_merge_tiles(
         // where the entry would land with none of its row's diff entries before it
         const int64_t base0 = i - deadG + dbase + dl;
         if (dl == dh) {
-            if (!dead) merge_put(col2, w2, cap, base0, (int32_t)cu, wt[u], cnt);
+            if (!dead) merge_put(col2, w2, cap, base0, (int32_t)(cu & keep), wt[u], cnt);
             continue;
         }
         // rows with diff entries: interleave them at their insertion points
@@ -552,10 +553,11 @@ __global__ __launch_bounds__(MG_THREADS, 8) void k_merge_tiles(
             return dlds ? lds_lower(s_dc, dl, dh, v) : (int)(lower_sorted(dcol, dbase + dl, dbase + dh, v) - dbase);
         };
         auto put_diff = [&](int q, int64_t o) {
-            merge_put(col2, w2, cap, o, dlds ? s_dc[q] : dcol[dbase + q], dlds ? s_dw[q] : dw[dbase + q], cnt);
+            merge_put(col2, w2, cap, o, (int32_t)((uint32_t)(dlds ? s_dc[q] : dcol[dbase + q]) & keep),
+                      dlds ? s_dw[q] : dw[dbase + q], cnt);
         };
         const int bq = lower(cur);
-        if (!dead) merge_put(col2, w2, cap, base0 + (bq - dl), (int32_t)cu, wt[u], cnt);
+        if (!dead) merge_put(col2, w2, cap, base0 + (bq - dl), (int32_t)(cu & keep), wt[u], cnt);
         int a = dl;
         if (i > ro) {
             const uint32_t p = l > 0 ? pc : (wv > 0 ? s_last[u][wv] : (u > 0 ? s_last[u - 1][MG_WAVES] : s_last[0][0]));
@@ -574,26 +576,32 @@ __global__ __launch_bounds__(MG_THREADS, 8) void k_merge_tiles(
 __global__ void k_merge_diff_empty(int64_t dm, const uint64_t *dkey, int B, const int64_t *off,
                                    const int64_t *doff, const int32_t *dcol, const int32_t *dw,
                                    const int64_t *off2, int32_t *col2, int32_t *w2, int64_t cap,
-                                   int64_t *cnt) {
+                                   uint32_t keep, int64_t *cnt) {
     for (int64_t j = gtid(); j < dm; j += gstride()) {
         int32_t r = (int32_t)(dkey[j] >> B);
         if (off[r] != off[r + 1]) continue;
         int64_t o = off2[r] + (j - doff[r]);
         if (o < 0 || o >= cap) { atomicOr((unsigned long long *)&cnt[C_ERR], 4ull); continue; }
-        col2[o] = dcol[j];
+        col2[o] = (int32_t)((uint32_t)dcol[j] & keep);
         w2[o] = dw[j];
     }
 }
 
 // Merge direction d into (off2, col2, w2).  side: on the graph's second stream,
 // with the merge's own error counter and scan scratch, and without waiting for it
-// (merge_side_check reads the counter once the stream is done).
+// (merge_side_check reads the counter once the stream is done).  A side merge
+// runs beside the post-hooks, which read the unmerged arrays, and its output is
+// swapped in after them: it drops the MARK of inserted entries as it copies them,
+// which the clearing pass would otherwise do on the merged arrays.  Merges on the
+// graph's stream run before the post-hooks and keep MARK (the triangle delta
+// weighs inserted arcs by it).
 static int merge_into(dg_graph *g, Dir &d, int64_t *off2, int32_t *col2, int32_t *w2, int64_t m2,
                       bool side = false) {
     hipStream_t s = side ? g->aux : g->stream;
     Work &ws = g->ws;
     int64_t *cnt = side ? ws.dcnt_m : ws.dcnt;
     SortWork &sw = side ? ws.sw_m : ws.sw;
+    const uint32_t keep = side ? ~MARK : ~0u;
     const int32_t n = g->n;
     const int64_t nblk = ntiles_for(d.m);
     DG_TRY(ws.scan64.ensure((size_t)n + 1 + 2 * (nblk + 2)));
@@ -626,11 +634,11 @@ static int merge_into(dg_graph *g, Dir &d, int64_t *off2, int32_t *col2, int32_t
     if (nb > 0)
         hipLaunchKernelGGL(tiles_kernel, dim3((unsigned)nb), dim3(MG_THREADS), 0, s, n, ws.mp_row.p,
                            ws.mp_edge.p, mp_dlo, mp_dhi, d.off.p, d.col.p, d.w.p, d.doff.p, d.dcol.p, d.dw.p, TB, col2, w2,
-                           m2, cnt);
+                           m2, keep, cnt);
     prof_end(pm, s, 8.0 * (double)d.m + 8.0 * (double)m2 + 16.0 * (double)n + 8.0 * (double)d.dm);
     if (d.dm > 0)
         hipLaunchKernelGGL(k_merge_diff_empty, dim3(grid_for(d.dm)), dim3(256), 0, s, d.dm, d.dkey.p,
-                           d.keybits, d.off.p, d.doff.p, d.dcol.p, d.dw.p, off2, col2, w2, m2, cnt);
+                           d.keybits, d.off.p, d.doff.p, d.dcol.p, d.dw.p, off2, col2, w2, m2, keep, cnt);
     DG_HIP(hipGetLastError());
     if (side) return DG_OK;
     DG_TRY(counters_read(g));
@@ -1641,11 +1649,13 @@ int apply_chunk(dg_graph *g, int64_t k, const int32_t *src, const int32_t *dst, 
         if (merge_f) DG_TRY(merge_dir_commit(g, F, g->m_live));
         if (merge_r) DG_TRY(merge_dir_commit(g, g->rev_own, g->m_live));
     }
-    // ---- drop the MARKs of inserted entries
+    // ---- drop the MARKs of inserted entries (a side merge dropped them in the
+    // arrays it replaced)
     if (ains > 0) {
-        hipLaunchKernelGGL(k_clear_marks, dim3(grid_for(ains)), dim3(256), 0, s, ains, ws.aiu.p, ws.aiv.p,
-                           0, F.off.p, F.col.p, F.doff.p, F.dcol.p);
-        if (!und)
+        if (!merge_f)
+            hipLaunchKernelGGL(k_clear_marks, dim3(grid_for(ains)), dim3(256), 0, s, ains, ws.aiu.p, ws.aiv.p,
+                               0, F.off.p, F.col.p, F.doff.p, F.dcol.p);
+        if (!und && !merge_r)
             hipLaunchKernelGGL(k_clear_marks, dim3(grid_for(ains)), dim3(256), 0, s, ains, ws.aiu.p,
                                ws.aiv.p, 1, R.off.p, R.col.p, R.doff.p, R.dcol.p);
         DG_HIP(hipGetLastError());
