@@ -1478,21 +1478,20 @@ int apply_chunk(dg_graph *g, int64_t k, const int32_t *src, const int32_t *dst, 
     }
 
     // ---- commit deletions, revive slots, rebuild the diff (both directions)
+    // The commits count into slots of their own (KILL_F, KILL_R: C_AUX2 and C_AUX3
+    // relative to them), so one read after the revivals serves both passes.
     PhaseTimer t_upd(g, 1, &st->t_update_ms);
+    constexpr int KILL_F = 16, KILL_R = 18;  // counts at 32..35, clear of every other use
+    static_assert(C_AUX3 + KILL_R < C_SORT_ERR && C_AUX2 + KILL_F > C_EDGES, "kill counts have free slots");
     DG_TRY(counters_clear(g));
     if (adel > 0) {
         hipLaunchKernelGGL(k_commit_deletes, dim3(grid_for(adel)), dim3(256), 0, s, adel, ws.adu.p,
-                           ws.adpos.p, F.col.p, F.dcol.p, F.deg.p, F.ntomb.p, F.ttomb.p, ws.dcnt);
+                           ws.adpos.p, F.col.p, F.dcol.p, F.deg.p, F.ntomb.p, F.ttomb.p, ws.dcnt + KILL_F);
         if (!und)
             hipLaunchKernelGGL(k_commit_deletes_rev, dim3(grid_for(adel)), dim3(256), 0, s, adel, ws.adu.p,
                                ws.adv.p, R.off.p, R.col.p, R.doff.p, R.dcol.p, R.deg.p, R.ntomb.p,
-                               R.ttomb.p, ws.dcnt + 8);
+                               R.ttomb.p, ws.dcnt + KILL_R);
     }
-    DG_HIP(hipGetLastError());
-    DG_TRY(counters_read(g));
-    const int64_t killed_base_f = ws.hcnt[C_AUX2], killed_diff_f = ws.hcnt[C_AUX3];
-    const int64_t killed_base_r = und ? 0 : ws.hcnt[C_AUX2 + 8], killed_diff_r = und ? 0 : ws.hcnt[C_AUX3 + 8];
-    DG_TRY(counters_clear(g));
     if (ains > 0) {
         hipLaunchKernelGGL(k_revive, dim3(grid_ch(ains)), dim3(256), 0, s, ains, ws.aiu.p, ws.aiv.p,
                            ws.aiw.p, ws.aipos.p, 0, F.off.p, F.col.p, F.w.p, F.doff.p, F.dcol.p, F.dw.p,
@@ -1509,6 +1508,9 @@ int apply_chunk(dg_graph *g, int64_t k, const int32_t *src, const int32_t *dst, 
     }
     DG_HIP(hipGetLastError());
     DG_TRY(counters_read(g));
+    const int64_t killed_base_f = ws.hcnt[C_AUX2 + KILL_F], killed_diff_f = ws.hcnt[C_AUX3 + KILL_F];
+    const int64_t killed_base_r = und ? 0 : ws.hcnt[C_AUX2 + KILL_R];
+    const int64_t killed_diff_r = und ? 0 : ws.hcnt[C_AUX3 + KILL_R];
     const int64_t revived_base_f = ws.hcnt[C_AUX2];
     const int64_t revived_base_r = und ? 0 : ws.hcnt[C_AUX2 + 8];
     // arcs new to the reverse store: the forward NEW arcs plus revivals whose reverse
