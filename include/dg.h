@@ -74,7 +74,9 @@ typedef struct dg_config {
     /* PageRank stops when the L1 step is <= tol * pr_tol_scale.  Default 1. */
     double pr_tol_scale;
     /* Vertices with more edges than this are split into chunks across waves.
-     * Default 0 = autotuned table / built-in value. */
+     * Default 0 = autotuned table / built-in value.  While no row is longer (the
+     * library keeps an upper bound on the longest row), the host-driven frontier
+     * steps launch no chunk kernel at all. */
     int32_t heavy_degree;
     /* Workgroups of the persistent SSSP kernel; 0 = autotuned / built-in. */
     int32_t persistent_groups;

@@ -177,6 +177,16 @@ __device__ __forceinline__ T wave_min(T x) {
     return x;
 }
 
+template <class T>
+__device__ __forceinline__ T wave_max(T x) {
+#pragma unroll
+    for (int d = WAVE / 2; d > 0; d >>= 1) {
+        T y = __shfl_xor(x, d, WAVE);
+        x = y > x ? y : x;
+    }
+    return x;
+}
+
 __device__ __forceinline__ int32_t wave_max_i32(int32_t x) {
 #pragma unroll
     for (int d = WAVE / 2; d > 0; d >>= 1) {

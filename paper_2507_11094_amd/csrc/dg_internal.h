@@ -193,6 +193,10 @@ enum Counter {
     C_TCDEL, C_TCINS, C_F0, C_F1, C_HEAVY, C_AUX0, C_AUX1, C_AUX2, C_AUX3,
     C_TC0, C_TC1, C_RED0 = 24,
     C_EDGES = 30,  // adjacency entries examined by an SSSP step (base + diff, tombstones included)
+    // an upper bound on the longest row (base + diff entries, tombstones included) of
+    // either direction: set at build, raised by the rows that gain diff entries, never
+    // cleared by counters_clear (the host copy refreshes with every counters_read)
+    C_MAXROW = 38,
     // set by a sort or scan whose look-back hit its spin limit; counters_clear
     // leaves it alone, counters_read reports it
     C_SORT_ERR = 39, C_COUNT = 40

@@ -77,7 +77,7 @@ int scan_excl(dg_graph *g, const int64_t *in, int64_t *out, int64_t n) {
 
 // ---------------------------------------------------------------- counters
 
-int counters_clear(dg_graph *g) { return fill_i64(g->ws.dcnt, 0, C_SORT_ERR, g->stream); }
+int counters_clear(dg_graph *g) { return fill_i64(g->ws.dcnt, 0, C_MAXROW, g->stream); }
 
 int counters_read(dg_graph *g) {
     DG_HIP(hipMemcpyAsync(g->ws.hcnt, g->ws.dcnt, sizeof(int64_t) * C_COUNT, hipMemcpyDeviceToHost,
@@ -207,8 +207,29 @@ __global__ void k_row_offsets(int32_t n, const uint64_t *k, int64_t m, int B, in
     for (int64_t r = gtid(); r <= n; r += gstride()) off[r] = lower_key(k, 0, m, (uint64_t)r << B);
 }
 
-__global__ void k_degrees(int32_t n, const int64_t *off, int32_t *deg) {
-    for (int64_t r = gtid(); r < n; r += gstride()) deg[r] = (int32_t)(off[r + 1] - off[r]);
+// Row lengths, and their maximum raised into *maxrow.
+__global__ void k_degrees(int32_t n, const int64_t *off, int32_t *deg, int64_t *maxrow) {
+    int64_t mx = 0;
+    for (int64_t r = gtid(); r < n; r += gstride()) {
+        const int64_t len = off[r + 1] - off[r];
+        deg[r] = (int32_t)len;
+        mx = max(mx, len);
+    }
+    mx = wave_max(mx);
+    if (lane_id() == 0 && mx > 0) atomicMax((unsigned long long *)maxrow, (unsigned long long)mx);
+}
+
+// The rows that gained the diff keys k[0, nk): their total lengths (base entries,
+// tombstones included, plus diff entries) raised into *maxrow.
+__global__ void k_diff_row_max(int64_t nk, const uint64_t *k, int B, const int64_t *off, const int64_t *doff,
+                               int64_t *maxrow) {
+    int64_t mx = 0;
+    for (int64_t j = gtid(); j < nk; j += gstride()) {
+        const int32_t r = (int32_t)(k[j] >> B);
+        mx = max(mx, (off[r + 1] - off[r]) + (doff[r + 1] - doff[r]));
+    }
+    mx = wave_max(mx);
+    if (lane_id() == 0 && mx > 0) atomicMax((unsigned long long *)maxrow, (unsigned long long)mx);
 }
 
 static int64_t ntiles_for(int64_t m) { return (m + TILE - 1) / TILE; }
@@ -234,7 +255,8 @@ static int dir_from_sorted(dg_graph *g, Dir &d, const uint64_t *keys, const int3
                            d.col.p, d.w.p);
     hipLaunchKernelGGL(k_row_offsets, dim3(grid_for(g->n + 1)), dim3(256), 0, s, g->n, keys, m, B,
                        d.off.p);
-    hipLaunchKernelGGL(k_degrees, dim3(grid_for(g->n)), dim3(256), 0, s, g->n, d.off.p, d.deg.p);
+    hipLaunchKernelGGL(k_degrees, dim3(grid_for(g->n)), dim3(256), 0, s, g->n, d.off.p, d.deg.p,
+                       g->ws.dcnt + C_MAXROW);
     DG_HIP(hipGetLastError());
     DG_TRY(fill_i32(d.ntomb.p, 0, g->n + 1, s));
     DG_TRY(fill_i32(d.ttomb.p, 0, ntiles_for(m) + 2, s));
@@ -340,8 +362,7 @@ int graph_build(dg_graph *g, int64_t m, const int32_t *src, const int32_t *dst, 
     g->m_live = arcs;
     // the build-sized scratch is not needed again
     ws.ikey.release(); ws.ikey_s.release(); ws.iw.release(); ws.iw_s.release(); ws.sw.release();
-    DG_HIP(hipStreamSynchronize(s));
-    return DG_OK;
+    return counters_read(g);  // also brings the longest-row bound to the host
 }
 
 // ---------------------------------------------------------------- merge (Section 3.5)
@@ -626,7 +647,7 @@ static int merge_into(dg_graph *g, Dir &d, int64_t *off2, int32_t *col2, int32_t
     hipLaunchKernelGGL(k_mg_partition, dim3(grid_for(nb + 1)), dim3(256), 0, s, d.off.p, d.doff.p, n, d.m, nb,
                        items, ws.mp_row.p, ws.mp_edge.p, mp_dlo, mp_dhi);
     DG_HIP(hipGetLastError());
-    DG_TRY(fill_i64(cnt, 0, C_SORT_ERR, s));
+    DG_TRY(fill_i64(cnt, 0, C_MAXROW, s));  // the longest-row bound stays (rows only shrink here)
     // merge bytes: col+w read 8 per old entry, write 8 per new entry, and per row
     // off and doff (8 each)
     int pm = prof_begin("merge_base", s);
@@ -1314,6 +1335,9 @@ static int diff_rebuild(dg_graph *g, Dir &d, const uint64_t *nkey, const int32_t
                            rank, d.keybits, d.dkey2.p, d.dcol2.p, d.dw2.p, dm2);
     hipLaunchKernelGGL(k_row_offsets, dim3(grid_for(g->n + 1)), dim3(256), 0, s, g->n, d.dkey2.p, dm2,
                        d.keybits, d.doff.p);
+    if (nk > 0)
+        hipLaunchKernelGGL(k_diff_row_max, dim3(grid_for(nk)), dim3(256), 0, s, nk, nkey, d.keybits, d.off.p,
+                           d.doff.p, g->ws.dcnt + C_MAXROW);
     DG_HIP(hipGetLastError());
     d.dkey.swap(d.dkey2);
     d.dcol.swap(d.dcol2);

@@ -212,6 +212,10 @@ static ExpandArgs make_args(dg_graph *g, const Dir &d, const int32_t *F, int64_t
     a.hcount = g->ws.dcnt + C_HEAVY;
     a.heavy_deg = heavy_deg(g);
     a.chunk = a.heavy_deg;
+    // No row longer than the heavy degree (the host copy of the bound, at most one
+    // update old): every row is walked in place and the chunk kernel is skipped.  A
+    // stale bound only costs time -- a row that grew past it is walked by one wave.
+    if (g->ws.hcnt[C_MAXROW] <= (int64_t)a.heavy_deg) a.heavy_deg = NO_HEAVY;
     return a;
 }
 
@@ -794,6 +798,9 @@ __global__ void k_nfd_refill(int64_t *ctr, int32_t *far0, int32_t *far1, const u
 static ExpandArgs dev_args(dg_graph *g, const Dir &d, const int32_t *F, const int64_t *nfp) {
     ExpandArgs a = make_args(g, d, F, 0);
     a.nfp = nfp;
+    // captured rounds are replayed for later batches, when rows may have grown:
+    // they keep the chunk kernel
+    a.heavy_deg = heavy_deg(g);
     return a;
 }
 

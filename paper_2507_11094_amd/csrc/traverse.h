@@ -208,14 +208,18 @@ __global__ __launch_bounds__(256) void k_expand_heavy(ExpandArgs a, Op op) {
 }
 
 // Host side: run one expansion step of `op` over frontier F (nf entries).
-// hcount must point at a zeroed device counter.
+// hcount must point at a zeroed device counter.  heavy_deg = NO_HEAVY: no row is
+// cut into chunks (every row is walked by k_expand) and the chunk kernel is not
+// launched.
+constexpr int NO_HEAVY = 0x7fffffff;
 template <class Op>
 inline int launch_expand(hipStream_t s, const ExpandArgs &a, const Op &op, int heavy_groups) {
     if (!a.nfp && a.nf <= 0) return DG_OK;
     int64_t blocks = a.nfp ? 4096 : (a.nf + 255) / 256;  // device-side count: fixed grid-stride grid
     if (blocks > 65535) blocks = 65535;
     hipLaunchKernelGGL(k_expand<Op>, dim3((unsigned)blocks), dim3(256), 0, s, a, op);
-    hipLaunchKernelGGL(k_expand_heavy<Op>, dim3(heavy_groups), dim3(256), 0, s, a, op);
+    if (a.heavy_deg != NO_HEAVY)
+        hipLaunchKernelGGL(k_expand_heavy<Op>, dim3(heavy_groups), dim3(256), 0, s, a, op);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return set_error(DG_EDEVICE, "expand launch failed: %s", hipGetErrorString(e));
     return DG_OK;

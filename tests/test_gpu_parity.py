@@ -376,6 +376,35 @@ def test_sssp_grid_and_hub(persistent, delta):
         assert_tree(n, cs, cd, cw, 0, dist, par)
 
 
+@pytest.mark.parametrize("delta", [0, 40])
+def test_sssp_row_grows_past_heavy_limit(delta):
+    """Frontier steps skip the chunk kernel while the graph's longest-row bound
+    (set at build, raised by rows that gain diff entries, brought to the host with
+    the counters) is within heavy_degree.  Batches that grow one row of a 30 x 30
+    grid far past the limit are relaxed by steps that still see the old bound (the
+    row walked in place by one wave) and then by chunked steps.  Distances equal
+    the oracle's and the trees are valid after every batch."""
+    n, s, d, w = graphgen.grid4(30, 30, 3, 50)
+    say("sssp row grows past the heavy limit, delta", delta)
+    G = dg.Graph(n, s, d, w, config=cfg(heavy=32, delta=delta))
+    q = G.sssp_attach(0)
+    assert np.array_equal(q.read()[0], oracle.sssp(n, s, d, w, 0))
+    cs, cd, cw = s, d, w
+    rng = np.random.default_rng(11)
+    for i, hub in enumerate([1, 1, 450]):
+        existing = set(zip(cs.tolist(), cd.tolist()))
+        cand = [v for v in rng.permutation(n).tolist() if v != hub and (hub, v) not in existing][:300]
+        bs = np.full(len(cand), hub, np.int32)
+        bd = np.array(cand, np.int32)
+        bw = rng.integers(1, 50, len(cand)).astype(np.int32)
+        bo = np.ones(len(cand), np.uint8)
+        G.apply(bs, bd, bw, bo)
+        cs, cd, cw, _ = oracle.apply(n, cs, cd, cw, bs, bd, bw, bo)
+        dist, par = q.read()
+        assert np.array_equal(dist, oracle.sssp(n, cs, cd, cw, 0)), i
+        assert_tree(n, cs, cd, cw, 0, dist, par)
+
+
 def test_work_queue_refuses_deep_graphs():
     """The work-queue schedule refuses a graph whose breadth-first levels from the
     source pass 64 (a 100 x 100 grid: 198 levels) before its queue runs; the
