@@ -428,15 +428,16 @@ __device__ __forceinline__ int lds_lower(const int32_t *a, int lo, int hi, uint3
     return lo;
 }
 
-// ITEMS rows + entries per tile; up to ITEMS / 4 diff column ids of its rows are
-// staged in LDS (more are read from memory).  Output positions need no per-row output
+// ITEMS rows + entries per tile; up to min(ITEMS / 4, 256) diff entries (column and
+// weight) of its rows are staged in LDS (more are read from memory).  Output
+// positions need no per-row output
 // offsets: after the update the diff level holds live entries only, so
 //   off2[r] = (base entries before row r) - (tombstones before row r) + doff[r],
 // and a live base entry i of row r lands at
 //   i - (tombstones before i) + doff[r] + (diff entries of row r below it),
 // the tombstones before i coming from the per-block counters (TB) and a ballot
-// count inside the tile.  A tile keeps about 10 bytes of LDS per item (row
-// starts, diff ranges and a quarter item of diff entries); the entries stay in
+// count inside the tile.  A tile keeps about 9 bytes of LDS per item (row starts
+// and diff ranges, plus the staged diff entries); the entries stay in
 // registers and the column before an entry comes from the neighbouring lane (or
 // the wave before).  No global load follows the tile's first barrier except for
 // tiles whose diff entries exceed the staging: on this GPU a wave's load counter
