@@ -237,8 +237,9 @@ __device__ __forceinline__ void block_sum_more(const double (&v)[K], double *out
 // two-step move, prs[15] = 1 once the applies also keep the step before the
 // previous one (after EX_LAG2_AFTER plain steps without a move, on a step whose
 // one-step fit left at least EX_LAG2_RES of |s_k|^2 unexplained: on a grid the
-// successive steps are orthogonal, while on R-MAT graphs the fit explains more
-// than 20 % by the fourth step and the older vector is never kept).
+// successive steps are orthogonal, while on R-MAT graphs from scale 16 up the fit
+// explains more than 20 % by the fourth step in the CPU models and the older
+// vector is not kept; where it is, on small graphs, no two-step move fired).
 // first = 1: the set-up call before the first step (resets the flags and counts).
 //
 // Extrapolation (extrap = 1, partials2 holds the block sums of |step|^2,
