@@ -813,7 +813,10 @@ __global__ __launch_bounds__(CH_T) void k_validate_batch(int64_t k, const int32_
 }
 
 // Split the chunk into deletion arcs and insertion keys (undirected updates give
-// both arcs).
+// both arcs).  A workgroup takes CH updates, each thread CH_IPT of them strided by
+// the workgroup size (coalesced loads); the outputs of one workgroup are one
+// contiguous range, in thread order (the order of arcs and keys is free: the keys
+// are sorted next, and repeated deletions are told apart by the MARK bit).
 __global__ __launch_bounds__(CH_T) void k_expand_batch(int64_t k, const int32_t *s, const int32_t *d,
                                                        const int32_t *w, const uint8_t *op, int B,
                                                        int undirected, const int32_t *perm, int32_t *ddu,
@@ -821,33 +824,34 @@ __global__ __launch_bounds__(CH_T) void k_expand_batch(int64_t k, const int32_t 
     __shared__ BlockScratch sc;
     const int rep = undirected ? 2 : 1;
     for (int64_t c0 = (int64_t)blockIdx.x * CH; c0 < k; c0 += (int64_t)gridDim.x * CH) {
-        const int64_t i0 = c0 + (int64_t)threadIdx.x * CH_IPT;
+        uint8_t o[CH_IPT];
+        int32_t su[CH_IPT], dv[CH_IPT], wt[CH_IPT];
         int64_t nd = 0, ni = 0;
 #pragma unroll
         for (int q = 0; q < CH_IPT; ++q) {
-            const int64_t i = i0 + q;
-            if (i < k) {
-                nd += op[i] == 0;
-                ni += op[i] == 1;
-            }
+            const int64_t i = c0 + (int64_t)q * CH_T + threadIdx.x;
+            o[q] = i < k ? op[i] : (uint8_t)2;
+            su[q] = i < k ? s[i] : 0;
+            dv[q] = i < k ? d[i] : 0;
+            wt[q] = i < k && w ? w[i] : 1;
+            nd += o[q] == 0;
+            ni += o[q] == 1;
         }
         int64_t pd = block_reserve(&cnt[C_AUX0], nd * rep, sc);
         int64_t pi = block_reserve(&cnt[C_AUX1], ni * rep, sc);
+#pragma unroll
         for (int q = 0; q < CH_IPT; ++q) {
-            const int64_t i = i0 + q;
-            if (i >= k) break;
-            const uint8_t o = op[i];
-            const uint32_t u0 = (uint32_t)(perm ? perm[s[i]] : s[i]), v0 = (uint32_t)(perm ? perm[d[i]] : d[i]);
-            const int32_t wt = w ? w[i] : 1;
+            if (o[q] > 1) continue;
+            const uint32_t u0 = (uint32_t)(perm ? perm[su[q]] : su[q]), v0 = (uint32_t)(perm ? perm[dv[q]] : dv[q]);
             for (int r = 0; r < rep; ++r) {
                 const uint32_t u = r ? v0 : u0, v = r ? u0 : v0;
-                if (o == 0) {
+                if (o[q] == 0) {
                     ddu[pd] = (int32_t)u;
                     ddv[pd] = (int32_t)v;
                     ++pd;
-                } else if (o == 1) {
+                } else {
                     ikey[pi] = ((uint64_t)u << B) | v;
-                    iw[pi] = wt;
+                    iw[pi] = wt[q];
                     ++pi;
                 }
             }
